@@ -1,0 +1,126 @@
+"""Pins of the direct-sum oracle O1 (eq. 2.1/2.2) and of the direct-sum
+gradient O3 against closed forms, invariants and finite differences."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1311_1006_amd import workloads as W
+
+
+def test_roots_of_unity_closed_form(orc):
+    # N unit charges at z_k = c + R w^k (w^N = 1): sum_{j!=k} 1/(z_k - z_j)
+    # = P''(z_k)/(2 P'(z_k)) for P = prod (z - z_j), which gives (N-1)/(2(z_k - c)).
+    for n, c, R in [(7, 0.0, 1.0), (64, 0.3 - 0.2j, 0.01), (501, 2.0 + 1.0j, 3.0)]:
+        z = W.roots_of_unity(n, c, R, phase=0.123)
+        phi = orc.direct(z, np.ones(n))
+        ref = (n - 1) / (2 * (z - c))
+        assert orc.rel_errinf(phi, ref) < 1e-13
+
+
+def test_equispaced_line_harmonic_numbers(orc):
+    # z_k = k h, unit strengths: phi_k = (H_k - H_{N-1-k}) / h
+    for n, h in [(10, 1.0), (300, 1e-3)]:
+        z = np.arange(n) * h + 0j
+        phi = orc.direct(z, np.ones(n))
+        H = np.concatenate([[0.0], np.cumsum(1.0 / np.arange(1, n + 1))])
+        k = np.arange(n)
+        ref = (H[k] - H[n - 1 - k]) / h
+        assert np.max(np.abs(phi - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_two_points(orc):
+    z = np.array([0.1 + 0.2j, -0.3 + 0.5j])
+    m = np.array([1.5 - 0.5j, -2.0 + 0.25j])
+    phi = orc.direct(z, m)
+    np.testing.assert_allclose(phi[0], m[1] / (z[0] - z[1]), rtol=1e-15)
+    np.testing.assert_allclose(phi[1], m[0] / (z[1] - z[0]), rtol=1e-15)
+
+
+def test_antisymmetry_and_linearity(orc):
+    z, m, _ = W.uniform(800, seed=3)
+    phi = orc.direct(z, m)
+    # sum_i m_i phi_i = sum_{i != j} m_i m_j / (z_i - z_j) = 0 (antisymmetric kernel)
+    s = np.sum(m * phi)
+    assert abs(s) <= 1e-13 * np.sum(np.abs(m * phi))
+    m2 = W.uniform(800, seed=4)[1]
+    a, b = 0.7 - 1.1j, -0.3 + 0.2j
+    lhs = orc.direct(z, a * m + b * m2)
+    rhs = a * phi + b * orc.direct(z, m2)
+    assert orc.rel_errinf(lhs, rhs) < 1e-13
+
+
+def test_compensated_agrees(orc):
+    z, m, _ = W.uniform(1500, seed=5)
+    a = orc.direct(z, m)
+    b = orc.direct_compensated(z, m)
+    assert orc.rel_err2(a, b) < 1e-14
+
+
+def test_exclusion_by_position(orc):
+    # a duplicated position contributes nothing at its twin (x_j != y_i in 2.2)
+    z = np.array([0.0, 1.0, 1.0, 2.0 + 1j])
+    m = np.array([1.0, 2.0, 3.0, 4.0])
+    phi = orc.direct(z, m)
+    assert phi[1] == pytest.approx(m[0] / (z[1] - z[0]) + m[3] / (z[1] - z[3]), rel=1e-15)
+    assert phi[2] == pytest.approx(phi[1], rel=1e-15)
+
+
+def test_points_and_subset_variants(orc):
+    z, m, _ = W.uniform(500, seed=6)
+    full = orc.direct(z, m)
+    t = np.array([0, 17, 499, 250])
+    np.testing.assert_array_equal(orc.direct(z, m, t), full[t])
+    np.testing.assert_array_equal(orc.direct_points(z, m, z[t]), full[t])
+
+
+def _loss(orc, z, m):
+    return float(np.sum(np.abs(orc.direct(z, m)) ** 2))
+
+
+def test_grad_direct_vs_central_fd(orc):
+    z, m, _ = W.uniform(12, seed=7)
+    phi = orc.direct(z, m)
+    gm, gz = orc.grad_direct(z, m, 2 * phi)      # L = sum |phi|^2 -> g = 2 phi
+    h = 1e-6
+    fd_z = np.zeros(12, complex)
+    fd_m = np.zeros(12, complex)
+    for k in range(12):
+        for unit, tgt in [(1.0, "re"), (1j, "im")]:
+            e = np.zeros(12, complex)
+            e[k] = unit * h
+            dz = (_loss(orc, z + e, m) - _loss(orc, z - e, m)) / (2 * h)
+            dm = (_loss(orc, z, m + e) - _loss(orc, z, m - e)) / (2 * h)
+            if tgt == "re":
+                fd_z[k] += dz
+                fd_m[k] += dm
+            else:
+                fd_z[k] += 1j * dz
+                fd_m[k] += 1j * dm
+    assert np.linalg.norm(gz - fd_z) / np.linalg.norm(fd_z) < 1e-6
+    assert np.linalg.norm(gm - fd_m) / np.linalg.norm(fd_m) < 1e-6
+
+
+def test_grad_direct_identities(orc):
+    z, m, _ = W.uniform(400, seed=8)
+    phi = orc.direct(z, m)
+    Lval = float(np.sum(np.abs(phi) ** 2))
+    gm, gz = orc.grad_direct(z, m, 2 * phi)
+    scale = np.sum(np.abs(gz * z)) + np.sum(np.abs(gm * m))
+    # translation invariance
+    assert abs(np.sum(gz)) <= 1e-12 * np.sum(np.abs(gz))
+    # z -> (1+e) z scales phi by 1/(1+e): dL/de = -2L
+    assert abs(np.sum(np.real(np.conj(gz) * z)) + 2 * Lval) <= 1e-12 * scale
+    # m -> (1+e) m: dL/de = 2L
+    assert abs(np.sum(np.real(np.conj(gm) * m)) - 2 * Lval) <= 1e-12 * scale
+    # rotations of z or m leave |phi| unchanged
+    assert abs(np.sum(np.real(np.conj(gz) * 1j * z))) <= 1e-12 * scale
+    assert abs(np.sum(np.real(np.conj(gm) * 1j * m))) <= 1e-12 * scale
+
+
+def test_p_rule_reproduces_table_4_1(orc):
+    path = os.path.join(os.path.dirname(__file__), "golden", "table_4_1_p.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 15
+    for tol, theta, p in rows:
+        assert orc.p_from_tol(float(tol), float(theta)) == int(p), (tol, theta)
