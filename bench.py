@@ -1,0 +1,175 @@
+"""Benchmark: full FMM evaluation at N = 1e6, mixed precision vs plain FP64.
+
+One step = fmm_build_tree + fmm_plan + fmm_evaluate on device-resident
+positions and strengths (the tree is rebuilt every call, as in a
+time-stepping code).  Workload: 1,000,000 points uniform in the unit square,
+complex N(0,1) strengths (seed 0), theta = 0.5, p = 16 terms (chosen by a
+measured error sweep: mixed e2 <= 0.5e-6), N_levels chosen by a timing sweep.
+The accuracy of both paths is measured against the FP64 direct sum (CPU
+oracle) on a 10,000-target subsample.
+
+Prints ONE JSON line (stdout).  Progress goes to stderr.
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3      # TFLOP/s, MI355X published FP32 vector peak (packed)
+PEAK_FP32_NOPACK = 78.6     # TFLOP/s, the same units issuing one FP32 op per lane per cycle
+P2P_FLOP_PER_PAIR = 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--levels", type=str, default="8,9,10")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1311_1006_amd as F
+    from paper_1311_1006_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    F.lib()
+    dev = torch.device("cuda:0")
+    n, p, theta = args.n, args.p, args.theta
+    z, m, sub = W.uniform(n, seed=0)
+    zd = torch.from_numpy(z).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    out = torch.empty_like(md)
+    stream = torch.cuda.current_stream()
+
+    def step(prec, L, timing=False):
+        tree = F.build_tree(zd, L)
+        pl = F.plan(tree, p, theta, prec, timing=timing)
+        F.evaluate(pl, md, out)
+        return tree, pl
+
+    # ---- N_levels by a timing sweep (per precision)
+    levels = [int(x) for x in args.levels.split(",") if 4 ** (int(x) - 1) <= n]
+    best_L = {}
+    for prec in ("mixed", "fp64"):
+        best = None
+        for L in levels:
+            for _ in range(2):
+                step(prec, L)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                step(prec, L)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            log("sweep %s L=%d: %.3f ms" % (prec, L, dt * 1e3))
+            if best is None or dt < best[0]:
+                best = (dt, L)
+        best_L[prec] = best[1]
+
+    # ---- timed region: K steps, mixed precision (the metric), then FP64
+    res = {}
+    for prec in ("mixed", "fp64"):
+        L = best_L[prec]
+        for _ in range(args.warmup):
+            step(prec, L, timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p2p_us = []
+        for _ in range(args.steps):
+            tree, pl = step(prec, L, timing=True)
+            p2p_us.append(pl.stats()["t_p2p_us"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = pl.stats()
+        # evaluate-only throughput on the last plan
+        for _ in range(3):
+            F.evaluate(pl, md, out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            F.evaluate(pl, md, out)
+        torch.cuda.synchronize()
+        dte = (time.perf_counter() - t1) / args.steps
+        phi = out.cpu().numpy()
+        res[prec] = dict(L=L, t=dt, t_eval=dte, stats=st, p2p_us=float(np.mean(p2p_us)), phi=phi)
+        log("%s: L=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, P2P %.1f us" %
+            (prec, L, dt * 1e3, n / dt / 1e6, dte * 1e3, res[prec]["p2p_us"]))
+
+    # ---- accuracy vs the FP64 direct sum (CPU oracle) on the subsample
+    err = {}
+    cpu_baseline = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.direct(z, m, sub)
+        log("direct sum on %d targets: %.1f s" % (sub.size, time.perf_counter() - t0))
+        for prec in res:
+            err[prec] = oracle.rel_err2(res[prec]["phi"][sub], ref)
+            log("%s e2 vs direct: %.3e" % (prec, err[prec]))
+        # CPU oracle (serial FMM O2, its P2P loop OpenMP-parallel) on the full workload
+        L = best_L["fp64"]
+        t0 = time.perf_counter()
+        oracle.fmm(z, m, p, theta, L)
+        tc = time.perf_counter() - t0
+        cpu_baseline = {"value": n / tc / 1e6, "unit": "Mpoints/s", "cores": oracle.threads(),
+                        "kind": "oracle",
+                        "sample": "one full serial-FMM evaluation (tree, lists, P2M..L2P, P2P) of the "
+                                  "same N=1e6 workload at p=%d, theta=%.2f, N_levels=%d; %.1f s" % (p, theta, L, tc)}
+        log("cpu oracle FMM: %.2f s" % tc)
+
+    mx, fp = res["mixed"], res["fp64"]
+    st = mx["stats"]
+    achieved = P2P_FLOP_PER_PAIR * st["n_p2p_pairs"] / (mx["p2p_us"] * 1e-6) / 1e12
+    line = {
+        "metric": "Mpoints/s full FMM eval N=1e6 @rel err<=1e-6: mixed-prec vs plain FP64 GPU",
+        "value": n / mx["t"] / 1e6,
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mx["t"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform unit square N=1e6, complex N(0,1) strengths, seed 0",
+                   "n": n, "p": p, "theta": theta, "n_levels": mx["L"], "precision": "mixed",
+                   "step": "build_tree+plan+evaluate"},
+        "fp64": {"value": n / fp["t"] / 1e6, "n_levels": fp["L"], "ms_per_step": fp["t"] * 1e3,
+                 "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64")},
+        "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed")},
+        "speedup_mixed_vs_fp64": fp["t"] / mx["t"],
+        "roofline": {"bound": "alu", "kernel": "p2p (mixed)", "achieved": achieved, "peak": PEAK_FP32_VALU,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "peak_without_packed_fp32": PEAK_FP32_NOPACK,
+                     "frac_without_packed_fp32": achieved / PEAK_FP32_NOPACK,
+                     "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR},
+        "cpu_baseline": cpu_baseline,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

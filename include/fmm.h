@@ -1,0 +1,256 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) fast multipole library for the 2D
+ * harmonic kernel
+ *
+ *     phi(z_i) = sum_{j : z_j != z_i} m_j / (z_i - z_j),
+ *
+ * following Holm, Engblom, Goude & Holmgren, "Dynamic autotuning of adaptive
+ * fast multipole methods on hybrid multicore CPU & GPU systems"
+ * (arXiv:1311.1006): eq. (2.1)/(2.2) for the sum, Sec. 2.1 for the
+ * theta-criterion (2.3) and the strong / weak / decoupled connectivity, Sec.
+ * 2.2 for the balanced ("pyramid") median-split tree, Sec. 2.3 for N_levels
+ * and p, Sec. 3.3 for the harmonic potential (the paper writes it with the
+ * opposite global sign).
+ *
+ * Conventions shared by every call
+ *   - Complex arrays are interleaved doubles (re, im), i.e. 16 bytes per value.
+ *   - Array arguments marked DEVICE are device pointers on the current HIP
+ *     device; HOST arrays are ordinary host memory read during the call.
+ *   - Every device-side effect is ordered on `stream` (a hipStream_t; NULL is
+ *     the null stream).  Calls return once the work is enqueued unless noted.
+ *   - Points of problem b are entries offsets[b] .. offsets[b+1]-1 of the
+ *     caller's arrays ("input order"); outputs are in input order too.
+ *   - Levels follow the paper: level 0 is the root, leaves are at level
+ *     n_levels-1, and a problem has N_f = 4^(n_levels-1) leaves.
+ *   - p is the number of expansion terms (coefficients k = 0 .. p-1).
+ *   - Return value: FMM_OK (0) or a negative fmm_status; on error nothing is
+ *     written to the outputs, no handle is created and no memory leaks.
+ *     fmm_last_error() then returns a message (thread-local).  Errors of
+ *     asynchronous device work surface as FMM_EDEVICE at a later call.
+ *   - Handles are not thread-safe; use each from one host thread at a time.
+ *     The library owns all tree and plan memory; the caller owns every array
+ *     it passes in.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_tree_s* fmm_tree_t;
+typedef struct fmm_plan_s* fmm_plan_t;
+
+enum fmm_status {
+    FMM_OK = 0,
+    FMM_EINVAL = -1,   /* invalid argument (sizes, levels, p, theta, non-finite input) */
+    FMM_ENOMEM = -2,   /* device or host allocation failed */
+    FMM_EDEVICE = -3,  /* a HIP runtime call or an earlier kernel failed */
+    FMM_ESTATE = -4    /* handle used in a state that does not allow the call */
+};
+
+enum fmm_precision {
+    FMM_FP64 = 0,   /* every step in FP64 */
+    FMM_MIXED = 1   /* P2P and M2L in FP32 (FP32 accumulation); FP64 box geometry,
+                       theta-tests, position differences and rescaling powers */
+};
+
+/* Flags of fmm_tuning.flags */
+enum {
+    FMM_FLAG_GRAPH = 1,       /* capture fmm_evaluate's kernels in a hipGraph on first
+                                 use and replay it on later calls with the same
+                                 pointers and stream */
+    FMM_FLAG_PHASE_TIMING = 2 /* record per-phase hipEvent timings into fmm_stats
+                                 (adds one event pair per phase) */
+};
+
+/* Launch-shape knobs of one plan; 0 means "choose automatically". */
+typedef struct {
+    int p2p_split;   /* P2P: lanes that split one target's sources (1, 2, 4, 8, 16) */
+    int m2l_batch;   /* M2L: pairs gathered per MFMA batch (8 .. 64, multiple of 8) */
+    int flags;       /* FMM_FLAG_* */
+    int reserved;
+} fmm_tuning;
+
+/* Host-side statistics of a plan (list sizes for the work model and the
+ * roofline, last measured phase times when FMM_FLAG_PHASE_TIMING is set). */
+typedef struct {
+    int64_t n_points;          /* total points over all problems */
+    int64_t n_boxes;           /* boxes over all levels and problems */
+    int64_t n_leaves;
+    int64_t n_p2p_pairs;       /* sum over leaves of n_T * (sources in its strong list) */
+    int64_t n_m2l_pairs;       /* weak-list entries over all levels */
+    int64_t n_strong_entries;  /* finest-level strong-list entries */
+    int p, precision, max_levels, nprob;
+    double theta;
+    /* microseconds of the last timed fmm_evaluate / fmm_evaluate_adjoint
+       phases (0 unless FMM_FLAG_PHASE_TIMING) */
+    double t_upward_us, t_m2l_us, t_downward_us, t_p2p_us, t_total_us;
+    double t_tree_us, t_plan_us;   /* last fmm_build_tree / fmm_plan device time, if timed */
+} fmm_stats;
+
+/*
+ * fmm_build_tree -- balanced median-split tree of Sec. 2.2 for nprob
+ * independent problems.
+ *   z        DEVICE, complex [offsets[nprob]]: source positions, input order.
+ *   offsets  HOST, int64 [nprob+1], offsets[0] = 0, nondecreasing.
+ *   nprob    >= 1.
+ *   n_levels HOST, int [nprob]: levels per problem, 1 <= L <= 16 with
+ *            4^(L-1) <= N_b (no empty box), N_b = offsets[b+1]-offsets[b] >= 1.
+ *   stream   hipStream_t.
+ *   out      receives the handle.
+ * Split rule (the paper defers details to its code; the reading used here):
+ * every box is split in four by two successive binary splits; each binary
+ * split cuts the longer side of the tight bounding box of the points being
+ * split (x when equal) and puts the floor(n/2) points smallest in
+ * (coordinate, input index) in the first half.  Box geometry: tight bounding
+ * box, centre at its midpoint, radius = half its diagonal.  The tree copies
+ * the positions: z may be freed once the stream has passed this call.
+ * Non-finite positions give FMM_EINVAL (detected on the device; the call
+ * synchronises `stream` once to read the flag).
+ */
+int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int* n_levels,
+                   void* stream, fmm_tree_t* out);
+
+/*
+ * fmm_tree_update_positions -- replace the positions of an existing tree
+ * while keeping its geometry (box centres, radii, membership) frozen.
+ *   z  DEVICE, complex [N], input order.
+ * Plans built on the tree then evaluate the FMM of the new positions with
+ * the old geometry: the operator whose exact derivative fmm_evaluate_adjoint
+ * returns (used for finite-difference checks and small position updates).
+ */
+int fmm_tree_update_positions(fmm_tree_t t, const double* z, void* stream);
+
+void fmm_tree_destroy(fmm_tree_t t);
+
+/*
+ * fmm_plan -- connectivity lists and launch structures for one (p, theta,
+ * precision) on a tree (Sec. 2.1: self is strongly coupled; children of a
+ * strong pair are strong unless the theta-criterion (2.3) R + theta r <=
+ * theta d holds, then weak; children of weak pairs are decoupled; finest-level
+ * strong pairs are summed directly).
+ *   p          1 .. 32 expansion terms.
+ *   theta      0 < theta < 1.
+ *   precision  FMM_FP64 or FMM_MIXED.
+ *   tune       HOST, optional (NULL = automatic).
+ * The plan references the tree, which must outlive it.  Synchronises
+ * `stream` once (to size the lists).
+ */
+int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning* tune,
+             void* stream, fmm_plan_t* out);
+
+void fmm_plan_destroy(fmm_plan_t pl);
+
+/*
+ * fmm_evaluate -- phi = FMM(m) (Sec. 2.1, Fig. 2.2: P2M, M2M, M2L, L2L, L2P,
+ * P2P).
+ *   m    DEVICE, complex [N] strengths, input order.
+ *   phi  DEVICE, complex [N] output, input order (overwritten).
+ * The plan keeps the local expansions of the last call for the adjoint.
+ */
+int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream);
+
+/*
+ * fmm_evaluate_parts -- same operator, near field (P2P) and far field
+ * (expansions) returned separately; phi = near + far.  Either pointer may be
+ * NULL.  For diagnostics and parity tests.
+ */
+int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double* phi_far,
+                       void* stream);
+
+/*
+ * fmm_evaluate_adjoint -- gradients of a real loss L through phi = FMM(m; z)
+ * with the tree geometry frozen.  Convention: for a complex w,
+ * G_w = dL/dRe(w) + i dL/dIm(w).
+ *   m      DEVICE, complex [N], the strengths of the forward call.
+ *   g_phi  DEVICE, complex [N], G_phi (input order).
+ *   g_m    DEVICE, complex [N], output G_m (may be NULL).
+ *   g_z    DEVICE, complex [N], output G_z (may be NULL).
+ * Runs the transposed chain (P2P^T, L2P^T, L2L^T, M2L^T, M2M^T, P2M^T) plus
+ * the position derivatives of P2P, P2M and L2P.  Needs a preceding
+ * fmm_evaluate with the same m on this plan (it reuses its local expansions).
+ */
+int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi,
+                         double* g_m, double* g_z, void* stream);
+
+/* Fill *st (HOST).  Does not synchronise. */
+int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st);
+
+/* ---- inspection (copies to HOST, synchronise `stream`) ------------------ */
+
+/*
+ * fmm_tree_layout -- sizes of problem `prob`: *n_levels, *n_points and the
+ * number of boxes over all levels ((4^L - 1)/3).
+ */
+int fmm_tree_layout(fmm_tree_t t, int prob, int* n_levels, int64_t* n_points, int64_t* n_boxes);
+
+/*
+ * fmm_tree_download -- tree of problem `prob`, boxes numbered level by level
+ * (box b of level l has index (4^l-1)/3 + b):
+ *   perm   int64 [N_b]: input index (within the problem) of tree position t.
+ *   range  int64 [n_boxes][2]: first tree position and point count per box.
+ *   geom   double [n_boxes][7]: xmin, xmax, ymin, ymax, cx, cy, r.
+ * Any pointer may be NULL.
+ */
+int fmm_tree_download(fmm_tree_t t, int prob, int64_t* perm, int64_t* range, double* geom,
+                      void* stream);
+
+/*
+ * fmm_plan_list_size / fmm_plan_download_list -- connectivity of problem
+ * `prob` at `level`, kind 0 = strong, 1 = weak, CSR over level-local box
+ * indices: off int64 [4^level + 1], ids int64 [*n_entries], ascending per box.
+ */
+int fmm_plan_list_size(fmm_plan_t pl, int prob, int level, int kind, int64_t* n_entries);
+int fmm_plan_download_list(fmm_plan_t pl, int prob, int level, int kind, int64_t* off,
+                           int64_t* ids, void* stream);
+
+/* ---- autotuner (host only) ---------------------------------------------- */
+
+/*
+ * Directed-walk autotuner with cost capping, after Algorithm 4 (AT3b) of
+ * Sec. 4.2, over the integer knobs N_levels, P2P split and M2L batch, fed one
+ * measured iteration time per call.  Rules kept from Sec. 4.2: a move is
+ * accepted or rejected on the timings that follow it, noise is handled by
+ * using the minimum time over a short window, a rejected move reverses the
+ * direction, and after a rejected N_levels move the next move in that
+ * direction is scheduled so that the accumulated cost of rejected moves
+ * stays below `cap` times the accumulated run time.
+ */
+typedef struct fmm_tuner_s* fmm_tuner_t;
+
+typedef struct {
+    int n_levels, p2p_split, m2l_batch;
+} fmm_tuner_params;
+
+typedef struct {
+    fmm_tuner_params init;      /* starting point */
+    int min_levels, max_levels; /* N_levels range (inclusive) */
+    double cap;                 /* max tuning cost / run time, e.g. 0.1 */
+    int window;                 /* iterations whose minimum time decides a move (>= 1) */
+    int knob_interval;          /* iterations between P2P/M2L knob moves (>= 1) */
+} fmm_tuner_config;
+
+int fmm_tuner_create(const fmm_tuner_config* cfg, fmm_tuner_t* out);
+/* parameters to use for the next FMM call */
+int fmm_tuner_next(fmm_tuner_t tu, fmm_tuner_params* out);
+/* report the measured time (seconds) of the call made with the last parameters */
+int fmm_tuner_observe(fmm_tuner_t tu, double seconds);
+/* current best parameters and the tuning cost spent so far */
+int fmm_tuner_best(fmm_tuner_t tu, fmm_tuner_params* best, double* cost_s, double* run_s);
+void fmm_tuner_destroy(fmm_tuner_t tu);
+
+/* Expansion order from tolerance: smallest p with the rule
+ * p = ceil(ln(17 TOL (1-theta)) / ln theta), which reproduces Table 4.1. */
+int fmm_p_from_tol(double tol, double theta);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* fmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

@@ -53,6 +53,8 @@ def lib():
         L.oracle_fmm.restype = C.c_int
         L.oracle_p_from_tol.argtypes = [C.c_double, C.c_double]
         L.oracle_p_from_tol.restype = C.c_int
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -217,6 +219,11 @@ def l2p(c, b, z):
 
 def p_from_tol(tol, theta):
     return int(lib().oracle_p_from_tol(tol, theta))
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 def rel_err2(phi, ref):

@@ -34,6 +34,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double re, im; } cplx;
 
@@ -605,4 +608,14 @@ int oracle_p_from_tol(double tol, double theta)
 {
     double v = log(17.0 * tol * (1.0 - theta)) / log(theta);
     return (int)ceil(v);
+}
+
+/* threads the OpenMP loops of this file use */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

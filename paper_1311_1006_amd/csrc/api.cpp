@@ -1,0 +1,458 @@
+// api.cpp -- the C ABI of include/fmm.h: argument validation, handle
+// lifetimes, a stream-ordered caching device allocator and the cache of tree
+// schedules (they depend only on the problem sizes and level counts).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "fmm_internal.h"
+#include "plan_extra.h"
+
+namespace fmm {
+
+// -------------------------------------------------------------- allocator
+// Blocks are never returned to the driver while the process lives (hipFree
+// synchronises the device); a freed block is reused for a request of the
+// same size class.  Blocks remember the stream of their last use; reuse on a
+// different stream first waits for that stream.
+namespace {
+struct Block {
+    void* p;
+    size_t cls;
+    hipStream_t s;
+};
+std::mutex g_mu;
+std::multimap<size_t, Block> g_free;
+std::map<void*, size_t> g_cls;
+
+size_t size_class(size_t b)
+{
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s)
+{
+    size_t c = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_free.find(c);
+        if (it != g_free.end()) {
+            Block b = it->second;
+            g_free.erase(it);
+            if (b.s != s) FMM_HIP(hipStreamSynchronize(b.s));
+            return b.p;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, c);
+    if (e != hipSuccess) {
+        // release cached blocks and retry once
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            for (auto& kv : g_free) drop.push_back(kv.second.p);
+            g_free.clear();
+        }
+        (void)hipDeviceSynchronize();
+        for (void* q : drop) {
+            (void)hipFree(q);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_cls.erase(q);
+        }
+        (void)hipGetLastError();
+        e = hipMalloc(&p, c);
+        if (e != hipSuccess) throw Error(FMM_ENOMEM, "device allocation of " + std::to_string(c) + " bytes failed");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cls[p] = c;
+    return p;
+}
+
+void dev_free(void* p, hipStream_t s)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cls.find(p);
+    if (it == g_cls.end()) return;
+    g_free.insert({it->second, Block{p, it->second, s}});
+}
+
+// --------------------------------------------------------- schedule cache
+namespace {
+struct SchedKey {
+    std::vector<int64_t> off;
+    std::vector<int> L;
+    bool operator<(const SchedKey& o) const { return off != o.off ? off < o.off : L < o.L; }
+};
+}  // namespace
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(const std::exception& e)
+{
+    if (auto* fe = dynamic_cast<const Error*>(&e)) {
+        g_err = fe->what();
+        return fe->code;
+    }
+    g_err = e.what();
+    return FMM_EDEVICE;
+}
+
+template <class F>
+static int guarded(F&& f)
+{
+    try {
+        g_err.clear();
+        f();
+        return FMM_OK;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return FMM_ENOMEM;
+    } catch (const std::exception& e) {
+        return fail(e);
+    }
+}
+
+static void check_device_state()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(FMM_EDEVICE, std::string("earlier device error: ") + hipGetErrorString(e));
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+struct fmm_tree_s {
+    Tree t;
+    std::vector<int64_t> off;
+    std::vector<int> L;
+};
+struct fmm_plan_s {
+    Plan pl;
+    fmm_tree_s* tree;
+};
+
+extern "C" {
+
+const char* fmm_last_error(void) { return g_err.c_str(); }
+
+int fmm_p_from_tol(double tol, double theta)
+{
+    if (!(tol > 0.0 && tol < 1.0) || !(theta > 0.0 && theta < 1.0)) {
+        g_err = "fmm_p_from_tol: need 0 < tol < 1 and 0 < theta < 1";
+        return FMM_EINVAL;
+    }
+    // p ~ log TOL / log theta (Sec. 2.3); the constant 17 and the geometric
+    // tail (1 - theta) reproduce Table 4.1
+    return (int)std::ceil(std::log(17.0 * tol * (1.0 - theta)) / std::log(theta));
+}
+
+int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int* n_levels, void* stream,
+                   fmm_tree_t* out)
+{
+    return guarded([&] {
+        FMM_REQUIRE(out, "out is NULL");
+        *out = nullptr;
+        FMM_REQUIRE(nprob >= 1, "nprob must be >= 1");
+        FMM_REQUIRE(offsets && n_levels, "offsets / n_levels are NULL");
+        FMM_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
+        std::vector<int64_t> off(offsets, offsets + nprob + 1);
+        std::vector<int> L(n_levels, n_levels + nprob);
+        for (int b = 0; b < nprob; ++b) {
+            int64_t nb = off[b + 1] - off[b];
+            FMM_REQUIRE(nb >= 1, "every problem needs at least one point");
+            FMM_REQUIRE(L[b] >= 1 && L[b] <= kMaxLevels, "n_levels out of range [1, 16]");
+            FMM_REQUIRE((int64_t(1) << (2 * (L[b] - 1))) <= nb, "4^(n_levels-1) must not exceed the point count");
+            FMM_REQUIRE(nb <= 100000000, "at most 1e8 points per problem");
+        }
+        FMM_REQUIRE(off[nprob] < (int64_t(1) << 31) - 1, "at most 2^31-2 points in total");
+        FMM_REQUIRE(z != nullptr, "z is NULL");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        static std::mutex mu;
+        static std::map<SchedKey, std::shared_ptr<TreeSchedule>> cache;
+        std::shared_ptr<TreeSchedule> sched;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            SchedKey k{off, L};
+            auto it = cache.find(k);
+            if (it != cache.end()) sched = it->second;
+        }
+        if (!sched) {
+            sched.reset(make_schedule(off, L));
+            upload_schedule(*sched, s);
+            std::lock_guard<std::mutex> lk(mu);
+            if (cache.size() > 16) cache.clear();
+            cache[SchedKey{off, L}] = sched;
+        }
+        auto tr = std::make_unique<fmm_tree_s>();
+        tr->off = off;
+        tr->L = L;
+        tr->t.stream = s;
+        // the schedule is shared with the cache: keep a reference in the tree
+        tr->t.sched = sched.get();
+        tr->t.sched_ref = sched;
+        build_tree_device(tr->t, z, s);
+        *out = tr.release();
+    });
+}
+
+int fmm_tree_update_positions(fmm_tree_t t, const double* z, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(t && z, "NULL argument");
+        check_device_state();
+        update_positions_device(t->t, z, (hipStream_t)stream);
+    });
+}
+
+void fmm_tree_destroy(fmm_tree_t t) { delete t; }
+
+int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning* tune, void* stream,
+             fmm_plan_t* out)
+{
+    return guarded([&] {
+        FMM_REQUIRE(out, "out is NULL");
+        *out = nullptr;
+        FMM_REQUIRE(t, "tree is NULL");
+        FMM_REQUIRE(p >= 1 && p <= kMaxP, "p must be in [1, 32]");
+        FMM_REQUIRE(theta > 0.0 && theta < 1.0, "theta must be in (0, 1)");
+        FMM_REQUIRE(precision == FMM_FP64 || precision == FMM_MIXED, "unknown precision");
+        fmm_tuning tn{};
+        if (tune) tn = *tune;
+        FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4 ||
+                        tn.p2p_split == 8 || tn.p2p_split == 16,
+                    "p2p_split must be 0, 1, 2, 4, 8 or 16");
+        FMM_REQUIRE(tn.m2l_batch == 0 || (tn.m2l_batch >= 8 && tn.m2l_batch <= 64 && tn.m2l_batch % 8 == 0),
+                    "m2l_batch must be 0 or a multiple of 8 in [8, 64]");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        auto pp = std::make_unique<fmm_plan_s>();
+        pp->tree = t;
+        Plan& pl = pp->pl;
+        pl.tree = &t->t;
+        pl.p = p;
+        pl.theta = theta;
+        pl.precision = precision;
+        pl.tune = tn;
+        pl.ex = new PlanExtra();
+        prepare_plan_host(pl, *pl.ex, s);
+        build_lists_device(pl, s);
+        alloc_eval_buffers(pl, s);
+        *out = pp.release();
+    });
+}
+
+void fmm_plan_destroy(fmm_plan_t pl)
+{
+    if (!pl) return;
+    if (pl->pl.graph) (void)hipGraphExecDestroy(pl->pl.graph);
+    delete pl->pl.ex;
+    delete pl;
+}
+
+int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m && phi, "NULL argument");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        Plan& P = pl->pl;
+        if (P.tune.flags & FMM_FLAG_GRAPH) {
+            if (!P.graph || P.graph_m != m || P.graph_phi != phi || P.graph_stream != s) {
+                if (P.graph) { FMM_HIP(hipGraphExecDestroy(P.graph)); P.graph = nullptr; }
+                hipGraph_t g;
+                FMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                int saved = P.tune.flags;
+                P.tune.flags &= ~FMM_FLAG_PHASE_TIMING;
+                try {
+                    evaluate_device(P, m, phi, nullptr, nullptr, s);
+                } catch (...) {
+                    P.tune.flags = saved;
+                    hipGraph_t dead;
+                    (void)hipStreamEndCapture(s, &dead);
+                    if (dead) (void)hipGraphDestroy(dead);
+                    throw;
+                }
+                P.tune.flags = saved;
+                FMM_HIP(hipStreamEndCapture(s, &g));
+                hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) throw Error(FMM_EDEVICE, "hipGraphInstantiate failed");
+                P.graph_m = m;
+                P.graph_phi = phi;
+                P.graph_stream = s;
+            }
+            FMM_HIP(hipGraphLaunch(P.graph, s));
+            P.have_forward = true;
+        } else {
+            evaluate_device(P, m, phi, nullptr, nullptr, s);
+        }
+        P.last_m = m;
+    });
+}
+
+int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double* phi_far, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m, "NULL argument");
+        check_device_state();
+        evaluate_device(pl->pl, m, nullptr, phi_near, phi_far, (hipStream_t)stream);
+        pl->pl.last_m = m;
+    });
+}
+
+int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, double* g_m, double* g_z,
+                         void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m && g_phi, "NULL argument");
+        if (!pl->pl.have_forward) throw Error(FMM_ESTATE, "fmm_evaluate_adjoint needs a preceding fmm_evaluate");
+        check_device_state();
+        adjoint_device(pl->pl, m, g_phi, g_m, g_z, (hipStream_t)stream);
+    });
+}
+
+int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && st, "NULL argument");
+        Plan& P = pl->pl;
+        TreeSchedule& sc = *P.tree->sched;
+        std::memset(st, 0, sizeof(*st));
+        st->n_points = sc.n;
+        st->n_boxes = sc.nbox;
+        st->n_leaves = sc.nleaf;
+        st->n_p2p_pairs = P.n_p2p_pairs;
+        st->n_m2l_pairs = P.n_weak;
+        st->n_strong_entries = P.n_strong;
+        st->p = P.p;
+        st->precision = P.precision;
+        st->max_levels = sc.max_levels;
+        st->nprob = sc.nprob;
+        st->theta = P.theta;
+        st->t_upward_us = P.t_up;
+        st->t_m2l_us = P.t_m2l;
+        st->t_p2p_us = P.t_p2p;
+        st->t_downward_us = P.t_down;
+        st->t_total_us = P.t_total;
+        st->t_tree_us = P.tree->t_build_us;
+        st->t_plan_us = P.t_plan_us;
+    });
+}
+
+int fmm_tree_layout(fmm_tree_t t, int prob, int* n_levels, int64_t* n_points, int64_t* n_boxes)
+{
+    return guarded([&] {
+        FMM_REQUIRE(t, "NULL tree");
+        FMM_REQUIRE(prob >= 0 && prob < (int)t->L.size(), "problem index out of range");
+        if (n_levels) *n_levels = t->L[prob];
+        if (n_points) *n_points = t->off[prob + 1] - t->off[prob];
+        if (n_boxes) *n_boxes = nbox_levels(t->L[prob]);
+    });
+}
+
+int fmm_tree_download(fmm_tree_t t, int prob, int64_t* perm, int64_t* range, double* geom, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(t, "NULL tree");
+        FMM_REQUIRE(prob >= 0 && prob < (int)t->L.size(), "problem index out of range");
+        hipStream_t s = (hipStream_t)stream;
+        TreeSchedule& sc = *t->t.sched;
+        int64_t o = t->off[prob], n = t->off[prob + 1] - o;
+        int64_t nb = nbox_levels(t->L[prob]), b0 = sc.pbox[prob];
+        std::vector<int32_t> pm(n);
+        std::vector<double> bb(4 * nb), gm(4 * nb);
+        FMM_HIP(hipMemcpyAsync(pm.data(), t->t.perm.p + o, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipMemcpyAsync(bb.data(), t->t.bbox.p + 4 * b0, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipMemcpyAsync(gm.data(), t->t.geom.p + 4 * b0, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        if (perm)
+            for (int64_t i = 0; i < n; ++i) perm[i] = pm[i] - o;
+        if (range)
+            for (int64_t b = 0; b < nb; ++b) {
+                range[2 * b] = sc.box_start[b0 + b] - o;
+                range[2 * b + 1] = sc.box_count[b0 + b];
+            }
+        if (geom)
+            for (int64_t b = 0; b < nb; ++b) {
+                for (int c = 0; c < 4; ++c) geom[7 * b + c] = bb[4 * b + c];
+                for (int c = 0; c < 3; ++c) geom[7 * b + 4 + c] = gm[4 * b + c];
+            }
+    });
+}
+
+static void list_host(fmm_plan_t pl, int prob, int level, int kind, std::vector<int32_t>& beg,
+                      std::vector<int32_t>& cnt, std::vector<int32_t>& ids, hipStream_t s)
+{
+    Plan& P = pl->pl;
+    TreeSchedule& sc = *P.tree->sched;
+    FMM_REQUIRE(prob >= 0 && prob < sc.nprob, "problem index out of range");
+    FMM_REQUIRE(level >= 0 && level < sc.L[prob], "level out of range");
+    FMM_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (strong) or 1 (weak)");
+    int64_t nb = int64_t(1) << (2 * level);
+    int64_t b0 = sc.pbox[prob] + level_base(level);
+    beg.resize(nb);
+    cnt.resize(nb);
+    const int32_t* db = kind ? P.w_beg.p : P.s_beg.p;
+    const int32_t* dc = kind ? P.w_cnt.p : P.s_cnt.p;
+    FMM_HIP(hipMemcpyAsync(beg.data(), db + b0, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(cnt.data(), dc + b0, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    int64_t tot = 0;
+    for (int64_t b = 0; b < nb; ++b) tot += cnt[b];
+    ids.clear();
+    ids.reserve(tot);
+    const int32_t* di = kind ? P.w_ids.p : P.s_ids.p;
+    // the boxes of one level occupy one contiguous run of the pool
+    if (tot) {
+        int64_t first = beg[0];
+        std::vector<int32_t> run(tot);
+        FMM_HIP(hipMemcpyAsync(run.data(), di + first, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        for (int64_t b = 0; b < nb; ++b)
+            for (int e = 0; e < cnt[b]; ++e) ids.push_back(run[beg[b] - first + e]);
+    }
+}
+
+int fmm_plan_list_size(fmm_plan_t pl, int prob, int level, int kind, int64_t* n_entries)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && n_entries, "NULL argument");
+        std::vector<int32_t> b, c, ids;
+        list_host(pl, prob, level, kind, b, c, ids, nullptr);
+        *n_entries = (int64_t)ids.size();
+    });
+}
+
+int fmm_plan_download_list(fmm_plan_t pl, int prob, int level, int kind, int64_t* off, int64_t* ids,
+                           void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl, "NULL plan");
+        std::vector<int32_t> b, c, id;
+        list_host(pl, prob, level, kind, b, c, id, (hipStream_t)stream);
+        TreeSchedule& sc = *pl->pl.tree->sched;
+        int64_t base = sc.pbox[prob] + level_base(level);
+        int64_t acc = 0;
+        for (size_t i = 0; i < c.size(); ++i) {
+            if (off) off[i] = acc;
+            acc += c[i];
+        }
+        if (off) off[c.size()] = acc;
+        if (ids)
+            for (size_t i = 0; i < id.size(); ++i) ids[i] = id[i] - base;
+    });
+}
+
+}  // extern "C"

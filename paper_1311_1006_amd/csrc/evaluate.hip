@@ -1,0 +1,266 @@
+// evaluate.hip -- the FMM evaluation sequence (Sec. 2.1, Fig. 2.2) and the
+// host-side work lists of a plan.
+//
+//   gather  strengths to tree order, P2P source records
+//   P2M     leaves of every problem
+//   M2M     level by level, deepest parents first
+//   M2L     every box over its weak list (writes the box's local expansion)
+//   L2L     level by level from level 2 down (adds the parent's expansion)
+//   P2P     leaves over their strong lists (near field, tree order)
+//   L2P     leaves: far field + near field, scattered to input order
+#include <algorithm>
+#include <cstring>
+
+#include "fmm_internal.h"
+#include "plan_extra.h"
+
+namespace fmm {
+
+void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
+                   const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
+template <class T>
+void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
+                const double*, int, void*, hipStream_t);
+template <class T>
+void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
+template <class T>
+void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
+template <class T>
+void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
+                const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
+template <class T>
+void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
+                int, const void*, void*, hipStream_t);
+void launch_p2p(bool mixed, int ns, int r, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
+                const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src, const void* lo,
+                double* out, hipStream_t s);
+
+struct P2PItemH {
+    int32_t leaf, t0, tn, pad;
+};
+
+// P2P launch shape for a leaf size: targets per lane-group and source splits
+static void p2p_shape(int nt, int split_knob, int* ns, int* r)
+{
+    int s;
+    if (split_knob > 0) s = split_knob;
+    else if (nt <= 16) s = 4;
+    else if (nt <= 32) s = 2;
+    else s = 1;
+    int tw = 64 / s;
+    int rr = (nt + tw - 1) / tw;
+    rr = rr <= 1 ? 1 : (rr <= 2 ? 2 : 4);
+    *ns = s;
+    *r = rr;
+}
+
+template <class T>
+static void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(std::max<size_t>(h.size(), 1), s);
+    if (!h.empty())
+        FMM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
+{
+    TreeSchedule& sc = *pl.tree->sched;
+    int ml = sc.max_levels;
+    pl.level_boxes.assign(ml, {});
+    ex.m2m_boxes.assign(ml, {});
+    std::vector<int32_t> leaves, child0(sc.nbox, -1);
+    for (int b = 0; b < sc.nprob; ++b) {
+        for (int l = 0; l < sc.L[b]; ++l) {
+            int64_t base = sc.pbox[b] + level_base(l);
+            for (int64_t j = 0; j < (int64_t(1) << (2 * l)); ++j) {
+                int32_t id = (int32_t)(base + j);
+                pl.level_boxes[l].push_back(id);
+                if (l + 1 < sc.L[b]) {
+                    child0[id] = (int32_t)(sc.pbox[b] + level_base(l + 1) + 4 * j);
+                    ex.m2m_boxes[l].push_back(id);
+                } else {
+                    leaves.push_back(id);
+                }
+            }
+        }
+    }
+    std::vector<int32_t> all;
+    pl.level_boxes_off.assign(ml + 1, 0);
+    for (int l = 0; l < ml; ++l) {
+        pl.level_boxes_off[l] = (int64_t)all.size();
+        all.insert(all.end(), pl.level_boxes[l].begin(), pl.level_boxes[l].end());
+    }
+    pl.level_boxes_off[ml] = (int64_t)all.size();
+    upload_vec(pl.d_level_boxes, all, s);
+    upload_vec(pl.leaves, leaves, s);
+    upload_vec(ex.child0, child0, s);
+    std::vector<int32_t> m2m;
+    ex.m2m_off.assign(ml + 1, 0);
+    for (int l = 0; l < ml; ++l) {
+        ex.m2m_off[l] = (int64_t)m2m.size();
+        m2m.insert(m2m.end(), ex.m2m_boxes[l].begin(), ex.m2m_boxes[l].end());
+    }
+    ex.m2m_off[ml] = (int64_t)m2m.size();
+    upload_vec(ex.d_m2m, m2m, s);
+    std::vector<int32_t> iota(sc.nbox);
+    for (int64_t i = 0; i < sc.nbox; ++i) iota[i] = (int32_t)i;
+    upload_vec(ex.all_boxes, iota, s);
+    // P2P work items grouped by launch shape
+    std::vector<std::vector<P2PItemH>> cls(5 * 3);
+    auto ci = [](int ns, int r) {
+        int a = ns == 1 ? 0 : ns == 2 ? 1 : ns == 4 ? 2 : ns == 8 ? 3 : 4;
+        int b = r == 1 ? 0 : r == 2 ? 1 : 2;
+        return a * 3 + b;
+    };
+    for (int32_t g : leaves) {
+        int nt = sc.box_count[g];
+        int ns, r;
+        p2p_shape(nt, pl.tune.p2p_split, &ns, &r);
+        int chunk = (64 / ns) * r;
+        for (int t0 = 0; t0 < nt; t0 += chunk) {
+            P2PItemH it{g, t0, std::min(chunk, nt - t0), 0};
+            cls[ci(ns, r)].push_back(it);
+        }
+    }
+    std::vector<P2PItemH> items;
+    ex.p2p_class.clear();
+    const int nsv[5] = {1, 2, 4, 8, 16}, rv[3] = {1, 2, 4};
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 3; ++b) {
+            auto& v = cls[a * 3 + b];
+            if (v.empty()) continue;
+            ex.p2p_class.push_back({nsv[a], rv[b], (int64_t)items.size(), (int64_t)v.size()});
+            items.insert(items.end(), v.begin(), v.end());
+        }
+    {
+        std::vector<char> raw(items.size() * sizeof(P2PItemH));
+        if (!items.empty()) std::memcpy(raw.data(), items.data(), raw.size());
+        upload_vec(ex.p2p_items, raw, s);
+    }
+    // binomial table C(n, k), n, k < 64
+    std::vector<double> bin(64 * 64, 0.0);
+    for (int n = 0; n < 64; ++n) {
+        bin[n * 64] = 1.0;
+        for (int k = 1; k <= n; ++k) bin[n * 64 + k] = bin[(n - 1) * 64 + k - 1] + (k < n ? bin[(n - 1) * 64 + k] : 0.0);
+    }
+    upload_vec(pl.binom, bin, s);
+    FMM_HIP(hipStreamSynchronize(s));
+}
+
+void alloc_eval_buffers(Plan& pl, hipStream_t s)
+{
+    TreeSchedule& sc = *pl.tree->sched;
+    int64_t n = sc.n;
+    bool mixed = pl.precision == FMM_MIXED;
+    size_t cs = mixed ? sizeof(float) : sizeof(double);
+    pl.mtree.alloc(2 * n, s);
+    pl.near.alloc(2 * n, s);
+    if (mixed) { pl.src32.alloc(4 * n, s); pl.srclo.alloc(2 * n, s); }
+    else pl.src64.alloc(4 * n, s);
+    pl.mpole.alloc(2 * cs * sc.nbox * pl.p, s);
+    pl.local.alloc(2 * cs * sc.nbox * pl.p, s);
+}
+
+template <class T>
+static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    launch_p2m<T>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, mt, pl.p,
+                  mp, s);
+    for (int l = sc.max_levels - 2; l >= 1; --l) {
+        int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
+        launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, pl.binom.p, pl.p, mp, s);
+    }
+}
+
+template <class T>
+static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, pl.binom.p, pl.p, mp,
+                  loc, s);
+    for (int l = 2; l < sc.max_levels; ++l) {
+        int n = (int)pl.level_boxes[l].size();
+        launch_l2l<T>(pl.d_level_boxes.p + pl.level_boxes_off[l], n, sc.d_box_parent.p, t.geom.p, pl.binom.p,
+                      pl.p, loc, s);
+    }
+}
+
+static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    bool mixed = pl.precision == FMM_MIXED;
+    for (auto& c : ex.p2p_class) {
+        const char* items = (const char*)ex.p2p_items.p + c.off * sizeof(P2PItemH);
+        launch_p2p(mixed, c.ns, c.r, items, (int)c.n, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
+                   pl.s_ids.p, mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
+                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s);
+    }
+}
+
+struct PhaseTimer {
+    bool on;
+    hipStream_t s;
+    hipEvent_t ev[6];
+    int k = 0;
+    PhaseTimer(bool o, hipStream_t st) : on(o), s(st)
+    {
+        if (on)
+            for (auto& e : ev) FMM_HIP(hipEventCreate(&e));
+    }
+    void mark()
+    {
+        if (on) FMM_HIP(hipEventRecord(ev[k++], s));
+    }
+    float between(int a, int b)
+    {
+        float ms = 0;
+        FMM_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        return ms * 1000.0f;
+    }
+    ~PhaseTimer()
+    {
+        if (on)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *extra(pl);
+    bool mixed = pl.precision == FMM_MIXED;
+    PhaseTimer tm((pl.tune.flags & FMM_FLAG_PHASE_TIMING) != 0, s);
+    tm.mark();
+    launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    tm.mark();
+    if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s);
+    else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s);
+    tm.mark();
+    run_p2p(pl, ex, s);
+    tm.mark();
+    if (mixed)
+        launch_l2p<float>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+                          pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
+    else
+        launch_l2p<double>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
+    tm.mark();
+    if (tm.on) {
+        FMM_HIP(hipEventSynchronize(tm.ev[4]));
+        pl.t_up = tm.between(0, 1);
+        pl.t_m2l = tm.between(1, 2);
+        pl.t_p2p = tm.between(2, 3);
+        pl.t_down = tm.between(3, 4);
+        pl.t_total = tm.between(0, 4);
+    }
+    pl.have_forward = true;
+}
+
+}  // namespace fmm

@@ -1,0 +1,219 @@
+// fmm_internal.h -- shared declarations of the HIP FMM library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define FMM_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::fmm::Error(e_ == hipErrorOutOfMemory ? FMM_ENOMEM : FMM_EDEVICE,      \
+                               std::string(#call) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+#define FMM_REQUIRE(cond, msg)                                                            \
+    do {                                                                                  \
+        if (!(cond)) throw ::fmm::Error(FMM_EINVAL, msg);                                 \
+    } while (0)
+
+inline void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        throw Error(FMM_EDEVICE, std::string("launch ") + what + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------- constants
+constexpr int kMaxLevels = 16;
+constexpr int kMaxP = 32;
+// tree build
+constexpr int kTile = 2048;        // points per workgroup tile in the global split stages
+constexpr int kTileThreads = 256;
+constexpr int kBuckets = 2048;     // histogram buckets per level of bucket selection
+constexpr int kCandCap = 2048;     // candidates sorted in LDS by one workgroup
+constexpr int kLdsCap = 4096;      // segments at most this large finish in one workgroup
+
+__host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+__host__ __device__ inline int64_t nbox_levels(int L) { return level_base(L); }
+
+// ---------------------------------------------------------- device memory
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void alloc(size_t count, hipStream_t st) {
+        release();
+        s = st;
+        n = count;
+        if (count) p = static_cast<T*>(dev_alloc(count * sizeof(T), st));
+    }
+    void release() {
+        if (p) dev_free(p, s);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ------------------------------------------------------------ tree layout
+// Per-stage bookkeeping of the global split stages (one binary split per
+// stage; level l's boxes are the segments of stage 2l).
+struct SegInfo {      // one segment of one stage
+    int32_t start;    // first point (global position)
+    int32_t count;
+    int32_t tile0;    // first tile (stage-local)
+    int32_t ntile;
+    int32_t child;    // stage-local index of the lower child in the next stage's arrays
+    int32_t box;      // global box id if this stage is even (a level), else -1
+    int32_t pad0, pad1;
+};
+struct TileInfo {
+    int32_t seg;      // stage-local segment
+    int32_t start;    // first point
+    int32_t count;
+    int32_t rank;     // tile index within its segment
+};
+struct LdsWork {      // one segment finished by the in-LDS split kernel
+    int32_t start, count;
+    int32_t stages;   // binary splits still to do
+    int32_t stage0;   // stage of the segment
+    int32_t j0;       // segment index at stage0 within its problem
+    int32_t boxbase;  // global id of the problem's box 0 (root)
+    int32_t pad0, pad1;
+};
+struct GeomJob {      // a box whose geometry comes from the bbox keys of a global stage
+    int32_t box;
+    int32_t seg;      // index into the stage's bbox key array (absolute, see keys_off)
+};
+
+struct TreeSchedule {
+    int nprob = 0;
+    int64_t n = 0;
+    std::vector<int64_t> off;
+    std::vector<int> L;
+    std::vector<int64_t> pbox;      // first global box id per problem
+    int64_t nbox = 0, nleaf = 0;
+    int nstage = 0;                 // number of global stages
+    std::vector<int> nseg, ntile;   // per global stage (active segments / tiles)
+    std::vector<int64_t> seg_off, tile_off, keys_off;   // offsets into packed arrays
+    std::vector<int> nkeys;         // bbox-key segments per stage (stage 0..nstage)
+    int64_t total_seg = 0, total_tile = 0, total_keys = 0;
+    std::vector<SegInfo> segs;
+    std::vector<TileInfo> tiles;
+    std::vector<int32_t> key_child_dummy;
+    std::vector<LdsWork> lds;
+    std::vector<GeomJob> geom;      // boxes whose geometry comes from global-stage keys
+    std::vector<int64_t> geom_stage_off;  // geom jobs grouped by stage
+    std::vector<TileInfo> copy_tiles;     // big-leaf problems: copy to final order
+    std::vector<int32_t> box_start, box_count;
+    std::vector<int32_t> box_parent;      // global id of the parent (-1 for roots)
+    std::vector<int8_t> box_level;
+    std::vector<int32_t> box_prob;
+    int max_levels = 0;
+    // device copies
+    DBuf<SegInfo> d_segs;
+    DBuf<TileInfo> d_tiles, d_copy;
+    DBuf<LdsWork> d_lds;
+    DBuf<GeomJob> d_geom;
+    DBuf<int32_t> d_box_start, d_box_count, d_box_parent;
+    DBuf<int32_t> d_box_prob;
+    DBuf<int8_t> d_box_level;
+};
+
+struct Tree {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    TreeSchedule* sched = nullptr;   // shared with the schedule cache
+    std::shared_ptr<TreeSchedule> sched_ref;
+    // points in tree order
+    DBuf<double> x, y;
+    DBuf<int32_t> perm;       // tree position -> global input index
+    DBuf<int32_t> iperm;      // global input index -> tree position
+    // per box (global id)
+    DBuf<double> bbox;        // [nbox][4] xmin xmax ymin ymax
+    DBuf<double> geom;        // [nbox][4] cx cy r rs (rs = scaling radius)
+    double t_build_us = 0;
+};
+
+// ------------------------------------------------------------------ plans
+struct PlanExtra;
+
+struct Plan {
+    Tree* tree = nullptr;
+    PlanExtra* ex = nullptr;     // launch lists (owned)
+    int p = 0, precision = 0;
+    double theta = 0;
+    fmm_tuning tune{};
+    // connectivity, per global box: [begin, count) into the id pools
+    DBuf<int32_t> s_beg, s_cnt, w_beg, w_cnt;
+    DBuf<int32_t> s_ids, w_ids;    // global box ids
+    int64_t n_strong = 0, n_weak = 0;
+    std::vector<int64_t> level_nstrong, level_nweak;   // per (prob, level) not kept; totals only
+    // work lists
+    DBuf<int32_t> leaves;          // global ids of all leaves
+    DBuf<int32_t> m2l_targets;     // boxes with a nonempty weak list
+    int64_t n_m2l_targets = 0;
+    std::vector<std::vector<int32_t>> level_boxes;   // host: global ids per level (all problems)
+    DBuf<int32_t> d_level_boxes;   // concatenated per level
+    std::vector<int64_t> level_boxes_off;
+    int64_t n_p2p_pairs = 0;
+    // evaluation buffers
+    DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
+    DBuf<float> src32;             // [N][4] xh yh mr mi (mixed path)
+    DBuf<float> srclo;             // [N][2] xl yl
+    DBuf<double> mtree;            // [N][2] strengths in tree order (FP64)
+    DBuf<double> near;             // [N][2] P2P result, tree order
+    DBuf<char> mpole, local;       // [nbox][p] complex coefficients (T)
+    DBuf<double> binom;            // binomial table (p x p) for the expansion shifts
+    // adjoint buffers
+    DBuf<double> gtree;            // conj(G_phi) in tree order
+    DBuf<double> near_d;           // derivative sums of the adjoint P2P
+    DBuf<char> amp, aloc;          // adjoint coefficient arrays
+    bool have_forward = false;
+    const double* last_m = nullptr;
+    // timing
+    double t_plan_us = 0;
+    double t_up = 0, t_m2l = 0, t_down = 0, t_p2p = 0, t_total = 0;
+    // graph
+    hipGraphExec_t graph = nullptr;
+    const double* graph_m = nullptr;
+    double* graph_phi = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+// ---------------------------------------------------------- launchers
+void build_tree_device(Tree& t, const double* z, hipStream_t s);
+void update_positions_device(Tree& t, const double* z, hipStream_t s);
+void build_lists_device(Plan& pl, hipStream_t s);
+void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
+                     hipStream_t s);
+void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,
+                    hipStream_t s);
+
+TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<int>& L);
+void upload_schedule(TreeSchedule& sc, hipStream_t s);
+
+}  // namespace fmm

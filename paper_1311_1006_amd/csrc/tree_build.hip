@@ -1,0 +1,1047 @@
+// tree_build.hip -- balanced median-split tree (Sec. 2.2) on gfx950.
+//
+// Every box is split in four by two successive binary splits.  A binary
+// split cuts the longer side of the tight bounding box of the points being
+// split (x when equal) and sends the floor(n/2) points smallest in
+// (coordinate, input index) to the first half.  Because every split halves a
+// count exactly, the size and position of every segment depend on N only;
+// the host precomputes them and the device only decides membership.
+//
+// Device pipeline for one build (all problems of a batch at once):
+//   init        copy positions into SoA buffers, bounding box of each root,
+//               finiteness check;
+//   per global stage s (segments larger than one workgroup's LDS):
+//     hist1     2048-bucket histogram of the split coordinate per segment
+//               (buckets are equal-width in value between the segment's
+//               min and max, hence monotone in the coordinate);
+//     hist2     if the bucket holding the median rank has too many points,
+//               a second 2048-bucket histogram inside that bucket;
+//     select    each tile counts its points below the median's bucket and
+//               appends the points of that bucket to a candidate list; the
+//               last tile of a segment sorts the candidates, takes the exact
+//               median (coordinate, index) and turns per-tile counts into
+//               per-tile output offsets (an exact single-workgroup radix
+//               select is the fallback for pathological ties);
+//     partition stable two-way partition of every tile into the next
+//               buffer plus the bounding boxes of both halves (atomic
+//               min/max on order-preserving integer images of the doubles);
+//   lds split   each remaining segment (<= 4096 points) is finished by one
+//               workgroup: the points are sorted once by (x, index) and once
+//               by (y, index); every later split keeps both lists sorted by
+//               a stable partition of the list of the other axis;
+//   geometry    box centre (bbox midpoint) and radius (half diagonal),
+//               computed with explicitly rounded operations so that they are
+//               bit-identical to a plain IEEE evaluation, and the scaling
+//               radius (r, or the nearest ancestor's r when r = 0).
+// The point order inside a segment after a stable partition is a function of
+// the input order only, and the final order inside a leaf is sorted by
+// (x, index), so the whole build is deterministic.
+#include <algorithm>
+#include <cstring>
+
+#include "fmm_internal.h"
+
+// Box geometry, split axes and the theta-criterion must round every product
+// and sum on its own (no fused multiply-add), like a plain IEEE evaluation.
+#pragma clang fp contract(off)
+
+namespace fmm {
+
+// ------------------------------------------------------------------ schedule
+
+static void seg_range(int64_t off, int64_t n, int s, int64_t j, int64_t* start, int64_t* cnt)
+{
+    int64_t st = off, c = n;
+    for (int t = s - 1; t >= 0; --t) {
+        int64_t h = c / 2;
+        if ((j >> t) & 1) { st += h; c -= h; } else c = h;
+    }
+    *start = st; *cnt = c;
+}
+
+TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<int>& L)
+{
+    auto* sc = new TreeSchedule();
+    int nprob = (int)L.size();
+    sc->nprob = nprob;
+    sc->off = off;
+    sc->L = L;
+    sc->n = off[nprob];
+    sc->pbox.resize(nprob);
+    int64_t nb = 0, nl = 0;
+    std::vector<int> g(nprob), S(nprob);
+    std::vector<char> lds(nprob);
+    int nstage = 0;
+    for (int b = 0; b < nprob; ++b) {
+        sc->pbox[b] = nb;
+        nb += nbox_levels(L[b]);
+        nl += int64_t(1) << (2 * (L[b] - 1));
+        sc->max_levels = std::max(sc->max_levels, L[b]);
+        int64_t n = off[b + 1] - off[b];
+        S[b] = 2 * (L[b] - 1);
+        int gb = 0;
+        while (gb < S[b] && ((n + (int64_t(1) << gb) - 1) >> gb) > kLdsCap) ++gb;
+        g[b] = gb;
+        lds[b] = ((n + (int64_t(1) << gb) - 1) >> gb) <= kLdsCap;
+        nstage = std::max(nstage, gb);
+    }
+    sc->nbox = nb;
+    sc->nleaf = nl;
+    sc->nstage = nstage;
+    // key segments of stage s: problems with s <= g_b
+    sc->nkeys.assign(nstage + 1, 0);
+    sc->keys_off.assign(nstage + 2, 0);
+    std::vector<std::vector<int64_t>> kbase(nstage + 1, std::vector<int64_t>(nprob, -1));
+    for (int s = 0; s <= nstage; ++s) {
+        int64_t c = 0;
+        for (int b = 0; b < nprob; ++b)
+            if (s <= g[b]) { kbase[s][b] = c; c += int64_t(1) << s; }
+        sc->nkeys[s] = (int)c;
+        sc->keys_off[s + 1] = sc->keys_off[s] + c;
+    }
+    sc->total_keys = sc->keys_off[nstage + 1];
+    sc->segs.assign(sc->total_keys, SegInfo{});
+    sc->tile_off.assign(nstage + 1, 0);
+    sc->ntile.assign(nstage, 0);
+    for (int s = 0; s <= nstage; ++s) {
+        for (int b = 0; b < nprob; ++b) {
+            if (s > g[b]) continue;
+            int64_t n = off[b + 1] - off[b];
+            for (int64_t j = 0; j < (int64_t(1) << s); ++j) {
+                int64_t st, cnt;
+                seg_range(off[b], n, s, j, &st, &cnt);
+                int64_t gi = sc->keys_off[s] + kbase[s][b] + j;
+                SegInfo& si = sc->segs[gi];
+                si.start = (int32_t)st;
+                si.count = (int32_t)cnt;
+                si.box = (s % 2 == 0) ? (int32_t)(sc->pbox[b] + level_base(s / 2) + j) : -1;
+                si.child = -1;
+                si.tile0 = 0;
+                si.ntile = 0;
+                if (s < g[b]) {
+                    si.child = (int32_t)(sc->keys_off[s + 1] + kbase[s + 1][b] + 2 * j);
+                    si.tile0 = (int32_t)sc->tiles.size();
+                    int32_t nt = (int32_t)((cnt + kTile - 1) / kTile);
+                    si.ntile = nt;
+                    for (int32_t t = 0; t < nt; ++t) {
+                        TileInfo ti;
+                        ti.seg = (int32_t)gi;
+                        ti.start = (int32_t)(st + int64_t(t) * kTile);
+                        ti.count = (int32_t)std::min<int64_t>(kTile, cnt - int64_t(t) * kTile);
+                        ti.rank = t;
+                        sc->tiles.push_back(ti);
+                    }
+                }
+            }
+        }
+        if (s < nstage) {
+            sc->tile_off[s + 1] = (int64_t)sc->tiles.size();
+            sc->ntile[s] = (int)(sc->tile_off[s + 1] - sc->tile_off[s]);
+        }
+    }
+    sc->total_tile = (int64_t)sc->tiles.size();
+    // init tiles: every problem's root (stage-0 key segment b' = kbase[0][b])
+    sc->copy_tiles.clear();
+    // geometry jobs from global-stage keys, lds work, copy tiles
+    sc->geom_stage_off.assign(nstage + 2, 0);
+    for (int s = 0; s <= nstage; ++s) {
+        sc->geom_stage_off[s] = (int64_t)sc->geom.size();
+        if (s % 2) continue;
+        for (int b = 0; b < nprob; ++b) {
+            bool from_keys = (s < g[b]) || (!lds[b] && s == g[b]);
+            if (!from_keys) continue;
+            for (int64_t j = 0; j < (int64_t(1) << s); ++j) {
+                GeomJob gj;
+                gj.box = (int32_t)(sc->pbox[b] + level_base(s / 2) + j);
+                gj.seg = (int32_t)(sc->keys_off[s] + kbase[s][b] + j);
+                sc->geom.push_back(gj);
+            }
+        }
+    }
+    sc->geom_stage_off[nstage + 1] = (int64_t)sc->geom.size();
+    for (int b = 0; b < nprob; ++b) {
+        int64_t n = off[b + 1] - off[b];
+        if (lds[b]) {
+            for (int64_t j = 0; j < (int64_t(1) << g[b]); ++j) {
+                int64_t st, cnt;
+                seg_range(off[b], n, g[b], j, &st, &cnt);
+                LdsWork w;
+                w.start = (int32_t)st; w.count = (int32_t)cnt;
+                w.stages = S[b] - g[b]; w.stage0 = g[b]; w.j0 = (int32_t)j;
+                w.boxbase = (int32_t)sc->pbox[b];
+                w.pad0 = w.pad1 = 0;
+                sc->lds.push_back(w);
+            }
+        } else {
+            for (int64_t st = off[b]; st < off[b + 1]; st += kTile) {
+                TileInfo ti;
+                ti.seg = g[b] % 2;      // ping-pong buffer holding the final stage
+                ti.start = (int32_t)st;
+                ti.count = (int32_t)std::min<int64_t>(kTile, off[b + 1] - st);
+                ti.rank = 0;
+                sc->copy_tiles.push_back(ti);
+            }
+        }
+    }
+    // per-box ranges, parents, levels, problems
+    sc->box_start.assign(nb, 0); sc->box_count.assign(nb, 0);
+    sc->box_parent.assign(nb, -1); sc->box_level.assign(nb, 0); sc->box_prob.assign(nb, 0);
+    for (int b = 0; b < nprob; ++b) {
+        int64_t n = off[b + 1] - off[b];
+        for (int l = 0; l < L[b]; ++l) {
+            for (int64_t j = 0; j < (int64_t(1) << (2 * l)); ++j) {
+                int64_t st, cnt;
+                seg_range(off[b], n, 2 * l, j, &st, &cnt);
+                int64_t id = sc->pbox[b] + level_base(l) + j;
+                sc->box_start[id] = (int32_t)st;
+                sc->box_count[id] = (int32_t)cnt;
+                sc->box_parent[id] = l ? (int32_t)(sc->pbox[b] + level_base(l - 1) + (j >> 2)) : -1;
+                sc->box_level[id] = (int8_t)l;
+                sc->box_prob[id] = b;
+            }
+        }
+    }
+    return sc;
+}
+
+template <class T>
+static void upload(DBuf<T>& d, const std::vector<T>& h, hipStream_t s)
+{
+    d.alloc(std::max<size_t>(h.size(), 1), s);
+    if (!h.empty())
+        FMM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void upload_schedule(TreeSchedule& sc, hipStream_t s)
+{
+    upload(sc.d_segs, sc.segs, s);
+    upload(sc.d_tiles, sc.tiles, s);
+    upload(sc.d_copy, sc.copy_tiles, s);
+    upload(sc.d_lds, sc.lds, s);
+    upload(sc.d_geom, sc.geom, s);
+    upload(sc.d_box_start, sc.box_start, s);
+    upload(sc.d_box_count, sc.box_count, s);
+    upload(sc.d_box_parent, sc.box_parent, s);
+    upload(sc.d_box_level, sc.box_level, s);
+    upload(sc.d_box_prob, sc.box_prob, s);
+    // the host vectors must stay alive until the copies ran
+    FMM_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------ device helpers
+
+// order-preserving unsigned image of a double (+0 and -0 map to the same key)
+__device__ __forceinline__ uint64_t okey(double x)
+{
+    x = x + 0.0;
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double okey_inv(uint64_t k)
+{
+    uint64_t u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+// geometry of a box from its bounding box, every operation rounded alone
+__device__ __forceinline__ void box_geometry(double x0, double x1, double y0, double y1,
+                                             double* bb, double* gm)
+{
+    bb[0] = x0; bb[1] = x1; bb[2] = y0; bb[3] = y1;
+    gm[0] = (0.5 * (x0 + x1));
+    gm[1] = (0.5 * (y0 + y1));
+    double dx = (x1 - x0), dy = (y1 - y0);
+    gm[2] = 0.5 * __dsqrt_rn((dx * dx) + (dy * dy));
+}
+
+struct Bucketer {
+    double lo, scale;
+    int axis;
+};
+
+__device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys)
+{
+    double x0 = okey_inv(keys[0]), x1 = okey_inv(keys[1]);
+    double y0 = okey_inv(keys[2]), y1 = okey_inv(keys[3]);
+    double w = (x1 - x0), h = (y1 - y0);
+    Bucketer b;
+    b.axis = (w >= h) ? 0 : 1;
+    b.lo = b.axis ? y0 : x0;
+    double ext = b.axis ? h : w;
+    double sc = ext > 0.0 ? (double)kBuckets / ext : 0.0;
+    b.scale = (sc < 1e300) ? sc : 0.0;
+    return b;
+}
+
+__device__ __forceinline__ int bucket_of(const Bucketer& b, double c)
+{
+    double v = ((c - b.lo) * b.scale);
+    int k = (int)fmin(fmax(v, 0.0), (double)(kBuckets - 1));
+    return k;
+}
+
+__device__ __forceinline__ bool key_less(double c, int32_t i, double sc, int32_t si)
+{
+    return (c < sc) || (c == sc && i < si);
+}
+
+// block-wide exclusive scan of one value per thread (256 threads); returns
+// the exclusive prefix, *total receives the block sum
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
+{
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        int s = sh[w];
+        if (w < wid) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// bounding-box keys: kxmin kxmax kymin kymax
+__global__ void k_fill_keys(uint64_t* k, int64_t nseg)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        k[4 * i + 0] = ~0ull; k[4 * i + 1] = 0ull; k[4 * i + 2] = ~0ull; k[4 * i + 3] = 0ull;
+    }
+}
+
+__device__ __forceinline__ void block_minmax_atomic(double x0, double x1, double y0, double y1,
+                                                    uint64_t* keys, bool any)
+{
+    __shared__ uint64_t red[4][kTileThreads / 64];
+    uint64_t a = any ? okey(x0) : ~0ull, b = any ? okey(x1) : 0ull;
+    uint64_t c = any ? okey(y0) : ~0ull, d = any ? okey(y1) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
+        uint64_t c2 = __shfl_xor(c, o, 64), d2 = __shfl_xor(d, o, 64);
+        a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
+        c = c2 < c ? c2 : c; d = d2 > d ? d2 : d;
+    }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; red[3][w] = d; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kTileThreads / 64; ++i) {
+            a = red[0][i] < a ? red[0][i] : a; b = red[1][i] > b ? red[1][i] : b;
+            c = red[2][i] < c ? red[2][i] : c; d = red[3][i] > d ? red[3][i] : d;
+        }
+        if (a != ~0ull) {
+            atomicMin((unsigned long long*)&keys[0], (unsigned long long)a);
+            atomicMax((unsigned long long*)&keys[1], (unsigned long long)b);
+            atomicMin((unsigned long long*)&keys[2], (unsigned long long)c);
+            atomicMax((unsigned long long*)&keys[3], (unsigned long long)d);
+        }
+    }
+    __syncthreads();
+}
+
+// positions into SoA buffers, input order; root bounding boxes; finiteness
+__global__ void __launch_bounds__(kTileThreads)
+k_init(const double* __restrict__ z, const int64_t* __restrict__ poff, int nprob,
+       double* X, double* Y, int32_t* I, uint64_t* keys0, uint32_t* err)
+{
+    int b = blockIdx.y;
+    int64_t s0 = poff[b], s1 = poff[b + 1];
+    int64_t t0 = s0 + (int64_t)blockIdx.x * kTile;
+    if (t0 >= s1) return;   // uniform per block
+    int64_t t1 = min(s1, t0 + (int64_t)kTile);
+    double x0 = 1e308, x1 = -1e308, y0 = 1e308, y1 = -1e308;
+    bool any = false, bad = false;
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += kTileThreads) {
+        double2 v = reinterpret_cast<const double2*>(z)[i];
+        bad |= !(isfinite(v.x) && isfinite(v.y));
+        X[i] = v.x; Y[i] = v.y; I[i] = (int32_t)i;
+        x0 = fmin(x0, v.x); x1 = fmax(x1, v.x); y0 = fmin(y0, v.y); y1 = fmax(y1, v.y);
+        any = true;
+    }
+    if (bad) atomicOr(err, 1u);
+    // any is false only for threads without points; min/max skip them
+    block_minmax_atomic(x0, x1, y0, y1, keys0 + 4 * b, any);
+}
+
+__global__ void __launch_bounds__(kTileThreads)
+k_hist1(const TileInfo* __restrict__ tiles, const double* __restrict__ X,
+        const double* __restrict__ Y, const uint64_t* __restrict__ keys, uint32_t* hist1)
+{
+    __shared__ uint32_t h[kBuckets];
+    TileInfo t = tiles[blockIdx.x];
+    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
+    __syncthreads();
+    const double* C = bk.axis ? Y : X;
+    for (int i = threadIdx.x; i < t.count; i += kTileThreads)
+        atomicAdd(&h[bucket_of(bk, C[t.start + i])], 1u);
+    __syncthreads();
+    uint32_t* g = hist1 + (int64_t)t.seg * kBuckets;
+    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
+        if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+// find the bucket holding rank k: returns bucket, writes the rank inside it
+// and the bucket's count.  hist in global memory, 256 threads.
+__device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_in, int* sh)
+{
+    constexpr int PER = kBuckets / kTileThreads;
+    int loc[PER];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { loc[i] = (int)hist[threadIdx.x * PER + i]; s += loc[i]; }
+    int tot;
+    int base = block_excl_scan<kTileThreads>(s, sh, &tot);
+    // the thread whose range holds rank k writes the answer
+    __shared__ int ans[3];
+    int c = base;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        if (loc[i] > 0 && c <= k && k < c + loc[i]) {
+            ans[0] = threadIdx.x * PER + i; ans[1] = k - c; ans[2] = loc[i];
+        }
+        c += loc[i];
+    }
+    __syncthreads();
+    int b = ans[0];
+    *rank_in = ans[1];
+    *cnt_in = ans[2];
+    __syncthreads();
+    return b;
+}
+
+struct SubBucketer {
+    double lo, scale;
+};
+__device__ __forceinline__ SubBucketer make_sub(const Bucketer& bk, int b1)
+{
+    SubBucketer s;
+    s.lo = bk.lo + (double)b1 / bk.scale;
+    s.scale = (bk.scale * (double)kBuckets);
+    return s;
+}
+__device__ __forceinline__ int sub_of(const SubBucketer& s, double c)
+{
+    double v = ((c - s.lo) * s.scale);
+    return (int)fmin(fmax(v, 0.0), (double)(kBuckets - 1));
+}
+
+__global__ void __launch_bounds__(kTileThreads)
+k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
+        const double* __restrict__ X, const double* __restrict__ Y,
+        const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, uint32_t* hist2)
+{
+    __shared__ uint32_t h[kBuckets];
+    __shared__ int sh[kTileThreads / 64];
+    TileInfo t = tiles[blockIdx.x];
+    SegInfo sg = segs[t.seg];
+    int r1, c1;
+    int b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, sg.count / 2, &r1, &c1, sh);
+    if (c1 <= kCandCap) return;   // uniform per block
+    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    if (bk.scale == 0.0) return;  // all points in one bucket: the exact fallback handles it
+    SubBucketer sb = make_sub(bk, b1);
+    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
+    __syncthreads();
+    const double* C = bk.axis ? Y : X;
+    for (int i = threadIdx.x; i < t.count; i += kTileThreads) {
+        double c = C[t.start + i];
+        if (bucket_of(bk, c) == b1) atomicAdd(&h[sub_of(sb, c)], 1u);
+    }
+    __syncthreads();
+    uint32_t* g = hist2 + (int64_t)t.seg * kBuckets;
+    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
+        if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+struct Cand {
+    double c;
+    int32_t idx;
+    int32_t tile;
+};
+struct Splitter {
+    double c;
+    int32_t idx;
+    int32_t pad;
+};
+
+// candidate class of a point: -1 below, 0 inside, 1 above
+struct ClassRule {
+    Bucketer bk;
+    SubBucketer sb;
+    int b1, b2;     // b2 < 0: one level
+};
+__device__ __forceinline__ int class_of(const ClassRule& r, double c)
+{
+    int b = bucket_of(r.bk, c);
+    if (b != r.b1) return b < r.b1 ? -1 : 1;
+    if (r.b2 < 0) return 0;
+    int s = sub_of(r.sb, c);
+    return s == r.b2 ? 0 : (s < r.b2 ? -1 : 1);
+}
+
+// exact selection of the k-th smallest (coordinate, index) of a segment by a
+// most-significant-digit radix select over the 96-bit key, by one workgroup.
+__device__ void exact_select(const double* C, const int32_t* I, int start, int count, int k,
+                             Splitter* out)
+{
+    __shared__ uint32_t h[256];
+    __shared__ int sh[kTileThreads / 64];
+    __shared__ uint64_t pre_hi;
+    __shared__ uint32_t pre_lo;
+    __shared__ int rk;
+    if (threadIdx.x == 0) { pre_hi = 0; pre_lo = 0; rk = k; }
+    __syncthreads();
+    for (int d = 0; d < 12; ++d) {
+        for (int i = threadIdx.x; i < 256; i += kTileThreads) h[i] = 0;
+        __syncthreads();
+        uint64_t ph = pre_hi;
+        uint32_t pl = pre_lo;
+        for (int i = threadIdx.x; i < count; i += kTileThreads) {
+            uint64_t kh = okey(C[start + i]);
+            uint32_t kl = (uint32_t)I[start + i];
+            bool match;
+            int digit;
+            if (d < 8) {
+                int sh_ = 8 * (8 - d);   // bits above the current digit
+                match = (sh_ >= 64) ? true : ((kh >> sh_) == (ph >> sh_));
+                digit = (int)((kh >> (8 * (7 - d))) & 0xff);
+            } else {
+                int dd = d - 8;
+                int sh_ = 8 * (4 - dd);
+                match = (kh == ph) && ((sh_ >= 32) ? true : ((kl >> sh_) == (pl >> sh_)));
+                digit = (int)((kl >> (8 * (3 - dd))) & 0xff);
+            }
+            if (match) atomicAdd(&h[digit], 1u);
+        }
+        __syncthreads();
+        int v = (int)h[threadIdx.x];
+        int tot;
+        int base = block_excl_scan<kTileThreads>(v, sh, &tot);
+        int r = rk;
+        __syncthreads();
+        if (v > 0 && base <= r && r < base + v) {
+            if (d < 8) pre_hi |= (uint64_t)threadIdx.x << (8 * (7 - d));
+            else pre_lo |= (uint32_t)threadIdx.x << (8 * (3 - (d - 8)));
+            rk = r - base;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out->c = okey_inv(pre_hi); out->idx = (int32_t)pre_lo; out->pad = 0; }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kTileThreads)
+k_select(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
+         const TileInfo* __restrict__ all_tiles,
+         const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
+         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1,
+         const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* done,
+         uint32_t* tile_below, uint32_t* tile_extra, uint32_t* lo_base, Splitter* split)
+{
+    __shared__ int sh[kTileThreads / 64];
+    __shared__ int is_last;
+    __shared__ uint64_t skey[kCandCap];
+    __shared__ uint32_t sidx[kCandCap];
+    __shared__ uint16_t stile[kCandCap];
+    __shared__ Splitter sp;
+    TileInfo t = tiles[blockIdx.x];
+    SegInfo sg = segs[t.seg];
+    int k = sg.count / 2;
+    ClassRule rule;
+    rule.bk = make_bucketer(keys + 4 * t.seg);
+    int r1, c1;
+    rule.b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, k, &r1, &c1, sh);
+    rule.b2 = -1;
+    int rank = r1, ccount = c1;
+    if (c1 > kCandCap && rule.bk.scale != 0.0) {
+        rule.sb = make_sub(rule.bk, rule.b1);
+        int r2, c2;
+        rule.b2 = find_bucket(hist2 + (int64_t)t.seg * kBuckets, r1, &r2, &c2, sh);
+        rank = r2; ccount = c2;
+    }
+    bool overflow = ccount > kCandCap;
+    const double* C = rule.bk.axis ? Y : X;
+    int below = 0;
+    for (int i = threadIdx.x; i < t.count; i += kTileThreads) {
+        double c = C[t.start + i];
+        int cl = class_of(rule, c);
+        below += (cl < 0);
+        if (cl == 0 && !overflow) {
+            uint32_t pos = atomicAdd(&cand_cnt[t.seg], 1u);
+            if (pos < (uint32_t)kCandCap) {
+                Cand cd; cd.c = c; cd.idx = I[t.start + i]; cd.tile = t.rank;
+                cand[(int64_t)t.seg * kCandCap + pos] = cd;
+            }
+        }
+    }
+    int tot;
+    block_excl_scan<kTileThreads>(below, sh, &tot);
+    if (threadIdx.x == 0) tile_below[sg.tile0 + t.rank] = (uint32_t)tot;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(&done[t.seg], 1u) == (uint32_t)(sg.ntile - 1));
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    // ---- last tile of the segment: exact median and per-tile offsets
+    if (!overflow) {
+        int n = ccount;
+        int P = 1;
+        while (P < n) P <<= 1;
+        const Cand* cs = cand + (int64_t)t.seg * kCandCap;
+        for (int i = threadIdx.x; i < P; i += kTileThreads) {
+            if (i < n) {
+                Cand cd = cs[i];
+                skey[i] = okey(cd.c); sidx[i] = (uint32_t)cd.idx; stile[i] = (uint16_t)cd.tile;
+            } else {
+                skey[i] = ~0ull; sidx[i] = 0xffffffffu; stile[i] = 0;
+            }
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= P; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < P / 2; i += kTileThreads) {
+                    int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                    int hi = lo + j;
+                    bool asc = (lo & kk) == 0;
+                    bool less_hl = (skey[hi] < skey[lo]) || (skey[hi] == skey[lo] && sidx[hi] < sidx[lo]);
+                    if (less_hl == asc) {
+                        uint64_t a = skey[lo]; skey[lo] = skey[hi]; skey[hi] = a;
+                        uint32_t b = sidx[lo]; sidx[lo] = sidx[hi]; sidx[hi] = b;
+                        uint16_t c = stile[lo]; stile[lo] = stile[hi]; stile[hi] = c;
+                    }
+                }
+                __syncthreads();
+            }
+        if (threadIdx.x == 0) { sp.c = okey_inv(skey[rank]); sp.idx = (int32_t)sidx[rank]; sp.pad = 0; }
+        for (int i = threadIdx.x; i < rank; i += kTileThreads)
+            atomicAdd(&tile_extra[sg.tile0 + stile[i]], 1u);
+        __threadfence();
+        __syncthreads();
+    } else {
+        exact_select(C, I, sg.start, sg.count, k, &sp);
+        // per-tile counts of points below the splitter
+        for (int tt = 0; tt < sg.ntile; ++tt) {
+            TileInfo ti = all_tiles[sg.tile0 + tt];
+            int cnt = 0;
+            for (int i = threadIdx.x; i < ti.count; i += kTileThreads)
+                cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
+            int tot2;
+            block_excl_scan<kTileThreads>(cnt, sh, &tot2);
+            if (threadIdx.x == 0) { tile_below[sg.tile0 + tt] = (uint32_t)tot2; tile_extra[sg.tile0 + tt] = 0; }
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    // exclusive scan of the per-tile lower counts into output offsets
+    int run = 0;
+    for (int c0 = 0; c0 < sg.ntile; c0 += kTileThreads) {
+        int i = c0 + threadIdx.x;
+        int v = (i < sg.ntile) ? (int)(tile_below[sg.tile0 + i] + tile_extra[sg.tile0 + i]) : 0;
+        int tot3;
+        int ex = block_excl_scan<kTileThreads>(v, sh, &tot3);
+        if (i < sg.ntile) lo_base[sg.tile0 + i] = (uint32_t)(run + ex);
+        run += tot3;
+    }
+    if (threadIdx.x == 0) split[t.seg] = sp;
+}
+
+__global__ void __launch_bounds__(kTileThreads)
+k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
+            const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
+            double* X2, double* Y2, int32_t* I2, const uint64_t* __restrict__ keys,
+            uint64_t* keys_next, const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
+{
+    __shared__ int sh[kTileThreads / 64];
+    TileInfo t = tiles[blockIdx.x];
+    SegInfo sg = segs[t.seg];
+    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    Splitter sp = split[t.seg];
+    int k = sg.count / 2;
+    int toff = t.start - sg.start;
+    int lob = (int)lo_base[sg.tile0 + t.rank];
+    int lo_run = lob, hi_run = toff - lob;
+    const double* C = bk.axis ? Y : X;
+    double lx0 = 1e308, lx1 = -1e308, ly0 = 1e308, ly1 = -1e308;
+    double ux0 = 1e308, ux1 = -1e308, uy0 = 1e308, uy1 = -1e308;
+    bool anyl = false, anyu = false;
+    for (int r0 = 0; r0 < t.count; r0 += kTileThreads) {
+        int i = r0 + threadIdx.x;
+        bool valid = i < t.count;
+        double x = 0, y = 0;
+        int32_t id = 0;
+        bool lower = false;
+        if (valid) {
+            x = X[t.start + i]; y = Y[t.start + i]; id = I[t.start + i];
+            lower = key_less(bk.axis ? y : x, id, sp.c, sp.idx);
+        }
+        int tot;
+        int ex = block_excl_scan<kTileThreads>(lower ? 1 : 0, sh, &tot);
+        int nvalid = min(kTileThreads, t.count - r0);
+        if (valid) {
+            int dst;
+            if (lower) {
+                dst = sg.start + lo_run + ex;
+                lx0 = fmin(lx0, x); lx1 = fmax(lx1, x); ly0 = fmin(ly0, y); ly1 = fmax(ly1, y);
+                anyl = true;
+            } else {
+                dst = sg.start + k + hi_run + (i - r0 - ex);
+                ux0 = fmin(ux0, x); ux1 = fmax(ux1, x); uy0 = fmin(uy0, y); uy1 = fmax(uy1, y);
+                anyu = true;
+            }
+            if (dst >= sg.start && dst < sg.start + sg.count) { X2[dst] = x; Y2[dst] = y; I2[dst] = id; }
+        }
+        lo_run += tot;
+        hi_run += nvalid - tot;
+    }
+    (void)C;
+    block_minmax_atomic(lx0, lx1, ly0, ly1, keys_next + 4 * (int64_t)sg.child, anyl);
+    block_minmax_atomic(ux0, ux1, uy0, uy1, keys_next + 4 * ((int64_t)sg.child + 1), anyu);
+}
+
+// geometry of boxes whose bounding box came from a global stage
+__global__ void k_geom_keys(const GeomJob* __restrict__ jobs, int64_t n, const uint64_t* __restrict__ keys,
+                            double* bbox, double* geom)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    GeomJob j = jobs[i];
+    const uint64_t* k = keys + 4 * (int64_t)j.seg;
+    double bb[4], gm[3];
+    box_geometry(okey_inv(k[0]), okey_inv(k[1]), okey_inv(k[2]), okey_inv(k[3]), bb, gm);
+    for (int q = 0; q < 4; ++q) bbox[4 * (int64_t)j.box + q] = bb[q];
+    for (int q = 0; q < 3; ++q) geom[4 * (int64_t)j.box + q] = gm[q];
+}
+
+__global__ void k_copy_final(const TileInfo* __restrict__ tiles, const double* XA, const double* YA,
+                             const int32_t* IA, const double* XB, const double* YB, const int32_t* IB,
+                             double* X, double* Y, int32_t* I)
+{
+    TileInfo t = tiles[blockIdx.x];
+    const double* xs = t.seg ? XB : XA;
+    const double* ys = t.seg ? YB : YA;
+    const int32_t* is = t.seg ? IB : IA;
+    for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+        X[t.start + i] = xs[t.start + i]; Y[t.start + i] = ys[t.start + i]; I[t.start + i] = is[t.start + i];
+    }
+}
+
+// ------------------------------------------------- in-LDS completion kernel
+// Sorted lists LX (by x, index) and LY (by y, index) of local point ids; a
+// split along an axis keeps that axis' list as is (its first floor(n/2)
+// entries are the lower half) and stably partitions the other list.
+constexpr int kLdsThreads = 256;
+constexpr int kPer = kLdsCap / kLdsThreads;
+
+struct LdsSort {
+    uint64_t key[kLdsCap];
+    uint16_t id[kLdsCap];
+};
+struct LdsSplit {
+    uint16_t LO2[kLdsCap];
+    uint8_t flag[kLdsCap];
+    uint16_t segid[kLdsCap];
+    // sub-segment q of the current stage is [sst[q], sst[q+1]); sst[ns] = n.
+    // At most n sub-segments exist (every leaf keeps >= 1 point).
+    uint16_t sst[2][kLdsCap + 1];
+    // axes and scan offsets are needed only before a split, when there are
+    // at most n/2 sub-segments
+    uint8_t sax[kLdsCap / 2];
+    uint16_t pst[kLdsCap / 2];
+};
+union LdsUnion {
+    LdsSort s;
+    LdsSplit p;
+};
+
+__device__ void lds_sort(LdsSort& S, const uint32_t* idxs, int n)
+{
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int kk = 2; kk <= P; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P / 2; i += kLdsThreads) {
+                int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                int hi = lo + j;
+                bool asc = (lo & kk) == 0;
+                uint64_t a = S.key[lo], b = S.key[hi];
+                uint16_t ia = S.id[lo], ib = S.id[hi];
+                bool less_hl;
+                if (ib == 0xffff) less_hl = false;          // padding sorts last
+                else if (ia == 0xffff) less_hl = true;
+                else less_hl = (b < a) || (b == a && idxs[ib] < idxs[ia]);
+                if (less_hl == asc) {
+                    S.key[lo] = b; S.key[hi] = a;
+                    uint16_t c = S.id[lo]; S.id[lo] = S.id[hi]; S.id[hi] = c;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+__global__ void __launch_bounds__(kLdsThreads)
+k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA, const int32_t* IA,
+            const double* XB, const double* YB, const int32_t* IB, double* Xo, double* Yo, int32_t* Io,
+            double* bbox, double* geom)
+{
+    __shared__ LdsUnion U;
+    __shared__ uint32_t idxs[kLdsCap];
+    __shared__ uint16_t LX[kLdsCap], LY[kLdsCap];
+    __shared__ int sh[kLdsThreads / 64];
+    LdsWork w = work[blockIdx.x];
+    const double* xs = (w.stage0 & 1) ? XB : XA;
+    const double* ys = (w.stage0 & 1) ? YB : YA;
+    const int32_t* is = (w.stage0 & 1) ? IB : IA;
+    xs += w.start; ys += w.start; is += w.start;
+    int n = w.count;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kLdsThreads) {
+        if (i < n) { idxs[i] = (uint32_t)is[i]; U.s.key[i] = okey(xs[i]); U.s.id[i] = (uint16_t)i; }
+        else { U.s.key[i] = ~0ull; U.s.id[i] = 0xffff; }
+    }
+    __syncthreads();
+    lds_sort(U.s, idxs, n);
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) LX[i] = U.s.id[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += kLdsThreads) {
+        if (i < n) { U.s.key[i] = okey(ys[i]); U.s.id[i] = (uint16_t)i; }
+        else { U.s.key[i] = ~0ull; U.s.id[i] = 0xffff; }
+    }
+    __syncthreads();
+    lds_sort(U.s, idxs, n);
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) LY[i] = U.s.id[i];
+    __syncthreads();
+    LdsSplit& S = U.p;
+    if (threadIdx.x == 0) { S.sst[0][0] = 0; S.sst[0][1] = (uint16_t)n; }
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) S.segid[i] = 0;
+    __syncthreads();
+    int cur = 0;
+    for (int d = 0; d <= w.stages; ++d) {
+        int t = w.stage0 + d;
+        int ns = 1 << d;
+        // bounding boxes from the list ends; geometry at even stages; axes
+        for (int q = threadIdx.x; q < ns; q += kLdsThreads) {
+            int st = S.sst[cur][q], cn = S.sst[cur][q + 1] - st;
+            double x0 = xs[LX[st]], x1 = xs[LX[st + cn - 1]];
+            double y0 = ys[LY[st]], y1 = ys[LY[st + cn - 1]];
+            if ((t & 1) == 0) {
+                int64_t box = (int64_t)w.boxbase + level_base(t / 2) + ((int64_t)w.j0 << d) + q;
+                double bb[4], gm[3];
+                box_geometry(x0, x1, y0, y1, bb, gm);
+                for (int c = 0; c < 4; ++c) bbox[4 * box + c] = bb[c];
+                for (int c = 0; c < 3; ++c) geom[4 * box + c] = gm[c];
+            }
+            if (d < w.stages) S.sax[q] = ((x1 - x0) >= (y1 - y0)) ? 0 : 1;
+        }
+        __syncthreads();
+        if (d == w.stages) break;
+        // flags: lower half along the split axis
+        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+            int q = S.segid[i];
+            int rel = i - S.sst[cur][q], kq = (S.sst[cur][q + 1] - S.sst[cur][q]) / 2;
+            uint16_t e = S.sax[q] ? LY[i] : LX[i];
+            S.flag[e] = rel < kq;
+        }
+        __syncthreads();
+        // stable partition of the other list; thread owns positions [kPer*tid, kPer*tid+kPer)
+        int f[kPer];
+        uint16_t e[kPer];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            int i = kPer * threadIdx.x + u;
+            f[u] = 0; e[u] = 0;
+            if (i < n) {
+                int q = S.segid[i];
+                e[u] = S.sax[q] ? LX[i] : LY[i];
+                f[u] = S.flag[e[u]];
+            }
+            cnt += f[u];
+        }
+        int tot;
+        int ex = block_excl_scan<kLdsThreads>(cnt, sh, &tot);
+        int run = ex;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            int i = kPer * threadIdx.x + u;
+            if (i < n && i == S.sst[cur][S.segid[i]]) S.pst[S.segid[i]] = (uint16_t)run;
+            run += f[u];
+        }
+        __syncthreads();
+        run = ex;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            int i = kPer * threadIdx.x + u;
+            if (i < n) {
+                int q = S.segid[i];
+                int st = S.sst[cur][q], kq = (S.sst[cur][q + 1] - st) / 2, rel = i - st;
+                int lower_before = run - S.pst[q];
+                int dst = f[u] ? st + lower_before : st + kq + (rel - lower_before);
+                S.LO2[dst] = e[u];
+            }
+            run += f[u];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+            int q = S.segid[i];
+            if (S.sax[q]) LX[i] = S.LO2[i]; else LY[i] = S.LO2[i];
+        }
+        // children of every sub-segment
+        for (int q = threadIdx.x; q < ns; q += kLdsThreads) {
+            int st = S.sst[cur][q], kq = (S.sst[cur][q + 1] - st) / 2;
+            S.sst[cur ^ 1][2 * q] = (uint16_t)st;
+            S.sst[cur ^ 1][2 * q + 1] = (uint16_t)(st + kq);
+        }
+        if (threadIdx.x == 0) S.sst[cur ^ 1][2 * ns] = (uint16_t)n;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+            int q = S.segid[i];
+            int rel = i - S.sst[cur][q], kq = (S.sst[cur][q + 1] - S.sst[cur][q]) / 2;
+            S.segid[i] = (uint16_t)(2 * q + (rel >= kq));
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    // final order: sorted by (x, index) inside every leaf
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+        int id = LX[i];
+        Xo[w.start + i] = xs[id]; Yo[w.start + i] = ys[id]; Io[w.start + i] = (int32_t)idxs[id];
+    }
+}
+
+// scaling radius: r, else the nearest ancestor's r, else 1
+__global__ void k_scaling_radius(int64_t nbox, const int32_t* __restrict__ parent, double* geom)
+{
+    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    int64_t a = b;
+    double rs = 1.0;
+    while (a >= 0) {
+        double r = geom[4 * a + 2];
+        if (r > 0.0) { rs = r; break; }
+        a = parent[a];
+    }
+    geom[4 * b + 3] = rs;
+}
+
+__global__ void k_update_positions(const double* __restrict__ z, const int32_t* __restrict__ perm,
+                                   int64_t n, double* X, double* Y)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 v = reinterpret_cast<const double2*>(z)[perm[i]];
+    X[i] = v.x; Y[i] = v.y;
+}
+
+// ------------------------------------------------------------------- driver
+
+static int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 65535 * 4); }
+
+void build_tree_device(Tree& t, const double* z, hipStream_t s)
+{
+    TreeSchedule& sc = *t.sched;
+    int64_t n = sc.n;
+    t.x.alloc(n, s); t.y.alloc(n, s); t.perm.alloc(n, s);
+    t.bbox.alloc(4 * sc.nbox, s); t.geom.alloc(4 * sc.nbox, s);
+    // workspace
+    DBuf<double> XA, YA, XB, YB;
+    DBuf<int32_t> IA, IB;
+    XA.alloc(n, s); YA.alloc(n, s); IA.alloc(n, s);
+    if (sc.nstage > 0) { XB.alloc(n, s); YB.alloc(n, s); IB.alloc(n, s); }
+    int64_t nkeys = sc.total_keys;
+    DBuf<uint64_t> keys; keys.alloc(4 * nkeys, s);
+    int64_t nseg_split = sc.nstage > 0 ? sc.keys_off[sc.nstage] : 0;   // segments of split stages
+    DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | done | tile_below | tile_extra | lo_base | err
+    int64_t nh = nseg_split * kBuckets;
+    int64_t nt = sc.total_tile;
+    int64_t o_h1 = 0, o_h2 = nh, o_cc = 2 * nh, o_dn = o_cc + nseg_split, o_tb = o_dn + nseg_split;
+    int64_t o_te = o_tb + nt, o_lb = o_te + nt, o_err = o_lb + nt, nwords = o_err + 1;
+    words.alloc(nwords, s);
+    DBuf<Cand> cand; cand.alloc(std::max<int64_t>(nseg_split, 1) * kCandCap, s);
+    DBuf<Splitter> split; split.alloc(std::max<int64_t>(nseg_split, 1), s);
+    DBuf<int64_t> poff; poff.alloc(sc.nprob + 1, s);
+    FMM_HIP(hipMemcpyAsync(poff.p, sc.off.data(), sizeof(int64_t) * (sc.nprob + 1), hipMemcpyHostToDevice, s));
+
+    k_fill_u32<<<grid_for(nwords, 256), 256, 0, s>>>(words.p, nwords, 0u);
+    k_fill_keys<<<grid_for(nkeys, 256), 256, 0, s>>>(keys.p, nkeys);
+    check_launch("fill");
+    uint32_t* W = words.p;
+    // init: every problem's root segment is stage-0 key segment b
+    int64_t maxn = 0;
+    for (int b = 0; b < sc.nprob; ++b) maxn = std::max(maxn, sc.off[b + 1] - sc.off[b]);
+    dim3 gi((unsigned)((maxn + kTile - 1) / kTile), (unsigned)sc.nprob);
+    k_init<<<gi, kTileThreads, 0, s>>>(z, poff.p, sc.nprob, XA.p, YA.p, IA.p, keys.p, W + o_err);
+    check_launch("init");
+    double* Xb[2] = {XA.p, XB.p};
+    double* Yb[2] = {YA.p, YB.p};
+    int32_t* Ib[2] = {IA.p, IB.p};
+    for (int st = 0; st < sc.nstage; ++st) {
+        int ntl = sc.ntile[st];
+        if (ntl == 0) continue;
+        const TileInfo* tl = sc.d_tiles.p + sc.tile_off[st];
+        int a = st & 1;
+        k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
+        k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2);
+        k_select<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, sc.d_tiles.p, Xb[a], Yb[a], Ib[a], keys.p,
+                                             W + o_h1, W + o_h2, cand.p, W + o_cc, W + o_dn, W + o_tb,
+                                             W + o_te, W + o_lb, split.p);
+        k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
+                                                Ib[a ^ 1], keys.p, keys.p, split.p, W + o_lb);
+        check_launch("split stage");
+    }
+    if (!sc.lds.empty()) {
+        k_lds_split<<<(unsigned)sc.lds.size(), kLdsThreads, 0, s>>>(sc.d_lds.p, XA.p, YA.p, IA.p, XB.p, YB.p,
+                                                                    IB.p, t.x.p, t.y.p, t.perm.p, t.bbox.p,
+                                                                    t.geom.p);
+        check_launch("lds split");
+    }
+    if (!sc.copy_tiles.empty()) {
+        k_copy_final<<<(unsigned)sc.copy_tiles.size(), 256, 0, s>>>(sc.d_copy.p, XA.p, YA.p, IA.p, XB.p, YB.p,
+                                                                    IB.p, t.x.p, t.y.p, t.perm.p);
+        check_launch("copy final");
+    }
+    if (!sc.geom.empty()) {
+        int64_t ng = (int64_t)sc.geom.size();
+        k_geom_keys<<<grid_for(ng, 256), 256, 0, s>>>(sc.d_geom.p, ng, keys.p, t.bbox.p, t.geom.p);
+        check_launch("geom");
+    }
+    k_scaling_radius<<<grid_for(sc.nbox, 256), 256, 0, s>>>(sc.nbox, sc.d_box_parent.p, t.geom.p);
+    check_launch("scaling radius");
+    // non-finite positions: read the flag (one synchronisation)
+    uint32_t err = 0;
+    FMM_HIP(hipMemcpyAsync(&err, W + o_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    if (err) throw Error(FMM_EINVAL, "non-finite position");
+}
+
+void update_positions_device(Tree& t, const double* z, hipStream_t s)
+{
+    int64_t n = t.sched->n;
+    k_update_positions<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(z, t.perm.p, n, t.x.p, t.y.p);
+    check_launch("update positions");
+}
+
+}  // namespace fmm

@@ -1,0 +1,162 @@
+"""Parity of the HIP path against the CPU oracle, called through the C ABI.
+
+Tree: same boxes and bit-identical geometry (the split rule and the
+geometry are evaluated with individually rounded IEEE operations on both
+sides).  Lists: identical.  FP64 FMM: relative 2-norm error <= 1e-12 against
+the serial FMM oracle at equal (p, theta, N_levels).  Mixed precision:
+<= 1e-6 against the FP64 direct sum.  Edge cases: one level, one point per
+leaf, ragged sizes, ties, clustered and line-like inputs, a batch of
+problems, the exact-selection fallback for heavy ties.
+"""
+import numpy as np
+import pytest
+
+from paper_1311_1006_amd import workloads as W
+
+from gpu_util import dev, e2, host, same_tree
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1311_1006_amd as F
+    F.lib()
+    return F
+
+
+def _lists_equal(orc, F, pl, geom, L, theta, prob=0):
+    lo = orc.lists(geom, L, theta)
+    for l in range(L):
+        so, sid, wo, wid = lo[l]
+        gso, gsid = pl.download_list(prob, l, 0)
+        gwo, gwid = pl.download_list(prob, l, 1)
+        assert np.array_equal(gso, so) and np.array_equal(gsid, sid), "strong list level %d" % l
+        assert np.array_equal(gwo, wo) and np.array_equal(gwid, wid), "weak list level %d" % l
+
+
+@pytest.mark.parametrize("n,L", [(10000, 5), (10007, 4), (16, 3), (1, 1), (777, 1), (50000, 6), (200000, 7)])
+def test_tree_and_lists_match_oracle(orc, F, n, L):
+    z, m, _ = W.uniform(n, seed=n)
+    tree = same_tree(orc, F, z, L)
+    pl = F.plan(tree, 12, 0.5)
+    _lists_equal(orc, F, pl, orc.tree(z, L)[2], L, 0.5)
+
+
+@pytest.mark.parametrize("kind", ["clustered", "line", "ties"])
+def test_tree_nonuniform(orc, F, kind):
+    n, L = 30000, 6
+    if kind == "clustered":
+        z, _ = W.clustered(n, seed=1, nclusters=8)
+    elif kind == "line":
+        z, _ = W.line_like(n, seed=1)
+    else:
+        rng = np.random.default_rng(2)
+        z = np.round(rng.random(n) * 64) / 64 + 1j * np.round(rng.random(n) * 64) / 64
+    tree = same_tree(orc, F, z, L)
+    pl = F.plan(tree, 10, 0.5)
+    _lists_equal(orc, F, pl, orc.tree(z, L)[2], L, 0.5)
+
+
+def test_tree_exact_select_fallback(orc, F):
+    # a segment whose median bucket holds > 2048 points with identical
+    # coordinates cannot be resolved by bucketing: the exact radix select runs
+    rng = np.random.default_rng(3)
+    n = 40000
+    x = rng.choice([0.25, 0.5, 0.75], n)
+    y = rng.random(n) * 0.1
+    same_tree(orc, F, x + 1j * y, 5)
+
+
+@pytest.mark.parametrize("n,L,p", [(10000, 5, 17), (10007, 4, 12), (50000, 6, 16), (4096, 6, 20)])
+def test_fp64_fmm_matches_oracle_fmm(orc, F, n, L, p):
+    z, m, _ = W.uniform(n, seed=n + 1)
+    tree = F.build_tree(dev(z), L)
+    pl = F.plan(tree, p, 0.5, "fp64")
+    phi = host(F.evaluate(pl, dev(m)))
+    ref, rnear, rfar = orc.fmm(z, m, p, 0.5, L, parts=True)
+    assert e2(phi, ref) <= 1e-12
+    near, far = F.evaluate_parts(pl, dev(m))
+    assert e2(host(near), rnear) <= 1e-12
+    assert e2(host(far), rfar) <= 1e-12
+
+
+def test_fp64_fmm_clustered_matches_oracle(orc, F):
+    z, m = W.clustered(20000, seed=4, nclusters=8)
+    tree = F.build_tree(dev(z), 6)
+    pl = F.plan(tree, 16, 0.5, "fp64")
+    phi = host(F.evaluate(pl, dev(m)))
+    assert e2(phi, orc.fmm(z, m, 16, 0.5, 6)) <= 1e-12
+
+
+def test_fp64_single_level_is_direct_sum(orc, F):
+    z, m, _ = W.uniform(700, seed=5)
+    pl = F.plan(F.build_tree(dev(z), 1), 8, 0.5, "fp64")
+    assert e2(host(F.evaluate(pl, dev(m))), orc.direct(z, m)) <= 1e-13
+
+
+def test_fp64_within_table_tolerance_of_direct(orc, F):
+    # Table 4.1: p = 17 for TOL = 1e-6 at theta = 0.5
+    z, m, _ = W.uniform(10000, seed=0)
+    pl = F.plan(F.build_tree(dev(z), 5), 17, 0.5, "fp64")
+    assert e2(host(F.evaluate(pl, dev(m))), orc.direct(z, m)) <= 1e-6
+
+
+@pytest.mark.parametrize("n,L,p", [(10000, 5, 17), (60000, 6, 16), (20000, 7, 16)])
+def test_mixed_within_1e6_of_direct(orc, F, n, L, p):
+    z, m, _ = W.uniform(n, seed=n + 2)
+    pl = F.plan(F.build_tree(dev(z), L), p, 0.5, "mixed")
+    phi = host(F.evaluate(pl, dev(m)))
+    assert e2(phi, orc.direct(z, m)) <= 1e-6
+
+
+def test_coincident_points_are_excluded(orc, F):
+    z, m, _ = W.uniform(3000, seed=6)
+    z[100:110] = z[5]            # ten duplicates of one position
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        pl = F.plan(F.build_tree(dev(z), 4), 14, 0.5, prec)
+        phi = host(F.evaluate(pl, dev(m)))
+        assert np.all(np.isfinite(phi))
+        assert e2(phi, orc.fmm(z, m, 14, 0.5, 4)) <= tol
+
+
+def test_batch_equals_single_problems(orc, F):
+    zs, ms, _ = W.batch(nprob=6, seed=7, nmin=500, nmax=30000)
+    Ls = [max(1, min(6, int(np.log(len(z) / 20) / np.log(4)) + 1)) for z in zs]
+    off = np.concatenate([[0], np.cumsum([len(z) for z in zs])]).tolist()
+    zc, mc = np.concatenate(zs), np.concatenate(ms)
+    tree = F.build_tree(dev(zc), Ls, offsets=off)
+    for b in range(len(zs)):
+        same_tree(orc, F, zs[b], Ls[b], prob=b, tree=tree)
+    pl = F.plan(tree, 16, 0.5, "fp64")
+    phi = host(F.evaluate(pl, dev(mc)))
+    for b in range(len(zs)):
+        single = F.plan(F.build_tree(dev(zs[b]), Ls[b]), 16, 0.5, "fp64")
+        one = host(F.evaluate(single, dev(ms[b])))
+        np.testing.assert_array_equal(phi[off[b]:off[b + 1]], one)
+        assert e2(one, orc.fmm(zs[b], ms[b], 16, 0.5, Ls[b])) <= 1e-12
+
+
+def test_deterministic_bitwise(F):
+    z, m, _ = W.uniform(100000, seed=8)
+    outs = []
+    for prec in ("fp64", "mixed", "fp64", "mixed"):
+        pl = F.plan(F.build_tree(dev(z), 7), 16, 0.5, prec)
+        outs.append(host(F.evaluate(pl, dev(m))))
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
+
+
+def test_invalid_arguments_raise(F):
+    z, m, _ = W.uniform(100, seed=9)
+    with pytest.raises(F.FmmError):
+        F.build_tree(dev(z), 5)           # 256 leaves > 100 points
+    bad = z.copy()
+    bad[3] = np.nan
+    with pytest.raises(F.FmmError):
+        F.build_tree(dev(bad), 2)
+    tree = F.build_tree(dev(z), 2)
+    for p, th in ((0, 0.5), (33, 0.5), (10, 0.0), (10, 1.0)):
+        with pytest.raises(F.FmmError):
+            F.plan(tree, p, th)
