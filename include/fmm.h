@@ -69,7 +69,8 @@ enum {
 
 /* Launch-shape knobs of one plan; 0 means "choose automatically". */
 typedef struct {
-    int p2p_split;   /* P2P: lanes that split one target's sources (1, 2, 4, 8, 16) */
+    int p2p_split;   /* P2P: lane subgroups per wavefront (1, 2, 4); each subgroup takes
+                        its own targets and one source per lane */
     int m2l_batch;   /* M2L: pairs gathered per MFMA batch (8 .. 64, multiple of 8) */
     int flags;       /* FMM_FLAG_* */
     int reserved;

@@ -278,3 +278,55 @@ class Tuner:
         cost, run = C.c_double(), C.c_double()
         _check(lib().fmm_tuner_best(self._h, C.byref(p), C.byref(cost), C.byref(run)))
         return {"n_levels": p.n_levels, "p2p_split": p.p2p_split, "m2l_batch": p.m2l_batch}, cost.value, run.value
+
+
+def update_positions(tree, z, stream=None):
+    """Replace the tree's positions, keeping its geometry frozen."""
+    tree.update_positions(z, stream)
+
+
+class _Potential:
+    """torch.autograd.Function: phi = FMM(z, m); backward runs the adjoint
+    FMM (fmm_evaluate_adjoint) with the geometry of the forward frozen."""
+
+    _fn = None
+
+    @classmethod
+    def fn(cls):
+        if cls._fn is None:
+            import torch
+
+            class PotentialFn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, z, m, p, theta, n_levels, precision):
+                    tree = build_tree(z.detach(), n_levels)
+                    pl = plan(tree, p, theta, precision)
+                    md = m.detach().contiguous()
+                    phi = evaluate(pl, md)
+                    ctx.pl = pl
+                    ctx.tree = tree
+                    ctx.save_for_backward(md)
+                    return phi
+
+                @staticmethod
+                def backward(ctx, g_phi):
+                    (md,) = ctx.saved_tensors
+                    # torch's gradient of a real loss w.r.t. a complex tensor is
+                    # dL/dRe + i dL/dIm, the convention of fmm_evaluate_adjoint
+                    g_m, g_z = evaluate_adjoint(ctx.pl, md, g_phi.contiguous())
+                    return g_z, g_m, None, None, None, None
+
+            cls._fn = PotentialFn
+        return cls._fn
+
+
+def potential(z, m, p=16, theta=0.5, n_levels=None, precision="fp64"):
+    """phi_i = sum_{z_j != z_i} m_j / (z_i - z_j) by the FMM, differentiable in
+    z and m (complex128 device tensors).  n_levels defaults to about 16
+    points per leaf."""
+    import math
+    if n_levels is None:
+        n_levels = max(1, int(math.log(max(z.numel(), 1) / 16.0, 4)) + 1)
+        while 4 ** (n_levels - 1) > z.numel():
+            n_levels -= 1
+    return _Potential.fn().apply(z, m, p, theta, n_levels, precision)

@@ -1,9 +1,366 @@
-// adjoint.hip -- placeholder until the transposed chain lands.
+// adjoint.hip -- gradients of a real loss through the FMM with the tree
+// geometry (centres, radii, lists) frozen: the transposed chain.
+//
+// Convention: for complex w, G_w = dL/dRe(w) + i dL/dIm(w); input g = G_phi.
+// The frozen-geometry FMM is phi = A(z) m, complex-linear in m and
+// holomorphic in every z, hence with gb = conj(g)
+//     G_m = conj(A^T gb)
+//     G_z_k = conj( gb_k dphi_k/dz_k  +  sum_i gb_i dphi_i/dz_k ).
+// Transposes of the operators (scaled expansions, see expansions.hip):
+//   L2P^T: point values -> leaf "local" sensitivities, mu_l(T) = sum gb_i v_i^l:
+//          the P2M operator applied to the strengths gb;
+//   L2L^T: child -> parent; L2L(C<-P) = M2M(P<-C)^T (same rho, tau), so this is M2M;
+//   M2L^T: K(T,S)^T = -K(S,T) (swap d -> -d), so lambda = -M2L(mu) over the
+//          symmetric weak lists;
+//   M2M^T: parent -> child, i.e. the L2L operator;
+//   P2M^T: leaf multipole sensitivities -> points, i.e. the L2P evaluation;
+//   P2P^T: sum_i gb_i/(z_i - z_k) = -(P2P of gb)(z_k).
+// So A^T gb = -FMM(gb), which the chain below computes operator by operator
+// (the sign is folded into the strengths of the far-field chain).
+// Position derivatives (geometry frozen, so z enters P2P, P2M and L2P):
+//   target part  dphi_k/dz_k = -sum_j m_j/(z_k - z_j)^2 + L2P'(b)(z_k)
+//                (b: the forward local expansions);
+//   source part  sum_i gb_i dphi_i/dz_k = m_k ( sum_i gb_i/(z_k - z_i)^2 + L2P'(lambda)(z_k) )
+//                (dP2M/dz_k: a_q += m_k q w^(q-1)/rs, contracted with lambda).
+#include <cfloat>
+
 #include "fmm_internal.h"
+#include "kernels_common.h"
+#include "plan_extra.h"
 
 namespace fmm {
-void adjoint_device(Plan&, const double*, const double*, double*, double*, hipStream_t)
+
+template <class T>
+void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
+                const double*, int, void*, hipStream_t);
+template <class T>
+void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
+template <class T>
+void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
+template <class T>
+void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
+                int, const void*, void*, hipStream_t);
+void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
+                   const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
+
+struct P2PItemA {
+    int32_t leaf, t0, tn, pad;
+};
+
+// conj(g) in tree order (for P2P^T) and -conj(g) (strengths of the far chain)
+__global__ void k_gather_adj(int64_t n, const int32_t* __restrict__ perm, const double2* __restrict__ g,
+                             double2* gb, double2* ngb, float2* gb32)
 {
-    throw Error(FMM_ESTATE, "fmm_evaluate_adjoint is not available in this build");
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 v = g[perm[i]];
+    gb[i] = make_double2(v.x, -v.y);
+    ngb[i] = make_double2(-v.x, v.y);
+    if (gb32) gb32[i] = make_float2((float)v.x, (float)-v.y);
 }
+
+__device__ __forceinline__ void wave_sync_a()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Near field of the adjoint, per target k over its strong list:
+//   A_k = sum gb_j/(z_k - z_j),  B_k = sum gb_j/(z_k - z_j)^2,  C_k = sum m_j/(z_k - z_j)^2
+// (coincident positions excluded).  Same lane layout as the forward P2P:
+// SUB subgroups, TG targets per lane, one source per lane, sources staged in
+// LDS; the 6 accumulators of a target (padded to 8) are summed by a
+// transposing butterfly.
+template <class R>
+struct AdjSrc {
+    R x, y, xl, yl, mr, mi, gr, gi;
+};
+
+template <class R, int TG, int SUB>
+__global__ void __launch_bounds__(256)
+k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+          const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
+          const int32_t* __restrict__ s_ids, const double* __restrict__ X, const double* __restrict__ Y,
+          const double2* __restrict__ mt, const double2* __restrict__ gb, double* __restrict__ out)
+{
+    constexpr int NL = 64 / SUB;
+    constexpr int CAP = 128;
+    constexpr int V = 8 * TG;
+    __shared__ AdjSrc<R> sbuf[4][CAP];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + w;
+    if (item >= nitems) return;
+    const P2PItemA it = items[item];
+    AdjSrc<R>* lds = sbuf[w];
+    const int g = lane / NL, sl = lane % NL;
+    const int base = bstart[it.leaf] + it.t0;
+    R xh[TG], yh[TG], xl[TG], yl[TG];
+    R acc[TG][6];
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+        int k = g * TG + t;
+        int i = base + (k < it.tn ? k : 0);
+        double x = X[i], y = Y[i];
+        xh[t] = (R)x; yh[t] = (R)y;
+        xl[t] = (R)(x - (double)xh[t]); yl[t] = (R)(y - (double)yh[t]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[t][q] = (R)0;
+    }
+    const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
+    int e = 0, off = 0;
+    while (e < ne) {
+        // stage up to CAP sources, entry by entry (an entry may be split)
+        int ns = 0;
+        while (e < ne && ns < CAP) {
+            const int S = s_ids[e0 + e];
+            const int st = bstart[S] + off, avail = bcount[S] - off;
+            const int take = min(avail, CAP - ns);
+            for (int f = lane; f < take; f += 64) {
+                int j = st + f;
+                double x = X[j], y = Y[j];
+                AdjSrc<R> s;
+                s.x = (R)x; s.y = (R)y;
+                s.xl = (R)(x - (double)s.x); s.yl = (R)(y - (double)s.y);
+                double2 mm = mt[j], gg = gb[j];
+                s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
+                lds[ns + f] = s;
+            }
+            ns += take;
+            if (take == avail) { ++e; off = 0; } else { off += take; }
+        }
+        wave_sync_a();
+        for (int c = 0; c < ns; c += NL) {
+            int f = c + sl;
+            AdjSrc<R> s = lds[f < ns ? f : 0];
+            if (f >= ns) { s.mr = (R)0; s.mi = (R)0; s.gr = (R)0; s.gi = (R)0; }
+#pragma unroll
+            for (int t = 0; t < TG; ++t) {
+                R dx = (xh[t] - s.x) + (xl[t] - s.xl);
+                R dy = (yh[t] - s.y) + (yl[t] - s.yl);
+                R r2 = dx * dx + dy * dy;
+                R q;
+                if (sizeof(R) == 8) {
+                    double yv = __builtin_amdgcn_rcp((double)r2);
+                    double ee = fma(-(double)r2, yv, 1.0);
+                    yv = fma(yv, ee, yv);
+                    ee = fma(-(double)r2, yv, 1.0);
+                    yv = fma(yv, ee, yv);
+                    q = (R)fmin(yv, DBL_MAX);
+                } else {
+                    q = (R)fminf(__builtin_amdgcn_rcpf((float)r2), FLT_MAX);
+                }
+                // w = 1/dz = conj(dz)/|dz|^2, w2 = w*w
+                R wr = dx * q, wi = -dy * q;
+                R w2r = wr * wr - wi * wi, w2i = (R)2 * wr * wi;
+                acc[t][0] += s.gr * wr - s.gi * wi;
+                acc[t][1] += s.gr * wi + s.gi * wr;
+                acc[t][2] += s.gr * w2r - s.gi * w2i;
+                acc[t][3] += s.gr * w2i + s.gi * w2r;
+                acc[t][4] += s.mr * w2r - s.mi * w2i;
+                acc[t][5] += s.mr * w2i + s.mi * w2r;
+            }
+        }
+        wave_sync_a();
+    }
+    R v[V];
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[8 * t + q] = acc[t][q];
+        v[8 * t + 6] = (R)0;
+        v[8 * t + 7] = (R)0;
+    }
+    // transposing butterfly over the NL lanes of the subgroup
+    int nv = V, idx = 0;
+#pragma unroll
+    for (int m = NL / 2; m >= 1; m >>= 1) {
+        if (nv > 1) {
+            const bool hi = (sl & m) != 0;
+            const int h = nv / 2;
+#pragma unroll
+            for (int i = 0; i < V / 2; ++i) {
+                if (i < h) {
+                    R keep = hi ? v[i + h] : v[i];
+                    R send = hi ? v[i] : v[i + h];
+                    v[i] = keep + __shfl_xor(send, m, 64);
+                }
+            }
+            nv = h;
+            if (hi) idx += h;
+        } else {
+            v[0] += __shfl_xor(v[0], m, 64);
+        }
+    }
+    const bool writer = (sl & ((NL / V > 1) ? (NL / V - 1) : 0)) == 0;
+    const int t = idx >> 3, q = idx & 7;
+    const int k = g * TG + t;
+    if (writer && q < 6 && k < it.tn) out[6 * (int64_t)(base + k) + q] = (double)v[0];
+}
+
+// Final per-leaf combination: value and derivative of the local expansions
+// (forward b, adjoint lambda) at the points, plus the near-field sums.
+template <class T>
+__global__ void __launch_bounds__(64)
+k_adj_final(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
+            const double* __restrict__ geom, const double* __restrict__ X, const double* __restrict__ Y,
+            const T* __restrict__ loc, const T* __restrict__ lam, int p, const double* __restrict__ nadj,
+            const double2* __restrict__ mt, const double2* __restrict__ gb, const int32_t* __restrict__ perm,
+            double2* gm, double2* gz)
+{
+    __shared__ double2 bl[kMaxP], ll[kMaxP];
+    const int g = leaves[blockIdx.x];
+    const int st = bstart[g], n = bcount[g];
+    const double cx = geom[4 * g], cy = geom[4 * g + 1], rs = geom[4 * g + 3], inv = 1.0 / rs;
+    if (threadIdx.x < p) {
+        const T* b = loc + 2 * ((int64_t)g * p + threadIdx.x);
+        const T* a = lam + 2 * ((int64_t)g * p + threadIdx.x);
+        bl[threadIdx.x] = make_double2((double)b[0], (double)b[1]);
+        ll[threadIdx.x] = make_double2((double)a[0], (double)a[1]);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 64) {
+        const int i = st + j;
+        const double2 v = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
+        // Horner for value and derivative (in v) of both expansions
+        double2 bv = bl[p - 1], bd = make_double2(0, 0), lv = ll[p - 1], ld = make_double2(0, 0);
+        for (int l = p - 2; l >= 0; --l) {
+            bd = cmul(bd, v); bd.x += bv.x; bd.y += bv.y;
+            bv = cmul(bv, v); bv.x += bl[l].x; bv.y += bl[l].y;
+            ld = cmul(ld, v); ld.x += lv.x; ld.y += lv.y;
+            lv = cmul(lv, v); lv.x += ll[l].x; lv.y += ll[l].y;
+        }
+        // d/dz = (1/rs) d/dv
+        const double2 D = make_double2(bd.x * inv, bd.y * inv);
+        const double2 E = make_double2(ld.x * inv, ld.y * inv);
+        const double2 F = lv;
+        const double* na = nadj + 6 * (int64_t)i;
+        const double2 A = make_double2(na[0], na[1]), B = make_double2(na[2], na[3]), C = make_double2(na[4], na[5]);
+        const double2 mk = mt[i], gk = gb[i];
+        const int o = perm[i];
+        if (gm) {
+            // (A^T gb)_k = -A_k + F_k
+            gm[o] = make_double2(F.x - A.x, -(F.y - A.y));
+        }
+        if (gz) {
+            const double2 tpart = cmul(gk, make_double2(D.x - C.x, D.y - C.y));
+            const double2 spart = cmul(mk, make_double2(B.x + E.x, B.y + E.y));
+            gz[o] = make_double2(tpart.x + spart.x, -(tpart.y + spart.y));
+        }
+    }
+}
+
+static void adj_shape(int nt, bool mixed, int* tg, int* sub)
+{
+    // V = 8 TG <= 64 / SUB
+    if (nt <= 4) { *sub = 4; *tg = 1; }
+    else if (nt <= 8) { *sub = 2; *tg = 4; }
+    else { *sub = 1; *tg = mixed ? 8 : 4; }
+}
+
+template <class R, int TG, int SUB>
+static void launch_adj_one(const P2PItemA* items, int n, const int32_t* bstart, const int32_t* bcount,
+                           const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const double* X,
+                           const double* Y, const double* mt, const double* gb, double* out, hipStream_t s)
+{
+    k_p2p_adj<R, TG, SUB><<<(n + 3) / 4, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, X, Y,
+                                                      (const double2*)mt, (const double2*)gb, out);
+}
+
+void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *pl.ex;
+    const bool mixed = pl.precision == FMM_MIXED;
+    const int64_t n = sc.n;
+    const size_t cs = mixed ? sizeof(float) : sizeof(double);
+    if (pl.gtree.n < (size_t)(2 * n)) pl.gtree.alloc(2 * n, s);
+    if (pl.near_d.n < (size_t)(6 * n)) pl.near_d.alloc(6 * n, s);
+    DBuf<double> ngb;
+    ngb.alloc(2 * n, s);
+    if (pl.amp.n < 2 * cs * sc.nbox * pl.p) pl.amp.alloc(2 * cs * sc.nbox * pl.p, s);
+    if (pl.aloc.n < 2 * cs * sc.nbox * pl.p) pl.aloc.alloc(2 * cs * sc.nbox * pl.p, s);
+    // strengths m in tree order (the forward's gather, repeated for safety)
+    launch_gather(mixed, n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    k_gather_adj<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, t.perm.p, (const double2*)gphi,
+                                                             (double2*)pl.gtree.p, (double2*)ngb.p, nullptr);
+    check_launch("gather adjoint");
+    // far chain on -gb: L2P^T (= P2M), L2L^T (= M2M), M2L^T (= -M2L), M2M^T (= L2L)
+    const int nleaf = (int)sc.nleaf;
+    auto far = [&](auto tag) {
+        using T = decltype(tag);
+        launch_p2m<T>(ex.leaves.p, nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, ngb.p, pl.p,
+                      pl.amp.p, s);
+        for (int l = sc.max_levels - 2; l >= 1; --l) {
+            int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
+            launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p, s);
+        }
+        launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p,
+                      pl.amp.p, pl.aloc.p, s);
+        for (int l = 1; l + 1 < sc.max_levels; ++l) {
+            int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
+            launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.aloc.p, s);
+        }
+    };
+    if (mixed) far(float()); else far(double());
+    // near field of the adjoint
+    const P2PItemA* items = (const P2PItemA*)ex.adj_items.p;
+    for (auto& c : ex.adj_class) {
+        const P2PItemA* it = items + c.off;
+        int nn = (int)c.n;
+#define ACASE(R_, TG_, SUB_)                                                                                  \
+    if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
+        launch_adj_one<R_, TG_, SUB_>(it, nn, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,     \
+                                      pl.s_ids.p, t.x.p, t.y.p, pl.mtree.p, pl.gtree.p, pl.near_d.p, s);      \
+        check_launch("p2p adjoint");                                                                          \
+        continue;                                                                                             \
+    }
+        if (mixed) {
+            ACASE(float, 1, 4) ACASE(float, 4, 2) ACASE(float, 8, 1)
+        } else {
+            ACASE(double, 1, 4) ACASE(double, 4, 2) ACASE(double, 4, 1)
+        }
+#undef ACASE
+        throw Error(FMM_EDEVICE, "unsupported adjoint P2P shape");
+    }
+    // combination and scatter
+    if (mixed)
+        k_adj_final<float><<<nleaf, 64, 0, s>>>(ex.leaves.p, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p,
+                                                t.y.p, (const float*)pl.local.p, (const float*)pl.aloc.p, pl.p,
+                                                pl.near_d.p, (const double2*)pl.mtree.p, (const double2*)pl.gtree.p,
+                                                t.perm.p, (double2*)gm, (double2*)gz);
+    else
+        k_adj_final<double><<<nleaf, 64, 0, s>>>(ex.leaves.p, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p,
+                                                 t.y.p, (const double*)pl.local.p, (const double*)pl.aloc.p, pl.p,
+                                                 pl.near_d.p, (const double2*)pl.mtree.p, (const double2*)pl.gtree.p,
+                                                 t.perm.p, (double2*)gm, (double2*)gz);
+    check_launch("adjoint final");
+}
+
+// adjoint P2P work items (leaf, target chunk) grouped by shape; host side
+void prepare_adjoint_items(Plan& pl, PlanExtra& ex, const std::vector<int32_t>& leaves, hipStream_t s)
+{
+    TreeSchedule& sc = *pl.tree->sched;
+    const bool mixed = pl.precision == FMM_MIXED;
+    std::map<std::pair<int, int>, std::vector<P2PItemA>> cls;
+    for (int32_t g : leaves) {
+        int nt = sc.box_count[g];
+        int tg, sub;
+        adj_shape(nt, mixed, &tg, &sub);
+        int chunk = tg * sub;
+        for (int t0 = 0; t0 < nt; t0 += chunk) cls[{tg, sub}].push_back(P2PItemA{g, t0, std::min(chunk, nt - t0), 0});
+    }
+    std::vector<P2PItemA> items;
+    ex.adj_class.clear();
+    for (auto& kv : cls) {
+        ex.adj_class.push_back({kv.first.first, kv.first.second, (int64_t)items.size(), (int64_t)kv.second.size()});
+        items.insert(items.end(), kv.second.begin(), kv.second.end());
+    }
+    ex.adj_items.alloc(std::max<size_t>(items.size() * sizeof(P2PItemA), 1), s);
+    if (!items.empty())
+        FMM_HIP(hipMemcpyAsync(ex.adj_items.p, items.data(), items.size() * sizeof(P2PItemA), hipMemcpyHostToDevice, s));
+    FMM_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace fmm

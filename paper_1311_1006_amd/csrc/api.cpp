@@ -230,9 +230,8 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         FMM_REQUIRE(precision == FMM_FP64 || precision == FMM_MIXED, "unknown precision");
         fmm_tuning tn{};
         if (tune) tn = *tune;
-        FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4 ||
-                        tn.p2p_split == 8 || tn.p2p_split == 16,
-                    "p2p_split must be 0, 1, 2, 4, 8 or 16");
+        FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4,
+                    "p2p_split must be 0, 1, 2 or 4");
         FMM_REQUIRE(tn.m2l_batch == 0 || (tn.m2l_batch >= 8 && tn.m2l_batch <= 64 && tn.m2l_batch % 8 == 0),
                     "m2l_batch must be 0 or a multiple of 8 in [8, 64]");
         check_device_state();
@@ -245,8 +244,20 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         pl.theta = theta;
         pl.precision = precision;
         pl.tune = tn;
-        pl.ex = new PlanExtra();
-        prepare_plan_host(pl, *pl.ex, s);
+        {
+            TreeSchedule& sc = *t->t.sched;
+            int key = precision * 64 + tn.p2p_split;
+            auto it = sc.plan_cache.find(key);
+            if (it != sc.plan_cache.end()) {
+                pl.ex_ref = it->second;
+            } else {
+                pl.ex_ref = std::make_shared<PlanExtra>();
+                pl.ex = pl.ex_ref.get();
+                prepare_plan_host(pl, *pl.ex, s);
+                sc.plan_cache[key] = pl.ex_ref;
+            }
+            pl.ex = pl.ex_ref.get();
+        }
         build_lists_device(pl, s);
         alloc_eval_buffers(pl, s);
         *out = pp.release();
@@ -257,7 +268,6 @@ void fmm_plan_destroy(fmm_plan_t pl)
 {
     if (!pl) return;
     if (pl->pl.graph) (void)hipGraphExecDestroy(pl->pl.graph);
-    delete pl->pl.ex;
     delete pl;
 }
 

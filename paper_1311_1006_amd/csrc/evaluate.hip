@@ -10,6 +10,7 @@
 //   L2P     leaves: far field + near field, scattered to input order
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "fmm_internal.h"
 #include "plan_extra.h"
@@ -31,7 +32,7 @@ void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, const doubl
 template <class T>
 void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
                 int, const void*, void*, hipStream_t);
-void launch_p2p(bool mixed, int ns, int r, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
+void launch_p2p(bool mixed, int tg, int sub, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
                 const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src, const void* lo,
                 double* out, hipStream_t s);
 
@@ -39,19 +40,21 @@ struct P2PItemH {
     int32_t leaf, t0, tn, pad;
 };
 
-// P2P launch shape for a leaf size: targets per lane-group and source splits
-static void p2p_shape(int nt, int split_knob, int* ns, int* r)
+// P2P launch shape for a leaf of nt targets: SUB lane subgroups, TG targets
+// per lane (TG <= 8 in FP64, <= 16 in FP32, and 2 TG <= 64/SUB); a work item
+// covers at most TG*SUB targets.  `knob` (> 0) fixes SUB.
+static void p2p_shape(int nt, int knob, bool mixed, int* tg, int* sub)
 {
-    int s;
-    if (split_knob > 0) s = split_knob;
-    else if (nt <= 16) s = 4;
-    else if (nt <= 32) s = 2;
-    else s = 1;
-    int tw = 64 / s;
-    int rr = (nt + tw - 1) / tw;
-    rr = rr <= 1 ? 1 : (rr <= 2 ? 2 : 4);
-    *ns = s;
-    *r = rr;
+    int tgmax = mixed ? 16 : 8;
+    int s = knob > 0 ? knob : (nt <= 4 ? 4 : (nt <= 2 * tgmax ? 2 : 1));
+    int need = (nt + s - 1) / s;
+    int t = 1;
+    while (t < need && t < tgmax) t <<= 1;
+    int lo = s == 4 ? 1 : (s == 2 ? 2 : 4);
+    int hi = s == 4 ? 4 : tgmax;
+    t = t < lo ? lo : (t > hi ? hi : t);
+    *tg = t;
+    *sub = s;
 }
 
 template <class T>
@@ -66,7 +69,7 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
 {
     TreeSchedule& sc = *pl.tree->sched;
     int ml = sc.max_levels;
-    pl.level_boxes.assign(ml, {});
+    ex.level_boxes.assign(ml, {});
     ex.m2m_boxes.assign(ml, {});
     std::vector<int32_t> leaves, child0(sc.nbox, -1);
     for (int b = 0; b < sc.nprob; ++b) {
@@ -74,7 +77,7 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
             int64_t base = sc.pbox[b] + level_base(l);
             for (int64_t j = 0; j < (int64_t(1) << (2 * l)); ++j) {
                 int32_t id = (int32_t)(base + j);
-                pl.level_boxes[l].push_back(id);
+                ex.level_boxes[l].push_back(id);
                 if (l + 1 < sc.L[b]) {
                     child0[id] = (int32_t)(sc.pbox[b] + level_base(l + 1) + 4 * j);
                     ex.m2m_boxes[l].push_back(id);
@@ -85,14 +88,14 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
         }
     }
     std::vector<int32_t> all;
-    pl.level_boxes_off.assign(ml + 1, 0);
+    ex.level_boxes_off.assign(ml + 1, 0);
     for (int l = 0; l < ml; ++l) {
-        pl.level_boxes_off[l] = (int64_t)all.size();
-        all.insert(all.end(), pl.level_boxes[l].begin(), pl.level_boxes[l].end());
+        ex.level_boxes_off[l] = (int64_t)all.size();
+        all.insert(all.end(), ex.level_boxes[l].begin(), ex.level_boxes[l].end());
     }
-    pl.level_boxes_off[ml] = (int64_t)all.size();
-    upload_vec(pl.d_level_boxes, all, s);
-    upload_vec(pl.leaves, leaves, s);
+    ex.level_boxes_off[ml] = (int64_t)all.size();
+    upload_vec(ex.d_level_boxes, all, s);
+    upload_vec(ex.leaves, leaves, s);
     upload_vec(ex.child0, child0, s);
     std::vector<int32_t> m2m;
     ex.m2m_off.assign(ml + 1, 0);
@@ -106,44 +109,35 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
     for (int64_t i = 0; i < sc.nbox; ++i) iota[i] = (int32_t)i;
     upload_vec(ex.all_boxes, iota, s);
     // P2P work items grouped by launch shape
-    std::vector<std::vector<P2PItemH>> cls(5 * 3);
-    auto ci = [](int ns, int r) {
-        int a = ns == 1 ? 0 : ns == 2 ? 1 : ns == 4 ? 2 : ns == 8 ? 3 : 4;
-        int b = r == 1 ? 0 : r == 2 ? 1 : 2;
-        return a * 3 + b;
-    };
+    const bool mixed = pl.precision == FMM_MIXED;
+    std::map<std::pair<int, int>, std::vector<P2PItemH>> cls;
     for (int32_t g : leaves) {
         int nt = sc.box_count[g];
-        int ns, r;
-        p2p_shape(nt, pl.tune.p2p_split, &ns, &r);
-        int chunk = (64 / ns) * r;
-        for (int t0 = 0; t0 < nt; t0 += chunk) {
-            P2PItemH it{g, t0, std::min(chunk, nt - t0), 0};
-            cls[ci(ns, r)].push_back(it);
-        }
+        int tg, sub;
+        p2p_shape(nt, pl.tune.p2p_split, mixed, &tg, &sub);
+        int chunk = tg * sub;
+        for (int t0 = 0; t0 < nt; t0 += chunk)
+            cls[{tg, sub}].push_back(P2PItemH{g, t0, std::min(chunk, nt - t0), 0});
     }
     std::vector<P2PItemH> items;
     ex.p2p_class.clear();
-    const int nsv[5] = {1, 2, 4, 8, 16}, rv[3] = {1, 2, 4};
-    for (int a = 0; a < 5; ++a)
-        for (int b = 0; b < 3; ++b) {
-            auto& v = cls[a * 3 + b];
-            if (v.empty()) continue;
-            ex.p2p_class.push_back({nsv[a], rv[b], (int64_t)items.size(), (int64_t)v.size()});
-            items.insert(items.end(), v.begin(), v.end());
-        }
+    for (auto& kv : cls) {
+        ex.p2p_class.push_back({kv.first.first, kv.first.second, (int64_t)items.size(), (int64_t)kv.second.size()});
+        items.insert(items.end(), kv.second.begin(), kv.second.end());
+    }
     {
         std::vector<char> raw(items.size() * sizeof(P2PItemH));
         if (!items.empty()) std::memcpy(raw.data(), items.data(), raw.size());
         upload_vec(ex.p2p_items, raw, s);
     }
+    prepare_adjoint_items(pl, ex, leaves, s);
     // binomial table C(n, k), n, k < 64
     std::vector<double> bin(64 * 64, 0.0);
     for (int n = 0; n < 64; ++n) {
         bin[n * 64] = 1.0;
         for (int k = 1; k <= n; ++k) bin[n * 64 + k] = bin[(n - 1) * 64 + k - 1] + (k < n ? bin[(n - 1) * 64 + k] : 0.0);
     }
-    upload_vec(pl.binom, bin, s);
+    upload_vec(ex.binom, bin, s);
     FMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -166,11 +160,11 @@ static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipS
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    launch_p2m<T>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, mt, pl.p,
+    launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, mt, pl.p,
                   mp, s);
     for (int l = sc.max_levels - 2; l >= 1; --l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
-        launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, pl.binom.p, pl.p, mp, s);
+        launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, mp, s);
     }
 }
 
@@ -179,12 +173,12 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, pl.binom.p, pl.p, mp,
+    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp,
                   loc, s);
-    for (int l = 2; l < sc.max_levels; ++l) {
-        int n = (int)pl.level_boxes[l].size();
-        launch_l2l<T>(pl.d_level_boxes.p + pl.level_boxes_off[l], n, sc.d_box_parent.p, t.geom.p, pl.binom.p,
-                      pl.p, loc, s);
+    // parents at level l (non-leaf) hand their expansion to level l+1
+    for (int l = 1; l + 1 < sc.max_levels; ++l) {
+        int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
+        launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, loc, s);
     }
 }
 
@@ -195,7 +189,7 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
     bool mixed = pl.precision == FMM_MIXED;
     for (auto& c : ex.p2p_class) {
         const char* items = (const char*)ex.p2p_items.p + c.off * sizeof(P2PItemH);
-        launch_p2p(mixed, c.ns, c.r, items, (int)c.n, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
+        launch_p2p(mixed, c.tg, c.sub, items, (int)c.n, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
                    pl.s_ids.p, mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
                    mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s);
     }
@@ -246,10 +240,10 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     run_p2p(pl, ex, s);
     tm.mark();
     if (mixed)
-        launch_l2p<float>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+        launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
     else
-        launch_l2p<double>(pl.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+        launch_l2p<double>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
                            pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
     tm.mark();
     if (tm.on) {

@@ -89,84 +89,101 @@ k_p2m(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, co
     }
 }
 
-// M2M into one parent from its four children
+__device__ __forceinline__ double2 cpow(double2 b, int e)
+{
+    double2 r = make_double2(1.0, 0.0);
+    while (e) {
+        if (e & 1) r = cmul(r, b);
+        b = cmul(b, b);
+        e >>= 1;
+    }
+    return r;
+}
+__device__ __forceinline__ double rpow(double b, int e)
+{
+    double r = 1.0;
+    while (e) {
+        if (e & 1) r *= b;
+        b *= b;
+        e >>= 1;
+    }
+    return r;
+}
+
+// M2M into one parent from its four children.  Lane (c, j): c = lane/16
+// child, j = lane%16 (+16 for p > 16).  The children's coefficients and the
+// powers rho_c^j, tau_c^j are staged in LDS; each lane forms one child's
+// contribution to one coefficient; the four contributions are added in child
+// order.
 template <class T>
 __global__ void __launch_bounds__(64)
 k_m2m(const int32_t* __restrict__ parents, const int32_t* __restrict__ child0, const double* __restrict__ geom,
       const double* __restrict__ binom, int p, T* mp)
 {
-    __shared__ double2 tau[4][kMaxP];
+    __shared__ double2 coef[4][kMaxP], tau[4][kMaxP], part[4][kMaxP];
     __shared__ double rho[4][kMaxP];
-    int P = parents[blockIdx.x];
-    int lane = threadIdx.x;
-    int c0 = child0[P];
-    double px = geom[4 * P], py = geom[4 * P + 1], prs = geom[4 * P + 3];
-    if (lane < p) {
-        for (int c = 0; c < 4; ++c) {
-            const double* gc = geom + 4 * (int64_t)(c0 + c);
-            double r = gc[3] / prs;
-            double2 t = make_double2((gc[0] - px) / prs, (gc[1] - py) / prs);
-            double2 tp = make_double2(1, 0);
-            double rp = 1.0;
-            for (int q = 0; q < lane; ++q) { tp = cmul(tp, t); rp *= r; }
-            tau[c][lane] = tp;
-            rho[c][lane] = rp;
-        }
+    const int P = parents[blockIdx.x];
+    const int lane = threadIdx.x, c = lane >> 4, j0 = lane & 15;
+    const int ch = child0[P] + c;
+    const double* gp = geom + 4 * (int64_t)P;
+    const double* gc = geom + 4 * (int64_t)ch;
+    const double prs = gp[3];
+    const double r = gc[3] / prs;
+    const double2 t = make_double2((gc[0] - gp[0]) / prs, (gc[1] - gp[1]) / prs);
+    const T* a = mp + 2 * (int64_t)ch * p;
+    for (int j = j0; j < p; j += 16) {
+        coef[c][j] = make_double2((double)a[2 * j], (double)a[2 * j + 1]);
+        tau[c][j] = cpow(t, j);
+        rho[c][j] = rpow(r, j);
     }
     __syncthreads();
-    if (lane < p) {
-        int k = lane;
+    for (int k = j0; k < p; k += 16) {
         double2 acc = make_double2(0, 0);
-        for (int c = 0; c < 4; ++c) {
-            const T* a = mp + 2 * (int64_t)(c0 + c) * p;
-            for (int l = 0; l <= k; ++l) {
-                double2 al = make_double2((double)a[2 * l], (double)a[2 * l + 1]);
-                double s = binom[k * kBinomStride + l] * rho[c][l];
-                double2 t = cmul(al, tau[c][k - l]);
-                acc.x += s * t.x;
-                acc.y += s * t.y;
-            }
+        for (int l = 0; l <= k; ++l) {
+            double s = binom[k * kBinomStride + l] * rho[c][l];
+            double2 v = cmul(coef[c][l], tau[c][k - l]);
+            acc.x += s * v.x;
+            acc.y += s * v.y;
         }
-        mp[2 * ((int64_t)P * p + k)] = (T)acc.x;
-        mp[2 * ((int64_t)P * p + k) + 1] = (T)acc.y;
+        part[c][k] = acc;
+    }
+    __syncthreads();
+    for (int k = lane; k < p; k += 64) {
+        double2 v0 = part[0][k], v1 = part[1][k], v2 = part[2][k], v3 = part[3][k];
+        mp[2 * ((int64_t)P * p + k)] = (T)(((v0.x + v1.x) + v2.x) + v3.x);
+        mp[2 * ((int64_t)P * p + k) + 1] = (T)(((v0.y + v1.y) + v2.y) + v3.y);
     }
 }
 
-// L2L: add the parent's local expansion to a child's
+// L2L from one parent into its four children (lane (c, l) as in k_m2m)
 template <class T>
 __global__ void __launch_bounds__(64)
-k_l2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ parent, const double* __restrict__ geom,
+k_l2l(const int32_t* __restrict__ parents, const int32_t* __restrict__ child0, const double* __restrict__ geom,
       const double* __restrict__ binom, int p, T* loc)
 {
-    __shared__ double2 tau[kMaxP];
-    int C = boxes[blockIdx.x];
-    int P = parent[C];
-    int lane = threadIdx.x;
-    const double* gc = geom + 4 * (int64_t)C;
+    __shared__ double2 bp[kMaxP], tau[4][kMaxP];
+    const int P = parents[blockIdx.x];
+    const int lane = threadIdx.x, c = lane >> 4, j0 = lane & 15;
+    const int ch = child0[P] + c;
     const double* gp = geom + 4 * (int64_t)P;
-    double prs = gp[3];
-    double r = gc[3] / prs;
-    if (lane < p) {
-        double2 t = make_double2((gc[0] - gp[0]) / prs, (gc[1] - gp[1]) / prs);
-        double2 tp = make_double2(1, 0);
-        for (int q = 0; q < lane; ++q) tp = cmul(tp, t);
-        tau[lane] = tp;
-    }
+    const double* gc = geom + 4 * (int64_t)ch;
+    const double prs = gp[3];
+    const double r = gc[3] / prs;
+    const double2 t = make_double2((gc[0] - gp[0]) / prs, (gc[1] - gp[1]) / prs);
+    const T* b = loc + 2 * (int64_t)P * p;
+    for (int j = lane; j < p; j += 64) bp[j] = make_double2((double)b[2 * j], (double)b[2 * j + 1]);
+    for (int j = j0; j < p; j += 16) tau[c][j] = cpow(t, j);
     __syncthreads();
-    if (lane < p) {
-        int l = lane;
-        double rl = 1.0;
-        for (int q = 0; q < l; ++q) rl *= r;
-        const T* b = loc + 2 * (int64_t)P * p;
+    for (int l = j0; l < p; l += 16) {
         double2 acc = make_double2(0, 0);
         for (int k = l; k < p; ++k) {
-            double2 bk = make_double2((double)b[2 * k], (double)b[2 * k + 1]);
-            double2 t = cmul(bk, tau[k - l]);
             double s = binom[k * kBinomStride + l];
-            acc.x += s * t.x;
-            acc.y += s * t.y;
+            double2 v = cmul(bp[k], tau[c][k - l]);
+            acc.x += s * v.x;
+            acc.y += s * v.y;
         }
-        T* o = loc + 2 * ((int64_t)C * p + l);
+        double rl = rpow(r, l);
+        T* o = loc + 2 * ((int64_t)ch * p + l);
         o[0] = (T)((double)o[0] + rl * acc.x);
         o[1] = (T)((double)o[1] + rl * acc.y);
     }
@@ -180,18 +197,21 @@ k_l2p(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, co
       const T* __restrict__ loc, int p, const double2* __restrict__ nearf, const int32_t* __restrict__ perm,
       double2* phi, double2* phi_near, double2* phi_far)
 {
+    __shared__ double2 bl[kMaxP];
     int g = leaves[blockIdx.x];
     int st = bstart[g], n = bcount[g];
     double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
     const T* b = loc + 2 * (int64_t)g * p;
+    if (threadIdx.x < p) bl[threadIdx.x] = make_double2((double)b[2 * threadIdx.x], (double)b[2 * threadIdx.x + 1]);
+    __syncthreads();
     for (int j = threadIdx.x; j < n; j += 64) {
         int i = st + j;
         double2 w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
-        double2 acc = make_double2((double)b[2 * (p - 1)], (double)b[2 * (p - 1) + 1]);
+        double2 acc = bl[p - 1];
         for (int l = p - 2; l >= 0; --l) {
             acc = cmul(acc, w);
-            acc.x += (double)b[2 * l];
-            acc.y += (double)b[2 * l + 1];
+            acc.x += bl[l].x;
+            acc.y += bl[l].y;
         }
         double2 nf = nearf[i];
         int o = perm[i];
@@ -241,11 +261,11 @@ void launch_m2m(const int32_t* parents, int n, const int32_t* child0, const doub
 }
 
 template <class T>
-void launch_l2l(const int32_t* boxes, int n, const int32_t* parent, const double* geom, const double* binom,
+void launch_l2l(const int32_t* parents, int n, const int32_t* child0, const double* geom, const double* binom,
                 int p, void* loc, hipStream_t s)
 {
     if (n == 0) return;
-    k_l2l<T><<<n, 64, 0, s>>>(boxes, parent, geom, binom, p, (T*)loc);
+    k_l2l<T><<<n, 64, 0, s>>>(parents, child0, geom, binom, p, (T*)loc);
     check_launch("l2l");
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -109,7 +110,11 @@ struct GeomJob {      // a box whose geometry comes from the bbox keys of a glob
     int32_t seg;      // index into the stage's bbox key array (absolute, see keys_off)
 };
 
+struct PlanExtra;
+
 struct TreeSchedule {
+    // launch lists of plans on trees of this layout, by (precision, P2P knob)
+    std::map<int, std::shared_ptr<PlanExtra>> plan_cache;
     int nprob = 0;
     int64_t n = 0;
     std::vector<int64_t> off;
@@ -123,6 +128,10 @@ struct TreeSchedule {
     int64_t total_seg = 0, total_tile = 0, total_keys = 0;
     std::vector<SegInfo> segs;
     std::vector<TileInfo> tiles;
+    std::vector<int32_t> act;             // segments split by a global stage, grouped by stage
+    std::vector<int64_t> act_off;
+    std::vector<int> nact;
+    DBuf<int32_t> d_act;
     std::vector<int32_t> key_child_dummy;
     std::vector<LdsWork> lds;
     std::vector<GeomJob> geom;      // boxes whose geometry comes from global-stage keys
@@ -159,11 +168,11 @@ struct Tree {
 };
 
 // ------------------------------------------------------------------ plans
-struct PlanExtra;
 
 struct Plan {
     Tree* tree = nullptr;
-    PlanExtra* ex = nullptr;     // launch lists (owned)
+    PlanExtra* ex = nullptr;     // launch lists, shared by plans of the same tree layout
+    std::shared_ptr<PlanExtra> ex_ref;
     int p = 0, precision = 0;
     double theta = 0;
     fmm_tuning tune{};
@@ -173,12 +182,8 @@ struct Plan {
     int64_t n_strong = 0, n_weak = 0;
     std::vector<int64_t> level_nstrong, level_nweak;   // per (prob, level) not kept; totals only
     // work lists
-    DBuf<int32_t> leaves;          // global ids of all leaves
     DBuf<int32_t> m2l_targets;     // boxes with a nonempty weak list
     int64_t n_m2l_targets = 0;
-    std::vector<std::vector<int32_t>> level_boxes;   // host: global ids per level (all problems)
-    DBuf<int32_t> d_level_boxes;   // concatenated per level
-    std::vector<int64_t> level_boxes_off;
     int64_t n_p2p_pairs = 0;
     // evaluation buffers
     DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
@@ -187,7 +192,6 @@ struct Plan {
     DBuf<double> mtree;            // [N][2] strengths in tree order (FP64)
     DBuf<double> near;             // [N][2] P2P result, tree order
     DBuf<char> mpole, local;       // [nbox][p] complex coefficients (T)
-    DBuf<double> binom;            // binomial table (p x p) for the expansion shifts
     // adjoint buffers
     DBuf<double> gtree;            // conj(G_phi) in tree order
     DBuf<double> near_d;           // derivative sums of the adjoint P2P

@@ -8,7 +8,10 @@
 // workgroup; it also offsets the level into the id pools), fill.  Fills are
 // bounds-checked against the pool capacity; an overflow flag makes the host
 // grow the pools and run the build again.
+#include <algorithm>
+
 #include "fmm_internal.h"
+#include "plan_extra.h"
 
 // Box geometry, split axes and the theta-criterion must round every product
 // and sum on its own (no fused multiply-add), like a plain IEEE evaluation.
@@ -40,75 +43,123 @@ struct LevelCtx {
     double theta;
 };
 
+// One wavefront per box: lanes take the candidates (children of the parent's
+// strong boxes, in ascending order) 64 at a time; ballots count them and,
+// in the fill pass, give every strong / weak candidate its ordered slot.
 template <bool FILL>
-__global__ void k_level(LevelCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt,
-                        int32_t* s_ids, int32_t* w_ids, int64_t cap_s, int64_t cap_w)
+__global__ void __launch_bounds__(256)
+k_level(LevelCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
+        int32_t* w_ids, int64_t cap_s, int64_t cap_w)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= c.n) return;
-    int32_t g = c.boxes[i];
-    int32_t P = c.parent[g];
-    int64_t pb = c.pbox[c.prob[g]];
+    const int32_t g = c.boxes[i];
+    const int32_t P = c.parent[g];
+    const int64_t pb = c.pbox[c.prob[g]];
     const double* gg = c.geom + 4 * (int64_t)g;
-    int32_t ps = s_beg[P], pn = s_cnt[P];
-    int ns = 0, nw = 0;
+    const int32_t ps = s_beg[P], pn = s_cnt[P];
+    const int ncand = 4 * pn;
     int64_t sb = 0, wb = 0;
     if (FILL) { sb = s_beg[g]; wb = w_beg[g]; }
-    for (int e = 0; e < pn; ++e) {
-        if ((int64_t)ps + e >= cap_s) break;   // pools overflowed at an earlier level
-        int32_t q = s_ids[ps + e];
-        int64_t c0 = pb + c.lb + 4 * ((int64_t)q - pb - c.lbp);
-        for (int k = 0; k < 4; ++k) {
-            int32_t cc = (int32_t)(c0 + k);
-            bool weak = (cc != g) && well_separated(gg, c.geom + 4 * (int64_t)cc, c.theta);
+    int ns = 0, nw = 0;
+    for (int c0 = 0; c0 < ncand; c0 += 64) {
+        const int idx = c0 + lane;
+        bool valid = idx < ncand && (int64_t)ps + (idx >> 2) < cap_s;
+        bool weak = false;
+        int32_t cc = 0;
+        if (valid) {
+            const int32_t q = s_ids[ps + (idx >> 2)];
+            cc = (int32_t)(pb + c.lb + 4 * ((int64_t)q - pb - c.lbp) + (idx & 3));
+            weak = (cc != g) && well_separated(gg, c.geom + 4 * (int64_t)cc, c.theta);
+        }
+        const unsigned long long bw = __ballot(valid && weak), bs = __ballot(valid && !weak);
+        if (FILL && valid) {
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
             if (weak) {
-                if (FILL && wb + nw < cap_w) w_ids[wb + nw] = cc;
-                ++nw;
+                int64_t o = wb + nw + __popcll(bw & below);
+                if (o < cap_w) w_ids[o] = cc;
             } else {
-                if (FILL && sb + ns < cap_s) s_ids[sb + ns] = cc;
-                ++ns;
+                int64_t o = sb + ns + __popcll(bs & below);
+                if (o < cap_s) s_ids[o] = cc;
             }
         }
+        nw += __popcll(bw);
+        ns += __popcll(bs);
     }
-    if (!FILL) { s_cnt[g] = ns; w_cnt[g] = nw; }
+    if (!FILL && lane == 0) { s_cnt[g] = ns; w_cnt[g] = nw; }
 }
 
-// exclusive scan of the level's counts into pool offsets; totals[0..1] hold
-// the running pool sizes (strong, weak), totals[2] an overflow flag
+// Exclusive scan of the level's counts into pool offsets, in two passes over
+// blocks of 1024 boxes: per-block sums, then every block adds the sums of
+// the blocks before it.  totals[0..1] hold the running pool sizes (strong,
+// weak), totals[2] an overflow flag; snap[0..1] keep the sizes before this
+// level so that the second pass can update totals without a race.
+__device__ __forceinline__ void block_sum2(long long& a, long long& b, long long (*sh)[16])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_xor(a, o, 64); b += __shfl_xor(b, o, 64); }
+    if (lane == 0) { sh[0][wid] = a; sh[1][wid] = b; }
+    __syncthreads();
+    a = 0; b = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += sh[0][w]; b += sh[1][w]; }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(1024)
-k_level_scan(const int32_t* boxes, int n, const int32_t* s_cnt, const int32_t* w_cnt, int32_t* s_beg,
-             int32_t* w_beg, long long* totals, int64_t cap_s, int64_t cap_w)
+k_scan_reduce(const int32_t* boxes, int n, const int32_t* s_cnt, const int32_t* w_cnt, long long* bsum,
+              const long long* totals, long long* snap)
 {
     __shared__ long long sh[2][16];
-    long long bs = totals[0], bw = totals[1];
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < n; c0 += 1024) {
-        int i = c0 + threadIdx.x;
-        long long vs = 0, vw = 0;
-        if (i < n) { vs = s_cnt[boxes[i]]; vw = w_cnt[boxes[i]]; }
-        long long xs = vs, xw = vw;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            long long ys = __shfl_up(xs, o, 64), yw = __shfl_up(xw, o, 64);
-            if (lane >= o) { xs += ys; xw += yw; }
-        }
-        if (lane == 63) { sh[0][wid] = xs; sh[1][wid] = xw; }
-        __syncthreads();
-        long long ps = 0, pw = 0, ts = 0, tw = 0;
-        for (int w = 0; w < 16; ++w) {
-            if (w < wid) { ps += sh[0][w]; pw += sh[1][w]; }
-            ts += sh[0][w]; tw += sh[1][w];
-        }
-        if (i < n) {
-            s_beg[boxes[i]] = (int32_t)(bs + ps + xs - vs);
-            w_beg[boxes[i]] = (int32_t)(bw + pw + xw - vw);
-        }
-        bs += ts; bw += tw;
-        __syncthreads();
-    }
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    long long vs = 0, vw = 0;
+    if (i < n) { const int32_t g = boxes[i]; vs = s_cnt[g]; vw = w_cnt[g]; }
+    block_sum2(vs, vw, sh);
     if (threadIdx.x == 0) {
-        totals[0] = bs; totals[1] = bw;
-        if (bs > cap_s || bw > cap_w) totals[2] = 1;
+        bsum[2 * blockIdx.x] = vs;
+        bsum[2 * blockIdx.x + 1] = vw;
+        if (blockIdx.x == 0) { snap[0] = totals[0]; snap[1] = totals[1]; }
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_apply(const int32_t* boxes, int n, const int32_t* s_cnt, const int32_t* w_cnt, const long long* bsum,
+             const long long* snap, int32_t* s_beg, int32_t* w_beg, long long* totals, int64_t cap_s,
+             int64_t cap_w)
+{
+    __shared__ long long sh[2][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // offset of this block: sum of the block sums before it
+    long long os = 0, ow = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 1024) { os += bsum[2 * b]; ow += bsum[2 * b + 1]; }
+    block_sum2(os, ow, sh);
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    long long vs = 0, vw = 0;
+    int32_t g = 0;
+    if (i < n) { g = boxes[i]; vs = s_cnt[g]; vw = w_cnt[g]; }
+    long long xs = vs, xw = vw;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        long long ys = __shfl_up(xs, o, 64), yw = __shfl_up(xw, o, 64);
+        if (lane >= o) { xs += ys; xw += yw; }
+    }
+    if (lane == 63) { sh[0][wid] = xs; sh[1][wid] = xw; }
+    __syncthreads();
+    long long ps = 0, pw = 0, ts = 0, tw = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wid) { ps += sh[0][w]; pw += sh[1][w]; }
+        ts += sh[0][w]; tw += sh[1][w];
+    }
+    const long long bs0 = snap[0] + os, bw0 = snap[1] + ow;
+    if (i < n) {
+        s_beg[g] = (int32_t)(bs0 + ps + xs - vs);
+        w_beg[g] = (int32_t)(bw0 + pw + xw - vw);
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        totals[0] = bs0 + ts;
+        totals[1] = bw0 + tw;
+        if (bs0 + ts > cap_s || bw0 + tw > cap_w) totals[2] = 1;
     }
 }
 
@@ -151,35 +202,41 @@ void build_lists_device(Plan& pl, hipStream_t s)
     DBuf<int64_t> pbox; pbox.alloc(sc.nprob, s);
     FMM_HIP(hipMemcpyAsync(pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
     DBuf<long long> totals; totals.alloc(4, s);
+    DBuf<long long> snap; snap.alloc(2, s);
+    int maxn = 1;
+    for (auto& v : pl.ex->level_boxes) maxn = std::max(maxn, (int)v.size());
+    DBuf<long long> bsum; bsum.alloc(2 * ((maxn + 1023) / 1024), s);
     int64_t cap_s = std::max<int64_t>(pl.n_strong, 24 * nb + 1024);
     int64_t cap_w = std::max<int64_t>(pl.n_weak, 64 * nb + 1024);
     for (int attempt = 0; attempt < 3; ++attempt) {
         pl.s_ids.alloc(cap_s, s);
         pl.w_ids.alloc(cap_w, s);
-        const int32_t* lv = pl.d_level_boxes.p;
-        int nroot = (int)pl.level_boxes[0].size();
+        const int32_t* lv = pl.ex->d_level_boxes.p;
+        int nroot = (int)pl.ex->level_boxes[0].size();
         k_root_lists<<<(nroot + 255) / 256, 256, 0, s>>>(lv, nroot, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
                                                          pl.w_cnt.p, pl.s_ids.p, totals.p);
         check_launch("root lists");
         for (int l = 1; l < sc.max_levels; ++l) {
             LevelCtx c;
-            c.boxes = lv + pl.level_boxes_off[l];
-            c.n = (int)pl.level_boxes[l].size();
+            c.boxes = lv + pl.ex->level_boxes_off[l];
+            c.n = (int)pl.ex->level_boxes[l].size();
             if (c.n == 0) continue;
             c.parent = sc.d_box_parent.p; c.prob = sc.d_box_prob.p; c.pbox = pbox.p;
             c.lb = level_base(l); c.lbp = level_base(l - 1);
             c.geom = t.geom.p; c.theta = pl.theta;
-            int g = (c.n + 255) / 256;
+            int g = (c.n + 3) / 4;
             k_level<false><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                              pl.w_ids.p, cap_s, cap_w);
-            k_level_scan<<<1, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, pl.s_beg.p, pl.w_beg.p,
-                                            totals.p, cap_s, cap_w);
+            int nb = (c.n + 1023) / 1024;
+            k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, totals.p, snap.p);
+            k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, snap.p, pl.s_beg.p,
+                                             pl.w_beg.p, totals.p, cap_s, cap_w);
             k_level<true><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                             pl.w_ids.p, cap_s, cap_w);
             check_launch("level lists");
         }
         int nl = (int)sc.nleaf;
-        k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
+        k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
                                                      pl.s_cnt.p, pl.s_ids.p, totals.p, cap_s);
         check_launch("count p2p");
         long long h[4];

@@ -61,6 +61,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, cons
     constexpr int KS = PP / 4;       // k-steps of 4
     // tile[0] = scaled source columns x, tile[1] = target row factors f
     __shared__ T2 tile[2][kM2LBatch][PP + 1];
+    __shared__ int sid[kM2LBatch];
     const int g = boxes[blockIdx.x];
     const int lane = threadIdx.x;
     const int nw = w_cnt[g], wb = w_beg[g];
@@ -83,28 +84,41 @@ k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, cons
 
     const double ctx = geom[4 * (int64_t)g], cty = geom[4 * (int64_t)g + 1], rsT = geom[4 * (int64_t)g + 3];
     for (int b0 = 0; b0 < nw; b0 += kM2LBatch) {
-        // ---- phase 1: lanes 0..31 scale the source columns, lanes 32..63 form
-        // the target factors; both run the same recurrence
+        // ---- phase 0: the batch's source multipoles into tile[0] (coalesced per source)
+        if (lane < kM2LBatch) sid[lane] = (b0 + lane < nw) ? w_ids[wb + b0 + lane] : -1;
+        __syncthreads();
+        for (int e = lane; e < kM2LBatch * PP; e += 64) {
+            const int q = e / PP, k = e % PP;
+            const int S = sid[q];
+            T2 v;
+            v.x = (T)0; v.y = (T)0;
+            if (S >= 0 && k < p) v = reinterpret_cast<const T2*>(mp)[(int64_t)S * p + k];
+            tile[0][q][k] = v;
+        }
+        __syncthreads();
+        // ---- phase 1: lanes 0..31 scale the source columns in place, lanes
+        // 32..63 form the target factors; both run the recurrence
         //     out_k = pw_k * c_k,  pw_{k+1} = pw_k * base
-        // with (base, c_k) = (rs_S/d, a_k) or (-rs_T/d, 1/d).
+        // with (base, c_k) = (rs_S/d, a_k) or (-rs_T/d, 1/d), in FP64.
         {
             const int q = lane & (kM2LBatch - 1);
             const int role = lane < kM2LBatch ? 0 : 1;
-            const bool valid = b0 + q < nw;
-            const int S = valid ? w_ids[wb + b0 + q] : g;
-            const double* gs = geom + 4 * (int64_t)S;
+            const int S = sid[q];
+            const bool valid = S >= 0;
+            const double* gs = geom + 4 * (int64_t)(valid ? S : g);
             double dx = ctx - gs[0], dy = cty - gs[1];
             double den = valid ? 1.0 / (dx * dx + dy * dy) : 0.0;
             double2 id = make_double2(dx * den, -dy * den);     // 1/d (0 for padding)
             double rb_ = role ? -rsT : gs[3];
             double2 base = make_double2(rb_ * id.x, rb_ * id.y);
-            const T* a = mp + 2 * (int64_t)S * p;
             double2 pw = make_double2(1.0, 0.0);
 #pragma unroll 4
             for (int k = 0; k < PP; ++k) {
                 double2 c = id;
-                if (role == 0) c = (k < p && valid) ? make_double2((double)a[2 * k], (double)a[2 * k + 1])
-                                                    : make_double2(0.0, 0.0);
+                if (role == 0) {
+                    T2 a = tile[0][q][k];
+                    c = make_double2((double)a.x, (double)a.y);
+                }
                 double2 t = cmul(pw, c);
                 T2 v;
                 v.x = (T)t.x; v.y = (T)t.y;

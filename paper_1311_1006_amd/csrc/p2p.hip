@@ -5,17 +5,20 @@
 //
 //     phi_i += sum_{S in strong(leaf(i))} sum_{j in S, z_j != z_i} m_j / (z_i - z_j)
 //
-// One wavefront per work item (a leaf, or a chunk of a large leaf's targets).
-// The 64 lanes are TW = 64/NS target slots times NS source splits: lane
-// (t, s) owns targets t, t+TW, ... (R of them in registers) and the sources
-// j = s, s+NS, ... of every leaf in the strong list; a butterfly over the NS
-// splits combines the partial sums.  Leaves at the optimum hold 15-60 points,
-// fewer than 64 lanes, hence the source split.  Exclusion by position: a pair
-// with z_j = z_i has r^2 = 0 and its reciprocal is clamped to the largest
-// finite value, which multiplies an exact zero.
+// One wavefront per work item (a leaf, or a group of a large leaf's
+// targets).  The sources of all leaves in the strong list are first gathered
+// into a contiguous LDS array (one coalesced pass).  The 64 lanes are SUB
+// subgroups of NL = 64/SUB lanes: within a subgroup every lane owns one
+// source of the current chunk and all TG targets of the subgroup (targets in
+// registers), so the inner loop has no memory traffic: per pair only the
+// kernel arithmetic.  Padding lanes carry zero strength.  A transposing
+// butterfly then sums the 2*TG accumulators over the NL lanes with about
+// 2*TG shuffles instead of 2*TG*log2(NL).
+// Exclusion by position: a pair with z_j = z_i has r^2 = 0; its reciprocal is
+// clamped to the largest finite value and multiplies an exact zero.
 //   FP64:  dz in FP64, 1/r^2 by v_rcp_f64 and two Newton steps.
-//   mixed: positions stored as FP32 hi + lo, dz = (hi_i - hi_j) + (lo_i - lo_j),
-//          everything else in FP32, FP32 accumulation.
+//   mixed: positions as FP32 hi + lo, dz = (hi_i - hi_j) + (lo_i - lo_j),
+//          everything else in FP32 with FP32 accumulation.
 #include <cfloat>
 
 #include "fmm_internal.h"
@@ -26,7 +29,23 @@ struct P2PItem {
     int32_t leaf, t0, tn, pad;
 };
 
-__device__ __forceinline__ void pair64(double xi, double yi, const double4& s, double& ar, double& ai)
+constexpr int kP2PSrcCap = 256;    // sources staged in LDS per pass and wavefront
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Src64 {
+    double x, y, mr, mi;
+};
+struct Src32 {
+    float xh, yh, mr, mi, xl, yl;
+};
+
+__device__ __forceinline__ void pair64(double xi, double yi, const Src64& s, double& ar, double& ai)
 {
     double dx = xi - s.x, dy = yi - s.y;
     double r2 = fma(dx, dx, dy * dy);
@@ -36,135 +55,269 @@ __device__ __forceinline__ void pair64(double xi, double yi, const double4& s, d
     e = fma(-r2, y, 1.0);
     y = fma(y, e, y);
     y = fmin(y, DBL_MAX);
-    double a = fma(s.z, dx, s.w * dy);
-    double b = fma(s.w, dx, -(s.z * dy));
+    double a = fma(s.mr, dx, s.mi * dy);
+    double b = fma(s.mi, dx, -(s.mr * dy));
     ar = fma(a, y, ar);
     ai = fma(b, y, ai);
 }
 
-__device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, const float4& s, const float2& l,
-                                       float& ar, float& ai)
+__device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, const Src32& s, float& ar, float& ai)
 {
-    float dx = (xh - s.x) + (xl - l.x);
-    float dy = (yh - s.y) + (yl - l.y);
+    float dx = (xh - s.xh) + (xl - s.xl);
+    float dy = (yh - s.yh) + (yl - s.yl);
     float r2 = fmaf(dx, dx, dy * dy);
     float y = fminf(__builtin_amdgcn_rcpf(r2), FLT_MAX);
-    float a = fmaf(s.z, dx, s.w * dy);
-    float b = fmaf(s.w, dx, -(s.z * dy));
+    float a = fmaf(s.mr, dx, s.mi * dy);
+    float b = fmaf(s.mi, dx, -(s.mr * dy));
     ar = fmaf(a, y, ar);
     ai = fmaf(b, y, ai);
 }
 
-template <int NS, int R>
-__global__ void __launch_bounds__(64)
-k_p2p64(const P2PItem* __restrict__ items, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
-        const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt, const int32_t* __restrict__ s_ids,
-        const double4* __restrict__ src, double2* __restrict__ out)
+// Sum v[0..V) over the lanes that differ in bits [0, log2(NL)) while
+// transposing: afterwards v[0] holds the total of value index
+// ((lane >> 1) & (V-1)) when V >= 2 (see the loop).  Requires V <= NL.
+template <int V, int NL, class T>
+__device__ __forceinline__ void butterfly(T (&v)[V], int lane)
 {
-    constexpr int TW = 64 / NS;
-    const P2PItem it = items[blockIdx.x];
-    const int lane = threadIdx.x, t = lane % TW, sp = lane / TW;
-    const int base = bstart[it.leaf] + it.t0;
-    double xi[R], yi[R], ar[R], ai[R];
+    int nv = V;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int k = t + TW * r;
+    for (int m = NL / 2; m >= 1; m >>= 1) {
+        if (nv > 1) {
+            const bool hi = (lane & m) != 0;
+            const int h = nv / 2;
+#pragma unroll
+            for (int i = 0; i < V / 2; ++i) {
+                if (i < h) {
+                    T keep = hi ? v[i + h] : v[i];
+                    T send = hi ? v[i] : v[i + h];
+                    v[i] = keep + __shfl_xor(send, m, 64);
+                }
+            }
+            nv = h;
+        } else {
+            v[0] += __shfl_xor(v[0], m, 64);
+        }
+    }
+}
+
+// value index held by `lane` after butterfly<V, NL>: the bits of the lane
+// used by the transposing steps, most significant step first
+template <int V, int NL>
+__device__ __forceinline__ int butterfly_index(int lane)
+{
+    int idx = 0, nv = V;
+#pragma unroll
+    for (int m = NL / 2; m >= 1; m >>= 1) {
+        if (nv > 1) {
+            nv /= 2;
+            if (lane & m) idx += nv;
+        }
+    }
+    return idx;
+}
+
+// Gather sources of the strong list into LDS, resuming at (entry e, offset
+// off) and stopping after kP2PSrcCap sources (an entry may be split between
+// passes).  Entries are looked at 64 at a time; their (first source, prefix)
+// pairs go through a per-wave LDS table so that the copy loop needs no
+// shuffles.  Returns the number of sources staged.
+template <class SRC, class LOADER>
+__device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, const int32_t* __restrict__ s_ids,
+                                             const int32_t* __restrict__ bstart,
+                                             const int32_t* __restrict__ bcount, int e0, int e_end, int& e,
+                                             int& off, int lane, LOADER load)
+{
+    int staged = 0;
+    while (e < e_end && staged < kP2PSrcCap) {
+        const int k = e + lane;
+        int st = 0, avail = 0;
+        if (k < e_end) {
+            const int S = s_ids[e0 + k];
+            st = bstart[S];
+            avail = bcount[S];
+            if (lane == 0) { st += off; avail -= off; }
+        }
+        int x = avail;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int excl = x - avail;
+        const int total = __shfl(x, 63, 64);
+        const int take = min(total, kP2PSrcCap - staged);
+        meta[lane] = make_int2(excl, st);
+        wave_sync();
+        for (int f = lane; f < take; f += 64) {
+            // the entry holding flat position f: largest j with excl_j <= f
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (meta[mid].x <= f) lo = mid; else hi = mid - 1;
+            }
+            int2 mj = meta[lo];
+            lds[staged + f] = load(mj.y + (f - mj.x));
+        }
+        // advance the cursor (uniform)
+        if (take == total) {
+            e = min(e + 64, e_end);
+            off = 0;
+        } else {
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (meta[mid].x <= take - 1) lo = mid; else hi = mid - 1;
+            }
+            int consumed = take - meta[lo].x;
+            int avail_lo = (lo + 1 < 64 ? meta[lo + 1].x : total) - meta[lo].x;
+            if (consumed == avail_lo) { e = e + lo + 1; off = 0; }
+            else { off = (lo == 0 ? off : 0) + consumed; e = e + lo; }
+        }
+        staged += take;
+        wave_sync();
+    }
+    return staged;
+}
+
+template <int TG, int SUB>
+__global__ void __launch_bounds__(256)
+k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+        const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
+        const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out)
+{
+    constexpr int NL = 64 / SUB;
+    __shared__ Src64 sbuf[4][kP2PSrcCap];
+    __shared__ int2 smeta[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + w;
+    if (item >= nitems) return;
+    const P2PItem it = items[item];
+    Src64* lds = sbuf[w];
+    const int g = lane / NL, sl = lane % NL;
+    const int base = bstart[it.leaf] + it.t0;
+    double xi[TG], yi[TG], ar[TG], ai[TG];
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+        int k = g * TG + t;
         double4 v = src[base + (k < it.tn ? k : 0)];
-        xi[r] = v.x; yi[r] = v.y; ar[r] = 0.0; ai[r] = 0.0;
+        xi[t] = v.x; yi[t] = v.y; ar[t] = 0.0; ai[t] = 0.0;
     }
     const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
-    for (int e = 0; e < ne; ++e) {
-        const int S = s_ids[e0 + e];
-        const int j0 = bstart[S], nj = bcount[S];
-#pragma unroll 4
-        for (int j = sp; j < nj; j += NS) {
-            const double4 s = src[j0 + j];
+    auto load = [&](int j) {
+        double4 v = src[j];
+        Src64 s; s.x = v.x; s.y = v.y; s.mr = v.z; s.mi = v.w;
+        return s;
+    };
+    int e = 0, off = 0;
+    while (e < ne) {
+        int ns = stage_sources(lds, smeta[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+        for (int c = 0; c < ns; c += NL) {
+            int f = c + sl;
+            Src64 s = lds[f < ns ? f : 0];
+            if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
 #pragma unroll
-            for (int r = 0; r < R; ++r) pair64(xi[r], yi[r], s, ar[r], ai[r]);
+            for (int t = 0; t < TG; ++t) pair64(xi[t], yi[t], s, ar[t], ai[t]);
         }
+        wave_sync();
     }
+    double v[2 * TG];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int o = TW; o < 64; o <<= 1) {
-            ar[r] += __shfl_xor(ar[r], o, 64);
-            ai[r] += __shfl_xor(ai[r], o, 64);
-        }
-        int k = t + TW * r;
-        if (sp == 0 && k < it.tn) out[base + k] = make_double2(ar[r], ai[r]);
-    }
+    for (int t = 0; t < TG; ++t) { v[2 * t] = ar[t]; v[2 * t + 1] = ai[t]; }
+    butterfly<2 * TG, NL>(v, lane);
+    const int idx = butterfly_index<2 * TG, NL>(sl);
+    // lanes holding the same value index: write from the lowest one
+    const int t = idx >> 1, comp = idx & 1;
+    const bool writer = (sl & ((NL / (2 * TG) > 1) ? (NL / (2 * TG) - 1) : 0)) == 0;
+    const int k = g * TG + t;
+    if (writer && k < it.tn) reinterpret_cast<double*>(out + base + k)[comp] = v[0];
 }
 
-template <int NS, int R>
-__global__ void __launch_bounds__(64)
-k_p2p32(const P2PItem* __restrict__ items, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
-        const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt, const int32_t* __restrict__ s_ids,
-        const float4* __restrict__ src, const float2* __restrict__ lo, double2* __restrict__ out)
+template <int TG, int SUB>
+__global__ void __launch_bounds__(256)
+k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+        const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
+        const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
+        double2* __restrict__ out)
 {
-    constexpr int TW = 64 / NS;
-    const P2PItem it = items[blockIdx.x];
-    const int lane = threadIdx.x, t = lane % TW, sp = lane / TW;
+    constexpr int NL = 64 / SUB;
+    __shared__ Src32 sbuf[4][kP2PSrcCap];
+    __shared__ int2 smeta[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + w;
+    if (item >= nitems) return;
+    const P2PItem it = items[item];
+    Src32* lds = sbuf[w];
+    const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
-    float xh[R], yh[R], xl[R], yl[R], ar[R], ai[R];
+    float xh[TG], yh[TG], xl[TG], yl[TG], ar[TG], ai[TG];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int k = t + TW * r;
+    for (int t = 0; t < TG; ++t) {
+        int k = g * TG + t;
         int i = base + (k < it.tn ? k : 0);
-        float4 v = src[i];
-        float2 w = lo[i];
-        xh[r] = v.x; yh[r] = v.y; xl[r] = w.x; yl[r] = w.y; ar[r] = 0.f; ai[r] = 0.f;
+        float4 a = src[i];
+        float2 b = lo[i];
+        xh[t] = a.x; yh[t] = a.y; xl[t] = b.x; yl[t] = b.y; ar[t] = 0.f; ai[t] = 0.f;
     }
     const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
-    for (int e = 0; e < ne; ++e) {
-        const int S = s_ids[e0 + e];
-        const int j0 = bstart[S], nj = bcount[S];
-#pragma unroll 4
-        for (int j = sp; j < nj; j += NS) {
-            const float4 s = src[j0 + j];
-            const float2 l = lo[j0 + j];
+    auto load = [&](int j) {
+        float4 a = src[j];
+        float2 b = lo[j];
+        Src32 s; s.xh = a.x; s.yh = a.y; s.mr = a.z; s.mi = a.w; s.xl = b.x; s.yl = b.y;
+        return s;
+    };
+    int e = 0, off = 0;
+    while (e < ne) {
+        int ns = stage_sources(lds, smeta[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+        for (int c = 0; c < ns; c += NL) {
+            int f = c + sl;
+            Src32 s = lds[f < ns ? f : 0];
+            if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
 #pragma unroll
-            for (int r = 0; r < R; ++r) pair32(xh[r], yh[r], xl[r], yl[r], s, l, ar[r], ai[r]);
+            for (int t = 0; t < TG; ++t) pair32(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
         }
+        wave_sync();
     }
+    float v[2 * TG];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int o = TW; o < 64; o <<= 1) {
-            ar[r] += __shfl_xor(ar[r], o, 64);
-            ai[r] += __shfl_xor(ai[r], o, 64);
-        }
-        int k = t + TW * r;
-        if (sp == 0 && k < it.tn) out[base + k] = make_double2((double)ar[r], (double)ai[r]);
-    }
+    for (int t = 0; t < TG; ++t) { v[2 * t] = ar[t]; v[2 * t + 1] = ai[t]; }
+    butterfly<2 * TG, NL>(v, lane);
+    const int idx = butterfly_index<2 * TG, NL>(sl);
+    const int t = idx >> 1, comp = idx & 1;
+    const bool writer = (sl & ((NL / (2 * TG) > 1) ? (NL / (2 * TG) - 1) : 0)) == 0;
+    const int k = g * TG + t;
+    if (writer && k < it.tn) reinterpret_cast<double*>(out + base + k)[comp] = (double)v[0];
 }
 
-template <int NS, int R>
+template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int n, const int32_t* bstart, const int32_t* bcount,
                        const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src,
                        const void* lo, double* out, hipStream_t s)
 {
+    int grid = (n + 3) / 4;
     if (mixed)
-        k_p2p32<NS, R><<<n, 64, 0, s>>>(items, bstart, bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                       (const float2*)lo, (double2*)out);
+        k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, (const float4*)src,
+                                             (const float2*)lo, (double2*)out);
     else
-        k_p2p64<NS, R><<<n, 64, 0, s>>>(items, bstart, bcount, s_beg, s_cnt, s_ids, (const double4*)src,
-                                       (double2*)out);
+        k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, (const double4*)src,
+                                             (double2*)out);
 }
 
-// one launch per (NS, R) class
-void launch_p2p(bool mixed, int ns, int r, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
-                const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src, const void* lo,
-                double* out, hipStream_t s)
+// one launch per (targets per subgroup, subgroups) class
+void launch_p2p(bool mixed, int tg, int sub, const void* items, int n, const int32_t* bstart,
+                const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
+                const void* src, const void* lo, double* out, hipStream_t s)
 {
     if (n == 0) return;
     const P2PItem* it = (const P2PItem*)items;
-#define CASE(NS_, R_) \
-    if (ns == NS_ && r == R_) { launch_one<NS_, R_>(mixed, it, n, bstart, bcount, s_beg, s_cnt, s_ids, src, lo, out, s); check_launch("p2p"); return; }
-    CASE(1, 1) CASE(1, 2) CASE(1, 4)
-    CASE(2, 1) CASE(2, 2) CASE(2, 4)
-    CASE(4, 1) CASE(4, 2) CASE(4, 4)
-    CASE(8, 1) CASE(8, 2) CASE(8, 4)
-    CASE(16, 1) CASE(16, 2) CASE(16, 4)
+#define CASE(TG_, SUB_)                                                                               \
+    if (tg == TG_ && sub == SUB_) {                                                                   \
+        launch_one<TG_, SUB_>(mixed, it, n, bstart, bcount, s_beg, s_cnt, s_ids, src, lo, out, s);    \
+        check_launch("p2p");                                                                          \
+        return;                                                                                       \
+    }
+    CASE(1, 4) CASE(2, 4) CASE(4, 4)
+    CASE(2, 2) CASE(4, 2) CASE(8, 2) CASE(16, 2)
+    CASE(4, 1) CASE(8, 1) CASE(16, 1)
 #undef CASE
     throw Error(FMM_EINVAL, "unsupported P2P launch shape");
 }

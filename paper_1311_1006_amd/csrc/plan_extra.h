@@ -1,25 +1,35 @@
 // plan_extra.h -- per-plan launch lists (host + device), internal.
 #pragma once
+#include <map>
+
 #include "fmm_internal.h"
 
 namespace fmm {
 
 struct P2PClass {
-    int ns, r;          // source splits, targets per lane
+    int tg, sub;        // targets per lane, lane subgroups
     int64_t off, n;     // range in the item array
 };
 
 struct PlanExtra {
+    std::vector<std::vector<int32_t>> level_boxes;  // global ids per level (all problems)
+    std::vector<int64_t> level_boxes_off;
+    DBuf<int32_t> d_level_boxes;                    // concatenated per level
+    DBuf<int32_t> leaves;                           // global ids of all leaves
+    DBuf<double> binom;                             // binomial table C(n, k), n, k < 64
     std::vector<std::vector<int32_t>> m2m_boxes;   // non-leaf boxes per level
     std::vector<int64_t> m2m_off;
     DBuf<int32_t> d_m2m, child0, all_boxes;
     DBuf<char> p2p_items;
     std::vector<P2PClass> p2p_class;
+    DBuf<char> adj_items;                           // adjoint P2P work items
+    std::vector<P2PClass> adj_class;
 };
 
 inline PlanExtra* extra(Plan& pl) { return pl.ex; }
 
 void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s);
 void alloc_eval_buffers(Plan& pl, hipStream_t s);
+void prepare_adjoint_items(Plan& pl, PlanExtra& ex, const std::vector<int32_t>& leaves, hipStream_t s);
 
 }  // namespace fmm

@@ -103,7 +103,10 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
     sc->segs.assign(sc->total_keys, SegInfo{});
     sc->tile_off.assign(nstage + 1, 0);
     sc->ntile.assign(nstage, 0);
+    sc->act_off.assign(nstage + 1, 0);
+    sc->nact.assign(nstage, 0);
     for (int s = 0; s <= nstage; ++s) {
+        sc->act_off[s] = (int64_t)sc->act.size();
         for (int b = 0; b < nprob; ++b) {
             if (s > g[b]) continue;
             int64_t n = off[b + 1] - off[b];
@@ -119,6 +122,7 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                 si.tile0 = 0;
                 si.ntile = 0;
                 if (s < g[b]) {
+                    sc->act.push_back((int32_t)gi);
                     si.child = (int32_t)(sc->keys_off[s + 1] + kbase[s + 1][b] + 2 * j);
                     si.tile0 = (int32_t)sc->tiles.size();
                     int32_t nt = (int32_t)((cnt + kTile - 1) / kTile);
@@ -137,6 +141,7 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
         if (s < nstage) {
             sc->tile_off[s + 1] = (int64_t)sc->tiles.size();
             sc->ntile[s] = (int)(sc->tile_off[s + 1] - sc->tile_off[s]);
+            sc->nact[s] = (int)((int64_t)sc->act.size() - sc->act_off[s]);
         }
     }
     sc->total_tile = (int64_t)sc->tiles.size();
@@ -216,6 +221,7 @@ void upload_schedule(TreeSchedule& sc, hipStream_t s)
 {
     upload(sc.d_segs, sc.segs, s);
     upload(sc.d_tiles, sc.tiles, s);
+    upload(sc.d_act, sc.act, s);
     upload(sc.d_copy, sc.copy_tiles, s);
     upload(sc.d_lds, sc.lds, s);
     upload(sc.d_geom, sc.geom, s);
@@ -254,6 +260,22 @@ __device__ __forceinline__ void box_geometry(double x0, double x1, double y0, do
     gm[2] = 0.5 * __dsqrt_rn((dx * dx) + (dy * dy));
 }
 
+// Every segment's bounding box is kept as kKeyCopies copies of four order
+// keys (xmin, xmax, ymin, ymax) so that the workgroups updating it with
+// atomics spread over several addresses; readers combine the copies.
+constexpr int kKeyCopies = 8;
+constexpr int kKeyWords = 4 * kKeyCopies;
+
+__device__ __forceinline__ void read_keys(const uint64_t* k, double* bb)
+{
+    uint64_t a = k[0], b = k[1], c = k[2], d = k[3];
+#pragma unroll
+    for (int i = 1; i < kKeyCopies; ++i) {
+        a = min(a, k[4 * i]); b = max(b, k[4 * i + 1]); c = min(c, k[4 * i + 2]); d = max(d, k[4 * i + 3]);
+    }
+    bb[0] = okey_inv(a); bb[1] = okey_inv(b); bb[2] = okey_inv(c); bb[3] = okey_inv(d);
+}
+
 struct Bucketer {
     double lo, scale;
     int axis;
@@ -261,8 +283,9 @@ struct Bucketer {
 
 __device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys)
 {
-    double x0 = okey_inv(keys[0]), x1 = okey_inv(keys[1]);
-    double y0 = okey_inv(keys[2]), y1 = okey_inv(keys[3]);
+    double bbx[4];
+    read_keys(keys, bbx);
+    double x0 = bbx[0], x1 = bbx[1], y0 = bbx[2], y1 = bbx[3];
     double w = (x1 - x0), h = (y1 - y0);
     Bucketer b;
     b.axis = (w >= h) ? 0 : 1;
@@ -325,7 +348,10 @@ __global__ void k_fill_keys(uint64_t* k, int64_t nseg)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg;
          i += (int64_t)gridDim.x * blockDim.x) {
-        k[4 * i + 0] = ~0ull; k[4 * i + 1] = 0ull; k[4 * i + 2] = ~0ull; k[4 * i + 3] = 0ull;
+        for (int c = 0; c < kKeyCopies; ++c) {
+            uint64_t* q = k + kKeyWords * i + 4 * c;
+            q[0] = ~0ull; q[1] = 0ull; q[2] = ~0ull; q[3] = 0ull;
+        }
     }
 }
 
@@ -346,6 +372,7 @@ __device__ __forceinline__ void block_minmax_atomic(double x0, double x1, double
     if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; red[3][w] = d; }
     __syncthreads();
     if (threadIdx.x == 0) {
+        keys += 4 * (blockIdx.x & (kKeyCopies - 1));
         for (int i = 1; i < kTileThreads / 64; ++i) {
             a = red[0][i] < a ? red[0][i] : a; b = red[1][i] > b ? red[1][i] : b;
             c = red[2][i] < c ? red[2][i] : c; d = red[3][i] > d ? red[3][i] : d;
@@ -381,7 +408,7 @@ k_init(const double* __restrict__ z, const int64_t* __restrict__ poff, int nprob
     }
     if (bad) atomicOr(err, 1u);
     // any is false only for threads without points; min/max skip them
-    block_minmax_atomic(x0, x1, y0, y1, keys0 + 4 * b, any);
+    block_minmax_atomic(x0, x1, y0, y1, keys0 + kKeyWords * b, any);
 }
 
 __global__ void __launch_bounds__(kTileThreads)
@@ -390,7 +417,7 @@ k_hist1(const TileInfo* __restrict__ tiles, const double* __restrict__ X,
 {
     __shared__ uint32_t h[kBuckets];
     TileInfo t = tiles[blockIdx.x];
-    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
     __syncthreads();
     const double* C = bk.axis ? Y : X;
@@ -431,6 +458,9 @@ __device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_i
     return b;
 }
 
+// a median bucket with more points than this is refined by a second histogram
+constexpr int kSubThreshold = 64;
+
 struct SubBucketer {
     double lo, scale;
 };
@@ -458,8 +488,8 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     SegInfo sg = segs[t.seg];
     int r1, c1;
     int b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, sg.count / 2, &r1, &c1, sh);
-    if (c1 <= kCandCap) return;   // uniform per block
-    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    if (c1 <= kSubThreshold) return;   // uniform per block
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     if (bk.scale == 0.0) return;  // all points in one bucket: the exact fallback handles it
     SubBucketer sb = make_sub(bk, b1);
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
@@ -552,36 +582,41 @@ __device__ void exact_select(const double* C, const int32_t* I, int start, int c
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(kTileThreads)
-k_select(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
-         const TileInfo* __restrict__ all_tiles,
-         const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1,
-         const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* done,
-         uint32_t* tile_below, uint32_t* tile_extra, uint32_t* lo_base, Splitter* split)
+// the candidate class (one or two histogram levels) of a segment's median
+__device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const uint32_t* hist1, const uint32_t* hist2,
+                                                  int seg, int k, int* rank, int* ccount, int* sh)
 {
-    __shared__ int sh[kTileThreads / 64];
-    __shared__ int is_last;
-    __shared__ uint64_t skey[kCandCap];
-    __shared__ uint32_t sidx[kCandCap];
-    __shared__ uint16_t stile[kCandCap];
-    __shared__ Splitter sp;
-    TileInfo t = tiles[blockIdx.x];
-    SegInfo sg = segs[t.seg];
-    int k = sg.count / 2;
     ClassRule rule;
-    rule.bk = make_bucketer(keys + 4 * t.seg);
+    rule.bk = make_bucketer(keys + kKeyWords * (int64_t)seg);
     int r1, c1;
-    rule.b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, k, &r1, &c1, sh);
+    rule.b1 = find_bucket(hist1 + (int64_t)seg * kBuckets, k, &r1, &c1, sh);
     rule.b2 = -1;
-    int rank = r1, ccount = c1;
-    if (c1 > kCandCap && rule.bk.scale != 0.0) {
+    *rank = r1;
+    *ccount = c1;
+    if (c1 > kSubThreshold && rule.bk.scale != 0.0) {
         rule.sb = make_sub(rule.bk, rule.b1);
         int r2, c2;
-        rule.b2 = find_bucket(hist2 + (int64_t)t.seg * kBuckets, r1, &r2, &c2, sh);
-        rank = r2; ccount = c2;
+        rule.b2 = find_bucket(hist2 + (int64_t)seg * kBuckets, r1, &r2, &c2, sh);
+        *rank = r2;
+        *ccount = c2;
     }
-    bool overflow = ccount > kCandCap;
+    return rule;
+}
+
+// every tile: count of points below the median's class, and the points of
+// that class appended to the segment's candidate list
+__global__ void __launch_bounds__(kTileThreads)
+k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
+          const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
+          const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1,
+          const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below)
+{
+    __shared__ int sh[kTileThreads / 64];
+    TileInfo t = tiles[blockIdx.x];
+    SegInfo sg = segs[t.seg];
+    int rank, ccount;
+    ClassRule rule = median_class(keys, hist1, hist2, t.seg, sg.count / 2, &rank, &ccount, sh);
+    const bool overflow = ccount > kCandCap;
     const double* C = rule.bk.axis ? Y : X;
     int below = 0;
     for (int i = threadIdx.x; i < t.count; i += kTileThreads) {
@@ -599,18 +634,32 @@ k_select(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     int tot;
     block_excl_scan<kTileThreads>(below, sh, &tot);
     if (threadIdx.x == 0) tile_below[sg.tile0 + t.rank] = (uint32_t)tot;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(&done[t.seg], 1u) == (uint32_t)(sg.ntile - 1));
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // ---- last tile of the segment: exact median and per-tile offsets
-    if (!overflow) {
-        int n = ccount;
+}
+
+// one workgroup per segment: the exact median (coordinate, index) and the
+// output offset of every tile's lower half
+__global__ void __launch_bounds__(kTileThreads)
+k_pick(const int32_t* __restrict__ seglist, const SegInfo* __restrict__ segs, const TileInfo* __restrict__ all_tiles,
+       const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
+       const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, const uint32_t* __restrict__ hist2,
+       const Cand* __restrict__ cand, uint32_t* tile_below, uint32_t* lo_base, Splitter* split)
+{
+    __shared__ int sh[kTileThreads / 64];
+    __shared__ uint64_t skey[kCandCap];
+    __shared__ uint32_t sidx[kCandCap];
+    __shared__ uint16_t stile[kCandCap];
+    __shared__ Splitter sp;
+    const int seg = seglist[blockIdx.x];
+    const SegInfo sg = segs[seg];
+    const int k = sg.count / 2;
+    int rank, ccount;
+    ClassRule rule = median_class(keys, hist1, hist2, seg, k, &rank, &ccount, sh);
+    const double* C = rule.bk.axis ? Y : X;
+    if (ccount <= kCandCap) {
+        const int n = ccount;
         int P = 1;
         while (P < n) P <<= 1;
-        const Cand* cs = cand + (int64_t)t.seg * kCandCap;
+        const Cand* cs = cand + (int64_t)seg * kCandCap;
         for (int i = threadIdx.x; i < P; i += kTileThreads) {
             if (i < n) {
                 Cand cd = cs[i];
@@ -636,13 +685,18 @@ k_select(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
                 __syncthreads();
             }
         if (threadIdx.x == 0) { sp.c = okey_inv(skey[rank]); sp.idx = (int32_t)sidx[rank]; sp.pad = 0; }
-        for (int i = threadIdx.x; i < rank; i += kTileThreads)
-            atomicAdd(&tile_extra[sg.tile0 + stile[i]], 1u);
-        __threadfence();
         __syncthreads();
+        // lower points of a tile = below its class + its candidates ranked below the median
+        for (int t0 = 0; t0 < sg.ntile; t0 += kTileThreads) {
+            int tt = t0 + threadIdx.x;
+            if (tt < sg.ntile) {
+                int extra = 0;
+                for (int i = 0; i < rank; ++i) extra += (stile[i] == tt);
+                tile_below[sg.tile0 + tt] += (uint32_t)extra;
+            }
+        }
     } else {
         exact_select(C, I, sg.start, sg.count, k, &sp);
-        // per-tile counts of points below the splitter
         for (int tt = 0; tt < sg.ntile; ++tt) {
             TileInfo ti = all_tiles[sg.tile0 + tt];
             int cnt = 0;
@@ -650,22 +704,21 @@ k_select(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
                 cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
             int tot2;
             block_excl_scan<kTileThreads>(cnt, sh, &tot2);
-            if (threadIdx.x == 0) { tile_below[sg.tile0 + tt] = (uint32_t)tot2; tile_extra[sg.tile0 + tt] = 0; }
+            if (threadIdx.x == 0) tile_below[sg.tile0 + tt] = (uint32_t)tot2;
         }
-        __threadfence();
-        __syncthreads();
     }
+    __syncthreads();
     // exclusive scan of the per-tile lower counts into output offsets
     int run = 0;
     for (int c0 = 0; c0 < sg.ntile; c0 += kTileThreads) {
         int i = c0 + threadIdx.x;
-        int v = (i < sg.ntile) ? (int)(tile_below[sg.tile0 + i] + tile_extra[sg.tile0 + i]) : 0;
+        int v = (i < sg.ntile) ? (int)tile_below[sg.tile0 + i] : 0;
         int tot3;
         int ex = block_excl_scan<kTileThreads>(v, sh, &tot3);
         if (i < sg.ntile) lo_base[sg.tile0 + i] = (uint32_t)(run + ex);
         run += tot3;
     }
-    if (threadIdx.x == 0) split[t.seg] = sp;
+    if (threadIdx.x == 0) split[seg] = sp;
 }
 
 __global__ void __launch_bounds__(kTileThreads)
@@ -674,29 +727,35 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             double* X2, double* Y2, int32_t* I2, const uint64_t* __restrict__ keys,
             uint64_t* keys_next, const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
 {
+    constexpr int R = kTile / kTileThreads;
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
     SegInfo sg = segs[t.seg];
-    Bucketer bk = make_bucketer(keys + 4 * t.seg);
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     Splitter sp = split[t.seg];
     int k = sg.count / 2;
     int toff = t.start - sg.start;
     int lob = (int)lo_base[sg.tile0 + t.rank];
+    // the whole tile into registers first (element r*256 + tid)
+    double x[R], y[R];
+    int32_t id[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i = r * kTileThreads + threadIdx.x;
+        int ii = t.start + (i < t.count ? i : 0);
+        x[r] = X[ii]; y[r] = Y[ii]; id[r] = I[ii];
+    }
     int lo_run = lob, hi_run = toff - lob;
-    const double* C = bk.axis ? Y : X;
     double lx0 = 1e308, lx1 = -1e308, ly0 = 1e308, ly1 = -1e308;
     double ux0 = 1e308, ux1 = -1e308, uy0 = 1e308, uy1 = -1e308;
     bool anyl = false, anyu = false;
-    for (int r0 = 0; r0 < t.count; r0 += kTileThreads) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int r0 = r * kTileThreads;
+        if (r0 >= t.count) break;   // uniform
         int i = r0 + threadIdx.x;
         bool valid = i < t.count;
-        double x = 0, y = 0;
-        int32_t id = 0;
-        bool lower = false;
-        if (valid) {
-            x = X[t.start + i]; y = Y[t.start + i]; id = I[t.start + i];
-            lower = key_less(bk.axis ? y : x, id, sp.c, sp.idx);
-        }
+        bool lower = valid && key_less(bk.axis ? y[r] : x[r], id[r], sp.c, sp.idx);
         int tot;
         int ex = block_excl_scan<kTileThreads>(lower ? 1 : 0, sh, &tot);
         int nvalid = min(kTileThreads, t.count - r0);
@@ -704,21 +763,20 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             int dst;
             if (lower) {
                 dst = sg.start + lo_run + ex;
-                lx0 = fmin(lx0, x); lx1 = fmax(lx1, x); ly0 = fmin(ly0, y); ly1 = fmax(ly1, y);
+                lx0 = fmin(lx0, x[r]); lx1 = fmax(lx1, x[r]); ly0 = fmin(ly0, y[r]); ly1 = fmax(ly1, y[r]);
                 anyl = true;
             } else {
                 dst = sg.start + k + hi_run + (i - r0 - ex);
-                ux0 = fmin(ux0, x); ux1 = fmax(ux1, x); uy0 = fmin(uy0, y); uy1 = fmax(uy1, y);
+                ux0 = fmin(ux0, x[r]); ux1 = fmax(ux1, x[r]); uy0 = fmin(uy0, y[r]); uy1 = fmax(uy1, y[r]);
                 anyu = true;
             }
-            if (dst >= sg.start && dst < sg.start + sg.count) { X2[dst] = x; Y2[dst] = y; I2[dst] = id; }
+            if (dst >= sg.start && dst < sg.start + sg.count) { X2[dst] = x[r]; Y2[dst] = y[r]; I2[dst] = id[r]; }
         }
         lo_run += tot;
         hi_run += nvalid - tot;
     }
-    (void)C;
-    block_minmax_atomic(lx0, lx1, ly0, ly1, keys_next + 4 * (int64_t)sg.child, anyl);
-    block_minmax_atomic(ux0, ux1, uy0, uy1, keys_next + 4 * ((int64_t)sg.child + 1), anyu);
+    block_minmax_atomic(lx0, lx1, ly0, ly1, keys_next + kKeyWords * (int64_t)sg.child, anyl);
+    block_minmax_atomic(ux0, ux1, uy0, uy1, keys_next + kKeyWords * ((int64_t)sg.child + 1), anyu);
 }
 
 // geometry of boxes whose bounding box came from a global stage
@@ -728,9 +786,9 @@ __global__ void k_geom_keys(const GeomJob* __restrict__ jobs, int64_t n, const u
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     GeomJob j = jobs[i];
-    const uint64_t* k = keys + 4 * (int64_t)j.seg;
-    double bb[4], gm[3];
-    box_geometry(okey_inv(k[0]), okey_inv(k[1]), okey_inv(k[2]), okey_inv(k[3]), bb, gm);
+    double kb[4], bb[4], gm[3];
+    read_keys(keys + kKeyWords * (int64_t)j.seg, kb);
+    box_geometry(kb[0], kb[1], kb[2], kb[3], bb, gm);
     for (int q = 0; q < 4; ++q) bbox[4 * (int64_t)j.box + q] = bb[q];
     for (int q = 0; q < 3; ++q) geom[4 * (int64_t)j.box + q] = gm[q];
 }
@@ -752,7 +810,7 @@ __global__ void k_copy_final(const TileInfo* __restrict__ tiles, const double* X
 // Sorted lists LX (by x, index) and LY (by y, index) of local point ids; a
 // split along an axis keeps that axis' list as is (its first floor(n/2)
 // entries are the lower half) and stably partitions the other list.
-constexpr int kLdsThreads = 256;
+constexpr int kLdsThreads = 1024;
 constexpr int kPer = kLdsCap / kLdsThreads;
 
 struct LdsSort {
@@ -972,7 +1030,7 @@ void build_tree_device(Tree& t, const double* z, hipStream_t s)
     XA.alloc(n, s); YA.alloc(n, s); IA.alloc(n, s);
     if (sc.nstage > 0) { XB.alloc(n, s); YB.alloc(n, s); IB.alloc(n, s); }
     int64_t nkeys = sc.total_keys;
-    DBuf<uint64_t> keys; keys.alloc(4 * nkeys, s);
+    DBuf<uint64_t> keys; keys.alloc(kKeyWords * nkeys, s);
     int64_t nseg_split = sc.nstage > 0 ? sc.keys_off[sc.nstage] : 0;   // segments of split stages
     DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | done | tile_below | tile_extra | lo_base | err
     int64_t nh = nseg_split * kBuckets;
@@ -1005,9 +1063,11 @@ void build_tree_device(Tree& t, const double* z, hipStream_t s)
         int a = st & 1;
         k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
         k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2);
-        k_select<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, sc.d_tiles.p, Xb[a], Yb[a], Ib[a], keys.p,
-                                             W + o_h1, W + o_h2, cand.p, W + o_cc, W + o_dn, W + o_tb,
-                                             W + o_te, W + o_lb, split.p);
+        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, W + o_h1, W + o_h2,
+                                              cand.p, W + o_cc, W + o_tb);
+        k_pick<<<sc.nact[st], kTileThreads, 0, s>>>(sc.d_act.p + sc.act_off[st], sc.d_segs.p, sc.d_tiles.p, Xb[a],
+                                                   Yb[a], Ib[a], keys.p, W + o_h1, W + o_h2, cand.p, W + o_tb,
+                                                   W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
                                                 Ib[a ^ 1], keys.p, keys.p, split.p, W + o_lb);
         check_launch("split stage");

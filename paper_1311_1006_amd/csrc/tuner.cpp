@@ -8,7 +8,9 @@
 //     window of iterations (the problem is assumed to drift slowly);
 //   * a rejected move reverses the walking direction of its knob;
 //   * cost capping for N_levels: a rejected N_levels move adds its extra time
-//     to upcost/downcost, and the next move in that direction is scheduled
+//     to upcost/downcost (each direction has its own budget), basetime sums
+//     the iterations whose move was not rejected, and the next move in that
+//     direction is scheduled
 //       uptime     = (upcost + cost) / cap - basetime
 //       upinterval = uptime * i / basetime
 //     (run time still needed before another misstep of the same cost keeps
@@ -29,7 +31,7 @@
 
 namespace {
 
-const int kSplits[] = {1, 2, 4, 8, 16};
+const int kSplits[] = {1, 2, 4};
 const int kBatches[] = {8, 16, 32, 64};
 
 template <size_t N>
@@ -49,7 +51,8 @@ struct fmm_tuner_s {
     fmm_tuner_params cur, prev;
     Move pending = kNone;
     int64_t i = 0;                 // iterations observed
-    double basetime = 0.0;         // accumulated run time
+    double basetime = 0.0;         // accumulated time of iterations whose move was not rejected
+    double runtime = 0.0;          // all iterations
     double upcost = 0.0, downcost = 0.0, knobcost = 0.0;
     double next_up = 0.0, next_down = 0.0, next_knob = 0.0;
     int split_dir = 1, batch_dir = 1, knob_turn = 0;
@@ -104,7 +107,7 @@ int fmm_tuner_observe(fmm_tuner_t tu, double seconds)
     if (!tu || !(seconds >= 0.0)) return FMM_EINVAL;
     fmm_tuner_s& t = *tu;
     ++t.i;
-    t.basetime += seconds;
+    t.runtime += seconds;
     t.win.push_back(seconds);
     if ((int)t.win.size() < t.cfg.window) return FMM_OK;
     double m = *std::min_element(t.win.begin(), t.win.end());
@@ -123,10 +126,12 @@ int fmm_tuner_observe(fmm_tuner_t tu, double seconds)
             t.cur = t.prev;
         } else {
             t.ref = m;
+            t.basetime += spent;
         }
         t.pending = kNone;
         return FMM_OK;
     }
+    t.basetime += spent;
     t.ref = m;   // steady state: follow the drifting time of the current configuration
     // choose the next move
     const double i = (double)t.i;
@@ -149,7 +154,7 @@ int fmm_tuner_observe(fmm_tuner_t tu, double seconds)
         for (int tries = 0; tries < 2 && t.pending == kNone; ++tries) {
             if ((t.knob_turn++ & 1) == 0) {
                 int k = index_of(kSplits, t.cur.p2p_split) + t.split_dir;
-                if (k >= 0 && k < 5) { t.cur.p2p_split = kSplits[k]; t.pending = kSplit; }
+                if (k >= 0 && k < 3) { t.cur.p2p_split = kSplits[k]; t.pending = kSplit; }
                 else t.split_dir = -t.split_dir;
             } else {
                 int k = index_of(kBatches, t.cur.m2l_batch) + t.batch_dir;
@@ -166,7 +171,7 @@ int fmm_tuner_best(fmm_tuner_t tu, fmm_tuner_params* best, double* cost_s, doubl
     if (!tu) return FMM_EINVAL;
     if (best) *best = tu->pending == kNone ? tu->cur : tu->prev;
     if (cost_s) *cost_s = tu->cost_total;
-    if (run_s) *run_s = tu->basetime;
+    if (run_s) *run_s = tu->runtime;
     return FMM_OK;
 }
 

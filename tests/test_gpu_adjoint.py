@@ -1,0 +1,113 @@
+"""The adjoint FMM (fmm_evaluate_adjoint) against finite differences of the
+same FMM with its geometry frozen, against the analytic gradient of the
+direct sum (CPU oracle), and against the transposition identity
+G_m = -conj(FMM[conj(g)]); plus the torch.autograd wrapper."""
+import numpy as np
+import pytest
+
+from paper_1311_1006_amd import workloads as W
+
+from gpu_util import dev, e2, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1311_1006_amd as F
+    F.lib()
+    return F
+
+
+def _loss(phi):
+    return float(np.sum(np.abs(phi) ** 2))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adjoint_matches_direct_gradient(orc, F, prec):
+    z, m, _ = W.uniform(2000, seed=1)
+    pl = F.plan(F.build_tree(dev(z), 4), 16, 0.5, prec)
+    phi = F.evaluate(pl, dev(m))
+    g = 2 * phi                              # L = sum |phi|^2
+    gm, gz = F.evaluate_adjoint(pl, dev(m), g)
+    rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))
+    tol = 1e-6 if prec == "fp64" else 1e-5
+    assert e2(host(gm), rgm) <= tol
+    assert e2(host(gz), rgz) <= tol
+
+
+def test_adjoint_matches_frozen_geometry_fd(F):
+    # directional central differences (h = 1e-6, FP64) of L = sum |phi|^2 with
+    # the tree geometry frozen (fmm_tree_update_positions)
+    z, m, _ = W.uniform(2000, seed=2)
+    tree = F.build_tree(dev(z), 4)
+    pl = F.plan(tree, 16, 0.5, "fp64")
+    md = dev(m)
+    phi = F.evaluate(pl, md)
+    gm, gz = F.evaluate_adjoint(pl, md, 2 * phi)
+    gm, gz = host(gm), host(gz)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    for _ in range(3):
+        v = rng.standard_normal(2000) + 1j * rng.standard_normal(2000)
+        tree.update_positions(dev(z + h * v))
+        lp = _loss(host(F.evaluate(pl, md)))
+        tree.update_positions(dev(z - h * v))
+        lm = _loss(host(F.evaluate(pl, md)))
+        fd = (lp - lm) / (2 * h)
+        an = float(np.sum(np.real(np.conj(gz) * v)))
+        assert abs(fd - an) <= 1e-6 * abs(an)
+        tree.update_positions(dev(z))
+        lp = _loss(host(F.evaluate(pl, dev(m + h * v))))
+        lm = _loss(host(F.evaluate(pl, dev(m - h * v))))
+        fd = (lp - lm) / (2 * h)
+        an = float(np.sum(np.real(np.conj(gm) * v)))
+        assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_transposition_identity(F):
+    # with symmetric lists the FMM operator is antisymmetric: A^T = -A, so
+    # G_m = conj(A^T conj(g)) = -conj(FMM[conj(g)])
+    z, m, _ = W.uniform(5000, seed=4)
+    g = W.uniform(5000, seed=5)[1]
+    pl = F.plan(F.build_tree(dev(z), 5), 16, 0.5, "fp64")
+    F.evaluate(pl, dev(m))
+    gm, _ = F.evaluate_adjoint(pl, dev(m), dev(g))
+    ref = -np.conj(host(F.evaluate(pl, dev(np.conj(g)))))
+    assert e2(host(gm), ref) <= 1e-12
+
+
+def test_gradient_identities(F):
+    z, m, _ = W.uniform(3000, seed=6)
+    pl = F.plan(F.build_tree(dev(z), 4), 16, 0.5, "fp64")
+    phi = F.evaluate(pl, dev(m))
+    Lv = _loss(host(phi))
+    gm, gz = F.evaluate_adjoint(pl, dev(m), 2 * phi)
+    gm, gz = host(gm), host(gz)
+    scale = np.sum(np.abs(gz * z)) + np.sum(np.abs(gm * m))
+    # scaling of m: dL/de = 2L exactly (phi is linear in m)
+    assert abs(np.sum(np.real(np.conj(gm) * m)) - 2 * Lv) <= 1e-12 * scale
+    # rotations of m leave |phi| unchanged
+    assert abs(np.sum(np.real(np.conj(gm) * 1j * m))) <= 1e-12 * scale
+    # translation and scaling of z hold up to the FMM's truncation (frozen geometry)
+    assert abs(np.sum(gz)) <= 1e-6 * np.sum(np.abs(gz))
+    assert abs(np.sum(np.real(np.conj(gz) * z)) + 2 * Lv) <= 1e-6 * scale
+
+
+def test_autograd_function(orc, F):
+    import torch
+    z, m, _ = W.uniform(2000, seed=7)
+    zt = dev(z).requires_grad_(True)
+    mt = dev(m).requires_grad_(True)
+    phi = F.potential(zt, mt, p=16, theta=0.5, n_levels=4, precision="fp64")
+    loss = (phi.abs() ** 2).sum()
+    loss.backward()
+    rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))
+    assert e2(zt.grad.cpu().numpy(), rgz) <= 1e-6
+    assert e2(mt.grad.cpu().numpy(), rgm) <= 1e-6
+    # torch's own complex-gradient convention on a holomorphic map of m
+    w = torch.tensor([1.0 + 2.0j], dtype=torch.complex128, requires_grad=True)
+    (w.abs() ** 2).sum().backward()
+    assert complex(w.grad[0]) == 2.0 + 4.0j
