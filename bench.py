@@ -31,6 +31,59 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _time(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def measure_forms(F, W, torch, dev, reps):
+    """(2) 128 problems of uneven size in one graph launch vs 128 sequential
+    plain launches (same trees, levels, p, shapes); (3) adjoint / forward time
+    at N = 2e5, p = 16, mixed precision."""
+    from paper_1311_1006_amd.driver import default_levels
+    out = {}
+    zs, ms, kinds = W.batch(nprob=128, seed=0)
+    Ls = [default_levels(len(z)) for z in zs]
+    off = [0]
+    for z in zs:
+        off.append(off[-1] + len(z))
+    zc = torch.from_numpy(np.concatenate(zs)).to(dev)
+    mc = torch.from_numpy(np.concatenate(ms)).to(dev)
+    oc = torch.empty_like(mc)
+    for prec in ("mixed", "fp64"):
+        tree = F.build_tree(zc, Ls, offsets=off)
+        pg = F.plan(tree, 16, 0.5, prec, graph=True)
+        tb = _time(lambda: F.evaluate(pg, mc, oc), reps, torch)
+        singles = []
+        for b in range(len(zs)):
+            zb = zc[off[b]:off[b + 1]]
+            tr = F.build_tree(zb, Ls[b])
+            singles.append((tr, F.plan(tr, 16, 0.5, prec), mc[off[b]:off[b + 1]], oc[off[b]:off[b + 1]]))
+        ts = _time(lambda: [F.evaluate(pl, mb, ob) for _, pl, mb, ob in singles], max(2, reps // 4), torch)
+        out["batch128_" + prec] = {"n_total": off[-1], "graph_ms": tb * 1e3, "sequential_ms": ts * 1e3,
+                                   "speedup": ts / tb, "mpoints_s": off[-1] / tb / 1e6}
+        log("batch of 128 (%s): graph %.3f ms, 128 sequential launches %.3f ms" % (prec, tb * 1e3, ts * 1e3))
+        del singles, pg, tree
+    z, m, _ = W.uniform(200000, seed=0)
+    zd = torch.from_numpy(z).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    tree = F.build_tree(zd, default_levels(z.size))
+    for prec in ("mixed", "fp64"):
+        pl = F.plan(tree, 16, 0.5, prec)
+        phi = F.evaluate(pl, md)
+        g = 2 * phi
+        tf = _time(lambda: F.evaluate(pl, md, phi), reps, torch)
+        ta = _time(lambda: F.evaluate_adjoint(pl, md, g), reps, torch)
+        out["adjoint_n2e5_" + prec] = {"forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3, "ratio": ta / tf}
+        log("adjoint N=2e5 (%s): forward %.3f ms, adjoint %.3f ms, ratio %.2f" % (prec, tf * 1e3, ta * 1e3, ta / tf))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +94,7 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--levels", type=str, default="8,9,10")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batch and adjoint measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +170,8 @@ def main():
         log("%s: L=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, P2P %.1f us" %
             (prec, L, dt * 1e3, n / dt / 1e6, dte * 1e3, res[prec]["p2p_us"]))
 
+    forms = None if args.no_forms else measure_forms(F, W, torch, dev, args.steps)
+
     # ---- accuracy vs the FP64 direct sum (CPU oracle) on the subsample
     err = {}
     cpu_baseline = None
@@ -167,6 +223,7 @@ def main():
                      "frac_without_packed_fp32": achieved / PEAK_FP32_NOPACK,
                      "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR},
         "cpu_baseline": cpu_baseline,
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
 

@@ -39,7 +39,7 @@ template <class T>
 void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
-                int, const void*, void*, hipStream_t);
+                int, const void*, void*, hipStream_t, int);
 void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
                    const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
 
@@ -297,7 +297,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
             launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p, s);
         }
         launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p,
-                      pl.amp.p, pl.aloc.p, s);
+                      pl.amp.p, pl.aloc.p, s, pl.tune.m2l_batch);
         for (int l = 1; l + 1 < sc.max_levels; ++l) {
             int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
             launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.aloc.p, s);

@@ -232,8 +232,8 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         if (tune) tn = *tune;
         FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4,
                     "p2p_split must be 0, 1, 2 or 4");
-        FMM_REQUIRE(tn.m2l_batch == 0 || (tn.m2l_batch >= 8 && tn.m2l_batch <= 64 && tn.m2l_batch % 8 == 0),
-                    "m2l_batch must be 0 or a multiple of 8 in [8, 64]");
+        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 8 || tn.m2l_batch == 16 || tn.m2l_batch == 32,
+                    "m2l_batch must be 0, 8, 16 or 32");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         auto pp = std::make_unique<fmm_plan_s>();
@@ -267,7 +267,14 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
 void fmm_plan_destroy(fmm_plan_t pl)
 {
     if (!pl) return;
-    if (pl->pl.graph) (void)hipGraphExecDestroy(pl->pl.graph);
+    Plan& P = pl->pl;
+    if (P.graph) (void)hipGraphExecDestroy(P.graph);
+    if (P.gstream) {
+        (void)hipStreamSynchronize(P.gstream);
+        (void)hipStreamDestroy(P.gstream);
+        (void)hipEventDestroy(P.ev_in);
+        (void)hipEventDestroy(P.ev_out);
+    }
     delete pl;
 }
 
@@ -279,31 +286,41 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
         hipStream_t s = (hipStream_t)stream;
         Plan& P = pl->pl;
         if (P.tune.flags & FMM_FLAG_GRAPH) {
-            if (!P.graph || P.graph_m != m || P.graph_phi != phi || P.graph_stream != s) {
+            // capture and replay on a plan-owned stream (the legacy null stream
+            // cannot be captured), ordered after the caller's stream by events
+            if (!P.gstream) {
+                FMM_HIP(hipStreamCreateWithFlags(&P.gstream, hipStreamNonBlocking));
+                FMM_HIP(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
+                FMM_HIP(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
+            }
+            FMM_HIP(hipEventRecord(P.ev_in, s));
+            FMM_HIP(hipStreamWaitEvent(P.gstream, P.ev_in, 0));
+            if (!P.graph || P.graph_m != m || P.graph_phi != phi) {
                 if (P.graph) { FMM_HIP(hipGraphExecDestroy(P.graph)); P.graph = nullptr; }
-                hipGraph_t g;
-                FMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                hipGraph_t g = nullptr;
+                FMM_HIP(hipStreamBeginCapture(P.gstream, hipStreamCaptureModeThreadLocal));
                 int saved = P.tune.flags;
                 P.tune.flags &= ~FMM_FLAG_PHASE_TIMING;
                 try {
-                    evaluate_device(P, m, phi, nullptr, nullptr, s);
+                    evaluate_device(P, m, phi, nullptr, nullptr, P.gstream);
                 } catch (...) {
                     P.tune.flags = saved;
-                    hipGraph_t dead;
-                    (void)hipStreamEndCapture(s, &dead);
+                    hipGraph_t dead = nullptr;
+                    (void)hipStreamEndCapture(P.gstream, &dead);
                     if (dead) (void)hipGraphDestroy(dead);
                     throw;
                 }
                 P.tune.flags = saved;
-                FMM_HIP(hipStreamEndCapture(s, &g));
+                FMM_HIP(hipStreamEndCapture(P.gstream, &g));
                 hipError_t e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 if (e != hipSuccess) throw Error(FMM_EDEVICE, "hipGraphInstantiate failed");
                 P.graph_m = m;
                 P.graph_phi = phi;
-                P.graph_stream = s;
             }
-            FMM_HIP(hipGraphLaunch(P.graph, s));
+            FMM_HIP(hipGraphLaunch(P.graph, P.gstream));
+            FMM_HIP(hipEventRecord(P.ev_out, P.gstream));
+            FMM_HIP(hipStreamWaitEvent(s, P.ev_out, 0));
             P.have_forward = true;
         } else {
             evaluate_device(P, m, phi, nullptr, nullptr, s);

@@ -31,7 +31,7 @@ void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, const doubl
                 const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
 template <class T>
 void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
-                int, const void*, void*, hipStream_t);
+                int, const void*, void*, hipStream_t, int);
 void launch_p2p(bool mixed, int tg, int sub, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
                 const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src, const void* lo,
                 double* out, hipStream_t s);
@@ -174,7 +174,7 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp,
-                  loc, s);
+                  loc, s, pl.tune.m2l_batch);
     // parents at level l (non-leaf) hand their expansion to level l+1
     for (int l = 1; l + 1 < sc.max_levels; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);

@@ -38,31 +38,43 @@ __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const doub
     }
 }
 
-// P2M at the leaves.  Lane = point; the p terms m_j w_j^k are reduced over the
-// points through LDS, 8 coefficients at a time, in point order.
-template <class T>
-__global__ void __launch_bounds__(64)
-k_p2m(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
-      const double* __restrict__ geom, const double* __restrict__ X, const double* __restrict__ Y,
-      const double2* __restrict__ mt, int p, T* mp)
+__device__ __forceinline__ void wave_sync_e()
 {
-    __shared__ double2 buf[64][9];
-    int g = leaves[blockIdx.x];
-    int lane = threadIdx.x;
-    int st = bstart[g], n = bcount[g];
-    double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// P2M at the leaves.  One wavefront per leaf (four per workgroup); lane =
+// point; the terms m_j w_j^k go through LDS, 8 coefficients at a time, and
+// are summed over the points in point order.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
+      const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
+      const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp)
+{
+    __shared__ double2 buf_all[4][64][9];
+    const int wv = threadIdx.x >> 6;
+    const int li = blockIdx.x * 4 + wv;
+    if (li >= nleaf) return;
+    auto& buf = buf_all[wv];
+    const int g = leaves[li];
+    const int lane = threadIdx.x & 63;
+    const int st = bstart[g], n = bcount[g];
+    const double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
     double acc[kMaxP / 8];
 #pragma unroll
     for (int c = 0; c < kMaxP / 8; ++c) acc[c] = 0.0;
-    int kk = lane >> 1, part = lane & 1;   // lanes 0..15: coefficient k0 + kk, component part
+    const int kk = lane >> 1, part = lane & 1;   // lanes 0..15: coefficient 8c + kk, component part
     for (int j0 = 0; j0 < n; j0 += 64) {
-        int j = j0 + lane;
+        const int j = j0 + lane;
         double2 w = make_double2(0, 0), pw = make_double2(1, 0), mm = make_double2(0, 0);
         if (j < n) {
             w = make_double2((X[st + j] - cx) * inv, (Y[st + j] - cy) * inv);
             mm = mt[st + j];
         }
-        int cnt = min(64, n - j0);
+        const int cnt = min(64, n - j0);
 #pragma unroll
         for (int c = 0; c < kMaxP / 8; ++c) {
             if (8 * c >= p) break;
@@ -71,19 +83,19 @@ k_p2m(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, co
                 buf[lane][q] = cmul(mm, pw);
                 pw = cmul(pw, w);
             }
-            __syncthreads();
+            wave_sync_e();
             if (lane < 16) {
                 double s = 0.0;
                 for (int jj = 0; jj < cnt; ++jj) s += part ? buf[jj][kk].y : buf[jj][kk].x;
                 acc[c] += s;
             }
-            __syncthreads();
+            wave_sync_e();
         }
     }
     if (lane < 16) {
 #pragma unroll
         for (int c = 0; c < kMaxP / 8; ++c) {
-            int k = 8 * c + kk;
+            const int k = 8 * c + kk;
             if (k < p) mp[2 * ((int64_t)g * p + k) + part] = (T)acc[c];
         }
     }
@@ -191,20 +203,25 @@ k_l2l(const int32_t* __restrict__ parents, const int32_t* __restrict__ child0, c
 
 // L2P at the leaves, plus the near field, scattered to input order
 template <class T>
-__global__ void __launch_bounds__(64)
-k_l2p(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
+__global__ void __launch_bounds__(256)
+k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
+      const int32_t* __restrict__ bcount,
       const double* __restrict__ geom, const double* __restrict__ X, const double* __restrict__ Y,
       const T* __restrict__ loc, int p, const double2* __restrict__ nearf, const int32_t* __restrict__ perm,
       double2* phi, double2* phi_near, double2* phi_far)
 {
-    __shared__ double2 bl[kMaxP];
-    int g = leaves[blockIdx.x];
+    __shared__ double2 bl_all[4][kMaxP];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = blockIdx.x * 4 + wv;
+    if (li >= nleaf) return;
+    double2* bl = bl_all[wv];
+    int g = leaves[li];
     int st = bstart[g], n = bcount[g];
     double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
     const T* b = loc + 2 * (int64_t)g * p;
-    if (threadIdx.x < p) bl[threadIdx.x] = make_double2((double)b[2 * threadIdx.x], (double)b[2 * threadIdx.x + 1]);
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += 64) {
+    if (lane < p) bl[lane] = make_double2((double)b[2 * lane], (double)b[2 * lane + 1]);
+    wave_sync_e();
+    for (int j = lane; j < n; j += 64) {
         int i = st + j;
         double2 w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
         double2 acc = bl[p - 1];
@@ -247,7 +264,8 @@ void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
                 hipStream_t s)
 {
     if (nleaf == 0) return;
-    k_p2m<T><<<nleaf, 64, 0, s>>>(leaves, bstart, bcount, geom, X, Y, (const double2*)mt, p, (T*)mp);
+    k_p2m<T><<<(nleaf + 3) / 4, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const double2*)mt, p,
+                                             (T*)mp);
     check_launch("p2m");
 }
 
@@ -276,7 +294,8 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
                 hipStream_t s)
 {
     if (nleaf == 0) return;
-    k_l2p<T><<<nleaf, 64, 0, s>>>(leaves, bstart, bcount, geom, X, Y, (const T*)loc, p, (const double2*)nearf,
+    k_l2p<T><<<(nleaf + 3) / 4, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const T*)loc, p,
+                                             (const double2*)nearf,
                                   perm, (double2*)phi, (double2*)phi_near, (double2*)phi_far);
     check_launch("l2p");
 }

@@ -205,7 +205,8 @@ struct Plan {
     hipGraphExec_t graph = nullptr;
     const double* graph_m = nullptr;
     double* graph_phi = nullptr;
-    hipStream_t graph_stream = nullptr;
+    hipStream_t gstream = nullptr;         // capture / replay stream of graph mode
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 // ---------------------------------------------------------- launchers

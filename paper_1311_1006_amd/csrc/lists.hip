@@ -9,6 +9,8 @@
 // bounds-checked against the pool capacity; an overflow flag makes the host
 // grow the pools and run the build again.
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "fmm_internal.h"
 #include "plan_extra.h"
@@ -159,7 +161,7 @@ k_scan_apply(const int32_t* boxes, int n, const int32_t* s_cnt, const int32_t* w
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         totals[0] = bs0 + ts;
         totals[1] = bw0 + tw;
-        if (bs0 + ts > cap_s || bw0 + tw > cap_w) totals[2] = 1;
+        if (bs0 + ts > cap_s || bw0 + tw > cap_w) totals[2] |= 1;
     }
 }
 
@@ -193,6 +195,163 @@ __global__ void k_count_p2p(const int32_t* leaves, int n, const int32_t* box_cou
     if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long*)&totals[3], (unsigned long long)v);
 }
 
+// ----------------------------------------------------------------------------
+// Several levels per pass: for the boxes of levels l0..l1 together, one
+// wavefront per box walks down from its ancestor at level l0-1 (whose strong
+// list is already in the pool; from the root itself when l0 = 0) to the box,
+// keeping the strong list of the ancestor at each level in an LDS frontier.
+// The frontier of the box's own level is its strong list, the candidates
+// rejected there its weak list; ballots keep both in the order the
+// level-by-level build gives.  A pass is count, scan, fill, so a few passes
+// replace four launches per level; a deeper pass repeats the upper levels of
+// its range once per box, so the passes are kept short near the leaves.  A
+// frontier larger than kFrontCap sets bit 1 of the overflow word and the
+// level-by-level build runs instead.
+constexpr int kFrontCap = 1024;
+
+struct TravCtx {
+    const int32_t* boxes;     // global ids of the pass's boxes (levels l0..l1)
+    int n;
+    int l0;
+    const int32_t* prob;
+    const int8_t* level;
+    const int64_t* pbox;
+    const double* geom;
+    double theta;
+};
+
+__device__ __forceinline__ void wave_sync_l()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256)
+k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
+           int32_t* w_ids, int64_t cap_s, int64_t cap_w, long long* totals)
+{
+    __shared__ int32_t front_all[4][2][kFrontCap];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wv;
+    if (i >= c.n) return;
+    int32_t* fa = front_all[wv][0];
+    int32_t* fb = front_all[wv][1];
+    const int64_t g = c.boxes[i];
+    const int L = c.level[g];
+    const int64_t pb = c.pbox[c.prob[g]];
+    const int64_t jl = g - pb - level_base(L);        // index of the box within its level
+    bool overflow = false;
+    int nf;
+    if (c.l0 == 0) {
+        nf = 1;
+        if (lane == 0) fa[0] = (int32_t)pb;           // the root is strong with itself
+    } else {
+        const int64_t a0 = pb + level_base(c.l0 - 1) + (jl >> (2 * (L - c.l0 + 1)));
+        const int64_t ab = s_beg[a0];
+        nf = s_cnt[a0];
+        if (nf > kFrontCap) { overflow = true; nf = kFrontCap; }
+        for (int e = lane; e < nf; e += 64) fa[e] = (ab + e < cap_s) ? s_ids[ab + e] : (int32_t)pb;
+    }
+    wave_sync_l();
+    int64_t sb = 0, wb = 0;
+    if (FILL) { sb = s_beg[g]; wb = w_beg[g]; }
+    int nw = 0;
+    for (int k = (c.l0 == 0 ? 1 : c.l0); k <= L; ++k) {
+        const int64_t anc = pb + level_base(k) + (jl >> (2 * (L - k)));
+        const double* ga = c.geom + 4 * anc;
+        const int64_t lb = level_base(k), lbp = level_base(k - 1);
+        const int ncand = 4 * nf;
+        const bool last = k == L;
+        int nn = 0;
+        for (int c0 = 0; c0 < ncand; c0 += 64) {
+            const int idx = c0 + lane;
+            const bool valid = idx < ncand;
+            bool weak = false;
+            int32_t cc = 0;
+            if (valid) {
+                const int32_t q = fa[idx >> 2];
+                cc = (int32_t)(pb + lb + 4 * ((int64_t)q - pb - lbp) + (idx & 3));
+                weak = (cc != anc) && well_separated(ga, c.geom + 4 * (int64_t)cc, c.theta);
+            }
+            const unsigned long long bs = __ballot(valid && !weak), bw = __ballot(valid && weak);
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            if (valid && !weak) {
+                const int o = nn + __popcll(bs & below);
+                if (!last && o < kFrontCap) fb[o] = cc;
+                if (FILL && last && sb + o < cap_s) s_ids[sb + o] = cc;
+            }
+            if (FILL && last && valid && weak) {
+                const int64_t o = wb + nw + __popcll(bw & below);
+                if (o < cap_w) w_ids[o] = cc;
+            }
+            nn += __popcll(bs);
+            if (last) nw += __popcll(bw);
+        }
+        if (!last && nn > kFrontCap) { overflow = true; nn = kFrontCap; }
+        wave_sync_l();
+        int32_t* t = fa; fa = fb; fb = t;
+        nf = nn;
+    }
+    if (lane == 0) {
+        if (L == 0) {                                  // a root (only in a pass with l0 = 0)
+            if (!FILL) { s_cnt[g] = 1; w_cnt[g] = 0; }
+            else if (sb < cap_s) s_ids[sb] = (int32_t)g;
+        } else if (!FILL) {
+            s_cnt[g] = nf;
+            w_cnt[g] = nw;
+        }
+        if (overflow) atomicOr((unsigned long long*)&totals[2], 2ull);
+    }
+}
+
+__global__ void k_totals_init(long long* totals)
+{
+    if (threadIdx.x == 0) { totals[0] = 0; totals[1] = 0; totals[2] = 0; totals[3] = 0; }
+}
+
+// Level ranges of the passes: the deepest level alone, the two above it
+// together, everything above those from the root.
+static std::vector<std::pair<int, int>> traversal_passes(int levels)
+{
+    std::vector<std::pair<int, int>> r;
+    const int top = levels - 1;
+    if (levels <= 4) { r.push_back({0, top}); return r; }
+    r.push_back({0, top - 3});
+    r.push_back({top - 2, top - 1});
+    r.push_back({top, top});
+    return r;
+}
+
+static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_t cap_w, long long* totals,
+                                  const int64_t* pbox, long long* bsum, long long* snap)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    const PlanExtra& ex = *pl.ex;
+    k_totals_init<<<1, 64, 0, s>>>(totals);
+    for (auto [l0, l1] : traversal_passes(sc.max_levels)) {
+        TravCtx c;
+        c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
+        c.n = (int)(ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]);
+        if (c.n == 0) continue;
+        c.l0 = l0;
+        c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
+        c.geom = t.geom.p; c.theta = pl.theta;
+        const unsigned grid = (unsigned)((c.n + 3) / 4);
+        k_traverse<false><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                               pl.w_ids.p, cap_s, cap_w, totals);
+        const int nb = (c.n + 1023) / 1024;
+        k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, totals, snap);
+        k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, snap, pl.s_beg.p,
+                                         pl.w_beg.p, totals, cap_s, cap_w);
+        k_traverse<true><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                              pl.w_ids.p, cap_s, cap_w, totals);
+        check_launch("traversal lists");
+    }
+}
+
 void build_lists_device(Plan& pl, hipStream_t s)
 {
     Tree& t = *pl.tree;
@@ -203,14 +362,31 @@ void build_lists_device(Plan& pl, hipStream_t s)
     FMM_HIP(hipMemcpyAsync(pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
     DBuf<long long> totals; totals.alloc(4, s);
     DBuf<long long> snap; snap.alloc(2, s);
-    int maxn = 1;
-    for (auto& v : pl.ex->level_boxes) maxn = std::max(maxn, (int)v.size());
-    DBuf<long long> bsum; bsum.alloc(2 * ((maxn + 1023) / 1024), s);
+    DBuf<long long> bsum; bsum.alloc(2 * ((nb + 1023) / 1024), s);
     int64_t cap_s = std::max<int64_t>(pl.n_strong, 24 * nb + 1024);
     int64_t cap_w = std::max<int64_t>(pl.n_weak, 64 * nb + 1024);
-    for (int attempt = 0; attempt < 3; ++attempt) {
+    bool levelwise = false;
+    for (int attempt = 0; attempt < 4; ++attempt) {
         pl.s_ids.alloc(cap_s, s);
         pl.w_ids.alloc(cap_w, s);
+        if (!levelwise) {
+            build_lists_traversal(pl, s, cap_s, cap_w, totals.p, pbox.p, bsum.p, snap.p);
+            int nl = (int)sc.nleaf;
+            k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
+                                                         pl.s_cnt.p, pl.s_ids.p, totals.p, cap_s);
+            check_launch("count p2p");
+            long long h[4];
+            FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
+            FMM_HIP(hipStreamSynchronize(s));
+            if (h[2] & 2) { levelwise = true; continue; }   // a frontier overflowed
+            pl.n_strong = h[0];
+            pl.n_weak = h[1];
+            pl.n_p2p_pairs = h[3];
+            if (!(h[2] & 1)) return;
+            cap_s = h[0] + h[0] / 4 + 1024;
+            cap_w = h[1] + h[1] / 4 + 1024;
+            continue;
+        }
         const int32_t* lv = pl.ex->d_level_boxes.p;
         int nroot = (int)pl.ex->level_boxes[0].size();
         k_root_lists<<<(nroot + 255) / 256, 256, 0, s>>>(lv, nroot, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,

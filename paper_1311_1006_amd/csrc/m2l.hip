@@ -47,23 +47,47 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int j) { return (lane >> 4) + 4 * j; }
 };
 
-constexpr int kM2LBatch = 32;   // pairs per LDS batch
+__device__ __forceinline__ void wave_sync_m()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-template <class T, int PB>
-__global__ void __launch_bounds__(64)
-k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, const int32_t* __restrict__ w_cnt,
-      const int32_t* __restrict__ w_ids, const double* __restrict__ geom, const double* __restrict__ binom,
-      int p, const T* __restrict__ mp, T* loc)
+__device__ __forceinline__ double2 cpow_m(double2 b, int e)
+{
+    double2 r = make_double2(1.0, 0.0);
+    while (e) {
+        if (e & 1) r = cmul(r, b);
+        b = cmul(b, b);
+        e >>= 1;
+    }
+    return r;
+}
+
+// B pairs per batch; the 64 lanes are (pair q < B, role, chunk h < H) with
+// B * 2 * H = 64: each lane runs PP/H steps of its power recurrence.
+// Four independent wavefronts per workgroup, each with its own LDS tile.
+template <class T, int PB, int B>
+__global__ void __launch_bounds__(256)
+k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w_beg,
+      const int32_t* __restrict__ w_cnt, const int32_t* __restrict__ w_ids, const double* __restrict__ geom,
+      const double* __restrict__ binom, int p, const T* __restrict__ mp, T* loc)
 {
     using T2 = typename Vec2<T>::type;
     using M = Mfma<T>;
     constexpr int PP = 16 * PB;      // padded number of terms
     constexpr int KS = PP / 4;       // k-steps of 4
+    constexpr int H = 32 / B;        // k-chunks per (pair, role)
+    constexpr int PH = PP / H;       // terms per chunk
     // tile[0] = scaled source columns x, tile[1] = target row factors f
-    __shared__ T2 tile[2][kM2LBatch][PP + 1];
-    __shared__ int sid[kM2LBatch];
-    const int g = boxes[blockIdx.x];
-    const int lane = threadIdx.x;
+    __shared__ T2 tile_all[4][2][B][PP + 1];
+    const int w = threadIdx.x >> 6;
+    const int bi = blockIdx.x * 4 + w;
+    if (bi >= nbox) return;
+    auto& tile = tile_all[w];
+    const int g = boxes[bi];
+    const int lane = threadIdx.x & 63;
     const int nw = w_cnt[g], wb = w_beg[g];
     const int col = lane & 15, kq = lane >> 4, part = col & 1, slot = col >> 1;
 
@@ -83,52 +107,42 @@ k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, cons
         for (int j = 0; j < 4; ++j) oacc[rb][j] = (T)0;
 
     const double ctx = geom[4 * (int64_t)g], cty = geom[4 * (int64_t)g + 1], rsT = geom[4 * (int64_t)g + 3];
-    for (int b0 = 0; b0 < nw; b0 += kM2LBatch) {
-        // ---- phase 0: the batch's source multipoles into tile[0] (coalesced per source)
-        if (lane < kM2LBatch) sid[lane] = (b0 + lane < nw) ? w_ids[wb + b0 + lane] : -1;
-        __syncthreads();
-        for (int e = lane; e < kM2LBatch * PP; e += 64) {
-            const int q = e / PP, k = e % PP;
-            const int S = sid[q];
-            T2 v;
-            v.x = (T)0; v.y = (T)0;
-            if (S >= 0 && k < p) v = reinterpret_cast<const T2*>(mp)[(int64_t)S * p + k];
-            tile[0][q][k] = v;
-        }
-        __syncthreads();
-        // ---- phase 1: lanes 0..31 scale the source columns in place, lanes
-        // 32..63 form the target factors; both run the recurrence
-        //     out_k = pw_k * c_k,  pw_{k+1} = pw_k * base
-        // with (base, c_k) = (rs_S/d, a_k) or (-rs_T/d, 1/d), in FP64.
+    // lane roles of phase 1
+    const int q = lane % B, role = (lane / B) & 1, h = lane / (2 * B);
+    const int k0 = h * PH;
+    for (int b0 = 0; b0 < nw; b0 += B) {
+        // ---- phase 1: x_k = (rs_S/d)^k a_k (role 0) or f_l = (1/d)(-rs_T/d)^l (role 1)
+        // for k in [k0, k0 + PH), FP64 powers, cast to the storage type
         {
-            const int q = lane & (kM2LBatch - 1);
-            const int role = lane < kM2LBatch ? 0 : 1;
-            const int S = sid[q];
-            const bool valid = S >= 0;
-            const double* gs = geom + 4 * (int64_t)(valid ? S : g);
-            double dx = ctx - gs[0], dy = cty - gs[1];
-            double den = valid ? 1.0 / (dx * dx + dy * dy) : 0.0;
-            double2 id = make_double2(dx * den, -dy * den);     // 1/d (0 for padding)
-            double rb_ = role ? -rsT : gs[3];
-            double2 base = make_double2(rb_ * id.x, rb_ * id.y);
-            double2 pw = make_double2(1.0, 0.0);
+            const bool valid = b0 + q < nw;
+            const int S = valid ? w_ids[wb + b0 + q] : g;
+            const double* gs = geom + 4 * (int64_t)S;
+            const double dx = ctx - gs[0], dy = cty - gs[1];
+            const double den = valid ? 1.0 / (dx * dx + dy * dy) : 0.0;
+            const double2 id = make_double2(dx * den, -dy * den);     // 1/d (0 for padding)
+            const double rb_ = role ? -rsT : gs[3];
+            const double2 base = make_double2(rb_ * id.x, rb_ * id.y);
+            double2 pw = cpow_m(base, k0);
+            if (role) pw = cmul(pw, id);
+            const T2* a = reinterpret_cast<const T2*>(mp) + (int64_t)S * p;
 #pragma unroll 4
-            for (int k = 0; k < PP; ++k) {
-                double2 c = id;
+            for (int j = 0; j < PH; ++j) {
+                const int k = k0 + j;
+                double2 t = pw;
                 if (role == 0) {
-                    T2 a = tile[0][q][k];
-                    c = make_double2((double)a.x, (double)a.y);
+                    T2 ak;
+                    if (k < p && valid) ak = a[k]; else { ak.x = (T)0; ak.y = (T)0; }
+                    t = cmul(pw, make_double2((double)ak.x, (double)ak.y));
                 }
-                double2 t = cmul(pw, c);
                 T2 v;
                 v.x = (T)t.x; v.y = (T)t.y;
                 tile[role][q][k] = v;
                 pw = cmul(pw, base);
             }
         }
-        __syncthreads();
+        wave_sync_m();
         // ---- phase 2: MFMA per block of 8 pairs, row scaling, accumulation
-        const int nblk = min(kM2LBatch / 8, (nw - b0 + 7) / 8);
+        const int nblk = min(B / 8, (nw - b0 + 7) / 8);
         for (int nb = 0; nb < nblk; ++nb) {
             const int qq = 8 * nb + slot;
 #pragma unroll
@@ -150,7 +164,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, cons
                 }
             }
         }
-        __syncthreads();
+        wave_sync_m();
     }
     // ---- sum over the 8 pair slots (lanes differing in bits 1..3)
 #pragma unroll
@@ -174,21 +188,38 @@ k_m2l(const int32_t* __restrict__ boxes, const int32_t* __restrict__ w_beg, cons
     }
 }
 
+template <class T, int PB, int B>
+static void m2l_one(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
+                    const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
+{
+    k_m2l<T, PB, B><<<(n + 3) / 4, 256, 0, s>>>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp,
+                                                (T*)loc);
+}
+
+// batch: pairs per LDS batch (8, 16, 32; 0 = automatic).  FP64 tiles are
+// twice as large, so FP64 defaults to smaller batches.
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
-                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
+                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s,
+                int batch)
 {
     if (n == 0) return;
-    if (p <= 16)
-        k_m2l<T, 1><<<n, 64, 0, s>>>(boxes, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp, (T*)loc);
-    else
-        k_m2l<T, 2><<<n, 64, 0, s>>>(boxes, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp, (T*)loc);
-    check_launch("m2l");
+    const bool dbl = sizeof(T) == 8;
+    if (batch <= 0) batch = dbl ? 16 : 32;
+    if (batch > 32) batch = 32;
+    if (batch != 8 && batch != 16 && batch != 32) batch = 16;
+    if (p > 16 && batch == 32 && dbl) batch = 16;   // LDS per workgroup
+#define M2L_CASE(PB_, B_) \
+    if ((p <= 16 ? 1 : 2) == PB_ && batch == B_) { m2l_one<T, PB_, B_>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s); check_launch("m2l"); return; }
+    M2L_CASE(1, 8) M2L_CASE(1, 16) M2L_CASE(1, 32)
+    M2L_CASE(2, 8) M2L_CASE(2, 16) M2L_CASE(2, 32)
+#undef M2L_CASE
+    throw Error(FMM_EINVAL, "unsupported M2L configuration");
 }
 
 template void launch_m2l<double>(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*,
-                                 const double*, const double*, int, const void*, void*, hipStream_t);
+                                 const double*, const double*, int, const void*, void*, hipStream_t, int);
 template void launch_m2l<float>(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*,
-                                const double*, const double*, int, const void*, void*, hipStream_t);
+                                const double*, const double*, int, const void*, void*, hipStream_t, int);
 
 }  // namespace fmm

@@ -148,16 +148,28 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, const int32_t
         const int take = min(total, kP2PSrcCap - staged);
         meta[lane] = make_int2(excl, st);
         wave_sync();
-        for (int f = lane; f < take; f += 64) {
-            // the entry holding flat position f: largest j with excl_j <= f
+        // positions f = lane + 64 r (take <= kP2PSrcCap = 4 * 64): find every
+        // position's source first, then issue all loads, then store
+        constexpr int R = kP2PSrcCap / 64;
+        int src_idx[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int f = lane + 64 * r;
             int lo = 0, hi = 63;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
                 if (meta[mid].x <= f) lo = mid; else hi = mid - 1;
             }
-            int2 mj = meta[lo];
-            lds[staged + f] = load(mj.y + (f - mj.x));
+            const int2 mj = meta[lo];
+            src_idx[r] = (f < take) ? mj.y + (f - mj.x) : -1;
         }
+        SRC v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (src_idx[r] >= 0) v[r] = load(src_idx[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (src_idx[r] >= 0) lds[staged + lane + 64 * r] = v[r];
         // advance the cursor (uniform)
         if (take == total) {
             e = min(e + 64, e_end);

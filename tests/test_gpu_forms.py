@@ -1,0 +1,80 @@
+"""The batched / graph-replayed form and the time-stepping driver with the
+tuner, through the C ABI.  Graph replays are checked against eager
+evaluations after every replay, with eager work in between."""
+import numpy as np
+import pytest
+
+from paper_1311_1006_amd import workloads as W
+
+from gpu_util import dev, e2, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1311_1006_amd as F
+    F.lib()
+    return F
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_match_eager(F, prec):
+    import torch
+    zs, ms, _ = W.batch(nprob=24, seed=3, nmin=1000, nmax=20000)
+    from paper_1311_1006_amd.driver import default_levels
+    Ls = [default_levels(len(z)) for z in zs]
+    off = np.concatenate([[0], np.cumsum([len(z) for z in zs])]).tolist()
+    zc = np.concatenate(zs)
+    tree = F.build_tree(dev(zc), Ls, offsets=off)
+    pg = F.plan(tree, 16, 0.5, prec, graph=True)
+    pe = F.plan(tree, 16, 0.5, prec)
+    m_buf = dev(np.concatenate(ms))
+    out = torch.empty_like(m_buf)
+    rng = np.random.default_rng(4)
+    for it in range(4):
+        mv = rng.standard_normal(zc.size) + 1j * rng.standard_normal(zc.size)
+        m_buf.copy_(dev(mv))
+        F.evaluate(pg, m_buf, out)              # first call captures, later calls replay
+        ref = F.evaluate(pe, m_buf)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(out), host(ref))
+        _ = (m_buf * 2).sum().item()            # eager work between replays
+
+
+def test_batch_of_many_problems_matches_single_problems(F, orc):
+    zs, ms, kinds = W.batch(nprob=40, seed=5, nmin=1000, nmax=30000)
+    from paper_1311_1006_amd.driver import default_levels
+    Ls = [default_levels(len(z)) for z in zs]
+    off = np.concatenate([[0], np.cumsum([len(z) for z in zs])]).tolist()
+    tree = F.build_tree(dev(np.concatenate(zs)), Ls, offsets=off)
+    pl = F.plan(tree, 16, 0.5, "mixed", graph=True)
+    phi = host(F.evaluate(pl, dev(np.concatenate(ms))))
+    for b in (0, 7, 21, 39):
+        one = host(F.evaluate(F.plan(F.build_tree(dev(zs[b]), Ls[b]), 16, 0.5, "mixed"), dev(ms[b])))
+        np.testing.assert_array_equal(phi[off[b]:off[b + 1]], one)
+        sub = W.subsample(len(zs[b]), 2000, seed=b)
+        ref = orc.direct(zs[b], ms[b], sub)
+        assert e2(one[sub], ref) <= 1e-6
+
+
+def test_timestepping_with_tuner(F, orc):
+    # a smaller copy of the clustered, dynamically re-tuned workload
+    import torch
+    from paper_1311_1006_amd.driver import advect, make_tuner
+    z, m = W.clustered(100000, seed=0, nclusters=32)
+    tu = make_tuner(z.size, cap=0.1, window=2, knob_interval=3)
+    errs = {}
+
+    def check(step, zt, phi, prm, sec):
+        if step in (0, 7):
+            zh = host(zt)
+            sub = W.subsample(zh.size, 1000, seed=step)
+            errs[step] = e2(host(phi)[sub], orc.direct(zh, m, sub))
+
+    zf, hist = advect(dev(z), dev(m), 8, 1e-4, p=16, theta=0.5, precision="mixed", tuner=tu, callback=check)
+    assert errs[0] <= 1e-6 and errs[7] <= 1e-6
+    assert torch.isfinite(zf.real).all() and torch.isfinite(zf.imag).all()
+    assert len(hist) == 8 and all(s > 0 for _, s in hist)
