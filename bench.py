@@ -116,46 +116,53 @@ def main():
     out = torch.empty_like(md)
     stream = torch.cuda.current_stream()
 
-    def step(prec, L, timing=False):
+    def step(prec, cfg, timing=False):
+        L, split, batch = cfg
         tree = F.build_tree(zd, L)
-        pl = F.plan(tree, p, theta, prec, timing=timing)
+        pl = F.plan(tree, p, theta, prec, p2p_split=split, m2l_batch=batch, timing=timing)
         F.evaluate(pl, md, out)
         return tree, pl
 
-    # ---- N_levels by a timing sweep (per precision)
+    def time_steps(prec, cfg, k):
+        for _ in range(2):
+            step(prec, cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            step(prec, cfg)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    # ---- N_levels, then the P2P split and the M2L batch, by timing sweeps
     levels = [int(x) for x in args.levels.split(",") if 4 ** (int(x) - 1) <= n]
-    best_L = {}
+    best_cfg = {}
     for prec in ("mixed", "fp64"):
         best = None
         for L in levels:
-            for _ in range(2):
-                step(prec, L)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                step(prec, L)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / 3
+            dt = time_steps(prec, (L, 0, 0), 3)
             log("sweep %s L=%d: %.3f ms" % (prec, L, dt * 1e3))
             if best is None or dt < best[0]:
-                best = (dt, L)
-        best_L[prec] = best[1]
+                best = (dt, (L, 0, 0))
+        L = best[1][0]
+        for cfg in ((L, 2, 0), (L, 0, 32)):
+            dt = time_steps(prec, cfg, 3)
+            log("sweep %s L=%d split=%d batch=%d: %.3f ms" % (prec, cfg[0], cfg[1], cfg[2], dt * 1e3))
+            if dt < best[0]:
+                best = (dt, cfg)
+        best_cfg[prec] = best[1]
 
     # ---- timed region: K steps, mixed precision (the metric), then FP64
     res = {}
     for prec in ("mixed", "fp64"):
-        L = best_L[prec]
+        cfg = best_cfg[prec]
         for _ in range(args.warmup):
-            step(prec, L, timing=True)
+            step(prec, cfg)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p2p_us = []
         for _ in range(args.steps):
-            tree, pl = step(prec, L, timing=True)
-            p2p_us.append(pl.stats()["t_p2p_us"])
+            tree, pl = step(prec, cfg)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
-        st = pl.stats()
         # evaluate-only throughput on the last plan
         for _ in range(3):
             F.evaluate(pl, md, out)
@@ -166,9 +173,21 @@ def main():
         torch.cuda.synchronize()
         dte = (time.perf_counter() - t1) / args.steps
         phi = out.cpu().numpy()
-        res[prec] = dict(L=L, t=dt, t_eval=dte, stats=st, p2p_us=float(np.mean(p2p_us)), phi=phi)
-        log("%s: L=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, P2P %.1f us" %
-            (prec, L, dt * 1e3, n / dt / 1e6, dte * 1e3, res[prec]["p2p_us"]))
+        # per-phase device times (hipEvents on the evaluation stream) of the same plan shape
+        plt = F.plan(tree, p, theta, prec, p2p_split=cfg[1], m2l_batch=cfg[2], timing=True)
+        ph = {}
+        for r in range(args.steps + 1):
+            F.evaluate(plt, md, out)
+            st = plt.stats()
+            if r:
+                for k in ("t_upward_us", "t_m2l_us", "t_p2p_us", "t_downward_us", "t_total_us"):
+                    ph[k] = ph.get(k, 0.0) + st[k] / args.steps
+        st = plt.stats()
+        res[prec] = dict(L=cfg[0], split=cfg[1], batch=cfg[2], t=dt, t_eval=dte, stats=st, phases=ph,
+                         p2p_us=ph["t_p2p_us"], phi=phi)
+        log("%s: L=%d split=%d batch=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, phases %s" %
+            (prec, cfg[0], cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
+             " ".join("%s=%.1f" % (k[2:-3], v) for k, v in ph.items())))
 
     forms = None if args.no_forms else measure_forms(F, W, torch, dev, args.steps)
 
@@ -184,7 +203,7 @@ def main():
             err[prec] = oracle.rel_err2(res[prec]["phi"][sub], ref)
             log("%s e2 vs direct: %.3e" % (prec, err[prec]))
         # CPU oracle (serial FMM O2, its P2P loop OpenMP-parallel) on the full workload
-        L = best_L["fp64"]
+        L = best_cfg["fp64"][0]
         t0 = time.perf_counter()
         oracle.fmm(z, m, p, theta, L)
         tc = time.perf_counter() - t0
@@ -211,11 +230,11 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "uniform unit square N=1e6, complex N(0,1) strengths, seed 0",
-                   "n": n, "p": p, "theta": theta, "n_levels": mx["L"], "precision": "mixed",
-                   "step": "build_tree+plan+evaluate"},
+                   "n": n, "p": p, "theta": theta, "n_levels": mx["L"], "p2p_split": mx["split"],
+                   "m2l_batch": mx["batch"], "precision": "mixed", "step": "build_tree+plan+evaluate"},
         "fp64": {"value": n / fp["t"] / 1e6, "n_levels": fp["L"], "ms_per_step": fp["t"] * 1e3,
-                 "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64")},
-        "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed")},
+                 "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64"), "phases_us": fp["phases"]},
+        "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed"), "phases_us": mx["phases"]},
         "speedup_mixed_vs_fp64": fp["t"] / mx["t"],
         "roofline": {"bound": "alu", "kernel": "p2p (mixed)", "achieved": achieved, "peak": PEAK_FP32_VALU,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,

@@ -71,7 +71,8 @@ enum {
 typedef struct {
     int p2p_split;   /* P2P: lane subgroups per wavefront (1, 2, 4); each subgroup takes
                         its own targets and one source per lane */
-    int m2l_batch;   /* M2L: weak pairs scaled per LDS batch before the MFMA (8, 16, 32) */
+    int m2l_batch;   /* M2L: weak pairs per wavefront iteration, 16 (one 16-pair MFMA
+                        block) or 32 (two blocks, two pairs per lane) */
     int flags;       /* FMM_FLAG_* */
     int reserved;
 } fmm_tuning;

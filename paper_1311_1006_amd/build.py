@@ -33,8 +33,6 @@ def _compile(src):
         cmd += HIPFLAGS
     if os.path.basename(src) in EXACT_FILES:
         cmd += ["-ffp-contract=off"]
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 target feature: harmless
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

@@ -23,16 +23,18 @@
 //   source part  sum_i gb_i dphi_i/dz_k = m_k ( sum_i gb_i/(z_k - z_i)^2 + L2P'(lambda)(z_k) )
 //                (dP2M/dz_k: a_q += m_k q w^(q-1)/rs, contracted with lambda).
 #include <cfloat>
+#include <type_traits>
 
 #include "fmm_internal.h"
 #include "kernels_common.h"
+#include "p2p_common.h"
 #include "plan_extra.h"
 
 namespace fmm {
 
 template <class T>
-void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
-                const double*, int, void*, hipStream_t);
+void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
+                const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
@@ -59,12 +61,6 @@ __global__ void k_gather_adj(int64_t n, const int32_t* __restrict__ perm, const 
     if (gb32) gb32[i] = make_float2((float)v.x, (float)-v.y);
 }
 
-__device__ __forceinline__ void wave_sync_a()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Near field of the adjoint, per target k over its strong list:
 //   A_k = sum gb_j/(z_k - z_j),  B_k = sum gb_j/(z_k - z_j)^2,  C_k = sum m_j/(z_k - z_j)^2
@@ -85,9 +81,11 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
           const double2* __restrict__ mt, const double2* __restrict__ gb, double* __restrict__ out)
 {
     constexpr int NL = 64 / SUB;
-    constexpr int CAP = 128;
+    constexpr int CAP = sizeof(R) == 4 ? 256 : 128;
     constexpr int V = 8 * TG;
     __shared__ AdjSrc<R> sbuf[4][CAP];
+    __shared__ int2 smeta[4][64];
+    __shared__ int smark[4][CAP];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int item = blockIdx.x * 4 + w;
     if (item >= nitems) return;
@@ -108,28 +106,18 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
         for (int q = 0; q < 6; ++q) acc[t][q] = (R)0;
     }
     const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
+    auto load = [&](int j) {
+        const double x = X[j], y = Y[j];
+        AdjSrc<R> s;
+        s.x = (R)x; s.y = (R)y;
+        s.xl = (R)(x - (double)s.x); s.yl = (R)(y - (double)s.y);
+        const double2 mm = mt[j], gg = gb[j];
+        s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
+        return s;
+    };
     int e = 0, off = 0;
     while (e < ne) {
-        // stage up to CAP sources, entry by entry (an entry may be split)
-        int ns = 0;
-        while (e < ne && ns < CAP) {
-            const int S = s_ids[e0 + e];
-            const int st = bstart[S] + off, avail = bcount[S] - off;
-            const int take = min(avail, CAP - ns);
-            for (int f = lane; f < take; f += 64) {
-                int j = st + f;
-                double x = X[j], y = Y[j];
-                AdjSrc<R> s;
-                s.x = (R)x; s.y = (R)y;
-                s.xl = (R)(x - (double)s.x); s.yl = (R)(y - (double)s.y);
-                double2 mm = mt[j], gg = gb[j];
-                s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
-                lds[ns + f] = s;
-            }
-            ns += take;
-            if (take == avail) { ++e; off = 0; } else { off += take; }
-        }
-        wave_sync_a();
+        const int ns = stage_sources<CAP>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             AdjSrc<R> s = lds[f < ns ? f : 0];
@@ -161,7 +149,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
                 acc[t][5] += s.mr * w2i + s.mi * w2r;
             }
         }
-        wave_sync_a();
+        wave_sync();
     }
     R v[V];
 #pragma unroll
@@ -171,60 +159,72 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
         v[8 * t + 6] = (R)0;
         v[8 * t + 7] = (R)0;
     }
-    // transposing butterfly over the NL lanes of the subgroup
-    int nv = V, idx = 0;
+    // transposing butterfly over the NL lanes of the subgroup: afterwards this
+    // lane holds the totals of value indices base + i, i < NV
+    treduce<V, NL>(v, lane);
+    constexpr int NV = V >= NL ? V / NL : 1;
+    const int base0 = treduce_base<V, NL>(sl);
+    const bool writer = V >= NL || (sl & (NL / V - 1)) == 0;
+    if (writer) {
 #pragma unroll
-    for (int m = NL / 2; m >= 1; m >>= 1) {
-        if (nv > 1) {
-            const bool hi = (sl & m) != 0;
-            const int h = nv / 2;
-#pragma unroll
-            for (int i = 0; i < V / 2; ++i) {
-                if (i < h) {
-                    R keep = hi ? v[i + h] : v[i];
-                    R send = hi ? v[i] : v[i + h];
-                    v[i] = keep + __shfl_xor(send, m, 64);
-                }
-            }
-            nv = h;
-            if (hi) idx += h;
-        } else {
-            v[0] += __shfl_xor(v[0], m, 64);
+        for (int i = 0; i < NV; ++i) {
+            const int idx = base0 + i, t = idx >> 3, q = idx & 7;
+            const int k = g * TG + t;
+            if (q < 6 && k < it.tn) out[6 * (int64_t)(base + k) + q] = (double)v[i];
         }
     }
-    const bool writer = (sl & ((NL / V > 1) ? (NL / V - 1) : 0)) == 0;
-    const int t = idx >> 3, q = idx & 7;
-    const int k = g * TG + t;
-    if (writer && q < 6 && k < it.tn) out[6 * (int64_t)(base + k) + q] = (double)v[0];
 }
 
 // Final per-leaf combination: value and derivative of the local expansions
-// (forward b, adjoint lambda) at the points, plus the near-field sums.
-template <class T>
-__global__ void __launch_bounds__(64)
-k_adj_final(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
-            const double* __restrict__ geom, const double* __restrict__ X, const double* __restrict__ Y,
-            const T* __restrict__ loc, const T* __restrict__ lam, int p, const double* __restrict__ nadj,
-            const double2* __restrict__ mt, const double2* __restrict__ gb, const int32_t* __restrict__ perm,
-            double2* gm, double2* gz)
+// (forward b, adjoint lambda) at the points, plus the near-field sums.  G
+// lanes per leaf (256/G leaves per workgroup), both expansions of every leaf
+// in LDS (FP64).
+template <class T, int G, int P>
+__global__ void __launch_bounds__(256)
+k_adj_final(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
+            const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
+            const double* __restrict__ Y, const T* __restrict__ loc, const T* __restrict__ lam, int p,
+            const double* __restrict__ nadj, const double2* __restrict__ mt, const double2* __restrict__ gb,
+            const int32_t* __restrict__ perm, double2* gm, double2* gz)
 {
-    __shared__ double2 bl[kMaxP], ll[kMaxP];
-    const int g = leaves[blockIdx.x];
-    const int st = bstart[g], n = bcount[g];
-    const double cx = geom[4 * g], cy = geom[4 * g + 1], rs = geom[4 * g + 3], inv = 1.0 / rs;
-    if (threadIdx.x < p) {
-        const T* b = loc + 2 * ((int64_t)g * p + threadIdx.x);
-        const T* a = lam + 2 * ((int64_t)g * p + threadIdx.x);
-        bl[threadIdx.x] = make_double2((double)b[0], (double)b[1]);
-        ll[threadIdx.x] = make_double2((double)a[0], (double)a[1]);
+    using T2 = typename Vec2<T>::type;
+    constexpr int NLEAF = 256 / G;                 // leaves per workgroup
+    __shared__ double2 sbl[NLEAF][P], sll[NLEAF][P];
+    const int lane = threadIdx.x & 63;
+    const int slot = threadIdx.x / G;             // leaf slot in the workgroup
+    const int li = blockIdx.x * NLEAF + slot;
+    const int sl = lane % G;
+    const bool valid = li < nleaf;
+    int g = 0, st = 0, n = 0;
+    double cx = 0.0, cy = 0.0, inv = 0.0;
+    if (valid) {
+        g = leaves[li];
+        st = bstart[g];
+        n = bcount[g];
+        cx = geom[4 * (int64_t)g];
+        cy = geom[4 * (int64_t)g + 1];
+        inv = 1.0 / geom[4 * (int64_t)g + 3];
+        const T2* bsrc = reinterpret_cast<const T2*>(loc) + (int64_t)g * p;
+        const T2* lsrc = reinterpret_cast<const T2*>(lam) + (int64_t)g * p;
+        for (int k = sl; k < P; k += G) {
+            const T2 zero = {(T)0, (T)0};
+            const T2 b = k < p ? bsrc[k] : zero, a = k < p ? lsrc[k] : zero;
+            sbl[slot][k] = make_double2((double)b.x, (double)b.y);
+            sll[slot][k] = make_double2((double)a.x, (double)a.y);
+        }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < n; j += 64) {
+    const double2* bl = sbl[slot];
+    const double2* ll = sll[slot];
+    for (int j = sl; j < n; j += G) {
         const int i = st + j;
         const double2 v = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
         // Horner for value and derivative (in v) of both expansions
-        double2 bv = bl[p - 1], bd = make_double2(0, 0), lv = ll[p - 1], ld = make_double2(0, 0);
-        for (int l = p - 2; l >= 0; --l) {
+        double2 bv = bl[P - 1], bd = make_double2(0, 0), lv = ll[P - 1], ld = make_double2(0, 0);
+        // partly unrolled so that the coefficients are read from LDS at use
+        // (fully unrolled, they would all be hoisted into registers)
+#pragma unroll 2
+        for (int l = P - 2; l >= 0; --l) {
             bd = cmul(bd, v); bd.x += bv.x; bd.y += bv.y;
             bv = cmul(bv, v); bv.x += bl[l].x; bv.y += bl[l].y;
             ld = cmul(ld, v); ld.x += lv.x; ld.y += lv.y;
@@ -252,10 +252,12 @@ k_adj_final(const int32_t* __restrict__ leaves, const int32_t* __restrict__ bsta
 
 static void adj_shape(int nt, bool mixed, int* tg, int* sub)
 {
-    // V = 8 TG <= 64 / SUB
-    if (nt <= 4) { *sub = 4; *tg = 1; }
-    else if (nt <= 8) { *sub = 2; *tg = 4; }
-    else { *sub = 1; *tg = mixed ? 8 : 4; }
+    // four lane subgroups; up to 4 (FP32) or 2 (FP64) targets per lane
+    const int tgmax = mixed ? 4 : 2;
+    int t = 1;
+    while (t < tgmax && 4 * t < nt) t <<= 1;
+    *sub = 4;
+    *tg = t;
 }
 
 template <class R, int TG, int SUB>
@@ -290,7 +292,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     const int nleaf = (int)sc.nleaf;
     auto far = [&](auto tag) {
         using T = decltype(tag);
-        launch_p2m<T>(ex.leaves.p, nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, ngb.p, pl.p,
+        launch_p2m<T>(ex.leaves.p, nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p, ngb.p, pl.p,
                       pl.amp.p, s);
         for (int l = sc.max_levels - 2; l >= 1; --l) {
             int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
@@ -317,24 +319,37 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
         continue;                                                                                             \
     }
         if (mixed) {
-            ACASE(float, 1, 4) ACASE(float, 4, 2) ACASE(float, 8, 1)
+            ACASE(float, 1, 4) ACASE(float, 2, 4) ACASE(float, 4, 4)
         } else {
-            ACASE(double, 1, 4) ACASE(double, 4, 2) ACASE(double, 4, 1)
+            ACASE(double, 1, 4) ACASE(double, 2, 4)
         }
 #undef ACASE
         throw Error(FMM_EDEVICE, "unsupported adjoint P2P shape");
     }
-    // combination and scatter
-    if (mixed)
-        k_adj_final<float><<<nleaf, 64, 0, s>>>(ex.leaves.p, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p,
-                                                t.y.p, (const float*)pl.local.p, (const float*)pl.aloc.p, pl.p,
-                                                pl.near_d.p, (const double2*)pl.mtree.p, (const double2*)pl.gtree.p,
-                                                t.perm.p, (double2*)gm, (double2*)gz);
-    else
-        k_adj_final<double><<<nleaf, 64, 0, s>>>(ex.leaves.p, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p,
-                                                 t.y.p, (const double*)pl.local.p, (const double*)pl.aloc.p, pl.p,
-                                                 pl.near_d.p, (const double2*)pl.mtree.p, (const double2*)pl.gtree.p,
-                                                 t.perm.p, (double2*)gm, (double2*)gz);
+    // combination and scatter: G lanes per leaf, P terms held per lane
+    const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
+    const int P = pl.p <= 16 ? 16 : 32;
+    const unsigned gridf = (unsigned)((nleaf + 256 / G - 1) / (256 / G));
+    auto fin = [&](auto tag, auto gtag, auto ptag) {
+        using T = decltype(tag);
+        constexpr int G_ = decltype(gtag)::value, P_ = decltype(ptag)::value;
+        k_adj_final<T, G_, P_><<<gridf, 256, 0, s>>>(ex.leaves.p, nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p,
+                                                      t.x.p, t.y.p, (const T*)pl.local.p, (const T*)pl.aloc.p, pl.p,
+                                                      pl.near_d.p, (const double2*)pl.mtree.p,
+                                                      (const double2*)pl.gtree.p, t.perm.p, (double2*)gm,
+                                                      (double2*)gz);
+    };
+    auto fin_g = [&](auto tag, auto ptag) {
+        if (G == 16) fin(tag, std::integral_constant<int, 16>{}, ptag);
+        else if (G == 32) fin(tag, std::integral_constant<int, 32>{}, ptag);
+        else fin(tag, std::integral_constant<int, 64>{}, ptag);
+    };
+    auto fin_p = [&](auto tag) {
+        if (P == 16) fin_g(tag, std::integral_constant<int, 16>{});
+        else fin_g(tag, std::integral_constant<int, 32>{});
+    };
+    if (mixed) fin_p(float{});
+    else fin_p(double{});
     check_launch("adjoint final");
 }
 

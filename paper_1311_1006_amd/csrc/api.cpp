@@ -232,8 +232,8 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         if (tune) tn = *tune;
         FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4,
                     "p2p_split must be 0, 1, 2 or 4");
-        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 8 || tn.m2l_batch == 16 || tn.m2l_batch == 32,
-                    "m2l_batch must be 0, 8, 16 or 32");
+        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 16 || tn.m2l_batch == 32,
+                    "m2l_batch must be 0, 16 or 32");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         auto pp = std::make_unique<fmm_plan_s>();
@@ -356,6 +356,7 @@ int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st)
         FMM_REQUIRE(pl && st, "NULL argument");
         Plan& P = pl->pl;
         TreeSchedule& sc = *P.tree->sched;
+        list_totals_device(P, P.list_stream);
         std::memset(st, 0, sizeof(*st));
         st->n_points = sc.n;
         st->n_boxes = sc.nbox;
@@ -441,11 +442,13 @@ static void list_host(fmm_plan_t pl, int prob, int level, int kind, std::vector<
     ids.clear();
     ids.reserve(tot);
     const int32_t* di = kind ? P.w_ids.p : P.s_ids.p;
-    // the boxes of one level occupy one contiguous run of the pool
+    // the lists of one level's boxes lie in one run of the pool, in box order
+    // (packed, or at fixed per-box capacities)
     if (tot) {
-        int64_t first = beg[0];
-        std::vector<int32_t> run(tot);
-        FMM_HIP(hipMemcpyAsync(run.data(), di + first, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, s));
+        int64_t first = beg[0], last = 0;
+        for (int64_t b = 0; b < nb; ++b) last = std::max<int64_t>(last, (int64_t)beg[b] + cnt[b]);
+        std::vector<int32_t> run(last - first);
+        FMM_HIP(hipMemcpyAsync(run.data(), di + first, sizeof(int32_t) * (last - first), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
         for (int64_t b = 0; b < nb; ++b)
             for (int e = 0; e < cnt[b]; ++e) ids.push_back(run[beg[b] - first + e]);

@@ -20,15 +20,15 @@ namespace fmm {
 void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
                    const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
 template <class T>
-void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
-                const double*, int, void*, hipStream_t);
+void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
+                const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
-void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, const double*, const double*, const double*,
-                const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
+void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
+                const double*, const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
 template <class T>
 void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
                 int, const void*, void*, hipStream_t, int);
@@ -46,7 +46,7 @@ struct P2PItemH {
 static void p2p_shape(int nt, int knob, bool mixed, int* tg, int* sub)
 {
     int tgmax = mixed ? 16 : 8;
-    int s = knob > 0 ? knob : (nt <= 4 ? 4 : (nt <= 2 * tgmax ? 2 : 1));
+    int s = knob > 0 ? knob : 4;   // measured best for 15..61 targets per leaf, both precisions
     int need = (nt + s - 1) / s;
     int t = 1;
     while (t < need && t < tgmax) t <<= 1;
@@ -83,6 +83,7 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
                     ex.m2m_boxes[l].push_back(id);
                 } else {
                     leaves.push_back(id);
+                    ex.leaf_max = std::max(ex.leaf_max, (int)sc.box_count[id]);
                 }
             }
         }
@@ -160,7 +161,7 @@ static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipS
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, mt, pl.p,
+    launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p, mt, pl.p,
                   mp, s);
     for (int l = sc.max_levels - 2; l >= 1; --l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
@@ -240,10 +241,10 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     run_p2p(pl, ex, s);
     tm.mark();
     if (mixed)
-        launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+        launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
     else
-        launch_l2p<double>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p,
+        launch_l2p<double>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
                            pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
     tm.mark();
     if (tm.on) {

@@ -12,7 +12,7 @@
 // with rho = rs_C / rs_P and tau = (c_C - c_P) / rs_P (both exact re-centrings
 // of the truncated series).  All four operators compute in FP64; T is the
 // storage type of the coefficients (double for the FP64 path, float for the
-// mixed path).  One 64-lane workgroup (one wavefront) per box.
+// mixed path).
 #include "fmm_internal.h"
 #include "kernels_common.h"
 
@@ -45,58 +45,54 @@ __device__ __forceinline__ void wave_sync_e()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// P2M at the leaves.  One wavefront per leaf (four per workgroup); lane =
-// point; the terms m_j w_j^k go through LDS, 8 coefficients at a time, and
-// are summed over the points in point order.
-template <class T>
+// P2M at the leaves.  G lanes per leaf (64/G leaves per wavefront, four
+// wavefronts per workgroup): each lane takes the points j = lane, lane + G,
+// ... of its leaf and accumulates all P terms m_j w_j^k (w_j = (z_j - c)/rs)
+// in FP64 registers; a transposing butterfly then sums them over the G
+// lanes.  P = 16 or 32 bounds p.
+template <class T, int G, int P>
 __global__ void __launch_bounds__(256)
 k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
       const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp)
 {
-    __shared__ double2 buf_all[4][64][9];
-    const int wv = threadIdx.x >> 6;
-    const int li = blockIdx.x * 4 + wv;
-    if (li >= nleaf) return;
-    auto& buf = buf_all[wv];
-    const int g = leaves[li];
+    constexpr int V = 2 * P;
     const int lane = threadIdx.x & 63;
-    const int st = bstart[g], n = bcount[g];
-    const double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
-    double acc[kMaxP / 8];
+    const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
+    const int sl = lane % G;
+    const bool valid = li < nleaf;
+    int g = 0, st = 0, n = 0;
+    double cx = 0.0, cy = 0.0, inv = 0.0;
+    if (valid) {
+        g = leaves[li];
+        st = bstart[g];
+        n = bcount[g];
+        cx = geom[4 * (int64_t)g];
+        cy = geom[4 * (int64_t)g + 1];
+        inv = 1.0 / geom[4 * (int64_t)g + 3];
+    }
+    double v[V];
 #pragma unroll
-    for (int c = 0; c < kMaxP / 8; ++c) acc[c] = 0.0;
-    const int kk = lane >> 1, part = lane & 1;   // lanes 0..15: coefficient 8c + kk, component part
-    for (int j0 = 0; j0 < n; j0 += 64) {
-        const int j = j0 + lane;
-        double2 w = make_double2(0, 0), pw = make_double2(1, 0), mm = make_double2(0, 0);
-        if (j < n) {
-            w = make_double2((X[st + j] - cx) * inv, (Y[st + j] - cy) * inv);
-            mm = mt[st + j];
-        }
-        const int cnt = min(64, n - j0);
+    for (int i = 0; i < V; ++i) v[i] = 0.0;
+    for (int j = sl; j < n; j += G) {
+        const double2 w = make_double2((X[st + j] - cx) * inv, (Y[st + j] - cy) * inv);
+        double2 t = mt[st + j];
 #pragma unroll
-        for (int c = 0; c < kMaxP / 8; ++c) {
-            if (8 * c >= p) break;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                buf[lane][q] = cmul(mm, pw);
-                pw = cmul(pw, w);
-            }
-            wave_sync_e();
-            if (lane < 16) {
-                double s = 0.0;
-                for (int jj = 0; jj < cnt; ++jj) s += part ? buf[jj][kk].y : buf[jj][kk].x;
-                acc[c] += s;
-            }
-            wave_sync_e();
+        for (int k = 0; k < P; ++k) {
+            v[2 * k] += t.x;
+            v[2 * k + 1] += t.y;
+            if (k + 1 < P) t = cmul(t, w);
         }
     }
-    if (lane < 16) {
+    treduce<V, G>(v, lane);
+    const int base = treduce_base<V, G>(sl);
+    constexpr int NV = V >= G ? V / G : 1;
+    const bool writer = V >= G || (sl & (G / V - 1)) == 0;
+    if (valid && writer) {
 #pragma unroll
-        for (int c = 0; c < kMaxP / 8; ++c) {
-            const int k = 8 * c + kk;
-            if (k < p) mp[2 * ((int64_t)g * p + k) + part] = (T)acc[c];
+        for (int i = 0; i < NV; ++i) {
+            const int idx = base + i, k = idx >> 1;
+            if (k < p) mp[2 * ((int64_t)g * p + k) + (idx & 1)] = (T)v[i];
         }
     }
 }
@@ -201,37 +197,43 @@ k_l2l(const int32_t* __restrict__ parents, const int32_t* __restrict__ child0, c
     }
 }
 
-// L2P at the leaves, plus the near field, scattered to input order
-template <class T>
+// L2P at the leaves, plus the near field, scattered to input order.  G
+// lanes per leaf as in P2M; every lane holds the leaf's P coefficients (FP64)
+// and evaluates the series by Horner's rule at its points.
+template <class T, int G, int P>
 __global__ void __launch_bounds__(256)
 k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
-      const int32_t* __restrict__ bcount,
-      const double* __restrict__ geom, const double* __restrict__ X, const double* __restrict__ Y,
-      const T* __restrict__ loc, int p, const double2* __restrict__ nearf, const int32_t* __restrict__ perm,
-      double2* phi, double2* phi_near, double2* phi_far)
+      const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
+      const double* __restrict__ Y, const T* __restrict__ loc, int p, const double2* __restrict__ nearf,
+      const int32_t* __restrict__ perm, double2* phi, double2* phi_near, double2* phi_far)
 {
-    __shared__ double2 bl_all[4][kMaxP];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = blockIdx.x * 4 + wv;
+    using T2 = typename Vec2<T>::type;
+    const int lane = threadIdx.x & 63;
+    const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
+    const int sl = lane % G;
     if (li >= nleaf) return;
-    double2* bl = bl_all[wv];
-    int g = leaves[li];
-    int st = bstart[g], n = bcount[g];
-    double cx = geom[4 * g], cy = geom[4 * g + 1], inv = 1.0 / geom[4 * g + 3];
-    const T* b = loc + 2 * (int64_t)g * p;
-    if (lane < p) bl[lane] = make_double2((double)b[2 * lane], (double)b[2 * lane + 1]);
-    wave_sync_e();
-    for (int j = lane; j < n; j += 64) {
-        int i = st + j;
-        double2 w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
-        double2 acc = bl[p - 1];
-        for (int l = p - 2; l >= 0; --l) {
+    const int g = leaves[li];
+    const int st = bstart[g], n = bcount[g];
+    const double cx = geom[4 * (int64_t)g], cy = geom[4 * (int64_t)g + 1], inv = 1.0 / geom[4 * (int64_t)g + 3];
+    const T2* b = reinterpret_cast<const T2*>(loc) + (int64_t)g * p;
+    double2 bl[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        if (k < p) { const T2 v = b[k]; bl[k] = make_double2((double)v.x, (double)v.y); }
+        else bl[k] = make_double2(0.0, 0.0);
+    }
+    for (int j = sl; j < n; j += G) {
+        const int i = st + j;
+        const double2 w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
+        double2 acc = bl[P - 1];
+#pragma unroll
+        for (int l = P - 2; l >= 0; --l) {
             acc = cmul(acc, w);
             acc.x += bl[l].x;
             acc.y += bl[l].y;
         }
-        double2 nf = nearf[i];
-        int o = perm[i];
+        const double2 nf = nearf[i];
+        const int o = perm[i];
         if (phi) phi[o] = make_double2(acc.x + nf.x, acc.y + nf.y);
         if (phi_near) phi_near[o] = nf;
         if (phi_far) phi_far[o] = acc;
@@ -258,15 +260,27 @@ void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, 
     check_launch("gather");
 }
 
+// lanes per leaf: the smallest of 16, 32, 64 not below the largest leaf
+static int leaf_lanes(int leaf_max) { return leaf_max <= 16 ? 16 : (leaf_max <= 32 ? 32 : 64); }
+
 template <class T>
-void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount,
+void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
                 const double* geom, const double* X, const double* Y, const double* mt, int p, void* mp,
                 hipStream_t s)
 {
     if (nleaf == 0) return;
-    k_p2m<T><<<(nleaf + 3) / 4, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const double2*)mt, p,
-                                             (T*)mp);
-    check_launch("p2m");
+    const int G = leaf_lanes(leaf_max);
+    const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
+#define P2M_CASE(G_, P_)                                                                                   \
+    if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
+        k_p2m<T, G_, P_><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const double2*)mt, \
+                                              p, (T*)mp);                                                 \
+        check_launch("p2m");                                                                              \
+        return;                                                                                           \
+    }
+    P2M_CASE(16, 16) P2M_CASE(32, 16) P2M_CASE(64, 16) P2M_CASE(16, 32) P2M_CASE(32, 32) P2M_CASE(64, 32)
+#undef P2M_CASE
+    throw Error(FMM_EINVAL, "unsupported P2M configuration");
 }
 
 template <class T>
@@ -288,26 +302,35 @@ void launch_l2l(const int32_t* parents, int n, const int32_t* child0, const doub
 }
 
 template <class T>
-void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount,
+void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
                 const double* geom, const double* X, const double* Y, const void* loc, int p,
                 const double* nearf, const int32_t* perm, double* phi, double* phi_near, double* phi_far,
                 hipStream_t s)
 {
     if (nleaf == 0) return;
-    k_l2p<T><<<(nleaf + 3) / 4, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const T*)loc, p,
-                                             (const double2*)nearf,
-                                  perm, (double2*)phi, (double2*)phi_near, (double2*)phi_far);
-    check_launch("l2p");
+    const int G = leaf_lanes(leaf_max);
+    const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
+#define L2P_CASE(G_, P_)                                                                                   \
+    if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
+        k_l2p<T, G_, P_><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const T*)loc, p,  \
+                                              (const double2*)nearf, perm, (double2*)phi,                 \
+                                              (double2*)phi_near, (double2*)phi_far);                     \
+        check_launch("l2p");                                                                              \
+        return;                                                                                           \
+    }
+    L2P_CASE(16, 16) L2P_CASE(32, 16) L2P_CASE(64, 16) L2P_CASE(16, 32) L2P_CASE(32, 32) L2P_CASE(64, 32)
+#undef L2P_CASE
+    throw Error(FMM_EINVAL, "unsupported L2P configuration");
 }
 
 #define INST(T)                                                                                          \
-    template void launch_p2m<T>(const int32_t*, int, const int32_t*, const int32_t*, const double*,      \
+    template void launch_p2m<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
                                 const double*, const double*, const double*, int, void*, hipStream_t);   \
     template void launch_m2m<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
                                 void*, hipStream_t);                                                     \
     template void launch_l2l<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
                                 void*, hipStream_t);                                                     \
-    template void launch_l2p<T>(const int32_t*, int, const int32_t*, const int32_t*, const double*,      \
+    template void launch_l2p<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
                                 const double*, const double*, const void*, int, const double*,           \
                                 const int32_t*, double*, double*, double*, hipStream_t);
 INST(double)

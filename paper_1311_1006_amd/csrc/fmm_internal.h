@@ -180,11 +180,9 @@ struct Plan {
     DBuf<int32_t> s_beg, s_cnt, w_beg, w_cnt;
     DBuf<int32_t> s_ids, w_ids;    // global box ids
     int64_t n_strong = 0, n_weak = 0;
-    std::vector<int64_t> level_nstrong, level_nweak;   // per (prob, level) not kept; totals only
-    // work lists
-    DBuf<int32_t> m2l_targets;     // boxes with a nonempty weak list
-    int64_t n_m2l_targets = 0;
     int64_t n_p2p_pairs = 0;
+    bool totals_known = false;     // n_strong, n_weak, n_p2p_pairs summed
+    hipStream_t list_stream = nullptr;
     // evaluation buffers
     DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
     DBuf<float> src32;             // [N][4] xh yh mr mi (mixed path)
@@ -213,6 +211,7 @@ struct Plan {
 void build_tree_device(Tree& t, const double* z, hipStream_t s);
 void update_positions_device(Tree& t, const double* z, hipStream_t s);
 void build_lists_device(Plan& pl, hipStream_t s);
+void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s);
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,

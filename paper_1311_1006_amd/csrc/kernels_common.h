@@ -19,4 +19,56 @@ template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
+// Sum v[0..V) over the NL lanes of each aligned lane group (lanes that
+// differ in bits [0, log2 NL)), halving the values a lane keeps at every
+// step: afterwards lane l holds the totals of the value indices
+// treduce_base<V, NL>(l) + i, i < max(V / NL, 1).  When V < NL the last
+// steps are plain sums, and NL / V lanes (differing in their low bits) hold
+// the same total.
+
+// one step with lane mask M while NV values are live (compile-time indices)
+template <class T, int V, int NV, int M>
+struct TStep {
+    static __device__ __forceinline__ void run(T (&v)[V], int lane)
+    {
+        if (NV > 1) {
+            constexpr int H = NV > 1 ? NV / 2 : 1;
+            const bool hi = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const T keep = hi ? v[i + H] : v[i];
+                const T send = hi ? v[i] : v[i + H];
+                v[i] = keep + __shfl_xor(send, M, 64);
+            }
+        } else {
+            v[0] += __shfl_xor(v[0], M, 64);
+        }
+        TStep<T, V, (NV > 1 ? NV / 2 : 1), M / 2>::run(v, lane);
+    }
+};
+template <class T, int V, int NV>
+struct TStep<T, V, NV, 0> {
+    static __device__ __forceinline__ void run(T (&)[V], int) {}
+};
+
+template <int V, int NL, class T>
+__device__ __forceinline__ void treduce(T (&v)[V], int lane)
+{
+    TStep<T, V, V, NL / 2>::run(v, lane);
+}
+
+template <int V, int NL>
+__device__ __forceinline__ int treduce_base(int lane)
+{
+    int base = 0, nv = V;
+#pragma unroll
+    for (int m = NL / 2; m >= 1; m >>= 1) {
+        if (nv > 1) {
+            nv /= 2;
+            if (lane & m) base += nv;
+        }
+    }
+    return base;
+}
+
 }  // namespace fmm

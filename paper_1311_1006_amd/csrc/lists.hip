@@ -9,6 +9,7 @@
 // bounds-checked against the pool capacity; an overflow flag makes the host
 // grow the pools and run the build again.
 #include <algorithm>
+#include <climits>
 #include <utility>
 #include <vector>
 
@@ -213,6 +214,7 @@ struct TravCtx {
     const int32_t* boxes;     // global ids of the pass's boxes (levels l0..l1)
     int n;
     int l0;
+    int cs, cw;               // per-box list capacities of the one-pass build
     const int32_t* prob;
     const int8_t* level;
     const int64_t* pbox;
@@ -227,11 +229,16 @@ __device__ __forceinline__ void wave_sync_l()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool FILL>
+// MODE 0 counts, MODE 1 fills at the offsets of the scan, MODE 2 does both in
+// one pass with fixed per-box capacities: the strong list of box g starts at
+// g * cs and its weak list at g * cw (bit 0 of the overflow word when a list
+// does not fit; the compact build then runs instead).
+template <int MODE>
 __global__ void __launch_bounds__(256)
 k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
            int32_t* w_ids, int64_t cap_s, int64_t cap_w, long long* totals)
 {
+    constexpr bool FILL = MODE != 0;
     __shared__ int32_t front_all[4][2][kFrontCap];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + wv;
@@ -242,21 +249,26 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
     const int L = c.level[g];
     const int64_t pb = c.pbox[c.prob[g]];
     const int64_t jl = g - pb - level_base(L);        // index of the box within its level
-    bool overflow = false;
+    bool overflow = false, cap_overflow = false;
     int nf;
     if (c.l0 == 0) {
         nf = 1;
         if (lane == 0) fa[0] = (int32_t)pb;           // the root is strong with itself
     } else {
+        // the ancestor's strong list from the pool: only the entries that
+        // were written (at most cs in the one-pass mode, where a longer list
+        // is truncated and flagged)
         const int64_t a0 = pb + level_base(c.l0 - 1) + (jl >> (2 * (L - c.l0 + 1)));
         const int64_t ab = s_beg[a0];
         nf = s_cnt[a0];
+        if (MODE == 2 && nf > c.cs) { cap_overflow = true; nf = c.cs; }
         if (nf > kFrontCap) { overflow = true; nf = kFrontCap; }
         for (int e = lane; e < nf; e += 64) fa[e] = (ab + e < cap_s) ? s_ids[ab + e] : (int32_t)pb;
     }
     wave_sync_l();
-    int64_t sb = 0, wb = 0;
-    if (FILL) { sb = s_beg[g]; wb = w_beg[g]; }
+    int64_t sb = 0, wb = 0, lim_s = cap_s, lim_w = cap_w;
+    if (MODE == 1) { sb = s_beg[g]; wb = w_beg[g]; }
+    if (MODE == 2) { sb = g * c.cs; wb = g * c.cw; lim_s = sb + c.cs; lim_w = wb + c.cw; }
     int nw = 0;
     for (int k = (c.l0 == 0 ? 1 : c.l0); k <= L; ++k) {
         const int64_t anc = pb + level_base(k) + (jl >> (2 * (L - k)));
@@ -267,24 +279,30 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
         int nn = 0;
         for (int c0 = 0; c0 < ncand; c0 += 64) {
             const int idx = c0 + lane;
-            const bool valid = idx < ncand;
+            bool valid = idx < ncand;
             bool weak = false;
             int32_t cc = 0;
             if (valid) {
                 const int32_t q = fa[idx >> 2];
-                cc = (int32_t)(pb + lb + 4 * ((int64_t)q - pb - lbp) + (idx & 3));
-                weak = (cc != anc) && well_separated(ga, c.geom + 4 * (int64_t)cc, c.theta);
+                const int64_t qj = (int64_t)q - pb - lbp;   // index of q within level k-1
+                if (qj < 0 || qj >= (int64_t(1) << (2 * (k - 1)))) {
+                    valid = false;                          // not a box of that level: never
+                    overflow = true;                        // dereferenced, list rebuilt
+                } else {
+                    cc = (int32_t)(pb + lb + 4 * qj + (idx & 3));
+                    weak = (cc != anc) && well_separated(ga, c.geom + 4 * (int64_t)cc, c.theta);
+                }
             }
             const unsigned long long bs = __ballot(valid && !weak), bw = __ballot(valid && weak);
             const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
             if (valid && !weak) {
                 const int o = nn + __popcll(bs & below);
                 if (!last && o < kFrontCap) fb[o] = cc;
-                if (FILL && last && sb + o < cap_s) s_ids[sb + o] = cc;
+                if (FILL && last && sb + o < lim_s) s_ids[sb + o] = cc;
             }
             if (FILL && last && valid && weak) {
                 const int64_t o = wb + nw + __popcll(bw & below);
-                if (o < cap_w) w_ids[o] = cc;
+                if (o < lim_w) w_ids[o] = cc;
             }
             nn += __popcll(bs);
             if (last) nw += __popcll(bw);
@@ -294,14 +312,22 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
         int32_t* t = fa; fa = fb; fb = t;
         nf = nn;
     }
+    // flags raised by any lane
+    cap_overflow = __ballot(cap_overflow) != 0ull;
+    overflow = __ballot(overflow) != 0ull;
     if (lane == 0) {
         if (L == 0) {                                  // a root (only in a pass with l0 = 0)
-            if (!FILL) { s_cnt[g] = 1; w_cnt[g] = 0; }
-            else if (sb < cap_s) s_ids[sb] = (int32_t)g;
-        } else if (!FILL) {
-            s_cnt[g] = nf;
-            w_cnt[g] = nw;
+            nf = 1;
+            nw = 0;
+            if (FILL && sb < lim_s) s_ids[sb] = (int32_t)g;
         }
+        if (MODE != 1) { s_cnt[g] = nf; w_cnt[g] = nw; }
+        if (MODE == 2) {
+            s_beg[g] = (int32_t)sb;
+            w_beg[g] = (int32_t)wb;
+            if (nf > c.cs || nw > c.cw) cap_overflow = true;
+        }
+        if (cap_overflow) atomicOr((unsigned long long*)&totals[2], 1ull);
         if (overflow) atomicOr((unsigned long long*)&totals[2], 2ull);
     }
 }
@@ -340,16 +366,106 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
         const unsigned grid = (unsigned)((c.n + 3) / 4);
-        k_traverse<false><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+        k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
         const int nb = (c.n + 1023) / 1024;
         k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, totals, snap);
         k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, snap, pl.s_beg.p,
                                          pl.w_beg.p, totals, cap_s, cap_w);
-        k_traverse<true><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+        k_traverse<1><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                               pl.w_ids.p, cap_s, cap_w, totals);
         check_launch("traversal lists");
     }
+}
+
+// One pass per level range, lists written at fixed per-box capacities (per
+// tree layout: they start at kCapStrong / kCapWeak and grow to the longest
+// lists seen when a build overflowed them).
+constexpr int kCapStrong = 96, kCapWeak = 224;
+
+__global__ void __launch_bounds__(256)
+k_max_counts(int64_t n, const int32_t* s_cnt, const int32_t* w_cnt, unsigned int* out)
+{
+    const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+    int a = i < n ? s_cnt[i] : 0, b = i < n ? w_cnt[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { a = max(a, __shfl_xor(a, o, 64)); b = max(b, __shfl_xor(b, o, 64)); }
+    if ((threadIdx.x & 63) == 0) { atomicMax(&out[0], (unsigned)a); atomicMax(&out[1], (unsigned)b); }
+}
+
+static void grow_capacities(Plan& pl, hipStream_t s)
+{
+    TreeSchedule& sc = *pl.tree->sched;
+    DBuf<unsigned int> mx;
+    mx.alloc(2, s);
+    FMM_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(unsigned int), s));
+    k_max_counts<<<(unsigned)((sc.nbox + 255) / 256), 256, 0, s>>>(sc.nbox, pl.s_cnt.p, pl.w_cnt.p, mx.p);
+    check_launch("max list counts");
+    unsigned int h[2];
+    FMM_HIP(hipMemcpyAsync(h, mx.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    PlanExtra& ex = *pl.ex;
+    ex.cap_strong = std::max<int>(ex.cap_strong, (int)((h[0] + 31) / 32 * 32));
+    ex.cap_weak = std::max<int>(ex.cap_weak, (int)((h[1] + 31) / 32 * 32));
+}
+
+static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const int64_t* pbox)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    const PlanExtra& ex = *pl.ex;
+    k_totals_init<<<1, 64, 0, s>>>(totals);
+    for (auto [l0, l1] : traversal_passes(sc.max_levels)) {
+        TravCtx c;
+        c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
+        c.n = (int)(ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]);
+        if (c.n == 0) continue;
+        c.l0 = l0;
+        c.cs = ex.cap_strong;
+        c.cw = ex.cap_weak;
+        c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
+        c.geom = t.geom.p; c.theta = pl.theta;
+        k_traverse<2><<<(unsigned)((c.n + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p,
+                                                                pl.s_ids.p, pl.w_ids.p, (int64_t)pl.s_ids.n,
+                                                                (int64_t)pl.w_ids.n, totals);
+        check_launch("one-pass lists");
+    }
+}
+
+// list sizes of all boxes (totals[0], totals[1]) by block sums
+__global__ void __launch_bounds__(1024)
+k_sum_counts(int64_t n, const int32_t* s_cnt, const int32_t* w_cnt, long long* totals)
+{
+    __shared__ long long sh[2][16];
+    const int64_t i = blockIdx.x * (int64_t)1024 + threadIdx.x;
+    long long a = 0, b = 0;
+    if (i < n) { a = s_cnt[i]; b = w_cnt[i]; }
+    block_sum2(a, b, sh);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&totals[0], (unsigned long long)a);
+        atomicAdd((unsigned long long*)&totals[1], (unsigned long long)b);
+    }
+}
+
+void list_totals_device(Plan& pl, hipStream_t s)
+{
+    if (pl.totals_known) return;
+    TreeSchedule& sc = *pl.tree->sched;
+    DBuf<long long> totals;
+    totals.alloc(4, s);
+    k_totals_init<<<1, 64, 0, s>>>(totals.p);
+    k_sum_counts<<<(unsigned)((sc.nbox + 1023) / 1024), 1024, 0, s>>>(sc.nbox, pl.s_cnt.p, pl.w_cnt.p, totals.p);
+    const int nl = (int)sc.nleaf;
+    k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
+                                                 pl.s_ids.p, totals.p, (int64_t)pl.s_ids.n);
+    check_launch("list totals");
+    long long h[4];
+    FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    pl.n_strong = h[0];
+    pl.n_weak = h[1];
+    pl.n_p2p_pairs = h[3];
+    pl.totals_known = true;
 }
 
 void build_lists_device(Plan& pl, hipStream_t s)
@@ -363,9 +479,27 @@ void build_lists_device(Plan& pl, hipStream_t s)
     DBuf<long long> totals; totals.alloc(4, s);
     DBuf<long long> snap; snap.alloc(2, s);
     DBuf<long long> bsum; bsum.alloc(2 * ((nb + 1023) / 1024), s);
+    pl.list_stream = s;
+    PlanExtra& ex = *pl.ex;
+    if (ex.cap_strong == 0) { ex.cap_strong = kCapStrong; ex.cap_weak = kCapWeak; }
+    bool grow = false;
+    if (nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only) {
+        pl.s_ids.alloc(nb * ex.cap_strong, s);
+        pl.w_ids.alloc(nb * ex.cap_weak, s);
+        build_lists_direct(pl, s, totals.p, pbox.p);
+        long long flag = 0;
+        FMM_HIP(hipMemcpyAsync(&flag, totals.p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        if (flag == 0) {
+            pl.totals_known = false;    // list sizes and pair counts are summed on request
+            return;
+        }
+        grow = (flag & 2) == 0;         // capacities too small, no frontier overflow
+        if (flag & 2) ex.levelwise_only = true;
+    }
     int64_t cap_s = std::max<int64_t>(pl.n_strong, 24 * nb + 1024);
     int64_t cap_w = std::max<int64_t>(pl.n_weak, 64 * nb + 1024);
-    bool levelwise = false;
+    bool levelwise = ex.levelwise_only;
     for (int attempt = 0; attempt < 4; ++attempt) {
         pl.s_ids.alloc(cap_s, s);
         pl.w_ids.alloc(cap_w, s);
@@ -378,11 +512,19 @@ void build_lists_device(Plan& pl, hipStream_t s)
             long long h[4];
             FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
             FMM_HIP(hipStreamSynchronize(s));
-            if (h[2] & 2) { levelwise = true; continue; }   // a frontier overflowed
+            if (h[2] & 2) {                 // a frontier overflowed
+                levelwise = true;
+                ex.levelwise_only = true;
+                continue;
+            }
             pl.n_strong = h[0];
             pl.n_weak = h[1];
             pl.n_p2p_pairs = h[3];
-            if (!(h[2] & 1)) return;
+            pl.totals_known = true;
+            if (!(h[2] & 1)) {
+                if (grow) grow_capacities(pl, s);
+                return;
+            }
             cap_s = h[0] + h[0] / 4 + 1024;
             cap_w = h[1] + h[1] / 4 + 1024;
             continue;
@@ -421,6 +563,7 @@ void build_lists_device(Plan& pl, hipStream_t s)
         pl.n_strong = h[0];
         pl.n_weak = h[1];
         pl.n_p2p_pairs = h[3];
+        pl.totals_known = true;
         if (!h[2]) return;
         cap_s = h[0] + h[0] / 4 + 1024;
         cap_w = h[1] + h[1] / 4 + 1024;

@@ -3,22 +3,26 @@
 // For a weak pair (target T, source S) at one level, with d = c_T - c_S and
 // scaled coefficients (a_k of S, b_l of T, scaling radii rs_S, rs_T), the
 // shift of Sec. 2.1 for the harmonic kernel reads
-//     b_l += (1/d) (-rs_T/d)^l  sum_k C(k+l, k) (rs_S/d)^k a_k .
-// The matrix B_lk = C(k+l, k) is the same for every pair, so the work is the
-// batched product Y = B X with X's columns x^(q)_k = u_q^k a^(q)_k
-// (u_q = rs_S/d, one complex column per pair, stored as two real columns),
-// followed by the per-pair row scaling f^(q)_l = (1/d)(-rs_T/d)^l and the sum
-// over the pairs of the target.  Under the theta-criterion |u_S| + |u_T| <=
-// 2 theta/(1+theta), so every scaled term is at most 1 in magnitude.
+//     b_l += f_l  sum_k C(k+l, k) x_k,   x_k = u^k a_k,  f_l = (1/d) w^l,
+//     u = rs_S/d,  w = -rs_T/d.
+// The matrix B_lk = C(k+l, k) is the same for every pair, so the work is a
+// batched real product Y = B X over complex columns x (real and imaginary
+// parts as two MFMA products), followed by the per-pair row scaling by f and
+// the sum over the pairs of the target.  Under the theta-criterion
+// |u| + |w| <= 2 theta/(1+theta), so every scaled term is at most 1.
 //
-// One wavefront per target box.  Per batch of 32 pairs: lanes 0..31 form the
-// scaled source columns, lanes 32..63 the target factors (FP64 powers, cast
-// to the storage type), both into LDS; then per block of 8 pairs (16 real
-// columns) the wavefront issues 16x16x4 MFMAs with the B matrix held in
-// registers as the A operand, scales each output row by its pair's factor
-// and accumulates; a butterfly over the 8 pair slots finishes the target.
-// FP32 path: v_mfma_f32_16x16x4f32, FP32 accumulation.  FP64 path:
-// v_mfma_f64_16x16x4f64.  p <= 16 uses one 16-row block, p <= 32 two.
+// One wavefront per target box, blocks of 16 weak pairs (one or two blocks
+// per iteration).  Lane (kq, q),
+// kq = lane/16, q = lane%16, owns pair q of the block: it computes in FP64
+// exactly the powers it feeds to the MFMA (x_k for k = kq + 4i, the B
+// operand of k-step i) and the row factors of the output rows it holds,
+// casts them to the storage type, and accumulates f_l * Y_lq in registers.
+// No LDS and no barriers: the geometry and coefficients of the next block
+// are loaded while the current one is computed.  At the end the 16 pair
+// slots are summed by a butterfly.
+// FP32 path: v_mfma_f32_16x16x4f32 (output rows 4 kq + j), FP32 accumulation.
+// FP64 path: v_mfma_f64_16x16x4f64 (output rows kq + 4 j).
+// p <= 16 uses one 16-row block (PB = 1), p <= 32 two.
 #include "fmm_internal.h"
 #include "kernels_common.h"
 
@@ -35,7 +39,7 @@ template <> struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     // output element j of lane l sits in row 4*(l/16)+j, column l%16
-    static __device__ __forceinline__ int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+    static constexpr bool kRowsConsecutive = true;
 };
 template <> struct Mfma<double> {
     using acc = doublex4;
@@ -44,52 +48,108 @@ template <> struct Mfma<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     // output element j of lane l sits in row l/16 + 4*j, column l%16
-    static __device__ __forceinline__ int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+    static constexpr bool kRowsConsecutive = false;
 };
 
-__device__ __forceinline__ void wave_sync_m()
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
 
-__device__ __forceinline__ double2 cpow_m(double2 b, int e)
+// z^e for e in 0..3 from z and z^2 (e differs between lanes): one product of
+// two selected factors, so that no lane-indexed table is needed
+__device__ __forceinline__ double2 cpow_lane(double2 z, double2 z2, int e)
 {
-    double2 r = make_double2(1.0, 0.0);
-    while (e) {
-        if (e & 1) r = cmul(r, b);
-        b = cmul(b, b);
-        e >>= 1;
+    const double2 one = make_double2(1.0, 0.0);
+    return cmul(csel(e & 1, z, one), csel(e & 2, z2, one));
+}
+
+// The data of one block of pairs held by one lane: source centre and scaling
+// radius, and the coefficients a_k, k = kq + 4i, of its pair.
+template <class T, int KS>
+struct PairData {
+    double sx, sy, rs;
+    typename Vec2<T>::type a[KS];
+};
+
+// Loads that stay where they are written: relaxed atomic loads of wavefront
+// scope are plain loads for the hardware, but the compiler neither sinks them
+// to their first use nor reissues them, so a prefetch stays a prefetch.
+__device__ __forceinline__ double ld_pin(const double* p)
+{
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+}
+__device__ __forceinline__ int ld_pin(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ float2 ld_pin(const float2* p)
+{
+    const unsigned long long u =
+        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    return make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+}
+__device__ __forceinline__ double2 ld_pin(const double2* p)
+{
+    const double* d = reinterpret_cast<const double*>(p);
+    return make_double2(ld_pin(d), ld_pin(d + 1));
+}
+
+template <class T, int KS>
+__device__ __forceinline__ void load_pair(PairData<T, KS>& d, int S, int kq, int p, const double* __restrict__ geom,
+                                          const T* __restrict__ mp)
+{
+    const double* gs = geom + 4 * (int64_t)S;
+    d.sx = ld_pin(gs);
+    d.sy = ld_pin(gs + 1);
+    d.rs = ld_pin(gs + 3);
+    const typename Vec2<T>::type* a = reinterpret_cast<const typename Vec2<T>::type*>(mp) + (int64_t)S * p;
+    // every load in bounds (S is a box, k clamped to p - 1); the values of
+    // padding lanes and of k >= p are masked where they are used
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        const int k = kq + 4 * i;
+        d.a[i] = ld_pin(a + (k < p ? k : p - 1));
     }
-    return r;
 }
 
-// B pairs per batch; the 64 lanes are (pair q < B, role, chunk h < H) with
-// B * 2 * H = 64: each lane runs PP/H steps of its power recurrence.
-// Four independent wavefronts per workgroup, each with its own LDS tile.
-template <class T, int PB, int B>
+// complex product in the storage type: FP32 for the mixed path (the FP64
+// power rounded first), FP64 for the FP64 path
+__device__ __forceinline__ float2 scale_coef(double2 pw, float2 a)
+{
+    const float2 w = make_float2((float)pw.x, (float)pw.y);
+    return cmul(w, a);
+}
+__device__ __forceinline__ double2 scale_coef(double2 pw, double2 a) { return cmul(pw, a); }
+
+// 1/(dx^2 + dy^2) by v_rcp_f64 and two Newton steps
+__device__ __forceinline__ double rcp_nr(double r2)
+{
+    double y = __builtin_amdgcn_rcp(r2);
+    double e = fma(-r2, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-r2, y, 1.0);
+    return fma(y, e, y);
+}
+
+template <class T, int PB, int NB>
 __global__ void __launch_bounds__(256)
 k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w_beg,
       const int32_t* __restrict__ w_cnt, const int32_t* __restrict__ w_ids, const double* __restrict__ geom,
       const double* __restrict__ binom, int p, const T* __restrict__ mp, T* loc)
 {
-    using T2 = typename Vec2<T>::type;
     using M = Mfma<T>;
-    constexpr int PP = 16 * PB;      // padded number of terms
-    constexpr int KS = PP / 4;       // k-steps of 4
-    constexpr int H = 32 / B;        // k-chunks per (pair, role)
-    constexpr int PH = PP / H;       // terms per chunk
-    // tile[0] = scaled source columns x, tile[1] = target row factors f
-    __shared__ T2 tile_all[4][2][B][PP + 1];
+    using T2 = typename Vec2<T>::type;
+    constexpr int KS = 4 * PB;       // k-steps of 4 (K = 16 PB)
+    constexpr int STEP = 16 * NB;    // pairs per iteration
     const int w = threadIdx.x >> 6;
     const int bi = blockIdx.x * 4 + w;
     if (bi >= nbox) return;
-    auto& tile = tile_all[w];
     const int g = boxes[bi];
     const int lane = threadIdx.x & 63;
+    const int q = lane & 15, kq = lane >> 4;
     const int nw = w_cnt[g], wb = w_beg[g];
-    const int col = lane & 15, kq = lane >> 4, part = col & 1, slot = col >> 1;
 
     // A operands: B_{row,k} = C(k+row, k), row = 16 rb + lane%16, k = 4 ks + lane/16
     T amat[PB][KS];
@@ -97,124 +157,176 @@ k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w
     for (int rb = 0; rb < PB; ++rb)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            int row = 16 * rb + (lane & 15), k = 4 * ks + (lane >> 4);
+            const int row = 16 * rb + q, k = 4 * ks + kq;
             amat[rb][ks] = (row < p && k < p) ? (T)binom[(k + row) * kBinomStride + k] : (T)0;
         }
-    T oacc[PB][4];
+    T ore[PB][4], oim[PB][4];
 #pragma unroll
     for (int rb = 0; rb < PB; ++rb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) oacc[rb][j] = (T)0;
+        for (int j = 0; j < 4; ++j) { ore[rb][j] = (T)0; oim[rb][j] = (T)0; }
 
     const double ctx = geom[4 * (int64_t)g], cty = geom[4 * (int64_t)g + 1], rsT = geom[4 * (int64_t)g + 3];
-    // lane roles of phase 1
-    const int q = lane % B, role = (lane / B) & 1, h = lane / (2 * B);
-    const int k0 = h * PH;
-    for (int b0 = 0; b0 < nw; b0 += B) {
-        // ---- phase 1: x_k = (rs_S/d)^k a_k (role 0) or f_l = (1/d)(-rs_T/d)^l (role 1)
-        // for k in [k0, k0 + PH), FP64 powers, cast to the storage type
+    // first output row of this lane within a 16-row block; the rows it holds
+    // are r0 + j (FP32) or r0 + 4 j (FP64)
+    const int r0 = M::kRowsConsecutive ? 4 * kq : kq;
+
+    // software pipeline over blocks of STEP pairs, unrolled by two with two
+    // register buffers: while one buffer's pairs are computed, the other
+    // buffer's geometry and coefficients (next block) and the ids of the block
+    // after are in flight.  Every load is unconditional (indices clamped into
+    // the list, padding replaced by the target itself where the id is used).
+    const int last = nw > 0 ? nw - 1 : 0;
+    auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : g; };
+    auto compute = [&](const PairData<T, KS>& c, int b0, int nb) {
+        const bool valid = b0 + 16 * nb + q < nw;
+        // ---- FP64 powers of this lane's pair
+        const double dx = ctx - c.sx, dy = cty - c.sy;
+        const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
+        const double2 id = make_double2(dx * den, -dy * den);          // 1/d (0 for padding)
+        const double2 u = make_double2(c.rs * id.x, c.rs * id.y);      // rs_S / d
+        const double2 wv = make_double2(-rsT * id.x, -rsT * id.y);     // -rs_T / d
+        const double2 u2 = cmul(u, u), u4 = cmul(u2, u2);
+        const double2 w2 = cmul(wv, wv), w4 = cmul(w2, w2);
+        // B operands x_k, k = kq + 4 i
+        T2 xv[KS];
         {
-            const bool valid = b0 + q < nw;
-            const int S = valid ? w_ids[wb + b0 + q] : g;
-            const double* gs = geom + 4 * (int64_t)S;
-            const double dx = ctx - gs[0], dy = cty - gs[1];
-            const double den = valid ? 1.0 / (dx * dx + dy * dy) : 0.0;
-            const double2 id = make_double2(dx * den, -dy * den);     // 1/d (0 for padding)
-            const double rb_ = role ? -rsT : gs[3];
-            const double2 base = make_double2(rb_ * id.x, rb_ * id.y);
-            double2 pw = cpow_m(base, k0);
-            if (role) pw = cmul(pw, id);
-            const T2* a = reinterpret_cast<const T2*>(mp) + (int64_t)S * p;
-#pragma unroll 4
-            for (int j = 0; j < PH; ++j) {
-                const int k = k0 + j;
-                double2 t = pw;
-                if (role == 0) {
-                    T2 ak;
-                    if (k < p && valid) ak = a[k]; else { ak.x = (T)0; ak.y = (T)0; }
-                    t = cmul(pw, make_double2((double)ak.x, (double)ak.y));
-                }
-                T2 v;
-                v.x = (T)t.x; v.y = (T)t.y;
-                tile[role][q][k] = v;
-                pw = cmul(pw, base);
+            double2 pw = cpow_lane(u, u2, kq);
+#pragma unroll
+            for (int i = 0; i < KS; ++i) {
+                T2 a = c.a[i];
+                const bool use = valid && kq + 4 * i < p;
+                a.x = use ? a.x : (T)0;
+                a.y = use ? a.y : (T)0;
+                xv[i] = scale_coef(pw, a);
+                if (i + 1 < KS) pw = cmul(pw, u4);
             }
         }
-        wave_sync_m();
-        // ---- phase 2: MFMA per block of 8 pairs, row scaling, accumulation
-        const int nblk = min(B / 8, (nw - b0 + 7) / 8);
-        for (int nb = 0; nb < nblk; ++nb) {
-            const int qq = 8 * nb + slot;
+        // row factors f_l = (1/d) w^l of this lane's output rows
+        T fre[PB][4], fim[PB][4];
+        {
+            double2 base;                    // w^r0
+            if (M::kRowsConsecutive) base = cpow_lane(w4, cmul(w4, w4), kq);
+            else base = cpow_lane(wv, w2, kq);
+            const double2 step = M::kRowsConsecutive ? wv : w4;
+            double2 f0 = cmul(base, id);
 #pragma unroll
             for (int rb = 0; rb < PB; ++rb) {
-                typename M::acc acc = {0, 0, 0, 0};
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    T2 xv = tile[0][qq][4 * ks + kq];
-                    acc = M::step(amat[rb][ks], part ? xv.y : xv.x, acc);
+                double2 f = f0;
+                if (rb > 0) {                // row r0 + 16: times w^16
+                    const double2 w8 = cmul(w4, w4);
+                    f = cmul(f0, cmul(w8, w8));
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int row = 16 * rb + M::row(lane, j);
-                    T mine = acc[j];
-                    T other = __shfl_xor(mine, 1, 64);
-                    T re = part ? other : mine, im = part ? mine : other;
-                    T2 f = tile[1][qq][row];
-                    oacc[rb][j] += part ? (f.x * im + f.y * re) : (f.x * re - f.y * im);
+                    fre[rb][j] = (T)f.x;
+                    fim[rb][j] = (T)f.y;
+                    if (j < 3) f = cmul(f, step);
                 }
             }
         }
-        wave_sync_m();
+        // ---- MFMA: Y = B Re(X), B Im(X); scale rows by f and accumulate
+#pragma unroll
+        for (int rb = 0; rb < PB; ++rb) {
+            typename M::acc yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                yr = M::step(amat[rb][ks], xv[ks].x, yr);
+                yi = M::step(amat[rb][ks], xv[ks].y, yi);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ore[rb][j] += fre[rb][j] * yr[j] - fim[rb][j] * yi[j];
+                oim[rb][j] += fre[rb][j] * yi[j] + fim[rb][j] * yr[j];
+            }
+        }
+    };
+    PairData<T, KS> bufA[NB], bufB[NB];
+    int sidA[NB], sidB[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int e0 = 16 * nb + q;
+        const int s0 = raw_id(e0);
+        sidB[nb] = raw_id(STEP + e0);
+        load_pair<T, KS>(bufA[nb], e0 < nw ? s0 : g, kq, p, geom, mp);
     }
-    // ---- sum over the 8 pair slots (lanes differing in bits 1..3)
+    for (int b0 = 0; b0 < nw; b0 += 2 * STEP) {
+        // block b0 in bufA; load block b0 + STEP into bufB
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int e1 = b0 + STEP + 16 * nb + q;
+            sidA[nb] = raw_id(e1 + STEP);
+            load_pair<T, KS>(bufB[nb], e1 < nw ? sidB[nb] : g, kq, p, geom, mp);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) compute(bufA[nb], b0, nb);
+        if (b0 + STEP >= nw) break;
+        // block b0 + STEP in bufB; load block b0 + 2 STEP into bufA
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int e2 = b0 + 2 * STEP + 16 * nb + q;
+            sidB[nb] = raw_id(e2 + STEP);
+            load_pair<T, KS>(bufA[nb], e2 < nw ? sidA[nb] : g, kq, p, geom, mp);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) compute(bufB[nb], b0 + STEP, nb);
+    }
+    // ---- sum over the 16 pair slots (lanes differing in bits 0..3)
 #pragma unroll
     for (int rb = 0; rb < PB; ++rb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            T v = oacc[rb][j];
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
-            v += __shfl_xor(v, 8, 64);
-            oacc[rb][j] = v;
-        }
-    if (slot == 0) {
+            T a = ore[rb][j], b = oim[rb][j];
 #pragma unroll
-        for (int rb = 0; rb < PB; ++rb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * rb + M::row(lane, j);
-                if (row < p) loc[2 * ((int64_t)g * p + row) + part] = oacc[rb][j];
+            for (int o = 1; o < 16; o <<= 1) {
+                a += __shfl_xor(a, o, 64);
+                b += __shfl_xor(b, o, 64);
             }
+            ore[rb][j] = a;
+            oim[rb][j] = b;
+        }
+    // lane q = j (< 4) writes element j of its rows (zeros for a box without
+    // weak pairs, so every box's local expansion is written)
+    if (q < 4) {
+#pragma unroll
+        for (int rb = 0; rb < PB; ++rb) {
+            T vr = ore[rb][0], vi = oim[rb][0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j)
+                if (q == j) { vr = ore[rb][j]; vi = oim[rb][j]; }
+            const int row = 16 * rb + r0 + (M::kRowsConsecutive ? q : 4 * q);
+            if (row < p) {
+                T* dst = loc + 2 * ((int64_t)g * p + row);
+                dst[0] = vr;
+                dst[1] = vi;
+            }
+        }
     }
 }
 
-template <class T, int PB, int B>
+template <class T, int PB, int NB>
 static void m2l_one(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                     const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
 {
-    k_m2l<T, PB, B><<<(n + 3) / 4, 256, 0, s>>>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp,
-                                                (T*)loc);
+    k_m2l<T, PB, NB><<<(n + 3) / 4, 256, 0, s>>>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp,
+                                                 (T*)loc);
 }
 
-// batch: pairs per LDS batch (8, 16, 32; 0 = automatic).  FP64 tiles are
-// twice as large, so FP64 defaults to smaller batches.
+// batch: weak pairs per iteration of a wavefront, 16 (one MFMA block) or 32
+// (two blocks, two pairs per lane); 0 = automatic (16).
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                 const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s,
                 int batch)
 {
     if (n == 0) return;
-    const bool dbl = sizeof(T) == 8;
-    if (batch <= 0) batch = dbl ? 16 : 32;
-    if (batch > 32) batch = 32;
-    if (batch != 8 && batch != 16 && batch != 32) batch = 16;
-    if (p > 16 && batch == 32 && dbl) batch = 16;   // LDS per workgroup
-#define M2L_CASE(PB_, B_) \
-    if ((p <= 16 ? 1 : 2) == PB_ && batch == B_) { m2l_one<T, PB_, B_>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s); check_launch("m2l"); return; }
-    M2L_CASE(1, 8) M2L_CASE(1, 16) M2L_CASE(1, 32)
-    M2L_CASE(2, 8) M2L_CASE(2, 16) M2L_CASE(2, 32)
-#undef M2L_CASE
-    throw Error(FMM_EINVAL, "unsupported M2L configuration");
+    const int nb = batch == 32 ? 2 : 1;
+    if (p <= 16 && nb == 1) m2l_one<T, 1, 1>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
+    else if (p <= 16) m2l_one<T, 1, 2>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
+    else if (p <= 32 && nb == 1) m2l_one<T, 2, 1>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
+    else if (p <= 32) m2l_one<T, 2, 2>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
+    else throw Error(FMM_EINVAL, "unsupported M2L configuration");
+    check_launch("m2l");
 }
 
 template void launch_m2l<double>(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*,

@@ -22,6 +22,7 @@
 #include <cfloat>
 
 #include "fmm_internal.h"
+#include "p2p_common.h"
 
 namespace fmm {
 
@@ -31,12 +32,6 @@ struct P2PItem {
 
 constexpr int kP2PSrcCap = 256;    // sources staged in LDS per pass and wavefront
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 struct Src64 {
     double x, y, mr, mi;
@@ -116,81 +111,6 @@ __device__ __forceinline__ int butterfly_index(int lane)
     return idx;
 }
 
-// Gather sources of the strong list into LDS, resuming at (entry e, offset
-// off) and stopping after kP2PSrcCap sources (an entry may be split between
-// passes).  Entries are looked at 64 at a time; their (first source, prefix)
-// pairs go through a per-wave LDS table so that the copy loop needs no
-// shuffles.  Returns the number of sources staged.
-template <class SRC, class LOADER>
-__device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, const int32_t* __restrict__ s_ids,
-                                             const int32_t* __restrict__ bstart,
-                                             const int32_t* __restrict__ bcount, int e0, int e_end, int& e,
-                                             int& off, int lane, LOADER load)
-{
-    int staged = 0;
-    while (e < e_end && staged < kP2PSrcCap) {
-        const int k = e + lane;
-        int st = 0, avail = 0;
-        if (k < e_end) {
-            const int S = s_ids[e0 + k];
-            st = bstart[S];
-            avail = bcount[S];
-            if (lane == 0) { st += off; avail -= off; }
-        }
-        int x = avail;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        const int excl = x - avail;
-        const int total = __shfl(x, 63, 64);
-        const int take = min(total, kP2PSrcCap - staged);
-        meta[lane] = make_int2(excl, st);
-        wave_sync();
-        // positions f = lane + 64 r (take <= kP2PSrcCap = 4 * 64): find every
-        // position's source first, then issue all loads, then store
-        constexpr int R = kP2PSrcCap / 64;
-        int src_idx[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int f = lane + 64 * r;
-            int lo = 0, hi = 63;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (meta[mid].x <= f) lo = mid; else hi = mid - 1;
-            }
-            const int2 mj = meta[lo];
-            src_idx[r] = (f < take) ? mj.y + (f - mj.x) : -1;
-        }
-        SRC v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (src_idx[r] >= 0) v[r] = load(src_idx[r]);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (src_idx[r] >= 0) lds[staged + lane + 64 * r] = v[r];
-        // advance the cursor (uniform)
-        if (take == total) {
-            e = min(e + 64, e_end);
-            off = 0;
-        } else {
-            int lo = 0, hi = 63;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (meta[mid].x <= take - 1) lo = mid; else hi = mid - 1;
-            }
-            int consumed = take - meta[lo].x;
-            int avail_lo = (lo + 1 < 64 ? meta[lo + 1].x : total) - meta[lo].x;
-            if (consumed == avail_lo) { e = e + lo + 1; off = 0; }
-            else { off = (lo == 0 ? off : 0) + consumed; e = e + lo; }
-        }
-        staged += take;
-        wave_sync();
-    }
-    return staged;
-}
-
 template <int TG, int SUB>
 __global__ void __launch_bounds__(256)
 k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
@@ -200,6 +120,7 @@ k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     constexpr int NL = 64 / SUB;
     __shared__ Src64 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
+    __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int item = blockIdx.x * 4 + w;
     if (item >= nitems) return;
@@ -222,7 +143,7 @@ k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     };
     int e = 0, off = 0;
     while (e < ne) {
-        int ns = stage_sources(lds, smeta[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+        int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             Src64 s = lds[f < ns ? f : 0];
@@ -254,6 +175,7 @@ k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     constexpr int NL = 64 / SUB;
     __shared__ Src32 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
+    __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int item = blockIdx.x * 4 + w;
     if (item >= nitems) return;
@@ -279,7 +201,7 @@ k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     };
     int e = 0, off = 0;
     while (e < ne) {
-        int ns = stage_sources(lds, smeta[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+        int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             Src32 s = lds[f < ns ? f : 0];

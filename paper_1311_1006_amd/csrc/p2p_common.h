@@ -1,0 +1,107 @@
+// p2p_common.h -- staging of near-field sources into LDS, shared by the
+// forward and the adjoint near-field kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fmm {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Gather sources of the strong list into LDS, resuming at (entry e, offset
+// off) and stopping after CAP sources (an entry may be split between
+// passes).  Entries are looked at 64 at a time (lane k: entry e + k, its
+// first source and the exclusive prefix of the source counts).  Every entry
+// marks the staging position where its sources start; the entry of a
+// position is then the largest mark at or before it (a running maximum over
+// the positions, lane-strided: position f = lane + 64 r).  Returns the
+// number of sources staged.
+template <int CAP, class SRC, class LOADER>
+__device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, const int32_t* __restrict__ s_ids,
+                                             const int32_t* __restrict__ bstart,
+                                             const int32_t* __restrict__ bcount, int e0, int e_end, int& e,
+                                             int& off, int lane, LOADER load)
+{
+    constexpr int R = CAP / 64;
+    int staged = 0;
+    while (e < e_end && staged < CAP) {
+        const int k = e + lane;
+        int st = 0, avail = 0;
+        if (k < e_end) {
+            const int S = s_ids[e0 + k];
+            st = bstart[S];
+            avail = bcount[S];
+            if (lane == 0) { st += off; avail -= off; }
+        }
+        int x = avail;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int excl = x - avail;
+        const int total = __shfl(x, 63, 64);
+        const int cap = CAP - staged;
+        const int take = min(total, cap);
+        meta[lane] = make_int2(excl, st);
+#pragma unroll
+        for (int r = 0; r < R; ++r) mark[lane + 64 * r] = -1;
+        wave_sync();
+        if (avail > 0 && excl < take) atomicMax(&mark[excl], lane);
+        wave_sync();
+        // entry of every position: running maximum of the marks
+        int ent[R];
+        int carry = -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int v = mark[lane + 64 * r];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(v, o, 64);
+                if (lane >= o) v = max(v, y);
+            }
+            v = max(v, carry);
+            ent[r] = v;
+            carry = __shfl(v, 63, 64);
+        }
+        int src_idx[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int f = lane + 64 * r;
+            const int2 mj = meta[ent[r] < 0 ? 0 : ent[r]];
+            src_idx[r] = (f < take) ? mj.y + (f - mj.x) : -1;
+        }
+        SRC v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (src_idx[r] >= 0) v[r] = load(src_idx[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (src_idx[r] >= 0) lds[staged + lane + 64 * r] = v[r];
+        // advance the cursor (uniform): the entry of the last staged position
+        if (take == total) {
+            e = min(e + 64, e_end);
+            off = 0;
+        } else {
+            const int fl = take - 1;
+            int el = ent[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) el = (fl >> 6) == r ? ent[r] : el;
+            const int lo = __shfl(el, fl & 63, 64);
+            const int2 ml = meta[lo];
+            const int consumed = take - ml.x;
+            const int avail_lo = (lo + 1 < 64 ? meta[lo + 1].x : total) - ml.x;
+            if (consumed == avail_lo) { e = e + lo + 1; off = 0; }
+            else { off = (lo == 0 ? off : 0) + consumed; e = e + lo; }
+        }
+        staged += take;
+        wave_sync();
+    }
+    return staged;
+}
+
+}  // namespace fmm

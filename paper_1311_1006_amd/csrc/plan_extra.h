@@ -16,6 +16,9 @@ struct PlanExtra {
     std::vector<int64_t> level_boxes_off;
     DBuf<int32_t> d_level_boxes;                    // concatenated per level
     DBuf<int32_t> leaves;                           // global ids of all leaves
+    int leaf_max = 0;                               // largest leaf population
+    int cap_strong = 0, cap_weak = 0;               // per-box list capacities of the one-pass build
+    bool levelwise_only = false;                    // a frontier overflowed on this layout
     DBuf<double> binom;                             // binomial table C(n, k), n, k < 64
     std::vector<std::vector<int32_t>> m2m_boxes;   // non-leaf boxes per level
     std::vector<int64_t> m2m_off;

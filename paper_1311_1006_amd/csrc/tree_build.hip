@@ -1018,12 +1018,10 @@ __global__ void k_update_positions(const double* __restrict__ z, const int32_t* 
 
 static int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 65535 * 4); }
 
-void build_tree_device(Tree& t, const double* z, hipStream_t s)
+static void build_tree_select(Tree& t, const double* z, hipStream_t s)
 {
     TreeSchedule& sc = *t.sched;
     int64_t n = sc.n;
-    t.x.alloc(n, s); t.y.alloc(n, s); t.perm.alloc(n, s);
-    t.bbox.alloc(4 * sc.nbox, s); t.geom.alloc(4 * sc.nbox, s);
     // workspace
     DBuf<double> XA, YA, XB, YB;
     DBuf<int32_t> IA, IB;
@@ -1095,6 +1093,15 @@ void build_tree_device(Tree& t, const double* z, hipStream_t s)
     FMM_HIP(hipMemcpyAsync(&err, W + o_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     FMM_HIP(hipStreamSynchronize(s));
     if (err) throw Error(FMM_EINVAL, "non-finite position");
+}
+
+void build_tree_device(Tree& t, const double* z, hipStream_t s)
+{
+    TreeSchedule& sc = *t.sched;
+    const int64_t n = sc.n;
+    t.x.alloc(n, s); t.y.alloc(n, s); t.perm.alloc(n, s);
+    t.bbox.alloc(4 * sc.nbox, s); t.geom.alloc(4 * sc.nbox, s);
+    build_tree_select(t, z, s);
 }
 
 void update_positions_device(Tree& t, const double* z, hipStream_t s)
