@@ -41,10 +41,42 @@ def _time(fn, reps, torch):
     return (time.perf_counter() - t0) / reps
 
 
-def measure_forms(F, W, torch, dev, reps):
+def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4):
+    """Clustered N = 1e6 (90% in 32 Gaussian clusters, sigma = 1e-3, strengths
+    +-1): `steps` explicit Euler steps z += dt conj(phi)/(2 pi i), tree rebuilt
+    and the tuner consulted every step (mixed precision, p = 16, theta = 0.5).
+    Reports per-step device time and, every 10 steps, e2 against the FP64 direct
+    sum on a 10,000-target subsample (CPU oracle)."""
+    from paper_1311_1006_amd.driver import advect, make_tuner
+    z, m = W.clustered(1_000_000, seed=0)
+    tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6)
+    errs = {}
+
+    def check(step, zt, phi, prm, sec):
+        if with_errors and step % 10 == 0:
+            import oracle
+            zh = zt.cpu().numpy()
+            sub = W.subsample(zh.size, 10000, seed=step)
+            errs[step] = oracle.rel_err2(phi.cpu().numpy()[sub], oracle.direct(zh, m, sub))
+
+    md = torch.from_numpy(m).to(dev)
+    zf, hist = advect(torch.from_numpy(z).to(dev), md, steps + 1, dt, p=16, theta=0.5, precision="mixed",
+                      tuner=tu, callback=check)
+    times = [sec for _, sec in hist]
+    best = tu.best()[0]
+    res = {"timestep_clustered_n1e6": {"steps": steps + 1, "ms_per_step_mean": 1e3 * float(np.mean(times)),
+                                       "ms_per_step_median": 1e3 * float(np.median(times)),
+                                       "mpoints_s_median": 1e6 / float(np.median(times)) / 1e6,
+                                       "tuned": best, "e2_every_10_steps": errs or None}}
+    log("time stepping clustered N=1e6: median %.3f ms/step, tuned %s, e2 %s" %
+        (1e3 * float(np.median(times)), best, errs))
+    return res
+
+
+def measure_forms(F, W, torch, dev, reps, with_errors):
     """(2) 128 problems of uneven size in one graph launch vs 128 sequential
-    plain launches (same trees, levels, p, shapes); (3) adjoint / forward time
-    at N = 2e5, p = 16, mixed precision."""
+    plain launches (same trees, levels, p, shapes); clustered time stepping
+    with the tuner; (3) adjoint / forward time at N = 2e5, p = 16."""
     from paper_1311_1006_amd.driver import default_levels
     out = {}
     zs, ms, kinds = W.batch(nprob=128, seed=0)
@@ -69,6 +101,7 @@ def measure_forms(F, W, torch, dev, reps):
                                    "speedup": ts / tb, "mpoints_s": off[-1] / tb / 1e6}
         log("batch of 128 (%s): graph %.3f ms, 128 sequential launches %.3f ms" % (prec, tb * 1e3, ts * 1e3))
         del singles, pg, tree
+    out.update(measure_timestepping(F, W, torch, dev, with_errors))
     z, m, _ = W.uniform(200000, seed=0)
     zd = torch.from_numpy(z).to(dev)
     md = torch.from_numpy(m).to(dev)
@@ -189,7 +222,7 @@ def main():
             (prec, cfg[0], cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
              " ".join("%s=%.1f" % (k[2:-3], v) for k, v in ph.items())))
 
-    forms = None if args.no_forms else measure_forms(F, W, torch, dev, args.steps)
+    forms = None if args.no_forms else measure_forms(F, W, torch, dev, args.steps, not args.no_cpu)
 
     # ---- accuracy vs the FP64 direct sum (CPU oracle) on the subsample
     err = {}

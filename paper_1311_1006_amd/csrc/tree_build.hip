@@ -829,9 +829,14 @@ struct LdsSplit {
     uint8_t sax[kLdsCap / 2];
     uint16_t pst[kLdsCap / 2];
 };
+struct LdsBucket {
+    uint32_t cnt[kLdsCap];      // bucket populations, then bucket ends
+    uint64_t key[kLdsCap];      // order keys in bucket order
+};
 union LdsUnion {
     LdsSort s;
     LdsSplit p;
+    LdsBucket b;
 };
 
 __device__ void lds_sort(LdsSort& S, const uint32_t* idxs, int n)
@@ -859,6 +864,121 @@ __device__ void lds_sort(LdsSort& S, const uint32_t* idxs, int n)
         }
 }
 
+// Local ids 0..n-1 of the segment ordered by (coordinate, input index) into
+// out.  Bucket sort: kLdsCap equal-width buckets between the segment's
+// minimum and maximum coordinate (a monotone map), an exclusive scan of the
+// populations, a scatter, and an insertion sort inside every bucket.  When a
+// bucket holds more than kBucketMax points (ties, tight clusters) the
+// bitonic sort runs instead.
+constexpr int kBucketMax = 16;
+
+__device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint32_t* idxs, int n, uint16_t* out,
+                          int* sh, double* red)
+{
+    constexpr int NB = kLdsCap;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // range of the coordinate
+    double lo = 1e308, hi = -1e308;
+    double cv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = tid + u * kLdsThreads;
+        cv[u] = i < n ? c[i] : 0.0;
+        if (i < n) { lo = fmin(lo, cv[u]); hi = fmax(hi, cv[u]); }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) { red[wid] = lo; red[16 + wid] = hi; }
+    for (int b = tid; b < NB; b += kLdsThreads) U.b.cnt[b] = 0;
+    __syncthreads();
+    lo = red[0]; hi = red[16];
+    for (int w = 1; w < kLdsThreads / 64; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[16 + w]); }
+    const double ext = hi - lo;
+    double scale = ext > 0.0 ? (double)NB / ext : 0.0;
+    scale = scale < 1e300 ? scale : 0.0;
+    int bk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = tid + u * kLdsThreads;
+        bk[u] = (int)fmin(fmax((cv[u] - lo) * scale, 0.0), (double)(NB - 1));
+        if (i < n) atomicAdd(&U.b.cnt[bk[u]], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the populations (thread t owns buckets 4t..4t+3) and
+    // the largest population
+    uint32_t q[4];
+    int loc = 0, mx = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        q[v] = U.b.cnt[4 * tid + v];
+        loc += (int)q[v];
+        mx = max(mx, (int)q[v]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    int tot;
+    int run = block_excl_scan<kLdsThreads>(loc, sh, &tot);
+    if (lane == 0) sh[16 + wid] = mx;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        U.b.cnt[4 * tid + v] = (uint32_t)run;
+        run += (int)q[v];
+    }
+    __syncthreads();
+    mx = 0;
+    for (int w = 0; w < kLdsThreads / 64; ++w) mx = max(mx, sh[16 + w]);
+    __syncthreads();
+    if (mx > kBucketMax) {
+        // bitonic fallback (uniform branch)
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int i = tid; i < P; i += kLdsThreads) {
+            if (i < n) { U.s.key[i] = okey(c[i]); U.s.id[i] = (uint16_t)i; }
+            else { U.s.key[i] = ~0ull; U.s.id[i] = 0xffff; }
+        }
+        __syncthreads();
+        lds_sort(U.s, idxs, n);
+        for (int i = tid; i < n; i += kLdsThreads) out[i] = U.s.id[i];
+        __syncthreads();
+        return;
+    }
+    // scatter into bucket order; cnt becomes the end of every bucket
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = tid + u * kLdsThreads;
+        if (i < n) {
+            const uint32_t pos = atomicAdd(&U.b.cnt[bk[u]], 1u);
+            U.b.key[pos] = okey(cv[u]);
+            out[pos] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    // insertion sort inside every bucket by (key, input index)
+    for (int b = tid; b < NB; b += kLdsThreads) {
+        const int e = (int)U.b.cnt[b], s0 = b == 0 ? 0 : (int)U.b.cnt[b - 1];
+        for (int a = s0 + 1; a < e; ++a) {
+            const uint64_t ka = U.b.key[a];
+            const uint16_t ia = out[a];
+            const uint32_t xa = idxs[ia];
+            int j = a - 1;
+            while (j >= s0) {
+                const uint64_t kj = U.b.key[j];
+                const uint16_t ij = out[j];
+                if (kj < ka || (kj == ka && idxs[ij] < xa)) break;
+                U.b.key[j + 1] = kj;
+                out[j + 1] = ij;
+                --j;
+            }
+            U.b.key[j + 1] = ka;
+            out[j + 1] = ia;
+        }
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(kLdsThreads)
 k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA, const int32_t* IA,
             const double* XB, const double* YB, const int32_t* IB, double* Xo, double* Yo, int32_t* Io,
@@ -867,31 +987,18 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
     __shared__ LdsUnion U;
     __shared__ uint32_t idxs[kLdsCap];
     __shared__ uint16_t LX[kLdsCap], LY[kLdsCap];
-    __shared__ int sh[kLdsThreads / 64];
+    __shared__ int sh[2 * (kLdsThreads / 64)];
+    __shared__ double red[2 * (kLdsThreads / 64)];
     LdsWork w = work[blockIdx.x];
     const double* xs = (w.stage0 & 1) ? XB : XA;
     const double* ys = (w.stage0 & 1) ? YB : YA;
     const int32_t* is = (w.stage0 & 1) ? IB : IA;
     xs += w.start; ys += w.start; is += w.start;
     int n = w.count;
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += kLdsThreads) {
-        if (i < n) { idxs[i] = (uint32_t)is[i]; U.s.key[i] = okey(xs[i]); U.s.id[i] = (uint16_t)i; }
-        else { U.s.key[i] = ~0ull; U.s.id[i] = 0xffff; }
-    }
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) idxs[i] = (uint32_t)is[i];
     __syncthreads();
-    lds_sort(U.s, idxs, n);
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) LX[i] = U.s.id[i];
-    __syncthreads();
-    for (int i = threadIdx.x; i < P; i += kLdsThreads) {
-        if (i < n) { U.s.key[i] = okey(ys[i]); U.s.id[i] = (uint16_t)i; }
-        else { U.s.key[i] = ~0ull; U.s.id[i] = 0xffff; }
-    }
-    __syncthreads();
-    lds_sort(U.s, idxs, n);
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) LY[i] = U.s.id[i];
-    __syncthreads();
+    lds_order(U, xs, idxs, n, LX, sh, red);
+    lds_order(U, ys, idxs, n, LY, sh, red);
     LdsSplit& S = U.p;
     if (threadIdx.x == 0) { S.sst[0][0] = 0; S.sst[0][1] = (uint16_t)n; }
     for (int i = threadIdx.x; i < n; i += kLdsThreads) S.segid[i] = 0;
