@@ -23,6 +23,7 @@
 //   source part  sum_i gb_i dphi_i/dz_k = m_k ( sum_i gb_i/(z_k - z_i)^2 + L2P'(lambda)(z_k) )
 //                (dP2M/dz_k: a_q += m_k q w^(q-1)/rs, contracted with lambda).
 #include <cfloat>
+#include <climits>
 #include <type_traits>
 
 #include "fmm_internal.h"
@@ -40,8 +41,9 @@ void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double
 template <class T>
 void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
-void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
-                int, const void*, void*, hipStream_t, int);
+void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
+                const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
+                hipStream_t, int);
 void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
                    const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
 
@@ -75,7 +77,9 @@ struct AdjSrc {
 
 template <class R, int TG, int SUB>
 __global__ void __launch_bounds__(256)
-k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
+          const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+          double* __restrict__ partial, const int32_t* __restrict__ bstart,
           const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
           const int32_t* __restrict__ s_ids, const double* __restrict__ X, const double* __restrict__ Y,
           const double2* __restrict__ mt, const double2* __restrict__ gb, double* __restrict__ out)
@@ -87,9 +91,14 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][CAP];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + w;
-    if (item >= nitems) return;
-    const P2PItemA it = items[item];
+    const int xi = blockIdx.x * 4 + w;
+    if (xi >= nx) return;
+    // (item, source chunk); without chunk lists every item is one chunk
+    const int2 xe = xitems ? xitems[xi] : make_int2(item_base + xi, 0);
+    const P2PItemA it = items[xe.x];
+    const int nch = icnt ? icnt[xe.x] : 1;
+    const int s_first = xe.y * kChunkSrc;
+    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     AdjSrc<R>* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -116,8 +125,11 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
         return s;
     };
     int e = 0, off = 0;
-    while (e < ne) {
-        const int ns = stage_sources<CAP>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
+    for (int done = 0; done < s_len && e < ne;) {
+        const int ns = stage_sources<CAP>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load,
+                                          s_len - done);
+        done += ns;
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             AdjSrc<R> s = lds[f < ns ? f : 0];
@@ -170,7 +182,10 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int nitems, const int32_t* __restr
         for (int i = 0; i < NV; ++i) {
             const int idx = base0 + i, t = idx >> 3, q = idx & 7;
             const int k = g * TG + t;
-            if (q < 6 && k < it.tn) out[6 * (int64_t)(base + k) + q] = (double)v[i];
+            if (q < 6 && k < it.tn) {
+                if (nch == 1) out[6 * (int64_t)(base + k) + q] = (double)v[i];
+                else partial[((int64_t)(ioff[xe.x] + xe.y) * kItemTargets + k) * 6 + q] = (double)v[i];
+            }
         }
     }
 }
@@ -261,13 +276,22 @@ static void adj_shape(int nt, bool mixed, int* tg, int* sub)
 }
 
 template <class R, int TG, int SUB>
-static void launch_adj_one(const P2PItemA* items, int n, const int32_t* bstart, const int32_t* bcount,
-                           const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const double* X,
-                           const double* Y, const double* mt, const double* gb, double* out, hipStream_t s)
+static void launch_adj_one(const P2PItemA* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
+                           const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                           const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
+                           const double* X, const double* Y, const double* mt, const double* gb, double* out,
+                           hipStream_t s)
 {
-    k_p2p_adj<R, TG, SUB><<<(n + 3) / 4, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, X, Y,
-                                                      (const double2*)mt, (const double2*)gb, out);
+    k_p2p_adj<R, TG, SUB><<<(nx + 3) / 4, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial,
+                                                       bstart, bcount, s_beg, s_cnt, s_ids, X, Y,
+                                                       (const double2*)mt, (const double2*)gb, out);
 }
+
+void balance_launch(Plan::Balance& b, const void* items, int n, const std::vector<P2PClass>& cls,
+                    const int32_t* nsrc, hipStream_t s);
+void balance_finish(Plan::Balance& b, int n, int vals, hipStream_t s);
+void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
+                    hipStream_t s);
 
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz, hipStream_t s)
 {
@@ -298,23 +322,43 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
             int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
             launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p, s);
         }
-        launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p,
-                      pl.amp.p, pl.aloc.p, s, pl.tune.m2l_batch);
+        const Plan::Balance& bm = pl.bal_m2l;
+        launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, bm.xitems.p, (int)bm.total, bm.icnt.p, bm.ioff.p, bm.partial.p,
+                      bm.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p,
+                      pl.aloc.p, s, pl.tune.m2l_batch);
         for (int l = 1; l + 1 < sc.max_levels; ++l) {
             int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
             launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.aloc.p, s);
         }
     };
     if (mixed) far(float()); else far(double());
-    // near field of the adjoint
+    // near field of the adjoint, in source chunks when some strong list is
+    // long (the chunk lists of the adjoint items are made once per plan)
     const P2PItemA* items = (const P2PItemA*)ex.adj_items.p;
-    for (auto& c : ex.adj_class) {
-        const P2PItemA* it = items + c.off;
-        int nn = (int)c.n;
+    int nadj = 0;
+    for (auto& c : ex.adj_class) nadj = std::max<int>(nadj, (int)(c.off + c.n));
+    Plan::Balance& ba = pl.bal_adj;
+    if (ba.cls.empty()) {
+        if (pl.split_p2p) {
+            balance_launch(ba, items, nadj, ex.adj_class, pl.nsrc.p, s);
+            FMM_HIP(hipStreamSynchronize(s));
+            balance_finish(ba, nadj, 6, s);
+        } else {
+            for (auto& c : ex.adj_class) ba.cls.push_back(c.off);
+            ba.cls.push_back(nadj);
+            ba.total = nadj;
+        }
+    }
+    for (size_t ci = 0; ci < ex.adj_class.size(); ++ci) {
+        const P2PClass& c = ex.adj_class[ci];
+        const int64_t x0 = ba.cls[ci], x1 = ba.cls[ci + 1];
+        const int2* xit = ba.xitems.p ? ba.xitems.p + x0 : nullptr;
+        const int nx = (int)(x1 - x0);
 #define ACASE(R_, TG_, SUB_)                                                                                  \
     if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
-        launch_adj_one<R_, TG_, SUB_>(it, nn, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,     \
-                                      pl.s_ids.p, t.x.p, t.y.p, pl.mtree.p, pl.gtree.p, pl.near_d.p, s);      \
+        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, pl.nsrc.p, ba.partial.p,  \
+                                      sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,  \
+                                      t.x.p, t.y.p, pl.mtree.p, pl.gtree.p, pl.near_d.p, s);                  \
         check_launch("p2p adjoint");                                                                          \
         continue;                                                                                             \
     }
@@ -326,6 +370,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
 #undef ACASE
         throw Error(FMM_EDEVICE, "unsupported adjoint P2P shape");
     }
+    combine_chunks(ba, items, nadj, sc.d_box_start.p, pl.near_d.p, s);
     // combination and scatter: G lanes per leaf, P terms held per lane
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
     const int P = pl.p <= 16 ? 16 : 32;

@@ -259,6 +259,7 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
             pl.ex = pl.ex_ref.get();
         }
         build_lists_device(pl, s);
+        plan_balance(pl, s);
         alloc_eval_buffers(pl, s);
         *out = pp.release();
     });

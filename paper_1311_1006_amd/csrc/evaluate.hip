@@ -30,11 +30,14 @@ template <class T>
 void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
                 const double*, const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
 template <class T>
-void launch_m2l(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, const double*, const double*,
-                int, const void*, void*, hipStream_t, int);
-void launch_p2p(bool mixed, int tg, int sub, const void* items, int n, const int32_t* bstart, const int32_t* bcount,
-                const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src, const void* lo,
-                double* out, hipStream_t s);
+void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
+                const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
+                hipStream_t, int);
+void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
+                const int32_t* icnt,
+                const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
+                const void* src, const void* lo, double* out, hipStream_t s);
 
 struct P2PItemH {
     int32_t leaf, t0, tn, pad;
@@ -174,8 +177,10 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp,
-                  loc, s, pl.tune.m2l_batch);
+    const Plan::Balance& b = pl.bal_m2l;
+    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
+                  b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
+                  pl.tune.m2l_batch);
     // parents at level l (non-leaf) hand their expansion to level l+1
     for (int l = 1; l + 1 < sc.max_levels; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
@@ -183,17 +188,27 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     }
 }
 
+void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
+                    hipStream_t s);
+
 static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     bool mixed = pl.precision == FMM_MIXED;
-    for (auto& c : ex.p2p_class) {
-        const char* items = (const char*)ex.p2p_items.p + c.off * sizeof(P2PItemH);
-        launch_p2p(mixed, c.tg, c.sub, items, (int)c.n, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
-                   pl.s_ids.p, mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
+    const Plan::Balance& b = pl.bal;
+    int nitems = 0;
+    for (size_t c = 0; c < ex.p2p_class.size(); ++c) {
+        const P2PClass& k = ex.p2p_class[c];
+        nitems = std::max<int>(nitems, (int)(k.off + k.n));
+        const int64_t x0 = b.cls[c], x1 = b.cls[c + 1];
+        launch_p2p(mixed, k.tg, k.sub, ex.p2p_items.p, (int)x0, b.xitems.p ? b.xitems.p + x0 : nullptr,
+                   (int)(x1 - x0), b.icnt.p, b.ioff.p,
+                   pl.nsrc.p, b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
+                   mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
                    mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s);
     }
+    combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }
 
 struct PhaseTimer {

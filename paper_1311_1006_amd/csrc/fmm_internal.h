@@ -48,6 +48,9 @@ constexpr int kTileThreads = 256;
 constexpr int kBuckets = 2048;     // histogram buckets per level of bucket selection
 constexpr int kCandCap = 2048;     // candidates sorted in LDS by one workgroup
 constexpr int kLdsCap = 4096;      // segments at most this large finish in one workgroup
+constexpr int kChunkSrc = 2048;    // near-field sources per work chunk (longer lists are split)
+constexpr int kItemTargets = 32;   // targets per near-field work item, at most
+constexpr int kChunkPairs = 128;   // M2L weak pairs per work chunk (longer lists are split)
 
 __host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
 __host__ __device__ inline int64_t nbox_levels(int L) { return level_base(L); }
@@ -183,12 +186,28 @@ struct Plan {
     int64_t n_p2p_pairs = 0;
     bool totals_known = false;     // n_strong, n_weak, n_p2p_pairs summed
     hipStream_t list_stream = nullptr;
+    bool split_p2p = false, split_m2l = false;   // some list may need work chunks
     // evaluation buffers
     DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
     DBuf<float> src32;             // [N][4] xh yh mr mi (mixed path)
     DBuf<float> srclo;             // [N][2] xl yl
     DBuf<double> mtree;            // [N][2] strengths in tree order (FP64)
     DBuf<double> near;             // [N][2] P2P result, tree order
+    // near-field work split into source chunks (see balance.hip)
+    DBuf<int32_t> nsrc;            // [nbox] sources in the strong list of every leaf
+    struct Balance {
+        DBuf<int32_t> icnt, ioff;  // per item: chunks, exclusive prefix (+ total)
+        DBuf<int2> xitems;         // (item, chunk) for every chunk, grouped by launch class
+        DBuf<double> partial;      // per chunk of a split item: kItemTargets x values
+        DBuf<int64_t> d_cls;       // expanded offsets of the classes (device)
+        std::vector<int64_t> cls;  // the same on the host, nclass + 1 entries
+        DBuf<int32_t> bsum;        // scan workspace
+        DBuf<int64_t> d_base;      // class starts in the item array
+        std::vector<int64_t> h_base;
+        int64_t total = 0;
+        int vals = 0;              // values per target in the partial sums
+        int32_t h32 = 0;           // host copy of a device total
+    } bal, bal_adj, bal_m2l;
     DBuf<char> mpole, local;       // [nbox][p] complex coefficients (T)
     // adjoint buffers
     DBuf<double> gtree;            // conj(G_phi) in tree order
@@ -211,6 +230,7 @@ struct Plan {
 void build_tree_device(Tree& t, const double* z, hipStream_t s);
 void update_positions_device(Tree& t, const double* z, hipStream_t s);
 void build_lists_device(Plan& pl, hipStream_t s);
+void plan_balance(Plan& pl, hipStream_t s);
 void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s);

@@ -220,6 +220,11 @@ struct TravCtx {
     const int64_t* pbox;
     const double* geom;
     double theta;
+    // one-pass mode: per-leaf source counts of the near field, and flags for
+    // lists long enough to be split into work chunks
+    const int32_t* child0;    // -1 for leaves
+    const int32_t* box_count;
+    int32_t* nsrc;
 };
 
 __device__ __forceinline__ void wave_sync_l()
@@ -250,6 +255,7 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
     const int64_t pb = c.pbox[c.prob[g]];
     const int64_t jl = g - pb - level_base(L);        // index of the box within its level
     bool overflow = false, cap_overflow = false;
+    long long src = 0;                                // near-field sources (one-pass mode)
     int nf;
     if (c.l0 == 0) {
         nf = 1;
@@ -299,6 +305,7 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
                 const int o = nn + __popcll(bs & below);
                 if (!last && o < kFrontCap) fb[o] = cc;
                 if (FILL && last && sb + o < lim_s) s_ids[sb + o] = cc;
+                if (MODE == 2 && last) src += c.box_count[cc];
             }
             if (FILL && last && valid && weak) {
                 const int64_t o = wb + nw + __popcll(bw & below);
@@ -311,6 +318,10 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
         wave_sync_l();
         int32_t* t = fa; fa = fb; fb = t;
         nf = nn;
+    }
+    if (MODE == 2) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) src += __shfl_xor(src, o, 64);
     }
     // flags raised by any lane
     cap_overflow = __ballot(cap_overflow) != 0ull;
@@ -326,6 +337,12 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
             s_beg[g] = (int32_t)sb;
             w_beg[g] = (int32_t)wb;
             if (nf > c.cs || nw > c.cw) cap_overflow = true;
+            if (nw > kChunkPairs) atomicOr((unsigned long long*)&totals[2], 8ull);
+            if (L == 0) src = c.box_count[g];
+            if (c.child0[g] < 0) {                      // a leaf: its near-field source count
+                c.nsrc[g] = (int32_t)(src < INT32_MAX ? src : INT32_MAX);
+                if (src > kChunkSrc) atomicOr((unsigned long long*)&totals[2], 4ull);
+            }
         }
         if (cap_overflow) atomicOr((unsigned long long*)&totals[2], 1ull);
         if (overflow) atomicOr((unsigned long long*)&totals[2], 2ull);
@@ -363,8 +380,10 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         c.n = (int)(ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]);
         if (c.n == 0) continue;
         c.l0 = l0;
+        c.cs = c.cw = 0;
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
+        c.child0 = nullptr; c.box_count = nullptr; c.nsrc = nullptr;
         const unsigned grid = (unsigned)((c.n + 3) / 4);
         k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
@@ -425,6 +444,7 @@ static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const
         c.cw = ex.cap_weak;
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
+        c.child0 = ex.child0.p; c.box_count = sc.d_box_count.p; c.nsrc = pl.nsrc.p;
         k_traverse<2><<<(unsigned)((c.n + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p,
                                                                 pl.s_ids.p, pl.w_ids.p, (int64_t)pl.s_ids.n,
                                                                 (int64_t)pl.w_ids.n, totals);
@@ -486,12 +506,15 @@ void build_lists_device(Plan& pl, hipStream_t s)
     if (nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only) {
         pl.s_ids.alloc(nb * ex.cap_strong, s);
         pl.w_ids.alloc(nb * ex.cap_weak, s);
+        pl.nsrc.alloc(nb, s);
         build_lists_direct(pl, s, totals.p, pbox.p);
         long long flag = 0;
         FMM_HIP(hipMemcpyAsync(&flag, totals.p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
-        if (flag == 0) {
+        if ((flag & 3) == 0) {
             pl.totals_known = false;    // list sizes and pair counts are summed on request
+            pl.split_p2p = (flag & 4) != 0;
+            pl.split_m2l = (flag & 8) != 0;
             return;
         }
         grow = (flag & 2) == 0;         // capacities too small, no frontier overflow
@@ -523,6 +546,7 @@ void build_lists_device(Plan& pl, hipStream_t s)
             pl.totals_known = true;
             if (!(h[2] & 1)) {
                 if (grow) grow_capacities(pl, s);
+                pl.split_p2p = pl.split_m2l = true;   // decided by the chunk counts
                 return;
             }
             cap_s = h[0] + h[0] / 4 + 1024;
@@ -564,7 +588,10 @@ void build_lists_device(Plan& pl, hipStream_t s)
         pl.n_weak = h[1];
         pl.n_p2p_pairs = h[3];
         pl.totals_known = true;
-        if (!h[2]) return;
+        if (!h[2]) {
+            pl.split_p2p = pl.split_m2l = true;       // decided by the chunk counts
+            return;
+        }
         cap_s = h[0] + h[0] / 4 + 1024;
         cap_w = h[1] + h[1] / 4 + 1024;
     }

@@ -135,7 +135,8 @@ __device__ __forceinline__ double rcp_nr(double r2)
 
 template <class T, int PB, int NB>
 __global__ void __launch_bounds__(256)
-k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w_beg,
+k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx, const int32_t* __restrict__ icnt,
+      const int32_t* __restrict__ ioff, double* __restrict__ partial, const int32_t* __restrict__ w_beg,
       const int32_t* __restrict__ w_cnt, const int32_t* __restrict__ w_ids, const double* __restrict__ geom,
       const double* __restrict__ binom, int p, const T* __restrict__ mp, T* loc)
 {
@@ -144,12 +145,17 @@ k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w
     constexpr int KS = 4 * PB;       // k-steps of 4 (K = 16 PB)
     constexpr int STEP = 16 * NB;    // pairs per iteration
     const int w = threadIdx.x >> 6;
-    const int bi = blockIdx.x * 4 + w;
-    if (bi >= nbox) return;
-    const int g = boxes[bi];
+    const int xi = blockIdx.x * 4 + w;
+    if (xi >= nx) return;
+    // (box, chunk of its weak list); without chunk lists every box is one chunk
+    const int2 xe = xitems ? xitems[xi] : make_int2(xi, 0);
+    const int g = boxes[xe.x];
+    const int nch = icnt ? icnt[xe.x] : 1;
     const int lane = threadIdx.x & 63;
     const int q = lane & 15, kq = lane >> 4;
-    const int nw = w_cnt[g], wb = w_beg[g];
+    const int nw_all = w_cnt[g], p0 = xe.y * kChunkPairs;
+    const int nw = nch == 1 ? nw_all : min(kChunkPairs, nw_all - p0);   // pairs of this chunk
+    const int wb = w_beg[g] + p0;
 
     // A operands: B_{row,k} = C(k+row, k), row = 16 rb + lane%16, k = 4 ks + lane/16
     T amat[PB][KS];
@@ -296,42 +302,83 @@ k_m2l(const int32_t* __restrict__ boxes, int nbox, const int32_t* __restrict__ w
                 if (q == j) { vr = ore[rb][j]; vi = oim[rb][j]; }
             const int row = 16 * rb + r0 + (M::kRowsConsecutive ? q : 4 * q);
             if (row < p) {
-                T* dst = loc + 2 * ((int64_t)g * p + row);
-                dst[0] = vr;
-                dst[1] = vi;
+                if (nch == 1) {
+                    T* dst = loc + 2 * ((int64_t)g * p + row);
+                    dst[0] = vr;
+                    dst[1] = vi;
+                } else {                          // partial sum of a split list
+                    double* dst = partial + 2 * ((int64_t)(ioff[xe.x] + xe.y) * p + row);
+                    dst[0] = (double)vr;
+                    dst[1] = (double)vi;
+                }
             }
         }
     }
 }
 
 template <class T, int PB, int NB>
-static void m2l_one(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
+static void m2l_one(const int32_t* boxes, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
+                    double* partial, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                     const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
 {
-    k_m2l<T, PB, NB><<<(n + 3) / 4, 256, 0, s>>>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, (const T*)mp,
-                                                 (T*)loc);
+    k_m2l<T, PB, NB><<<(nx + 3) / 4, 256, 0, s>>>(boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom,
+                                                  binom, p, (const T*)mp, (T*)loc);
 }
 
-// batch: weak pairs per iteration of a wavefront, 16 (one MFMA block) or 32
-// (two blocks, two pairs per lane); 0 = automatic (16).
+// the partial local expansions of split lists, added in chunk order
 template <class T>
-void launch_m2l(const int32_t* boxes, int n, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
-                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s,
-                int batch)
+__global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const int32_t* __restrict__ icnt,
+                              const int32_t* __restrict__ ioff, const double* __restrict__ partial, int p, T* loc)
 {
-    if (n == 0) return;
-    const int nb = batch == 32 ? 2 : 1;
-    if (p <= 16 && nb == 1) m2l_one<T, 1, 1>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
-    else if (p <= 16) m2l_one<T, 1, 2>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
-    else if (p <= 32 && nb == 1) m2l_one<T, 2, 1>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
-    else if (p <= 32) m2l_one<T, 2, 2>(boxes, n, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s);
-    else throw Error(FMM_EINVAL, "unsupported M2L configuration");
-    check_launch("m2l");
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * p) return;
+    const int i = (int)(t / p), row = (int)(t % p);
+    const int c = icnt[i];
+    if (c <= 1) return;
+    const int64_t o = ioff[i];
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < c; ++k) {
+        re += partial[2 * ((o + k) * p + row)];
+        im += partial[2 * ((o + k) * p + row) + 1];
+    }
+    T* dst = loc + 2 * ((int64_t)boxes[i] * p + row);
+    dst[0] = (T)re;
+    dst[1] = (T)im;
 }
 
-template void launch_m2l<double>(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*,
-                                 const double*, const double*, int, const void*, void*, hipStream_t, int);
-template void launch_m2l<float>(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*,
-                                const double*, const double*, int, const void*, void*, hipStream_t, int);
+// Every box of `boxes` gets its local expansion written (zeros for a box
+// without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
+// box index; partial holds the chunks of split lists.  batch: weak pairs per
+// iteration of a wavefront, 16 (one MFMA block) or 32 (two blocks, two pairs
+// per lane); 0 = automatic (16).
+template <class T>
+void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
+                double* partial, bool split, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
+                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s, int batch)
+{
+    if (nx == 0) return;
+    const int nb = batch == 32 ? 2 : 1;
+#define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s
+    if (p <= 16 && nb == 1) m2l_one<T, 1, 1>(ARGS);
+    else if (p <= 16) m2l_one<T, 1, 2>(ARGS);
+    else if (p <= 32 && nb == 1) m2l_one<T, 2, 1>(ARGS);
+    else if (p <= 32) m2l_one<T, 2, 2>(ARGS);
+    else throw Error(FMM_EINVAL, "unsupported M2L configuration");
+#undef ARGS
+    check_launch("m2l");
+    if (split) {
+        const int64_t nt = (int64_t)n * p;
+        k_m2l_combine<T><<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(boxes, n, icnt, ioff, partial, p, (T*)loc);
+        check_launch("m2l combine");
+    }
+}
+
+#define INST_M2L(T)                                                                                        \
+    template void launch_m2l<T>(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, \
+                                bool, const int32_t*, const int32_t*, const int32_t*, const double*,            \
+                                const double*, int, const void*, void*, hipStream_t, int);
+INST_M2L(double)
+INST_M2L(float)
+#undef INST_M2L
 
 }  // namespace fmm

@@ -20,6 +20,7 @@
 //   mixed: positions as FP32 hi + lo, dz = (hi_i - hi_j) + (lo_i - lo_j),
 //          everything else in FP32 with FP32 accumulation.
 #include <cfloat>
+#include <climits>
 
 #include "fmm_internal.h"
 #include "p2p_common.h"
@@ -113,7 +114,9 @@ __device__ __forceinline__ int butterfly_index(int lane)
 
 template <int TG, int SUB>
 __global__ void __launch_bounds__(256)
-k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
+        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+        double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out)
 {
@@ -122,9 +125,14 @@ k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + w;
-    if (item >= nitems) return;
-    const P2PItem it = items[item];
+    const int xi_ = blockIdx.x * 4 + w;
+    if (xi_ >= nx) return;
+    // (item, source chunk); without chunk lists every item is one chunk
+    const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
+    const P2PItem it = items[xe.x];
+    const int nch = icnt ? icnt[xe.x] : 1;
+    const int s_first = xe.y * kChunkSrc;
+    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     Src64* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -142,8 +150,11 @@ k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
         return s;
     };
     int e = 0, off = 0;
-    while (e < ne) {
-        int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
+    for (int done = 0; done < s_len && e < ne;) {
+        const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
+                                                 lane, load, s_len - done);
+        done += ns;
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             Src64 s = lds[f < ns ? f : 0];
@@ -162,12 +173,17 @@ k_p2p64(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     const int t = idx >> 1, comp = idx & 1;
     const bool writer = (sl & ((NL / (2 * TG) > 1) ? (NL / (2 * TG) - 1) : 0)) == 0;
     const int k = g * TG + t;
-    if (writer && k < it.tn) reinterpret_cast<double*>(out + base + k)[comp] = v[0];
+    if (writer && k < it.tn) {
+        if (nch == 1) reinterpret_cast<double*>(out + base + k)[comp] = v[0];
+        else partial[((int64_t)(ioff[xe.x] + xe.y) * kItemTargets + k) * 2 + comp] = v[0];
+    }
 }
 
 template <int TG, int SUB>
 __global__ void __launch_bounds__(256)
-k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict__ bstart,
+k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
+        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+        double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
         double2* __restrict__ out)
@@ -177,9 +193,14 @@ k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + w;
-    if (item >= nitems) return;
-    const P2PItem it = items[item];
+    const int xi_ = blockIdx.x * 4 + w;
+    if (xi_ >= nx) return;
+    // (item, source chunk); without chunk lists every item is one chunk
+    const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
+    const P2PItem it = items[xe.x];
+    const int nch = icnt ? icnt[xe.x] : 1;
+    const int s_first = xe.y * kChunkSrc;
+    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     Src32* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -200,8 +221,11 @@ k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
         return s;
     };
     int e = 0, off = 0;
-    while (e < ne) {
-        int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
+    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
+    for (int done = 0; done < s_len && e < ne;) {
+        const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
+                                                 lane, load, s_len - done);
+        done += ns;
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             Src32 s = lds[f < ns ? f : 0];
@@ -219,35 +243,44 @@ k_p2p32(const P2PItem* __restrict__ items, int nitems, const int32_t* __restrict
     const int t = idx >> 1, comp = idx & 1;
     const bool writer = (sl & ((NL / (2 * TG) > 1) ? (NL / (2 * TG) - 1) : 0)) == 0;
     const int k = g * TG + t;
-    if (writer && k < it.tn) reinterpret_cast<double*>(out + base + k)[comp] = (double)v[0];
+    if (writer && k < it.tn) {
+        if (nch == 1) reinterpret_cast<double*>(out + base + k)[comp] = (double)v[0];
+        else partial[((int64_t)(ioff[xe.x] + xe.y) * kItemTargets + k) * 2 + comp] = (double)v[0];
+    }
 }
 
 template <int TG, int SUB>
-static void launch_one(bool mixed, const P2PItem* items, int n, const int32_t* bstart, const int32_t* bcount,
-                       const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids, const void* src,
-                       const void* lo, double* out, hipStream_t s)
+static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
+                       const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                       const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
+                       const void* src, const void* lo, double* out, hipStream_t s)
 {
-    int grid = (n + 3) / 4;
+    int grid = (nx + 3) / 4;
     if (mixed)
-        k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                             (const float2*)lo, (double2*)out);
+        k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
+                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out);
     else
-        k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, n, bstart, bcount, s_beg, s_cnt, s_ids, (const double4*)src,
-                                             (double2*)out);
+        k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
+                                             s_cnt, s_ids, (const double4*)src, (double2*)out);
 }
 
-// one launch per (targets per subgroup, subgroups) class
-void launch_p2p(bool mixed, int tg, int sub, const void* items, int n, const int32_t* bstart,
+// one launch per (targets per subgroup, subgroups) class over its chunks
+// xitems[0 .. nx) (entries (item, chunk), item indices into `items`), or,
+// without chunk lists (xitems and icnt null), over items item_base + i
+void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
+                const int32_t* icnt,
+                const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s)
 {
-    if (n == 0) return;
+    if (nx == 0) return;
     const P2PItem* it = (const P2PItem*)items;
-#define CASE(TG_, SUB_)                                                                               \
-    if (tg == TG_ && sub == SUB_) {                                                                   \
-        launch_one<TG_, SUB_>(mixed, it, n, bstart, bcount, s_beg, s_cnt, s_ids, src, lo, out, s);    \
-        check_launch("p2p");                                                                          \
-        return;                                                                                       \
+#define CASE(TG_, SUB_)                                                                                   \
+    if (tg == TG_ && sub == SUB_) {                                                                       \
+        launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, \
+                              s_ids, src, lo, out, s);                                                    \
+        check_launch("p2p");                                                                              \
+        return;                                                                                           \
     }
     CASE(1, 4) CASE(2, 4) CASE(4, 4)
     CASE(2, 2) CASE(4, 2) CASE(8, 2) CASE(16, 2)

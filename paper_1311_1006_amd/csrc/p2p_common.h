@@ -19,16 +19,17 @@ __device__ __forceinline__ void wave_sync()
 // marks the staging position where its sources start; the entry of a
 // position is then the largest mark at or before it (a running maximum over
 // the positions, lane-strided: position f = lane + 64 r).  Returns the
-// number of sources staged.
+// number of sources staged (at most `limit`).
 template <int CAP, class SRC, class LOADER>
 __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, const int32_t* __restrict__ s_ids,
                                              const int32_t* __restrict__ bstart,
                                              const int32_t* __restrict__ bcount, int e0, int e_end, int& e,
-                                             int& off, int lane, LOADER load)
+                                             int& off, int lane, LOADER load, int limit = CAP)
 {
     constexpr int R = CAP / 64;
+    const int lim = limit < CAP ? limit : CAP;
     int staged = 0;
-    while (e < e_end && staged < CAP) {
+    while (e < e_end && staged < lim) {
         const int k = e + lane;
         int st = 0, avail = 0;
         if (k < e_end) {
@@ -45,7 +46,7 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
         }
         const int excl = x - avail;
         const int total = __shfl(x, 63, 64);
-        const int cap = CAP - staged;
+        const int cap = lim - staged;
         const int take = min(total, cap);
         meta[lane] = make_int2(excl, st);
 #pragma unroll
@@ -102,6 +103,38 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
         wave_sync();
     }
     return staged;
+}
+
+// Entry e and offset off of source ordinal o of the concatenated strong list
+// (entries e0 .. e0 + e_end); e = e_end when o is past the end.
+__device__ __forceinline__ void seek_source(const int32_t* __restrict__ s_ids, const int32_t* __restrict__ bcount,
+                                            int e0, int e_end, int o, int& e, int& off, int lane)
+{
+    e = 0;
+    off = 0;
+    while (e < e_end) {
+        const int k = e + lane;
+        const int c = k < e_end ? bcount[s_ids[e0 + k]] : 0;
+        int x = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        const int total = __shfl(x, 63, 64);
+        if (o >= total) {
+            o -= total;
+            e += 64;
+            continue;
+        }
+        const unsigned long long m = __ballot(x > o);
+        const int f = __ffsll((long long)m) - 1;
+        const int xf = __shfl(x, f, 64), cf = __shfl(c, f, 64);
+        e += f;
+        off = o - (xf - cf);
+        return;
+    }
+    e = e_end;
 }
 
 }  // namespace fmm

@@ -54,6 +54,19 @@ def test_adjoint_matches_direct_gradient(orc, F, prec):
     assert e2(host(gz), rgz) <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_adjoint_with_split_source_lists(orc, F, prec, tol):
+    # one leaf of 5000 points: the adjoint near field is summed in source
+    # chunks and combined; at one level the FMM is the direct sum
+    z, m, _ = W.uniform(5000, seed=11)
+    pl = F.plan(F.build_tree(dev(z), 1), 8, 0.5, prec)
+    phi = F.evaluate(pl, dev(m))
+    gm, gz = F.evaluate_adjoint(pl, dev(m), 2 * phi)
+    rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))
+    assert e2(host(gm), rgm) <= tol
+    assert e2(host(gz), rgz) <= tol
+
+
 def test_adjoint_matches_frozen_geometry_fd(F):
     # directional central differences (h = 1e-6, FP64) of L = sum |phi|^2 with
     # the tree geometry frozen (fmm_tree_update_positions).  The O(h^2) error

@@ -97,6 +97,17 @@ def test_fp64_single_level_is_direct_sum(orc, F):
     assert e2(host(F.evaluate(pl, dev(m))), orc.direct(z, m)) <= 1e-13
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 1e-6)])
+def test_split_source_lists_match_direct_sum(orc, F, prec, tol):
+    # one leaf of 5000 points: every near-field work item sums over 5000
+    # sources, split into chunks whose partial sums are combined in order
+    z, m, _ = W.uniform(5000, seed=6)
+    pl = F.plan(F.build_tree(dev(z), 1), 8, 0.5, prec)
+    phi = host(F.evaluate(pl, dev(m)))
+    assert e2(phi, orc.direct(z, m)) <= tol
+    assert np.array_equal(phi, host(F.evaluate(pl, dev(m))))   # deterministic
+
+
 def test_fp64_within_table_tolerance_of_direct(orc, F):
     # Table 4.1: p = 17 for TOL = 1e-6 at theta = 0.5
     z, m, _ = W.uniform(10000, seed=0)
