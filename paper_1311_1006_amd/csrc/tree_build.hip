@@ -392,37 +392,63 @@ __global__ void __launch_bounds__(kTileThreads)
 k_init(const double* __restrict__ z, const int64_t* __restrict__ poff, int nprob,
        double* X, double* Y, int32_t* I, uint64_t* keys0, uint32_t* err)
 {
+    constexpr int R = kTile / kTileThreads;
     int b = blockIdx.y;
     int64_t s0 = poff[b], s1 = poff[b + 1];
     int64_t t0 = s0 + (int64_t)blockIdx.x * kTile;
     if (t0 >= s1) return;   // uniform per block
-    int64_t t1 = min(s1, t0 + (int64_t)kTile);
+    const int cnt = (int)min(s1 - t0, (int64_t)kTile);
+    // every load of the tile issued before the first use
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kTileThreads + threadIdx.x;
+        v[r] = reinterpret_cast<const double2*>(z)[t0 + (i < cnt ? i : 0)];
+    }
     double x0 = 1e308, x1 = -1e308, y0 = 1e308, y1 = -1e308;
     bool any = false, bad = false;
-    for (int64_t i = t0 + threadIdx.x; i < t1; i += kTileThreads) {
-        double2 v = reinterpret_cast<const double2*>(z)[i];
-        bad |= !(isfinite(v.x) && isfinite(v.y));
-        X[i] = v.x; Y[i] = v.y; I[i] = (int32_t)i;
-        x0 = fmin(x0, v.x); x1 = fmax(x1, v.x); y0 = fmin(y0, v.y); y1 = fmax(y1, v.y);
-        any = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kTileThreads + threadIdx.x;
+        if (i < cnt) {
+            bad |= !(isfinite(v[r].x) && isfinite(v[r].y));
+            X[t0 + i] = v[r].x; Y[t0 + i] = v[r].y; I[t0 + i] = (int32_t)(t0 + i);
+            x0 = fmin(x0, v[r].x); x1 = fmax(x1, v[r].x); y0 = fmin(y0, v[r].y); y1 = fmax(y1, v[r].y);
+            any = true;
+        }
     }
     if (bad) atomicOr(err, 1u);
     // any is false only for threads without points; min/max skip them
     block_minmax_atomic(x0, x1, y0, y1, keys0 + kKeyWords * b, any);
 }
 
+// the split coordinate of the tile's points (element r * kTileThreads + tid)
+// into registers, every load issued before the first use
+template <int R>
+__device__ __forceinline__ void load_tile(const double* __restrict__ C, const TileInfo& t, double (&v)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kTileThreads + threadIdx.x;
+        v[r] = C[t.start + (i < t.count ? i : 0)];
+    }
+}
+
 __global__ void __launch_bounds__(kTileThreads)
 k_hist1(const TileInfo* __restrict__ tiles, const double* __restrict__ X,
         const double* __restrict__ Y, const uint64_t* __restrict__ keys, uint32_t* hist1)
 {
+    constexpr int R = kTile / kTileThreads;
     __shared__ uint32_t h[kBuckets];
     TileInfo t = tiles[blockIdx.x];
     Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
+    double v[R];
+    load_tile(bk.axis ? Y : X, t, v);
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
     __syncthreads();
-    const double* C = bk.axis ? Y : X;
-    for (int i = threadIdx.x; i < t.count; i += kTileThreads)
-        atomicAdd(&h[bucket_of(bk, C[t.start + i])], 1u);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r * kTileThreads + (int)threadIdx.x < t.count) atomicAdd(&h[bucket_of(bk, v[r])], 1u);
     __syncthreads();
     uint32_t* g = hist1 + (int64_t)t.seg * kBuckets;
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
@@ -492,13 +518,15 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     if (bk.scale == 0.0) return;  // all points in one bucket: the exact fallback handles it
     SubBucketer sb = make_sub(bk, b1);
+    constexpr int R = kTile / kTileThreads;
+    double v[R];
+    load_tile(bk.axis ? Y : X, t, v);
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
     __syncthreads();
-    const double* C = bk.axis ? Y : X;
-    for (int i = threadIdx.x; i < t.count; i += kTileThreads) {
-        double c = C[t.start + i];
-        if (bucket_of(bk, c) == b1) atomicAdd(&h[sub_of(sb, c)], 1u);
-    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r * kTileThreads + (int)threadIdx.x < t.count && bucket_of(bk, v[r]) == b1)
+            atomicAdd(&h[sub_of(sb, v[r])], 1u);
     __syncthreads();
     uint32_t* g = hist2 + (int64_t)t.seg * kBuckets;
     for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
@@ -617,16 +645,20 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     int rank, ccount;
     ClassRule rule = median_class(keys, hist1, hist2, t.seg, sg.count / 2, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
-    const double* C = rule.bk.axis ? Y : X;
+    constexpr int R = kTile / kTileThreads;
+    double v[R];
+    load_tile(rule.bk.axis ? Y : X, t, v);
     int below = 0;
-    for (int i = threadIdx.x; i < t.count; i += kTileThreads) {
-        double c = C[t.start + i];
-        int cl = class_of(rule, c);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kTileThreads + threadIdx.x;
+        if (i >= t.count) continue;
+        int cl = class_of(rule, v[r]);
         below += (cl < 0);
         if (cl == 0 && !overflow) {
             uint32_t pos = atomicAdd(&cand_cnt[t.seg], 1u);
             if (pos < (uint32_t)kCandCap) {
-                Cand cd; cd.c = c; cd.idx = I[t.start + i]; cd.tile = t.rank;
+                Cand cd; cd.c = v[r]; cd.idx = I[t.start + i]; cd.tile = t.rank;
                 cand[(int64_t)t.seg * kCandCap + pos] = cd;
             }
         }
@@ -721,6 +753,48 @@ k_pick(const int32_t* __restrict__ seglist, const SegInfo* __restrict__ segs, co
     if (threadIdx.x == 0) split[seg] = sp;
 }
 
+// bounding boxes of both halves of a tile into the next stage's keys (one
+// barrier for the two)
+__device__ __forceinline__ void block_minmax2_atomic(const double (&l)[4], const double (&u)[4], bool anyl,
+                                                     bool anyu, uint64_t* keys_lo, uint64_t* keys_hi)
+{
+    __shared__ uint64_t red[8][kTileThreads / 64];
+    uint64_t k[8];
+    k[0] = anyl ? okey(l[0]) : ~0ull; k[1] = anyl ? okey(l[1]) : 0ull;
+    k[2] = anyl ? okey(l[2]) : ~0ull; k[3] = anyl ? okey(l[3]) : 0ull;
+    k[4] = anyu ? okey(u[0]) : ~0ull; k[5] = anyu ? okey(u[1]) : 0ull;
+    k[6] = anyu ? okey(u[2]) : ~0ull; k[7] = anyu ? okey(u[3]) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint64_t v = __shfl_xor(k[q], o, 64);
+            k[q] = (q & 1) ? (v > k[q] ? v : k[q]) : (v < k[q] ? v : k[q]);
+        }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][w] = k[q];
+    __syncthreads();
+    // thread q < 8 combines value q over the waves and updates one key
+    if (threadIdx.x < 8) {
+        const int q = threadIdx.x;
+        uint64_t a = red[q][0];
+        for (int i = 1; i < kTileThreads / 64; ++i) a = (q & 1) ? (red[q][i] > a ? red[q][i] : a)
+                                                                : (red[q][i] < a ? red[q][i] : a);
+        uint64_t* kk = (q < 4 ? keys_lo : keys_hi) + 4 * (blockIdx.x & (kKeyCopies - 1)) + (q & 3);
+        const bool empty = (q & 1) ? a == 0ull : a == ~0ull;
+        if (!empty) {
+            if (q & 1) atomicMax((unsigned long long*)kk, (unsigned long long)a);
+            else atomicMin((unsigned long long*)kk, (unsigned long long)a);
+        }
+    }
+}
+
+// Stable two-way partition of one tile.  Element i = r * kTileThreads + tid
+// is lower if (coordinate, index) < splitter; its rank among the lower
+// (upper) elements of the tile comes from per-wave ballots of every row,
+// combined with one barrier.
 __global__ void __launch_bounds__(kTileThreads)
 k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
@@ -728,55 +802,67 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             uint64_t* keys_next, const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
 {
     constexpr int R = kTile / kTileThreads;
-    __shared__ int sh[kTileThreads / 64];
+    constexpr int NW = kTileThreads / 64;
+    __shared__ int wcnt[R][NW];
     TileInfo t = tiles[blockIdx.x];
     SegInfo sg = segs[t.seg];
     Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     Splitter sp = split[t.seg];
-    int k = sg.count / 2;
-    int toff = t.start - sg.start;
-    int lob = (int)lo_base[sg.tile0 + t.rank];
-    // the whole tile into registers first (element r*256 + tid)
+    const int k = sg.count / 2;
+    const int toff = t.start - sg.start;
+    const int lob = (int)lo_base[sg.tile0 + t.rank];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double x[R], y[R];
     int32_t id[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int i = r * kTileThreads + threadIdx.x;
-        int ii = t.start + (i < t.count ? i : 0);
+        const int i = r * kTileThreads + threadIdx.x;
+        const int ii = t.start + (i < t.count ? i : 0);
         x[r] = X[ii]; y[r] = Y[ii]; id[r] = I[ii];
     }
-    int lo_run = lob, hi_run = toff - lob;
-    double lx0 = 1e308, lx1 = -1e308, ly0 = 1e308, ly1 = -1e308;
-    double ux0 = 1e308, ux1 = -1e308, uy0 = 1e308, uy1 = -1e308;
-    bool anyl = false, anyu = false;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int inwave[R];
+    bool lower[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int r0 = r * kTileThreads;
-        if (r0 >= t.count) break;   // uniform
-        int i = r0 + threadIdx.x;
-        bool valid = i < t.count;
-        bool lower = valid && key_less(bk.axis ? y[r] : x[r], id[r], sp.c, sp.idx);
-        int tot;
-        int ex = block_excl_scan<kTileThreads>(lower ? 1 : 0, sh, &tot);
-        int nvalid = min(kTileThreads, t.count - r0);
-        if (valid) {
+        const int i = r * kTileThreads + threadIdx.x;
+        lower[r] = i < t.count && key_less(bk.axis ? y[r] : x[r], id[r], sp.c, sp.idx);
+        const unsigned long long m = __ballot(lower[r]);
+        inwave[r] = __popcll(m & lt);
+        if (lane == 0) wcnt[r][wid] = __popcll(m);
+    }
+    __syncthreads();
+    double l[4] = {1e308, -1e308, 1e308, -1e308}, u[4] = {1e308, -1e308, 1e308, -1e308};
+    bool anyl = false, anyu = false;
+    int before = 0;   // lower elements of the tile in earlier rows
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int rowtot = 0, prev = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int c = wcnt[r][w];
+            prev += (w < wid) ? c : 0;
+            rowtot += c;
+        }
+        const int i = r * kTileThreads + threadIdx.x;
+        if (i < t.count) {
+            const int lb = before + prev + inwave[r];   // lower elements before i in the tile
             int dst;
-            if (lower) {
-                dst = sg.start + lo_run + ex;
-                lx0 = fmin(lx0, x[r]); lx1 = fmax(lx1, x[r]); ly0 = fmin(ly0, y[r]); ly1 = fmax(ly1, y[r]);
+            if (lower[r]) {
+                dst = sg.start + lob + lb;
+                l[0] = fmin(l[0], x[r]); l[1] = fmax(l[1], x[r]); l[2] = fmin(l[2], y[r]); l[3] = fmax(l[3], y[r]);
                 anyl = true;
             } else {
-                dst = sg.start + k + hi_run + (i - r0 - ex);
-                ux0 = fmin(ux0, x[r]); ux1 = fmax(ux1, x[r]); uy0 = fmin(uy0, y[r]); uy1 = fmax(uy1, y[r]);
+                dst = sg.start + k + (toff - lob) + (i - lb);
+                u[0] = fmin(u[0], x[r]); u[1] = fmax(u[1], x[r]); u[2] = fmin(u[2], y[r]); u[3] = fmax(u[3], y[r]);
                 anyu = true;
             }
             if (dst >= sg.start && dst < sg.start + sg.count) { X2[dst] = x[r]; Y2[dst] = y[r]; I2[dst] = id[r]; }
         }
-        lo_run += tot;
-        hi_run += nvalid - tot;
+        before += rowtot;
     }
-    block_minmax_atomic(lx0, lx1, ly0, ly1, keys_next + kKeyWords * (int64_t)sg.child, anyl);
-    block_minmax_atomic(ux0, ux1, uy0, uy1, keys_next + kKeyWords * ((int64_t)sg.child + 1), anyu);
+    block_minmax2_atomic(l, u, anyl, anyu, keys_next + kKeyWords * (int64_t)sg.child,
+                         keys_next + kKeyWords * ((int64_t)sg.child + 1));
 }
 
 // geometry of boxes whose bounding box came from a global stage
