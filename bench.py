@@ -24,7 +24,39 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3      # TFLOP/s, MI355X published FP32 vector peak (packed)
 PEAK_FP32_NOPACK = 78.6     # TFLOP/s, the same units issuing one FP32 op per lane per cycle
-P2P_FLOP_PER_PAIR = 16
+PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X published dense FP32 matrix peak
+P2P_FLOP_PER_PAIR = 16      # per (target, source) pair: see the near-field kernel's header
+
+
+def m2l_flop_per_pair(p):
+    # a p x p real matrix times p complex coefficients: 2 p^2 real multiply-adds
+    return 4 * p * p
+
+
+def profile_traffic(name):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None when a source it names changed after the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in fields["kernel_sources"].split():
+            with open(os.path.join(ROOT, "paper_1311_1006_amd", "csrc", src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def log(*a):
@@ -128,6 +160,9 @@ def main():
     ap.add_argument("--levels", type=str, default="8,9,10")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-forms", action="store_true", help="skip the batch and adjoint measurements")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="for hardware-counter runs: warmup + steps mixed-precision steps at the first "
+                         "--levels value, then a 256 MiB device copy (counter calibration); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -166,8 +201,20 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k
 
-    # ---- N_levels, then the P2P split and the M2L batch, by timing sweeps
     levels = [int(x) for x in args.levels.split(",") if 4 ** (int(x) - 1) <= n]
+    if args.pmc_workload:
+        for _ in range(args.warmup + args.steps):
+            step("mixed", (levels[0], 0, 0))
+        torch.cuda.synchronize()
+        a = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("pmc workload: %d mixed steps at N_levels=%d, then a copy of %d bytes" %
+            (args.warmup + args.steps, levels[0], a.numel() * 8))
+        return
+
+    # ---- N_levels, then the P2P split and the M2L batch, by timing sweeps
     best_cfg = {}
     for prec in ("mixed", "fp64"):
         best = None
@@ -213,11 +260,11 @@ def main():
             F.evaluate(plt, md, out)
             st = plt.stats()
             if r:
-                for k in ("t_upward_us", "t_m2l_us", "t_p2p_us", "t_downward_us", "t_total_us"):
+                for k in ("t_upward_us", "t_m2l_us", "t_l2l_us", "t_p2p_us", "t_downward_us", "t_total_us"):
                     ph[k] = ph.get(k, 0.0) + st[k] / args.steps
         st = plt.stats()
         res[prec] = dict(L=cfg[0], split=cfg[1], batch=cfg[2], t=dt, t_eval=dte, stats=st, phases=ph,
-                         p2p_us=ph["t_p2p_us"], phi=phi)
+                         p2p_us=ph["t_p2p_us"], m2l_us=ph["t_m2l_us"], phi=phi)
         log("%s: L=%d split=%d batch=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, phases %s" %
             (prec, cfg[0], cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
              " ".join("%s=%.1f" % (k[2:-3], v) for k, v in ph.items())))
@@ -248,7 +295,26 @@ def main():
 
     mx, fp = res["mixed"], res["fp64"]
     st = mx["stats"]
-    achieved = P2P_FLOP_PER_PAIR * st["n_p2p_pairs"] / (mx["p2p_us"] * 1e-6) / 1e12
+    # roofline of the two evaluation kernels (mixed precision), each from its
+    # own average launch duration (hipEvents on the evaluation stream); the
+    # one with the longer launch is reported as the dominant kernel
+    tflop = P2P_FLOP_PER_PAIR * st["n_p2p_pairs"] / (mx["p2p_us"] * 1e-6) / 1e12
+    roof_p2p = {"bound": "alu", "kernel": "k_p2p32 (mixed near field)", "achieved": tflop,
+                "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": tflop / PEAK_FP32_VALU,
+                "traffic": profile_traffic("p2p_mixed_uniform_n1e6_L9_pmc.txt"),
+                "peak_without_packed_fp32": PEAK_FP32_NOPACK,
+                "frac_without_packed_fp32": tflop / PEAK_FP32_NOPACK,
+                "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR}
+    fpp = m2l_flop_per_pair(p)
+    tflop = fpp * st["n_m2l_pairs"] / (mx["m2l_us"] * 1e-6) / 1e12
+    roof_m2l = {"bound": "mfma", "kernel": "k_m2l<float> (mixed M2L, FP32 MFMA)", "achieved": tflop,
+                "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": tflop / PEAK_FP32_MFMA,
+                "traffic": profile_traffic("m2l_mixed_uniform_n1e6_L9_pmc.txt"),
+                "avg_us": mx["m2l_us"], "pairs": st["n_m2l_pairs"], "flop_per_pair": fpp}
+    if mx["m2l_us"] >= mx["p2p_us"]:
+        roofline, other = roof_m2l, {"p2p": roof_p2p}
+    else:
+        roofline, other = roof_p2p, {"m2l": roof_m2l}
     line = {
         "metric": "Mpoints/s full FMM eval N=1e6 @rel err<=1e-6: mixed-prec vs plain FP64 GPU",
         "value": n / mx["t"] / 1e6,
@@ -269,11 +335,8 @@ def main():
                  "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64"), "phases_us": fp["phases"]},
         "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed"), "phases_us": mx["phases"]},
         "speedup_mixed_vs_fp64": fp["t"] / mx["t"],
-        "roofline": {"bound": "alu", "kernel": "p2p (mixed)", "achieved": achieved, "peak": PEAK_FP32_VALU,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "peak_without_packed_fp32": PEAK_FP32_NOPACK,
-                     "frac_without_packed_fp32": achieved / PEAK_FP32_NOPACK,
-                     "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR},
+        "roofline": roofline,
+        "roofline_other": other,
         "cpu_baseline": cpu_baseline,
         "forms": forms,
     }

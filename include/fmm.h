@@ -88,10 +88,13 @@ typedef struct {
     int64_t n_strong_entries;  /* finest-level strong-list entries */
     int p, precision, max_levels, nprob;
     double theta;
-    /* microseconds of the last timed fmm_evaluate / fmm_evaluate_adjoint
-       phases (0 unless FMM_FLAG_PHASE_TIMING) */
+    /* microseconds of the phases of the last fmm_evaluate run with
+       FMM_FLAG_PHASE_TIMING (0 otherwise), from events on its stream:
+       upward = gather + P2M + M2M, m2l = the M2L kernel(s) alone,
+       downward = L2P, p2p = near field, l2l (below) = the L2L sweep */
     double t_upward_us, t_m2l_us, t_downward_us, t_p2p_us, t_total_us;
     double t_tree_us, t_plan_us;   /* last fmm_build_tree / fmm_plan device time, if timed */
+    double t_l2l_us;
 } fmm_stats;
 
 /*

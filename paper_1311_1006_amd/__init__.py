@@ -44,7 +44,7 @@ class _Stats(C.Structure):
                 ("theta", C.c_double),
                 ("t_upward_us", C.c_double), ("t_m2l_us", C.c_double), ("t_downward_us", C.c_double),
                 ("t_p2p_us", C.c_double), ("t_total_us", C.c_double), ("t_tree_us", C.c_double),
-                ("t_plan_us", C.c_double)]
+                ("t_plan_us", C.c_double), ("t_l2l_us", C.c_double)]
 
 
 class _TunerParams(C.Structure):

@@ -372,6 +372,7 @@ int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st)
         st->theta = P.theta;
         st->t_upward_us = P.t_up;
         st->t_m2l_us = P.t_m2l;
+        st->t_l2l_us = P.t_l2l;
         st->t_p2p_us = P.t_p2p;
         st->t_downward_us = P.t_down;
         st->t_total_us = P.t_total;

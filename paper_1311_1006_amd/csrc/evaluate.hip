@@ -172,8 +172,41 @@ static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipS
     }
 }
 
+struct PhaseTimer;
+
 template <class T>
-static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s)
+static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm);
+
+struct PhaseTimer {
+    static constexpr int kEvents = 6;
+    bool on;
+    hipStream_t s;
+    hipEvent_t ev[kEvents];
+    int k = 0;
+    PhaseTimer(bool o, hipStream_t st) : on(o), s(st)
+    {
+        if (on)
+            for (auto& e : ev) FMM_HIP(hipEventCreate(&e));
+    }
+    void mark()
+    {
+        if (on) FMM_HIP(hipEventRecord(ev[k++], s));
+    }
+    float between(int a, int b)
+    {
+        float ms = 0;
+        FMM_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        return ms * 1000.0f;
+    }
+    ~PhaseTimer()
+    {
+        if (on)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+template <class T>
+static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -181,6 +214,7 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
                   b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
                   pl.tune.m2l_batch);
+    tm.mark();
     // parents at level l (non-leaf) hand their expansion to level l+1
     for (int l = 1; l + 1 < sc.max_levels; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
@@ -211,33 +245,6 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }
 
-struct PhaseTimer {
-    bool on;
-    hipStream_t s;
-    hipEvent_t ev[6];
-    int k = 0;
-    PhaseTimer(bool o, hipStream_t st) : on(o), s(st)
-    {
-        if (on)
-            for (auto& e : ev) FMM_HIP(hipEventCreate(&e));
-    }
-    void mark()
-    {
-        if (on) FMM_HIP(hipEventRecord(ev[k++], s));
-    }
-    float between(int a, int b)
-    {
-        float ms = 0;
-        FMM_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
-        return ms * 1000.0f;
-    }
-    ~PhaseTimer()
-    {
-        if (on)
-            for (auto& e : ev) (void)hipEventDestroy(e);
-    }
-};
-
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s)
 {
     Tree& t = *pl.tree;
@@ -250,8 +257,8 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
     else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
     tm.mark();
-    if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s);
-    else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s);
+    if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
+    else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
     tm.mark();
     run_p2p(pl, ex, s);
     tm.mark();
@@ -263,12 +270,13 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
                            pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
     tm.mark();
     if (tm.on) {
-        FMM_HIP(hipEventSynchronize(tm.ev[4]));
+        FMM_HIP(hipEventSynchronize(tm.ev[5]));
         pl.t_up = tm.between(0, 1);
         pl.t_m2l = tm.between(1, 2);
-        pl.t_p2p = tm.between(2, 3);
-        pl.t_down = tm.between(3, 4);
-        pl.t_total = tm.between(0, 4);
+        pl.t_l2l = tm.between(2, 3);
+        pl.t_p2p = tm.between(3, 4);
+        pl.t_down = tm.between(4, 5);
+        pl.t_total = tm.between(0, 5);
     }
     pl.have_forward = true;
 }

@@ -217,7 +217,7 @@ struct Plan {
     const double* last_m = nullptr;
     // timing
     double t_plan_us = 0;
-    double t_up = 0, t_m2l = 0, t_down = 0, t_p2p = 0, t_total = 0;
+    double t_up = 0, t_m2l = 0, t_l2l = 0, t_down = 0, t_p2p = 0, t_total = 0;
     // graph
     hipGraphExec_t graph = nullptr;
     const double* graph_m = nullptr;
