@@ -91,7 +91,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][CAP];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int xi = blockIdx.x * 4 + w;
+    const int xi = xcd_block() * 4 + w;
     if (xi >= nx) return;
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi] : make_int2(item_base + xi, 0);

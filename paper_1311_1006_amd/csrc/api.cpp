@@ -276,6 +276,10 @@ void fmm_plan_destroy(fmm_plan_t pl)
         (void)hipEventDestroy(P.ev_in);
         (void)hipEventDestroy(P.ev_out);
     }
+    // the near-field stream is shared; work on it is joined into the
+    // evaluation stream, so the plan's buffers are released in stream order
+    if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
+    if (P.ev_join) (void)hipEventDestroy(P.ev_join);
     delete pl;
 }
 

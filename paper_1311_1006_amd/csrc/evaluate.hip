@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "fmm_internal.h"
 #include "plan_extra.h"
@@ -245,6 +246,22 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }
 
+// One near-field stream per device, shared by all plans and kept until the
+// process ends (creating a stream per plan costs more than a whole step).
+// Plans that share it are ordered by their own fork/join events.
+static hipStream_t near_stream(int device)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(device);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    FMM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams[device] = st;
+    return st;
+}
+
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s)
 {
     Tree& t = *pl.tree;
@@ -252,15 +269,31 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     PlanExtra& ex = *extra(pl);
     bool mixed = pl.precision == FMM_MIXED;
     PhaseTimer tm((pl.tune.flags & FMM_FLAG_PHASE_TIMING) != 0, s);
+    // The near field needs only the gathered sources: it runs on a second
+    // stream beside the far-field chain (P2M .. L2L) and joins before L2P.
+    // Phase timing keeps the phases one after another on `s`.
+    const bool overlap = !tm.on;
+    if (overlap && !pl.nstream) {
+        pl.nstream = near_stream(t.device);
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+    }
     tm.mark();
     launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    if (overlap) {
+        FMM_HIP(hipEventRecord(pl.ev_fork, s));
+        FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
+        run_p2p(pl, ex, pl.nstream);
+        FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
+    }
     if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
     else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
     tm.mark();
     if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
     else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
     tm.mark();
-    run_p2p(pl, ex, s);
+    if (overlap) FMM_HIP(hipStreamWaitEvent(s, pl.ev_join, 0));
+    else run_p2p(pl, ex, s);
     tm.mark();
     if (mixed)
         launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,

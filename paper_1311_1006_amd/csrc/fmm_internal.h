@@ -224,6 +224,8 @@ struct Plan {
     double* graph_phi = nullptr;
     hipStream_t gstream = nullptr;         // capture / replay stream of graph mode
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t nstream = nullptr;         // near-field stream of the device (shared, not owned)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // ---------------------------------------------------------- launchers

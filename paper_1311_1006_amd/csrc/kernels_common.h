@@ -15,6 +15,16 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Workgroups are handed to the 8 XCDs of the chip in turn (workgroup b to
+// XCD b mod 8).  This maps them so that each XCD runs one contiguous range of
+// the launch: neighbouring work items (nearby boxes) then share that XCD's L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b & 7, i = b >> 3, full = G >> 3, rem = G & 7;
+    return x < rem ? x * (full + 1) + i : rem * (full + 1) + (x - rem) * full + i;
+}
+
 template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };

@@ -13,10 +13,12 @@
 //
 // One wavefront per target box, blocks of 16 weak pairs (one or two blocks
 // per iteration).  Lane (kq, q),
-// kq = lane/16, q = lane%16, owns pair q of the block: it computes in FP64
-// exactly the powers it feeds to the MFMA (x_k for k = kq + 4i, the B
-// operand of k-step i) and the row factors of the output rows it holds,
-// casts them to the storage type, and accumulates f_l * Y_lq in registers.
+// kq = lane/16, q = lane%16, owns pair q of the block: it computes the powers
+// it feeds to the MFMA (x_k for k = kq + 4i, the B operand of k-step i) and
+// the row factors of the output rows it holds, and accumulates f_l * Y_lq in
+// registers.  FP64 path: powers in FP64.  Mixed path: the centre difference
+// in FP64, the powers in FP32 (their rounding stays below that of the FP32
+// coefficients they multiply).
 // No LDS and no barriers: the geometry and coefficients of the next block
 // are loaded while the current one is computed.  At the end the 16 pair
 // slots are summed by a butterfly.
@@ -25,6 +27,8 @@
 // p <= 16 uses one 16-row block (PB = 1), p <= 32 two.
 #include "fmm_internal.h"
 #include "kernels_common.h"
+
+#include <type_traits>
 
 namespace fmm {
 
@@ -56,11 +60,19 @@ __device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
     return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
 
+__device__ __forceinline__ float2 csel(bool c, float2 a, float2 b)
+{
+    return make_float2(c ? a.x : b.x, c ? a.y : b.y);
+}
+
 // z^e for e in 0..3 from z and z^2 (e differs between lanes): one product of
 // two selected factors, so that no lane-indexed table is needed
-__device__ __forceinline__ double2 cpow_lane(double2 z, double2 z2, int e)
+template <class C2>
+__device__ __forceinline__ C2 cpow_lane(C2 z, C2 z2, int e)
 {
-    const double2 one = make_double2(1.0, 0.0);
+    C2 one;
+    one.x = 1;
+    one.y = 0;
     return cmul(csel(e & 1, z, one), csel(e & 2, z2, one));
 }
 
@@ -145,7 +157,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     constexpr int KS = 4 * PB;       // k-steps of 4 (K = 16 PB)
     constexpr int STEP = 16 * NB;    // pairs per iteration
     const int w = threadIdx.x >> 6;
-    const int xi = blockIdx.x * 4 + w;
+    const int xi = xcd_block() * 4 + w;
     if (xi >= nx) return;
     // (box, chunk of its weak list); without chunk lists every box is one chunk
     const int2 xe = xitems ? xitems[xi] : make_int2(xi, 0);
@@ -173,6 +185,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         for (int j = 0; j < 4; ++j) { ore[rb][j] = (T)0; oim[rb][j] = (T)0; }
 
     const double ctx = geom[4 * (int64_t)g], cty = geom[4 * (int64_t)g + 1], rsT = geom[4 * (int64_t)g + 3];
+    const float rsTf = (float)rsT;
     // first output row of this lane within a 16-row block; the rows it holds
     // are r0 + j (FP32) or r0 + 4 j (FP64)
     const int r0 = M::kRowsConsecutive ? 4 * kq : kq;
@@ -186,31 +199,58 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : g; };
     auto compute = [&](const PairData<T, KS>& c, int b0, int nb) {
         const bool valid = b0 + 16 * nb + q < nw;
-        // ---- FP64 powers of this lane's pair
-        const double dx = ctx - c.sx, dy = cty - c.sy;
-        const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
-        const double2 id = make_double2(dx * den, -dy * den);          // 1/d (0 for padding)
-        const double2 u = make_double2(c.rs * id.x, c.rs * id.y);      // rs_S / d
-        const double2 wv = make_double2(-rsT * id.x, -rsT * id.y);     // -rs_T / d
-        const double2 u2 = cmul(u, u), u4 = cmul(u2, u2);
-        const double2 w2 = cmul(wv, wv), w4 = cmul(w2, w2);
-        // B operands x_k, k = kq + 4 i
+        // Padding slots (past the end of the list) hold a real weak source of
+        // this list, so every coefficient is finite; they get 1/d = 0, hence
+        // zero row factors, and add nothing.  Terms k >= p meet zero columns
+        // of B and rows l >= p are not stored.
         T2 xv[KS];
-        {
+        T fre[PB][4], fim[PB][4];
+        if constexpr (std::is_same<T, float>::value) {
+            // mixed: the centre difference in FP64 (the centres are close in
+            // value), everything after it in FP32
+            const float dx = (float)(ctx - c.sx), dy = (float)(cty - c.sy);
+            const float den = valid ? __builtin_amdgcn_rcpf(dx * dx + dy * dy) : 0.f;
+            const float2 id = make_float2(dx * den, -dy * den);        // 1/d (0 for padding)
+            const float rs = (float)c.rs;
+            const float2 u = make_float2(rs * id.x, rs * id.y);        // rs_S / d
+            const float2 wv = make_float2(-rsTf * id.x, -rsTf * id.y); // -rs_T / d
+            const float2 u2 = cmul(u, u), u4 = cmul(u2, u2);
+            const float2 w2 = cmul(wv, wv), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+            float2 pw = cpow_lane(u, u2, kq);                           // u^kq
+#pragma unroll
+            for (int i = 0; i < KS; ++i) {
+                xv[i] = cmul(pw, c.a[i]);
+                if (i + 1 < KS) pw = cmul(pw, u4);
+            }
+            // output rows 16 rb + 4 kq + j: f = (1/d) w^(4 kq + j) w^(16 rb)
+            const float2 f0 = cmul(cpow_lane(w4, w8, kq), id);
+#pragma unroll
+            for (int rb = 0; rb < PB; ++rb) {
+                float2 f = rb > 0 ? cmul(f0, cmul(w8, w8)) : f0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    fre[rb][j] = f.x;
+                    fim[rb][j] = f.y;
+                    if (j < 3) f = cmul(f, wv);
+                }
+            }
+        } else {
+            // ---- FP64 powers of this lane's pair
+            const double dx = ctx - c.sx, dy = cty - c.sy;
+            const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
+            const double2 id = make_double2(dx * den, -dy * den);          // 1/d (0 for padding)
+            const double2 u = make_double2(c.rs * id.x, c.rs * id.y);      // rs_S / d
+            const double2 wv = make_double2(-rsT * id.x, -rsT * id.y);     // -rs_T / d
+            const double2 u2 = cmul(u, u), u4 = cmul(u2, u2);
+            const double2 w2 = cmul(wv, wv), w4 = cmul(w2, w2);
+            // B operands x_k, k = kq + 4 i
             double2 pw = cpow_lane(u, u2, kq);
 #pragma unroll
             for (int i = 0; i < KS; ++i) {
-                T2 a = c.a[i];
-                const bool use = valid && kq + 4 * i < p;
-                a.x = use ? a.x : (T)0;
-                a.y = use ? a.y : (T)0;
-                xv[i] = scale_coef(pw, a);
+                xv[i] = scale_coef(pw, c.a[i]);
                 if (i + 1 < KS) pw = cmul(pw, u4);
             }
-        }
-        // row factors f_l = (1/d) w^l of this lane's output rows
-        T fre[PB][4], fim[PB][4];
-        {
+            // row factors f_l = (1/d) w^l of this lane's output rows
             double2 base;                    // w^r0
             if (M::kRowsConsecutive) base = cpow_lane(w4, cmul(w4, w4), kq);
             else base = cpow_lane(wv, w2, kq);
@@ -254,7 +294,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         const int e0 = 16 * nb + q;
         const int s0 = raw_id(e0);
         sidB[nb] = raw_id(STEP + e0);
-        load_pair<T, KS>(bufA[nb], e0 < nw ? s0 : g, kq, p, geom, mp);
+        load_pair<T, KS>(bufA[nb], s0, kq, p, geom, mp);
     }
     for (int b0 = 0; b0 < nw; b0 += 2 * STEP) {
         // block b0 in bufA; load block b0 + STEP into bufB
@@ -262,7 +302,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         for (int nb = 0; nb < NB; ++nb) {
             const int e1 = b0 + STEP + 16 * nb + q;
             sidA[nb] = raw_id(e1 + STEP);
-            load_pair<T, KS>(bufB[nb], e1 < nw ? sidB[nb] : g, kq, p, geom, mp);
+            load_pair<T, KS>(bufB[nb], sidB[nb], kq, p, geom, mp);
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) compute(bufA[nb], b0, nb);
@@ -272,7 +312,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         for (int nb = 0; nb < NB; ++nb) {
             const int e2 = b0 + 2 * STEP + 16 * nb + q;
             sidB[nb] = raw_id(e2 + STEP);
-            load_pair<T, KS>(bufA[nb], e2 < nw ? sidA[nb] : g, kq, p, geom, mp);
+            load_pair<T, KS>(bufA[nb], sidA[nb], kq, p, geom, mp);
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) compute(bufB[nb], b0 + STEP, nb);

@@ -14,8 +14,10 @@
 // kernel arithmetic.  Padding lanes carry zero strength.  A transposing
 // butterfly then sums the 2*TG accumulators over the NL lanes with about
 // 2*TG shuffles instead of 2*TG*log2(NL).
-// Exclusion by position: a pair with z_j = z_i has r^2 = 0; its reciprocal is
-// clamped to the largest finite value and multiplies an exact zero.
+// Exclusion by position: r^2 is formed as dx^2 + (dy^2 + tiny) with tiny the
+// smallest normal number, which leaves every r^2 of two distinct points
+// unchanged and turns r^2 = 0 (z_j = z_i) into a finite reciprocal that
+// multiplies an exact zero.
 //   FP64:  dz in FP64, 1/r^2 by v_rcp_f64 and two Newton steps.
 //   mixed: positions as FP32 hi + lo, dz = (hi_i - hi_j) + (lo_i - lo_j),
 //          everything else in FP32 with FP32 accumulation.
@@ -23,6 +25,7 @@
 #include <climits>
 
 #include "fmm_internal.h"
+#include "kernels_common.h"
 #include "p2p_common.h"
 
 namespace fmm {
@@ -44,13 +47,12 @@ struct Src32 {
 __device__ __forceinline__ void pair64(double xi, double yi, const Src64& s, double& ar, double& ai)
 {
     double dx = xi - s.x, dy = yi - s.y;
-    double r2 = fma(dx, dx, dy * dy);
+    double r2 = fma(dx, dx, fma(dy, dy, DBL_MIN));
     double y = __builtin_amdgcn_rcp(r2);
     double e = fma(-r2, y, 1.0);
     y = fma(y, e, y);
     e = fma(-r2, y, 1.0);
     y = fma(y, e, y);
-    y = fmin(y, DBL_MAX);
     double a = fma(s.mr, dx, s.mi * dy);
     double b = fma(s.mi, dx, -(s.mr * dy));
     ar = fma(a, y, ar);
@@ -61,8 +63,8 @@ __device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, c
 {
     float dx = (xh - s.xh) + (xl - s.xl);
     float dy = (yh - s.yh) + (yl - s.yl);
-    float r2 = fmaf(dx, dx, dy * dy);
-    float y = fminf(__builtin_amdgcn_rcpf(r2), FLT_MAX);
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
+    float y = __builtin_amdgcn_rcpf(r2);
     float a = fmaf(s.mr, dx, s.mi * dy);
     float b = fmaf(s.mi, dx, -(s.mr * dy));
     ar = fmaf(a, y, ar);
@@ -125,7 +127,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int xi_ = blockIdx.x * 4 + w;
+    const int xi_ = xcd_block() * 4 + w;
     if (xi_ >= nx) return;
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
@@ -193,7 +195,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int xi_ = blockIdx.x * 4 + w;
+    const int xi_ = xcd_block() * 4 + w;
     if (xi_ >= nx) return;
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
