@@ -263,7 +263,7 @@ __device__ __forceinline__ void box_geometry(double x0, double x1, double y0, do
 // Every segment's bounding box is kept as kKeyCopies copies of four order
 // keys (xmin, xmax, ymin, ymax) so that the workgroups updating it with
 // atomics spread over several addresses; readers combine the copies.
-constexpr int kKeyCopies = 8;
+constexpr int kKeyCopies = 32;
 constexpr int kKeyWords = 4 * kKeyCopies;
 
 __device__ __forceinline__ void read_keys(const uint64_t* k, double* bb)
@@ -276,15 +276,38 @@ __device__ __forceinline__ void read_keys(const uint64_t* k, double* bb)
     bb[0] = okey_inv(a); bb[1] = okey_inv(b); bb[2] = okey_inv(c); bb[3] = okey_inv(d);
 }
 
+// read_keys for a whole workgroup: lane c of wave 0 reads copy c and the
+// wave combines them; every thread receives the result (one barrier)
+__device__ __forceinline__ void block_read_keys(const uint64_t* k, double* bb)
+{
+    __shared__ uint64_t sk[4];
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x & (kKeyCopies - 1);
+        uint64_t a = k[4 * c], b = k[4 * c + 1], d = k[4 * c + 2], e = k[4 * c + 3];
+#pragma unroll
+        for (int o = kKeyCopies / 2; o > 0; o >>= 1) {
+            const uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
+            const uint64_t d2 = __shfl_xor(d, o, 64), e2 = __shfl_xor(e, o, 64);
+            a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
+            d = d2 < d ? d2 : d; e = e2 > e ? e2 : e;
+        }
+        if (threadIdx.x == 0) { sk[0] = a; sk[1] = b; sk[2] = d; sk[3] = e; }
+    }
+    __syncthreads();
+    bb[0] = okey_inv(sk[0]); bb[1] = okey_inv(sk[1]); bb[2] = okey_inv(sk[2]); bb[3] = okey_inv(sk[3]);
+}
+
 struct Bucketer {
     double lo, scale;
     int axis;
 };
 
+// the bucketer of a segment, computed by the whole workgroup (every thread
+// of the block calls it, once per kernel)
 __device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys)
 {
     double bbx[4];
-    read_keys(keys, bbx);
+    block_read_keys(keys, bbx);
     double x0 = bbx[0], x1 = bbx[1], y0 = bbx[2], y1 = bbx[3];
     double w = (x1 - x0), h = (y1 - y0);
     Bucketer b;
@@ -343,16 +366,12 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
-// bounding-box keys: kxmin kxmax kymin kymax
-__global__ void k_fill_keys(uint64_t* k, int64_t nseg)
+// bounding-box keys (every copy): kxmin kxmax kymin kymax = empty box
+__global__ void k_fill_keys(uint64_t* k, int64_t nwords)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int c = 0; c < kKeyCopies; ++c) {
-            uint64_t* q = k + kKeyWords * i + 4 * c;
-            q[0] = ~0ull; q[1] = 0ull; q[2] = ~0ull; q[3] = 0ull;
-        }
-    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x)
+        k[i] = (i & 1) ? 0ull : ~0ull;
 }
 
 __device__ __forceinline__ void block_minmax_atomic(double x0, double x1, double y0, double y1,
@@ -1075,13 +1094,17 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
     __shared__ uint16_t LX[kLdsCap], LY[kLdsCap];
     __shared__ int sh[2 * (kLdsThreads / 64)];
     __shared__ double red[2 * (kLdsThreads / 64)];
+    __shared__ double xs[kLdsCap], ys[kLdsCap];   // coordinates by local id
     LdsWork w = work[blockIdx.x];
-    const double* xs = (w.stage0 & 1) ? XB : XA;
-    const double* ys = (w.stage0 & 1) ? YB : YA;
-    const int32_t* is = (w.stage0 & 1) ? IB : IA;
-    xs += w.start; ys += w.start; is += w.start;
+    const double* xg = ((w.stage0 & 1) ? XB : XA) + w.start;
+    const double* yg = ((w.stage0 & 1) ? YB : YA) + w.start;
+    const int32_t* is = ((w.stage0 & 1) ? IB : IA) + w.start;
     int n = w.count;
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) idxs[i] = (uint32_t)is[i];
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+        idxs[i] = (uint32_t)is[i];
+        xs[i] = xg[i];
+        ys[i] = yg[i];
+    }
     __syncthreads();
     lds_order(U, xs, idxs, n, LX, sh, red);
     lds_order(U, ys, idxs, n, LY, sh, red);
@@ -1235,7 +1258,7 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     FMM_HIP(hipMemcpyAsync(poff.p, sc.off.data(), sizeof(int64_t) * (sc.nprob + 1), hipMemcpyHostToDevice, s));
 
     k_fill_u32<<<grid_for(nwords, 256), 256, 0, s>>>(words.p, nwords, 0u);
-    k_fill_keys<<<grid_for(nkeys, 256), 256, 0, s>>>(keys.p, nkeys);
+    k_fill_keys<<<grid_for(kKeyWords * nkeys, 256), 256, 0, s>>>(keys.p, kKeyWords * nkeys);
     check_launch("fill");
     uint32_t* W = words.p;
     // init: every problem's root segment is stage-0 key segment b

@@ -70,6 +70,16 @@ def test_tree_exact_select_fallback(orc, F):
     same_tree(orc, F, x + 1j * y, 5)
 
 
+def test_tree_many_tied_coordinates(orc, F):
+    # 64 distinct x values with 200 points each: every x split meets runs of
+    # tied coordinates, ordered by input index
+    rng = np.random.default_rng(13)
+    x = np.repeat(np.arange(64) / 64.0, 200)
+    rng.shuffle(x)
+    z = x + 1j * rng.random(x.size)
+    same_tree(orc, F, z, 5)
+
+
 @pytest.mark.parametrize("n,L,p", [(10000, 5, 17), (10007, 4, 12), (50000, 6, 16), (4096, 6, 20)])
 def test_fp64_fmm_matches_oracle_fmm(orc, F, n, L, p):
     z, m, _ = W.uniform(n, seed=n + 1)
