@@ -114,8 +114,9 @@ typedef struct {
  * (coordinate, input index) in the first half.  Box geometry: tight bounding
  * box, centre at its midpoint, radius = half its diagonal.  The tree copies
  * the positions: z may be freed once the stream has passed this call.
- * Non-finite positions give FMM_EINVAL (detected on the device; the call
- * synchronises `stream` once to read the flag).
+ * The call does not wait for the device.  Non-finite positions are detected
+ * on the device: the next fmm_plan or fmm_tree_download on this tree then
+ * returns FMM_EINVAL ("non-finite position") without creating anything.
  */
 int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int* n_levels,
                    void* stream, fmm_tree_t* out);

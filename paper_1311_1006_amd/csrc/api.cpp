@@ -410,7 +410,10 @@ int fmm_tree_download(fmm_tree_t t, int prob, int64_t* perm, int64_t* range, dou
         FMM_HIP(hipMemcpyAsync(pm.data(), t->t.perm.p + o, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
         FMM_HIP(hipMemcpyAsync(bb.data(), t->t.bbox.p + 4 * b0, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
         FMM_HIP(hipMemcpyAsync(gm.data(), t->t.geom.p + 4 * b0, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+        uint32_t err = 0;
+        FMM_HIP(hipMemcpyAsync(&err, t->t.err.p, sizeof(err), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
+        if (err) throw Error(FMM_EINVAL, "non-finite position");
         if (perm)
             for (int64_t i = 0; i < n; ++i) perm[i] = pm[i] - o;
         if (range)

@@ -167,6 +167,7 @@ struct Tree {
     // per box (global id)
     DBuf<double> bbox;        // [nbox][4] xmin xmax ymin ymax
     DBuf<double> geom;        // [nbox][4] cx cy r rs (rs = scaling radius)
+    DBuf<uint32_t> err;       // nonzero when a position is not finite (set by the build)
     double t_build_us = 0;
 };
 

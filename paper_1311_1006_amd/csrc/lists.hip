@@ -349,9 +349,18 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
     }
 }
 
-__global__ void k_totals_init(long long* totals)
+// totals cleared; the tree's error word (non-finite positions) becomes flag 16
+__global__ void k_totals_init(long long* totals, const uint32_t* tree_err)
 {
-    if (threadIdx.x == 0) { totals[0] = 0; totals[1] = 0; totals[2] = 0; totals[3] = 0; }
+    if (threadIdx.x == 0) {
+        totals[0] = 0; totals[1] = 0; totals[3] = 0;
+        totals[2] = *tree_err ? 16 : 0;
+    }
+}
+
+static void check_tree_flag(long long flag)
+{
+    if (flag & 16) throw Error(FMM_EINVAL, "non-finite position");
 }
 
 // Level ranges of the passes: the deepest level alone, the two above it
@@ -373,7 +382,7 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const PlanExtra& ex = *pl.ex;
-    k_totals_init<<<1, 64, 0, s>>>(totals);
+    k_totals_init<<<1, 64, 0, s>>>(totals, t.err.p);
     for (auto [l0, l1] : traversal_passes(sc.max_levels)) {
         TravCtx c;
         c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
@@ -433,7 +442,7 @@ static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const PlanExtra& ex = *pl.ex;
-    k_totals_init<<<1, 64, 0, s>>>(totals);
+    k_totals_init<<<1, 64, 0, s>>>(totals, t.err.p);
     for (auto [l0, l1] : traversal_passes(sc.max_levels)) {
         TravCtx c;
         c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
@@ -473,7 +482,7 @@ void list_totals_device(Plan& pl, hipStream_t s)
     TreeSchedule& sc = *pl.tree->sched;
     DBuf<long long> totals;
     totals.alloc(4, s);
-    k_totals_init<<<1, 64, 0, s>>>(totals.p);
+    k_totals_init<<<1, 64, 0, s>>>(totals.p, pl.tree->err.p);
     k_sum_counts<<<(unsigned)((sc.nbox + 1023) / 1024), 1024, 0, s>>>(sc.nbox, pl.s_cnt.p, pl.w_cnt.p, totals.p);
     const int nl = (int)sc.nleaf;
     k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
@@ -511,6 +520,7 @@ void build_lists_device(Plan& pl, hipStream_t s)
         long long flag = 0;
         FMM_HIP(hipMemcpyAsync(&flag, totals.p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
+        check_tree_flag(flag);
         if ((flag & 3) == 0) {
             pl.totals_known = false;    // list sizes and pair counts are summed on request
             pl.split_p2p = (flag & 4) != 0;
@@ -535,6 +545,7 @@ void build_lists_device(Plan& pl, hipStream_t s)
             long long h[4];
             FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
             FMM_HIP(hipStreamSynchronize(s));
+            check_tree_flag(h[2]);
             if (h[2] & 2) {                 // a frontier overflowed
                 levelwise = true;
                 ex.levelwise_only = true;
@@ -584,6 +595,7 @@ void build_lists_device(Plan& pl, hipStream_t s)
         long long h[4];
         FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
+        check_tree_flag(h[2]);
         pl.n_strong = h[0];
         pl.n_weak = h[1];
         pl.n_p2p_pairs = h[3];

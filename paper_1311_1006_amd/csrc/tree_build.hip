@@ -366,9 +366,11 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
-// bounding-box keys (every copy): kxmin kxmax kymin kymax = empty box
-__global__ void k_fill_keys(uint64_t* k, int64_t nwords)
+// bounding-box keys (every copy): kxmin kxmax kymin kymax = empty box; the
+// tree's error word cleared
+__global__ void k_fill_keys(uint64_t* k, int64_t nwords, uint32_t* err)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
          i += (int64_t)gridDim.x * blockDim.x)
         k[i] = (i & 1) ? 0ull : ~0ull;
@@ -1258,14 +1260,14 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     FMM_HIP(hipMemcpyAsync(poff.p, sc.off.data(), sizeof(int64_t) * (sc.nprob + 1), hipMemcpyHostToDevice, s));
 
     k_fill_u32<<<grid_for(nwords, 256), 256, 0, s>>>(words.p, nwords, 0u);
-    k_fill_keys<<<grid_for(kKeyWords * nkeys, 256), 256, 0, s>>>(keys.p, kKeyWords * nkeys);
+    k_fill_keys<<<grid_for(kKeyWords * nkeys, 256), 256, 0, s>>>(keys.p, kKeyWords * nkeys, t.err.p);
     check_launch("fill");
     uint32_t* W = words.p;
     // init: every problem's root segment is stage-0 key segment b
     int64_t maxn = 0;
     for (int b = 0; b < sc.nprob; ++b) maxn = std::max(maxn, sc.off[b + 1] - sc.off[b]);
     dim3 gi((unsigned)((maxn + kTile - 1) / kTile), (unsigned)sc.nprob);
-    k_init<<<gi, kTileThreads, 0, s>>>(z, poff.p, sc.nprob, XA.p, YA.p, IA.p, keys.p, W + o_err);
+    k_init<<<gi, kTileThreads, 0, s>>>(z, poff.p, sc.nprob, XA.p, YA.p, IA.p, keys.p, t.err.p);
     check_launch("init");
     double* Xb[2] = {XA.p, XB.p};
     double* Yb[2] = {YA.p, YB.p};
@@ -1304,11 +1306,7 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     }
     k_scaling_radius<<<grid_for(sc.nbox, 256), 256, 0, s>>>(sc.nbox, sc.d_box_parent.p, t.geom.p);
     check_launch("scaling radius");
-    // non-finite positions: read the flag (one synchronisation)
-    uint32_t err = 0;
-    FMM_HIP(hipMemcpyAsync(&err, W + o_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    FMM_HIP(hipStreamSynchronize(s));
-    if (err) throw Error(FMM_EINVAL, "non-finite position");
+    // non-finite positions: t.err, read at the next synchronising call on the tree
 }
 
 void build_tree_device(Tree& t, const double* z, hipStream_t s)
@@ -1317,6 +1315,7 @@ void build_tree_device(Tree& t, const double* z, hipStream_t s)
     const int64_t n = sc.n;
     t.x.alloc(n, s); t.y.alloc(n, s); t.perm.alloc(n, s);
     t.bbox.alloc(4 * sc.nbox, s); t.geom.alloc(4 * sc.nbox, s);
+    t.err.alloc(1, s);
     build_tree_select(t, z, s);
 }
 

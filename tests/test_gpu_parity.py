@@ -175,8 +175,11 @@ def test_invalid_arguments_raise(F):
         F.build_tree(dev(z), 5)           # 256 leaves > 100 points
     bad = z.copy()
     bad[3] = np.nan
+    # the build does not wait for the device: the next call on the tree reports it
     with pytest.raises(F.FmmError):
-        F.build_tree(dev(bad), 2)
+        F.plan(F.build_tree(dev(bad), 2), 8, 0.5)
+    with pytest.raises(F.FmmError):
+        F.build_tree(dev(bad), 2).download(0)
     tree = F.build_tree(dev(z), 2)
     for p, th in ((0, 0.5), (33, 0.5), (10, 0.0), (10, 1.0)):
         with pytest.raises(F.FmmError):
