@@ -437,6 +437,110 @@ static void grow_capacities(Plan& pl, hipStream_t s)
     ex.cap_weak = std::max<int>(ex.cap_weak, (int)((h[1] + 31) / 32 * 32));
 }
 
+// The one-pass build of a single level l >= 1 (the pass of the finest
+// level): one wavefront per group of four siblings.  The parent's strong list
+// is loaded once, every candidate (a child of an entry) is loaded once and
+// tested against the four siblings; each sibling's strong and weak lists are
+// compacted by ballots in candidate order, as in k_traverse<2>.
+__global__ void __launch_bounds__(256)
+k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
+               int32_t* w_ids, int64_t cap_s, long long* totals)
+{
+    __shared__ int32_t front_all[4][kFrontCap];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = (blockIdx.x * 4 + wv) * 4;
+    if (i >= c.n) return;
+    int32_t* fa = front_all[wv];
+    const int64_t g0 = c.boxes[i];                    // first of four siblings
+    const int L = c.level[g0];
+    const int64_t pb = c.pbox[c.prob[g0]];
+    const int64_t jl = g0 - pb - level_base(L);
+    bool overflow = false, cap_overflow = false;
+    const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
+    const int64_t ab = s_beg[a0];
+    int nf = s_cnt[a0];
+    if (nf > c.cs) { cap_overflow = true; nf = c.cs; }
+    if (nf > kFrontCap) { overflow = true; nf = kFrontCap; }
+    for (int e = lane; e < nf; e += 64) fa[e] = (ab + e < cap_s) ? s_ids[ab + e] : (int32_t)pb;
+    wave_sync_l();
+    double gx[4], gy[4], gr[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double* gg = c.geom + 4 * (g0 + t);
+        gx[t] = gg[0]; gy[t] = gg[1]; gr[t] = gg[2];
+    }
+    const int64_t lb = level_base(L), lbp = level_base(L - 1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
+    long long src[4] = {0, 0, 0, 0};
+    const int ncand = 4 * nf;
+    for (int c0 = 0; c0 < ncand; c0 += 64) {
+        const int idx = c0 + lane;
+        bool valid = idx < ncand;
+        int32_t cc = 0;
+        double cg[4] = {0.0, 0.0, 0.0, 0.0};
+        long long cnt = 0;
+        if (valid) {
+            const int32_t q = fa[idx >> 2];
+            const int64_t qj = (int64_t)q - pb - lbp;
+            if (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1)))) {
+                valid = false;                          // not a box of that level: never
+                overflow = true;                        // dereferenced, list rebuilt
+            } else {
+                cc = (int32_t)(pb + lb + 4 * qj + (idx & 3));
+                const double* gc = c.geom + 4 * (int64_t)cc;
+                cg[0] = gc[0]; cg[1] = gc[1]; cg[2] = gc[2];
+                cnt = c.box_count[cc];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
+            const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
+            const bool strong = valid && !weak;
+            const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
+            const int64_t sb = (g0 + t) * c.cs, wb = (g0 + t) * c.cw;
+            if (strong) {
+                const int o = ns[t] + __popcll(bs & below);
+                if (o < c.cs) s_ids[sb + o] = cc;
+                src[t] += cnt;
+            }
+            if (weak) {
+                const int o = nw[t] + __popcll(bw & below);
+                if (o < c.cw) w_ids[wb + o] = cc;
+            }
+            ns[t] += __popcll(bs);
+            nw[t] += __popcll(bw);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) src[t] += __shfl_xor(src[t], o, 64);
+    cap_overflow = __ballot(cap_overflow) != 0ull;
+    overflow = __ballot(overflow) != 0ull;
+    if (lane == 0) {
+        unsigned long long fl = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t g = g0 + t;
+            s_cnt[g] = ns[t];
+            w_cnt[g] = nw[t];
+            s_beg[g] = (int32_t)(g * c.cs);
+            w_beg[g] = (int32_t)(g * c.cw);
+            if (ns[t] > c.cs || nw[t] > c.cw) cap_overflow = true;
+            if (nw[t] > kChunkPairs) fl |= 8ull;
+            if (c.child0[g] < 0) {                      // a leaf: its near-field source count
+                c.nsrc[g] = (int32_t)(src[t] < INT32_MAX ? src[t] : INT32_MAX);
+                if (src[t] > kChunkSrc) fl |= 4ull;
+            }
+        }
+        if (cap_overflow) fl |= 1ull;
+        if (overflow) fl |= 2ull;
+        if (fl) atomicOr((unsigned long long*)&totals[2], fl);
+    }
+}
+
 static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const int64_t* pbox)
 {
     Tree& t = *pl.tree;
@@ -454,9 +558,18 @@ static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
         c.child0 = ex.child0.p; c.box_count = sc.d_box_count.p; c.nsrc = pl.nsrc.p;
-        k_traverse<2><<<(unsigned)((c.n + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p,
-                                                                pl.s_ids.p, pl.w_ids.p, (int64_t)pl.s_ids.n,
-                                                                (int64_t)pl.w_ids.n, totals);
+        if (l0 == l1 && l0 >= 1) {
+            // one level: sibling groups (the level's box list is four-aligned)
+            const int groups = c.n / 4;
+            k_traverse_sib<<<(unsigned)((groups + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
+                                                                       pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
+                                                                       (int64_t)pl.s_ids.n, totals);
+        } else {
+            k_traverse<2><<<(unsigned)((c.n + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
+                                                                    pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
+                                                                    (int64_t)pl.s_ids.n, (int64_t)pl.w_ids.n,
+                                                                    totals);
+        }
         check_launch("one-pass lists");
     }
 }
