@@ -115,8 +115,9 @@ typedef struct {
  * box, centre at its midpoint, radius = half its diagonal.  The tree copies
  * the positions: z may be freed once the stream has passed this call.
  * The call does not wait for the device.  Non-finite positions are detected
- * on the device: the next fmm_plan or fmm_tree_download on this tree then
- * returns FMM_EINVAL ("non-finite position") without creating anything.
+ * on the device: fmm_tree_download on this tree, and the first call that
+ * needs the lists of a plan on it (see fmm_plan), then return FMM_EINVAL
+ * ("non-finite position").
  */
 int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int* n_levels,
                    void* stream, fmm_tree_t* out);
@@ -143,8 +144,14 @@ void fmm_tree_destroy(fmm_tree_t t);
  *   theta      0 < theta < 1.
  *   precision  FMM_FP64 or FMM_MIXED.
  *   tune       HOST, optional (NULL = automatic).
- * The plan references the tree, which must outlive it.  Synchronises
- * `stream` once (to size the lists).
+ * The plan references the tree, which must outlive it.  The call does not
+ * wait for the device: the list build is enqueued on `stream`, and the first
+ * call that needs the lists (fmm_evaluate, fmm_evaluate_parts,
+ * fmm_evaluate_adjoint, fmm_plan_stats, fmm_plan_list_size,
+ * fmm_plan_download_list) reads its flags (one synchronisation of `stream`)
+ * and, rarely, rebuilds the lists with larger pools.  An error found there
+ * (non-finite positions in the tree: FMM_EINVAL) is returned by that call
+ * and by every later call on the plan.
  */
 int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning* tune,
              void* stream, fmm_plan_t* out);

@@ -258,12 +258,38 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
             }
             pl.ex = pl.ex_ref.get();
         }
-        build_lists_device(pl, s);
-        plan_balance(pl, s);
+        // the lists are enqueued; their flags are read by the first call
+        // that needs them (plan_finalize), so the host returns meanwhile
+        build_lists_begin(pl, s);
         alloc_eval_buffers(pl, s);
         *out = pp.release();
     });
 }
+
+}  // extern "C"
+
+namespace fmm {
+// Finish a plan's list build (flags, fallbacks) and its work balancing, once.
+// An error of this deferred part is kept and repeated by every later call.
+void plan_finalize(Plan& P)
+{
+    if (P.finalized) return;
+    if (P.final_code) throw Error(P.final_code, P.final_msg);
+    try {
+        build_lists_finish(P);
+        plan_balance(P, P.list_stream);
+    } catch (const Error& e) {
+        P.final_code = e.code;
+        P.final_msg = e.what();
+        throw;
+    }
+    P.lt_totals.release();
+    P.lt_pbox.release();
+    P.finalized = true;
+}
+}  // namespace fmm
+
+extern "C" {
 
 void fmm_plan_destroy(fmm_plan_t pl)
 {
@@ -290,6 +316,7 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         Plan& P = pl->pl;
+        plan_finalize(P);
         if (P.tune.flags & FMM_FLAG_GRAPH) {
             // capture and replay on a plan-owned stream (the legacy null stream
             // cannot be captured), ordered after the caller's stream by events
@@ -339,6 +366,7 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
     return guarded([&] {
         FMM_REQUIRE(pl && m, "NULL argument");
         check_device_state();
+        plan_finalize(pl->pl);
         evaluate_device(pl->pl, m, nullptr, phi_near, phi_far, (hipStream_t)stream);
         pl->pl.last_m = m;
     });
@@ -351,6 +379,7 @@ int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, do
         FMM_REQUIRE(pl && m && g_phi, "NULL argument");
         if (!pl->pl.have_forward) throw Error(FMM_ESTATE, "fmm_evaluate_adjoint needs a preceding fmm_evaluate");
         check_device_state();
+        plan_finalize(pl->pl);
         adjoint_device(pl->pl, m, g_phi, g_m, g_z, (hipStream_t)stream);
     });
 }
@@ -361,6 +390,7 @@ int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st)
         FMM_REQUIRE(pl && st, "NULL argument");
         Plan& P = pl->pl;
         TreeSchedule& sc = *P.tree->sched;
+        plan_finalize(P);
         list_totals_device(P, P.list_stream);
         std::memset(st, 0, sizeof(*st));
         st->n_points = sc.n;
@@ -468,6 +498,7 @@ int fmm_plan_list_size(fmm_plan_t pl, int prob, int level, int kind, int64_t* n_
 {
     return guarded([&] {
         FMM_REQUIRE(pl && n_entries, "NULL argument");
+        plan_finalize(pl->pl);
         std::vector<int32_t> b, c, ids;
         list_host(pl, prob, level, kind, b, c, ids, nullptr);
         *n_entries = (int64_t)ids.size();
@@ -479,6 +510,7 @@ int fmm_plan_download_list(fmm_plan_t pl, int prob, int level, int kind, int64_t
 {
     return guarded([&] {
         FMM_REQUIRE(pl, "NULL plan");
+        plan_finalize(pl->pl);
         std::vector<int32_t> b, c, id;
         list_host(pl, prob, level, kind, b, c, id, (hipStream_t)stream);
         TreeSchedule& sc = *pl->pl.tree->sched;

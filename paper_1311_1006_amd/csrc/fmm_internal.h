@@ -187,6 +187,13 @@ struct Plan {
     int64_t n_p2p_pairs = 0;
     bool totals_known = false;     // n_strong, n_weak, n_p2p_pairs summed
     hipStream_t list_stream = nullptr;
+    // list build enqueued by fmm_plan and finished by the first call that
+    // needs the lists (see plan_finalize)
+    bool lists_pending = false, lists_direct = false, finalized = false;
+    int final_code = 0;            // an error of the deferred part, repeated by later calls
+    std::string final_msg;
+    DBuf<long long> lt_totals;     // list totals and flags of the pending build
+    DBuf<int64_t> lt_pbox;
     bool split_p2p = false, split_m2l = false;   // some list may need work chunks
     // evaluation buffers
     DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
@@ -233,6 +240,9 @@ struct Plan {
 void build_tree_device(Tree& t, const double* z, hipStream_t s);
 void update_positions_device(Tree& t, const double* z, hipStream_t s);
 void build_lists_device(Plan& pl, hipStream_t s);
+void build_lists_begin(Plan& pl, hipStream_t s);
+void build_lists_finish(Plan& pl);
+void plan_finalize(Plan& pl);
 void plan_balance(Plan& pl, hipStream_t s);
 void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,

@@ -610,28 +610,46 @@ void list_totals_device(Plan& pl, hipStream_t s)
     pl.totals_known = true;
 }
 
-void build_lists_device(Plan& pl, hipStream_t s)
+// Enqueue the list build without waiting: the one-pass build when the
+// capacities allow it.  build_lists_finish reads its flags (one
+// synchronisation) and runs the compact or level-wise build if needed.
+void build_lists_begin(Plan& pl, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     int64_t nb = sc.nbox;
     pl.s_beg.alloc(nb, s); pl.s_cnt.alloc(nb, s); pl.w_beg.alloc(nb, s); pl.w_cnt.alloc(nb, s);
-    DBuf<int64_t> pbox; pbox.alloc(sc.nprob, s);
-    FMM_HIP(hipMemcpyAsync(pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
-    DBuf<long long> totals; totals.alloc(4, s);
-    DBuf<long long> snap; snap.alloc(2, s);
-    DBuf<long long> bsum; bsum.alloc(2 * ((nb + 1023) / 1024), s);
+    pl.lt_pbox.alloc(sc.nprob, s);
+    FMM_HIP(hipMemcpyAsync(pl.lt_pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
+    pl.lt_totals.alloc(4, s);
     pl.list_stream = s;
     PlanExtra& ex = *pl.ex;
     if (ex.cap_strong == 0) { ex.cap_strong = kCapStrong; ex.cap_weak = kCapWeak; }
-    bool grow = false;
-    if (nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only) {
+    pl.lists_direct = nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only;
+    if (pl.lists_direct) {
         pl.s_ids.alloc(nb * ex.cap_strong, s);
         pl.w_ids.alloc(nb * ex.cap_weak, s);
         pl.nsrc.alloc(nb, s);
-        build_lists_direct(pl, s, totals.p, pbox.p);
+        build_lists_direct(pl, s, pl.lt_totals.p, pl.lt_pbox.p);
+    }
+    pl.lists_pending = true;
+}
+
+void build_lists_finish(Plan& pl)
+{
+    if (!pl.lists_pending) return;
+    pl.lists_pending = false;
+    hipStream_t s = pl.list_stream;
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    int64_t nb = sc.nbox;
+    long long* totals_p = pl.lt_totals.p;
+    const int64_t* pbox_p = pl.lt_pbox.p;
+    PlanExtra& ex = *pl.ex;
+    bool grow = false;
+    if (pl.lists_direct) {
         long long flag = 0;
-        FMM_HIP(hipMemcpyAsync(&flag, totals.p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipMemcpyAsync(&flag, totals_p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
         check_tree_flag(flag);
         if ((flag & 3) == 0) {
@@ -643,6 +661,8 @@ void build_lists_device(Plan& pl, hipStream_t s)
         grow = (flag & 2) == 0;         // capacities too small, no frontier overflow
         if (flag & 2) ex.levelwise_only = true;
     }
+    DBuf<long long> snap; snap.alloc(2, s);
+    DBuf<long long> bsum; bsum.alloc(2 * ((nb + 1023) / 1024), s);
     int64_t cap_s = std::max<int64_t>(pl.n_strong, 24 * nb + 1024);
     int64_t cap_w = std::max<int64_t>(pl.n_weak, 64 * nb + 1024);
     bool levelwise = ex.levelwise_only;
@@ -650,13 +670,13 @@ void build_lists_device(Plan& pl, hipStream_t s)
         pl.s_ids.alloc(cap_s, s);
         pl.w_ids.alloc(cap_w, s);
         if (!levelwise) {
-            build_lists_traversal(pl, s, cap_s, cap_w, totals.p, pbox.p, bsum.p, snap.p);
+            build_lists_traversal(pl, s, cap_s, cap_w, totals_p, pbox_p, bsum.p, snap.p);
             int nl = (int)sc.nleaf;
             k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
-                                                         pl.s_cnt.p, pl.s_ids.p, totals.p, cap_s);
+                                                         pl.s_cnt.p, pl.s_ids.p, totals_p, cap_s);
             check_launch("count p2p");
             long long h[4];
-            FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
+            FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
             FMM_HIP(hipStreamSynchronize(s));
             check_tree_flag(h[2]);
             if (h[2] & 2) {                 // a frontier overflowed
@@ -680,33 +700,33 @@ void build_lists_device(Plan& pl, hipStream_t s)
         const int32_t* lv = pl.ex->d_level_boxes.p;
         int nroot = (int)pl.ex->level_boxes[0].size();
         k_root_lists<<<(nroot + 255) / 256, 256, 0, s>>>(lv, nroot, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
-                                                         pl.w_cnt.p, pl.s_ids.p, totals.p);
+                                                         pl.w_cnt.p, pl.s_ids.p, totals_p);
         check_launch("root lists");
         for (int l = 1; l < sc.max_levels; ++l) {
             LevelCtx c;
             c.boxes = lv + pl.ex->level_boxes_off[l];
             c.n = (int)pl.ex->level_boxes[l].size();
             if (c.n == 0) continue;
-            c.parent = sc.d_box_parent.p; c.prob = sc.d_box_prob.p; c.pbox = pbox.p;
+            c.parent = sc.d_box_parent.p; c.prob = sc.d_box_prob.p; c.pbox = pbox_p;
             c.lb = level_base(l); c.lbp = level_base(l - 1);
             c.geom = t.geom.p; c.theta = pl.theta;
             int g = (c.n + 3) / 4;
             k_level<false><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                              pl.w_ids.p, cap_s, cap_w);
             int nb = (c.n + 1023) / 1024;
-            k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, totals.p, snap.p);
+            k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, totals_p, snap.p);
             k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, snap.p, pl.s_beg.p,
-                                             pl.w_beg.p, totals.p, cap_s, cap_w);
+                                             pl.w_beg.p, totals_p, cap_s, cap_w);
             k_level<true><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                             pl.w_ids.p, cap_s, cap_w);
             check_launch("level lists");
         }
         int nl = (int)sc.nleaf;
         k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
-                                                     pl.s_cnt.p, pl.s_ids.p, totals.p, cap_s);
+                                                     pl.s_cnt.p, pl.s_ids.p, totals_p, cap_s);
         check_launch("count p2p");
         long long h[4];
-        FMM_HIP(hipMemcpyAsync(h, totals.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
         check_tree_flag(h[2]);
         pl.n_strong = h[0];
@@ -721,6 +741,12 @@ void build_lists_device(Plan& pl, hipStream_t s)
         cap_w = h[1] + h[1] / 4 + 1024;
     }
     throw Error(FMM_EDEVICE, "connectivity lists did not fit after growing the pools");
+}
+
+void build_lists_device(Plan& pl, hipStream_t s)
+{
+    build_lists_begin(pl, s);
+    build_lists_finish(pl);
 }
 
 }  // namespace fmm

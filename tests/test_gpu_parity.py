@@ -175,9 +175,13 @@ def test_invalid_arguments_raise(F):
         F.build_tree(dev(z), 5)           # 256 leaves > 100 points
     bad = z.copy()
     bad[3] = np.nan
-    # the build does not wait for the device: the next call on the tree reports it
+    # neither the build nor the plan waits for the device: the first call
+    # that needs the lists reports it, and so does every later call
+    pl = F.plan(F.build_tree(dev(bad), 2), 8, 0.5)
     with pytest.raises(F.FmmError):
-        F.plan(F.build_tree(dev(bad), 2), 8, 0.5)
+        F.evaluate(pl, dev(m))
+    with pytest.raises(F.FmmError):
+        pl.stats()
     with pytest.raises(F.FmmError):
         F.build_tree(dev(bad), 2).download(0)
     tree = F.build_tree(dev(z), 2)
