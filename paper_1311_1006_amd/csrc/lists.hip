@@ -178,22 +178,33 @@ __global__ void k_root_lists(const int32_t* roots, int n, int32_t* s_beg, int32_
     if (i == 0) { totals[0] = n; totals[1] = 0; totals[2] = 0; totals[3] = 0; }
 }
 
-// pairs of the near field: sum over leaves of n_T * (points of its strong list)
-__global__ void k_count_p2p(const int32_t* leaves, int n, const int32_t* box_count, const int32_t* s_beg,
-                            const int32_t* s_cnt, const int32_t* s_ids, long long* totals, int64_t cap_s)
+// pairs of the near field: sum over leaves of n_T * (points of its strong
+// list); one wavefront per leaf, lanes over the list
+__global__ void __launch_bounds__(256)
+k_count_p2p(const int32_t* leaves, int n, const int32_t* box_count, const int32_t* s_beg, const int32_t* s_cnt,
+            const int32_t* s_ids, long long* totals, int64_t cap_s)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    long long v = 0;
-    if (i < n) {
-        int32_t g = leaves[i];
-        long long src = 0;
-        for (int e = 0; e < s_cnt[g] && (int64_t)s_beg[g] + e < cap_s; ++e)
-            src += box_count[s_ids[s_beg[g] + e]];
-        v = src * box_count[g];
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int32_t g = leaves[i];
+    const int64_t b0 = s_beg[g];
+    const int cnt = s_cnt[g];
+    long long src = 0;
+    for (int e0 = lane; e0 < cnt; e0 += 256) {
+        int32_t id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 64 * u;
+            id[u] = (e < cnt && b0 + e < cap_s) ? s_ids[b0 + e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (id[u] >= 0) src += box_count[id[u]];
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long*)&totals[3], (unsigned long long)v);
+    for (int o = 32; o > 0; o >>= 1) src += __shfl_xor(src, o, 64);
+    if (lane == 0 && src) atomicAdd((unsigned long long*)&totals[3], (unsigned long long)(src * box_count[g]));
 }
 
 // ----------------------------------------------------------------------------
@@ -376,6 +387,118 @@ static std::vector<std::pair<int, int>> traversal_passes(int levels)
     return r;
 }
 
+// A single level l >= 1 (the pass of the finest level), one wavefront per
+// group of four siblings: every candidate (a child of an entry of the
+// parent's strong list, read from the pool, so the list may have any length)
+// is loaded once and tested against the four siblings; each sibling's strong
+// and weak lists are compacted by ballots in candidate order, as in
+// k_traverse.  MODE 0 counts, MODE 1 fills at the scanned offsets, MODE 2
+// fills at fixed per-box capacities and also counts each leaf's near-field
+// sources and raises the chunk flags.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
+               int32_t* w_ids, int64_t cap_s, int64_t cap_w, long long* totals)
+{
+    constexpr bool FILL = MODE != 0;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = (blockIdx.x * 4 + wv) * 4;
+    if (i >= c.n) return;
+    const int64_t g0 = c.boxes[i];                    // first of four siblings
+    const int L = c.level[g0];
+    const int64_t pb = c.pbox[c.prob[g0]];
+    const int64_t jl = g0 - pb - level_base(L);
+    bool overflow = false, cap_overflow = false;
+    const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
+    const int64_t ab = s_beg[a0];
+    int nf = s_cnt[a0];
+    if (MODE == 2 && nf > c.cs) { cap_overflow = true; nf = c.cs; }
+    double gx[4], gy[4], gr[4];
+    int64_t sb[4], wb[4], ls[4], lw[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t g = g0 + t;
+        const double* gg = c.geom + 4 * g;
+        gx[t] = gg[0]; gy[t] = gg[1]; gr[t] = gg[2];
+        sb[t] = 0; wb[t] = 0; ls[t] = cap_s; lw[t] = cap_w;
+        if (MODE == 1) { sb[t] = s_beg[g]; wb[t] = w_beg[g]; }
+        if (MODE == 2) { sb[t] = g * c.cs; wb[t] = g * c.cw; ls[t] = sb[t] + c.cs; lw[t] = wb[t] + c.cw; }
+    }
+    const int64_t lb = level_base(L), lbp = level_base(L - 1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
+    long long src[4] = {0, 0, 0, 0};
+    const int64_t ncand = 4 * (int64_t)nf;
+    for (int64_t c0 = 0; c0 < ncand; c0 += 64) {
+        const int64_t idx = c0 + lane;
+        bool valid = idx < ncand;
+        int32_t cc = 0;
+        double cg[4] = {0.0, 0.0, 0.0, 0.0};
+        long long cnt = 0;
+        if (valid) {
+            const int64_t e = ab + (idx >> 2);
+            const int32_t q = e < cap_s ? s_ids[e] : (int32_t)pb;
+            const int64_t qj = (int64_t)q - pb - lbp;
+            if (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1)))) {
+                valid = false;                          // not a box of that level: never
+                overflow = true;                        // dereferenced, list rebuilt
+            } else {
+                cc = (int32_t)(pb + lb + 4 * qj + (idx & 3));
+                const double* gc = c.geom + 4 * (int64_t)cc;
+                cg[0] = gc[0]; cg[1] = gc[1]; cg[2] = gc[2];
+                if (MODE == 2) cnt = c.box_count[cc];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
+            const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
+            const bool strong = valid && !weak;
+            const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
+            if (FILL && strong) {
+                const int64_t o = sb[t] + ns[t] + __popcll(bs & below);
+                if (o < ls[t]) s_ids[o] = cc;
+            }
+            if (FILL && weak) {
+                const int64_t o = wb[t] + nw[t] + __popcll(bw & below);
+                if (o < lw[t]) w_ids[o] = cc;
+            }
+            if (MODE == 2 && strong) src[t] += cnt;
+            ns[t] += __popcll(bs);
+            nw[t] += __popcll(bw);
+        }
+    }
+    if (MODE == 2) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) src[t] += __shfl_xor(src[t], o, 64);
+    }
+    cap_overflow = __ballot(cap_overflow) != 0ull;
+    overflow = __ballot(overflow) != 0ull;
+    if (lane == 0) {
+        unsigned long long fl = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t g = g0 + t;
+            if (MODE != 1) { s_cnt[g] = ns[t]; w_cnt[g] = nw[t]; }
+            if (MODE == 2) {
+                s_beg[g] = (int32_t)sb[t];
+                w_beg[g] = (int32_t)wb[t];
+                if (ns[t] > c.cs || nw[t] > c.cw) cap_overflow = true;
+                if (nw[t] > kChunkPairs) fl |= 8ull;
+                if (c.child0[g] < 0) {                  // a leaf: its near-field source count
+                    c.nsrc[g] = (int32_t)(src[t] < INT32_MAX ? src[t] : INT32_MAX);
+                    if (src[t] > kChunkSrc) fl |= 4ull;
+                }
+            }
+        }
+        if (cap_overflow) fl |= 1ull;
+        if (overflow) fl |= 2ull;
+        if (fl) atomicOr((unsigned long long*)&totals[2], fl);
+    }
+}
+
 static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_t cap_w, long long* totals,
                                   const int64_t* pbox, long long* bsum, long long* snap)
 {
@@ -393,15 +516,24 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
         c.child0 = nullptr; c.box_count = nullptr; c.nsrc = nullptr;
-        const unsigned grid = (unsigned)((c.n + 3) / 4);
-        k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+        const bool sib = l0 == l1 && l0 >= 1;   // one level: sibling groups
+        const unsigned grid = (unsigned)((c.n + 3) / 4), sgrid = (unsigned)((c.n / 4 + 3) / 4);
+        if (sib)
+            k_traverse_sib<0><<<sgrid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                                    pl.w_ids.p, cap_s, cap_w, totals);
+        else
+            k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
         const int nb = (c.n + 1023) / 1024;
         k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, totals, snap);
         k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, snap, pl.s_beg.p,
                                          pl.w_beg.p, totals, cap_s, cap_w);
-        k_traverse<1><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
-                                              pl.w_ids.p, cap_s, cap_w, totals);
+        if (sib)
+            k_traverse_sib<1><<<sgrid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                                    pl.w_ids.p, cap_s, cap_w, totals);
+        else
+            k_traverse<1><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                               pl.w_ids.p, cap_s, cap_w, totals);
         check_launch("traversal lists");
     }
 }
@@ -410,6 +542,7 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
 // tree layout: they start at kCapStrong / kCapWeak and grow to the longest
 // lists seen when a build overflowed them).
 constexpr int kCapStrong = 96, kCapWeak = 224;
+constexpr int64_t kMaxPaddedPools = int64_t(1) << 30;   // bytes of the fixed-capacity id pools
 
 __global__ void __launch_bounds__(256)
 k_max_counts(int64_t n, const int32_t* s_cnt, const int32_t* w_cnt, unsigned int* out)
@@ -435,110 +568,10 @@ static void grow_capacities(Plan& pl, hipStream_t s)
     PlanExtra& ex = *pl.ex;
     ex.cap_strong = std::max<int>(ex.cap_strong, (int)((h[0] + 31) / 32 * 32));
     ex.cap_weak = std::max<int>(ex.cap_weak, (int)((h[1] + 31) / 32 * 32));
-}
-
-// The one-pass build of a single level l >= 1 (the pass of the finest
-// level): one wavefront per group of four siblings.  The parent's strong list
-// is loaded once, every candidate (a child of an entry) is loaded once and
-// tested against the four siblings; each sibling's strong and weak lists are
-// compacted by ballots in candidate order, as in k_traverse<2>.
-__global__ void __launch_bounds__(256)
-k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
-               int32_t* w_ids, int64_t cap_s, long long* totals)
-{
-    __shared__ int32_t front_all[4][kFrontCap];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = (blockIdx.x * 4 + wv) * 4;
-    if (i >= c.n) return;
-    int32_t* fa = front_all[wv];
-    const int64_t g0 = c.boxes[i];                    // first of four siblings
-    const int L = c.level[g0];
-    const int64_t pb = c.pbox[c.prob[g0]];
-    const int64_t jl = g0 - pb - level_base(L);
-    bool overflow = false, cap_overflow = false;
-    const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
-    const int64_t ab = s_beg[a0];
-    int nf = s_cnt[a0];
-    if (nf > c.cs) { cap_overflow = true; nf = c.cs; }
-    if (nf > kFrontCap) { overflow = true; nf = kFrontCap; }
-    for (int e = lane; e < nf; e += 64) fa[e] = (ab + e < cap_s) ? s_ids[ab + e] : (int32_t)pb;
-    wave_sync_l();
-    double gx[4], gy[4], gr[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const double* gg = c.geom + 4 * (g0 + t);
-        gx[t] = gg[0]; gy[t] = gg[1]; gr[t] = gg[2];
-    }
-    const int64_t lb = level_base(L), lbp = level_base(L - 1);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
-    long long src[4] = {0, 0, 0, 0};
-    const int ncand = 4 * nf;
-    for (int c0 = 0; c0 < ncand; c0 += 64) {
-        const int idx = c0 + lane;
-        bool valid = idx < ncand;
-        int32_t cc = 0;
-        double cg[4] = {0.0, 0.0, 0.0, 0.0};
-        long long cnt = 0;
-        if (valid) {
-            const int32_t q = fa[idx >> 2];
-            const int64_t qj = (int64_t)q - pb - lbp;
-            if (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1)))) {
-                valid = false;                          // not a box of that level: never
-                overflow = true;                        // dereferenced, list rebuilt
-            } else {
-                cc = (int32_t)(pb + lb + 4 * qj + (idx & 3));
-                const double* gc = c.geom + 4 * (int64_t)cc;
-                cg[0] = gc[0]; cg[1] = gc[1]; cg[2] = gc[2];
-                cnt = c.box_count[cc];
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
-            const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
-            const bool strong = valid && !weak;
-            const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
-            const int64_t sb = (g0 + t) * c.cs, wb = (g0 + t) * c.cw;
-            if (strong) {
-                const int o = ns[t] + __popcll(bs & below);
-                if (o < c.cs) s_ids[sb + o] = cc;
-                src[t] += cnt;
-            }
-            if (weak) {
-                const int o = nw[t] + __popcll(bw & below);
-                if (o < c.cw) w_ids[wb + o] = cc;
-            }
-            ns[t] += __popcll(bs);
-            nw[t] += __popcll(bw);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) src[t] += __shfl_xor(src[t], o, 64);
-    cap_overflow = __ballot(cap_overflow) != 0ull;
-    overflow = __ballot(overflow) != 0ull;
-    if (lane == 0) {
-        unsigned long long fl = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t g = g0 + t;
-            s_cnt[g] = ns[t];
-            w_cnt[g] = nw[t];
-            s_beg[g] = (int32_t)(g * c.cs);
-            w_beg[g] = (int32_t)(g * c.cw);
-            if (ns[t] > c.cs || nw[t] > c.cw) cap_overflow = true;
-            if (nw[t] > kChunkPairs) fl |= 8ull;
-            if (c.child0[g] < 0) {                      // a leaf: its near-field source count
-                c.nsrc[g] = (int32_t)(src[t] < INT32_MAX ? src[t] : INT32_MAX);
-                if (src[t] > kChunkSrc) fl |= 4ull;
-            }
-        }
-        if (cap_overflow) fl |= 1ull;
-        if (overflow) fl |= 2ull;
-        if (fl) atomicOr((unsigned long long*)&totals[2], fl);
-    }
+    // a few very long lists (clustered points) would make the padded pools
+    // huge: this layout then keeps the compact build
+    if ((int64_t)sc.nbox * (ex.cap_strong + ex.cap_weak) * (int64_t)sizeof(int32_t) > kMaxPaddedPools)
+        ex.compact_only = true;
 }
 
 static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const int64_t* pbox)
@@ -561,9 +594,10 @@ static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const
         if (l0 == l1 && l0 >= 1) {
             // one level: sibling groups (the level's box list is four-aligned)
             const int groups = c.n / 4;
-            k_traverse_sib<<<(unsigned)((groups + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
-                                                                       pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
-                                                                       (int64_t)pl.s_ids.n, totals);
+            k_traverse_sib<2><<<(unsigned)((groups + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
+                                                                          pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
+                                                                          (int64_t)pl.s_ids.n, (int64_t)pl.w_ids.n,
+                                                                          totals);
         } else {
             k_traverse<2><<<(unsigned)((c.n + 3) / 4), 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
                                                                     pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
@@ -598,7 +632,7 @@ void list_totals_device(Plan& pl, hipStream_t s)
     k_totals_init<<<1, 64, 0, s>>>(totals.p, pl.tree->err.p);
     k_sum_counts<<<(unsigned)((sc.nbox + 1023) / 1024), 1024, 0, s>>>(sc.nbox, pl.s_cnt.p, pl.w_cnt.p, totals.p);
     const int nl = (int)sc.nleaf;
-    k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
+    k_count_p2p<<<(nl + 3) / 4, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p,
                                                  pl.s_ids.p, totals.p, (int64_t)pl.s_ids.n);
     check_launch("list totals");
     long long h[4];
@@ -625,7 +659,8 @@ void build_lists_begin(Plan& pl, hipStream_t s)
     pl.list_stream = s;
     PlanExtra& ex = *pl.ex;
     if (ex.cap_strong == 0) { ex.cap_strong = kCapStrong; ex.cap_weak = kCapWeak; }
-    pl.lists_direct = nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only;
+    pl.lists_direct = nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only &&
+                      !ex.compact_only;
     if (pl.lists_direct) {
         pl.s_ids.alloc(nb * ex.cap_strong, s);
         pl.w_ids.alloc(nb * ex.cap_weak, s);
@@ -671,10 +706,6 @@ void build_lists_finish(Plan& pl)
         pl.w_ids.alloc(cap_w, s);
         if (!levelwise) {
             build_lists_traversal(pl, s, cap_s, cap_w, totals_p, pbox_p, bsum.p, snap.p);
-            int nl = (int)sc.nleaf;
-            k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
-                                                         pl.s_cnt.p, pl.s_ids.p, totals_p, cap_s);
-            check_launch("count p2p");
             long long h[4];
             FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
             FMM_HIP(hipStreamSynchronize(s));
@@ -686,8 +717,7 @@ void build_lists_finish(Plan& pl)
             }
             pl.n_strong = h[0];
             pl.n_weak = h[1];
-            pl.n_p2p_pairs = h[3];
-            pl.totals_known = true;
+            pl.totals_known = false;        // the pair count is summed on request
             if (!(h[2] & 1)) {
                 if (grow) grow_capacities(pl, s);
                 pl.split_p2p = pl.split_m2l = true;   // decided by the chunk counts
@@ -721,18 +751,13 @@ void build_lists_finish(Plan& pl)
                                             pl.w_ids.p, cap_s, cap_w);
             check_launch("level lists");
         }
-        int nl = (int)sc.nleaf;
-        k_count_p2p<<<(nl + 255) / 256, 256, 0, s>>>(pl.ex->leaves.p, nl, sc.d_box_count.p, pl.s_beg.p,
-                                                     pl.s_cnt.p, pl.s_ids.p, totals_p, cap_s);
-        check_launch("count p2p");
         long long h[4];
         FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
         check_tree_flag(h[2]);
         pl.n_strong = h[0];
         pl.n_weak = h[1];
-        pl.n_p2p_pairs = h[3];
-        pl.totals_known = true;
+        pl.totals_known = false;            // the pair count is summed on request
         if (!h[2]) {
             pl.split_p2p = pl.split_m2l = true;       // decided by the chunk counts
             return;

@@ -19,6 +19,7 @@ struct PlanExtra {
     int leaf_max = 0;                               // largest leaf population
     int cap_strong = 0, cap_weak = 0;               // per-box list capacities of the one-pass build
     bool levelwise_only = false;                    // a frontier overflowed on this layout
+    bool compact_only = false;                      // fixed capacities would need too much memory
     DBuf<double> binom;                             // binomial table C(n, k), n, k < 64
     std::vector<std::vector<int32_t>> m2m_boxes;   // non-leaf boxes per level
     std::vector<int64_t> m2m_off;

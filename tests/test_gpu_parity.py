@@ -60,6 +60,21 @@ def test_tree_nonuniform(orc, F, kind):
     _lists_equal(orc, F, pl, orc.tree(z, L)[2], L, 0.5)
 
 
+def test_clustered_long_lists_match_oracle(orc, F):
+    # four tight clusters: strong lists of up to ~2000 boxes one level above
+    # the leaves and ~8000 at the leaves (longer than a wavefront's LDS
+    # frontier, and too long for fixed per-box pools)
+    z, m = W.clustered(100000, seed=3, nclusters=4, sigma=1e-5)
+    L = 8
+    tree = same_tree(orc, F, z, L)
+    geom = orc.tree(z, L)[2]
+    for _ in range(2):   # the first plan learns the layout, the second uses it
+        pl = F.plan(tree, 12, 0.5, "fp64")
+        _lists_equal(orc, F, pl, geom, L, 0.5)
+    phi = host(F.evaluate(pl, dev(m)))
+    assert e2(phi, orc.fmm(z, m, 12, 0.5, L)) <= 1e-12
+
+
 def test_tree_exact_select_fallback(orc, F):
     # a segment whose median bucket holds > 2048 points with identical
     # coordinates cannot be resolved by bucketing: the exact radix select runs
