@@ -85,6 +85,38 @@ void dev_free(void* p, hipStream_t s)
     g_free.insert({it->second, Block{p, it->second, s}});
 }
 
+// ------------------------------------------------------ pinned flag words
+namespace {
+constexpr int kFlagSlots = 4096;
+std::mutex g_flag_mu;
+long long* g_flags = nullptr;       // pinned, allocated once
+std::vector<int> g_flag_free;
+}  // namespace
+
+int flag_slot_acquire()
+{
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    if (!g_flags) {
+        void* p = nullptr;
+        FMM_HIP(hipHostMalloc(&p, sizeof(long long) * kFlagSlots, hipHostMallocDefault));
+        g_flags = static_cast<long long*>(p);
+        for (int i = kFlagSlots - 1; i >= 0; --i) g_flag_free.push_back(i);
+    }
+    if (g_flag_free.empty()) return -1;
+    const int s = g_flag_free.back();
+    g_flag_free.pop_back();
+    return s;
+}
+
+volatile long long* flag_slot_ptr(int slot) { return g_flags + slot; }
+
+void flag_slot_release(int slot)
+{
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    g_flag_free.push_back(slot);
+}
+
 // --------------------------------------------------------- schedule cache
 namespace {
 struct SchedKey {
@@ -306,6 +338,7 @@ void fmm_plan_destroy(fmm_plan_t pl)
     // evaluation stream, so the plan's buffers are released in stream order
     if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
     if (P.ev_join) (void)hipEventDestroy(P.ev_join);
+    release_list_flag(P);
     delete pl;
 }
 
@@ -316,6 +349,10 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         Plan& P = pl->pl;
+        // a plan whose lists are still pending: the upward pass (which needs
+        // no lists) goes first, so the device works while the flags arrive
+        if (!P.finalized && !P.final_code && !(P.tune.flags & (FMM_FLAG_GRAPH | FMM_FLAG_PHASE_TIMING)))
+            evaluate_upward(P, m, s);
         plan_finalize(P);
         if (P.tune.flags & FMM_FLAG_GRAPH) {
             // capture and replay on a plan-owned stream (the legacy null stream

@@ -262,6 +262,26 @@ static hipStream_t near_stream(int device)
     return st;
 }
 
+// The part of an evaluation that needs no lists: gather and the upward
+// pass.  evaluate_device then continues from there on the same stream (the
+// near field is forked there, after the plan's remaining kernels).
+void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *extra(pl);
+    const bool mixed = pl.precision == FMM_MIXED;
+    if (!pl.nstream) {
+        pl.nstream = near_stream(t.device);
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+    }
+    launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    pl.upward_done = true;
+}
+
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s)
 {
     Tree& t = *pl.tree;
@@ -279,15 +299,23 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
     tm.mark();
-    launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    const bool up = pl.upward_done && overlap;   // gather and upward pass enqueued by evaluate_upward
+    pl.upward_done = false;
+    if (!up)
+        launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
     if (overlap) {
+        // the near field starts after everything enqueued on `s` so far: the
+        // gather, and the list and work-chunk kernels of the plan (which
+        // follow the upward pass when evaluate_upward ran first)
         FMM_HIP(hipEventRecord(pl.ev_fork, s));
         FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
         run_p2p(pl, ex, pl.nstream);
         FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
     }
-    if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
-    else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    if (!up) {
+        if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+        else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    }
     tm.mark();
     if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
     else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm);

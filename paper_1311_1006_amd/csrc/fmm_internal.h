@@ -194,6 +194,9 @@ struct Plan {
     std::string final_msg;
     DBuf<long long> lt_totals;     // list totals and flags of the pending build
     DBuf<int64_t> lt_pbox;
+    int flag_slot = -1;            // pinned host word receiving the one-pass flags
+    hipEvent_t ev_lists = nullptr; // recorded after that copy
+    bool upward_done = false;      // the evaluation's upward pass is already enqueued
     bool split_p2p = false, split_m2l = false;   // some list may need work chunks
     // evaluation buffers
     DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
@@ -242,6 +245,12 @@ void update_positions_device(Tree& t, const double* z, hipStream_t s);
 void build_lists_device(Plan& pl, hipStream_t s);
 void build_lists_begin(Plan& pl, hipStream_t s);
 void build_lists_finish(Plan& pl);
+void release_list_flag(Plan& pl);
+// pinned host words for flags read back without stalling the stream
+int flag_slot_acquire();
+volatile long long* flag_slot_ptr(int slot);
+void flag_slot_release(int slot);
+void evaluate_upward(Plan& pl, const double* m, hipStream_t s);
 void plan_finalize(Plan& pl);
 void plan_balance(Plan& pl, hipStream_t s);
 void list_totals_device(Plan& pl, hipStream_t s);

@@ -666,8 +666,27 @@ void build_lists_begin(Plan& pl, hipStream_t s)
         pl.w_ids.alloc(nb * ex.cap_weak, s);
         pl.nsrc.alloc(nb, s);
         build_lists_direct(pl, s, pl.lt_totals.p, pl.lt_pbox.p);
+        // the flags go to a pinned word now, so that reading them later does
+        // not wait for work enqueued after the lists
+        pl.flag_slot = flag_slot_acquire();
+        if (pl.flag_slot >= 0) {
+            if (!pl.ev_lists) FMM_HIP(hipEventCreateWithFlags(&pl.ev_lists, hipEventDisableTiming));
+            FMM_HIP(hipMemcpyAsync((void*)flag_slot_ptr(pl.flag_slot), pl.lt_totals.p + 2, sizeof(long long),
+                                   hipMemcpyDeviceToHost, s));
+            FMM_HIP(hipEventRecord(pl.ev_lists, s));
+        }
     }
     pl.lists_pending = true;
+}
+
+void release_list_flag(Plan& pl)
+{
+    if (pl.flag_slot >= 0) {
+        (void)hipEventSynchronize(pl.ev_lists);   // the copy into the word has landed
+        flag_slot_release(pl.flag_slot);
+        pl.flag_slot = -1;
+    }
+    if (pl.ev_lists) { (void)hipEventDestroy(pl.ev_lists); pl.ev_lists = nullptr; }
 }
 
 void build_lists_finish(Plan& pl)
@@ -684,8 +703,14 @@ void build_lists_finish(Plan& pl)
     bool grow = false;
     if (pl.lists_direct) {
         long long flag = 0;
-        FMM_HIP(hipMemcpyAsync(&flag, totals_p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
-        FMM_HIP(hipStreamSynchronize(s));
+        if (pl.flag_slot >= 0) {
+            FMM_HIP(hipEventSynchronize(pl.ev_lists));
+            flag = *flag_slot_ptr(pl.flag_slot);
+            release_list_flag(pl);
+        } else {
+            FMM_HIP(hipMemcpyAsync(&flag, totals_p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
+            FMM_HIP(hipStreamSynchronize(s));
+        }
         check_tree_flag(flag);
         if ((flag & 3) == 0) {
             pl.totals_known = false;    // list sizes and pair counts are summed on request

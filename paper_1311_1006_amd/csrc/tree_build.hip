@@ -432,7 +432,12 @@ k_init(const double* __restrict__ z, const int64_t* __restrict__ poff, int nprob
     for (int r = 0; r < R; ++r) {
         const int i = r * kTileThreads + threadIdx.x;
         if (i < cnt) {
-            bad |= !(isfinite(v[r].x) && isfinite(v[r].y));
+            // a non-finite position is flagged and built as (0, 0): the tree
+            // stays a valid permutation, whatever runs before the flag is read
+            if (!(isfinite(v[r].x) && isfinite(v[r].y))) {
+                bad = true;
+                v[r] = make_double2(0.0, 0.0);
+            }
             X[t0 + i] = v[r].x; Y[t0 + i] = v[r].y; I[t0 + i] = (int32_t)(t0 + i);
             x0 = fmin(x0, v[r].x); x1 = fmax(x1, v[r].x); y0 = fmin(y0, v[r].y); y1 = fmax(y1, v[r].y);
             any = true;

@@ -73,6 +73,12 @@ def test_clustered_long_lists_match_oracle(orc, F):
         _lists_equal(orc, F, pl, geom, L, 0.5)
     phi = host(F.evaluate(pl, dev(m)))
     assert e2(phi, orc.fmm(z, m, 12, 0.5, L)) <= 1e-12
+    # a fresh plan evaluated at once: the upward pass is enqueued before the
+    # plan's list and work-chunk kernels, and the near field must wait for them
+    for prec in ("fp64", "mixed"):
+        ref = host(F.evaluate(F.plan(tree, 12, 0.5, prec), dev(m)))
+        for _ in range(3):
+            assert np.array_equal(host(F.evaluate(F.plan(tree, 12, 0.5, prec), dev(m))), ref)
 
 
 def test_tree_exact_select_fallback(orc, F):
