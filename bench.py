@@ -224,7 +224,7 @@ def main():
             if best is None or dt < best[0]:
                 best = (dt, (L, 0, 0))
         L = best[1][0]
-        for cfg in ((L, 2, 0), (L, 0, 32)):
+        for cfg in ((L, 2, 0), (L, 0, 8), (L, 0, 16)):
             dt = time_steps(prec, cfg, 3)
             log("sweep %s L=%d split=%d batch=%d: %.3f ms" % (prec, cfg[0], cfg[1], cfg[2], dt * 1e3))
             if dt < best[0]:

@@ -71,8 +71,9 @@ enum {
 typedef struct {
     int p2p_split;   /* P2P: lane subgroups per wavefront (1, 2, 4); each subgroup takes
                         its own targets and one source per lane */
-    int m2l_batch;   /* M2L: weak pairs per wavefront iteration, 16 (one 16-pair MFMA
-                        block) or 32 (two blocks, two pairs per lane) */
+    int m2l_batch;   /* M2L: pair slots of one box in each 16-pair MFMA block: 16 (one
+                        box per wavefront), 8 or 4 (two or four boxes share a
+                        wavefront and its blocks) */
     int flags;       /* FMM_FLAG_* */
     int reserved;
 } fmm_tuning;

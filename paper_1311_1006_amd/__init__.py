@@ -251,7 +251,7 @@ class Tuner:
     """Online autotuner (AT3b-style, Sec. 4.2) over N_levels, P2P split and
     M2L batch; host only."""
 
-    def __init__(self, n_levels, min_levels, max_levels, p2p_split=4, m2l_batch=16, cap=0.1, window=3,
+    def __init__(self, n_levels, min_levels, max_levels, p2p_split=4, m2l_batch=4, cap=0.1, window=3,
                  knob_interval=6):
         cfg = _TunerConfig(_TunerParams(n_levels, p2p_split, m2l_batch), min_levels, max_levels, cap, window,
                            knob_interval)

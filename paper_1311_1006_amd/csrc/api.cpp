@@ -264,8 +264,8 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         if (tune) tn = *tune;
         FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4,
                     "p2p_split must be 0, 1, 2 or 4");
-        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 16 || tn.m2l_batch == 32,
-                    "m2l_batch must be 0, 16 or 32");
+        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 4 || tn.m2l_batch == 8 || tn.m2l_batch == 16,
+                    "m2l_batch must be 0, 4, 8 or 16");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         auto pp = std::make_unique<fmm_plan_s>();

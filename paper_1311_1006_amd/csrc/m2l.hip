@@ -145,7 +145,7 @@ __device__ __forceinline__ double rcp_nr(double r2)
     return fma(y, e, y);
 }
 
-template <class T, int PB, int NB>
+template <class T, int PB, int G>
 __global__ void __launch_bounds__(256)
 k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx, const int32_t* __restrict__ icnt,
       const int32_t* __restrict__ ioff, double* __restrict__ partial, const int32_t* __restrict__ w_beg,
@@ -155,19 +155,36 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     using M = Mfma<T>;
     using T2 = typename Vec2<T>::type;
     constexpr int KS = 4 * PB;       // k-steps of 4 (K = 16 PB)
-    constexpr int STEP = 16 * NB;    // pairs per iteration
+    constexpr int S = 16 / G;        // pair slots of one item in a block of 16
     const int w = threadIdx.x >> 6;
-    const int xi = xcd_block() * 4 + w;
-    if (xi >= nx) return;
-    // (box, chunk of its weak list); without chunk lists every box is one chunk
-    const int2 xe = xitems ? xitems[xi] : make_int2(xi, 0);
-    const int g = boxes[xe.x];
-    const int nch = icnt ? icnt[xe.x] : 1;
     const int lane = threadIdx.x & 63;
     const int q = lane & 15, kq = lane >> 4;
-    const int nw_all = w_cnt[g], p0 = xe.y * kChunkPairs;
-    const int nw = nch == 1 ? nw_all : min(kChunkPairs, nw_all - p0);   // pairs of this chunk
-    const int wb = w_beg[g] + p0;
+    const int grp = q / S, sl = q % S;   // the item of this lane's column, its slot in the item
+    const int xi0 = (xcd_block() * 4 + w) * G;
+    if (xi0 >= nx) return;               // uniform per wavefront
+    const int xi = xi0 + grp;
+    // item (box, chunk of its weak list); without chunk lists every box is one item
+    const bool item_ok = xi < nx;
+    int2 xe = make_int2(0, 0);
+    int g = 0, nch = 1, nw = 0, wb = 0;
+    if (item_ok) {
+        xe = xitems ? xitems[xi] : make_int2(xi, 0);
+        g = boxes[xe.x];
+        nch = icnt ? icnt[xe.x] : 1;
+        const int nw_all = w_cnt[g], p0 = xe.y * kChunkPairs;
+        nw = nch == 1 ? nw_all : min(kChunkPairs, nw_all - p0);   // pairs of this item
+        wb = w_beg[g] + p0;
+    }
+    // blocks: as many as the longest item of the wavefront needs
+    int nblk = (nw + S - 1) / S;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) nblk = max(nblk, __shfl_xor(nblk, o, 64));
+    // padding id: the first weak source of the first item that has pairs
+    // (its coefficients are computed; an item without pairs may be a root,
+    // whose multipole is not)
+    const unsigned long long has = __ballot(nw > 0);
+    const int first = nw > 0 ? w_ids[wb] : 0;
+    const int pad_id = has ? __shfl(first, __ffsll((long long)has) - 1, 64) : 0;
 
     // A operands: B_{row,k} = C(k+row, k), row = 16 rb + lane%16, k = 4 ks + lane/16
     T amat[PB][KS];
@@ -190,17 +207,17 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     // are r0 + j (FP32) or r0 + 4 j (FP64)
     const int r0 = M::kRowsConsecutive ? 4 * kq : kq;
 
-    // software pipeline over blocks of STEP pairs, unrolled by two with two
-    // register buffers: while one buffer's pairs are computed, the other
-    // buffer's geometry and coefficients (next block) and the ids of the block
-    // after are in flight.  Every load is unconditional (indices clamped into
-    // the list, padding replaced by the target itself where the id is used).
+    // software pipeline over blocks, unrolled by two with two register
+    // buffers: while one buffer's pairs are computed, the other buffer's
+    // geometry and coefficients (next block) and the ids of the block after
+    // are in flight.  Every load is unconditional (indices clamped into the
+    // list, padding replaced by pad_id).
     const int last = nw > 0 ? nw - 1 : 0;
-    auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : g; };
-    auto compute = [&](const PairData<T, KS>& c, int b0, int nb) {
-        const bool valid = b0 + 16 * nb + q < nw;
-        // Padding slots (past the end of the list) hold a real weak source of
-        // this list, so every coefficient is finite; they get 1/d = 0, hence
+    auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : pad_id; };
+    auto compute = [&](const PairData<T, KS>& c, int bi) {
+        const bool valid = bi * S + sl < nw;
+        // Padding slots (past the end of an item's list) hold a real weak
+        // source, so every coefficient is finite; they get 1/d = 0, hence
         // zero row factors, and add nothing.  Terms k >= p meet zero columns
         // of B and rows l >= p are not stored.
         T2 xv[KS];
@@ -287,60 +304,45 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
             }
         }
     };
-    PairData<T, KS> bufA[NB], bufB[NB];
-    int sidA[NB], sidB[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int e0 = 16 * nb + q;
-        const int s0 = raw_id(e0);
-        sidB[nb] = raw_id(STEP + e0);
-        load_pair<T, KS>(bufA[nb], s0, kq, p, geom, mp);
+    PairData<T, KS> bufA, bufB;
+    int sidA, sidB;
+    load_pair<T, KS>(bufA, raw_id(sl), kq, p, geom, mp);
+    sidB = raw_id(S + sl);
+    for (int bi = 0; bi < nblk; bi += 2) {
+        // block bi in bufA; load block bi + 1 into bufB, the id of block bi + 2
+        sidA = raw_id((bi + 2) * S + sl);
+        load_pair<T, KS>(bufB, sidB, kq, p, geom, mp);
+        compute(bufA, bi);
+        if (bi + 1 >= nblk) break;
+        // block bi + 1 in bufB; load block bi + 2 into bufA, the id of block bi + 3
+        sidB = raw_id((bi + 3) * S + sl);
+        load_pair<T, KS>(bufA, sidA, kq, p, geom, mp);
+        compute(bufB, bi + 1);
     }
-    for (int b0 = 0; b0 < nw; b0 += 2 * STEP) {
-        // block b0 in bufA; load block b0 + STEP into bufB
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int e1 = b0 + STEP + 16 * nb + q;
-            sidA[nb] = raw_id(e1 + STEP);
-            load_pair<T, KS>(bufB[nb], sidB[nb], kq, p, geom, mp);
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) compute(bufA[nb], b0, nb);
-        if (b0 + STEP >= nw) break;
-        // block b0 + STEP in bufB; load block b0 + 2 STEP into bufA
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int e2 = b0 + 2 * STEP + 16 * nb + q;
-            sidB[nb] = raw_id(e2 + STEP);
-            load_pair<T, KS>(bufA[nb], sidA[nb], kq, p, geom, mp);
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) compute(bufB[nb], b0 + STEP, nb);
-    }
-    // ---- sum over the 16 pair slots (lanes differing in bits 0..3)
+    // ---- sum over the S slots of every item (lanes differing in the low bits of q)
 #pragma unroll
     for (int rb = 0; rb < PB; ++rb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             T a = ore[rb][j], b = oim[rb][j];
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
+            for (int o = 1; o < S; o <<= 1) {
                 a += __shfl_xor(a, o, 64);
                 b += __shfl_xor(b, o, 64);
             }
             ore[rb][j] = a;
             oim[rb][j] = b;
         }
-    // lane q = j (< 4) writes element j of its rows (zeros for a box without
-    // weak pairs, so every box's local expansion is written)
-    if (q < 4) {
+    // slot j (< 4) of an item writes element j of its rows (zeros for a box
+    // without weak pairs, so every box's local expansion is written)
+    if (item_ok && sl < 4) {
 #pragma unroll
         for (int rb = 0; rb < PB; ++rb) {
             T vr = ore[rb][0], vi = oim[rb][0];
 #pragma unroll
             for (int j = 1; j < 4; ++j)
-                if (q == j) { vr = ore[rb][j]; vi = oim[rb][j]; }
-            const int row = 16 * rb + r0 + (M::kRowsConsecutive ? q : 4 * q);
+                if (sl == j) { vr = ore[rb][j]; vi = oim[rb][j]; }
+            const int row = 16 * rb + r0 + (M::kRowsConsecutive ? sl : 4 * sl);
             if (row < p) {
                 if (nch == 1) {
                     T* dst = loc + 2 * ((int64_t)g * p + row);
@@ -356,13 +358,15 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     }
 }
 
-template <class T, int PB, int NB>
+template <class T, int PB, int G>
 static void m2l_one(const int32_t* boxes, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                     double* partial, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                     const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
 {
-    k_m2l<T, PB, NB><<<(nx + 3) / 4, 256, 0, s>>>(boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom,
-                                                  binom, p, (const T*)mp, (T*)loc);
+    const int per_block = 4 * G;   // items per workgroup (4 wavefronts)
+    k_m2l<T, PB, G><<<(nx + per_block - 1) / per_block, 256, 0, s>>>(boxes, xitems, nx, icnt, ioff, partial, w_beg,
+                                                                     w_cnt, w_ids, geom, binom, p, (const T*)mp,
+                                                                     (T*)loc);
 }
 
 // the partial local expansions of split lists, added in chunk order
@@ -388,22 +392,30 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
 
 // Every box of `boxes` gets its local expansion written (zeros for a box
 // without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
-// box index; partial holds the chunks of split lists.  batch: weak pairs per
-// iteration of a wavefront, 16 (one MFMA block) or 32 (two blocks, two pairs
-// per lane); 0 = automatic (16).
+// box index; partial holds the chunks of split lists.  batch: pair slots of
+// one item in each 16-pair MFMA block: 16 (one item per wavefront), 8 (two)
+// or 4 (four items share a wavefront); 0 = automatic (4).
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                 double* partial, bool split, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                 const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s, int batch)
 {
     if (nx == 0) return;
-    const int nb = batch == 32 ? 2 : 1;
+    const int slots = batch == 0 ? 4 : batch;
 #define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s
-    if (p <= 16 && nb == 1) m2l_one<T, 1, 1>(ARGS);
-    else if (p <= 16) m2l_one<T, 1, 2>(ARGS);
-    else if (p <= 32 && nb == 1) m2l_one<T, 2, 1>(ARGS);
-    else if (p <= 32) m2l_one<T, 2, 2>(ARGS);
-    else throw Error(FMM_EINVAL, "unsupported M2L configuration");
+    if (p <= 16) {
+        if (slots == 16) m2l_one<T, 1, 1>(ARGS);
+        else if (slots == 8) m2l_one<T, 1, 2>(ARGS);
+        else if (slots == 4) m2l_one<T, 1, 4>(ARGS);
+        else throw Error(FMM_EINVAL, "unsupported M2L batch");
+    } else if (p <= 32) {
+        if (slots == 16) m2l_one<T, 2, 1>(ARGS);
+        else if (slots == 8) m2l_one<T, 2, 2>(ARGS);
+        else if (slots == 4) m2l_one<T, 2, 4>(ARGS);
+        else throw Error(FMM_EINVAL, "unsupported M2L batch");
+    } else {
+        throw Error(FMM_EINVAL, "unsupported M2L configuration");
+    }
 #undef ARGS
     check_launch("m2l");
     if (split) {

@@ -32,7 +32,7 @@
 namespace {
 
 const int kSplits[] = {1, 2, 4};
-const int kBatches[] = {16, 32};
+const int kBatches[] = {4, 8, 16};
 
 template <size_t N>
 int index_of(const int (&v)[N], int x)
@@ -158,7 +158,7 @@ int fmm_tuner_observe(fmm_tuner_t tu, double seconds)
                 else t.split_dir = -t.split_dir;
             } else {
                 int k = index_of(kBatches, t.cur.m2l_batch) + t.batch_dir;
-                if (k >= 0 && k < 2) { t.cur.m2l_batch = kBatches[k]; t.pending = kBatch; }
+                if (k >= 0 && k < 3) { t.cur.m2l_batch = kBatches[k]; t.pending = kBatch; }
                 else t.batch_dir = -t.batch_dir;
             }
         }

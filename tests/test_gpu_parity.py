@@ -114,6 +114,17 @@ def test_fp64_fmm_matches_oracle_fmm(orc, F, n, L, p):
     assert e2(host(far), rfar) <= 1e-12
 
 
+@pytest.mark.parametrize("batch,p", [(4, 16), (8, 16), (16, 16), (8, 20), (16, 24)])
+def test_m2l_batch_shapes_match_oracle(orc, F, batch, p):
+    # M2L with one, two or four boxes sharing a wavefront's 16 pair slots
+    z, m, _ = W.uniform(30000, seed=14)
+    tree = F.build_tree(dev(z), 6)
+    pl = F.plan(tree, p, 0.5, "fp64", m2l_batch=batch)
+    assert e2(host(F.evaluate(pl, dev(m))), orc.fmm(z, m, p, 0.5, 6)) <= 1e-12
+    plm = F.plan(tree, p, 0.5, "mixed", m2l_batch=batch)
+    assert e2(host(F.evaluate(plm, dev(m))), orc.direct(z, m)) <= 1e-6
+
+
 def test_fp64_fmm_clustered_matches_oracle(orc, F):
     z, m = W.clustered(20000, seed=4, nclusters=8)
     tree = F.build_tree(dev(z), 6)

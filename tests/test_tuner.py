@@ -29,7 +29,7 @@ def argmin_L(cost_at, lo=3, hi=12):
 def test_converges_to_the_optimum_and_respects_the_cap():
     rng = np.random.default_rng(0)
     best = argmin_L(lambda L: model(L))
-    tu = F.Tuner(n_levels=5, min_levels=3, max_levels=12, p2p_split=2, m2l_batch=32, cap=0.1, window=3)
+    tu = F.Tuner(n_levels=5, min_levels=3, max_levels=12, p2p_split=2, m2l_batch=8, cap=0.1, window=3)
     hist = run(tu, 600, lambda i, p: model(p["n_levels"]), rng)
     Ls = np.array([h[0] for h in hist])
     # the optimum is where the tuner spends most of its time; it keeps probing
@@ -69,13 +69,13 @@ def test_knob_moves_are_accepted_only_when_faster():
     pref = {1: 1.3, 2: 1.0, 4: 1.2}
 
     def cost(i, p):
-        return model(p["n_levels"]) * pref[p["p2p_split"]] * (1.0 if p["m2l_batch"] == 32 else 1.1)
+        return model(p["n_levels"]) * pref[p["p2p_split"]] * (1.0 if p["m2l_batch"] == 8 else 1.1)
 
     tu = F.Tuner(n_levels=8, min_levels=8, max_levels=8, p2p_split=4, m2l_batch=16, cap=0.1, window=3,
                  knob_interval=4)
     hist = run(tu, 400, cost, rng, noise=0.01)
     b, _, _ = tu.best()
-    assert b["p2p_split"] == 2 and b["m2l_batch"] == 32
+    assert b["p2p_split"] == 2 and b["m2l_batch"] == 8
 
 
 def test_invalid_configuration_is_rejected():
