@@ -374,16 +374,15 @@ static void check_tree_flag(long long flag)
     if (flag & 16) throw Error(FMM_EINVAL, "non-finite position");
 }
 
-// Level ranges of the passes: the deepest level alone, the two above it
-// together, everything above those from the root.
+// Level ranges of the passes: the three deepest levels one at a time (by
+// sibling groups), everything above them in one pass from the root.
 static std::vector<std::pair<int, int>> traversal_passes(int levels)
 {
     std::vector<std::pair<int, int>> r;
     const int top = levels - 1;
     if (levels <= 4) { r.push_back({0, top}); return r; }
     r.push_back({0, top - 3});
-    r.push_back({top - 2, top - 1});
-    r.push_back({top, top});
+    for (int l = top - 2; l <= top; ++l) r.push_back({l, l});
     return r;
 }
 
