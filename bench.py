@@ -26,6 +26,7 @@ PEAK_FP32_VALU = 157.3      # TFLOP/s, MI355X published FP32 vector peak (packed
 PEAK_FP32_NOPACK = 78.6     # TFLOP/s, the same units issuing one FP32 op per lane per cycle
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X published dense FP32 matrix peak
 P2P_FLOP_PER_PAIR = 16      # per (target, source) pair: see the near-field kernel's header
+M2L_AUTO_SLOTS_MIXED = 8    # M2L pair slots per box chosen automatically for mixed precision
 
 
 def m2l_flop_per_pair(p):
@@ -307,9 +308,11 @@ def main():
                 "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR}
     fpp = m2l_flop_per_pair(p)
     tflop = fpp * st["n_m2l_pairs"] / (mx["m2l_us"] * 1e-6) / 1e12
-    roof_m2l = {"bound": "mfma", "kernel": "k_m2l<float> (mixed M2L, FP32 MFMA)", "achieved": tflop,
-                "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": tflop / PEAK_FP32_MFMA,
-                "traffic": profile_traffic("m2l_mixed_uniform_n1e6_L9_pmc.txt"),
+    slots = mx["batch"] or M2L_AUTO_SLOTS_MIXED   # the counters were taken with the automatic shape
+    roof_m2l = {"bound": "mfma", "kernel": "k_m2l<float> (mixed M2L, FP32 MFMA, %d slots per box)" % slots,
+                "achieved": tflop, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": tflop / PEAK_FP32_MFMA,
+                "traffic": profile_traffic("m2l_mixed_uniform_n1e6_L9_pmc.txt")
+                if slots == M2L_AUTO_SLOTS_MIXED else None,
                 "avg_us": mx["m2l_us"], "pairs": st["n_m2l_pairs"], "flop_per_pair": fpp}
     if mx["m2l_us"] >= mx["p2p_us"]:
         roofline, other = roof_m2l, {"p2p": roof_p2p}

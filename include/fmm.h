@@ -73,7 +73,7 @@ typedef struct {
                         its own targets and one source per lane */
     int m2l_batch;   /* M2L: pair slots of one box in each 16-pair MFMA block: 16 (one
                         box per wavefront), 8 or 4 (two or four boxes share a
-                        wavefront and its blocks) */
+                        wavefront and its blocks); automatic: 8 mixed, 4 FP64 */
     int flags;       /* FMM_FLAG_* */
     int reserved;
 } fmm_tuning;

@@ -394,14 +394,15 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
 // without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
 // box index; partial holds the chunks of split lists.  batch: pair slots of
 // one item in each 16-pair MFMA block: 16 (one item per wavefront), 8 (two)
-// or 4 (four items share a wavefront); 0 = automatic (4).
+// or 4 (four items share a wavefront); 0 = automatic (8 for FP32, 4 for
+// FP64: the fastest on the uniform million-point case).
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                 double* partial, bool split, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
                 const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s, int batch)
 {
     if (nx == 0) return;
-    const int slots = batch == 0 ? 4 : batch;
+    const int slots = batch != 0 ? batch : (std::is_same<T, float>::value ? 8 : 4);
 #define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s
     if (p <= 16) {
         if (slots == 16) m2l_one<T, 1, 1>(ARGS);
