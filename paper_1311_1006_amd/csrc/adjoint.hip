@@ -43,7 +43,7 @@ void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double
 template <class T>
 void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
                 const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
-                hipStream_t, int);
+                hipStream_t, int, const long long*);
 void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
                    const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
 
@@ -325,7 +325,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
         const Plan::Balance& bm = pl.bal_m2l;
         launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, bm.xitems.p, (int)bm.total, bm.icnt.p, bm.ioff.p, bm.partial.p,
                       bm.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p,
-                      pl.aloc.p, s, pl.tune.m2l_batch);
+                      pl.aloc.p, s, pl.tune.m2l_batch, nullptr);
         for (int l = 1; l + 1 < sc.max_levels; ++l) {
             int nn = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
             launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.aloc.p, s);

@@ -290,10 +290,16 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
             }
             pl.ex = pl.ex_ref.get();
         }
-        // the lists are enqueued; their flags are read by the first call
-        // that needs them (plan_finalize), so the host returns meanwhile
-        build_lists_begin(pl, s);
+        // the lists are enqueued on the device's list stream after the tree's
+        // work on `s`, so they run beside what the caller enqueues next (the
+        // upward pass); their flags are read by the first call that needs
+        // them (plan_finalize), so the host returns meanwhile
         alloc_eval_buffers(pl, s);
+        hipStream_t ls = side_stream(pl.tree->device, kListStream);
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_tree, hipEventDisableTiming));
+        FMM_HIP(hipEventRecord(pl.ev_tree, s));
+        FMM_HIP(hipStreamWaitEvent(ls, pl.ev_tree, 0));
+        build_lists_begin(pl, ls, s);
         *out = pp.release();
     });
 }
@@ -317,7 +323,16 @@ void plan_finalize(Plan& P)
     }
     P.lt_totals.release();
     P.lt_pbox.release();
+    // the plan's last device work on the list stream: consumers wait for it
+    if (!P.ev_plan_done) FMM_HIP(hipEventCreateWithFlags(&P.ev_plan_done, hipEventDisableTiming));
+    FMM_HIP(hipEventRecord(P.ev_plan_done, P.list_stream));
     P.finalized = true;
+}
+
+// order `s` after the plan's list and work-chunk kernels
+void plan_join(Plan& P, hipStream_t s)
+{
+    if (P.ev_plan_done) FMM_HIP(hipStreamWaitEvent(s, P.ev_plan_done, 0));
 }
 }  // namespace fmm
 
@@ -339,6 +354,13 @@ void fmm_plan_destroy(fmm_plan_t pl)
     if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
     if (P.ev_join) (void)hipEventDestroy(P.ev_join);
     release_list_flag(P);
+    // list work still in flight (a plan never used) finishes before its
+    // buffers go back to the pool
+    if (P.lists_pending && P.list_stream) (void)hipStreamSynchronize(P.list_stream);
+    if (P.ev_tree) (void)hipEventDestroy(P.ev_tree);
+    if (P.ev_lists_k) (void)hipEventDestroy(P.ev_lists_k);
+    if (P.ev_spec) (void)hipEventDestroy(P.ev_spec);
+    if (P.ev_plan_done) (void)hipEventDestroy(P.ev_plan_done);
     delete pl;
 }
 
@@ -349,10 +371,30 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         Plan& P = pl->pl;
-        // a plan whose lists are still pending: the upward pass (which needs
-        // no lists) goes first, so the device works while the flags arrive
-        if (!P.finalized && !P.final_code && !(P.tune.flags & (FMM_FLAG_GRAPH | FMM_FLAG_PHASE_TIMING)))
+        const bool pending = !P.finalized && !P.final_code && !(P.tune.flags & (FMM_FLAG_GRAPH | FMM_FLAG_PHASE_TIMING));
+        if (pending && P.lists_pending && P.lists_direct && P.flag_slot >= 0) {
+            // The one-pass lists are still in flight.  The whole evaluation
+            // is enqueued now for the usual outcome (no flag: every list fit
+            // and none needs work chunks); its list-reading kernels wait for
+            // the lists and read the device flag word first, doing nothing
+            // when it is set.  The host reads the same flags meanwhile; only
+            // when one is set does it enqueue the evaluation again, after
+            // the rebuild or the work chunks.
+            P.split_p2p = P.split_m2l = false;
+            plan_balance(P, s);                 // unsplit tables: host only
+            evaluate_device(P, m, phi, nullptr, nullptr, s, P.ev_lists_k, P.lt_totals.p + 2);
+            if (!P.ev_spec) FMM_HIP(hipEventCreateWithFlags(&P.ev_spec, hipEventDisableTiming));
+            FMM_HIP(hipEventRecord(P.ev_spec, s));
+            plan_finalize(P);
+            if (P.list_flag == 0) {
+                P.last_m = m;
+                return;
+            }
+        } else if (pending) {
+            // lists built by several passes: the upward pass (which needs no
+            // lists) goes first, so the device works while the flags arrive
             evaluate_upward(P, m, s);
+        }
         plan_finalize(P);
         if (P.tune.flags & FMM_FLAG_GRAPH) {
             // capture and replay on a plan-owned stream (the legacy null stream
@@ -364,6 +406,7 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
             }
             FMM_HIP(hipEventRecord(P.ev_in, s));
             FMM_HIP(hipStreamWaitEvent(P.gstream, P.ev_in, 0));
+            plan_join(P, P.gstream);
             if (!P.graph || P.graph_m != m || P.graph_phi != phi) {
                 if (P.graph) { FMM_HIP(hipGraphExecDestroy(P.graph)); P.graph = nullptr; }
                 hipGraph_t g = nullptr;
@@ -392,6 +435,7 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
             FMM_HIP(hipStreamWaitEvent(s, P.ev_out, 0));
             P.have_forward = true;
         } else {
+            plan_join(P, s);
             evaluate_device(P, m, phi, nullptr, nullptr, s);
         }
         P.last_m = m;
@@ -404,6 +448,7 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
         FMM_REQUIRE(pl && m, "NULL argument");
         check_device_state();
         plan_finalize(pl->pl);
+        plan_join(pl->pl, (hipStream_t)stream);
         evaluate_device(pl->pl, m, nullptr, phi_near, phi_far, (hipStream_t)stream);
         pl->pl.last_m = m;
     });
@@ -417,6 +462,7 @@ int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, do
         if (!pl->pl.have_forward) throw Error(FMM_ESTATE, "fmm_evaluate_adjoint needs a preceding fmm_evaluate");
         check_device_state();
         plan_finalize(pl->pl);
+        plan_join(pl->pl, (hipStream_t)stream);
         adjoint_device(pl->pl, m, g_phi, g_m, g_z, (hipStream_t)stream);
     });
 }
@@ -506,6 +552,7 @@ static void list_host(fmm_plan_t pl, int prob, int level, int kind, std::vector<
     FMM_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (strong) or 1 (weak)");
     int64_t nb = int64_t(1) << (2 * level);
     int64_t b0 = sc.pbox[prob] + level_base(level);
+    plan_join(P, s);   // after the list kernels on the list stream
     beg.resize(nb);
     cnt.resize(nb);
     const int32_t* db = kind ? P.w_beg.p : P.s_beg.p;

@@ -29,16 +29,17 @@ template <class T>
 void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
-                const double*, const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t);
+                const double*, const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t,
+                const long long*);
 template <class T>
 void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
                 const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
-                hipStream_t, int);
+                hipStream_t, int, const long long*);
 void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s);
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard);
 
 struct P2PItemH {
     int32_t leaf, t0, tn, pad;
@@ -176,7 +177,8 @@ static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipS
 struct PhaseTimer;
 
 template <class T>
-static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm);
+static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm,
+                         const long long* guard);
 
 struct PhaseTimer {
     static constexpr int kEvents = 6;
@@ -207,14 +209,15 @@ struct PhaseTimer {
 };
 
 template <class T>
-static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm)
+static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm,
+                         const long long* guard)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const Plan::Balance& b = pl.bal_m2l;
     launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
                   b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
-                  pl.tune.m2l_batch);
+                  pl.tune.m2l_batch, guard);
     tm.mark();
     // parents at level l (non-leaf) hand their expansion to level l+1
     for (int l = 1; l + 1 < sc.max_levels; ++l) {
@@ -226,7 +229,7 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
 void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
                     hipStream_t s);
 
-static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
+static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* guard)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -241,24 +244,25 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s)
                    (int)(x1 - x0), b.icnt.p, b.ioff.p,
                    pl.nsrc.p, b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
-                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s);
+                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard);
     }
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }
 
-// One near-field stream per device, shared by all plans and kept until the
-// process ends (creating a stream per plan costs more than a whole step).
-// Plans that share it are ordered by their own fork/join events.
-static hipStream_t near_stream(int device)
+// Side streams per device (the near field; the list build), shared by all
+// plans and kept until the process ends (creating a stream per plan costs
+// more than a whole step).  Plans that share one are ordered by their own
+// events.
+hipStream_t side_stream(int device, int which)
 {
     static std::mutex mu;
-    static std::map<int, hipStream_t> streams;
+    static std::map<std::pair<int, int>, hipStream_t> streams;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = streams.find(device);
+    auto it = streams.find({device, which});
     if (it != streams.end()) return it->second;
     hipStream_t st = nullptr;
     FMM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    streams[device] = st;
+    streams[{device, which}] = st;
     return st;
 }
 
@@ -272,7 +276,7 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
     PlanExtra& ex = *extra(pl);
     const bool mixed = pl.precision == FMM_MIXED;
     if (!pl.nstream) {
-        pl.nstream = near_stream(t.device);
+        pl.nstream = side_stream(t.device, kNearStream);
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
@@ -282,7 +286,8 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
     pl.upward_done = true;
 }
 
-void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s)
+void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s,
+                     hipEvent_t lists_ev, const long long* guard)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -293,8 +298,9 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     // stream beside the far-field chain (P2M .. L2L) and joins before L2P.
     // Phase timing keeps the phases one after another on `s`.
     const bool overlap = !tm.on;
+    if (lists_ev && !overlap) throw Error(FMM_EINVAL, "an evaluation ahead of its lists needs the overlapped order");
     if (overlap && !pl.nstream) {
-        pl.nstream = near_stream(t.device);
+        pl.nstream = side_stream(t.device, kNearStream);
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
@@ -309,7 +315,8 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
         // follow the upward pass when evaluate_upward ran first)
         FMM_HIP(hipEventRecord(pl.ev_fork, s));
         FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
-        run_p2p(pl, ex, pl.nstream);
+        if (lists_ev) FMM_HIP(hipStreamWaitEvent(pl.nstream, lists_ev, 0));
+        run_p2p(pl, ex, pl.nstream, guard);
         FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
     }
     if (!up) {
@@ -317,18 +324,19 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
         else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
     }
     tm.mark();
-    if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
-    else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm);
+    if (lists_ev) FMM_HIP(hipStreamWaitEvent(s, lists_ev, 0));
+    if (mixed) run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm, guard);
+    else run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm, guard);
     tm.mark();
     if (overlap) FMM_HIP(hipStreamWaitEvent(s, pl.ev_join, 0));
-    else run_p2p(pl, ex, s);
+    else run_p2p(pl, ex, s, nullptr);
     tm.mark();
     if (mixed)
         launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
-                          pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
+                          pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard);
     else
         launch_l2p<double>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
-                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s);
+                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard);
     tm.mark();
     if (tm.on) {
         FMM_HIP(hipEventSynchronize(tm.ev[5]));

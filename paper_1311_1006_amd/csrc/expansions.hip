@@ -205,8 +205,10 @@ __global__ void __launch_bounds__(256)
 k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
       const double* __restrict__ Y, const T* __restrict__ loc, int p, const double2* __restrict__ nearf,
-      const int32_t* __restrict__ perm, double2* phi, double2* phi_near, double2* phi_far)
+      const int32_t* __restrict__ perm, double2* phi, double2* phi_near, double2* phi_far,
+      const long long* __restrict__ guard)
 {
+    if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     using T2 = typename Vec2<T>::type;
     const int lane = threadIdx.x & 63;
     const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
@@ -305,7 +307,7 @@ template <class T>
 void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
                 const double* geom, const double* X, const double* Y, const void* loc, int p,
                 const double* nearf, const int32_t* perm, double* phi, double* phi_near, double* phi_far,
-                hipStream_t s)
+                hipStream_t s, const long long* guard)
 {
     if (nleaf == 0) return;
     const int G = leaf_lanes(leaf_max);
@@ -314,7 +316,7 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
     if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
         k_l2p<T, G_, P_><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const T*)loc, p,  \
                                               (const double2*)nearf, perm, (double2*)phi,                 \
-                                              (double2*)phi_near, (double2*)phi_far);                     \
+                                              (double2*)phi_near, (double2*)phi_far, guard);              \
         check_launch("l2p");                                                                              \
         return;                                                                                           \
     }
@@ -332,7 +334,8 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
                                 void*, hipStream_t);                                                     \
     template void launch_l2p<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
                                 const double*, const double*, const void*, int, const double*,           \
-                                const int32_t*, double*, double*, double*, hipStream_t);
+                                const int32_t*, double*, double*, double*, hipStream_t,     \
+                                const long long*);
 INST(double)
 INST(float)
 #undef INST

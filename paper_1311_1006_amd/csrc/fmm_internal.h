@@ -196,6 +196,11 @@ struct Plan {
     DBuf<int64_t> lt_pbox;
     int flag_slot = -1;            // pinned host word receiving the one-pass flags
     hipEvent_t ev_lists = nullptr; // recorded after that copy
+    hipEvent_t ev_lists_k = nullptr;     // recorded after the list kernels (before the copy)
+    hipEvent_t ev_spec = nullptr;  // after an evaluation enqueued ahead of the flags
+    long long list_flag = -1;      // the flags read by build_lists_finish (-1: not read)
+    hipEvent_t ev_tree = nullptr;  // the tree's work on the caller's stream, before the lists
+    hipEvent_t ev_plan_done = nullptr;   // the plan's last device work (list stream)
     bool upward_done = false;      // the evaluation's upward pass is already enqueued
     bool split_p2p = false, split_m2l = false;   // some list may need work chunks
     // evaluation buffers
@@ -243,7 +248,7 @@ struct Plan {
 void build_tree_device(Tree& t, const double* z, hipStream_t s);
 void update_positions_device(Tree& t, const double* z, hipStream_t s);
 void build_lists_device(Plan& pl, hipStream_t s);
-void build_lists_begin(Plan& pl, hipStream_t s);
+void build_lists_begin(Plan& pl, hipStream_t ls, hipStream_t as);
 void build_lists_finish(Plan& pl);
 void release_list_flag(Plan& pl);
 // pinned host words for flags read back without stalling the stream
@@ -251,11 +256,17 @@ int flag_slot_acquire();
 volatile long long* flag_slot_ptr(int slot);
 void flag_slot_release(int slot);
 void evaluate_upward(Plan& pl, const double* m, hipStream_t s);
+constexpr int kNearStream = 0, kListStream = 1;
+hipStream_t side_stream(int device, int which);
+void plan_join(Plan& pl, hipStream_t s);
 void plan_finalize(Plan& pl);
 void plan_balance(Plan& pl, hipStream_t s);
 void list_totals_device(Plan& pl, hipStream_t s);
+// lists_ev/guard: an evaluation enqueued before the list flags are read.
+// Its list-reading kernels wait for lists_ev and do nothing when the flag
+// word *guard is non-zero (the lists then need a rebuild or work chunks).
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
-                     hipStream_t s);
+                     hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,
                     hipStream_t s);
 

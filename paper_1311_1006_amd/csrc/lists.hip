@@ -646,25 +646,30 @@ void list_totals_device(Plan& pl, hipStream_t s)
 // Enqueue the list build without waiting: the one-pass build when the
 // capacities allow it.  build_lists_finish reads its flags (one
 // synchronisation) and runs the compact or level-wise build if needed.
-void build_lists_begin(Plan& pl, hipStream_t s)
+// The kernels go to `ls`; the plan's buffers are allocated on `as` (the
+// stream that later uses and releases them, joined to `ls` by events).
+void build_lists_begin(Plan& pl, hipStream_t ls, hipStream_t as)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     int64_t nb = sc.nbox;
-    pl.s_beg.alloc(nb, s); pl.s_cnt.alloc(nb, s); pl.w_beg.alloc(nb, s); pl.w_cnt.alloc(nb, s);
-    pl.lt_pbox.alloc(sc.nprob, s);
+    hipStream_t s = ls;
+    pl.s_beg.alloc(nb, as); pl.s_cnt.alloc(nb, as); pl.w_beg.alloc(nb, as); pl.w_cnt.alloc(nb, as);
+    pl.lt_pbox.alloc(sc.nprob, as);
     FMM_HIP(hipMemcpyAsync(pl.lt_pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
-    pl.lt_totals.alloc(4, s);
+    pl.lt_totals.alloc(4, as);
     pl.list_stream = s;
     PlanExtra& ex = *pl.ex;
     if (ex.cap_strong == 0) { ex.cap_strong = kCapStrong; ex.cap_weak = kCapWeak; }
     pl.lists_direct = nb * std::max(ex.cap_strong, ex.cap_weak) < INT32_MAX && !ex.levelwise_only &&
                       !ex.compact_only;
     if (pl.lists_direct) {
-        pl.s_ids.alloc(nb * ex.cap_strong, s);
-        pl.w_ids.alloc(nb * ex.cap_weak, s);
-        pl.nsrc.alloc(nb, s);
+        pl.s_ids.alloc(nb * ex.cap_strong, as);
+        pl.w_ids.alloc(nb * ex.cap_weak, as);
+        pl.nsrc.alloc(nb, as);
         build_lists_direct(pl, s, pl.lt_totals.p, pl.lt_pbox.p);
+        if (!pl.ev_lists_k) FMM_HIP(hipEventCreateWithFlags(&pl.ev_lists_k, hipEventDisableTiming));
+        FMM_HIP(hipEventRecord(pl.ev_lists_k, s));
         // the flags go to a pinned word now, so that reading them later does
         // not wait for work enqueued after the lists
         pl.flag_slot = flag_slot_acquire();
@@ -710,6 +715,11 @@ void build_lists_finish(Plan& pl)
             FMM_HIP(hipMemcpyAsync(&flag, totals_p + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
             FMM_HIP(hipStreamSynchronize(s));
         }
+        pl.list_flag = flag;
+        // an evaluation enqueued ahead of these flags skipped its list work
+        // (flag set); nothing below may touch the lists or the flag word
+        // before that evaluation has drained
+        if (flag != 0 && pl.ev_spec) FMM_HIP(hipStreamWaitEvent(s, pl.ev_spec, 0));
         check_tree_flag(flag);
         if ((flag & 3) == 0) {
             pl.totals_known = false;    // list sizes and pair counts are summed on request
@@ -794,7 +804,7 @@ void build_lists_finish(Plan& pl)
 
 void build_lists_device(Plan& pl, hipStream_t s)
 {
-    build_lists_begin(pl, s);
+    build_lists_begin(pl, s, s);
     build_lists_finish(pl);
 }
 

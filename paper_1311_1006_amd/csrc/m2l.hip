@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(256)
 k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx, const int32_t* __restrict__ icnt,
       const int32_t* __restrict__ ioff, double* __restrict__ partial, const int32_t* __restrict__ w_beg,
       const int32_t* __restrict__ w_cnt, const int32_t* __restrict__ w_ids, const double* __restrict__ geom,
-      const double* __restrict__ binom, int p, const T* __restrict__ mp, T* loc)
+      const double* __restrict__ binom, int p, const T* __restrict__ mp, T* loc,
+      const long long* __restrict__ guard)
 {
     using M = Mfma<T>;
     using T2 = typename Vec2<T>::type;
@@ -162,6 +163,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     const int grp = q / S, sl = q % S;   // the item of this lane's column, its slot in the item
     const int xi0 = (xcd_block() * 4 + w) * G;
     if (xi0 >= nx) return;               // uniform per wavefront
+    if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     const int xi = xi0 + grp;
     // item (box, chunk of its weak list); without chunk lists every box is one item
     const bool item_ok = xi < nx;
@@ -361,12 +363,13 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
 template <class T, int PB, int G>
 static void m2l_one(const int32_t* boxes, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                     double* partial, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
-                    const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s)
+                    const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s,
+                    const long long* guard)
 {
     const int per_block = 4 * G;   // items per workgroup (4 wavefronts)
     k_m2l<T, PB, G><<<(nx + per_block - 1) / per_block, 256, 0, s>>>(boxes, xitems, nx, icnt, ioff, partial, w_beg,
                                                                      w_cnt, w_ids, geom, binom, p, (const T*)mp,
-                                                                     (T*)loc);
+                                                                     (T*)loc, guard);
 }
 
 // the partial local expansions of split lists, added in chunk order
@@ -399,11 +402,12 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                 double* partial, bool split, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
-                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s, int batch)
+                const double* geom, const double* binom, int p, const void* mp, void* loc, hipStream_t s, int batch,
+                const long long* guard)
 {
     if (nx == 0) return;
     const int slots = batch != 0 ? batch : (std::is_same<T, float>::value ? 8 : 4);
-#define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s
+#define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s, guard
     if (p <= 16) {
         if (slots == 16) m2l_one<T, 1, 1>(ARGS);
         else if (slots == 8) m2l_one<T, 1, 2>(ARGS);
@@ -429,7 +433,8 @@ void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const i
 #define INST_M2L(T)                                                                                        \
     template void launch_m2l<T>(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, \
                                 bool, const int32_t*, const int32_t*, const int32_t*, const double*,            \
-                                const double*, int, const void*, void*, hipStream_t, int);
+                                const double*, int, const void*, void*, hipStream_t, int,     \
+                                const long long*);
 INST_M2L(double)
 INST_M2L(float)
 #undef INST_M2L

@@ -120,8 +120,10 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
-        const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out)
+        const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
+        const long long* __restrict__ guard)
 {
+    if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
     __shared__ Src64 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
@@ -188,8 +190,9 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
-        double2* __restrict__ out)
+        double2* __restrict__ out, const long long* __restrict__ guard)
 {
+    if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
     __shared__ Src32 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
@@ -255,15 +258,15 @@ template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
                        const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                       const void* src, const void* lo, double* out, hipStream_t s)
+                       const void* src, const void* lo, double* out, hipStream_t s, const long long* guard)
 {
     int grid = (nx + 3) / 4;
     if (mixed)
         k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out);
+                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out, guard);
     else
         k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const double4*)src, (double2*)out);
+                                             s_cnt, s_ids, (const double4*)src, (double2*)out, guard);
 }
 
 // one launch per (targets per subgroup, subgroups) class over its chunks
@@ -273,14 +276,14 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s)
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard)
 {
     if (nx == 0) return;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s);                                                    \
+                              s_ids, src, lo, out, s, guard);                                                    \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }
