@@ -663,7 +663,8 @@ __global__ void __launch_bounds__(kTileThreads)
 k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
           const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
           const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1,
-          const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below)
+          const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below,
+          uint32_t* seg_over)
 {
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
@@ -671,6 +672,7 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     int rank, ccount;
     ClassRule rule = median_class(keys, hist1, hist2, t.seg, sg.count / 2, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
+    if (t.rank == 0 && threadIdx.x == 0) seg_over[t.seg] = overflow ? 1u : 0u;
     constexpr int R = kTile / kTileThreads;
     double v[R];
     load_tile(rule.bk.axis ? Y : X, t, v);
@@ -694,76 +696,33 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     if (threadIdx.x == 0) tile_below[sg.tile0 + t.rank] = (uint32_t)tot;
 }
 
-// one workgroup per segment: the exact median (coordinate, index) and the
-// output offset of every tile's lower half
+// Segments whose median class holds more than kCandCap points (heavy ties):
+// one workgroup per segment finds the exact median (coordinate, index) by a
+// radix select and the output offset of every tile's lower half.  Other
+// segments leave at once; their partition tiles find the median themselves.
 __global__ void __launch_bounds__(kTileThreads)
 k_pick(const int32_t* __restrict__ seglist, const SegInfo* __restrict__ segs, const TileInfo* __restrict__ all_tiles,
        const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-       const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, const uint32_t* __restrict__ hist2,
-       const Cand* __restrict__ cand, uint32_t* tile_below, uint32_t* lo_base, Splitter* split)
+       const uint64_t* __restrict__ keys, const uint32_t* __restrict__ seg_over, uint32_t* tile_below,
+       uint32_t* lo_base, Splitter* split)
 {
     __shared__ int sh[kTileThreads / 64];
-    __shared__ uint64_t skey[kCandCap];
-    __shared__ uint32_t sidx[kCandCap];
-    __shared__ uint16_t stile[kCandCap];
     __shared__ Splitter sp;
     const int seg = seglist[blockIdx.x];
+    if (seg_over[seg] == 0u) return;   // uniform per block
     const SegInfo sg = segs[seg];
     const int k = sg.count / 2;
-    int rank, ccount;
-    ClassRule rule = median_class(keys, hist1, hist2, seg, k, &rank, &ccount, sh);
-    const double* C = rule.bk.axis ? Y : X;
-    if (ccount <= kCandCap) {
-        const int n = ccount;
-        int P = 1;
-        while (P < n) P <<= 1;
-        const Cand* cs = cand + (int64_t)seg * kCandCap;
-        for (int i = threadIdx.x; i < P; i += kTileThreads) {
-            if (i < n) {
-                Cand cd = cs[i];
-                skey[i] = okey(cd.c); sidx[i] = (uint32_t)cd.idx; stile[i] = (uint16_t)cd.tile;
-            } else {
-                skey[i] = ~0ull; sidx[i] = 0xffffffffu; stile[i] = 0;
-            }
-        }
-        __syncthreads();
-        for (int kk = 2; kk <= P; kk <<= 1)
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int i = threadIdx.x; i < P / 2; i += kTileThreads) {
-                    int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-                    int hi = lo + j;
-                    bool asc = (lo & kk) == 0;
-                    bool less_hl = (skey[hi] < skey[lo]) || (skey[hi] == skey[lo] && sidx[hi] < sidx[lo]);
-                    if (less_hl == asc) {
-                        uint64_t a = skey[lo]; skey[lo] = skey[hi]; skey[hi] = a;
-                        uint32_t b = sidx[lo]; sidx[lo] = sidx[hi]; sidx[hi] = b;
-                        uint16_t c = stile[lo]; stile[lo] = stile[hi]; stile[hi] = c;
-                    }
-                }
-                __syncthreads();
-            }
-        if (threadIdx.x == 0) { sp.c = okey_inv(skey[rank]); sp.idx = (int32_t)sidx[rank]; sp.pad = 0; }
-        __syncthreads();
-        // lower points of a tile = below its class + its candidates ranked below the median
-        for (int t0 = 0; t0 < sg.ntile; t0 += kTileThreads) {
-            int tt = t0 + threadIdx.x;
-            if (tt < sg.ntile) {
-                int extra = 0;
-                for (int i = 0; i < rank; ++i) extra += (stile[i] == tt);
-                tile_below[sg.tile0 + tt] += (uint32_t)extra;
-            }
-        }
-    } else {
-        exact_select(C, I, sg.start, sg.count, k, &sp);
-        for (int tt = 0; tt < sg.ntile; ++tt) {
-            TileInfo ti = all_tiles[sg.tile0 + tt];
-            int cnt = 0;
-            for (int i = threadIdx.x; i < ti.count; i += kTileThreads)
-                cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
-            int tot2;
-            block_excl_scan<kTileThreads>(cnt, sh, &tot2);
-            if (threadIdx.x == 0) tile_below[sg.tile0 + tt] = (uint32_t)tot2;
-        }
+    const Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)seg);
+    const double* C = bk.axis ? Y : X;
+    exact_select(C, I, sg.start, sg.count, k, &sp);
+    for (int tt = 0; tt < sg.ntile; ++tt) {
+        TileInfo ti = all_tiles[sg.tile0 + tt];
+        int cnt = 0;
+        for (int i = threadIdx.x; i < ti.count; i += kTileThreads)
+            cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
+        int tot2;
+        block_excl_scan<kTileThreads>(cnt, sh, &tot2);
+        if (threadIdx.x == 0) tile_below[sg.tile0 + tt] = (uint32_t)tot2;
     }
     __syncthreads();
     // exclusive scan of the per-tile lower counts into output offsets
@@ -817,27 +776,95 @@ __device__ __forceinline__ void block_minmax2_atomic(const double (&l)[4], const
     }
 }
 
+// The median (coordinate, index) of a segment from its candidate list (the
+// points of the median's class), and the lower points of the tiles before
+// tile `rank_t`: below-class counts of those tiles plus their candidates
+// ranked below the median.  Every tile of the segment computes the same
+// median.  Up to one candidate per thread, a candidate's rank is its count
+// of smaller candidates; longer lists are sorted (bitonic, in LDS).
+__device__ void tile_median(const Cand* __restrict__ cs, int n, int rank, const uint32_t* __restrict__ below,
+                            int rank_t, Splitter* sp, int* lob, int* sh)
+{
+    __shared__ uint64_t skey[kCandCap];
+    __shared__ uint32_t sidx[kCandCap];
+    __shared__ uint32_t stile[kCandCap];
+    __shared__ Splitter ssp;
+    int P = n;
+    if (n > kTileThreads) {
+        P = 1;
+        while (P < n) P <<= 1;
+    }
+    for (int i = threadIdx.x; i < P; i += kTileThreads) {
+        if (i < n) {
+            const Cand cd = cs[i];
+            skey[i] = okey(cd.c);
+            sidx[i] = (uint32_t)cd.idx;
+            stile[i] = (uint32_t)cd.tile;
+        } else {
+            skey[i] = ~0ull; sidx[i] = 0xffffffffu; stile[i] = 0xffffffffu;
+        }
+    }
+    int v = 0;
+    for (int i = threadIdx.x; i < rank_t; i += kTileThreads) v += (int)below[i];
+    __syncthreads();
+    if (n <= kTileThreads) {
+        const int i = threadIdx.x;
+        if (i < n) {
+            const uint64_t ki = skey[i];
+            const uint32_t ii = sidx[i];
+            int ri = 0;
+            for (int j = 0; j < n; ++j) ri += (skey[j] < ki) | ((skey[j] == ki) & (sidx[j] < ii));
+            if (ri == rank) { ssp.c = okey_inv(ki); ssp.idx = (int32_t)ii; ssp.pad = 0; }
+            v += (ri < rank) & ((int)stile[i] < rank_t);
+        }
+    } else {
+        for (int kk = 2; kk <= P; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < P / 2; i += kTileThreads) {
+                    const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                    const int hi = lo + j;
+                    const bool asc = (lo & kk) == 0;
+                    const bool less_hl = (skey[hi] < skey[lo]) || (skey[hi] == skey[lo] && sidx[hi] < sidx[lo]);
+                    if (less_hl == asc) {
+                        const uint64_t a = skey[lo]; skey[lo] = skey[hi]; skey[hi] = a;
+                        const uint32_t b = sidx[lo]; sidx[lo] = sidx[hi]; sidx[hi] = b;
+                        const uint32_t c = stile[lo]; stile[lo] = stile[hi]; stile[hi] = c;
+                    }
+                }
+                __syncthreads();
+            }
+        if (threadIdx.x == 0) { ssp.c = okey_inv(skey[rank]); ssp.idx = (int32_t)sidx[rank]; ssp.pad = 0; }
+        for (int i = threadIdx.x; i < rank; i += kTileThreads) v += ((int)stile[i] < rank_t);
+    }
+    int tot;
+    block_excl_scan<kTileThreads>(v, sh, &tot);   // its barriers also publish ssp
+    *lob = tot;
+    *sp = ssp;
+}
+
 // Stable two-way partition of one tile.  Element i = r * kTileThreads + tid
 // is lower if (coordinate, index) < splitter; its rank among the lower
 // (upper) elements of the tile comes from per-wave ballots of every row,
-// combined with one barrier.
+// combined with one barrier.  The splitter and the tile's output offset come
+// from tile_median, or from k_pick for a segment whose class overflowed.
 __global__ void __launch_bounds__(kTileThreads)
 k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
             double* X2, double* Y2, int32_t* I2, const uint64_t* __restrict__ keys,
-            uint64_t* keys_next, const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
+            uint64_t* keys_next, const uint32_t* __restrict__ hist1, const uint32_t* __restrict__ hist2,
+            const Cand* __restrict__ cand, const uint32_t* __restrict__ tile_below,
+            const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
 {
     constexpr int R = kTile / kTileThreads;
     constexpr int NW = kTileThreads / 64;
     __shared__ int wcnt[R][NW];
+    __shared__ int sh[NW];
     TileInfo t = tiles[blockIdx.x];
     SegInfo sg = segs[t.seg];
-    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
-    Splitter sp = split[t.seg];
     const int k = sg.count / 2;
     const int toff = t.start - sg.start;
-    const int lob = (int)lo_base[sg.tile0 + t.rank];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // the tile's points first: their loads overlap the median search
     double x[R], y[R];
     int32_t id[R];
 #pragma unroll
@@ -845,6 +872,17 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
         const int i = r * kTileThreads + threadIdx.x;
         const int ii = t.start + (i < t.count ? i : 0);
         x[r] = X[ii]; y[r] = Y[ii]; id[r] = I[ii];
+    }
+    int rank, ccount;
+    const ClassRule rule = median_class(keys, hist1, hist2, t.seg, k, &rank, &ccount, sh);
+    const Bucketer& bk = rule.bk;
+    Splitter sp;
+    int lob;
+    if (ccount > kCandCap) {
+        sp = split[t.seg];
+        lob = (int)lo_base[sg.tile0 + t.rank];
+    } else {
+        tile_median(cand + (int64_t)t.seg * kCandCap, ccount, rank, tile_below + sg.tile0, t.rank, &sp, &lob, sh);
     }
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int inwave[R];
@@ -1253,10 +1291,10 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     int64_t nkeys = sc.total_keys;
     DBuf<uint64_t> keys; keys.alloc(kKeyWords * nkeys, s);
     int64_t nseg_split = sc.nstage > 0 ? sc.keys_off[sc.nstage] : 0;   // segments of split stages
-    DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | done | tile_below | tile_extra | lo_base | err
+    DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | overflow flags | tile_below | tile_extra | lo_base | err
     int64_t nh = nseg_split * kBuckets;
     int64_t nt = sc.total_tile;
-    int64_t o_h1 = 0, o_h2 = nh, o_cc = 2 * nh, o_dn = o_cc + nseg_split, o_tb = o_dn + nseg_split;
+    int64_t o_h1 = 0, o_h2 = nh, o_cc = 2 * nh, o_ov = o_cc + nseg_split, o_tb = o_ov + nseg_split;
     int64_t o_te = o_tb + nt, o_lb = o_te + nt, o_err = o_lb + nt, nwords = o_err + 1;
     words.alloc(nwords, s);
     DBuf<Cand> cand; cand.alloc(std::max<int64_t>(nseg_split, 1) * kCandCap, s);
@@ -1285,12 +1323,12 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
         k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
         k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2);
         k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, W + o_h1, W + o_h2,
-                                              cand.p, W + o_cc, W + o_tb);
+                                              cand.p, W + o_cc, W + o_tb, W + o_ov);
         k_pick<<<sc.nact[st], kTileThreads, 0, s>>>(sc.d_act.p + sc.act_off[st], sc.d_segs.p, sc.d_tiles.p, Xb[a],
-                                                   Yb[a], Ib[a], keys.p, W + o_h1, W + o_h2, cand.p, W + o_tb,
-                                                   W + o_lb, split.p);
+                                                   Yb[a], Ib[a], keys.p, W + o_ov, W + o_tb, W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
-                                                Ib[a ^ 1], keys.p, keys.p, split.p, W + o_lb);
+                                                Ib[a ^ 1], keys.p, keys.p, W + o_h1, W + o_h2, cand.p, W + o_tb,
+                                                split.p, W + o_lb);
         check_launch("split stage");
     }
     if (!sc.lds.empty()) {
