@@ -959,7 +959,12 @@ __global__ void k_copy_final(const TileInfo* __restrict__ tiles, const double* X
 // ------------------------------------------------- in-LDS completion kernel
 // Sorted lists LX (by x, index) and LY (by y, index) of local point ids; a
 // split along an axis keeps that axis' list as is (its first floor(n/2)
-// entries are the lower half) and stably partitions the other list.
+// entries are the lower half) and stably partitions the other list.  Both
+// lists hold every sub-segment at the same positions, so a thread owns
+// positions [kPer*tid, kPer*tid + kPer) of both and keeps the sub-segment of
+// each of them (start, count, box) in registers.  posX/posY invert the
+// lists: an element is in the lower half of its sub-segment iff its
+// position in the split axis' list is below start + count/2.
 constexpr int kLdsThreads = 1024;
 constexpr int kPer = kLdsCap / kLdsThreads;
 
@@ -967,17 +972,9 @@ struct LdsSort {
     uint64_t key[kLdsCap];
     uint16_t id[kLdsCap];
 };
-struct LdsSplit {
-    uint16_t LO2[kLdsCap];
-    uint8_t flag[kLdsCap];
-    uint16_t segid[kLdsCap];
-    // sub-segment q of the current stage is [sst[q], sst[q+1]); sst[ns] = n.
-    // At most n sub-segments exist (every leaf keeps >= 1 point).
-    uint16_t sst[2][kLdsCap + 1];
-    // axes and scan offsets are needed only before a split, when there are
-    // at most n/2 sub-segments
-    uint8_t sax[kLdsCap / 2];
-    uint16_t pst[kLdsCap / 2];
+struct LdsPos {
+    uint16_t posX[kLdsCap];
+    uint16_t posY[kLdsCap];
 };
 struct LdsBucket {
     uint32_t cnt[kLdsCap];      // bucket populations, then bucket ends
@@ -985,7 +982,7 @@ struct LdsBucket {
 };
 union LdsUnion {
     LdsSort s;
-    LdsSplit p;
+    LdsPos q;
     LdsBucket b;
 };
 
@@ -1153,95 +1150,100 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
     __syncthreads();
     lds_order(U, xs, idxs, n, LX, sh, red);
     lds_order(U, ys, idxs, n, LY, sh, red);
-    LdsSplit& S = U.p;
-    if (threadIdx.x == 0) { S.sst[0][0] = 0; S.sst[0][1] = (uint16_t)n; }
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) S.segid[i] = 0;
+    uint16_t* posX = U.q.posX;
+    uint16_t* posY = U.q.posY;
+    for (int i = threadIdx.x; i < n; i += kLdsThreads) {
+        posX[LX[i]] = (uint16_t)i;
+        posY[LY[i]] = (uint16_t)i;
+    }
     __syncthreads();
-    int cur = 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int st[kPer], cn[kPer], sid[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) { st[u] = 0; cn[u] = n; sid[u] = 0; }
     for (int d = 0; d <= w.stages; ++d) {
-        int t = w.stage0 + d;
-        int ns = 1 << d;
-        // bounding boxes from the list ends; geometry at even stages; axes
-        for (int q = threadIdx.x; q < ns; q += kLdsThreads) {
-            int st = S.sst[cur][q], cn = S.sst[cur][q + 1] - st;
-            double x0 = xs[LX[st]], x1 = xs[LX[st + cn - 1]];
-            double y0 = ys[LY[st]], y1 = ys[LY[st + cn - 1]];
-            if ((t & 1) == 0) {
-                int64_t box = (int64_t)w.boxbase + level_base(t / 2) + ((int64_t)w.j0 << d) + q;
+        const int t = w.stage0 + d;
+        // split axis of the sub-segment of every owned position, from the
+        // ends of both lists; the head position (the sub-segment's first)
+        // writes the box geometry at even stages
+        int ax[kPer];
+        bool valid[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = kPer * threadIdx.x + u;
+            valid[u] = i < n;
+            ax[u] = 0;
+            if (!valid[u]) continue;
+            if (u > 0 && valid[u - 1] && st[u] == st[u - 1]) { ax[u] = ax[u - 1]; continue; }
+            const int e1 = st[u] + cn[u] - 1;
+            const double x0 = xs[LX[st[u]]], x1 = xs[LX[e1]];
+            const double y0 = ys[LY[st[u]]], y1 = ys[LY[e1]];
+            ax[u] = ((x1 - x0) >= (y1 - y0)) ? 0 : 1;
+            if (i == st[u] && (t & 1) == 0) {
+                const int64_t box = (int64_t)w.boxbase + level_base(t / 2) + ((int64_t)w.j0 << d) + sid[u];
                 double bb[4], gm[3];
                 box_geometry(x0, x1, y0, y1, bb, gm);
                 for (int c = 0; c < 4; ++c) bbox[4 * box + c] = bb[c];
                 for (int c = 0; c < 3; ++c) geom[4 * box + c] = gm[c];
             }
-            if (d < w.stages) S.sax[q] = ((x1 - x0) >= (y1 - y0)) ? 0 : 1;
         }
-        __syncthreads();
         if (d == w.stages) break;
-        // flags: lower half along the split axis
-        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
-            int q = S.segid[i];
-            int rel = i - S.sst[cur][q], kq = (S.sst[cur][q + 1] - S.sst[cur][q]) / 2;
-            uint16_t e = S.sax[q] ? LY[i] : LX[i];
-            S.flag[e] = rel < kq;
-        }
-        __syncthreads();
-        // stable partition of the other list; thread owns positions [kPer*tid, kPer*tid+kPer)
-        int f[kPer];
+        // element of the other list at every owned position and whether it
+        // lies in the lower half along the split axis
         uint16_t e[kPer];
-        int cnt = 0;
+        int f[kPer], lb[kPer];
+        bool tail[kPer];   // no head at or before this position within the thread
+        int run = 0;
+        bool seen = false;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            int i = kPer * threadIdx.x + u;
-            f[u] = 0; e[u] = 0;
-            if (i < n) {
-                int q = S.segid[i];
-                e[u] = S.sax[q] ? LX[i] : LY[i];
-                f[u] = S.flag[e[u]];
+            const int i = kPer * threadIdx.x + u;
+            f[u] = 0;
+            e[u] = 0;
+            if (valid[u]) {
+                e[u] = ax[u] ? LX[i] : LY[i];
+                const int pa = ax[u] ? (int)posY[e[u]] : (int)posX[e[u]];
+                f[u] = (pa - st[u]) < (cn[u] >> 1);
+                if (i == st[u]) { run = 0; seen = true; }
             }
-            cnt += f[u];
-        }
-        int tot;
-        int ex = block_excl_scan<kLdsThreads>(cnt, sh, &tot);
-        int run = ex;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            int i = kPer * threadIdx.x + u;
-            if (i < n && i == S.sst[cur][S.segid[i]]) S.pst[S.segid[i]] = (uint16_t)run;
+            tail[u] = !seen;
+            lb[u] = run;
             run += f[u];
         }
+        // segmented exclusive scan of the lower flags over the positions
+        // (restarting at every sub-segment head): within the wavefront by
+        // shuffles, across wavefronts through one barrier
+        int v = run, hf = seen ? 1 : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int pv = __shfl_up(v, o, 64), ph = __shfl_up(hf, o, 64);
+            if (lane >= o) {
+                if (!hf) v += pv;
+                hf |= ph;
+            }
+        }
+        int ev = __shfl_up(v, 1, 64), eh = __shfl_up(hf, 1, 64);
+        if (lane == 0) { ev = 0; eh = 0; }
+        if (lane == 63) { sh[wid] = v; sh[16 + wid] = hf; }
         __syncthreads();
-        run = ex;
+        int carry = 0;
+        for (int q = 0; q < wid; ++q) carry = sh[16 + q] ? sh[q] : carry + sh[q];
+        const int cin = eh ? ev : carry + ev;
+        // scatter the other list's elements in place (every read of the
+        // lists and positions of this stage came before the barrier) and
+        // step every owned position into its child
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            int i = kPer * threadIdx.x + u;
-            if (i < n) {
-                int q = S.segid[i];
-                int st = S.sst[cur][q], kq = (S.sst[cur][q + 1] - st) / 2, rel = i - st;
-                int lower_before = run - S.pst[q];
-                int dst = f[u] ? st + lower_before : st + kq + (rel - lower_before);
-                S.LO2[dst] = e[u];
-            }
-            run += f[u];
+            if (!valid[u]) continue;
+            const int i = kPer * threadIdx.x + u;
+            const int before = lb[u] + (tail[u] ? cin : 0);   // lower elements in [st, i)
+            const int kq = cn[u] >> 1, rel = i - st[u];
+            const int dst = f[u] ? st[u] + before : st[u] + kq + (rel - before);
+            if (ax[u]) { LX[dst] = e[u]; posX[e[u]] = (uint16_t)dst; }
+            else { LY[dst] = e[u]; posY[e[u]] = (uint16_t)dst; }
+            if (rel < kq) { cn[u] = kq; sid[u] = 2 * sid[u]; }
+            else { st[u] += kq; cn[u] -= kq; sid[u] = 2 * sid[u] + 1; }
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
-            int q = S.segid[i];
-            if (S.sax[q]) LX[i] = S.LO2[i]; else LY[i] = S.LO2[i];
-        }
-        // children of every sub-segment
-        for (int q = threadIdx.x; q < ns; q += kLdsThreads) {
-            int st = S.sst[cur][q], kq = (S.sst[cur][q + 1] - st) / 2;
-            S.sst[cur ^ 1][2 * q] = (uint16_t)st;
-            S.sst[cur ^ 1][2 * q + 1] = (uint16_t)(st + kq);
-        }
-        if (threadIdx.x == 0) S.sst[cur ^ 1][2 * ns] = (uint16_t)n;
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kLdsThreads) {
-            int q = S.segid[i];
-            int rel = i - S.sst[cur][q], kq = (S.sst[cur][q + 1] - S.sst[cur][q]) / 2;
-            S.segid[i] = (uint16_t)(2 * q + (rel >= kq));
-        }
-        cur ^= 1;
         __syncthreads();
     }
     // final order: sorted by (x, index) inside every leaf
