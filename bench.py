@@ -3,8 +3,10 @@
 One step = fmm_build_tree + fmm_plan + fmm_evaluate on device-resident
 positions and strengths (the tree is rebuilt every call, as in a
 time-stepping code).  Workload: 1,000,000 points uniform in the unit square,
-complex N(0,1) strengths (seed 0), theta = 0.5, p = 16 terms (chosen by a
-measured error sweep: mixed e2 <= 0.5e-6), N_levels chosen by a timing sweep.
+complex N(0,1) strengths (seed 0), theta = 0.5; p is chosen for the 1e-6
+error target (fmm_choose_order: the smallest p whose FP64 and mixed results
+agree with an FP64 evaluation at p = 32 to half the target, relative 2-norm
+over all points); N_levels is chosen by a timing sweep.
 The accuracy of both paths is measured against the FP64 direct sum (CPU
 oracle) on a 10,000-target subsample.
 
@@ -27,6 +29,7 @@ PEAK_FP32_NOPACK = 78.6     # TFLOP/s, the same units issuing one FP32 op per la
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X published dense FP32 matrix peak
 P2P_FLOP_PER_PAIR = 16      # per (target, source) pair: see the near-field kernel's header
 M2L_AUTO_SLOTS_MIXED = 8    # M2L pair slots per box chosen automatically for mixed precision
+ERR_TARGET = 1e-6           # relative error target of both forms against the FP64 direct sum
 
 
 def m2l_flop_per_pair(p):
@@ -156,7 +159,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--p", type=int, default=0,
+                    help="expansion order; 0 (default): chosen for the error target by fmm_choose_order")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--levels", type=str, default="8,9,10")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
@@ -184,11 +188,30 @@ def main():
     md = torch.from_numpy(m).to(dev)
     out = torch.empty_like(md)
     stream = torch.cuda.current_stream()
+    # expansion order per N_levels: fixed (--p), or the smallest p whose FP64
+    # and mixed results meet half the error target on that tree
+    p_fixed = p
+    orders = {}
+
+    def order(L):
+        if p_fixed:
+            return p_fixed
+        if L not in orders:
+            t0 = time.perf_counter()
+            tr = F.build_tree(zd, L)
+            pL, (e64, emx) = F.choose_order(tr, md, theta, ERR_TARGET / 2, p_lo=8, p_hi=24)
+            del tr
+            if pL < 0:
+                raise SystemExit("N_levels=%d: no expansion order in [8, 24] reaches half the error target" % L)
+            orders[L] = {"p": pL, "err_fp64": e64, "err_mixed": emx}
+            log("N_levels=%d: expansion order p=%d (fp64 %.2e, mixed %.2e against p=32; %.2f s)" %
+                (L, pL, e64, emx, time.perf_counter() - t0))
+        return orders[L]["p"]
 
     def step(prec, cfg, timing=False):
         L, split, batch = cfg
         tree = F.build_tree(zd, L)
-        pl = F.plan(tree, p, theta, prec, p2p_split=split, m2l_batch=batch, timing=timing)
+        pl = F.plan(tree, order(L), theta, prec, p2p_split=split, m2l_batch=batch, timing=timing)
         F.evaluate(pl, md, out)
         return tree, pl
 
@@ -255,7 +278,7 @@ def main():
         dte = (time.perf_counter() - t1) / args.steps
         phi = out.cpu().numpy()
         # per-phase device times (hipEvents on the evaluation stream) of the same plan shape
-        plt = F.plan(tree, p, theta, prec, p2p_split=cfg[1], m2l_batch=cfg[2], timing=True)
+        plt = F.plan(tree, order(cfg[0]), theta, prec, p2p_split=cfg[1], m2l_batch=cfg[2], timing=True)
         ph = {}
         for r in range(args.steps + 1):
             F.evaluate(plt, md, out)
@@ -264,10 +287,10 @@ def main():
                 for k in ("t_upward_us", "t_m2l_us", "t_l2l_us", "t_p2p_us", "t_downward_us", "t_total_us"):
                     ph[k] = ph.get(k, 0.0) + st[k] / args.steps
         st = plt.stats()
-        res[prec] = dict(L=cfg[0], split=cfg[1], batch=cfg[2], t=dt, t_eval=dte, stats=st, phases=ph,
+        res[prec] = dict(L=cfg[0], p=order(cfg[0]), split=cfg[1], batch=cfg[2], t=dt, t_eval=dte, stats=st, phases=ph,
                          p2p_us=ph["t_p2p_us"], m2l_us=ph["t_m2l_us"], phi=phi)
-        log("%s: L=%d split=%d batch=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, phases %s" %
-            (prec, cfg[0], cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
+        log("%s: L=%d p=%d split=%d batch=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, phases %s" %
+            (prec, cfg[0], order(cfg[0]), cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
              " ".join("%s=%.1f" % (k[2:-3], v) for k, v in ph.items())))
 
     forms = None if args.no_forms else measure_forms(F, W, torch, dev, args.steps, not args.no_cpu)
@@ -285,6 +308,7 @@ def main():
             log("%s e2 vs direct: %.3e" % (prec, err[prec]))
         # CPU oracle (serial FMM O2, its P2P loop OpenMP-parallel) on the full workload
         L = best_cfg["fp64"][0]
+        p = order(L)
         t0 = time.perf_counter()
         oracle.fmm(z, m, p, theta, L)
         tc = time.perf_counter() - t0
@@ -295,6 +319,10 @@ def main():
         log("cpu oracle FMM: %.2f s" % tc)
 
     mx, fp = res["mixed"], res["fp64"]
+    p_rule = ("fixed by --p" if p_fixed else
+              {"rule": "smallest p in [8, 24] whose FP64 and mixed results agree with an FP64 evaluation "
+                       "at p=32 to half the error target (relative 2-norm over all points), per N_levels",
+               "tol": ERR_TARGET / 2, "per_n_levels": {str(k): v for k, v in orders.items()}})
     st = mx["stats"]
     # roofline of the two evaluation kernels (mixed precision), each from its
     # own average launch duration (hipEvents on the evaluation stream); the
@@ -306,7 +334,7 @@ def main():
                 "peak_without_packed_fp32": PEAK_FP32_NOPACK,
                 "frac_without_packed_fp32": tflop / PEAK_FP32_NOPACK,
                 "avg_us": mx["p2p_us"], "pairs": st["n_p2p_pairs"], "flop_per_pair": P2P_FLOP_PER_PAIR}
-    fpp = m2l_flop_per_pair(p)
+    fpp = m2l_flop_per_pair(mx["p"])
     tflop = fpp * st["n_m2l_pairs"] / (mx["m2l_us"] * 1e-6) / 1e12
     slots = mx["batch"] or M2L_AUTO_SLOTS_MIXED   # the counters were taken with the automatic shape
     roof_m2l = {"bound": "mfma", "kernel": "k_m2l<float> (mixed M2L, FP32 MFMA, %d slots per box)" % slots,
@@ -332,9 +360,9 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "uniform unit square N=1e6, complex N(0,1) strengths, seed 0",
-                   "n": n, "p": p, "theta": theta, "n_levels": mx["L"], "p2p_split": mx["split"],
+                   "n": n, "p": mx["p"], "p_rule": p_rule, "theta": theta, "n_levels": mx["L"], "p2p_split": mx["split"],
                    "m2l_batch": mx["batch"], "precision": "mixed", "step": "build_tree+plan+evaluate"},
-        "fp64": {"value": n / fp["t"] / 1e6, "n_levels": fp["L"], "ms_per_step": fp["t"] * 1e3,
+        "fp64": {"value": n / fp["t"] / 1e6, "n_levels": fp["L"], "p": fp["p"], "ms_per_step": fp["t"] * 1e3,
                  "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64"), "phases_us": fp["phases"]},
         "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed"), "phases_us": mx["phases"]},
         "speedup_mixed_vs_fp64": fp["t"] / mx["t"],

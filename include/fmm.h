@@ -261,6 +261,29 @@ void fmm_tuner_destroy(fmm_tuner_t tu);
  * p = ceil(ln(17 TOL (1-theta)) / ln theta), which reproduces Table 4.1. */
 int fmm_p_from_tol(double tol, double theta);
 
+/*
+ * fmm_choose_order -- expansion order from a measured error.  The rule above
+ * bounds the worst case; the error actually reached on a point set is often
+ * several orders of p smaller, since the truncation error falls
+ * geometrically in p at fixed theta (Sec. 2.3).  This call measures it:
+ * the reference is the FP64 evaluation at p = 32 of the same tree and
+ * strengths (its truncation error is below 1e-12 relative at theta <= 0.5);
+ * for p = p_lo .. p_hi the FP64 and the mixed-precision evaluations are
+ * compared with it in the relative 2-norm over all targets,
+ *     e(p) = ||phi_p - phi_ref||_2 / ||phi_ref||_2,
+ * and *p_out receives the smallest p at which both are <= tol, or -1 when no
+ * p in the range reaches it.  err_out (may be NULL) receives
+ * [e_fp64(p), e_mixed(p)] at that p (at p_hi when none qualifies).
+ *   t: tree (one problem or several; the norm runs over all points);
+ *   m: device complex128 [N] strengths, as for fmm_evaluate;
+ *   1 <= p_lo <= p_hi <= 31, 0 < theta < 1, 0 < tol < 1.
+ * Device work on `stream`, temporary device memory of 2 N complex values
+ * plus the plans' own; the call waits for the device.  Errors: FMM_EINVAL
+ * (arguments, non-finite tree), FMM_ENOMEM, FMM_EDEVICE.
+ */
+int fmm_choose_order(fmm_tree_t t, const double* m, double theta, double tol, int p_lo, int p_hi,
+                     void* stream, int* p_out, double* err_out);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* fmm_last_error(void);
 

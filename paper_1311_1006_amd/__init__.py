@@ -88,6 +88,8 @@ def lib():
         "fmm_tuner_best": (C.c_int, [vp, C.POINTER(_TunerParams), dp, dp]),
         "fmm_tuner_destroy": (None, [vp]),
         "fmm_p_from_tol": (C.c_int, [C.c_double, C.c_double]),
+        "fmm_choose_order": (C.c_int, [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, vp,
+                                       C.POINTER(C.c_int), dp]),
         "fmm_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -128,6 +130,18 @@ def p_from_tol(tol, theta):
     if r < 0:
         _check(r)
     return r
+
+
+def choose_order(tree, m, theta=0.5, tol=5e-7, p_lo=8, p_hi=24, stream=None):
+    """Smallest expansion order p in [p_lo, p_hi] whose FP64 and mixed results
+    agree with an FP64 evaluation at p = 32 to `tol` (relative 2-norm over all
+    targets); returns (p, (err_fp64, err_mixed)), p = -1 when none does."""
+    m = _dev_complex(m, "m")
+    p = C.c_int(-1)
+    err = (C.c_double * 2)()
+    _check(lib().fmm_choose_order(tree._h, C.c_void_p(m.data_ptr()), float(theta), float(tol), int(p_lo),
+                                  int(p_hi), _stream(stream), C.byref(p), err))
+    return p.value, (err[0], err[1])
 
 
 class Tree:

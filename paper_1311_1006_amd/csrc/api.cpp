@@ -189,6 +189,47 @@ int fmm_p_from_tol(double tol, double theta)
     return (int)std::ceil(std::log(17.0 * tol * (1.0 - theta)) / std::log(theta));
 }
 
+int fmm_choose_order(fmm_tree_t t, const double* m, double theta, double tol, int p_lo, int p_hi,
+                     void* stream, int* p_out, double* err_out)
+{
+    return guarded([&] {
+        FMM_REQUIRE(t && m && p_out, "NULL argument");
+        *p_out = -1;
+        FMM_REQUIRE(1 <= p_lo && p_lo <= p_hi && p_hi < kMaxP, "need 1 <= p_lo <= p_hi <= 31");
+        FMM_REQUIRE(theta > 0.0 && theta < 1.0, "theta must be in (0, 1)");
+        FMM_REQUIRE(tol > 0.0 && tol < 1.0, "tol must be in (0, 1)");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = t->t.sched->n;
+        DBuf<double> ref, phi;
+        ref.alloc(2 * (size_t)n, s);
+        phi.alloc(2 * (size_t)n, s);
+        // one evaluation through the public calls (a plan per order)
+        auto run = [&](int p, int precision, double* out) {
+            fmm_plan_t pl = nullptr;
+            int rc = fmm_plan(t, p, theta, precision, nullptr, stream, &pl);
+            if (rc != FMM_OK) throw Error(rc, g_err);
+            rc = fmm_evaluate(pl, m, out, stream);
+            const std::string msg = g_err;
+            fmm_plan_destroy(pl);
+            if (rc != FMM_OK) throw Error(rc, msg);
+        };
+        run(kMaxP, FMM_FP64, ref.p);
+        double e[2] = {0.0, 0.0};
+        for (int p = p_lo; p <= p_hi; ++p) {
+            run(p, FMM_FP64, phi.p);
+            e[0] = rel_err2_device(phi.p, ref.p, n, s);
+            run(p, FMM_MIXED, phi.p);
+            e[1] = rel_err2_device(phi.p, ref.p, n, s);
+            if (e[0] <= tol && e[1] <= tol) {
+                *p_out = p;
+                break;
+            }
+        }
+        if (err_out) { err_out[0] = e[0]; err_out[1] = e[1]; }
+    });
+}
+
 int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int* n_levels, void* stream,
                    fmm_tree_t* out)
 {

@@ -256,6 +256,7 @@ int flag_slot_acquire();
 volatile long long* flag_slot_ptr(int slot);
 void flag_slot_release(int slot);
 void evaluate_upward(Plan& pl, const double* m, hipStream_t s);
+double rel_err2_device(const double* a, const double* ref, int64_t n, hipStream_t s);
 constexpr int kNearStream = 0, kListStream = 1;
 hipStream_t side_stream(int device, int which);
 void plan_join(Plan& pl, hipStream_t s);

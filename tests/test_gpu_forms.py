@@ -78,3 +78,33 @@ def test_timestepping_with_tuner(F, orc):
     assert errs[0] <= 1e-6 and errs[7] <= 1e-6
     assert torch.isfinite(zf.real).all() and torch.isfinite(zf.imag).all()
     assert len(hist) == 8 and all(s > 0 for _, s in hist)
+
+
+def test_choose_order_meets_tolerance_against_direct_sum(F, orc):
+    """Measured order selection: the chosen p meets the tolerance against the
+    p = 32 FP64 reference, and against the FP64 direct sum (oracle) as well;
+    no lower order in the range does; a looser tolerance needs no more."""
+    n, L, tol = 40000, 6, 1e-6
+    z, m, _ = W.uniform(n, seed=11)
+    tree = F.build_tree(dev(z), L)
+    md = dev(m)
+    p, (e64, emx) = F.choose_order(tree, md, 0.5, tol, p_lo=4, p_hi=24)
+    assert 4 < p <= 24 and e64 <= tol and emx <= tol, (p, e64, emx)
+    sub = np.arange(0, n, 7)
+    ref = orc.direct(z, m, sub)
+    for prec in ("fp64", "mixed"):
+        out = F.evaluate(F.plan(tree, p, 0.5, prec), md)
+        assert e2(host(out)[sub], ref) <= 1.5 * tol, prec
+    p_below, _ = F.choose_order(tree, md, 0.5, tol, p_lo=4, p_hi=p - 1)
+    assert p_below == -1
+    p_loose, _ = F.choose_order(tree, md, 0.5, 1e-3, p_lo=4, p_hi=24)
+    assert 4 <= p_loose < p
+
+
+def test_choose_order_rejects_bad_arguments(F):
+    z, m, _ = W.uniform(1000, seed=1)
+    tree = F.build_tree(dev(z), 3)
+    md = dev(m)
+    for args in [(0.5, 1e-6, 0, 10), (0.5, 1e-6, 10, 9), (0.5, 1e-6, 4, 32), (1.0, 1e-6, 4, 10), (0.5, 0.0, 4, 10)]:
+        with pytest.raises(F.FmmError):
+            F.choose_order(tree, md, *args)
