@@ -99,6 +99,9 @@ struct TileInfo {
     int32_t start;    // first point
     int32_t count;
     int32_t rank;     // tile index within its segment
+    // the segment's fields the split kernels need, copied here so that a
+    // tile's first load brings them (no second dependent load)
+    int32_t seg_start, seg_count, tile0, child;
 };
 struct LdsWork {      // one segment finished by the in-LDS split kernel
     int32_t start, count;

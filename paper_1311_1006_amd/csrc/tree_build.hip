@@ -133,6 +133,10 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                         ti.start = (int32_t)(st + int64_t(t) * kTile);
                         ti.count = (int32_t)std::min<int64_t>(kTile, cnt - int64_t(t) * kTile);
                         ti.rank = t;
+                        ti.seg_start = si.start;
+                        ti.seg_count = si.count;
+                        ti.tile0 = si.tile0;
+                        ti.child = si.child;
                         sc->tiles.push_back(ti);
                     }
                 }
@@ -184,6 +188,7 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                 ti.start = (int32_t)st;
                 ti.count = (int32_t)std::min<int64_t>(kTile, off[b + 1] - st);
                 ti.rank = 0;
+                ti.seg_start = ti.seg_count = ti.tile0 = ti.child = 0;
                 sc->copy_tiles.push_back(ti);
             }
         }
@@ -529,17 +534,27 @@ __device__ __forceinline__ int sub_of(const SubBucketer& s, double c)
     return (int)fmin(fmax(v, 0.0), (double)(kBuckets - 1));
 }
 
+// the first-level bucket of a segment's median (its rank inside the bucket
+// and the bucket's population), found by hist2 and read by collect
+struct Level1 {
+    int32_t b1, r1, c1, pad;
+};
+
 __global__ void __launch_bounds__(kTileThreads)
 k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
         const double* __restrict__ X, const double* __restrict__ Y,
-        const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, uint32_t* hist2)
+        const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, uint32_t* hist2, Level1* lvl1)
 {
     __shared__ uint32_t h[kBuckets];
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
-    SegInfo sg = segs[t.seg];
     int r1, c1;
-    int b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, sg.count / 2, &r1, &c1, sh);
+    int b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, t.seg_count / 2, &r1, &c1, sh);
+    if (t.rank == 0 && threadIdx.x == 0) {
+        Level1 v;
+        v.b1 = b1; v.r1 = r1; v.c1 = c1; v.pad = 0;
+        lvl1[t.seg] = v;
+    }
     if (c1 <= kSubThreshold) return;   // uniform per block
     Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     if (bk.scale == 0.0) return;  // all points in one bucket: the exact fallback handles it
@@ -567,6 +582,13 @@ struct Cand {
 struct Splitter {
     double c;
     int32_t idx;
+    int32_t pad;
+};
+// the median's class of a segment as collect found it, for the partition
+struct ClassInfo {
+    int32_t rank;     // rank of the median within the class
+    int32_t count;    // points in the class (the candidates, when <= kCandCap)
+    int32_t axis;     // split axis: 0 x, 1 y
     int32_t pad;
 };
 
@@ -636,14 +658,16 @@ __device__ void exact_select(const double* C, const int32_t* I, int start, int c
     __syncthreads();
 }
 
-// the candidate class (one or two histogram levels) of a segment's median
-__device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const uint32_t* hist1, const uint32_t* hist2,
-                                                  int seg, int k, int* rank, int* ccount, int* sh)
+// the candidate class (one or two histogram levels) of a segment's median,
+// from the first-level bucket that hist2 recorded
+__device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const Level1* lvl1, const uint32_t* hist2,
+                                                  int seg, int* rank, int* ccount, int* sh)
 {
     ClassRule rule;
     rule.bk = make_bucketer(keys + kKeyWords * (int64_t)seg);
-    int r1, c1;
-    rule.b1 = find_bucket(hist1 + (int64_t)seg * kBuckets, k, &r1, &c1, sh);
+    const Level1 L1 = lvl1[seg];
+    const int r1 = L1.r1, c1 = L1.c1;
+    rule.b1 = L1.b1;
     rule.b2 = -1;
     *rank = r1;
     *ccount = c1;
@@ -662,17 +686,21 @@ __device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const ui
 __global__ void __launch_bounds__(kTileThreads)
 k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
           const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-          const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1,
+          const uint64_t* __restrict__ keys, const Level1* __restrict__ lvl1,
           const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below,
-          uint32_t* seg_over)
+          uint32_t* seg_over, ClassInfo* cinfo)
 {
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
-    SegInfo sg = segs[t.seg];
     int rank, ccount;
-    ClassRule rule = median_class(keys, hist1, hist2, t.seg, sg.count / 2, &rank, &ccount, sh);
+    ClassRule rule = median_class(keys, lvl1, hist2, t.seg, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
-    if (t.rank == 0 && threadIdx.x == 0) seg_over[t.seg] = overflow ? 1u : 0u;
+    if (t.rank == 0 && threadIdx.x == 0) {
+        seg_over[t.seg] = overflow ? 1u : 0u;
+        ClassInfo ci;
+        ci.rank = rank; ci.count = ccount; ci.axis = rule.bk.axis; ci.pad = 0;
+        cinfo[t.seg] = ci;
+    }
     constexpr int R = kTile / kTileThreads;
     double v[R];
     load_tile(rule.bk.axis ? Y : X, t, v);
@@ -693,7 +721,7 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     }
     int tot;
     block_excl_scan<kTileThreads>(below, sh, &tot);
-    if (threadIdx.x == 0) tile_below[sg.tile0 + t.rank] = (uint32_t)tot;
+    if (threadIdx.x == 0) tile_below[t.tile0 + t.rank] = (uint32_t)tot;
 }
 
 // Segments whose median class holds more than kCandCap points (heavy ties):
@@ -850,8 +878,7 @@ __device__ void tile_median(const Cand* __restrict__ cs, int n, int rank, const 
 __global__ void __launch_bounds__(kTileThreads)
 k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-            double* X2, double* Y2, int32_t* I2, const uint64_t* __restrict__ keys,
-            uint64_t* keys_next, const uint32_t* __restrict__ hist1, const uint32_t* __restrict__ hist2,
+            double* X2, double* Y2, int32_t* I2, uint64_t* keys_next, const ClassInfo* __restrict__ cinfo,
             const Cand* __restrict__ cand, const uint32_t* __restrict__ tile_below,
             const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
 {
@@ -859,10 +886,9 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
     constexpr int NW = kTileThreads / 64;
     __shared__ int wcnt[R][NW];
     __shared__ int sh[NW];
-    TileInfo t = tiles[blockIdx.x];
-    SegInfo sg = segs[t.seg];
-    const int k = sg.count / 2;
-    const int toff = t.start - sg.start;
+    const TileInfo t = tiles[blockIdx.x];
+    const int k = t.seg_count / 2;
+    const int toff = t.start - t.seg_start;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // the tile's points first: their loads overlap the median search
     double x[R], y[R];
@@ -873,16 +899,14 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
         const int ii = t.start + (i < t.count ? i : 0);
         x[r] = X[ii]; y[r] = Y[ii]; id[r] = I[ii];
     }
-    int rank, ccount;
-    const ClassRule rule = median_class(keys, hist1, hist2, t.seg, k, &rank, &ccount, sh);
-    const Bucketer& bk = rule.bk;
+    const ClassInfo ci = cinfo[t.seg];
     Splitter sp;
     int lob;
-    if (ccount > kCandCap) {
+    if (ci.count > kCandCap) {
         sp = split[t.seg];
-        lob = (int)lo_base[sg.tile0 + t.rank];
+        lob = (int)lo_base[t.tile0 + t.rank];
     } else {
-        tile_median(cand + (int64_t)t.seg * kCandCap, ccount, rank, tile_below + sg.tile0, t.rank, &sp, &lob, sh);
+        tile_median(cand + (int64_t)t.seg * kCandCap, ci.count, ci.rank, tile_below + t.tile0, t.rank, &sp, &lob, sh);
     }
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int inwave[R];
@@ -890,7 +914,7 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = r * kTileThreads + threadIdx.x;
-        lower[r] = i < t.count && key_less(bk.axis ? y[r] : x[r], id[r], sp.c, sp.idx);
+        lower[r] = i < t.count && key_less(ci.axis ? y[r] : x[r], id[r], sp.c, sp.idx);
         const unsigned long long m = __ballot(lower[r]);
         inwave[r] = __popcll(m & lt);
         if (lane == 0) wcnt[r][wid] = __popcll(m);
@@ -913,20 +937,20 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             const int lb = before + prev + inwave[r];   // lower elements before i in the tile
             int dst;
             if (lower[r]) {
-                dst = sg.start + lob + lb;
+                dst = t.seg_start + lob + lb;
                 l[0] = fmin(l[0], x[r]); l[1] = fmax(l[1], x[r]); l[2] = fmin(l[2], y[r]); l[3] = fmax(l[3], y[r]);
                 anyl = true;
             } else {
-                dst = sg.start + k + (toff - lob) + (i - lb);
+                dst = t.seg_start + k + (toff - lob) + (i - lb);
                 u[0] = fmin(u[0], x[r]); u[1] = fmax(u[1], x[r]); u[2] = fmin(u[2], y[r]); u[3] = fmax(u[3], y[r]);
                 anyu = true;
             }
-            if (dst >= sg.start && dst < sg.start + sg.count) { X2[dst] = x[r]; Y2[dst] = y[r]; I2[dst] = id[r]; }
+            if (dst >= t.seg_start && dst < t.seg_start + t.seg_count) { X2[dst] = x[r]; Y2[dst] = y[r]; I2[dst] = id[r]; }
         }
         before += rowtot;
     }
-    block_minmax2_atomic(l, u, anyl, anyu, keys_next + kKeyWords * (int64_t)sg.child,
-                         keys_next + kKeyWords * ((int64_t)sg.child + 1));
+    block_minmax2_atomic(l, u, anyl, anyu, keys_next + kKeyWords * (int64_t)t.child,
+                         keys_next + kKeyWords * ((int64_t)t.child + 1));
 }
 
 // geometry of boxes whose bounding box came from a global stage
@@ -1301,6 +1325,8 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     words.alloc(nwords, s);
     DBuf<Cand> cand; cand.alloc(std::max<int64_t>(nseg_split, 1) * kCandCap, s);
     DBuf<Splitter> split; split.alloc(std::max<int64_t>(nseg_split, 1), s);
+    DBuf<ClassInfo> cinfo; cinfo.alloc(std::max<int64_t>(nseg_split, 1), s);
+    DBuf<Level1> lvl1; lvl1.alloc(std::max<int64_t>(nseg_split, 1), s);
     DBuf<int64_t> poff; poff.alloc(sc.nprob + 1, s);
     FMM_HIP(hipMemcpyAsync(poff.p, sc.off.data(), sizeof(int64_t) * (sc.nprob + 1), hipMemcpyHostToDevice, s));
 
@@ -1323,14 +1349,13 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
         const TileInfo* tl = sc.d_tiles.p + sc.tile_off[st];
         int a = st & 1;
         k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
-        k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2);
-        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, W + o_h1, W + o_h2,
-                                              cand.p, W + o_cc, W + o_tb, W + o_ov);
+        k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2, lvl1.p);
+        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, lvl1.p, W + o_h2,
+                                              cand.p, W + o_cc, W + o_tb, W + o_ov, cinfo.p);
         k_pick<<<sc.nact[st], kTileThreads, 0, s>>>(sc.d_act.p + sc.act_off[st], sc.d_segs.p, sc.d_tiles.p, Xb[a],
                                                    Yb[a], Ib[a], keys.p, W + o_ov, W + o_tb, W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
-                                                Ib[a ^ 1], keys.p, keys.p, W + o_h1, W + o_h2, cand.p, W + o_tb,
-                                                split.p, W + o_lb);
+                                                Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb);
         check_launch("split stage");
     }
     if (!sc.lds.empty()) {
