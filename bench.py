@@ -77,15 +77,47 @@ def _time(fn, reps, torch):
     return (time.perf_counter() - t0) / reps
 
 
-def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4):
+def measure_theta(F, W, torch, dev, reps, tol=1e-6, n_levels=9):
+    """Static theta sweep (Sec. 4.1): N = 1e6 uniform and line-like points,
+    mixed precision, p from tol and theta by Table 4.1's rule, a fixed tree
+    (N_levels 9); time of plan + evaluate per theta in [0.35, 0.65]."""
+    out = {}
+    thetas = [round(0.35 + 0.01 * k, 2) for k in range(31)]
+    z_u, m_u, _ = W.uniform(1_000_000, seed=0)
+    for name, (z, m) in (("uniform", (z_u, m_u)), ("line", W.line_like(1_000_000, seed=0))):
+        zd = torch.from_numpy(z).to(dev)
+        md = torch.from_numpy(m).to(dev)
+        ob = torch.empty_like(md)
+        tree = F.build_tree(zd, n_levels)
+        res = {}
+        for th in thetas:
+            p = F.p_from_tol(tol, th)
+            t = _time(lambda: F.evaluate(F.plan(tree, p, th, "mixed"), md, ob), reps, torch)
+            res["%.2f" % th] = {"p": p, "ms": t * 1e3}
+        best = min(res, key=lambda k: res[k]["ms"])
+        out["theta_sweep_" + name] = {"n_levels": n_levels, "tol": tol, "rule": "p = fmm_p_from_tol(tol, theta)",
+                                      "ms_by_theta": res, "best_theta": float(best), "best_ms": res[best]["ms"],
+                                      "ms_at_0.50": res["0.50"]["ms"]}
+        log("theta sweep (%s): best theta %s (p=%d) %.3f ms; theta 0.50 (p=%d) %.3f ms" %
+            (name, best, res[best]["p"], res[best]["ms"], res["0.50"]["p"], res["0.50"]["ms"]))
+        del tree
+    return out
+
+
+def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4, tune_theta=False):
     """Clustered N = 1e6 (90% in 32 Gaussian clusters, sigma = 1e-3, strengths
     +-1): `steps` explicit Euler steps z += dt conj(phi)/(2 pi i), tree rebuilt
-    and the tuner consulted every step (mixed precision, p = 16, theta = 0.5).
-    Reports per-step device time and, every 10 steps, e2 against the FP64 direct
-    sum on a 10,000-target subsample (CPU oracle)."""
+    and the tuner consulted every step (mixed precision, p = 16, theta = 0.5;
+    with tune_theta the AT3b walk also moves theta, p following it by Table
+    4.1's rule for 1e-6).  Reports per-step device time and, every 10 steps,
+    e2 against the FP64 direct sum on a 10,000-target subsample (CPU oracle)."""
     from paper_1311_1006_amd.driver import advect, make_tuner
     z, m = W.clustered(1_000_000, seed=0)
-    tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6)
+    if tune_theta:
+        tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6, theta=0.5, theta_interval=4,
+                        theta_min=0.35, theta_max=0.65, tol=1e-6)
+    else:
+        tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6)
     errs = {}
 
     def check(step, zt, phi, prm, sec):
@@ -100,12 +132,13 @@ def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4):
                       tuner=tu, callback=check)
     times = [sec for _, sec in hist]
     best = tu.best()[0]
-    res = {"timestep_clustered_n1e6": {"steps": steps + 1, "ms_per_step_mean": 1e3 * float(np.mean(times)),
+    key = "timestep_clustered_n1e6" + ("_theta_tuned" if tune_theta else "")
+    res = {key: {"steps": steps + 1, "ms_per_step_mean": 1e3 * float(np.mean(times)),
                                        "ms_per_step_median": 1e3 * float(np.median(times)),
                                        "mpoints_s_median": 1e6 / float(np.median(times)) / 1e6,
                                        "tuned": best, "e2_every_10_steps": errs or None}}
-    log("time stepping clustered N=1e6: median %.3f ms/step, tuned %s, e2 %s" %
-        (1e3 * float(np.median(times)), best, errs))
+    log("time stepping clustered N=1e6%s: median %.3f ms/step, tuned %s, e2 %s" %
+        (" (theta walked)" if tune_theta else "", 1e3 * float(np.median(times)), best, errs))
     return res
 
 
@@ -138,6 +171,8 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
         log("batch of 128 (%s): graph %.3f ms, 128 sequential launches %.3f ms" % (prec, tb * 1e3, ts * 1e3))
         del singles, pg, tree
     out.update(measure_timestepping(F, W, torch, dev, with_errors))
+    out.update(measure_timestepping(F, W, torch, dev, with_errors, tune_theta=True))
+    out.update(measure_theta(F, W, torch, dev, max(3, reps // 4)))
     z, m, _ = W.uniform(200000, seed=0)
     zd = torch.from_numpy(z).to(dev)
     md = torch.from_numpy(m).to(dev)

@@ -225,27 +225,58 @@ int fmm_plan_download_list(fmm_plan_t pl, int prob, int level, int kind, int64_t
 /* ---- autotuner (host only) ---------------------------------------------- */
 
 /*
- * Directed-walk autotuner with cost capping, after Algorithm 4 (AT3b) of
- * Sec. 4.2, over the integer knobs N_levels, P2P split and M2L batch, fed one
- * measured iteration time per call.  Rules kept from Sec. 4.2: a move is
- * accepted or rejected on the timings that follow it, noise is handled by
- * using the minimum time over a short window, a rejected move reverses the
- * direction, and after a rejected N_levels move the next move in that
- * direction is scheduled so that the accumulated cost of rejected moves
- * stays below `cap` times the accumulated run time.
+ * Online autotuner after Sec. 4.2, fed one measured iteration time per call.
+ * Rules kept from Sec. 4.2: a move is accepted or rejected on the timings
+ * that follow it; noise is handled by judging a configuration by the minimum
+ * time over a short window (window = 1 compares single iterations, as the
+ * algorithms are printed); N_levels moves first when due, then theta, then
+ * the launch-shape knobs.  Three walks (`algorithm`):
+ *   FMM_TUNER_AT3B (Algorithm 4): directed walk; after a rejected N_levels
+ *     move the next move in that direction is scheduled so that the
+ *     accumulated cost of rejected moves stays below `cap` times the run
+ *     time; theta moves as in AT2; in addition the P2P split and M2L batch
+ *     knobs walk every knob_interval iterations, reversing on rejection.
+ *   FMM_TUNER_AT2 (Algorithm 2): directed walk; N_levels moves every
+ *     level_interval iterations in its current direction, reversed on
+ *     rejection; theta moves every theta_interval iterations by
+ *     thetastep * theta_unit in its direction; a rejected theta move reverses
+ *     the direction and takes the next step length of a Fibonacci cycle
+ *     (fib(1), fib(2), ... up to fib(fiblength - 1), then back to fib(1) with
+ *     fiblength one longer), so that a walk held at an apparent optimum probes
+ *     ever farther on both sides.
+ *   FMM_TUNER_AT1 (Algorithm 1): random walk; N_levels (every level_interval
+ *     iterations) and theta (every theta_interval, one theta_unit) move in a
+ *     random direction (a SplitMix64 stream from `seed`).
+ * theta stays on the grid theta_min + k * theta_unit inside
+ * [theta_min, theta_max]; a move that would leave it is turned back (AT2,
+ * AT3b) or mirrored (AT1).  theta_interval = 0 keeps theta at init.theta.
+ * With tol > 0 every parameter set carries p = fmm_p_from_tol(tol, theta)
+ * (Table 4.1's rule), so that theta acts as a pure performance knob (Sec.
+ * 2.3); with tol = 0 p stays at init.p.
  */
 typedef struct fmm_tuner_s* fmm_tuner_t;
 
+enum { FMM_TUNER_AT3B = 0, FMM_TUNER_AT2 = 1, FMM_TUNER_AT1 = 2 };
+
 typedef struct {
     int n_levels, p2p_split, m2l_batch;
+    int p;                      /* expansion order for theta (see tol) */
+    double theta;
 } fmm_tuner_params;
 
 typedef struct {
     fmm_tuner_params init;      /* starting point */
     int min_levels, max_levels; /* N_levels range (inclusive) */
-    double cap;                 /* max tuning cost / run time, e.g. 0.1 */
+    double cap;                 /* max tuning cost / run time, e.g. 0.1 (AT3b) */
     int window;                 /* iterations whose minimum time decides a move (>= 1) */
-    int knob_interval;          /* iterations between P2P/M2L knob moves (>= 1) */
+    int knob_interval;          /* iterations between P2P/M2L knob moves (>= 1, AT3b) */
+    int algorithm;              /* FMM_TUNER_AT3B, FMM_TUNER_AT2 or FMM_TUNER_AT1 */
+    int level_interval;         /* iterations between N_levels moves (AT1, AT2; >= 1) */
+    int theta_interval;         /* iterations between theta moves; 0: theta fixed */
+    int fib_length;             /* initial Fibonacci cycle length (>= 2; AT2, AT3b) */
+    double theta_min, theta_max, theta_unit;   /* theta grid, e.g. 0.3, 0.7, 0.01 */
+    double tol;                 /* > 0: p from tol and theta; 0: p fixed */
+    unsigned long long seed;    /* AT1 directions */
 } fmm_tuner_config;
 
 int fmm_tuner_create(const fmm_tuner_config* cfg, fmm_tuner_t* out);

@@ -48,12 +48,19 @@ class _Stats(C.Structure):
 
 
 class _TunerParams(C.Structure):
-    _fields_ = [("n_levels", C.c_int), ("p2p_split", C.c_int), ("m2l_batch", C.c_int)]
+    _fields_ = [("n_levels", C.c_int), ("p2p_split", C.c_int), ("m2l_batch", C.c_int), ("p", C.c_int),
+                ("theta", C.c_double)]
 
 
 class _TunerConfig(C.Structure):
     _fields_ = [("init", _TunerParams), ("min_levels", C.c_int), ("max_levels", C.c_int),
-                ("cap", C.c_double), ("window", C.c_int), ("knob_interval", C.c_int)]
+                ("cap", C.c_double), ("window", C.c_int), ("knob_interval", C.c_int),
+                ("algorithm", C.c_int), ("level_interval", C.c_int), ("theta_interval", C.c_int),
+                ("fib_length", C.c_int), ("theta_min", C.c_double), ("theta_max", C.c_double),
+                ("theta_unit", C.c_double), ("tol", C.c_double), ("seed", C.c_ulonglong)]
+
+
+_ALGORITHMS = {"at3b": 0, "at2": 1, "at1": 2}
 
 
 _lib = None
@@ -262,17 +269,22 @@ def evaluate_adjoint(pl, m, g_phi, stream=None):
 
 
 class Tuner:
-    """Online autotuner (AT3b-style, Sec. 4.2) over N_levels, P2P split and
-    M2L batch; host only."""
+    """Online autotuner (Sec. 4.2; host only): the AT3b, AT2 or AT1 walk over
+    N_levels and, with theta_interval > 0, theta (p following theta by
+    Table 4.1's rule when tol > 0); AT3b also walks the P2P split and M2L
+    batch knobs."""
 
     def __init__(self, n_levels, min_levels, max_levels, p2p_split=4, m2l_batch=4, cap=0.1, window=3,
-                 knob_interval=6):
-        cfg = _TunerConfig(_TunerParams(n_levels, p2p_split, m2l_batch), min_levels, max_levels, cap, window,
-                           knob_interval)
+                 knob_interval=6, algorithm="at3b", level_interval=6, theta=0.5, theta_interval=0,
+                 theta_min=0.3, theta_max=0.7, theta_unit=0.01, fib_length=4, tol=0.0, p=0, seed=0):
+        cfg = _TunerConfig(_TunerParams(n_levels, p2p_split, m2l_batch, p, theta), min_levels, max_levels, cap,
+                           window, knob_interval, _ALGORITHMS[algorithm], level_interval, theta_interval,
+                           fib_length, theta_min, theta_max, theta_unit, tol, seed)
         self._h = C.c_void_p()
         rc = lib().fmm_tuner_create(C.byref(cfg), C.byref(self._h))
         if rc != 0:
             raise FmmError(rc, "invalid tuner configuration")
+        self.tunes_theta = theta_interval > 0 or tol > 0.0   # its parameters carry theta and p
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -282,7 +294,7 @@ class Tuner:
     def next(self):
         p = _TunerParams()
         _check(lib().fmm_tuner_next(self._h, C.byref(p)))
-        return {"n_levels": p.n_levels, "p2p_split": p.p2p_split, "m2l_batch": p.m2l_batch}
+        return _params_dict(p)
 
     def observe(self, seconds):
         _check(lib().fmm_tuner_observe(self._h, float(seconds)))
@@ -291,7 +303,12 @@ class Tuner:
         p = _TunerParams()
         cost, run = C.c_double(), C.c_double()
         _check(lib().fmm_tuner_best(self._h, C.byref(p), C.byref(cost), C.byref(run)))
-        return {"n_levels": p.n_levels, "p2p_split": p.p2p_split, "m2l_batch": p.m2l_batch}, cost.value, run.value
+        return _params_dict(p), cost.value, run.value
+
+
+def _params_dict(p):
+    return {"n_levels": p.n_levels, "p2p_split": p.p2p_split, "m2l_batch": p.m2l_batch, "p": p.p,
+            "theta": p.theta}
 
 
 def update_positions(tree, z, stream=None):

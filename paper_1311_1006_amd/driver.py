@@ -38,7 +38,9 @@ def advect(z, m, steps, dt, p=16, theta=0.5, precision="mixed", tuner=None, n_le
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         tree = build_tree(z, L)
-        pl = plan(tree, p, theta, precision, p2p_split=prm["p2p_split"], m2l_batch=prm["m2l_batch"])
+        # a tuner that walks theta also carries the order for it (p from its tolerance)
+        pp, th = (prm["p"], prm["theta"]) if getattr(tuner, "tunes_theta", False) else (p, theta)
+        pl = plan(tree, pp, th, precision, p2p_split=prm["p2p_split"], m2l_batch=prm["m2l_batch"])
         phi = evaluate(pl, m)
         e1.record()
         e1.synchronize()

@@ -108,3 +108,27 @@ def test_choose_order_rejects_bad_arguments(F):
     for args in [(0.5, 1e-6, 0, 10), (0.5, 1e-6, 10, 9), (0.5, 1e-6, 4, 32), (1.0, 1e-6, 4, 10), (0.5, 0.0, 4, 10)]:
         with pytest.raises(F.FmmError):
             F.choose_order(tree, md, *args)
+
+
+def test_timestepping_with_theta_walk(F, orc):
+    """The driver evaluates with the theta and p the tuner hands out (AT3b
+    with a theta walk, p from the tolerance by Table 4.1's rule), and every
+    such evaluation meets the tolerance against the FP64 direct sum."""
+    import torch
+    from paper_1311_1006_amd.driver import advect, make_tuner
+    z, m = W.clustered(60000, seed=2, nclusters=16)
+    tu = make_tuner(z.size, cap=0.1, window=1, knob_interval=5, theta=0.5, theta_interval=1, theta_min=0.40,
+                    theta_max=0.60, tol=1e-6)
+    seen = []
+
+    def check(step, zt, phi, prm, sec):
+        assert prm["p"] == F.p_from_tol(1e-6, prm["theta"])
+        if step % 3 == 0:
+            zh = host(zt)
+            sub = W.subsample(zh.size, 800, seed=step)
+            seen.append((prm["theta"], prm["p"], e2(host(phi)[sub], orc.direct(zh, m, sub))))
+
+    zf, hist = advect(dev(z), dev(m), 12, 1e-4, precision="mixed", tuner=tu, callback=check)
+    assert all(err <= 1e-6 for _, _, err in seen), seen
+    assert len({th for th, _, _ in seen}) >= 2 or len({round(h[0]["theta"], 6) for h in hist}) >= 2
+    assert torch.isfinite(zf.real).all() and torch.isfinite(zf.imag).all()
