@@ -323,7 +323,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
             launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], nn, ex.child0.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p, s);
         }
         const Plan::Balance& bm = pl.bal_m2l;
-        launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, bm.xitems.p, (int)bm.total, bm.icnt.p, bm.ioff.p, bm.partial.p,
+        launch_m2l<T>(nullptr, (int)sc.nbox, bm.xitems.p, (int)bm.total, bm.icnt.p, bm.ioff.p, bm.partial.p,
                       bm.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, pl.amp.p,
                       pl.aloc.p, s, pl.tune.m2l_batch, nullptr);
         for (int l = 1; l + 1 < sc.max_levels; ++l) {

@@ -111,9 +111,6 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
     }
     ex.m2m_off[ml] = (int64_t)m2m.size();
     upload_vec(ex.d_m2m, m2m, s);
-    std::vector<int32_t> iota(sc.nbox);
-    for (int64_t i = 0; i < sc.nbox; ++i) iota[i] = (int32_t)i;
-    upload_vec(ex.all_boxes, iota, s);
     // P2P work items grouped by launch shape
     const bool mixed = pl.precision == FMM_MIXED;
     std::map<std::pair<int, int>, std::vector<P2PItemH>> cls;
@@ -215,7 +212,7 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const Plan::Balance& b = pl.bal_m2l;
-    launch_m2l<T>(ex.all_boxes.p, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
+    launch_m2l<T>(nullptr, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
                   b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
                   pl.tune.m2l_batch, guard);
     tm.mark();

@@ -155,6 +155,7 @@ struct TreeSchedule {
     DBuf<GeomJob> d_geom;
     DBuf<int32_t> d_box_start, d_box_count, d_box_parent;
     DBuf<int32_t> d_box_prob;
+    DBuf<int64_t> d_off;           // point offsets of the problems [nprob + 1]
     DBuf<int8_t> d_box_level;
 };
 

@@ -171,7 +171,7 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     int g = 0, nch = 1, nw = 0, wb = 0;
     if (item_ok) {
         xe = xitems ? xitems[xi] : make_int2(xi, 0);
-        g = boxes[xe.x];
+        g = boxes ? boxes[xe.x] : xe.x;
         nch = icnt ? icnt[xe.x] : 1;
         const int nw_all = w_cnt[g], p0 = xe.y * kChunkPairs;
         nw = nch == 1 ? nw_all : min(kChunkPairs, nw_all - p0);   // pairs of this item
@@ -388,13 +388,13 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
         re += partial[2 * ((o + k) * p + row)];
         im += partial[2 * ((o + k) * p + row) + 1];
     }
-    T* dst = loc + 2 * ((int64_t)boxes[i] * p + row);
+    T* dst = loc + 2 * ((int64_t)(boxes ? boxes[i] : i) * p + row);
     dst[0] = (T)re;
     dst[1] = (T)im;
 }
 
-// Every box of `boxes` gets its local expansion written (zeros for a box
-// without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
+// Every box of `boxes` (NULL: boxes 0 .. n-1, no lookup) gets its local
+// expansion written (zeros for a box without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
 // box index; partial holds the chunks of split lists.  batch: pair slots of
 // one item in each 16-pair MFMA block: 16 (one item per wavefront), 8 (two)
 // or 4 (four items share a wavefront); 0 = automatic (8 for FP32, 4 for

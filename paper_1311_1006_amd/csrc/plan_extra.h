@@ -23,7 +23,7 @@ struct PlanExtra {
     DBuf<double> binom;                             // binomial table C(n, k), n, k < 64
     std::vector<std::vector<int32_t>> m2m_boxes;   // non-leaf boxes per level
     std::vector<int64_t> m2m_off;
-    DBuf<int32_t> d_m2m, child0, all_boxes;
+    DBuf<int32_t> d_m2m, child0;
     DBuf<char> p2p_items;
     std::vector<P2PClass> p2p_class;
     DBuf<char> adj_items;                           // adjoint P2P work items

@@ -235,6 +235,7 @@ void upload_schedule(TreeSchedule& sc, hipStream_t s)
     upload(sc.d_box_parent, sc.box_parent, s);
     upload(sc.d_box_level, sc.box_level, s);
     upload(sc.d_box_prob, sc.box_prob, s);
+    upload(sc.d_off, sc.off, s);
     // the host vectors must stay alive until the copies ran
     FMM_HIP(hipStreamSynchronize(s));
 }
@@ -364,20 +365,15 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-// bounding-box keys (every copy): kxmin kxmax kymin kymax = empty box; the
-// tree's error word cleared
-__global__ void k_fill_keys(uint64_t* k, int64_t nwords, uint32_t* err)
+// start of a build: the counter words zeroed; the bounding-box keys (every
+// copy: kxmin kxmax kymin kymax) set to the empty box; the tree's error word
+// cleared
+__global__ void k_fill_start(uint32_t* words, int64_t nwords, uint64_t* k, int64_t nkeywords, uint32_t* err)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
-         i += (int64_t)gridDim.x * blockDim.x)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += stride) words[i] = 0u;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nkeywords; i += stride)
         k[i] = (i & 1) ? 0ull : ~0ull;
 }
 
@@ -1327,18 +1323,16 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     DBuf<Splitter> split; split.alloc(std::max<int64_t>(nseg_split, 1), s);
     DBuf<ClassInfo> cinfo; cinfo.alloc(std::max<int64_t>(nseg_split, 1), s);
     DBuf<Level1> lvl1; lvl1.alloc(std::max<int64_t>(nseg_split, 1), s);
-    DBuf<int64_t> poff; poff.alloc(sc.nprob + 1, s);
-    FMM_HIP(hipMemcpyAsync(poff.p, sc.off.data(), sizeof(int64_t) * (sc.nprob + 1), hipMemcpyHostToDevice, s));
 
-    k_fill_u32<<<grid_for(nwords, 256), 256, 0, s>>>(words.p, nwords, 0u);
-    k_fill_keys<<<grid_for(kKeyWords * nkeys, 256), 256, 0, s>>>(keys.p, kKeyWords * nkeys, t.err.p);
+    k_fill_start<<<grid_for(std::max<int64_t>(nwords, kKeyWords * nkeys), 256), 256, 0, s>>>(
+        words.p, nwords, keys.p, kKeyWords * nkeys, t.err.p);
     check_launch("fill");
     uint32_t* W = words.p;
     // init: every problem's root segment is stage-0 key segment b
     int64_t maxn = 0;
     for (int b = 0; b < sc.nprob; ++b) maxn = std::max(maxn, sc.off[b + 1] - sc.off[b]);
     dim3 gi((unsigned)((maxn + kTile - 1) / kTile), (unsigned)sc.nprob);
-    k_init<<<gi, kTileThreads, 0, s>>>(z, poff.p, sc.nprob, XA.p, YA.p, IA.p, keys.p, t.err.p);
+    k_init<<<gi, kTileThreads, 0, s>>>(z, sc.d_off.p, sc.nprob, XA.p, YA.p, IA.p, keys.p, t.err.p);
     check_launch("init");
     double* Xb[2] = {XA.p, XB.p};
     double* Yb[2] = {YA.p, YB.p};
