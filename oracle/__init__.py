@@ -8,6 +8,7 @@ re/im in memory), indices as ``int64``.
 Functions (each follows the paper passage named in the C source):
   direct(z, m, targets=None)           O1, eq. (2.1)/(2.2), exclusion by position
   direct_points(z, m, y)               eq. (2.2), separate evaluation points
+  direct_deriv_points(z, m, y)         the y-derivative of (2.2)'s field
   direct_compensated(z, m)             O1 with Neumaier summation
   grad_direct(z, m, g)                 O3, gradient through the direct sum
   tree(z, L)                           balanced median-split pyramid, Sec. 2.2
@@ -35,6 +36,7 @@ def lib():
         i64 = C.c_int64
         L.oracle_direct.argtypes = [i64, dp, dp, i64, ip, dp]
         L.oracle_direct_points.argtypes = [i64, dp, dp, i64, dp, dp]
+        L.oracle_direct_deriv_points.argtypes = [i64, dp, dp, i64, dp, dp]
         L.oracle_direct_compensated.argtypes = [i64, dp, dp, dp]
         L.oracle_grad_direct.argtypes = [i64, dp, dp, dp, dp, dp]
         L.oracle_p2m.argtypes = [dp, i64, dp, dp, C.c_int, dp]
@@ -89,6 +91,13 @@ def direct_points(z, m, y):
     z, m, y = _c(z), _c(m), _c(y)
     out = np.zeros(y.size, np.complex128)
     lib().oracle_direct_points(z.size, _dp(z), _dp(m), y.size, _dp(y), _dp(out))
+    return out
+
+
+def direct_deriv_points(z, m, y):
+    z, m, y = _c(z), _c(m), _c(y)
+    out = np.zeros(y.size, np.complex128)
+    lib().oracle_direct_deriv_points(z.size, _dp(z), _dp(m), y.size, _dp(y), _dp(out))
     return out
 
 

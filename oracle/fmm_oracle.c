@@ -16,7 +16,8 @@
  *       with the strong / weak / decoupled connectivity of Sec. 2.1 and the
  *       theta-criterion (2.3), in the unscaled textbook form of the
  *       multipole / local expansions (Sec. 2.1, harmonic kernel of Sec. 3.3);
- *   O3  analytic gradient of a real loss through the direct sum;
+ *   O3  analytic gradient of a real loss through the direct sum, and the
+ *       derivative of the field at separate evaluation points;
  *   the p(TOL, theta) rule that reproduces Table 4.1.
  *
  * Conventions
@@ -99,6 +100,26 @@ void oracle_direct_points(int64_t n, const double* z, const double* m,
             acc = c_add(acc, c_div(ld(m, j), w));
         }
         st(phi, t, acc);
+    }
+}
+
+/* Derivative of the field of eq. (2.2) at separate points y: the y-derivative
+ * of m_j / (y - x_j) is -m_j / (y - x_j)^2; sources at the evaluation point
+ * are left out, as in the potential.  Evaluating at the sources themselves
+ * (y = z) gives the derivative of (2.1)'s field with the self term removed. */
+void oracle_direct_deriv_points(int64_t n, const double* z, const double* m,
+                                int64_t ny, const double* y, double* dphi)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < ny; ++t) {
+        cplx yi = ld(y, t), acc = c_make(0.0, 0.0);
+        for (int64_t j = 0; j < n; ++j) {
+            cplx w = c_sub(yi, ld(z, j));
+            if (w.re == 0.0 && w.im == 0.0) continue;
+            cplx iw = c_inv(w);
+            acc = c_sub(acc, c_mul(ld(m, j), c_mul(iw, iw)));
+        }
+        st(dphi, t, acc);
     }
 }
 

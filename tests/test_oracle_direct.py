@@ -18,6 +18,45 @@ def test_roots_of_unity_closed_form(orc):
         assert orc.rel_errinf(phi, ref) < 1e-13
 
 
+def test_derivative_roots_of_unity_closed_form(orc):
+    # N unit charges at z_k = c + u_k, u_k^N = R^N.  With P = prod (z - z_j) =
+    # (z - c)^N - R^N and Q = P/(z - z_k): sum_{j!=k} 1/(z_k - z_j)^2 =
+    # (Q'/Q)^2 - Q''/Q at z_k = (P''/(2P'))^2 - P'''/(3P') = (N-1)(5-N)/(12 u^2),
+    # so the field's derivative there (self term left out) is (N-1)(N-5)/(12 u^2).
+    for n, c, R in [(2, 0.0, 1.0), (7, 0.0, 1.0), (64, 0.3 - 0.2j, 0.01), (301, 2.0 + 1.0j, 3.0)]:
+        z = W.roots_of_unity(n, c, R, phase=0.321)
+        d = orc.direct_deriv_points(z, np.ones(n), z)
+        ref = (n - 1) * (n - 5) / (12 * (z - c) ** 2)
+        if n == 5:
+            ref = np.zeros(n)
+        assert orc.rel_errinf(d, ref) < 1e-12, n
+
+
+def test_derivative_matches_central_differences_of_the_field(orc):
+    rng = np.random.default_rng(3)
+    z = rng.random(300) + 1j * rng.random(300)
+    m = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    y = 0.2 + 0.6 * (rng.random(40) + 1j * rng.random(40))
+    d = orc.direct_deriv_points(z, m, y)
+
+    def err(h):
+        fd = (orc.direct_points(z, m, y + h) - orc.direct_points(z, m, y - h)) / (2 * h)
+        return np.max(np.abs(fd - d)) / np.max(np.abs(d))
+    for h in (1e-6, 1e-6j):       # holomorphic: the same derivative along x and along y
+        assert err(h) <= 1e-6
+    # the difference converges to it at second order
+    assert 80 < err(1e-4) / err(1e-5) < 120
+
+
+def test_derivative_leaves_out_coincident_sources(orc):
+    rng = np.random.default_rng(4)
+    z = rng.random(50) + 1j * rng.random(50)
+    m = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    a = orc.direct_deriv_points(z, m, z[:1])
+    b = orc.direct_deriv_points(z[1:], m[1:], z[:1])
+    assert a[0] == b[0]
+
+
 def test_equispaced_line_harmonic_numbers(orc):
     # z_k = k h, unit strengths: phi_k = (H_k - H_{N-1-k}) / h
     for n, h in [(10, 1.0), (300, 1e-3)]:
