@@ -173,6 +173,20 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
     out.update(measure_timestepping(F, W, torch, dev, with_errors))
     out.update(measure_timestepping(F, W, torch, dev, with_errors, tune_theta=True))
     out.update(measure_theta(F, W, torch, dev, max(3, reps // 4)))
+    # field and its derivative (fmm_evaluate_field) against the plain evaluation
+    z, m, _ = W.uniform(1_000_000, seed=0)
+    zd = torch.from_numpy(z).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    tree = F.build_tree(zd, 9)
+    for prec in ("mixed", "fp64"):
+        pl = F.plan(tree, 13, 0.5, prec)
+        phi, dphi = torch.empty_like(md), torch.empty_like(md)
+        te = _time(lambda: F.evaluate(pl, md, phi), reps, torch)
+        tf = _time(lambda: F.evaluate_field(pl, md, phi, dphi), reps, torch)
+        out["field_n1e6_" + prec] = {"p": 13, "n_levels": 9, "evaluate_ms": te * 1e3, "field_ms": tf * 1e3,
+                                     "ratio": tf / te}
+        log("field N=1e6 (%s, p=13): evaluate %.3f ms, evaluate_field %.3f ms" % (prec, te * 1e3, tf * 1e3))
+    del tree, phi, dphi
     z, m, _ = W.uniform(200000, seed=0)
     zd = torch.from_numpy(z).to(dev)
     md = torch.from_numpy(m).to(dev)

@@ -177,6 +177,23 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
                        void* stream);
 
 /*
+ * fmm_evaluate_field -- phi as fmm_evaluate, plus the derivative of the field
+ * at every point,
+ *     dphi_i = dphi/dz (z_i) = -sum_{z_j != z_i} m_j / (z_i - z_j)^2
+ * (the y-derivative of eq. 2.2's field; in a vortex method the derivative of
+ * the velocity, Sec. 5.1).  The near field is summed directly over the strong
+ * lists, the far field is the derivative of each leaf's local expansion (Sec.
+ * 2.1), whose truncation error is larger than that of phi by roughly the
+ * factor p.  Evaluation points apart from the sources (eq. 2.2): build the
+ * tree over the sources and the evaluation points together, the latter with
+ * zero strength; the values at those points are the field of the sources
+ * alone (a source at the position of an evaluation point is left out, as in
+ * eq. 2.2).  phi, dphi: device complex128 [N], input order.  Errors as for
+ * fmm_evaluate.
+ */
+int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi, void* stream);
+
+/*
  * fmm_evaluate_adjoint -- gradients of a real loss L through phi = FMM(m; z)
  * with the tree geometry frozen.  Convention: for a complex w,
  * G_w = dL/dRe(w) + i dL/dIm(w).

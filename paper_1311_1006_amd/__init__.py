@@ -94,6 +94,7 @@ def lib():
         "fmm_tuner_observe": (C.c_int, [vp, C.c_double]),
         "fmm_tuner_best": (C.c_int, [vp, C.POINTER(_TunerParams), dp, dp]),
         "fmm_tuner_destroy": (None, [vp]),
+        "fmm_evaluate_field": (C.c_int, [vp, vp, vp, vp, vp]),
         "fmm_p_from_tol": (C.c_int, [C.c_double, C.c_double]),
         "fmm_choose_order": (C.c_int, [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, vp,
                                        C.POINTER(C.c_int), dp]),
@@ -245,6 +246,40 @@ def evaluate(pl, m, out=None, stream=None):
         out = torch.empty_like(m)
     _check(lib().fmm_evaluate(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def evaluate_field(pl, m, phi=None, dphi=None, stream=None):
+    """phi and its derivative dphi/dz at every point of the plan's tree."""
+    import torch
+    m = _dev_complex(m, "m")
+    if phi is None:
+        phi = torch.empty_like(m)
+    if dphi is None:
+        dphi = torch.empty_like(m)
+    _check(lib().fmm_evaluate_field(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                    C.c_void_p(dphi.data_ptr()), _stream(stream)))
+    return phi, dphi
+
+
+def evaluate_at(z, m, y, p=16, theta=0.5, n_levels=None, precision="fp64", field=False, stream=None):
+    """The field of the sources (z, m) at separate evaluation points y (eq.
+    2.2): one tree over sources and points, the points with zero strength; a
+    source at the position of an evaluation point is left out.  Returns phi
+    at y, or (phi, dphi) with field=True."""
+    import torch
+    z, m, y = _dev_complex(z, "z"), _dev_complex(m, "m"), _dev_complex(y, "y")
+    n = z.numel()
+    zz = torch.cat([z, y])
+    mm = torch.cat([m, torch.zeros_like(y)])
+    if n_levels is None:
+        from .driver import default_levels
+        n_levels = default_levels(zz.numel())
+    tr = build_tree(zz, n_levels, stream=stream)
+    pl = plan(tr, p, theta, precision, stream=stream)
+    if field:
+        phi, dphi = evaluate_field(pl, mm, stream=stream)
+        return phi[n:], dphi[n:]
+    return evaluate(pl, mm, stream=stream)[n:]
 
 
 def evaluate_parts(pl, m, stream=None):

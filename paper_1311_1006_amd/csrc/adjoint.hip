@@ -293,6 +293,56 @@ void balance_finish(Plan::Balance& b, int n, int vals, hipStream_t s);
 void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
                     hipStream_t s);
 
+// Near-field sums of the transposed chain for the weights gb (tree order),
+// into pl.near_d (6 doubles per point, see k_p2p_adj), in source chunks when
+// some strong list is long (the chunk lists of the adjoint items are made
+// once per plan).  pl.mtree holds the strengths in tree order.
+static void adjoint_near(Plan& pl, const double* gb_tree, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *pl.ex;
+    const bool mixed = pl.precision == FMM_MIXED;
+    if (pl.near_d.n < (size_t)(6 * sc.n)) pl.near_d.alloc(6 * sc.n, s);
+    const P2PItemA* items = (const P2PItemA*)ex.adj_items.p;
+    int nadj = 0;
+    for (auto& c : ex.adj_class) nadj = std::max<int>(nadj, (int)(c.off + c.n));
+    Plan::Balance& ba = pl.bal_adj;
+    if (ba.cls.empty()) {
+        if (pl.split_p2p) {
+            balance_launch(ba, items, nadj, ex.adj_class, pl.nsrc.p, s);
+            FMM_HIP(hipStreamSynchronize(s));
+            balance_finish(ba, nadj, 6, s);
+        } else {
+            for (auto& c : ex.adj_class) ba.cls.push_back(c.off);
+            ba.cls.push_back(nadj);
+            ba.total = nadj;
+        }
+    }
+    for (size_t ci = 0; ci < ex.adj_class.size(); ++ci) {
+        const P2PClass& c = ex.adj_class[ci];
+        const int64_t x0 = ba.cls[ci], x1 = ba.cls[ci + 1];
+        const int2* xit = ba.xitems.p ? ba.xitems.p + x0 : nullptr;
+        const int nx = (int)(x1 - x0);
+#define ACASE(R_, TG_, SUB_)                                                                                  \
+    if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
+        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, pl.nsrc.p, ba.partial.p,  \
+                                      sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,  \
+                                      t.x.p, t.y.p, pl.mtree.p, gb_tree, pl.near_d.p, s);                  \
+        check_launch("p2p adjoint");                                                                          \
+        continue;                                                                                             \
+    }
+        if (mixed) {
+            ACASE(float, 1, 4) ACASE(float, 2, 4) ACASE(float, 4, 4)
+        } else {
+            ACASE(double, 1, 4) ACASE(double, 2, 4)
+        }
+#undef ACASE
+        throw Error(FMM_EDEVICE, "unsupported adjoint P2P shape");
+    }
+    combine_chunks(ba, items, nadj, sc.d_box_start.p, pl.near_d.p, s);
+}
+
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz, hipStream_t s)
 {
     Tree& t = *pl.tree;
@@ -302,7 +352,6 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     const int64_t n = sc.n;
     const size_t cs = mixed ? sizeof(float) : sizeof(double);
     if (pl.gtree.n < (size_t)(2 * n)) pl.gtree.alloc(2 * n, s);
-    if (pl.near_d.n < (size_t)(6 * n)) pl.near_d.alloc(6 * n, s);
     DBuf<double> ngb;
     ngb.alloc(2 * n, s);
     if (pl.amp.n < 2 * cs * sc.nbox * pl.p) pl.amp.alloc(2 * cs * sc.nbox * pl.p, s);
@@ -332,45 +381,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
         }
     };
     if (mixed) far(float()); else far(double());
-    // near field of the adjoint, in source chunks when some strong list is
-    // long (the chunk lists of the adjoint items are made once per plan)
-    const P2PItemA* items = (const P2PItemA*)ex.adj_items.p;
-    int nadj = 0;
-    for (auto& c : ex.adj_class) nadj = std::max<int>(nadj, (int)(c.off + c.n));
-    Plan::Balance& ba = pl.bal_adj;
-    if (ba.cls.empty()) {
-        if (pl.split_p2p) {
-            balance_launch(ba, items, nadj, ex.adj_class, pl.nsrc.p, s);
-            FMM_HIP(hipStreamSynchronize(s));
-            balance_finish(ba, nadj, 6, s);
-        } else {
-            for (auto& c : ex.adj_class) ba.cls.push_back(c.off);
-            ba.cls.push_back(nadj);
-            ba.total = nadj;
-        }
-    }
-    for (size_t ci = 0; ci < ex.adj_class.size(); ++ci) {
-        const P2PClass& c = ex.adj_class[ci];
-        const int64_t x0 = ba.cls[ci], x1 = ba.cls[ci + 1];
-        const int2* xit = ba.xitems.p ? ba.xitems.p + x0 : nullptr;
-        const int nx = (int)(x1 - x0);
-#define ACASE(R_, TG_, SUB_)                                                                                  \
-    if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
-        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, pl.nsrc.p, ba.partial.p,  \
-                                      sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,  \
-                                      t.x.p, t.y.p, pl.mtree.p, pl.gtree.p, pl.near_d.p, s);                  \
-        check_launch("p2p adjoint");                                                                          \
-        continue;                                                                                             \
-    }
-        if (mixed) {
-            ACASE(float, 1, 4) ACASE(float, 2, 4) ACASE(float, 4, 4)
-        } else {
-            ACASE(double, 1, 4) ACASE(double, 2, 4)
-        }
-#undef ACASE
-        throw Error(FMM_EDEVICE, "unsupported adjoint P2P shape");
-    }
-    combine_chunks(ba, items, nadj, sc.d_box_start.p, pl.near_d.p, s);
+    adjoint_near(pl, pl.gtree.p, s);
     // combination and scatter: G lanes per leaf, P terms held per lane
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
     const int P = pl.p <= 16 ? 16 : 32;
@@ -396,6 +407,92 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     if (mixed) fin_p(float{});
     else fin_p(double{});
     check_launch("adjoint final");
+}
+
+// Derivative of the field at the points: the derivative of the forward local
+// expansion of the point's leaf (d/dz = (1/rs) d/dv, Horner in v) minus the
+// near-field sum sum_j m_j / (z_i - z_j)^2, written in input order.  G lanes
+// per leaf, the leaf's expansion in LDS (FP64).
+template <class T, int G, int P>
+__global__ void __launch_bounds__(256)
+k_field_final(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
+              const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
+              const double* __restrict__ Y, const T* __restrict__ loc, int p, const double* __restrict__ nadj,
+              const int32_t* __restrict__ perm, double2* dphi)
+{
+    using T2 = typename Vec2<T>::type;
+    constexpr int NLEAF = 256 / G;
+    __shared__ double2 sbl[NLEAF][P];
+    const int lane = threadIdx.x & 63;
+    const int slot = threadIdx.x / G;
+    const int li = blockIdx.x * NLEAF + slot;
+    const int sl = lane % G;
+    const bool valid = li < nleaf;
+    int st = 0, n = 0;
+    double cx = 0.0, cy = 0.0, inv = 0.0;
+    if (valid) {
+        const int g = leaves[li];
+        st = bstart[g];
+        n = bcount[g];
+        cx = geom[4 * (int64_t)g];
+        cy = geom[4 * (int64_t)g + 1];
+        inv = 1.0 / geom[4 * (int64_t)g + 3];
+        const T2* bsrc = reinterpret_cast<const T2*>(loc) + (int64_t)g * p;
+        for (int k = sl; k < P; k += G) {
+            const T2 zero = {(T)0, (T)0};
+            const T2 b = k < p ? bsrc[k] : zero;
+            sbl[slot][k] = make_double2((double)b.x, (double)b.y);
+        }
+    }
+    __syncthreads();
+    const double2* bl = sbl[slot];
+    for (int j = sl; j < n; j += G) {
+        const int i = st + j;
+        const double2 v = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
+        double2 bv = bl[P - 1], bd = make_double2(0, 0);
+#pragma unroll 2
+        for (int l = P - 2; l >= 0; --l) {
+            bd = cmul(bd, v); bd.x += bv.x; bd.y += bv.y;
+            bv = cmul(bv, v); bv.x += bl[l].x; bv.y += bl[l].y;
+        }
+        const double* na = nadj + 6 * (int64_t)i;
+        dphi[perm[i]] = make_double2(bd.x * inv - na[4], bd.y * inv - na[5]);
+    }
+}
+
+void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *pl.ex;
+    const bool mixed = pl.precision == FMM_MIXED;
+    // the forward evaluation: phi, the local expansions and m in tree order
+    evaluate_device(pl, m, phi, nullptr, nullptr, s);
+    // near-field sums with both weights the strengths: near_d[4..5] = sum m_j w^2
+    adjoint_near(pl, pl.mtree.p, s);
+    const int nleaf = (int)sc.nleaf;
+    const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
+    const int P = pl.p <= 16 ? 16 : 32;
+    const unsigned grid = (unsigned)((nleaf + 256 / G - 1) / (256 / G));
+    auto fin = [&](auto tag, auto gtag, auto ptag) {
+        using T = decltype(tag);
+        constexpr int G_ = decltype(gtag)::value, P_ = decltype(ptag)::value;
+        k_field_final<T, G_, P_><<<grid, 256, 0, s>>>(ex.leaves.p, nleaf, sc.d_box_start.p, sc.d_box_count.p,
+                                                      t.geom.p, t.x.p, t.y.p, (const T*)pl.local.p, pl.p,
+                                                      pl.near_d.p, t.perm.p, (double2*)dphi);
+    };
+    auto fin_g = [&](auto tag, auto ptag) {
+        if (G == 16) fin(tag, std::integral_constant<int, 16>{}, ptag);
+        else if (G == 32) fin(tag, std::integral_constant<int, 32>{}, ptag);
+        else fin(tag, std::integral_constant<int, 64>{}, ptag);
+    };
+    auto fin_p = [&](auto tag) {
+        if (P == 16) fin_g(tag, std::integral_constant<int, 16>{});
+        else fin_g(tag, std::integral_constant<int, 32>{});
+    };
+    if (mixed) fin_p(float{});
+    else fin_p(double{});
+    check_launch("field final");
 }
 
 // adjoint P2P work items (leaf, target chunk) grouped by shape; host side

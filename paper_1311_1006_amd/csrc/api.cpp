@@ -495,6 +495,20 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
     });
 }
 
+int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m && phi && dphi, "NULL argument");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        Plan& P = pl->pl;
+        plan_finalize(P);
+        plan_join(P, s);
+        field_device(P, m, phi, dphi, s);
+        P.last_m = m;
+    });
+}
+
 int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, double* g_m, double* g_z,
                          void* stream)
 {

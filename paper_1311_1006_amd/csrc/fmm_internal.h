@@ -272,6 +272,7 @@ void list_totals_device(Plan& pl, hipStream_t s);
 // word *guard is non-zero (the lists then need a rebuild or work chunks).
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
+void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,
                     hipStream_t s);
 
