@@ -9,6 +9,7 @@ Functions (each follows the paper passage named in the C source):
   direct(z, m, targets=None)           O1, eq. (2.1)/(2.2), exclusion by position
   direct_points(z, m, y)               eq. (2.2), separate evaluation points
   direct_deriv_points(z, m, y)         the y-derivative of (2.2)'s field
+  direct_smoothed(z, m, delta, targets=None)   O1 with the smoother of Sec. 5.1
   direct_compensated(z, m)             O1 with Neumaier summation
   grad_direct(z, m, g)                 O3, gradient through the direct sum
   tree(z, L)                           balanced median-split pyramid, Sec. 2.2
@@ -37,6 +38,7 @@ def lib():
         L.oracle_direct.argtypes = [i64, dp, dp, i64, ip, dp]
         L.oracle_direct_points.argtypes = [i64, dp, dp, i64, dp, dp]
         L.oracle_direct_deriv_points.argtypes = [i64, dp, dp, i64, dp, dp]
+        L.oracle_direct_smoothed.argtypes = [i64, dp, dp, C.c_double, i64, ip, dp]
         L.oracle_direct_compensated.argtypes = [i64, dp, dp, dp]
         L.oracle_grad_direct.argtypes = [i64, dp, dp, dp, dp, dp]
         L.oracle_p2m.argtypes = [dp, i64, dp, dp, C.c_int, dp]
@@ -91,6 +93,19 @@ def direct_points(z, m, y):
     z, m, y = _c(z), _c(m), _c(y)
     out = np.zeros(y.size, np.complex128)
     lib().oracle_direct_points(z.size, _dp(z), _dp(m), y.size, _dp(y), _dp(out))
+    return out
+
+
+def direct_smoothed(z, m, delta, targets=None):
+    z, m = _c(z), _c(m)
+    n = z.size
+    if targets is None:
+        out = np.zeros(n, np.complex128)
+        lib().oracle_direct_smoothed(n, _dp(z), _dp(m), float(delta), n, None, _dp(out))
+    else:
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.zeros(t.size, np.complex128)
+        lib().oracle_direct_smoothed(n, _dp(z), _dp(m), float(delta), t.size, _ip(t), _dp(out))
     return out
 
 

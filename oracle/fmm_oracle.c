@@ -16,6 +16,7 @@
  *       with the strong / weak / decoupled connectivity of Sec. 2.1 and the
  *       theta-criterion (2.3), in the unscaled textbook form of the
  *       multipole / local expansions (Sec. 2.1, harmonic kernel of Sec. 3.3);
+ *   O1s the same sum with the Gaussian smoother of Sec. 5.1 (eq. 5.2);
  *   O3  analytic gradient of a real loss through the direct sum, and the
  *       derivative of the field at separate evaluation points;
  *   the p(TOL, theta) rule that reproduces Table 4.1.
@@ -98,6 +99,32 @@ void oracle_direct_points(int64_t n, const double* z, const double* m,
             cplx w = c_sub(yi, ld(z, j));
             if (w.re == 0.0 && w.im == 0.0) continue;
             acc = c_add(acc, c_div(ld(m, j), w));
+        }
+        st(phi, t, acc);
+    }
+}
+
+/* Direct sum with the Gaussian smoother of the vortex application (Sec. 5.1,
+ * eq. 5.2): every term m_j / (z_i - z_j) is multiplied by
+ * g_delta(r) = 1 - exp(-r^2 / delta^2), r = |z_i - z_j|, which takes the
+ * divergence out as z_j -> z_i; coincident positions are left out as above
+ * (their smoothed term is 0).  Evaluated at the sources themselves
+ * (targets == NULL) or at the listed ones. */
+void oracle_direct_smoothed(int64_t n, const double* z, const double* m, double delta, int64_t nt,
+                            const int64_t* targets, double* phi)
+{
+    int64_t cnt = targets ? nt : n;
+    const double id2 = 1.0 / (delta * delta);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        cplx zi = ld(z, i), acc = c_make(0.0, 0.0);
+        for (int64_t j = 0; j < n; ++j) {
+            cplx w = c_sub(zi, ld(z, j));
+            if (w.re == 0.0 && w.im == 0.0) continue;
+            double r2 = w.re * w.re + w.im * w.im;
+            double g = 1.0 - exp(-r2 * id2);
+            acc = c_add(acc, c_scale(c_div(ld(m, j), w), g));
         }
         st(phi, t, acc);
     }

@@ -57,6 +57,27 @@ def test_derivative_leaves_out_coincident_sources(orc):
     assert a[0] == b[0]
 
 
+def test_smoothed_sum_limits(orc):
+    """The smoother of Sec. 5.1: with delta far below every distance the
+    factor is 1 to the last bit (the plain sum); with every distance far
+    below delta, g ~ r^2/delta^2 turns each term into m conj(dz)/delta^2
+    (relative deviation ~ r^2/(2 delta^2)); a coincident source adds nothing."""
+    rng = np.random.default_rng(8)
+    z = rng.random(400) + 1j * rng.random(400)
+    m = rng.standard_normal(400) + 1j * rng.standard_normal(400)
+    np.testing.assert_array_equal(orc.direct_smoothed(z, m, 1e-30), orc.direct(z, m))
+    c = 0.3 + 0.2j + 1e-4 * (rng.random(60) + 1j * rng.random(60))
+    mc = m[:60]
+    delta = 1.0
+    lin = np.array([np.sum(np.delete(mc * np.conj(c[i] - c), i)) / delta ** 2 for i in range(60)])
+    assert orc.rel_errinf(orc.direct_smoothed(c, mc, delta), lin) < 1e-7
+    zz = np.concatenate([z[:50], z[:1]])
+    mm = np.concatenate([m[:50], [5.0 + 0j]])
+    a = orc.direct_smoothed(zz, mm, 0.05, targets=[0])
+    b = orc.direct_smoothed(z[:50], m[:50], 0.05, targets=[0])
+    assert a[0] == b[0]
+
+
 def test_equispaced_line_harmonic_numbers(orc):
     # z_k = k h, unit strengths: phi_k = (H_k - H_{N-1-k}) / h
     for n, h in [(10, 1.0), (300, 1e-3)]:
