@@ -76,6 +76,13 @@ typedef struct {
                         wavefront and its blocks); automatic: 8 mixed, 4 FP64 */
     int flags;       /* FMM_FLAG_* */
     int reserved;
+    double smooth_delta;   /* > 0: the near field (P2P) takes every term times the Gaussian
+                              smoother g(r) = 1 - exp(-r^2/delta^2) of the vortex application
+                              (Sec. 5.1, eq. 5.2); the far field is left unsmoothed, which is
+                              exact to exp(-R^2/delta^2) with R the smallest leaf radius (the
+                              points of two well-separated boxes are at least the larger
+                              radius apart at theta <= 0.5), so delta should be well below the
+                              leaf radii.  fmm_evaluate and fmm_evaluate_parts only. 0: none */
 } fmm_tuning;
 
 /* Host-side statistics of a plan (list sizes for the work model and the

@@ -34,7 +34,8 @@ class FmmError(RuntimeError):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("p2p_split", C.c_int), ("m2l_batch", C.c_int), ("flags", C.c_int), ("reserved", C.c_int)]
+    _fields_ = [("p2p_split", C.c_int), ("m2l_batch", C.c_int), ("flags", C.c_int), ("reserved", C.c_int),
+                ("smooth_delta", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -232,8 +233,10 @@ class Plan:
         return off, ids[:n.value]
 
 
-def plan(tree, p, theta, precision="fp64", p2p_split=0, m2l_batch=0, graph=False, timing=False, stream=None):
-    tn = _Tuning(p2p_split, m2l_batch, (FMM_FLAG_GRAPH if graph else 0) | (FMM_FLAG_PHASE_TIMING if timing else 0), 0)
+def plan(tree, p, theta, precision="fp64", p2p_split=0, m2l_batch=0, graph=False, timing=False, smooth_delta=0.0,
+         stream=None):
+    tn = _Tuning(p2p_split, m2l_batch, (FMM_FLAG_GRAPH if graph else 0) | (FMM_FLAG_PHASE_TIMING if timing else 0), 0,
+                 float(smooth_delta))
     h = C.c_void_p()
     _check(lib().fmm_plan(tree._h, p, float(theta), _PREC[precision], C.byref(tn), _stream(stream), C.byref(h)))
     return Plan(h, tree, p, theta, precision)

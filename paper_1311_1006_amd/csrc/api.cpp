@@ -307,6 +307,7 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
                     "p2p_split must be 0, 1, 2 or 4");
         FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 4 || tn.m2l_batch == 8 || tn.m2l_batch == 16,
                     "m2l_batch must be 0, 4, 8 or 16");
+        FMM_REQUIRE(tn.smooth_delta >= 0.0 && std::isfinite(tn.smooth_delta), "smooth_delta must be >= 0 and finite");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         auto pp = std::make_unique<fmm_plan_s>();
@@ -499,6 +500,7 @@ int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi
 {
     return guarded([&] {
         FMM_REQUIRE(pl && m && phi && dphi, "NULL argument");
+        FMM_REQUIRE(pl->pl.tune.smooth_delta == 0.0, "a smoothed near field is evaluated by fmm_evaluate only");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         Plan& P = pl->pl;
@@ -515,6 +517,7 @@ int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, do
     return guarded([&] {
         FMM_REQUIRE(pl && m && g_phi, "NULL argument");
         if (!pl->pl.have_forward) throw Error(FMM_ESTATE, "fmm_evaluate_adjoint needs a preceding fmm_evaluate");
+        FMM_REQUIRE(pl->pl.tune.smooth_delta == 0.0, "a smoothed near field is evaluated by fmm_evaluate only");
         check_device_state();
         plan_finalize(pl->pl);
         plan_join(pl->pl, (hipStream_t)stream);

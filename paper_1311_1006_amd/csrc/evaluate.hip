@@ -39,7 +39,7 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard);
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2);
 
 struct P2PItemH {
     int32_t leaf, t0, tn, pad;
@@ -241,7 +241,8 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* gua
                    (int)(x1 - x0), b.icnt.p, b.ioff.p,
                    pl.nsrc.p, b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
-                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard);
+                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard,
+                   pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0);
     }
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }

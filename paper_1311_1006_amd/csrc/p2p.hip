@@ -59,12 +59,42 @@ __device__ __forceinline__ void pair64(double xi, double yi, const Src64& s, dou
     ai = fma(b, y, ai);
 }
 
+// the same terms times the Gaussian smoother 1 - exp(-r^2/delta^2) (id2 = 1/delta^2)
+__device__ __forceinline__ void pair64s(double xi, double yi, const Src64& s, double id2, double& ar, double& ai)
+{
+    double dx = xi - s.x, dy = yi - s.y;
+    double r2 = fma(dx, dx, fma(dy, dy, DBL_MIN));
+    double y = __builtin_amdgcn_rcp(r2);
+    double e = fma(-r2, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-r2, y, 1.0);
+    y = fma(y, e, y);
+    y *= 1.0 - exp(-r2 * id2);
+    double a = fma(s.mr, dx, s.mi * dy);
+    double b = fma(s.mi, dx, -(s.mr * dy));
+    ar = fma(a, y, ar);
+    ai = fma(b, y, ai);
+}
+
 __device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, const Src32& s, float& ar, float& ai)
 {
     float dx = (xh - s.xh) + (xl - s.xl);
     float dy = (yh - s.yh) + (yl - s.yl);
     float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
     float y = __builtin_amdgcn_rcpf(r2);
+    float a = fmaf(s.mr, dx, s.mi * dy);
+    float b = fmaf(s.mi, dx, -(s.mr * dy));
+    ar = fmaf(a, y, ar);
+    ai = fmaf(b, y, ai);
+}
+
+__device__ __forceinline__ void pair32s(float xh, float yh, float xl, float yl, const Src32& s, float id2, float& ar,
+                                        float& ai)
+{
+    float dx = (xh - s.xh) + (xl - s.xl);
+    float dy = (yh - s.yh) + (yl - s.yl);
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
+    float y = __builtin_amdgcn_rcpf(r2) * (1.0f - __expf(-r2 * id2));
     float a = fmaf(s.mr, dx, s.mi * dy);
     float b = fmaf(s.mi, dx, -(s.mr * dy));
     ar = fmaf(a, y, ar);
@@ -121,7 +151,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
-        const long long* __restrict__ guard)
+        const long long* __restrict__ guard, double id2)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -159,12 +189,22 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
                                                  lane, load, s_len - done);
         done += ns;
-        for (int c = 0; c < ns; c += NL) {
-            int f = c + sl;
-            Src64 s = lds[f < ns ? f : 0];
-            if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
+        if (id2 > 0.0) {            // uniform: the smoothed near field
+            for (int c = 0; c < ns; c += NL) {
+                int f = c + sl;
+                Src64 s = lds[f < ns ? f : 0];
+                if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
 #pragma unroll
-            for (int t = 0; t < TG; ++t) pair64(xi[t], yi[t], s, ar[t], ai[t]);
+                for (int t = 0; t < TG; ++t) pair64s(xi[t], yi[t], s, id2, ar[t], ai[t]);
+            }
+        } else {
+            for (int c = 0; c < ns; c += NL) {
+                int f = c + sl;
+                Src64 s = lds[f < ns ? f : 0];
+                if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
+#pragma unroll
+                for (int t = 0; t < TG; ++t) pair64(xi[t], yi[t], s, ar[t], ai[t]);
+            }
         }
         wave_sync();
     }
@@ -190,7 +230,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
-        double2* __restrict__ out, const long long* __restrict__ guard)
+        double2* __restrict__ out, const long long* __restrict__ guard, float id2)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -231,12 +271,22 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
                                                  lane, load, s_len - done);
         done += ns;
-        for (int c = 0; c < ns; c += NL) {
-            int f = c + sl;
-            Src32 s = lds[f < ns ? f : 0];
-            if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
+        if (id2 > 0.f) {            // uniform: the smoothed near field
+            for (int c = 0; c < ns; c += NL) {
+                int f = c + sl;
+                Src32 s = lds[f < ns ? f : 0];
+                if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
 #pragma unroll
-            for (int t = 0; t < TG; ++t) pair32(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
+                for (int t = 0; t < TG; ++t) pair32s(xh[t], yh[t], xl[t], yl[t], s, id2, ar[t], ai[t]);
+            }
+        } else {
+            for (int c = 0; c < ns; c += NL) {
+                int f = c + sl;
+                Src32 s = lds[f < ns ? f : 0];
+                if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
+#pragma unroll
+                for (int t = 0; t < TG; ++t) pair32(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
+            }
         }
         wave_sync();
     }
@@ -258,15 +308,16 @@ template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
                        const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                       const void* src, const void* lo, double* out, hipStream_t s, const long long* guard)
+                       const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
+                       double id2)
 {
     int grid = (nx + 3) / 4;
     if (mixed)
         k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out, guard);
+                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out, guard, (float)id2);
     else
         k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const double4*)src, (double2*)out, guard);
+                                             s_cnt, s_ids, (const double4*)src, (double2*)out, guard, id2);
 }
 
 // one launch per (targets per subgroup, subgroups) class over its chunks
@@ -276,14 +327,14 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard)
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2)
 {
     if (nx == 0) return;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s, guard);                                                    \
+                              s_ids, src, lo, out, s, guard, id2);                                                    \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }

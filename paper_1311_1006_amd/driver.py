@@ -20,11 +20,14 @@ def default_levels(n, per_leaf=16):
     return L
 
 
-def advect(z, m, steps, dt, p=16, theta=0.5, precision="mixed", tuner=None, n_levels=None, callback=None):
+def advect(z, m, steps, dt, p=16, theta=0.5, precision="mixed", tuner=None, n_levels=None, callback=None,
+           smooth_delta=0.0):
     """Advance positions z (complex128 device tensor) by `steps` Euler steps.
     tuner: a Tuner (or None for fixed parameters).  callback(step, z, phi,
-    params, seconds) is called after every evaluation.  Returns the final z
-    and the list of per-step (params, seconds)."""
+    params, seconds) is called after every evaluation.  smooth_delta > 0:
+    the near field takes the Gaussian smoother of the vortex application
+    (Sec. 5.1).  Returns the final z and the list of per-step (params,
+    seconds)."""
     import torch
     L0 = n_levels or default_levels(z.numel())
     hist = []
@@ -40,7 +43,8 @@ def advect(z, m, steps, dt, p=16, theta=0.5, precision="mixed", tuner=None, n_le
         tree = build_tree(z, L)
         # a tuner that walks theta also carries the order for it (p from its tolerance)
         pp, th = (prm["p"], prm["theta"]) if getattr(tuner, "tunes_theta", False) else (p, theta)
-        pl = plan(tree, pp, th, precision, p2p_split=prm["p2p_split"], m2l_batch=prm["m2l_batch"])
+        pl = plan(tree, pp, th, precision, p2p_split=prm["p2p_split"], m2l_batch=prm["m2l_batch"],
+                  smooth_delta=smooth_delta)
         phi = evaluate(pl, m)
         e1.record()
         e1.synchronize()

@@ -99,6 +99,29 @@ def batch(nprob=128, seed=0, nmin=1_000, nmax=200_000):
     return zs, ms, kinds
 
 
+def kelvin_helmholtz(n, seed=0, aspect=20.0, amp=1e-3):
+    """The vortex-sheet start of Sec. 5.1: about n vortices on a regular grid
+    in a long thin rectangle [0, 1] x [-h/2, h/2], h = 1/aspect, the upper
+    half of the rows with strength +1/N and the lower half -1/N (total
+    circulation zero), displaced by amp*h*sin(2 pi x) in y to seed the
+    instability, plus a seeded jitter of 1e-6 of the spacing.  Returns
+    (z, m, spacing); spacing = grid spacing in x (about that in y)."""
+    ny = max(2, 2 * int(round(math.sqrt(n / aspect) / 2)))
+    nx = max(1, n // ny)
+    h = 1.0 / aspect
+    xs = (np.arange(nx) + 0.5) / nx
+    ys = ((np.arange(ny) + 0.5) / ny - 0.5) * h
+    X, Y = np.meshgrid(xs, ys)
+    X, Y = X.ravel(), Y.ravel()
+    N = X.size
+    m = np.where(Y > 0, 1.0, -1.0) / N + 0j
+    rng = np.random.default_rng(seed)
+    sp = 1.0 / nx
+    Y = Y + amp * h * np.sin(2 * np.pi * X) + 1e-6 * sp * rng.standard_normal(N)
+    X = X + 1e-6 * sp * rng.standard_normal(N)
+    return X + 1j * Y, m, sp
+
+
 def roots_of_unity(n, centre=0.0 + 0.0j, radius=1.0, phase=0.0):
     """n points equally spaced on a circle (closed-form test input)."""
     k = np.arange(n)
