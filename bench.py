@@ -142,6 +142,43 @@ def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4, tune_
     return res
 
 
+def measure_kh(F, W, torch, dev, reps, with_errors, steps=20, dt=1e-4):
+    """The vortex sheet of Sec. 5.1 (Kelvin-Helmholtz start, about 1.5e6
+    vortices, Gaussian smoother with delta = half the grid spacing): Euler
+    steps with the tuner (mixed, p = 16); e2 every 10 steps against the
+    oracle's smoothed direct sum on 2,000 targets; and the cost of the
+    smoother: the first tree evaluated with and without it."""
+    from paper_1311_1006_amd.driver import advect, default_levels, make_tuner
+    z, m, sp = W.kelvin_helmholtz(1_500_000, seed=0)
+    delta = sp / 2
+    zd = torch.from_numpy(z).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    tree = F.build_tree(zd, default_levels(z.size))
+    ob = torch.empty_like(md)
+    t_s = _time(lambda: F.evaluate(F.plan(tree, 16, 0.5, "mixed", smooth_delta=delta), md, ob), reps, torch)
+    t_p = _time(lambda: F.evaluate(F.plan(tree, 16, 0.5, "mixed"), md, ob), reps, torch)
+    del tree
+    tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6)
+    errs = {}
+
+    def check(step, zt, phi, prm, sec):
+        if with_errors and step % 10 == 0:
+            import oracle
+            zh = zt.cpu().numpy()
+            sub = W.subsample(zh.size, 2000, seed=step)
+            errs[step] = oracle.rel_err2(phi.cpu().numpy()[sub], oracle.direct_smoothed(zh, m, delta, targets=sub))
+
+    zf, hist = advect(zd, md, steps + 1, dt, p=16, precision="mixed", tuner=tu, callback=check, smooth_delta=delta)
+    times = [sec for _, sec in hist]
+    res = {"kelvin_helmholtz_n1p5e6": {"n": int(z.size), "delta": delta, "steps": steps + 1,
+                                       "ms_per_step_median": 1e3 * float(np.median(times)),
+                                       "plan_eval_ms_smoothed": t_s * 1e3, "plan_eval_ms_plain": t_p * 1e3,
+                                       "tuned": tu.best()[0], "e2_every_10_steps": errs or None}}
+    log("Kelvin-Helmholtz N=%d: median %.3f ms/step; plan+evaluate smoothed %.3f ms, plain %.3f ms; e2 %s" %
+        (z.size, 1e3 * float(np.median(times)), t_s * 1e3, t_p * 1e3, errs))
+    return res
+
+
 def measure_forms(F, W, torch, dev, reps, with_errors):
     """(2) 128 problems of uneven size in one graph launch vs 128 sequential
     plain launches (same trees, levels, p, shapes); clustered time stepping
@@ -173,6 +210,7 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
     out.update(measure_timestepping(F, W, torch, dev, with_errors))
     out.update(measure_timestepping(F, W, torch, dev, with_errors, tune_theta=True))
     out.update(measure_theta(F, W, torch, dev, max(3, reps // 4)))
+    out.update(measure_kh(F, W, torch, dev, max(3, reps // 4), with_errors))
     # field and its derivative (fmm_evaluate_field) against the plain evaluation
     z, m, _ = W.uniform(1_000_000, seed=0)
     zd = torch.from_numpy(z).to(dev)

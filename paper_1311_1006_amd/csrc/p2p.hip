@@ -144,7 +144,7 @@ __device__ __forceinline__ int butterfly_index(int lane)
     return idx;
 }
 
-template <int TG, int SUB>
+template <int TG, int SUB, bool SMOOTH>
 __global__ void __launch_bounds__(256)
 k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
@@ -189,7 +189,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
                                                  lane, load, s_len - done);
         done += ns;
-        if (id2 > 0.0) {            // uniform: the smoothed near field
+        if constexpr (SMOOTH) {     // the smoothed near field
             for (int c = 0; c < ns; c += NL) {
                 int f = c + sl;
                 Src64 s = lds[f < ns ? f : 0];
@@ -223,7 +223,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     }
 }
 
-template <int TG, int SUB>
+template <int TG, int SUB, bool SMOOTH>
 __global__ void __launch_bounds__(256)
 k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
@@ -271,7 +271,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
                                                  lane, load, s_len - done);
         done += ns;
-        if (id2 > 0.f) {            // uniform: the smoothed near field
+        if constexpr (SMOOTH) {     // the smoothed near field
             for (int c = 0; c < ns; c += NL) {
                 int f = c + sl;
                 Src32 s = lds[f < ns ? f : 0];
@@ -312,12 +312,26 @@ static void launch_one(bool mixed, const P2PItem* items, int item_base, const in
                        double id2)
 {
     int grid = (nx + 3) / 4;
-    if (mixed)
-        k_p2p32<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const float4*)src, (const float2*)lo, (double2*)out, guard, (float)id2);
-    else
-        k_p2p64<TG, SUB><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg,
-                                             s_cnt, s_ids, (const double4*)src, (double2*)out, guard, id2);
+    // the smoother is a separate instantiation: the plain kernel keeps its registers
+    if (mixed) {
+        if (id2 > 0.0)
+            k_p2p32<TG, SUB, true><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                       bcount, s_beg, s_cnt, s_ids, (const float4*)src,
+                                                       (const float2*)lo, (double2*)out, guard, (float)id2);
+        else
+            k_p2p32<TG, SUB, false><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                        bcount, s_beg, s_cnt, s_ids, (const float4*)src,
+                                                        (const float2*)lo, (double2*)out, guard, 0.f);
+    } else {
+        if (id2 > 0.0)
+            k_p2p64<TG, SUB, true><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                       bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
+                                                       guard, id2);
+        else
+            k_p2p64<TG, SUB, false><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                        bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
+                                                        guard, 0.0);
+    }
 }
 
 // one launch per (targets per subgroup, subgroups) class over its chunks
