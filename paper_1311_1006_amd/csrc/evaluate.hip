@@ -29,8 +29,8 @@ template <class T>
 void launch_l2l(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
 void launch_l2p(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
-                const double*, const void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t,
-                const long long*);
+                const double*, void*, int, const double*, const int32_t*, double*, double*, double*, hipStream_t,
+                const long long*, const int32_t*, const double*);
 template <class T>
 void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
                 const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
@@ -92,6 +92,11 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
                 }
             }
         }
+    }
+    {
+        bool same = sc.nprob > 0;
+        for (int b = 0; b < sc.nprob; ++b) same = same && sc.L[b] == sc.L[0];
+        ex.leaf_l2l_in_l2p = same && sc.L[0] >= 2;
     }
     std::vector<int32_t> all;
     ex.level_boxes_off.assign(ml + 1, 0);
@@ -216,8 +221,11 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
                   b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
                   pl.tune.m2l_batch, guard);
     tm.mark();
-    // parents at level l (non-leaf) hand their expansion to level l+1
-    for (int l = 1; l + 1 < sc.max_levels; ++l) {
+    // parents at level l (non-leaf) hand their expansion to level l+1; the
+    // hand-over into the leaves is done by L2P when every problem has the
+    // same depth
+    const int lend = sc.max_levels - (ex.leaf_l2l_in_l2p ? 2 : 1);
+    for (int l = 1; l < lend; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, loc, s);
     }
@@ -331,10 +339,12 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     tm.mark();
     if (mixed)
         launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
-                          pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard);
+                          pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard,
+                          ex.leaf_l2l_in_l2p ? sc.d_box_parent.p : nullptr, ex.binom.p);
     else
         launch_l2p<double>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
-                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard);
+                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard,
+                          ex.leaf_l2l_in_l2p ? sc.d_box_parent.p : nullptr, ex.binom.p);
     tm.mark();
     if (tm.on) {
         FMM_HIP(hipEventSynchronize(tm.ev[5]));

@@ -200,16 +200,23 @@ k_l2l(const int32_t* __restrict__ parents, const int32_t* __restrict__ child0, c
 // L2P at the leaves, plus the near field, scattered to input order.  G
 // lanes per leaf as in P2M; every lane holds the leaf's P coefficients (FP64)
 // and evaluates the series by Horner's rule at its points.
-template <class T, int G, int P>
+// L2P (and with LEAF_L2L the L2L from the leaf's parent first: lane l of
+// the leaf's group forms rho^l sum_{k>=l} C(k, l) b_k(parent) tau^(k-l) with
+// the operations of k_l2l, adds it to coefficient l and stores the
+// completed coefficient, so that the leaf's local expansion in `loc` is
+// whole afterwards; the group shares the coefficients through LDS).
+template <class T, int G, int P, bool LEAF_L2L>
 __global__ void __launch_bounds__(256)
 k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
-      const double* __restrict__ Y, const T* __restrict__ loc, int p, const double2* __restrict__ nearf,
+      const double* __restrict__ Y, T* loc, int p, const double2* __restrict__ nearf,
       const int32_t* __restrict__ perm, double2* phi, double2* phi_near, double2* phi_far,
-      const long long* __restrict__ guard)
+      const long long* __restrict__ guard, const int32_t* __restrict__ parent, const double* __restrict__ binom)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     using T2 = typename Vec2<T>::type;
+    __shared__ double2 sco[LEAF_L2L ? 256 / G : 1][LEAF_L2L ? P : 1];
+    __shared__ double2 stau[LEAF_L2L ? 256 / G : 1][LEAF_L2L ? P : 1];
     const int lane = threadIdx.x & 63;
     const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
     const int sl = lane % G;
@@ -217,12 +224,49 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
     const int g = leaves[li];
     const int st = bstart[g], n = bcount[g];
     const double cx = geom[4 * (int64_t)g], cy = geom[4 * (int64_t)g + 1], inv = 1.0 / geom[4 * (int64_t)g + 3];
-    const T2* b = reinterpret_cast<const T2*>(loc) + (int64_t)g * p;
+    T2* b = reinterpret_cast<T2*>(loc) + (int64_t)g * p;
     double2 bl[P];
+    if constexpr (LEAF_L2L) {
+        const int pg = parent[g];
+        const double prs = geom[4 * (int64_t)pg + 3];
+        const double rho = geom[4 * (int64_t)g + 3] / prs;
+        const double2 tau = make_double2((cx - geom[4 * (int64_t)pg]) / prs, (cy - geom[4 * (int64_t)pg + 1]) / prs);
+        const T2* bp = reinterpret_cast<const T2*>(loc) + (int64_t)pg * p;
+        double2* co = sco[threadIdx.x / G];
+        double2* tp = stau[threadIdx.x / G];
+        for (int j = sl; j < p; j += G) tp[j] = cpow(tau, j);   // the table of k_l2l
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int l = sl; l < p; l += G) {
+            // the operations of k_l2l, in its order, so that the result does not
+            // depend on which of the two kernels hands the expansion over
+            double2 acc = make_double2(0, 0);
+            for (int k = l; k < p; ++k) {
+                const T2 bk = bp[k];
+                double s = binom[k * kBinomStride + l];
+                double2 v = cmul(make_double2((double)bk.x, (double)bk.y), tp[k - l]);
+                acc.x += s * v.x;
+                acc.y += s * v.y;
+            }
+            const double rl = rpow(rho, l);
+            const T2 own = b[l];
+            const T tx = (T)((double)own.x + rl * acc.x), ty = (T)((double)own.y + rl * acc.y);
+            b[l] = T2{tx, ty};
+            co[l] = make_double2((double)tx, (double)ty);
+        }
+        // the group lies in one wavefront
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        if (k < p) { const T2 v = b[k]; bl[k] = make_double2((double)v.x, (double)v.y); }
-        else bl[k] = make_double2(0.0, 0.0);
+        for (int k = 0; k < P; ++k) bl[k] = k < p ? co[k] : make_double2(0.0, 0.0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k < p) { const T2 v = b[k]; bl[k] = make_double2((double)v.x, (double)v.y); }
+            else bl[k] = make_double2(0.0, 0.0);
+        }
     }
     for (int j = sl; j < n; j += G) {
         const int i = st + j;
@@ -305,18 +349,25 @@ void launch_l2l(const int32_t* parents, int n, const int32_t* child0, const doub
 
 template <class T>
 void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
-                const double* geom, const double* X, const double* Y, const void* loc, int p,
+                const double* geom, const double* X, const double* Y, void* loc, int p,
                 const double* nearf, const int32_t* perm, double* phi, double* phi_near, double* phi_far,
-                hipStream_t s, const long long* guard)
+                hipStream_t s, const long long* guard, const int32_t* parent, const double* binom)
 {
     if (nleaf == 0) return;
     const int G = leaf_lanes(leaf_max);
     const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
 #define L2P_CASE(G_, P_)                                                                                   \
     if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
-        k_l2p<T, G_, P_><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const T*)loc, p,  \
-                                              (const double2*)nearf, perm, (double2*)phi,                 \
-                                              (double2*)phi_near, (double2*)phi_far, guard);              \
+        if (parent)                                                                                       \
+            k_l2p<T, G_, P_, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (T*)loc, p, \
+                                                        (const double2*)nearf, perm, (double2*)phi,       \
+                                                        (double2*)phi_near, (double2*)phi_far, guard,     \
+                                                        parent, binom);                                   \
+        else                                                                                              \
+            k_l2p<T, G_, P_, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (T*)loc, p, \
+                                                         (const double2*)nearf, perm, (double2*)phi,      \
+                                                         (double2*)phi_near, (double2*)phi_far, guard,    \
+                                                         nullptr, nullptr);                               \
         check_launch("l2p");                                                                              \
         return;                                                                                           \
     }
@@ -333,9 +384,9 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
     template void launch_l2l<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
                                 void*, hipStream_t);                                                     \
     template void launch_l2p<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
-                                const double*, const double*, const void*, int, const double*,           \
-                                const int32_t*, double*, double*, double*, hipStream_t,     \
-                                const long long*);
+                                const double*, const double*, void*, int, const double*,                 \
+                                const int32_t*, double*, double*, double*, hipStream_t,                  \
+                                const long long*, const int32_t*, const double*);
 INST(double)
 INST(float)
 #undef INST

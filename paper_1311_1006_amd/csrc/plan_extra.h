@@ -17,6 +17,8 @@ struct PlanExtra {
     DBuf<int32_t> d_level_boxes;                    // concatenated per level
     DBuf<int32_t> leaves;                           // global ids of all leaves
     int leaf_max = 0;                               // largest leaf population
+    bool leaf_l2l_in_l2p = false;                   // every problem has the same N_levels >= 2: the
+                                                    // L2L into the leaves runs inside L2P
     int cap_strong = 0, cap_weak = 0;               // per-box list capacities of the one-pass build
     bool levelwise_only = false;                    // a frontier overflowed on this layout
     bool compact_only = false;                      // fixed capacities would need too much memory
