@@ -22,7 +22,8 @@ void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, 
                    const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
 template <class T>
 void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
-                const double*, const double*, int, void*, hipStream_t);
+                const double*, const double*, int, void*, hipStream_t, const int32_t* = nullptr,
+                const double* = nullptr);
 template <class T>
 void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
@@ -97,6 +98,7 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
         bool same = sc.nprob > 0;
         for (int b = 0; b < sc.nprob; ++b) same = same && sc.L[b] == sc.L[0];
         ex.leaf_l2l_in_l2p = same && sc.L[0] >= 2;
+        ex.leaf_m2m_in_p2m = ex.leaf_l2l_in_l2p && ex.leaf_max <= 16;
     }
     std::vector<int32_t> all;
     ex.level_boxes_off.assign(ml + 1, 0);
@@ -168,9 +170,11 @@ static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipS
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
+    // with leaf_m2m_in_p2m the P2M kernel also forms the leaves' parents
+    const bool fm = ex.leaf_m2m_in_p2m;
     launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p, mt, pl.p,
-                  mp, s);
-    for (int l = sc.max_levels - 2; l >= 1; --l) {
+                  mp, s, fm ? sc.d_box_parent.p : nullptr, ex.binom.p);
+    for (int l = sc.max_levels - (fm ? 3 : 2); l >= 1; --l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, mp, s);
     }

@@ -50,12 +50,41 @@ __device__ __forceinline__ void wave_sync_e()
 // ... of its leaf and accumulates all P terms m_j w_j^k (w_j = (z_j - c)/rs)
 // in FP64 registers; a transposing butterfly then sums them over the G
 // lanes.  P = 16 or 32 bounds p.
-template <class T, int G, int P>
+__device__ __forceinline__ double2 cpow(double2 b, int e)
+{
+    double2 r = make_double2(1.0, 0.0);
+    while (e) {
+        if (e & 1) r = cmul(r, b);
+        b = cmul(b, b);
+        e >>= 1;
+    }
+    return r;
+}
+__device__ __forceinline__ double rpow(double b, int e)
+{
+    double r = 1.0;
+    while (e) {
+        if (e & 1) r *= b;
+        b *= b;
+        e >>= 1;
+    }
+    return r;
+}
+
+// P2M (and with LEAF_M2M, G = 16, the M2M of the leaves' parents: a
+// wavefront holds four leaves, which are one sibling group when every
+// problem has the same depth; it then forms their parent's expansion with
+// the lane layout and the operations of k_m2m, from the children's
+// coefficients rounded to the storage type as k_m2m reads them, so that the
+// result does not depend on which kernel forms it).
+template <class T, int G, int P, bool LEAF_M2M>
 __global__ void __launch_bounds__(256)
 k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
-      const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp)
+      const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp,
+      const int32_t* __restrict__ parent, const double* __restrict__ binom)
 {
+    static_assert(!LEAF_M2M || G == 16, "a sibling group per wavefront needs 16 lanes per leaf");
     constexpr int V = 2 * P;
     const int lane = threadIdx.x & 63;
     const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
@@ -95,28 +124,61 @@ k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
             if (k < p) mp[2 * ((int64_t)g * p + k) + (idx & 1)] = (T)v[i];
         }
     }
+    if constexpr (LEAF_M2M) {
+        __shared__ double2 coef[4][4][P], tau[4][4][P], part[4][4][P];
+        __shared__ double rho[4][4][P];
+        const int w = threadIdx.x >> 6, c = lane >> 4, j0 = lane & 15;
+        if (valid && writer) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int idx = base + i, k = idx >> 1;
+                if (k < p) {
+                    const double val = (double)(T)v[i];
+                    if (idx & 1) coef[w][c][k].y = val;
+                    else coef[w][c][k].x = val;
+                }
+            }
+        }
+        int pg = 0;
+        if (valid) {            // the four leaves of the wavefront are valid together
+            pg = parent[g];
+            const double* gp = geom + 4 * (int64_t)pg;
+            const double prs = gp[3];
+            const double r = geom[4 * (int64_t)g + 3] / prs;
+            const double2 t = make_double2((cx - gp[0]) / prs, (cy - gp[1]) / prs);
+            for (int j = j0; j < p; j += 16) {
+                tau[w][c][j] = cpow(t, j);
+                rho[w][c][j] = rpow(r, j);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid) {
+            for (int k = j0; k < p; k += 16) {
+                double2 acc = make_double2(0, 0);
+                for (int l = 0; l <= k; ++l) {
+                    double s = binom[k * kBinomStride + l] * rho[w][c][l];
+                    double2 vv = cmul(coef[w][c][l], tau[w][c][k - l]);
+                    acc.x += s * vv.x;
+                    acc.y += s * vv.y;
+                }
+                part[w][c][k] = acc;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid) {
+            for (int k = lane; k < p; k += 64) {
+                double2 v0 = part[w][0][k], v1 = part[w][1][k], v2 = part[w][2][k], v3 = part[w][3][k];
+                mp[2 * ((int64_t)pg * p + k)] = (T)(((v0.x + v1.x) + v2.x) + v3.x);
+                mp[2 * ((int64_t)pg * p + k) + 1] = (T)(((v0.y + v1.y) + v2.y) + v3.y);
+            }
+        }
+    }
 }
 
-__device__ __forceinline__ double2 cpow(double2 b, int e)
-{
-    double2 r = make_double2(1.0, 0.0);
-    while (e) {
-        if (e & 1) r = cmul(r, b);
-        b = cmul(b, b);
-        e >>= 1;
-    }
-    return r;
-}
-__device__ __forceinline__ double rpow(double b, int e)
-{
-    double r = 1.0;
-    while (e) {
-        if (e & 1) r *= b;
-        b *= b;
-        e >>= 1;
-    }
-    return r;
-}
 
 // M2M into one parent from its four children.  Lane (c, j): c = lane/16
 // child, j = lane%16 (+16 for p > 16).  The children's coefficients and the
@@ -312,15 +374,22 @@ static int leaf_lanes(int leaf_max) { return leaf_max <= 16 ? 16 : (leaf_max <= 
 template <class T>
 void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
                 const double* geom, const double* X, const double* Y, const double* mt, int p, void* mp,
-                hipStream_t s)
+                hipStream_t s, const int32_t* parent, const double* binom)
 {
     if (nleaf == 0) return;
     const int G = leaf_lanes(leaf_max);
     const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
 #define P2M_CASE(G_, P_)                                                                                   \
     if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
-        k_p2m<T, G_, P_><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (const double2*)mt, \
-                                              p, (T*)mp);                                                 \
+        if constexpr (G_ == 16)                                                                           \
+            if (parent) {                                                                                 \
+                k_p2m<T, G_, P_, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y,    \
+                                                            (const double2*)mt, p, (T*)mp, parent, binom); \
+                check_launch("p2m");                                                                      \
+                return;                                                                                   \
+            }                                                                                             \
+        k_p2m<T, G_, P_, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y,           \
+                                                     (const double2*)mt, p, (T*)mp, nullptr, nullptr);    \
         check_launch("p2m");                                                                              \
         return;                                                                                           \
     }
@@ -378,7 +447,8 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
 
 #define INST(T)                                                                                          \
     template void launch_p2m<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
-                                const double*, const double*, const double*, int, void*, hipStream_t);   \
+                                const double*, const double*, const double*, int, void*, hipStream_t,    \
+                                const int32_t*, const double*);                                          \
     template void launch_m2m<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
                                 void*, hipStream_t);                                                     \
     template void launch_l2l<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
