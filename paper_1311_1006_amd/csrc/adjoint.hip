@@ -36,7 +36,7 @@ namespace fmm {
 template <class T>
 void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
                 const double*, const double*, int, void*, hipStream_t, const int32_t* = nullptr,
-                const double* = nullptr);
+                const double* = nullptr, const GatherOut* = nullptr);
 template <class T>
 void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>

@@ -364,7 +364,6 @@ void plan_finalize(Plan& P)
         throw;
     }
     P.lt_totals.release();
-    P.lt_pbox.release();
     // the plan's last device work on the list stream: consumers wait for it
     if (!P.ev_plan_done) FMM_HIP(hipEventCreateWithFlags(&P.ev_plan_done, hipEventDisableTiming));
     FMM_HIP(hipEventRecord(P.ev_plan_done, P.list_stream));

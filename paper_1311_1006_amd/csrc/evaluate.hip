@@ -2,7 +2,8 @@
 // host-side work lists of a plan.
 //
 //   gather  strengths to tree order, P2P source records
-//   P2M     leaves of every problem
+//   P2M     leaves of every problem (does the gather when the leaves hold
+//           every point, which is the case for every tree this library builds)
 //   M2M     level by level, deepest parents first
 //   M2L     every box over its weak list (writes the box's local expansion)
 //   L2L     level by level from level 2 down (adds the parent's expansion)
@@ -12,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "fmm_internal.h"
 #include "plan_extra.h"
@@ -23,7 +25,7 @@ void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, 
 template <class T>
 void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
                 const double*, const double*, int, void*, hipStream_t, const int32_t* = nullptr,
-                const double* = nullptr);
+                const double* = nullptr, const GatherOut* = nullptr);
 template <class T>
 void launch_m2m(const int32_t*, int, const int32_t*, const double*, const double*, int, void*, hipStream_t);
 template <class T>
@@ -99,6 +101,9 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
         for (int b = 0; b < sc.nprob; ++b) same = same && sc.L[b] == sc.L[0];
         ex.leaf_l2l_in_l2p = same && sc.L[0] >= 2;
         ex.leaf_m2m_in_p2m = ex.leaf_l2l_in_l2p && ex.leaf_max <= 16;
+        int64_t covered = 0;
+        for (int32_t g : leaves) covered += sc.box_count[g];
+        ex.gather_in_p2m = covered == sc.n;
     }
     std::vector<int32_t> all;
     ex.level_boxes_off.assign(ml + 1, 0);
@@ -165,15 +170,31 @@ void alloc_eval_buffers(Plan& pl, hipStream_t s)
     pl.local.alloc(2 * cs * sc.nbox * pl.p, s);
 }
 
+// gather (own kernel, or inside P2M) and P2M; m = strengths in input order
 template <class T>
-static void run_far_up(Plan& pl, PlanExtra& ex, void* mp, const double* mt, hipStream_t s)
+static void run_p2m(Plan& pl, PlanExtra& ex, const double* m, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
+    const bool mixed = std::is_same<T, float>::value;
+    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p, (double4*)pl.src64.p, (float4*)pl.src32.p,
+                 (float2*)pl.srclo.p};
+    if (!ex.gather_in_p2m)
+        launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
     // with leaf_m2m_in_p2m the P2M kernel also forms the leaves' parents
     const bool fm = ex.leaf_m2m_in_p2m;
-    launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p, mt, pl.p,
-                  mp, s, fm ? sc.d_box_parent.p : nullptr, ex.binom.p);
+    launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
+                  pl.mtree.p, pl.p, pl.mpole.p, s, fm ? sc.d_box_parent.p : nullptr, ex.binom.p,
+                  ex.gather_in_p2m ? &go : nullptr);
+}
+
+// M2M above what P2M formed
+template <class T>
+static void run_m2m(Plan& pl, PlanExtra& ex, void* mp, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    const bool fm = ex.leaf_m2m_in_p2m;
     for (int l = sc.max_levels - (fm ? 3 : 2); l >= 1; --l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, mp, s);
@@ -290,9 +311,13 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
-    launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
-    if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
-    else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+    if (mixed) {
+        run_p2m<float>(pl, ex, m, s);
+        run_m2m<float>(pl, ex, pl.mpole.p, s);
+    } else {
+        run_p2m<double>(pl, ex, m, s);
+        run_m2m<double>(pl, ex, pl.mpole.p, s);
+    }
     pl.upward_done = true;
 }
 
@@ -317,12 +342,14 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     tm.mark();
     const bool up = pl.upward_done && overlap;   // gather and upward pass enqueued by evaluate_upward
     pl.upward_done = false;
-    if (!up)
-        launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    if (!up) {
+        if (mixed) run_p2m<float>(pl, ex, m, s);
+        else run_p2m<double>(pl, ex, m, s);
+    }
     if (overlap) {
         // the near field starts after everything enqueued on `s` so far: the
-        // gather, and the list and work-chunk kernels of the plan (which
-        // follow the upward pass when evaluate_upward ran first)
+        // gather (with P2M), and the list and work-chunk kernels of the plan
+        // (which follow the upward pass when evaluate_upward ran first)
         FMM_HIP(hipEventRecord(pl.ev_fork, s));
         FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
         if (lists_ev) FMM_HIP(hipStreamWaitEvent(pl.nstream, lists_ev, 0));
@@ -330,8 +357,8 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
         FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
     }
     if (!up) {
-        if (mixed) run_far_up<float>(pl, ex, pl.mpole.p, pl.mtree.p, s);
-        else run_far_up<double>(pl, ex, pl.mpole.p, pl.mtree.p, s);
+        if (mixed) run_m2m<float>(pl, ex, pl.mpole.p, s);
+        else run_m2m<double>(pl, ex, pl.mpole.p, s);
     }
     tm.mark();
     if (lists_ev) FMM_HIP(hipStreamWaitEvent(s, lists_ev, 0));

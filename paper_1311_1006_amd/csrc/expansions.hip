@@ -77,12 +77,12 @@ __device__ __forceinline__ double rpow(double b, int e)
 // the lane layout and the operations of k_m2m, from the children's
 // coefficients rounded to the storage type as k_m2m reads them, so that the
 // result does not depend on which kernel forms it).
-template <class T, int G, int P, bool LEAF_M2M>
+template <class T, int G, int P, bool LEAF_M2M, bool GATHER>
 __global__ void __launch_bounds__(256)
 k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
       const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp,
-      const int32_t* __restrict__ parent, const double* __restrict__ binom)
+      const int32_t* __restrict__ parent, const double* __restrict__ binom, GatherOut go)
 {
     static_assert(!LEAF_M2M || G == 16, "a sibling group per wavefront needs 16 lanes per leaf");
     constexpr int V = 2 * P;
@@ -104,8 +104,26 @@ k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = 0.0;
     for (int j = sl; j < n; j += G) {
-        const double2 w = make_double2((X[st + j] - cx) * inv, (Y[st + j] - cy) * inv);
-        double2 t = mt[st + j];
+        const int i = st + j;
+        double2 w, t;
+        if constexpr (GATHER) {
+            // the gather's outputs for this point, as k_gather writes them
+            const double2 mm = go.m[go.perm[i]];
+            const double x = X[i], y = Y[i];
+            go.mtree[i] = mm;
+            if constexpr (std::is_same<T, float>::value) {
+                const float xh = (float)x, yh = (float)y;
+                go.src32[i] = make_float4(xh, yh, (float)mm.x, (float)mm.y);
+                go.srclo[i] = make_float2((float)(x - (double)xh), (float)(y - (double)yh));
+            } else {
+                go.src64[i] = make_double4(x, y, mm.x, mm.y);
+            }
+            w = make_double2((x - cx) * inv, (y - cy) * inv);
+            t = mm;
+        } else {
+            w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
+            t = mt[i];
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             v[2 * k] += t.x;
@@ -374,8 +392,10 @@ static int leaf_lanes(int leaf_max) { return leaf_max <= 16 ? 16 : (leaf_max <= 
 template <class T>
 void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount, int leaf_max,
                 const double* geom, const double* X, const double* Y, const double* mt, int p, void* mp,
-                hipStream_t s, const int32_t* parent, const double* binom)
+                hipStream_t s, const int32_t* parent, const double* binom, const GatherOut* go)
 {
+    const GatherOut none{};
+    const GatherOut& gg = go ? *go : none;
     if (nleaf == 0) return;
     const int G = leaf_lanes(leaf_max);
     const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
@@ -383,13 +403,21 @@ void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
     if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
         if constexpr (G_ == 16)                                                                           \
             if (parent) {                                                                                 \
-                k_p2m<T, G_, P_, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y,    \
-                                                            (const double2*)mt, p, (T*)mp, parent, binom); \
+                if (go)                                                                                   \
+                    k_p2m<T, G_, P_, true, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, \
+                        Y, (const double2*)mt, p, (T*)mp, parent, binom, gg);                             \
+                else                                                                                      \
+                    k_p2m<T, G_, P_, true, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, \
+                        Y, (const double2*)mt, p, (T*)mp, parent, binom, gg);                             \
                 check_launch("p2m");                                                                      \
                 return;                                                                                   \
             }                                                                                             \
-        k_p2m<T, G_, P_, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y,           \
-                                                     (const double2*)mt, p, (T*)mp, nullptr, nullptr);    \
+        if (go)                                                                                           \
+            k_p2m<T, G_, P_, false, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, \
+                (const double2*)mt, p, (T*)mp, nullptr, nullptr, gg);                                     \
+        else                                                                                              \
+            k_p2m<T, G_, P_, false, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, \
+                (const double2*)mt, p, (T*)mp, nullptr, nullptr, gg);                                     \
         check_launch("p2m");                                                                              \
         return;                                                                                           \
     }
@@ -448,7 +476,7 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
 #define INST(T)                                                                                          \
     template void launch_p2m<T>(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, \
                                 const double*, const double*, const double*, int, void*, hipStream_t,    \
-                                const int32_t*, const double*);                                          \
+                                const int32_t*, const double*, const GatherOut*);                        \
     template void launch_m2m<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \
                                 void*, hipStream_t);                                                     \
     template void launch_l2l<T>(const int32_t*, int, const int32_t*, const double*, const double*, int,  \

@@ -156,6 +156,7 @@ struct TreeSchedule {
     DBuf<int32_t> d_box_start, d_box_count, d_box_parent;
     DBuf<int32_t> d_box_prob;
     DBuf<int64_t> d_off;           // point offsets of the problems [nprob + 1]
+    DBuf<int64_t> d_pbox;          // global id of every problem's root box [nprob]
     DBuf<int8_t> d_box_level;
 };
 
@@ -197,7 +198,6 @@ struct Plan {
     int final_code = 0;            // an error of the deferred part, repeated by later calls
     std::string final_msg;
     DBuf<long long> lt_totals;     // list totals and flags of the pending build
-    DBuf<int64_t> lt_pbox;
     int flag_slot = -1;            // pinned host word receiving the one-pass flags
     hipEvent_t ev_lists = nullptr; // recorded after that copy
     hipEvent_t ev_lists_k = nullptr;     // recorded after the list kernels (before the copy)
@@ -273,6 +273,16 @@ void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
+// the gather of an evaluation (strengths into tree order, P2P source records)
+// done by the P2M kernel as it reads every point of its leaves
+struct GatherOut {
+    const int32_t* perm;     // tree position -> input index
+    const double2* m;        // strengths, input order
+    double2* mtree;          // strengths, tree order
+    double4* src64;          // FP64 path: (x, y, Re m, Im m)
+    float4* src32;           // mixed path: (x_hi, y_hi, Re m, Im m)
+    float2* srclo;           //             (x_lo, y_lo)
+};
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,
                     hipStream_t s);
 

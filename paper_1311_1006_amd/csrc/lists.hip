@@ -655,8 +655,6 @@ void build_lists_begin(Plan& pl, hipStream_t ls, hipStream_t as)
     int64_t nb = sc.nbox;
     hipStream_t s = ls;
     pl.s_beg.alloc(nb, as); pl.s_cnt.alloc(nb, as); pl.w_beg.alloc(nb, as); pl.w_cnt.alloc(nb, as);
-    pl.lt_pbox.alloc(sc.nprob, as);
-    FMM_HIP(hipMemcpyAsync(pl.lt_pbox.p, sc.pbox.data(), sizeof(int64_t) * sc.nprob, hipMemcpyHostToDevice, s));
     pl.lt_totals.alloc(4, as);
     pl.list_stream = s;
     PlanExtra& ex = *pl.ex;
@@ -667,7 +665,7 @@ void build_lists_begin(Plan& pl, hipStream_t ls, hipStream_t as)
         pl.s_ids.alloc(nb * ex.cap_strong, as);
         pl.w_ids.alloc(nb * ex.cap_weak, as);
         pl.nsrc.alloc(nb, as);
-        build_lists_direct(pl, s, pl.lt_totals.p, pl.lt_pbox.p);
+        build_lists_direct(pl, s, pl.lt_totals.p, sc.d_pbox.p);
         if (!pl.ev_lists_k) FMM_HIP(hipEventCreateWithFlags(&pl.ev_lists_k, hipEventDisableTiming));
         FMM_HIP(hipEventRecord(pl.ev_lists_k, s));
         // the flags go to a pinned word now, so that reading them later does
@@ -702,7 +700,7 @@ void build_lists_finish(Plan& pl)
     TreeSchedule& sc = *t.sched;
     int64_t nb = sc.nbox;
     long long* totals_p = pl.lt_totals.p;
-    const int64_t* pbox_p = pl.lt_pbox.p;
+    const int64_t* pbox_p = sc.d_pbox.p;
     PlanExtra& ex = *pl.ex;
     bool grow = false;
     if (pl.lists_direct) {

@@ -21,6 +21,7 @@ struct PlanExtra {
                                                     // L2L into the leaves runs inside L2P
     bool leaf_m2m_in_p2m = false;                   // ... and no leaf holds more than 16 points: the
                                                     // M2M of the leaves' parents runs inside P2M
+    bool gather_in_p2m = false;                     // the leaves hold every point: P2M does the gather
     int cap_strong = 0, cap_weak = 0;               // per-box list capacities of the one-pass build
     bool levelwise_only = false;                    // a frontier overflowed on this layout
     bool compact_only = false;                      // fixed capacities would need too much memory

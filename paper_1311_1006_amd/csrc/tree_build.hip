@@ -236,6 +236,7 @@ void upload_schedule(TreeSchedule& sc, hipStream_t s)
     upload(sc.d_box_level, sc.box_level, s);
     upload(sc.d_box_prob, sc.box_prob, s);
     upload(sc.d_off, sc.off, s);
+    upload(sc.d_pbox, sc.pbox, s);
     // the host vectors must stay alive until the copies ran
     FMM_HIP(hipStreamSynchronize(s));
 }
