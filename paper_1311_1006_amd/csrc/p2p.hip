@@ -101,31 +101,68 @@ __device__ __forceinline__ void pair32s(float xh, float yh, float xl, float yl, 
     ai = fmaf(b, y, ai);
 }
 
-// Sum v[0..V) over the lanes that differ in bits [0, log2(NL)) while
-// transposing: afterwards v[0] holds the total of value index
-// ((lane >> 1) & (V-1)) when V >= 2 (see the loop).  Requires V <= NL.
+// The value x of a partner lane whose bit M differs from this lane's and
+// whose other bits above M agree: lane ^ 1 and lane ^ 2 (quad
+// permutations), lane ^ 7 and lane ^ 15 (half-row and row mirrors) by DPP,
+// wider distances by a cross-lane permute (lane ^ M).
+template <int M>
+constexpr int kDppCtrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : M == 4 ? 0x141 : 0x140;
+template <int M>
+__device__ __forceinline__ float partner(float x)
+{
+    if constexpr (M <= 8)
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kDppCtrl<M>, 0xF, 0xF, false));
+    else
+        return __shfl_xor(x, M, 64);
+}
+template <int M>
+__device__ __forceinline__ double partner(double x)
+{
+    if constexpr (M <= 8) {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kDppCtrl<M>, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kDppCtrl<M>, 0xF, 0xF, false);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    } else {
+        return __shfl_xor(x, M, 64);
+    }
+}
+
+// Sum v[0..NV) over the aligned group of 2M lanes while transposing: at the
+// step of distance M the lane keeps the half of its values selected by its
+// bit M, summed with the partner's.  Both halves are summed and the sum is
+// selected (a select of two array elements would become a run-time index).
+// Every step's partner differs from the lane in bit M and in lower bits only,
+// so the lanes summed into a value form the whole group, each once.
+template <int M, int NV, int V, class T>
+__device__ __forceinline__ void butterfly_step(T (&v)[V], int lane)
+{
+    if constexpr (M >= 1) {
+        if constexpr (NV > 1) {
+            constexpr int H = NV / 2;
+            const bool hi = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const T lo_sum = v[i] + partner<M>(v[i]);
+                const T hi_sum = v[i + H] + partner<M>(v[i + H]);
+                v[i] = hi ? hi_sum : lo_sum;
+            }
+            butterfly_step<M / 2, H>(v, lane);
+        } else {
+            v[0] += partner<M>(v[0]);
+            butterfly_step<M / 2, 1>(v, lane);
+        }
+    }
+}
+
+// Sum v[0..V) over the NL lanes of the subgroup while transposing:
+// afterwards v[0] holds the total of value index butterfly_index<V, NL>.
+// Requires V <= NL.
 template <int V, int NL, class T>
 __device__ __forceinline__ void butterfly(T (&v)[V], int lane)
 {
-    int nv = V;
-#pragma unroll
-    for (int m = NL / 2; m >= 1; m >>= 1) {
-        if (nv > 1) {
-            const bool hi = (lane & m) != 0;
-            const int h = nv / 2;
-#pragma unroll
-            for (int i = 0; i < V / 2; ++i) {
-                if (i < h) {
-                    T keep = hi ? v[i + h] : v[i];
-                    T send = hi ? v[i] : v[i + h];
-                    v[i] = keep + __shfl_xor(send, m, 64);
-                }
-            }
-            nv = h;
-        } else {
-            v[0] += __shfl_xor(v[0], m, 64);
-        }
-    }
+    static_assert(V <= NL, "more values than lanes");
+    butterfly_step<NL / 2, V>(v, lane);
 }
 
 // value index held by `lane` after butterfly<V, NL>: the bits of the lane
@@ -155,11 +192,12 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
+    static_assert(kP2PSrcCap % NL == 0, "the padded run must fit the staging buffer");
     __shared__ Src64 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int xi_ = xcd_block() * 4 + w;
+    const int xi_ = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + w);   // one work item per wavefront
     if (xi_ >= nx) return;
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
@@ -186,22 +224,23 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     int e = 0, off = 0;
     if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
     for (int done = 0; done < s_len && e < ne;) {
-        const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
-                                                 lane, load, s_len - done);
+        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, s_len - done));
         done += ns;
+        // zero-strength sources (at the origin) pad the staged run to whole passes
+        const int npad = (ns + NL - 1) / NL * NL;
+        if (lane < npad - ns) lds[ns + lane] = Src64{0.0, 0.0, 0.0, 0.0};
+        wave_sync();
+        const Src64* sp = lds + sl;
         if constexpr (SMOOTH) {     // the smoothed near field
-            for (int c = 0; c < ns; c += NL) {
-                int f = c + sl;
-                Src64 s = lds[f < ns ? f : 0];
-                if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src64 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair64s(xi[t], yi[t], s, id2, ar[t], ai[t]);
             }
         } else {
-            for (int c = 0; c < ns; c += NL) {
-                int f = c + sl;
-                Src64 s = lds[f < ns ? f : 0];
-                if (f >= ns) { s.mr = 0.0; s.mi = 0.0; }
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src64 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair64(xi[t], yi[t], s, ar[t], ai[t]);
             }
@@ -234,11 +273,12 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
+    static_assert(kP2PSrcCap % NL == 0, "the padded run must fit the staging buffer");
     __shared__ Src32 sbuf[4][kP2PSrcCap];
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][kP2PSrcCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int xi_ = xcd_block() * 4 + w;
+    const int xi_ = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + w);   // one work item per wavefront
     if (xi_ >= nx) return;
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
@@ -268,22 +308,23 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     int e = 0, off = 0;
     if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
     for (int done = 0; done < s_len && e < ne;) {
-        const int ns = stage_sources<kP2PSrcCap>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off,
-                                                 lane, load, s_len - done);
+        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, s_len - done));
         done += ns;
+        // zero-strength sources (at the origin) pad the staged run to whole passes
+        const int npad = (ns + NL - 1) / NL * NL;
+        if (lane < npad - ns) lds[ns + lane] = Src32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        wave_sync();
+        const Src32* sp = lds + sl;
         if constexpr (SMOOTH) {     // the smoothed near field
-            for (int c = 0; c < ns; c += NL) {
-                int f = c + sl;
-                Src32 s = lds[f < ns ? f : 0];
-                if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src32 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair32s(xh[t], yh[t], xl[t], yl[t], s, id2, ar[t], ai[t]);
             }
         } else {
-            for (int c = 0; c < ns; c += NL) {
-                int f = c + sl;
-                Src32 s = lds[f < ns ? f : 0];
-                if (f >= ns) { s.mr = 0.f; s.mi = 0.f; }
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src32 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair32(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
             }

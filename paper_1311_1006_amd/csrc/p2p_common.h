@@ -15,11 +15,12 @@ __device__ __forceinline__ void wave_sync()
 // Gather sources of the strong list into LDS, resuming at (entry e, offset
 // off) and stopping after CAP sources (an entry may be split between
 // passes).  Entries are looked at 64 at a time (lane k: entry e + k, its
-// first source and the exclusive prefix of the source counts).  Every entry
-// marks the staging position where its sources start; the entry of a
-// position is then the largest mark at or before it (a running maximum over
-// the positions, lane-strided: position f = lane + 64 r).  Returns the
-// number of sources staged (at most `limit`).
+// first source and the exclusive prefix of the source counts).  The
+// non-empty entries that start inside the staged run are compacted in entry
+// order (meta) and flag their first staging position (mark); the entry of
+// position f = lane + 64 r is then the number of flags at or before f, less
+// one, counted with one ballot per row.  Returns the number of sources
+// staged (at most `limit`).
 template <int CAP, class SRC, class LOADER>
 __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, const int32_t* __restrict__ s_ids,
                                              const int32_t* __restrict__ bstart,
@@ -28,6 +29,7 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
 {
     constexpr int R = CAP / 64;
     const int lim = limit < CAP ? limit : CAP;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes before this one
     int staged = 0;
     while (e < e_end && staged < lim) {
         const int k = e + lane;
@@ -48,32 +50,23 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
         const int total = __shfl(x, 63, 64);
         const int cap = lim - staged;
         const int take = min(total, cap);
-        meta[lane] = make_int2(excl, st);
+        const bool starts = avail > 0 && excl < take;
+        const unsigned long long sm = __ballot(starts);
+        if (starts) meta[__popcll(sm & below)] = make_int2(excl, st);
 #pragma unroll
-        for (int r = 0; r < R; ++r) mark[lane + 64 * r] = -1;
+        for (int r = 0; r < R; ++r) mark[lane + 64 * r] = 0;
         wave_sync();
-        if (avail > 0 && excl < take) atomicMax(&mark[excl], lane);
+        if (starts) mark[excl] = 1;
         wave_sync();
-        // entry of every position: running maximum of the marks
-        int ent[R];
-        int carry = -1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            int v = mark[lane + 64 * r];
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(v, o, 64);
-                if (lane >= o) v = max(v, y);
-            }
-            v = max(v, carry);
-            ent[r] = v;
-            carry = __shfl(v, 63, 64);
-        }
         int src_idx[R];
+        int seen = 0;   // flags in earlier rows
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int f = lane + 64 * r;
-            const int2 mj = meta[ent[r] < 0 ? 0 : ent[r]];
+            const unsigned long long fl = __ballot(mark[f] != 0);
+            const int rk = seen + __popcll(fl & below) + (int)((fl >> lane) & 1ull) - 1;
+            seen += __popcll(fl);
+            const int2 mj = meta[rk < 0 ? 0 : rk];
             src_idx[r] = (f < take) ? mj.y + (f - mj.x) : -1;
         }
         SRC v[R];
@@ -84,20 +77,16 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
         for (int r = 0; r < R; ++r)
             if (src_idx[r] >= 0) lds[staged + lane + 64 * r] = v[r];
         // advance the cursor (uniform): the entry of the last staged position
+        // is the last non-empty entry starting at or before it
         if (take == total) {
             e = min(e + 64, e_end);
             off = 0;
         } else {
-            const int fl = take - 1;
-            int el = ent[0];
-#pragma unroll
-            for (int r = 1; r < R; ++r) el = (fl >> 6) == r ? ent[r] : el;
-            const int lo = __shfl(el, fl & 63, 64);
-            const int2 ml = meta[lo];
-            const int consumed = take - ml.x;
-            const int avail_lo = (lo + 1 < 64 ? meta[lo + 1].x : total) - ml.x;
-            if (consumed == avail_lo) { e = e + lo + 1; off = 0; }
-            else { off = (lo == 0 ? off : 0) + consumed; e = e + lo; }
+            const unsigned long long lm = __ballot(starts && excl <= take - 1);
+            const int L = 63 - __clzll((long long)lm);
+            const int consumed = take - __shfl(excl, L, 64);
+            if (consumed == __shfl(avail, L, 64)) { e = e + L + 1; off = 0; }
+            else { off = (L == 0 ? off : 0) + consumed; e = e + L; }
         }
         staged += take;
         wave_sync();
