@@ -102,6 +102,10 @@ struct TileInfo {
     // the segment's fields the split kernels need, copied here so that a
     // tile's first load brings them (no second dependent load)
     int32_t seg_start, seg_count, tile0, child;
+    int32_t range;    // segment whose bounding box sets the first-level histogram range
+                      // (the parent; the segment itself at stage 0)
+    int32_t flags;    // bit 0: the children are split by a global stage (this tile's
+                      // partition histograms them)
 };
 struct LdsWork {      // one segment finished by the in-LDS split kernel
     int32_t start, count;

@@ -300,9 +300,9 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
                 yi = M::step(amat[rb][ks], xv[ks].y, yi);
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                ore[rb][j] += fre[rb][j] * yr[j] - fim[rb][j] * yi[j];
-                oim[rb][j] += fre[rb][j] * yi[j] + fim[rb][j] * yr[j];
+            for (int j = 0; j < 4; ++j) {   // o += f y, complex, as two fused steps per part
+                ore[rb][j] = fma(fre[rb][j], (T)yr[j], fma(-fim[rb][j], (T)yi[j], ore[rb][j]));
+                oim[rb][j] = fma(fre[rb][j], (T)yi[j], fma(fim[rb][j], (T)yr[j], oim[rb][j]));
             }
         }
     };

@@ -11,20 +11,24 @@
 //   init        copy positions into SoA buffers, bounding box of each root,
 //               finiteness check;
 //   per global stage s (segments larger than one workgroup's LDS):
-//     hist1     2048-bucket histogram of the split coordinate per segment
-//               (buckets are equal-width in value between the segment's
-//               min and max, hence monotone in the coordinate);
+//     hist1     256-bucket histogram of the split coordinate per segment
+//               (buckets are equal-width in value over a range that holds
+//               the segment, hence monotone in the coordinate): at stage 0
+//               a kernel of its own over the root's bounding box; at later
+//               stages the parent stage's partition has already counted its
+//               children on both axes over the parent's bounding box;
 //     hist2     if the bucket holding the median rank has too many points,
 //               a second 2048-bucket histogram inside that bucket;
-//     select    each tile counts its points below the median's bucket and
-//               appends the points of that bucket to a candidate list; the
-//               last tile of a segment sorts the candidates, takes the exact
-//               median (coordinate, index) and turns per-tile counts into
-//               per-tile output offsets (an exact single-workgroup radix
-//               select is the fallback for pathological ties);
-//     partition stable two-way partition of every tile into the next
-//               buffer plus the bounding boxes of both halves (atomic
-//               min/max on order-preserving integer images of the doubles);
+//     collect   each tile counts its points below the median's bucket and
+//               appends the points of that bucket to a candidate list (an
+//               exact single-workgroup radix select is the fallback for
+//               pathological ties);
+//     partition every tile takes the exact median (coordinate, index) from
+//               the sorted candidates and its output offset, then does a
+//               stable two-way partition into the next buffer, with the
+//               bounding boxes of both halves (atomic min/max on
+//               order-preserving integer images of the doubles) and the
+//               children's histograms for the next stage;
 //   lds split   each remaining segment (<= 4096 points) is finished by one
 //               workgroup: the points are sorted once by (x, index) and once
 //               by (y, index); every later split keeps both lists sorted by
@@ -137,6 +141,8 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                         ti.seg_count = si.count;
                         ti.tile0 = si.tile0;
                         ti.child = si.child;
+                        ti.range = s == 0 ? (int32_t)gi : (int32_t)(sc->keys_off[s - 1] + kbase[s - 1][b] + (j >> 1));
+                        ti.flags = (s + 1 < g[b]) ? 1 : 0;
                         sc->tiles.push_back(ti);
                     }
                 }
@@ -188,7 +194,7 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                 ti.start = (int32_t)st;
                 ti.count = (int32_t)std::min<int64_t>(kTile, off[b + 1] - st);
                 ti.rank = 0;
-                ti.seg_start = ti.seg_count = ti.tile0 = ti.child = 0;
+                ti.seg_start = ti.seg_count = ti.tile0 = ti.child = ti.range = ti.flags = 0;
                 sc->copy_tiles.push_back(ti);
             }
         }
@@ -304,32 +310,82 @@ __device__ __forceinline__ void block_read_keys(const uint64_t* k, double* bb)
     bb[0] = okey_inv(sk[0]); bb[1] = okey_inv(sk[1]); bb[2] = okey_inv(sk[2]); bb[3] = okey_inv(sk[3]);
 }
 
+// Two levels of bucket selection: the first histogram of a segment has
+// kBuckets1 buckets over its extent, the second kBuckets2 buckets inside the
+// first-level bucket that holds the median (when that bucket is large).
+constexpr int kBuckets1 = 256;
+constexpr int kBuckets2 = kBuckets;
+// Every first-level histogram is kept as kHistCopies copies, updated by
+// workgroups of different block index, so that the atomics of the many
+// tiles of a large segment spread over several addresses; readers add them.
+// Layout: ((segment * 2 + axis) * kHistCopies + copy) * kBuckets1 + bucket.
+constexpr int kHistCopies = 8;
+static_assert(kBuckets1 == kTileThreads, "one first-level bucket per thread");
+
+template <class W>
+__device__ __forceinline__ W* hist1_at(W* h, int64_t seg, int axis, int copy)
+{
+    return h + ((seg * 2 + axis) * kHistCopies + copy) * kBuckets1;
+}
+
 struct Bucketer {
     double lo, scale;
     int axis;
 };
 
-// the bucketer of a segment, computed by the whole workgroup (every thread
-// of the block calls it, once per kernel)
-__device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys)
+// first-level buckets of one axis over the bounding box bb (x0 x1 y0 y1)
+__device__ __forceinline__ Bucketer axis_bucketer(const double* bb, int axis)
 {
-    double bbx[4];
-    block_read_keys(keys, bbx);
-    double x0 = bbx[0], x1 = bbx[1], y0 = bbx[2], y1 = bbx[3];
-    double w = (x1 - x0), h = (y1 - y0);
     Bucketer b;
-    b.axis = (w >= h) ? 0 : 1;
-    b.lo = b.axis ? y0 : x0;
-    double ext = b.axis ? h : w;
-    double sc = ext > 0.0 ? (double)kBuckets / ext : 0.0;
+    b.axis = axis;
+    b.lo = axis ? bb[2] : bb[0];
+    const double ext = axis ? (bb[3] - bb[2]) : (bb[1] - bb[0]);
+    const double sc = ext > 0.0 ? (double)kBuckets1 / ext : 0.0;
     b.scale = (sc < 1e300) ? sc : 0.0;
     return b;
+}
+
+// read_keys of two segments for a whole workgroup (one barrier)
+__device__ __forceinline__ void block_read_keys2(const uint64_t* k0, const uint64_t* k1, double* b0, double* b1)
+{
+    __shared__ uint64_t sk[8];
+    if (threadIdx.x < 64) {
+        const uint64_t* k = threadIdx.x < 32 ? k0 : k1;
+        const int c = threadIdx.x & (kKeyCopies - 1);
+        uint64_t a = k[4 * c], b = k[4 * c + 1], d = k[4 * c + 2], e = k[4 * c + 3];
+#pragma unroll
+        for (int o = kKeyCopies / 2; o > 0; o >>= 1) {
+            const uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
+            const uint64_t d2 = __shfl_xor(d, o, 64), e2 = __shfl_xor(e, o, 64);
+            a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
+            d = d2 < d ? d2 : d; e = e2 > e ? e2 : e;
+        }
+        if ((threadIdx.x & 31) == 0) {
+            const int o = threadIdx.x >> 3;   // 0 or 4
+            sk[o] = a; sk[o + 1] = b; sk[o + 2] = d; sk[o + 3] = e;
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) { b0[i] = okey_inv(sk[i]); b1[i] = okey_inv(sk[4 + i]); }
+}
+
+// The bucketer of a segment, computed by the whole workgroup (every thread
+// of the block calls it, once per kernel): the split axis from the
+// segment's own bounding box (the longer side), the bucket range from the
+// bounding box of segment `range` along that axis (the parent, whose
+// partition histograms the segment before its own box is complete).
+__device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys, const uint64_t* range_keys)
+{
+    double bb[4], rb[4];
+    block_read_keys2(keys, range_keys, bb, rb);
+    const double w = (bb[1] - bb[0]), h = (bb[3] - bb[2]);
+    return axis_bucketer(rb, (w >= h) ? 0 : 1);
 }
 
 __device__ __forceinline__ int bucket_of(const Bucketer& b, double c)
 {
     double v = ((c - b.lo) * b.scale);
-    int k = (int)fmin(fmax(v, 0.0), (double)(kBuckets - 1));
+    int k = (int)fmin(fmax(v, 0.0), (double)(kBuckets1 - 1));
     return k;
 }
 
@@ -467,31 +523,31 @@ k_hist1(const TileInfo* __restrict__ tiles, const double* __restrict__ X,
         const double* __restrict__ Y, const uint64_t* __restrict__ keys, uint32_t* hist1)
 {
     constexpr int R = kTile / kTileThreads;
-    __shared__ uint32_t h[kBuckets];
+    __shared__ uint32_t h[kBuckets1];
     TileInfo t = tiles[blockIdx.x];
-    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg, keys + kKeyWords * (int64_t)t.range);
     double v[R];
     load_tile(bk.axis ? Y : X, t, v);
-    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < kBuckets1; i += kTileThreads) h[i] = 0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (r * kTileThreads + (int)threadIdx.x < t.count) atomicAdd(&h[bucket_of(bk, v[r])], 1u);
     __syncthreads();
-    uint32_t* g = hist1 + (int64_t)t.seg * kBuckets;
-    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
+    uint32_t* g = hist1_at(hist1, t.seg, bk.axis, blockIdx.x & (kHistCopies - 1));
+    for (int i = threadIdx.x; i < kBuckets1; i += kTileThreads)
         if (h[i]) atomicAdd(&g[i], h[i]);
 }
 
-// find the bucket holding rank k: returns bucket, writes the rank inside it
-// and the bucket's count.  hist in global memory, 256 threads.
-__device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_in, int* sh)
+// find the bucket holding rank k among NB buckets: returns bucket, writes the
+// rank inside it and the bucket's count.  hist in global memory, 256 threads.
+// (find_bucket_loc: thread i holds the counts loc of buckets PER i .. PER i + PER - 1)
+template <int PER>
+__device__ int find_bucket_loc(const int (&loc)[PER], int k, int* rank_in, int* cnt_in, int* sh)
 {
-    constexpr int PER = kBuckets / kTileThreads;
-    int loc[PER];
     int s = 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) { loc[i] = (int)hist[threadIdx.x * PER + i]; s += loc[i]; }
+    for (int i = 0; i < PER; ++i) s += loc[i];
     int tot;
     int base = block_excl_scan<kTileThreads>(s, sh, &tot);
     // the thread whose range holds rank k writes the answer
@@ -511,6 +567,16 @@ __device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_i
     __syncthreads();
     return b;
 }
+template <int NB>
+__device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_in, int* sh)
+{
+    static_assert(NB % kTileThreads == 0, "whole buckets per thread");
+    constexpr int PER = NB / kTileThreads;
+    int loc[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) loc[i] = (int)hist[threadIdx.x * PER + i];
+    return find_bucket_loc<PER>(loc, k, rank_in, cnt_in, sh);
+}
 
 // a median bucket with more points than this is refined by a second histogram
 constexpr int kSubThreshold = 64;
@@ -522,13 +588,13 @@ __device__ __forceinline__ SubBucketer make_sub(const Bucketer& bk, int b1)
 {
     SubBucketer s;
     s.lo = bk.lo + (double)b1 / bk.scale;
-    s.scale = (bk.scale * (double)kBuckets);
+    s.scale = (bk.scale * (double)kBuckets2);
     return s;
 }
 __device__ __forceinline__ int sub_of(const SubBucketer& s, double c)
 {
     double v = ((c - s.lo) * s.scale);
-    return (int)fmin(fmax(v, 0.0), (double)(kBuckets - 1));
+    return (int)fmin(fmax(v, 0.0), (double)(kBuckets2 - 1));
 }
 
 // the first-level bucket of a segment's median (its rank inside the bucket
@@ -542,32 +608,41 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
         const double* __restrict__ X, const double* __restrict__ Y,
         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ hist1, uint32_t* hist2, Level1* lvl1)
 {
-    __shared__ uint32_t h[kBuckets];
+    __shared__ uint32_t h[kBuckets2];
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
+    // this thread's first-level bucket on both axes (the copies added),
+    // loaded while the bounding boxes are read
+    int hx = 0, hy = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) {
+        hx += (int)hist1_at(hist1, t.seg, 0, c)[threadIdx.x];
+        hy += (int)hist1_at(hist1, t.seg, 1, c)[threadIdx.x];
+    }
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg, keys + kKeyWords * (int64_t)t.range);
     int r1, c1;
-    int b1 = find_bucket(hist1 + (int64_t)t.seg * kBuckets, t.seg_count / 2, &r1, &c1, sh);
+    const int loc[1] = {bk.axis ? hy : hx};
+    int b1 = find_bucket_loc<1>(loc, t.seg_count / 2, &r1, &c1, sh);
     if (t.rank == 0 && threadIdx.x == 0) {
         Level1 v;
         v.b1 = b1; v.r1 = r1; v.c1 = c1; v.pad = 0;
         lvl1[t.seg] = v;
     }
     if (c1 <= kSubThreshold) return;   // uniform per block
-    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg);
     if (bk.scale == 0.0) return;  // all points in one bucket: the exact fallback handles it
     SubBucketer sb = make_sub(bk, b1);
     constexpr int R = kTile / kTileThreads;
     double v[R];
     load_tile(bk.axis ? Y : X, t, v);
-    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < kBuckets2; i += kTileThreads) h[i] = 0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (r * kTileThreads + (int)threadIdx.x < t.count && bucket_of(bk, v[r]) == b1)
             atomicAdd(&h[sub_of(sb, v[r])], 1u);
     __syncthreads();
-    uint32_t* g = hist2 + (int64_t)t.seg * kBuckets;
-    for (int i = threadIdx.x; i < kBuckets; i += kTileThreads)
+    uint32_t* g = hist2 + (int64_t)t.seg * kBuckets2;
+    for (int i = threadIdx.x; i < kBuckets2; i += kTileThreads)
         if (h[i]) atomicAdd(&g[i], h[i]);
 }
 
@@ -658,10 +733,10 @@ __device__ void exact_select(const double* C, const int32_t* I, int start, int c
 // the candidate class (one or two histogram levels) of a segment's median,
 // from the first-level bucket that hist2 recorded
 __device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const Level1* lvl1, const uint32_t* hist2,
-                                                  int seg, int* rank, int* ccount, int* sh)
+                                                  int seg, int range, int* rank, int* ccount, int* sh)
 {
     ClassRule rule;
-    rule.bk = make_bucketer(keys + kKeyWords * (int64_t)seg);
+    rule.bk = make_bucketer(keys + kKeyWords * (int64_t)seg, keys + kKeyWords * (int64_t)range);
     const Level1 L1 = lvl1[seg];
     const int r1 = L1.r1, c1 = L1.c1;
     rule.b1 = L1.b1;
@@ -671,7 +746,7 @@ __device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const Le
     if (c1 > kSubThreshold && rule.bk.scale != 0.0) {
         rule.sb = make_sub(rule.bk, rule.b1);
         int r2, c2;
-        rule.b2 = find_bucket(hist2 + (int64_t)seg * kBuckets, r1, &r2, &c2, sh);
+        rule.b2 = find_bucket<kBuckets2>(hist2 + (int64_t)seg * kBuckets2, r1, &r2, &c2, sh);
         *rank = r2;
         *ccount = c2;
     }
@@ -689,8 +764,9 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
 {
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
+    constexpr int R = kTile / kTileThreads;
     int rank, ccount;
-    ClassRule rule = median_class(keys, lvl1, hist2, t.seg, &rank, &ccount, sh);
+    ClassRule rule = median_class(keys, lvl1, hist2, t.seg, t.range, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
     if (t.rank == 0 && threadIdx.x == 0) {
         seg_over[t.seg] = overflow ? 1u : 0u;
@@ -698,7 +774,6 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
         ci.rank = rank; ci.count = ccount; ci.axis = rule.bk.axis; ci.pad = 0;
         cinfo[t.seg] = ci;
     }
-    constexpr int R = kTile / kTileThreads;
     double v[R];
     load_tile(rule.bk.axis ? Y : X, t, v);
     int below = 0;
@@ -737,7 +812,7 @@ k_pick(const int32_t* __restrict__ seglist, const SegInfo* __restrict__ segs, co
     if (seg_over[seg] == 0u) return;   // uniform per block
     const SegInfo sg = segs[seg];
     const int k = sg.count / 2;
-    const Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)seg);
+    const Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)seg, keys + kKeyWords * (int64_t)seg);
     const double* C = bk.axis ? Y : X;
     exact_select(C, I, sg.start, sg.count, k, &sp);
     for (int tt = 0; tt < sg.ntile; ++tt) {
@@ -877,13 +952,15 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
             double* X2, double* Y2, int32_t* I2, uint64_t* keys_next, const ClassInfo* __restrict__ cinfo,
             const Cand* __restrict__ cand, const uint32_t* __restrict__ tile_below,
-            const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base)
+            const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base, uint32_t* hist1)
 {
     constexpr int R = kTile / kTileThreads;
     constexpr int NW = kTileThreads / 64;
     __shared__ int wcnt[R][NW];
     __shared__ int sh[NW];
+    __shared__ uint32_t chist[4 * kBuckets1];   // the children's first-level histograms, (child, axis)
     const TileInfo t = tiles[blockIdx.x];
+    const bool hist_children = (t.flags & 1) != 0;   // uniform per block
     const int k = t.seg_count / 2;
     const int toff = t.start - t.seg_start;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -895,6 +972,16 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
         const int i = r * kTileThreads + threadIdx.x;
         const int ii = t.start + (i < t.count ? i : 0);
         x[r] = X[ii]; y[r] = Y[ii]; id[r] = I[ii];
+    }
+    // a child split by a later global stage is histogrammed here, on both
+    // axes over this segment's bounding box (its split axis is not known yet)
+    Bucketer cb[2];
+    if (hist_children) {
+        double bb[4];
+        block_read_keys(keys_next + kKeyWords * (int64_t)t.seg, bb);
+        cb[0] = axis_bucketer(bb, 0);
+        cb[1] = axis_bucketer(bb, 1);
+        for (int i = threadIdx.x; i < 4 * kBuckets1; i += kTileThreads) chist[i] = 0u;
     }
     const ClassInfo ci = cinfo[t.seg];
     Splitter sp;
@@ -943,11 +1030,25 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
                 anyu = true;
             }
             if (dst >= t.seg_start && dst < t.seg_start + t.seg_count) { X2[dst] = x[r]; Y2[dst] = y[r]; I2[dst] = id[r]; }
+            if (hist_children) {
+                const int c = lower[r] ? 0 : 2;   // (child, axis) slot of axis 0
+                atomicAdd(&chist[c * kBuckets1 + bucket_of(cb[0], x[r])], 1u);
+                atomicAdd(&chist[(c + 1) * kBuckets1 + bucket_of(cb[1], y[r])], 1u);
+            }
         }
         before += rowtot;
     }
+    // its barrier also completes the histogram updates above
     block_minmax2_atomic(l, u, anyl, anyu, keys_next + kKeyWords * (int64_t)t.child,
                          keys_next + kKeyWords * ((int64_t)t.child + 1));
+    if (hist_children) {   // slot c * 2 + axis: child t.child + c, one bucket per thread
+        const int copy = blockIdx.x & (kHistCopies - 1);
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+            const uint32_t v = chist[sl * kBuckets1 + threadIdx.x];
+            if (v) atomicAdd(&hist1_at(hist1, (int64_t)t.child + (sl >> 1), sl & 1, copy)[threadIdx.x], v);
+        }
+    }
 }
 
 // geometry of boxes whose bounding box came from a global stage
@@ -1315,9 +1416,9 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     DBuf<uint64_t> keys; keys.alloc(kKeyWords * nkeys, s);
     int64_t nseg_split = sc.nstage > 0 ? sc.keys_off[sc.nstage] : 0;   // segments of split stages
     DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | overflow flags | tile_below | tile_extra | lo_base | err
-    int64_t nh = nseg_split * kBuckets;
     int64_t nt = sc.total_tile;
-    int64_t o_h1 = 0, o_h2 = nh, o_cc = 2 * nh, o_ov = o_cc + nseg_split, o_tb = o_ov + nseg_split;
+    int64_t o_h1 = 0, o_h2 = nseg_split * 2 * kHistCopies * kBuckets1, o_cc = o_h2 + nseg_split * kBuckets2;
+    int64_t o_ov = o_cc + nseg_split, o_tb = o_ov + nseg_split;
     int64_t o_te = o_tb + nt, o_lb = o_te + nt, o_err = o_lb + nt, nwords = o_err + 1;
     words.alloc(nwords, s);
     DBuf<Cand> cand; cand.alloc(std::max<int64_t>(nseg_split, 1) * kCandCap, s);
@@ -1343,14 +1444,16 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
         if (ntl == 0) continue;
         const TileInfo* tl = sc.d_tiles.p + sc.tile_off[st];
         int a = st & 1;
-        k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
+        // later stages' first-level histograms come from the previous partition
+        if (st == 0) k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
         k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2, lvl1.p);
         k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, lvl1.p, W + o_h2,
                                               cand.p, W + o_cc, W + o_tb, W + o_ov, cinfo.p);
         k_pick<<<sc.nact[st], kTileThreads, 0, s>>>(sc.d_act.p + sc.act_off[st], sc.d_segs.p, sc.d_tiles.p, Xb[a],
                                                    Yb[a], Ib[a], keys.p, W + o_ov, W + o_tb, W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
-                                                Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb);
+                                                Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb,
+                                                W + o_h1);
         check_launch("split stage");
     }
     if (!sc.lds.empty()) {
