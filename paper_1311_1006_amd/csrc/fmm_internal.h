@@ -138,10 +138,6 @@ struct TreeSchedule {
     int64_t total_seg = 0, total_tile = 0, total_keys = 0;
     std::vector<SegInfo> segs;
     std::vector<TileInfo> tiles;
-    std::vector<int32_t> act;             // segments split by a global stage, grouped by stage
-    std::vector<int64_t> act_off;
-    std::vector<int> nact;
-    DBuf<int32_t> d_act;
     std::vector<int32_t> key_child_dummy;
     std::vector<LdsWork> lds;
     std::vector<GeomJob> geom;      // boxes whose geometry comes from global-stage keys

@@ -107,10 +107,7 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
     sc->segs.assign(sc->total_keys, SegInfo{});
     sc->tile_off.assign(nstage + 1, 0);
     sc->ntile.assign(nstage, 0);
-    sc->act_off.assign(nstage + 1, 0);
-    sc->nact.assign(nstage, 0);
     for (int s = 0; s <= nstage; ++s) {
-        sc->act_off[s] = (int64_t)sc->act.size();
         for (int b = 0; b < nprob; ++b) {
             if (s > g[b]) continue;
             int64_t n = off[b + 1] - off[b];
@@ -126,7 +123,6 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
                 si.tile0 = 0;
                 si.ntile = 0;
                 if (s < g[b]) {
-                    sc->act.push_back((int32_t)gi);
                     si.child = (int32_t)(sc->keys_off[s + 1] + kbase[s + 1][b] + 2 * j);
                     si.tile0 = (int32_t)sc->tiles.size();
                     int32_t nt = (int32_t)((cnt + kTile - 1) / kTile);
@@ -151,7 +147,6 @@ TreeSchedule* make_schedule(const std::vector<int64_t>& off, const std::vector<i
         if (s < nstage) {
             sc->tile_off[s + 1] = (int64_t)sc->tiles.size();
             sc->ntile[s] = (int)(sc->tile_off[s + 1] - sc->tile_off[s]);
-            sc->nact[s] = (int)((int64_t)sc->act.size() - sc->act_off[s]);
         }
     }
     sc->total_tile = (int64_t)sc->tiles.size();
@@ -232,7 +227,6 @@ void upload_schedule(TreeSchedule& sc, hipStream_t s)
 {
     upload(sc.d_segs, sc.segs, s);
     upload(sc.d_tiles, sc.tiles, s);
-    upload(sc.d_act, sc.act, s);
     upload(sc.d_copy, sc.copy_tiles, s);
     upload(sc.d_lds, sc.lds, s);
     upload(sc.d_geom, sc.geom, s);
@@ -753,14 +747,50 @@ __device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const Le
     return rule;
 }
 
+// Segments whose median class holds more than kCandCap points (heavy ties):
+// one workgroup finds the exact median (coordinate, index) of the segment
+// by a radix select, and the output offset of every tile's lower half.
+__device__ void pick_exact(int seg, const SegInfo& sg, const TileInfo* __restrict__ all_tiles,
+                           const double* __restrict__ C, const int32_t* __restrict__ I, uint32_t* tile_below,
+                           uint32_t* lo_base, Splitter* split, int* sh)
+{
+    __shared__ Splitter sp;
+    const int k = sg.count / 2;
+    exact_select(C, I, sg.start, sg.count, k, &sp);
+    for (int tt = 0; tt < sg.ntile; ++tt) {
+        TileInfo ti = all_tiles[sg.tile0 + tt];
+        int cnt = 0;
+        for (int i = threadIdx.x; i < ti.count; i += kTileThreads)
+            cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
+        int tot2;
+        block_excl_scan<kTileThreads>(cnt, sh, &tot2);
+        if (threadIdx.x == 0) tile_below[sg.tile0 + tt] = (uint32_t)tot2;
+    }
+    __syncthreads();
+    // exclusive scan of the per-tile lower counts into output offsets
+    int run = 0;
+    for (int c0 = 0; c0 < sg.ntile; c0 += kTileThreads) {
+        int i = c0 + threadIdx.x;
+        int v = (i < sg.ntile) ? (int)tile_below[sg.tile0 + i] : 0;
+        int tot3;
+        int ex = block_excl_scan<kTileThreads>(v, sh, &tot3);
+        if (i < sg.ntile) lo_base[sg.tile0 + i] = (uint32_t)(run + ex);
+        run += tot3;
+    }
+    if (threadIdx.x == 0) split[seg] = sp;
+}
+
 // every tile: count of points below the median's class, and the points of
-// that class appended to the segment's candidate list
+// that class appended to the segment's candidate list.  When the class
+// overflowed, the last tile of the segment to finish (per-segment counter
+// seg_done) runs the exact selection for the whole segment; the partition
+// tiles of other segments find the median themselves.
 __global__ void __launch_bounds__(kTileThreads)
-k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
+k_collect(const TileInfo* __restrict__ tiles, const TileInfo* __restrict__ all_tiles, const SegInfo* __restrict__ segs,
           const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
           const uint64_t* __restrict__ keys, const Level1* __restrict__ lvl1,
           const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below,
-          uint32_t* seg_over, ClassInfo* cinfo)
+          uint32_t* seg_done, ClassInfo* cinfo, uint32_t* lo_base, Splitter* split)
 {
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
@@ -769,7 +799,6 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     ClassRule rule = median_class(keys, lvl1, hist2, t.seg, t.range, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
     if (t.rank == 0 && threadIdx.x == 0) {
-        seg_over[t.seg] = overflow ? 1u : 0u;
         ClassInfo ci;
         ci.rank = rank; ci.count = ccount; ci.axis = rule.bk.axis; ci.pad = 0;
         cinfo[t.seg] = ci;
@@ -794,48 +823,17 @@ k_collect(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     int tot;
     block_excl_scan<kTileThreads>(below, sh, &tot);
     if (threadIdx.x == 0) tile_below[t.tile0 + t.rank] = (uint32_t)tot;
-}
-
-// Segments whose median class holds more than kCandCap points (heavy ties):
-// one workgroup per segment finds the exact median (coordinate, index) by a
-// radix select and the output offset of every tile's lower half.  Other
-// segments leave at once; their partition tiles find the median themselves.
-__global__ void __launch_bounds__(kTileThreads)
-k_pick(const int32_t* __restrict__ seglist, const SegInfo* __restrict__ segs, const TileInfo* __restrict__ all_tiles,
-       const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-       const uint64_t* __restrict__ keys, const uint32_t* __restrict__ seg_over, uint32_t* tile_below,
-       uint32_t* lo_base, Splitter* split)
-{
-    __shared__ int sh[kTileThreads / 64];
-    __shared__ Splitter sp;
-    const int seg = seglist[blockIdx.x];
-    if (seg_over[seg] == 0u) return;   // uniform per block
-    const SegInfo sg = segs[seg];
-    const int k = sg.count / 2;
-    const Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)seg, keys + kKeyWords * (int64_t)seg);
-    const double* C = bk.axis ? Y : X;
-    exact_select(C, I, sg.start, sg.count, k, &sp);
-    for (int tt = 0; tt < sg.ntile; ++tt) {
-        TileInfo ti = all_tiles[sg.tile0 + tt];
-        int cnt = 0;
-        for (int i = threadIdx.x; i < ti.count; i += kTileThreads)
-            cnt += key_less(C[ti.start + i], I[ti.start + i], sp.c, sp.idx);
-        int tot2;
-        block_excl_scan<kTileThreads>(cnt, sh, &tot2);
-        if (threadIdx.x == 0) tile_below[sg.tile0 + tt] = (uint32_t)tot2;
+    if (overflow) {   // uniform per block
+        __shared__ bool last;
+        __threadfence();   // this tile's count is visible before the tile is counted done
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(&seg_done[t.seg], 1u) + 1u == (uint32_t)segs[t.seg].ntile;
+        __syncthreads();
+        if (last) {   // every tile of the segment has written its count: overwrite them all
+            __threadfence();
+            pick_exact(t.seg, segs[t.seg], all_tiles, rule.bk.axis ? Y : X, I, tile_below, lo_base, split, sh);
+        }
     }
-    __syncthreads();
-    // exclusive scan of the per-tile lower counts into output offsets
-    int run = 0;
-    for (int c0 = 0; c0 < sg.ntile; c0 += kTileThreads) {
-        int i = c0 + threadIdx.x;
-        int v = (i < sg.ntile) ? (int)tile_below[sg.tile0 + i] : 0;
-        int tot3;
-        int ex = block_excl_scan<kTileThreads>(v, sh, &tot3);
-        if (i < sg.ntile) lo_base[sg.tile0 + i] = (uint32_t)(run + ex);
-        run += tot3;
-    }
-    if (threadIdx.x == 0) split[seg] = sp;
 }
 
 // bounding boxes of both halves of a tile into the next stage's keys (one
@@ -1415,10 +1413,10 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
     int64_t nkeys = sc.total_keys;
     DBuf<uint64_t> keys; keys.alloc(kKeyWords * nkeys, s);
     int64_t nseg_split = sc.nstage > 0 ? sc.keys_off[sc.nstage] : 0;   // segments of split stages
-    DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | overflow flags | tile_below | tile_extra | lo_base | err
+    DBuf<uint32_t> words;   // hist1 | hist2 | cand_cnt | tiles done per segment | tile_below | tile_extra | lo_base | err
     int64_t nt = sc.total_tile;
     int64_t o_h1 = 0, o_h2 = nseg_split * 2 * kHistCopies * kBuckets1, o_cc = o_h2 + nseg_split * kBuckets2;
-    int64_t o_ov = o_cc + nseg_split, o_tb = o_ov + nseg_split;
+    int64_t o_sd = o_cc + nseg_split, o_tb = o_sd + nseg_split;
     int64_t o_te = o_tb + nt, o_lb = o_te + nt, o_err = o_lb + nt, nwords = o_err + 1;
     words.alloc(nwords, s);
     DBuf<Cand> cand; cand.alloc(std::max<int64_t>(nseg_split, 1) * kCandCap, s);
@@ -1447,10 +1445,9 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
         // later stages' first-level histograms come from the previous partition
         if (st == 0) k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
         k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2, lvl1.p);
-        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, lvl1.p, W + o_h2,
-                                              cand.p, W + o_cc, W + o_tb, W + o_ov, cinfo.p);
-        k_pick<<<sc.nact[st], kTileThreads, 0, s>>>(sc.d_act.p + sc.act_off[st], sc.d_segs.p, sc.d_tiles.p, Xb[a],
-                                                   Yb[a], Ib[a], keys.p, W + o_ov, W + o_tb, W + o_lb, split.p);
+        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_tiles.p, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, lvl1.p,
+                                              W + o_h2, cand.p, W + o_cc, W + o_tb, W + o_sd, cinfo.p, W + o_lb,
+                                              split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
                                                 Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb,
                                                 W + o_h1);
