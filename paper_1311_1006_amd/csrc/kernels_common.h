@@ -25,6 +25,14 @@ __device__ __forceinline__ int xcd_block()
     return x < rem ? x * (full + 1) + i : rem * (full + 1) + (x - rem) * full + i;
 }
 
+// orders the LDS accesses of one wavefront (no workgroup barrier)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <class T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };

@@ -11,17 +11,20 @@
 // the sum over the pairs of the target.  Under the theta-criterion
 // |u| + |w| <= 2 theta/(1+theta), so every scaled term is at most 1.
 //
-// One wavefront per target box, blocks of 16 weak pairs (one or two blocks
-// per iteration).  Lane (kq, q),
-// kq = lane/16, q = lane%16, owns pair q of the block: it computes the powers
+// One wavefront per target box (or 2 or 4 boxes), blocks of 16 weak pairs.
+// Lane (kq, q), kq = lane/16, q = lane%16, feeds column q of the block (a
+// pair): it computes the powers
 // it feeds to the MFMA (x_k for k = kq + 4i, the B operand of k-step i) and
 // the row factors of the output rows it holds, and accumulates f_l * Y_lq in
 // registers.  FP64 path: powers in FP64.  Mixed path: the centre difference
 // in FP64, the powers in FP32 (their rounding stays below that of the FP32
 // coefficients they multiply).
-// No LDS and no barriers: the geometry and coefficients of the next block
-// are loaded while the current one is computed.  At the end the 16 pair
-// slots are summed by a butterfly.
+// The blocks go in groups of four: each lane computes the geometry of one
+// pair of the group (centre difference, 1/d and the powers of u and w) once
+// and shares it through the wavefront's LDS with the other three lanes of
+// that pair's column; no workgroup barriers.  Source centres are loaded a
+// group ahead, coefficients a block ahead.  At the end the 16 pair slots
+// are summed by a butterfly.
 // FP32 path: v_mfma_f32_16x16x4f32 (output rows 4 kq + j), FP32 accumulation.
 // FP64 path: v_mfma_f64_16x16x4f64 (output rows kq + 4 j).
 // p <= 16 uses one 16-row block (PB = 1), p <= 32 two.
@@ -76,12 +79,13 @@ __device__ __forceinline__ C2 cpow_lane(C2 z, C2 z2, int e)
     return cmul(csel(e & 1, z, one), csel(e & 2, z2, one));
 }
 
-// The data of one block of pairs held by one lane: source centre and scaling
-// radius, and the coefficients a_k, k = kq + 4i, of its pair.
-template <class T, int KS>
-struct PairData {
-    double sx, sy, rs;
-    typename Vec2<T>::type a[KS];
+// The geometry of one pair, computed once by one lane and shared through
+// LDS with the four lanes that feed the pair's MFMA column: 1/d, u = rs_S/d
+// and its square and fourth power, w = -rs_T/d and its powers 2, 4, 8.
+template <class T>
+struct PairGeo {
+    using T2 = typename Vec2<T>::type;
+    T2 id, u, u2, u4, wv, w2, w4, w8;
 };
 
 // Loads that stay where they are written: relaxed atomic loads of wavefront
@@ -108,21 +112,17 @@ __device__ __forceinline__ double2 ld_pin(const double2* p)
     return make_double2(ld_pin(d), ld_pin(d + 1));
 }
 
+// the coefficients a_k, k = kq + 4i, of box S (k clamped to p - 1: every
+// load in bounds; the values of k >= p meet zero columns of B)
 template <class T, int KS>
-__device__ __forceinline__ void load_pair(PairData<T, KS>& d, int S, int kq, int p, const double* __restrict__ geom,
+__device__ __forceinline__ void load_coef(typename Vec2<T>::type (&a)[KS], int S, int kq, int p,
                                           const T* __restrict__ mp)
 {
-    const double* gs = geom + 4 * (int64_t)S;
-    d.sx = ld_pin(gs);
-    d.sy = ld_pin(gs + 1);
-    d.rs = ld_pin(gs + 3);
-    const typename Vec2<T>::type* a = reinterpret_cast<const typename Vec2<T>::type*>(mp) + (int64_t)S * p;
-    // every load in bounds (S is a box, k clamped to p - 1); the values of
-    // padding lanes and of k >= p are masked where they are used
+    const typename Vec2<T>::type* src = reinterpret_cast<const typename Vec2<T>::type*>(mp) + (int64_t)S * p;
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
         const int k = kq + 4 * i;
-        d.a[i] = ld_pin(a + (k < p ? k : p - 1));
+        a[i] = ld_pin(src + (k < p ? k : p - 1));
     }
 }
 
@@ -134,6 +134,7 @@ __device__ __forceinline__ float2 scale_coef(double2 pw, float2 a)
     return cmul(w, a);
 }
 __device__ __forceinline__ double2 scale_coef(double2 pw, double2 a) { return cmul(pw, a); }
+__device__ __forceinline__ float2 scale_coef(float2 pw, float2 a) { return cmul(pw, a); }
 
 // 1/(dx^2 + dy^2) by v_rcp_f64 and two Newton steps
 __device__ __forceinline__ double rcp_nr(double r2)
@@ -143,6 +144,44 @@ __device__ __forceinline__ double rcp_nr(double r2)
     y = fma(y, e, y);
     e = fma(-r2, y, 1.0);
     return fma(y, e, y);
+}
+
+// Geometry of the pair (target centre ct, radius rsT; source centre cs,
+// radius rs).  A padding pair (valid false) gets 1/d = 0, hence zero
+// factors everywhere.  Mixed path: the centre difference in FP64 (the
+// centres are close in value), everything after it in FP32.
+__device__ __forceinline__ PairGeo<float> make_geo(float, double ctx, double cty, double rsT, double sx, double sy,
+                                                   double rs_s, bool valid)
+{
+    PairGeo<float> g;
+    const float dx = (float)(ctx - sx), dy = (float)(cty - sy);
+    const float den = valid ? __builtin_amdgcn_rcpf(dx * dx + dy * dy) : 0.f;
+    g.id = make_float2(dx * den, -dy * den);
+    const float rs = (float)rs_s, rt = (float)rsT;
+    g.u = make_float2(rs * g.id.x, rs * g.id.y);
+    g.wv = make_float2(-rt * g.id.x, -rt * g.id.y);
+    g.u2 = cmul(g.u, g.u);
+    g.u4 = cmul(g.u2, g.u2);
+    g.w2 = cmul(g.wv, g.wv);
+    g.w4 = cmul(g.w2, g.w2);
+    g.w8 = cmul(g.w4, g.w4);
+    return g;
+}
+__device__ __forceinline__ PairGeo<double> make_geo(double, double ctx, double cty, double rsT, double sx, double sy,
+                                                    double rs, bool valid)
+{
+    PairGeo<double> g;
+    const double dx = ctx - sx, dy = cty - sy;
+    const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
+    g.id = make_double2(dx * den, -dy * den);
+    g.u = make_double2(rs * g.id.x, rs * g.id.y);
+    g.wv = make_double2(-rsT * g.id.x, -rsT * g.id.y);
+    g.u2 = cmul(g.u, g.u);
+    g.u4 = cmul(g.u2, g.u2);
+    g.w2 = cmul(g.wv, g.wv);
+    g.w4 = cmul(g.w2, g.w2);
+    g.w8 = cmul(g.w4, g.w4);
+    return g;
 }
 
 template <class T, int PB, int G>
@@ -204,90 +243,59 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         for (int j = 0; j < 4; ++j) { ore[rb][j] = (T)0; oim[rb][j] = (T)0; }
 
     const double ctx = geom[4 * (int64_t)g], cty = geom[4 * (int64_t)g + 1], rsT = geom[4 * (int64_t)g + 3];
-    const float rsTf = (float)rsT;
+
     // first output row of this lane within a 16-row block; the rows it holds
     // are r0 + j (FP32) or r0 + 4 j (FP64)
     const int r0 = M::kRowsConsecutive ? 4 * kq : kq;
 
-    // software pipeline over blocks, unrolled by two with two register
-    // buffers: while one buffer's pairs are computed, the other buffer's
-    // geometry and coefficients (next block) and the ids of the block after
-    // are in flight.  Every load is unconditional (indices clamped into the
+    // Blocks go in groups of four.  Lane (kq, q) computes the geometry of the
+    // pair in column q of block 4 gi + kq once and puts it (with the source
+    // id) into LDS; every block then reads its column's geometry from there.
+    // Loads run ahead: the next group's source centres and the ids of the
+    // group after it during a group, the coefficients of the next block
+    // during a block.  Every load is unconditional (indices clamped into the
     // list, padding replaced by pad_id).
+    // one array per field ([field][block][column]): the 16 columns of a
+    // block read 16 consecutive entries, free of bank conflicts
+    __shared__ T2 sgeo[4][8][4][16];
+    __shared__ int ssid[4][4][16];
+    T2(*geo)[4][16] = sgeo[w];
+    int(*gsid)[16] = ssid[w];
+    auto put_geo = [&](const PairGeo<T>& c) {
+        geo[0][kq][q] = c.id; geo[1][kq][q] = c.u; geo[2][kq][q] = c.u2; geo[3][kq][q] = c.u4;
+        geo[4][kq][q] = c.wv; geo[5][kq][q] = c.w2; geo[6][kq][q] = c.w4; geo[7][kq][q] = c.w8;
+    };
+    auto get_geo = [&](int j) {
+        PairGeo<T> c;
+        c.id = geo[0][j][q]; c.u = geo[1][j][q]; c.u2 = geo[2][j][q]; c.u4 = geo[3][j][q];
+        c.wv = geo[4][j][q]; c.w2 = geo[5][j][q]; c.w4 = geo[6][j][q]; c.w8 = geo[7][j][q];
+        return c;
+    };
     const int last = nw > 0 ? nw - 1 : 0;
     auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : pad_id; };
-    auto compute = [&](const PairData<T, KS>& c, int bi) {
-        const bool valid = bi * S + sl < nw;
-        // Padding slots (past the end of an item's list) hold a real weak
-        // source, so every coefficient is finite; they get 1/d = 0, hence
-        // zero row factors, and add nothing.  Terms k >= p meet zero columns
-        // of B and rows l >= p are not stored.
+    auto gpair = [&](int gi) { return (4 * gi + kq) * S + sl; };   // this lane's geometry pair in group gi
+    auto compute = [&](const PairGeo<T>& c, const T2 (&a)[KS]) {
+        // Terms k >= p meet zero columns of B and rows l >= p are not stored.
         T2 xv[KS];
         T fre[PB][4], fim[PB][4];
-        if constexpr (std::is_same<T, float>::value) {
-            // mixed: the centre difference in FP64 (the centres are close in
-            // value), everything after it in FP32
-            const float dx = (float)(ctx - c.sx), dy = (float)(cty - c.sy);
-            const float den = valid ? __builtin_amdgcn_rcpf(dx * dx + dy * dy) : 0.f;
-            const float2 id = make_float2(dx * den, -dy * den);        // 1/d (0 for padding)
-            const float rs = (float)c.rs;
-            const float2 u = make_float2(rs * id.x, rs * id.y);        // rs_S / d
-            const float2 wv = make_float2(-rsTf * id.x, -rsTf * id.y); // -rs_T / d
-            const float2 u2 = cmul(u, u), u4 = cmul(u2, u2);
-            const float2 w2 = cmul(wv, wv), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
-            float2 pw = cpow_lane(u, u2, kq);                           // u^kq
+        auto pw = cpow_lane(c.u, c.u2, kq);                             // u^kq
 #pragma unroll
-            for (int i = 0; i < KS; ++i) {
-                xv[i] = cmul(pw, c.a[i]);
-                if (i + 1 < KS) pw = cmul(pw, u4);
-            }
-            // output rows 16 rb + 4 kq + j: f = (1/d) w^(4 kq + j) w^(16 rb)
-            const float2 f0 = cmul(cpow_lane(w4, w8, kq), id);
+        for (int i = 0; i < KS; ++i) {
+            xv[i] = scale_coef(pw, a[i]);
+            if (i + 1 < KS) pw = cmul(pw, c.u4);
+        }
+        // row factors f_l = (1/d) w^l of this lane's output rows
+        const auto base = M::kRowsConsecutive ? cpow_lane(c.w4, c.w8, kq) : cpow_lane(c.wv, c.w2, kq);   // w^r0
+        const auto step = M::kRowsConsecutive ? c.wv : c.w4;
+        const auto f0 = cmul(base, c.id);
 #pragma unroll
-            for (int rb = 0; rb < PB; ++rb) {
-                float2 f = rb > 0 ? cmul(f0, cmul(w8, w8)) : f0;
+        for (int rb = 0; rb < PB; ++rb) {
+            auto f = rb > 0 ? cmul(f0, cmul(c.w8, c.w8)) : f0;             // row r0 + 16: times w^16
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    fre[rb][j] = f.x;
-                    fim[rb][j] = f.y;
-                    if (j < 3) f = cmul(f, wv);
-                }
-            }
-        } else {
-            // ---- FP64 powers of this lane's pair
-            const double dx = ctx - c.sx, dy = cty - c.sy;
-            const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
-            const double2 id = make_double2(dx * den, -dy * den);          // 1/d (0 for padding)
-            const double2 u = make_double2(c.rs * id.x, c.rs * id.y);      // rs_S / d
-            const double2 wv = make_double2(-rsT * id.x, -rsT * id.y);     // -rs_T / d
-            const double2 u2 = cmul(u, u), u4 = cmul(u2, u2);
-            const double2 w2 = cmul(wv, wv), w4 = cmul(w2, w2);
-            // B operands x_k, k = kq + 4 i
-            double2 pw = cpow_lane(u, u2, kq);
-#pragma unroll
-            for (int i = 0; i < KS; ++i) {
-                xv[i] = scale_coef(pw, c.a[i]);
-                if (i + 1 < KS) pw = cmul(pw, u4);
-            }
-            // row factors f_l = (1/d) w^l of this lane's output rows
-            double2 base;                    // w^r0
-            if (M::kRowsConsecutive) base = cpow_lane(w4, cmul(w4, w4), kq);
-            else base = cpow_lane(wv, w2, kq);
-            const double2 step = M::kRowsConsecutive ? wv : w4;
-            double2 f0 = cmul(base, id);
-#pragma unroll
-            for (int rb = 0; rb < PB; ++rb) {
-                double2 f = f0;
-                if (rb > 0) {                // row r0 + 16: times w^16
-                    const double2 w8 = cmul(w4, w4);
-                    f = cmul(f0, cmul(w8, w8));
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    fre[rb][j] = (T)f.x;
-                    fim[rb][j] = (T)f.y;
-                    if (j < 3) f = cmul(f, step);
-                }
+            for (int j = 0; j < 4; ++j) {
+                fre[rb][j] = (T)f.x;
+                fim[rb][j] = (T)f.y;
+                if (j < 3) f = cmul(f, step);
             }
         }
         // ---- MFMA: Y = B Re(X), B Im(X); scale rows by f and accumulate
@@ -306,20 +314,39 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
             }
         }
     };
-    PairData<T, KS> bufA, bufB;
-    int sidA, sidB;
-    load_pair<T, KS>(bufA, raw_id(sl), kq, p, geom, mp);
-    sidB = raw_id(S + sl);
-    for (int bi = 0; bi < nblk; bi += 2) {
-        // block bi in bufA; load block bi + 1 into bufB, the id of block bi + 2
-        sidA = raw_id((bi + 2) * S + sl);
-        load_pair<T, KS>(bufB, sidB, kq, p, geom, mp);
-        compute(bufA, bi);
-        if (bi + 1 >= nblk) break;
-        // block bi + 1 in bufB; load block bi + 2 into bufA, the id of block bi + 3
-        sidB = raw_id((bi + 3) * S + sl);
-        load_pair<T, KS>(bufA, sidA, kq, p, geom, mp);
-        compute(bufB, bi + 1);
+    const int ngrp = (nblk + 3) / 4;
+    int gid = raw_id(gpair(0));                 // this lane's geometry pair, group 0
+    const double* gs = geom + 4 * (int64_t)gid;
+    double gsx = ld_pin(gs), gsy = ld_pin(gs + 1), grs = ld_pin(gs + 3);
+    int gid_n = raw_id(gpair(1));               // group 1
+    T2 ca[KS], cb[KS];
+    load_coef<T, KS>(ca, __shfl(gid, q, 64), kq, p, mp);   // block 0: lane q's geometry pair
+    for (int gi = 0; gi < ngrp; ++gi) {
+        put_geo(make_geo(T(0), ctx, cty, rsT, gsx, gsy, grs, gpair(gi) < nw));
+        gsid[kq][q] = gid;
+        // the next group's source centres, the ids of the group after it
+        gid = gid_n;
+        gs = geom + 4 * (int64_t)gid;
+        gsx = ld_pin(gs);
+        gsy = ld_pin(gs + 1);
+        grs = ld_pin(gs + 3);
+        gid_n = raw_id(gpair(gi + 2));
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (4 * gi + j >= nblk) break;   // uniform per wavefront
+            // the next block's source: the next column of this group, or
+            // block 0 of the next group (lane q's geometry pair there)
+            const int nsid = j < 3 ? gsid[j + 1][q] : __shfl(gid, q, 64);
+            if (j % 2 == 0) {
+                load_coef<T, KS>(cb, nsid, kq, p, mp);
+                compute(get_geo(j), ca);
+            } else {
+                load_coef<T, KS>(ca, nsid, kq, p, mp);
+                compute(get_geo(j), cb);
+            }
+        }
+        wave_sync();   // the group's LDS is rewritten next
     }
     // ---- sum over the S slots of every item (lanes differing in the low bits of q)
 #pragma unroll

@@ -3,14 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-namespace fmm {
+#include "kernels_common.h"
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+namespace fmm {
 
 // Gather sources of the strong list into LDS, resuming at (entry e, offset
 // off) and stopping after CAP sources (an entry may be split between
