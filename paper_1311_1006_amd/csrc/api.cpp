@@ -18,8 +18,11 @@ namespace fmm {
 // -------------------------------------------------------------- allocator
 // Blocks are never returned to the driver while the process lives (hipFree
 // synchronises the device); a freed block is reused for a request of the
-// same size class.  Blocks remember the stream of their last use; reuse on a
-// different stream first waits for that stream.
+// same size class on the same stream only.  A block is freed in stream order
+// on the stream it was allocated on (work of other streams on it has been
+// joined into that stream), so a reuse there needs no wait at all; a request
+// on another stream takes a fresh block instead of waiting for the old
+// stream (which would stall the host behind unrelated work queued there).
 namespace {
 struct Block {
     void* p;
@@ -27,7 +30,7 @@ struct Block {
     hipStream_t s;
 };
 std::mutex g_mu;
-std::multimap<size_t, Block> g_free;
+std::multimap<std::pair<hipStream_t, size_t>, Block> g_free;
 std::map<void*, size_t> g_cls;
 
 size_t size_class(size_t b)
@@ -43,11 +46,10 @@ void* dev_alloc(size_t bytes, hipStream_t s)
     size_t c = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_free.find(c);
+        auto it = g_free.find({s, c});
         if (it != g_free.end()) {
             Block b = it->second;
             g_free.erase(it);
-            if (b.s != s) FMM_HIP(hipStreamSynchronize(b.s));
             return b.p;
         }
     }
@@ -82,7 +84,7 @@ void dev_free(void* p, hipStream_t s)
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cls.find(p);
     if (it == g_cls.end()) return;
-    g_free.insert({it->second, Block{p, it->second, s}});
+    g_free.insert({{s, it->second}, Block{p, it->second, s}});
 }
 
 // ------------------------------------------------------ pinned flag words
