@@ -10,6 +10,7 @@ Functions (each follows the paper passage named in the C source):
   direct_points(z, m, y)               eq. (2.2), separate evaluation points
   direct_deriv_points(z, m, y)         the y-derivative of (2.2)'s field
   direct_smoothed(z, m, delta, targets=None)   O1 with the smoother of Sec. 5.1
+  direct_log_points(z, q, y)           the logarithmic potential, real strengths
   direct_compensated(z, m)             O1 with Neumaier summation
   grad_direct(z, m, g)                 O3, gradient through the direct sum
   tree(z, L)                           balanced median-split pyramid, Sec. 2.2
@@ -39,6 +40,7 @@ def lib():
         L.oracle_direct_points.argtypes = [i64, dp, dp, i64, dp, dp]
         L.oracle_direct_deriv_points.argtypes = [i64, dp, dp, i64, dp, dp]
         L.oracle_direct_smoothed.argtypes = [i64, dp, dp, C.c_double, i64, ip, dp]
+        L.oracle_direct_log_points.argtypes = [i64, dp, dp, i64, dp, dp]
         L.oracle_direct_compensated.argtypes = [i64, dp, dp, dp]
         L.oracle_grad_direct.argtypes = [i64, dp, dp, dp, dp, dp]
         L.oracle_p2m.argtypes = [dp, i64, dp, dp, C.c_int, dp]
@@ -106,6 +108,16 @@ def direct_smoothed(z, m, delta, targets=None):
         t = np.ascontiguousarray(targets, dtype=np.int64)
         out = np.zeros(t.size, np.complex128)
         lib().oracle_direct_smoothed(n, _dp(z), _dp(m), float(delta), t.size, _ip(t), _dp(out))
+    return out
+
+
+def direct_log_points(z, q, y):
+    """u_i = sum over z_j != y_i of q_j log|y_i - z_j| (real q, real u)."""
+    z, y = _c(z), _c(y)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == (z.size,)
+    out = np.zeros(y.size, np.float64)
+    lib().oracle_direct_log_points(z.size, _dp(z), _dp(q), y.size, _dp(y), _dp(out))
     return out
 
 

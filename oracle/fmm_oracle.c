@@ -130,6 +130,28 @@ void oracle_direct_smoothed(int64_t n, const double* z, const double* m, double 
     }
 }
 
+/* The logarithmic potential, the second kernel of the paper (end of Sec. 3;
+ * the multipole expansion with its a_0 log term sits at the start of Sec. 2):
+ * for real strengths q the real part of sum_j q_j log(y_i - z_j), i.e.
+ *     u_i = sum over j with z_j != y_i of q_j log|y_i - z_j|,
+ * single-valued (the imaginary part would depend on the branch of the
+ * logarithm).  Sources at the evaluation point are left out, as in (2.1). */
+void oracle_direct_log_points(int64_t n, const double* z, const double* q,
+                              int64_t ny, const double* y, double* u)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < ny; ++t) {
+        cplx yi = ld(y, t);
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            cplx w = c_sub(yi, ld(z, j));
+            if (w.re == 0.0 && w.im == 0.0) continue;
+            acc += q[j] * log(hypot(w.re, w.im));
+        }
+        u[t] = acc;
+    }
+}
+
 /* Derivative of the field of eq. (2.2) at separate points y: the y-derivative
  * of m_j / (y - x_j) is -m_j / (y - x_j)^2; sources at the evaluation point
  * are left out, as in the potential.  Evaluating at the sources themselves

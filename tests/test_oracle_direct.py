@@ -184,3 +184,51 @@ def test_p_rule_reproduces_table_4_1(orc):
     assert len(rows) == 15
     for tol, theta, p in rows:
         assert orc.p_from_tol(float(tol), float(theta)) == int(p), (tol, theta)
+
+
+# ---- the logarithmic potential (the paper's second kernel)
+
+def test_log_roots_of_unity_closed_form(orc):
+    # N unit charges at z_k = c + u_k, u_k^N = R^N: prod_{j!=k} (z_k - z_j) =
+    # P'(z_k) = N u_k^(N-1), so sum_{j!=k} log|z_k - z_j| = log N + (N-1) log R.
+    for n, c, R in [(2, 0.0, 1.0), (7, 0.5 + 0.5j, 0.3), (301, 2.0 + 1.0j, 3.0)]:
+        z = W.roots_of_unity(n, c, R, phase=0.2)
+        u = orc.direct_log_points(z, np.ones(n), z)
+        ref = np.log(n) + (n - 1) * np.log(R)
+        assert np.max(np.abs(u - ref)) < 1e-11 * max(1.0, abs(ref))
+
+
+def test_log_two_points_and_exclusion(orc):
+    z = np.array([0.1 + 0.2j, 0.7 - 0.3j, 0.1 + 0.2j])      # point 2 coincides with point 0
+    q = np.array([1.5, -0.25, 2.0])
+    u = orc.direct_log_points(z, q, z)
+    d = abs(z[0] - z[1])
+    np.testing.assert_allclose(u, [q[1] * np.log(d), (q[0] + q[2]) * np.log(d), q[1] * np.log(d)], rtol=1e-15)
+
+
+def test_log_scaling_and_translation(orc):
+    # scaling every position by s adds (sum_{j != i} q_j) log s; a shift changes nothing
+    rng = np.random.default_rng(3)
+    z = rng.random(300) + 1j * rng.random(300)
+    q = rng.standard_normal(300)
+    u = orc.direct_log_points(z, q, z)
+    s = 7.5
+    us = orc.direct_log_points(s * z, q, s * z)
+    np.testing.assert_allclose(us - u, (q.sum() - q) * np.log(s), rtol=1e-12, atol=1e-12)
+    ut = orc.direct_log_points(z + (3 - 2j), q, z + (3 - 2j))
+    np.testing.assert_allclose(ut, u, rtol=1e-12, atol=1e-12)
+
+
+def test_log_gradient_is_the_harmonic_field(orc):
+    # d/dx log|y - z| = Re 1/(y - z), d/dy log|y - z| = -Im 1/(y - z): central
+    # differences of the log oracle against the harmonic oracle (real strengths)
+    rng = np.random.default_rng(4)
+    z = rng.random(200) + 1j * rng.random(200)
+    q = rng.standard_normal(200)
+    y = 1.5 + rng.random(20) + 1j * rng.random(20)
+    f = orc.direct_points(z, q + 0j, y)
+    h = 1e-5
+    gx = (orc.direct_log_points(z, q, y + h) - orc.direct_log_points(z, q, y - h)) / (2 * h)
+    gy = (orc.direct_log_points(z, q, y + 1j * h) - orc.direct_log_points(z, q, y - 1j * h)) / (2 * h)
+    np.testing.assert_allclose(gx, f.real, rtol=1e-7, atol=1e-7)
+    np.testing.assert_allclose(gy, -f.imag, rtol=1e-7, atol=1e-7)
