@@ -224,6 +224,22 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
         out["field_n1e6_" + prec] = {"p": 13, "n_levels": 9, "evaluate_ms": te * 1e3, "field_ms": tf * 1e3,
                                      "ratio": tf / te}
         log("field N=1e6 (%s, p=13): evaluate %.3f ms, evaluate_field %.3f ms" % (prec, te * 1e3, tf * 1e3))
+    # the logarithmic potential (fmm_evaluate_log, real strengths) on the same tree
+    q = np.random.default_rng(1).standard_normal(z.size)
+    qd = torch.from_numpy(q).to(dev)
+    ud = torch.empty_like(qd)
+    for prec in ("mixed", "fp64"):
+        pl = F.plan(tree, 13, 0.5, prec)
+        tl = _time(lambda: F.evaluate_log(pl, qd, ud), reps, torch)
+        rec = {"p": 13, "n_levels": 9, "log_ms": tl * 1e3, "mpoints_s": z.size / tl / 1e6}
+        if with_errors:
+            import oracle
+            sub = W.subsample(z.size, 2000, seed=3)
+            ref = oracle.direct_log_points(z, q, z[sub])
+            rec["e2"] = float(np.linalg.norm(ud.cpu().numpy()[sub] - ref) / np.linalg.norm(ref))
+        out["log_n1e6_" + prec] = rec
+        log("log kernel N=1e6 (%s, p=13): evaluate_log %.3f ms%s" % (prec, tl * 1e3,
+            ", e2 %.2e" % rec["e2"] if "e2" in rec else ""))
     del tree, phi, dphi
     z, m, _ = W.uniform(200000, seed=0)
     zd = torch.from_numpy(z).to(dev)

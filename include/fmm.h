@@ -201,6 +201,25 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
 int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi, void* stream);
 
 /*
+ * fmm_evaluate_log -- the logarithmic potential, the second kernel of the
+ * paper (Sec. 3.3), for real strengths:
+ *     u_i = sum_{z_j != z_i} q_j log|z_i - z_j|
+ * (the real part of sum_j q_j log(z_i - z_j); the imaginary part depends on
+ * the branch of the logarithm and is not formed).  The far field uses the
+ * multipole expansion a_0 log(z - z0) + sum_k a_k / (z - z0)^k of Sec. 2.1:
+ * the harmonic expansions of the plan (the derivative of the potential) plus
+ * a constant term per box, formed by M2L over the weak list and handed down
+ * by L2L; the near field is summed directly over the strong lists.
+ *   q  DEVICE, real float64 [N] strengths, input order.
+ *   u  DEVICE, real float64 [N] output, input order (overwritten).
+ * Separate evaluation points: as for fmm_evaluate_field, with zero strength.
+ * Errors as for fmm_evaluate; FMM_EINVAL for a plan with a smoothed near
+ * field.  Runs eagerly on `stream` also for a plan with FMM_FLAG_GRAPH; the
+ * plan's state for fmm_evaluate_adjoint is cleared.
+ */
+int fmm_evaluate_log(fmm_plan_t pl, const double* q, double* u, void* stream);
+
+/*
  * fmm_evaluate_adjoint -- gradients of a real loss L through phi = FMM(m; z)
  * with the tree geometry frozen.  Convention: for a complex w,
  * G_w = dL/dRe(w) + i dL/dIm(w).

@@ -96,6 +96,7 @@ def lib():
         "fmm_tuner_best": (C.c_int, [vp, C.POINTER(_TunerParams), dp, dp]),
         "fmm_tuner_destroy": (None, [vp]),
         "fmm_evaluate_field": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fmm_evaluate_log": (C.c_int, [vp, vp, vp, vp]),
         "fmm_p_from_tol": (C.c_int, [C.c_double, C.c_double]),
         "fmm_choose_order": (C.c_int, [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, vp,
                                        C.POINTER(C.c_int), dp]),
@@ -262,6 +263,19 @@ def evaluate_field(pl, m, phi=None, dphi=None, stream=None):
     _check(lib().fmm_evaluate_field(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(phi.data_ptr()),
                                     C.c_void_p(dphi.data_ptr()), _stream(stream)))
     return phi, dphi
+
+
+def evaluate_log(pl, q, out=None, stream=None):
+    """The logarithmic potential u_i = sum over z_j != z_i of q_j log|z_i - z_j|
+    for real strengths q (float64 device tensor, input order); returns u."""
+    import torch
+    if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == torch.float64):
+        raise TypeError("q must be a float64 tensor on the HIP device")
+    q = q.contiguous()
+    if out is None:
+        out = torch.empty_like(q)
+    _check(lib().fmm_evaluate_log(pl._h, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
 
 
 def evaluate_at(z, m, y, p=16, theta=0.5, n_levels=None, precision="fp64", field=False, stream=None):

@@ -512,6 +512,20 @@ int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi
     });
 }
 
+int fmm_evaluate_log(fmm_plan_t pl, const double* q, double* u, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && q && u, "NULL argument");
+        FMM_REQUIRE(pl->pl.tune.smooth_delta == 0.0, "a smoothed near field has no logarithmic form");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        Plan& P = pl->pl;
+        plan_finalize(P);
+        plan_join(P, s);
+        evaluate_log_device(P, q, u, s);
+    });
+}
+
 int fmm_evaluate_adjoint(fmm_plan_t pl, const double* m, const double* g_phi, double* g_m, double* g_z,
                          void* stream)
 {

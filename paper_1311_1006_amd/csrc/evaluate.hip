@@ -42,7 +42,8 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2);
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
+                bool log_kernel);
 
 struct P2PItemH {
     int32_t leaf, t0, tn, pad;
@@ -205,7 +206,7 @@ struct PhaseTimer;
 
 template <class T>
 static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm,
-                         const long long* guard);
+                         const long long* guard, bool all_l2l = false);
 
 struct PhaseTimer {
     static constexpr int kEvents = 6;
@@ -237,7 +238,7 @@ struct PhaseTimer {
 
 template <class T>
 static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hipStream_t s, PhaseTimer& tm,
-                         const long long* guard)
+                         const long long* guard, bool all_l2l)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -248,8 +249,8 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     tm.mark();
     // parents at level l (non-leaf) hand their expansion to level l+1; the
     // hand-over into the leaves is done by L2P when every problem has the
-    // same depth
-    const int lend = sc.max_levels - (ex.leaf_l2l_in_l2p ? 2 : 1);
+    // same depth (all_l2l: every level here, the leaves' expansions whole)
+    const int lend = sc.max_levels - (ex.leaf_l2l_in_l2p && !all_l2l ? 2 : 1);
     for (int l = 1; l < lend; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, loc, s);
@@ -259,7 +260,7 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
 void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
                     hipStream_t s);
 
-static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* guard)
+static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* guard, bool log_kernel = false)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -275,7 +276,8 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* gua
                    pl.nsrc.p, b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
                    mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard,
-                   pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0);
+                   pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0,
+                   log_kernel);
     }
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }
@@ -319,6 +321,51 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
         run_m2m<double>(pl, ex, pl.mpole.p, s);
     }
     pl.upward_done = true;
+}
+
+void launch_real_to_complex(int64_t n, const double* q, double* m, hipStream_t s);
+template <class T>
+void launch_log_constants(int nbox, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
+                          const double* geom, const void* mp, const void* loc, int p, const int32_t* level_boxes,
+                          const std::vector<int64_t>& level_off, int nlevels, const int32_t* parent, double* c0,
+                          hipStream_t s);
+template <class T>
+void launch_l2p_log(const int32_t* leaves, int nleaf, const int32_t* bstart, const int32_t* bcount,
+                    const double* geom, const double* X, const double* Y, const void* loc, int p, const double* c0,
+                    const double* near, const int32_t* perm, double* u, hipStream_t s);
+
+// The logarithmic potential (see log.hip): the harmonic upward pass and far
+// field of the strengths q as complex numbers, the near field with the
+// logarithmic kernel, the constant terms of the local expansions, and L2P of
+// the integrated series.  One stream, phases in order.
+void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    PlanExtra& ex = *extra(pl);
+    const bool mixed = pl.precision == FMM_MIXED;
+    pl.mlog.alloc(2 * sc.n, s);
+    pl.c0.alloc(sc.nbox, s);
+    launch_real_to_complex(sc.n, q, pl.mlog.p, s);
+    PhaseTimer tm(false, s);
+    if (mixed) {
+        run_p2m<float>(pl, ex, pl.mlog.p, s);
+        run_m2m<float>(pl, ex, pl.mpole.p, s);
+        run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
+    } else {
+        run_p2m<double>(pl, ex, pl.mlog.p, s);
+        run_m2m<double>(pl, ex, pl.mpole.p, s);
+        run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
+    }
+    run_p2p(pl, ex, s, nullptr, true);
+    auto constants = mixed ? launch_log_constants<float> : launch_log_constants<double>;
+    constants((int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, pl.mpole.p, pl.local.p, pl.p,
+              ex.d_level_boxes.p, ex.level_boxes_off, sc.max_levels, sc.d_box_parent.p, pl.c0.p, s);
+    auto l2p = mixed ? launch_l2p_log<float> : launch_l2p_log<double>;
+    l2p(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.local.p, pl.p,
+        pl.c0.p, pl.near.p, t.perm.p, u, s);
+    // the harmonic state of the plan now holds these strengths: no adjoint of it
+    pl.have_forward = false;
 }
 
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far, hipStream_t s,

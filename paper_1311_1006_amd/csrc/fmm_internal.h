@@ -213,6 +213,8 @@ struct Plan {
     DBuf<float> srclo;             // [N][2] xl yl
     DBuf<double> mtree;            // [N][2] strengths in tree order (FP64)
     DBuf<double> near;             // [N][2] P2P result, tree order
+    DBuf<double> mlog;             // [N][2] real strengths of the logarithmic kernel as complex numbers
+    DBuf<double> c0;               // [nbox] constant term of the logarithmic local expansions
     // near-field work split into source chunks (see balance.hip)
     DBuf<int32_t> nsrc;            // [nbox] sources in the strong list of every leaf
     struct Balance {
@@ -273,6 +275,8 @@ void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
+// the logarithmic potential u (real, input order) of real strengths q
+void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s);
 // the gather of an evaluation (strengths into tree order, P2P source records)
 // done by the P2M kernel as it reads every point of its leaves
 struct GatherOut {

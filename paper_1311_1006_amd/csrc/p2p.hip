@@ -101,6 +101,33 @@ __device__ __forceinline__ void pair32s(float xh, float yh, float xl, float yl, 
     ai = fmaf(b, y, ai);
 }
 
+// The logarithmic kernel: log|z_i - z_j| times the real and the imaginary
+// part of the strength (real strengths leave the second sum 0).  Coincident
+// positions are left out, as in the other kernels; FLT_MIN (DBL_MIN) in r^2
+// only keeps the logarithm finite there.
+__device__ __forceinline__ void pair32l(float xh, float yh, float xl, float yl, const Src32& s, float& ar, float& ai)
+{
+    const float dx = (xh - s.xh) + (xl - s.xl);
+    const float dy = (yh - s.yh) + (yl - s.yl);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
+    const float lg = (dx != 0.f || dy != 0.f) ? 0.5f * __logf(r2) : 0.f;
+    ar = fmaf(s.mr, lg, ar);
+    ai = fmaf(s.mi, lg, ai);
+}
+__device__ __forceinline__ void pair64l(double xi, double yi, const Src64& s, double& ar, double& ai)
+{
+    const double dx = xi - s.x, dy = yi - s.y;
+    const double r2 = fma(dx, dx, fma(dy, dy, DBL_MIN));
+    const double lg = (dx != 0.0 || dy != 0.0) ? 0.5 * log(r2) : 0.0;
+    ar = fma(s.mr, lg, ar);
+    ai = fma(s.mi, lg, ai);
+}
+
+// near-field kernels: KERN 0 the plain harmonic kernel, 1 with the Gaussian
+// smoother, 2 the logarithmic kernel (each its own instantiation, so the
+// plain kernel keeps its registers)
+constexpr int kKernPlain = 0, kKernSmooth = 1, kKernLog = 2;
+
 // The value x of a partner lane whose bit M differs from this lane's and
 // whose other bits above M agree: lane ^ 1 and lane ^ 2 (quad
 // permutations), lane ^ 7 and lane ^ 15 (half-row and row mirrors) by DPP,
@@ -181,7 +208,7 @@ __device__ __forceinline__ int butterfly_index(int lane)
     return idx;
 }
 
-template <int TG, int SUB, bool SMOOTH>
+template <int TG, int SUB, int KERN>
 __global__ void __launch_bounds__(256)
 k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
@@ -232,11 +259,17 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         if (lane < npad - ns) lds[ns + lane] = Src64{0.0, 0.0, 0.0, 0.0};
         wave_sync();
         const Src64* sp = lds + sl;
-        if constexpr (SMOOTH) {     // the smoothed near field
+        if constexpr (KERN == kKernSmooth) {     // the smoothed near field
             for (int c = 0; c < npad; c += NL, sp += NL) {
                 const Src64 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair64s(xi[t], yi[t], s, id2, ar[t], ai[t]);
+            }
+        } else if constexpr (KERN == kKernLog) {
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src64 s = *sp;
+#pragma unroll
+                for (int t = 0; t < TG; ++t) pair64l(xi[t], yi[t], s, ar[t], ai[t]);
             }
         } else {
             for (int c = 0; c < npad; c += NL, sp += NL) {
@@ -262,7 +295,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     }
 }
 
-template <int TG, int SUB, bool SMOOTH>
+template <int TG, int SUB, int KERN>
 __global__ void __launch_bounds__(256)
 k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
@@ -316,11 +349,17 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         if (lane < npad - ns) lds[ns + lane] = Src32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         wave_sync();
         const Src32* sp = lds + sl;
-        if constexpr (SMOOTH) {     // the smoothed near field
+        if constexpr (KERN == kKernSmooth) {     // the smoothed near field
             for (int c = 0; c < npad; c += NL, sp += NL) {
                 const Src32 s = *sp;
 #pragma unroll
                 for (int t = 0; t < TG; ++t) pair32s(xh[t], yh[t], xl[t], yl[t], s, id2, ar[t], ai[t]);
+            }
+        } else if constexpr (KERN == kKernLog) {
+            for (int c = 0; c < npad; c += NL, sp += NL) {
+                const Src32 s = *sp;
+#pragma unroll
+                for (int t = 0; t < TG; ++t) pair32l(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
             }
         } else {
             for (int c = 0; c < npad; c += NL, sp += NL) {
@@ -345,34 +384,37 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     }
 }
 
+template <int TG, int SUB, int KERN>
+static void launch_kern(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx,
+                        const int32_t* icnt, const int32_t* ioff, const int32_t* nsrc, double* partial,
+                        const int32_t* bstart, const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt,
+                        const int32_t* s_ids, const void* src, const void* lo, double* out, hipStream_t s,
+                        const long long* guard, double id2)
+{
+    const int grid = (nx + 3) / 4;
+    if (mixed)
+        k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                   bcount, s_beg, s_cnt, s_ids, (const float4*)src,
+                                                   (const float2*)lo, (double2*)out, guard, (float)id2);
+    else
+        k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+                                                   bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
+                                                   guard, id2);
+}
+
 template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
                        const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                        const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
-                       double id2)
+                       double id2, bool log_kernel)
 {
-    int grid = (nx + 3) / 4;
-    // the smoother is a separate instantiation: the plain kernel keeps its registers
-    if (mixed) {
-        if (id2 > 0.0)
-            k_p2p32<TG, SUB, true><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
-                                                       bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                                       (const float2*)lo, (double2*)out, guard, (float)id2);
-        else
-            k_p2p32<TG, SUB, false><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
-                                                        bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                                        (const float2*)lo, (double2*)out, guard, 0.f);
-    } else {
-        if (id2 > 0.0)
-            k_p2p64<TG, SUB, true><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
-                                                       bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
-                                                       guard, id2);
-        else
-            k_p2p64<TG, SUB, false><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
-                                                        bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
-                                                        guard, 0.0);
-    }
+#define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
+             lo, out, s, guard, id2
+    if (log_kernel) launch_kern<TG, SUB, kKernLog>(ARGS);
+    else if (id2 > 0.0) launch_kern<TG, SUB, kKernSmooth>(ARGS);
+    else launch_kern<TG, SUB, kKernPlain>(ARGS);
+#undef ARGS
 }
 
 // one launch per (targets per subgroup, subgroups) class over its chunks
@@ -382,14 +424,15 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2)
+                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
+                bool log_kernel)
 {
     if (nx == 0) return;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s, guard, id2);                                                    \
+                              s_ids, src, lo, out, s, guard, id2, log_kernel);                                        \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }
