@@ -336,31 +336,41 @@ void launch_l2p_log(const int32_t* leaves, int nleaf, const int32_t* bstart, con
 
 // The logarithmic potential (see log.hip): the harmonic upward pass and far
 // field of the strengths q as complex numbers, the near field with the
-// logarithmic kernel, the constant terms of the local expansions, and L2P of
-// the integrated series.  One stream, phases in order.
+// logarithmic kernel (on the second stream, beside the far field, from the
+// source records P2M writes), the constant terms of the local expansions,
+// and L2P of the integrated series after the join.
 void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     PlanExtra& ex = *extra(pl);
     const bool mixed = pl.precision == FMM_MIXED;
+    if (!pl.nstream) {
+        pl.nstream = side_stream(t.device, kNearStream);
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+    }
     pl.mlog.alloc(2 * sc.n, s);
     pl.c0.alloc(sc.nbox, s);
     launch_real_to_complex(sc.n, q, pl.mlog.p, s);
     PhaseTimer tm(false, s);
+    if (mixed) run_p2m<float>(pl, ex, pl.mlog.p, s);
+    else run_p2m<double>(pl, ex, pl.mlog.p, s);
+    FMM_HIP(hipEventRecord(pl.ev_fork, s));
+    FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
+    run_p2p(pl, ex, pl.nstream, nullptr, true);
+    FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
     if (mixed) {
-        run_p2m<float>(pl, ex, pl.mlog.p, s);
         run_m2m<float>(pl, ex, pl.mpole.p, s);
         run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
     } else {
-        run_p2m<double>(pl, ex, pl.mlog.p, s);
         run_m2m<double>(pl, ex, pl.mpole.p, s);
         run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
     }
-    run_p2p(pl, ex, s, nullptr, true);
     auto constants = mixed ? launch_log_constants<float> : launch_log_constants<double>;
     constants((int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, pl.mpole.p, pl.local.p, pl.p,
               ex.d_level_boxes.p, ex.level_boxes_off, sc.max_levels, sc.d_box_parent.p, pl.c0.p, s);
+    FMM_HIP(hipStreamWaitEvent(s, pl.ev_join, 0));
     auto l2p = mixed ? launch_l2p_log<float> : launch_l2p_log<double>;
     l2p(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.local.p, pl.p,
         pl.c0.p, pl.near.p, t.perm.p, u, s);

@@ -29,18 +29,21 @@ __global__ void k_real_to_complex(int64_t n, const double* __restrict__ q, doubl
     if (i < n) m[i] = make_double2(q[i], 0.0);
 }
 
-// c0 of every box from its weak list (one thread per box; zero without one)
+// c0 of every box from its weak list (zero without one): one wavefront per
+// box, lane e takes pairs e, e + 64, ...; the lanes' sums are added by a
+// butterfly (a fixed order, so the result is reproducible)
 template <class T>
-__global__ void k_m2l_log0(int nbox, const int32_t* __restrict__ w_beg, const int32_t* __restrict__ w_cnt,
-                           const int32_t* __restrict__ w_ids, const double* __restrict__ geom,
-                           const T* __restrict__ mp, int p, double* __restrict__ c0)
+__global__ void __launch_bounds__(256)
+k_m2l_log0(int nbox, const int32_t* __restrict__ w_beg, const int32_t* __restrict__ w_cnt,
+           const int32_t* __restrict__ w_ids, const double* __restrict__ geom, const T* __restrict__ mp, int p,
+           double* __restrict__ c0)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (g >= nbox) return;   // uniform per wavefront
     const double cx = geom[4 * (int64_t)g], cy = geom[4 * (int64_t)g + 1];
     const int b = w_beg[g], n = w_cnt[g];
     double acc = 0.0;
-    for (int e = 0; e < n; ++e) {
+    for (int e = lane; e < n; e += 64) {
         const int S = w_ids[b + e];
         const double dx = cx - geom[4 * (int64_t)S], dy = cy - geom[4 * (int64_t)S + 1];
         const double rs = geom[4 * (int64_t)S + 3];
@@ -55,7 +58,9 @@ __global__ void k_m2l_log0(int nbox, const int32_t* __restrict__ w_beg, const in
             pw = cmul(pw, u);
         }
     }
-    c0[g] = acc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) c0[g] = acc;
 }
 
 // c0 of the boxes of one level += Re F_parent(centre): the parent's constant
@@ -135,8 +140,7 @@ void launch_log_constants(int nbox, const int32_t* w_beg, const int32_t* w_cnt, 
                           const int32_t* parent, double* c0, hipStream_t s)
 {
     if (nbox == 0) return;
-    k_m2l_log0<T><<<(unsigned)((nbox + 255) / 256), 256, 0, s>>>(nbox, w_beg, w_cnt, w_ids, geom, (const T*)mp, p,
-                                                                 c0);
+    k_m2l_log0<T><<<(unsigned)((nbox + 3) / 4), 256, 0, s>>>(nbox, w_beg, w_cnt, w_ids, geom, (const T*)mp, p, c0);
     check_launch("log m2l constants");
     for (int l = 1; l < nlevels; ++l) {
         const int n = (int)(level_off[l + 1] - level_off[l]);
