@@ -944,7 +944,8 @@ __device__ void tile_median(const Cand* __restrict__ cs, int n, int rank, const 
 // is lower if (coordinate, index) < splitter; its rank among the lower
 // (upper) elements of the tile comes from per-wave ballots of every row,
 // combined with one barrier.  The splitter and the tile's output offset come
-// from tile_median, or from k_pick for a segment whose class overflowed.
+// from tile_median, or from the exact selection (pick_exact, run by the last
+// collect tile) for a segment whose class overflowed.
 __global__ void __launch_bounds__(kTileThreads)
 k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
