@@ -592,9 +592,11 @@ __device__ __forceinline__ int sub_of(const SubBucketer& s, double c)
 }
 
 // the first-level bucket of a segment's median (its rank inside the bucket
-// and the bucket's population), found by hist2 and read by collect
+// and the bucket's population) and the segment's bucketer, found by hist2
+// and read by collect (which then needs no bounding box of its own)
 struct Level1 {
-    int32_t b1, r1, c1, pad;
+    int32_t b1, r1, c1, axis;
+    double lo, scale;
 };
 
 __global__ void __launch_bounds__(kTileThreads)
@@ -619,7 +621,8 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
     int b1 = find_bucket_loc<1>(loc, t.seg_count / 2, &r1, &c1, sh);
     if (t.rank == 0 && threadIdx.x == 0) {
         Level1 v;
-        v.b1 = b1; v.r1 = r1; v.c1 = c1; v.pad = 0;
+        v.b1 = b1; v.r1 = r1; v.c1 = c1; v.axis = bk.axis;
+        v.lo = bk.lo; v.scale = bk.scale;
         lvl1[t.seg] = v;
     }
     if (c1 <= kSubThreshold) return;   // uniform per block
@@ -725,13 +728,15 @@ __device__ void exact_select(const double* C, const int32_t* I, int start, int c
 }
 
 // the candidate class (one or two histogram levels) of a segment's median,
-// from the first-level bucket that hist2 recorded
-__device__ __forceinline__ ClassRule median_class(const uint64_t* keys, const Level1* lvl1, const uint32_t* hist2,
-                                                  int seg, int range, int* rank, int* ccount, int* sh)
+// from the first-level bucket and the bucketer that hist2 recorded
+__device__ __forceinline__ ClassRule median_class(const Level1* lvl1, const uint32_t* hist2, int seg, int* rank,
+                                                  int* ccount, int* sh)
 {
     ClassRule rule;
-    rule.bk = make_bucketer(keys + kKeyWords * (int64_t)seg, keys + kKeyWords * (int64_t)range);
     const Level1 L1 = lvl1[seg];
+    rule.bk.axis = L1.axis;
+    rule.bk.lo = L1.lo;
+    rule.bk.scale = L1.scale;
     const int r1 = L1.r1, c1 = L1.c1;
     rule.b1 = L1.b1;
     rule.b2 = -1;
@@ -788,15 +793,14 @@ __device__ void pick_exact(int seg, const SegInfo& sg, const TileInfo* __restric
 __global__ void __launch_bounds__(kTileThreads)
 k_collect(const TileInfo* __restrict__ tiles, const TileInfo* __restrict__ all_tiles, const SegInfo* __restrict__ segs,
           const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
-          const uint64_t* __restrict__ keys, const Level1* __restrict__ lvl1,
-          const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt, uint32_t* tile_below,
-          uint32_t* seg_done, ClassInfo* cinfo, uint32_t* lo_base, Splitter* split)
+          const Level1* __restrict__ lvl1, const uint32_t* __restrict__ hist2, Cand* cand, uint32_t* cand_cnt,
+          uint32_t* tile_below, uint32_t* seg_done, ClassInfo* cinfo, uint32_t* lo_base, Splitter* split)
 {
     __shared__ int sh[kTileThreads / 64];
     TileInfo t = tiles[blockIdx.x];
     constexpr int R = kTile / kTileThreads;
     int rank, ccount;
-    ClassRule rule = median_class(keys, lvl1, hist2, t.seg, t.range, &rank, &ccount, sh);
+    ClassRule rule = median_class(lvl1, hist2, t.seg, &rank, &ccount, sh);
     const bool overflow = ccount > kCandCap;
     if (t.rank == 0 && threadIdx.x == 0) {
         ClassInfo ci;
@@ -1446,9 +1450,8 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
         // later stages' first-level histograms come from the previous partition
         if (st == 0) k_hist1<<<ntl, kTileThreads, 0, s>>>(tl, Xb[a], Yb[a], keys.p, W + o_h1);
         k_hist2<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], keys.p, W + o_h1, W + o_h2, lvl1.p);
-        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_tiles.p, sc.d_segs.p, Xb[a], Yb[a], Ib[a], keys.p, lvl1.p,
-                                              W + o_h2, cand.p, W + o_cc, W + o_tb, W + o_sd, cinfo.p, W + o_lb,
-                                              split.p);
+        k_collect<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_tiles.p, sc.d_segs.p, Xb[a], Yb[a], Ib[a], lvl1.p, W + o_h2,
+                                              cand.p, W + o_cc, W + o_tb, W + o_sd, cinfo.p, W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
                                                 Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb,
                                                 W + o_h1);
