@@ -368,10 +368,13 @@ __device__ __forceinline__ void block_read_keys2(const uint64_t* k0, const uint6
 // segment's own bounding box (the longer side), the bucket range from the
 // bounding box of segment `range` along that axis (the parent, whose
 // partition histograms the segment before its own box is complete).
-__device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys, const uint64_t* range_keys)
+__device__ __forceinline__ Bucketer make_bucketer(const uint64_t* keys, const uint64_t* range_keys,
+                                                  double* own_bb = nullptr)
 {
     double bb[4], rb[4];
     block_read_keys2(keys, range_keys, bb, rb);
+    if (own_bb)
+        for (int i = 0; i < 4; ++i) own_bb[i] = bb[i];
     const double w = (bb[1] - bb[0]), h = (bb[3] - bb[2]);
     return axis_bucketer(rb, (w >= h) ? 0 : 1);
 }
@@ -597,6 +600,7 @@ __device__ __forceinline__ int sub_of(const SubBucketer& s, double c)
 struct Level1 {
     int32_t b1, r1, c1, axis;
     double lo, scale;
+    double bb[4];     // the segment's bounding box, for its partition
 };
 
 __global__ void __launch_bounds__(kTileThreads)
@@ -615,7 +619,8 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
         hx += (int)hist1_at(hist1, t.seg, 0, c)[threadIdx.x];
         hy += (int)hist1_at(hist1, t.seg, 1, c)[threadIdx.x];
     }
-    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg, keys + kKeyWords * (int64_t)t.range);
+    double bb[4];
+    Bucketer bk = make_bucketer(keys + kKeyWords * (int64_t)t.seg, keys + kKeyWords * (int64_t)t.range, bb);
     int r1, c1;
     const int loc[1] = {bk.axis ? hy : hx};
     int b1 = find_bucket_loc<1>(loc, t.seg_count / 2, &r1, &c1, sh);
@@ -623,6 +628,7 @@ k_hist2(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs,
         Level1 v;
         v.b1 = b1; v.r1 = r1; v.c1 = c1; v.axis = bk.axis;
         v.lo = bk.lo; v.scale = bk.scale;
+        for (int i = 0; i < 4; ++i) v.bb[i] = bb[i];
         lvl1[t.seg] = v;
     }
     if (c1 <= kSubThreshold) return;   // uniform per block
@@ -955,7 +961,8 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
             const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ I,
             double* X2, double* Y2, int32_t* I2, uint64_t* keys_next, const ClassInfo* __restrict__ cinfo,
             const Cand* __restrict__ cand, const uint32_t* __restrict__ tile_below,
-            const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base, uint32_t* hist1)
+            const Splitter* __restrict__ split, const uint32_t* __restrict__ lo_base, uint32_t* hist1,
+            const Level1* __restrict__ lvl1)
 {
     constexpr int R = kTile / kTileThreads;
     constexpr int NW = kTileThreads / 64;
@@ -980,8 +987,8 @@ k_partition(const TileInfo* __restrict__ tiles, const SegInfo* __restrict__ segs
     // axes over this segment's bounding box (its split axis is not known yet)
     Bucketer cb[2];
     if (hist_children) {
-        double bb[4];
-        block_read_keys(keys_next + kKeyWords * (int64_t)t.seg, bb);
+        double bb[4];   // this segment's bounding box, as hist2 read it
+        for (int i = 0; i < 4; ++i) bb[i] = lvl1[t.seg].bb[i];
         cb[0] = axis_bucketer(bb, 0);
         cb[1] = axis_bucketer(bb, 1);
         for (int i = threadIdx.x; i < 4 * kBuckets1; i += kTileThreads) chist[i] = 0u;
@@ -1454,7 +1461,7 @@ static void build_tree_select(Tree& t, const double* z, hipStream_t s)
                                               cand.p, W + o_cc, W + o_tb, W + o_sd, cinfo.p, W + o_lb, split.p);
         k_partition<<<ntl, kTileThreads, 0, s>>>(tl, sc.d_segs.p, Xb[a], Yb[a], Ib[a], Xb[a ^ 1], Yb[a ^ 1],
                                                 Ib[a ^ 1], keys.p, cinfo.p, cand.p, W + o_tb, split.p, W + o_lb,
-                                                W + o_h1);
+                                                W + o_h1, lvl1.p);
         check_launch("split stage");
     }
     if (!sc.lds.empty()) {
