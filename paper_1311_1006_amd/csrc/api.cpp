@@ -396,6 +396,8 @@ void fmm_plan_destroy(fmm_plan_t pl)
     // evaluation stream, so the plan's buffers are released in stream order
     if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
     if (P.ev_join) (void)hipEventDestroy(P.ev_join);
+    if (P.ev_top0) (void)hipEventDestroy(P.ev_top0);
+    if (P.ev_top1) (void)hipEventDestroy(P.ev_top1);
     release_list_flag(P);
     // list work still in flight (a plan never used) finishes before its
     // buffers go back to the pool

@@ -243,15 +243,47 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const Plan::Balance& b = pl.bal_m2l;
-    launch_m2l<T>(nullptr, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
-                  b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
-                  pl.tune.m2l_batch, guard);
-    tm.mark();
     // parents at level l (non-leaf) hand their expansion to level l+1; the
     // hand-over into the leaves is done by L2P when every problem has the
     // same depth (all_l2l: every level here, the leaves' expansions whole)
     const int lend = sc.max_levels - (ex.leaf_l2l_in_l2p && !all_l2l ? 2 : 1);
-    for (int l = 1; l < lend; ++l) {
+    // The top levels' chain (M2L of levels < cut, then the L2L steps among
+    // them) runs on a third stream beside the M2L of the deeper levels, which
+    // takes nearly all the work: every L2L step adds to a child's expansion
+    // after that child's M2L wrote it, and the children of those steps are
+    // all above the cut.  Lists split into chunks, and phase timing, keep the
+    // single launch.
+    const int cut = std::min(sc.max_levels - 3, 6);
+    const int ltop = std::min(cut - 2, lend - 1);      // last parent level of the side chain
+    int lstart = 1;
+    if (!tm.on && b.xitems.p == nullptr && b.total == sc.nbox && ltop >= 1) {
+        if (!pl.ev_top0) {
+            FMM_HIP(hipEventCreateWithFlags(&pl.ev_top0, hipEventDisableTiming));
+            FMM_HIP(hipEventCreateWithFlags(&pl.ev_top1, hipEventDisableTiming));
+        }
+        hipStream_t ts = side_stream(t.device, kTopStream);
+        const int na = (int)ex.level_boxes_off[cut];   // boxes of levels 0 .. cut-1, all problems
+        const int nb = (int)(ex.level_boxes_off[sc.max_levels] - na);
+        FMM_HIP(hipEventRecord(pl.ev_top0, s));
+        FMM_HIP(hipStreamWaitEvent(ts, pl.ev_top0, 0));
+        launch_m2l<T>(ex.d_level_boxes.p, na, nullptr, na, nullptr, nullptr, nullptr, false, pl.w_beg.p, pl.w_cnt.p,
+                      pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, ts, pl.tune.m2l_batch, guard);
+        for (int l = 1; l <= ltop; ++l) {
+            int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
+            launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, loc, ts);
+        }
+        FMM_HIP(hipEventRecord(pl.ev_top1, ts));
+        launch_m2l<T>(ex.d_level_boxes.p + na, nb, nullptr, nb, nullptr, nullptr, nullptr, false, pl.w_beg.p,
+                      pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s, pl.tune.m2l_batch, guard);
+        FMM_HIP(hipStreamWaitEvent(s, pl.ev_top1, 0));
+        lstart = ltop + 1;
+    } else {
+        launch_m2l<T>(nullptr, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
+                      b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s,
+                      pl.tune.m2l_batch, guard);
+    }
+    tm.mark();
+    for (int l = lstart; l < lend; ++l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_l2l<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, loc, s);
     }

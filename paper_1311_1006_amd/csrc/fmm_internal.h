@@ -248,6 +248,7 @@ struct Plan {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipStream_t nstream = nullptr;         // near-field stream of the device (shared, not owned)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_top0 = nullptr, ev_top1 = nullptr;   // the top levels' far field on a third stream
 };
 
 // ---------------------------------------------------------- launchers
@@ -263,7 +264,7 @@ volatile long long* flag_slot_ptr(int slot);
 void flag_slot_release(int slot);
 void evaluate_upward(Plan& pl, const double* m, hipStream_t s);
 double rel_err2_device(const double* a, const double* ref, int64_t n, hipStream_t s);
-constexpr int kNearStream = 0, kListStream = 1;
+constexpr int kNearStream = 0, kListStream = 1, kTopStream = 2;
 hipStream_t side_stream(int device, int which);
 void plan_join(Plan& pl, hipStream_t s);
 void plan_finalize(Plan& pl);
