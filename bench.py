@@ -273,7 +273,7 @@ def main():
                          "--levels value, then a 256 MiB device copy (counter calibration); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
