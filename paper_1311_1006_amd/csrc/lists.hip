@@ -257,7 +257,7 @@ k_traverse(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w
     constexpr bool FILL = MODE != 0;
     __shared__ int32_t front_all[4][2][kFrontCap];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + wv;
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // one box per wavefront: uniform
     if (i >= c.n) return;
     int32_t* fa = front_all[wv][0];
     int32_t* fb = front_all[wv][1];
@@ -401,7 +401,8 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
 {
     constexpr bool FILL = MODE != 0;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = (blockIdx.x * 4 + wv) * 4;
+    // one sibling group per wavefront: its values are uniform (scalar registers)
+    const int i = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + wv) * 4);
     if (i >= c.n) return;
     const int64_t g0 = c.boxes[i];                    // first of four siblings
     const int L = c.level[g0];
