@@ -576,7 +576,9 @@ __device__ int find_bucket(const uint32_t* hist, int k, int* rank_in, int* cnt_i
 }
 
 // a median bucket with more points than this is refined by a second histogram
-constexpr int kSubThreshold = 64;
+// (a second pass over the segment's coordinates costs less than ranking a
+// longer candidate list in every partition tile)
+constexpr int kSubThreshold = 16;
 
 struct SubBucketer {
     double lo, scale;
