@@ -29,21 +29,35 @@ __global__ void k_real_to_complex(int64_t n, const double* __restrict__ q, doubl
     if (i < n) m[i] = make_double2(q[i], 0.0);
 }
 
-// c0 of every box from its weak list (zero without one): one wavefront per
-// box, lane e takes pairs e, e + 64, ...; the lanes' sums are added by a
-// butterfly (a fixed order, so the result is reproducible)
+// 1/k for the series of the constant terms (a multiplication in place of an
+// FP64 division per term)
+struct InvK {
+    double v[kMaxP];
+};
+constexpr InvK make_inv_k()
+{
+    InvK t{};
+    for (int k = 1; k < kMaxP; ++k) t.v[k] = 1.0 / k;
+    return t;
+}
+__constant__ InvK kInvK = make_inv_k();
+
+// c0 of every box from its weak list (zero without one): 32 lanes per box (a
+// weak list holds at most 27 entries), lane e takes pairs e, e + 32, ...; the
+// lanes' sums are added by a butterfly (a fixed order, so the result is
+// reproducible)
 template <class T>
 __global__ void __launch_bounds__(256)
 k_m2l_log0(int nbox, const int32_t* __restrict__ w_beg, const int32_t* __restrict__ w_cnt,
            const int32_t* __restrict__ w_ids, const double* __restrict__ geom, const T* __restrict__ mp, int p,
            double* __restrict__ c0)
 {
-    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (g >= nbox) return;   // uniform per wavefront
-    const double cx = geom[4 * (int64_t)g], cy = geom[4 * (int64_t)g + 1];
-    const int b = w_beg[g], n = w_cnt[g];
+    const int g = blockIdx.x * 8 + (threadIdx.x >> 5), lane = threadIdx.x & 31;
+    const bool live = g < nbox;   // every lane stays for the butterfly
+    const int b = live ? w_beg[g] : 0, n = live ? w_cnt[g] : 0;
+    const double cx = live ? geom[4 * (int64_t)g] : 0.0, cy = live ? geom[4 * (int64_t)g + 1] : 0.0;
     double acc = 0.0;
-    for (int e = lane; e < n; e += 64) {
+    for (int e = lane; e < n; e += 32) {
         const int S = w_ids[b + e];
         const double dx = cx - geom[4 * (int64_t)S], dy = cy - geom[4 * (int64_t)S + 1];
         const double rs = geom[4 * (int64_t)S + 3];
@@ -54,13 +68,13 @@ k_m2l_log0(int nbox, const int32_t* __restrict__ w_beg, const int32_t* __restric
         double2 pw = u;
         for (int k = 1; k < p; ++k) {
             const double2 x = cmul(pw, make_double2((double)a[2 * k], (double)a[2 * k + 1]));
-            acc -= x.x / k;
+            acc -= x.x * kInvK.v[k];
             pw = cmul(pw, u);
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) c0[g] = acc;
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+    if (live && lane == 0) c0[g] = acc;
 }
 
 // c0 of the boxes of one level += Re F_parent(centre): the parent's constant
@@ -140,7 +154,7 @@ void launch_log_constants(int nbox, const int32_t* w_beg, const int32_t* w_cnt, 
                           const int32_t* parent, double* c0, hipStream_t s)
 {
     if (nbox == 0) return;
-    k_m2l_log0<T><<<(unsigned)((nbox + 3) / 4), 256, 0, s>>>(nbox, w_beg, w_cnt, w_ids, geom, (const T*)mp, p, c0);
+    k_m2l_log0<T><<<(unsigned)((nbox + 7) / 8), 256, 0, s>>>(nbox, w_beg, w_cnt, w_ids, geom, (const T*)mp, p, c0);
     check_launch("log m2l constants");
     for (int l = 1; l < nlevels; ++l) {
         const int n = (int)(level_off[l + 1] - level_off[l]);
