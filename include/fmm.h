@@ -148,7 +148,7 @@ void fmm_tree_destroy(fmm_tree_t t);
  * strong pair are strong unless the theta-criterion (2.3) R + theta r <=
  * theta d holds, then weak; children of weak pairs are decoupled; finest-level
  * strong pairs are summed directly).
- *   p          1 .. 32 expansion terms.
+ *   p          1 .. 64 expansion terms.
  *   theta      0 < theta < 1.
  *   precision  FMM_FP64 or FMM_MIXED.
  *   tune       HOST, optional (NULL = automatic).
@@ -340,8 +340,9 @@ int fmm_p_from_tol(double tol, double theta);
  * bounds the worst case; the error actually reached on a point set is often
  * several orders of p smaller, since the truncation error falls
  * geometrically in p at fixed theta (Sec. 2.3).  This call measures it:
- * the reference is the FP64 evaluation at p = 32 of the same tree and
- * strengths (its truncation error is below 1e-12 relative at theta <= 0.5);
+ * the reference is the FP64 evaluation of the same tree and strengths at
+ * p_ref = 32 when p_hi <= 24, else at p_ref = min(64, p_hi + 16) (at
+ * theta <= 0.5 the truncation error of p = 32 is below 1e-12 relative);
  * for p = p_lo .. p_hi the FP64 and the mixed-precision evaluations are
  * compared with it in the relative 2-norm over all targets,
  *     e(p) = ||phi_p - phi_ref||_2 / ||phi_ref||_2,
@@ -350,7 +351,7 @@ int fmm_p_from_tol(double tol, double theta);
  * [e_fp64(p), e_mixed(p)] at that p (at p_hi when none qualifies).
  *   t: tree (one problem or several; the norm runs over all points);
  *   m: device complex128 [N] strengths, as for fmm_evaluate;
- *   1 <= p_lo <= p_hi <= 31, 0 < theta < 1, 0 < tol < 1.
+ *   1 <= p_lo <= p_hi <= 48, 0 < theta < 1, 0 < tol < 1.
  * Device work on `stream`, temporary device memory of 2 N complex values
  * plus the plans' own; the call waits for the device.  Errors: FMM_EINVAL
  * (arguments, non-finite tree), FMM_ENOMEM, FMM_EDEVICE.

@@ -144,7 +144,7 @@ def p_from_tol(tol, theta):
 
 def choose_order(tree, m, theta=0.5, tol=5e-7, p_lo=8, p_hi=24, stream=None):
     """Smallest expansion order p in [p_lo, p_hi] whose FP64 and mixed results
-    agree with an FP64 evaluation at p = 32 to `tol` (relative 2-norm over all
+    agree with an FP64 evaluation at a higher order (p = 32 for p_hi <= 24) to `tol` (relative 2-norm over all
     targets); returns (p, (err_fp64, err_mixed)), p = -1 when none does."""
     m = _dev_complex(m, "m")
     p = C.c_int(-1)

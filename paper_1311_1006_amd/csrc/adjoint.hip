@@ -385,7 +385,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     adjoint_near(pl, pl.gtree.p, s);
     // combination and scatter: G lanes per leaf, P terms held per lane
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
-    const int P = pl.p <= 16 ? 16 : 32;
+    const int P = pl.p <= 16 ? 16 : (pl.p <= 32 ? 32 : 64);
     const unsigned gridf = (unsigned)((nleaf + 256 / G - 1) / (256 / G));
     auto fin = [&](auto tag, auto gtag, auto ptag) {
         using T = decltype(tag);
@@ -403,7 +403,8 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     };
     auto fin_p = [&](auto tag) {
         if (P == 16) fin_g(tag, std::integral_constant<int, 16>{});
-        else fin_g(tag, std::integral_constant<int, 32>{});
+        else if (P == 32) fin_g(tag, std::integral_constant<int, 32>{});
+        else fin_g(tag, std::integral_constant<int, 64>{});
     };
     if (mixed) fin_p(float{});
     else fin_p(double{});
@@ -473,7 +474,7 @@ void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStrea
     adjoint_near(pl, pl.mtree.p, s);
     const int nleaf = (int)sc.nleaf;
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
-    const int P = pl.p <= 16 ? 16 : 32;
+    const int P = pl.p <= 16 ? 16 : (pl.p <= 32 ? 32 : 64);
     const unsigned grid = (unsigned)((nleaf + 256 / G - 1) / (256 / G));
     auto fin = [&](auto tag, auto gtag, auto ptag) {
         using T = decltype(tag);
@@ -489,7 +490,8 @@ void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStrea
     };
     auto fin_p = [&](auto tag) {
         if (P == 16) fin_g(tag, std::integral_constant<int, 16>{});
-        else fin_g(tag, std::integral_constant<int, 32>{});
+        else if (P == 32) fin_g(tag, std::integral_constant<int, 32>{});
+        else fin_g(tag, std::integral_constant<int, 64>{});
     };
     if (mixed) fin_p(float{});
     else fin_p(double{});

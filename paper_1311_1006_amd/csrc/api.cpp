@@ -121,10 +121,15 @@ void flag_slot_release(int slot)
 
 // --------------------------------------------------------- schedule cache
 namespace {
-struct SchedKey {
+struct SchedKey {     // schedules hold device arrays: one per device
+    int device;
     std::vector<int64_t> off;
     std::vector<int> L;
-    bool operator<(const SchedKey& o) const { return off != o.off ? off < o.off : L < o.L; }
+    bool operator<(const SchedKey& o) const
+    {
+        if (device != o.device) return device < o.device;
+        return off != o.off ? off < o.off : L < o.L;
+    }
 };
 }  // namespace
 
@@ -197,7 +202,7 @@ int fmm_choose_order(fmm_tree_t t, const double* m, double theta, double tol, in
     return guarded([&] {
         FMM_REQUIRE(t && m && p_out, "NULL argument");
         *p_out = -1;
-        FMM_REQUIRE(1 <= p_lo && p_lo <= p_hi && p_hi < kMaxP, "need 1 <= p_lo <= p_hi <= 31");
+        FMM_REQUIRE(1 <= p_lo && p_lo <= p_hi && p_hi <= 48, "need 1 <= p_lo <= p_hi <= 48");
         FMM_REQUIRE(theta > 0.0 && theta < 1.0, "theta must be in (0, 1)");
         FMM_REQUIRE(tol > 0.0 && tol < 1.0, "tol must be in (0, 1)");
         check_device_state();
@@ -216,7 +221,10 @@ int fmm_choose_order(fmm_tree_t t, const double* m, double theta, double tol, in
             fmm_plan_destroy(pl);
             if (rc != FMM_OK) throw Error(rc, msg);
         };
-        run(kMaxP, FMM_FP64, ref.p);
+        // the reference order: 32 terms for the usual range, else 16 more
+        // than the highest order tried (at most 64)
+        const int pref = p_hi <= 24 ? 32 : std::min(kMaxP, p_hi + 16);
+        run(pref, FMM_FP64, ref.p);
         double e[2] = {0.0, 0.0};
         for (int p = p_lo; p <= p_hi; ++p) {
             run(p, FMM_FP64, phi.p);
@@ -254,12 +262,14 @@ int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int
         FMM_REQUIRE(z != nullptr, "z is NULL");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
+        int device = 0;
+        FMM_HIP(hipGetDevice(&device));
         static std::mutex mu;
         static std::map<SchedKey, std::shared_ptr<TreeSchedule>> cache;
         std::shared_ptr<TreeSchedule> sched;
         {
             std::lock_guard<std::mutex> lk(mu);
-            SchedKey k{off, L};
+            SchedKey k{device, off, L};
             auto it = cache.find(k);
             if (it != cache.end()) sched = it->second;
         }
@@ -268,12 +278,13 @@ int fmm_build_tree(const double* z, const int64_t* offsets, int nprob, const int
             upload_schedule(*sched, s);
             std::lock_guard<std::mutex> lk(mu);
             if (cache.size() > 16) cache.clear();
-            cache[SchedKey{off, L}] = sched;
+            cache[SchedKey{device, off, L}] = sched;
         }
         auto tr = std::make_unique<fmm_tree_s>();
         tr->off = off;
         tr->L = L;
         tr->t.stream = s;
+        tr->t.device = device;   // the device of the tree, its plans and their side streams
         // the schedule is shared with the cache: keep a reference in the tree
         tr->t.sched = sched.get();
         tr->t.sched_ref = sched;
@@ -300,7 +311,7 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         FMM_REQUIRE(out, "out is NULL");
         *out = nullptr;
         FMM_REQUIRE(t, "tree is NULL");
-        FMM_REQUIRE(p >= 1 && p <= kMaxP, "p must be in [1, 32]");
+        FMM_REQUIRE(p >= 1 && p <= kMaxP, "p must be in [1, 64]");
         FMM_REQUIRE(theta > 0.0 && theta < 1.0, "theta must be in (0, 1)");
         FMM_REQUIRE(precision == FMM_FP64 || precision == FMM_MIXED, "unknown precision");
         fmm_tuning tn{};
@@ -339,6 +350,7 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         // upward pass); their flags are read by the first call that needs
         // them (plan_finalize), so the host returns meanwhile
         alloc_eval_buffers(pl, s);
+        plan_events(pl);
         hipStream_t ls = side_stream(pl.tree->device, kListStream);
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_tree, hipEventDisableTiming));
         FMM_HIP(hipEventRecord(pl.ev_tree, s));

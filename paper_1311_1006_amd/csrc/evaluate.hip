@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "fmm_internal.h"
+#include "kernels_common.h"
 #include "plan_extra.h"
 
 namespace fmm {
@@ -147,11 +148,12 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
         upload_vec(ex.p2p_items, raw, s);
     }
     prepare_adjoint_items(pl, ex, leaves, s);
-    // binomial table C(n, k), n, k < 64
-    std::vector<double> bin(64 * 64, 0.0);
-    for (int n = 0; n < 64; ++n) {
-        bin[n * 64] = 1.0;
-        for (int k = 1; k <= n; ++k) bin[n * 64 + k] = bin[(n - 1) * 64 + k - 1] + (k < n ? bin[(n - 1) * 64 + k] : 0.0);
+    // binomial table C(n, k), n < kBinomRows, k < kBinomStride (Pascal's rule)
+    std::vector<double> bin(kBinomRows * kBinomStride, 0.0);
+    for (int n = 0; n < kBinomRows; ++n) {
+        bin[n * kBinomStride] = 1.0;
+        for (int k = 1; k <= n && k < kBinomStride; ++k)
+            bin[n * kBinomStride + k] = bin[(n - 1) * kBinomStride + k - 1] + (k < n ? bin[(n - 1) * kBinomStride + k] : 0.0);
     }
     upload_vec(ex.binom, bin, s);
     FMM_HIP(hipStreamSynchronize(s));
@@ -171,6 +173,9 @@ void alloc_eval_buffers(Plan& pl, hipStream_t s)
     pl.local.alloc(2 * cs * sc.nbox * pl.p, s);
 }
 
+// whether P2M also forms the M2M of the leaves' parents
+static bool leaf_m2m(const Plan& pl, const PlanExtra& ex) { return ex.leaf_m2m_in_p2m && pl.p <= 32; }
+
 // gather (own kernel, or inside P2M) and P2M; m = strengths in input order
 template <class T>
 static void run_p2m(Plan& pl, PlanExtra& ex, const double* m, hipStream_t s)
@@ -183,7 +188,8 @@ static void run_p2m(Plan& pl, PlanExtra& ex, const double* m, hipStream_t s)
     if (!ex.gather_in_p2m)
         launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
     // with leaf_m2m_in_p2m the P2M kernel also forms the leaves' parents
-    const bool fm = ex.leaf_m2m_in_p2m;
+    // (up to 32 terms: above that P2M runs in two blocks of terms)
+    const bool fm = leaf_m2m(pl, ex);
     launch_p2m<T>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
                   pl.mtree.p, pl.p, pl.mpole.p, s, fm ? sc.d_box_parent.p : nullptr, ex.binom.p,
                   ex.gather_in_p2m ? &go : nullptr);
@@ -195,7 +201,7 @@ static void run_m2m(Plan& pl, PlanExtra& ex, void* mp, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    const bool fm = ex.leaf_m2m_in_p2m;
+    const bool fm = leaf_m2m(pl, ex);
     for (int l = sc.max_levels - (fm ? 3 : 2); l >= 1; --l) {
         int n = (int)(ex.m2m_off[l + 1] - ex.m2m_off[l]);
         launch_m2m<T>(ex.d_m2m.p + ex.m2m_off[l], n, ex.child0.p, t.geom.p, ex.binom.p, pl.p, mp, s);
@@ -331,6 +337,21 @@ hipStream_t side_stream(int device, int which)
     return st;
 }
 
+// The evaluation's side stream and events, made when the plan is made (the
+// evaluations then create nothing)
+void plan_events(Plan& pl)
+{
+    if (!pl.nstream) {
+        pl.nstream = side_stream(pl.tree->device, kNearStream);
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
+    }
+    if (!pl.ev_top0) {
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_top0, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&pl.ev_top1, hipEventDisableTiming));
+    }
+}
+
 // The part of an evaluation that needs no lists: gather and the upward
 // pass.  evaluate_device then continues from there on the same stream (the
 // near field is forked there, after the plan's remaining kernels).
@@ -371,7 +392,7 @@ void launch_l2p_log(const int32_t* leaves, int nleaf, const int32_t* bstart, con
 // logarithmic kernel (on the second stream, beside the far field, from the
 // source records P2M writes), the constant terms of the local expansions,
 // and L2P of the integrated series after the join.
-void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s)
+void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s, double* mlog, double* c0)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -382,12 +403,16 @@ void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s)
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
-    pl.mlog.alloc(2 * sc.n, s);
-    pl.c0.alloc(sc.nbox, s);
-    launch_real_to_complex(sc.n, q, pl.mlog.p, s);
+    if (!mlog) {
+        pl.mlog.alloc(2 * sc.n, s);
+        pl.c0.alloc(sc.nbox, s);
+        mlog = pl.mlog.p;
+        c0 = pl.c0.p;
+    }
+    launch_real_to_complex(sc.n, q, mlog, s);
     PhaseTimer tm(false, s);
-    if (mixed) run_p2m<float>(pl, ex, pl.mlog.p, s);
-    else run_p2m<double>(pl, ex, pl.mlog.p, s);
+    if (mixed) run_p2m<float>(pl, ex, mlog, s);
+    else run_p2m<double>(pl, ex, mlog, s);
     FMM_HIP(hipEventRecord(pl.ev_fork, s));
     FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
     run_p2p(pl, ex, pl.nstream, nullptr, true);
@@ -401,11 +426,11 @@ void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s)
     }
     auto constants = mixed ? launch_log_constants<float> : launch_log_constants<double>;
     constants((int)sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, pl.mpole.p, pl.local.p, pl.p,
-              ex.d_level_boxes.p, ex.level_boxes_off, sc.max_levels, sc.d_box_parent.p, pl.c0.p, s);
+              ex.d_level_boxes.p, ex.level_boxes_off, sc.max_levels, sc.d_box_parent.p, c0, s);
     FMM_HIP(hipStreamWaitEvent(s, pl.ev_join, 0));
     auto l2p = mixed ? launch_l2p_log<float> : launch_l2p_log<double>;
     l2p(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.local.p, pl.p,
-        pl.c0.p, pl.near.p, t.perm.p, u, s);
+        c0, pl.near.p, t.perm.p, u, s);
     // the harmonic state of the plan now holds these strengths: no adjoint of it
     pl.have_forward = false;
 }

@@ -47,9 +47,10 @@ __device__ __forceinline__ void wave_sync_e()
 
 // P2M at the leaves.  G lanes per leaf (64/G leaves per wavefront, four
 // wavefronts per workgroup): each lane takes the points j = lane, lane + G,
-// ... of its leaf and accumulates all P terms m_j w_j^k (w_j = (z_j - c)/rs)
-// in FP64 registers; a transposing butterfly then sums them over the G
-// lanes.  P = 16 or 32 bounds p.
+// ... of its leaf and accumulates the P terms m_j w_j^k, k = k0 .. k0+P-1
+// (w_j = (z_j - c)/rs) in FP64 registers; a transposing butterfly then sums
+// them over the G lanes.  P = 16 or 32; p > 32 takes two launches (k0 = 0
+// and 32).
 __device__ __forceinline__ double2 cpow(double2 b, int e)
 {
     double2 r = make_double2(1.0, 0.0);
@@ -81,7 +82,7 @@ template <class T, int G, int P, bool LEAF_M2M, bool GATHER>
 __global__ void __launch_bounds__(256)
 k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ bstart,
       const int32_t* __restrict__ bcount, const double* __restrict__ geom, const double* __restrict__ X,
-      const double* __restrict__ Y, const double2* __restrict__ mt, int p, T* mp,
+      const double* __restrict__ Y, const double2* __restrict__ mt, int p, int k0, T* mp,
       const int32_t* __restrict__ parent, const double* __restrict__ binom, GatherOut go)
 {
     static_assert(!LEAF_M2M || G == 16, "a sibling group per wavefront needs 16 lanes per leaf");
@@ -124,6 +125,7 @@ k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
             w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
             t = mt[i];
         }
+        if (k0 != 0) t = cmul(t, cpow(w, k0));   // the block of terms from k0 on
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             v[2 * k] += t.x;
@@ -138,7 +140,7 @@ k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
     if (valid && writer) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int idx = base + i, k = idx >> 1;
+            const int idx = base + i, k = k0 + (idx >> 1);
             if (k < p) mp[2 * ((int64_t)g * p + k) + (idx & 1)] = (T)v[i];
         }
     }
@@ -295,7 +297,10 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     using T2 = typename Vec2<T>::type;
-    __shared__ double2 sco[LEAF_L2L ? 256 / G : 1][LEAF_L2L ? P : 1];
+    // P = 64: the coefficients stay in LDS (64 complex FP64 values would
+    // take every register of a lane); below that they go to registers
+    constexpr bool kLdsCoef = P > 32;
+    __shared__ double2 sco[LEAF_L2L || kLdsCoef ? 256 / G : 1][LEAF_L2L || kLdsCoef ? P : 1];
     __shared__ double2 stau[LEAF_L2L ? 256 / G : 1][LEAF_L2L ? P : 1];
     const int lane = threadIdx.x & 63;
     const int li = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / G) + lane / G;
@@ -305,14 +310,14 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
     const int st = bstart[g], n = bcount[g];
     const double cx = geom[4 * (int64_t)g], cy = geom[4 * (int64_t)g + 1], inv = 1.0 / geom[4 * (int64_t)g + 3];
     T2* b = reinterpret_cast<T2*>(loc) + (int64_t)g * p;
-    double2 bl[P];
+    double2 bl[kLdsCoef ? 1 : P];
+    double2* co = sco[(LEAF_L2L || kLdsCoef) ? threadIdx.x / G : 0];
     if constexpr (LEAF_L2L) {
         const int pg = parent[g];
         const double prs = geom[4 * (int64_t)pg + 3];
         const double rho = geom[4 * (int64_t)g + 3] / prs;
         const double2 tau = make_double2((cx - geom[4 * (int64_t)pg]) / prs, (cy - geom[4 * (int64_t)pg + 1]) / prs);
         const T2* bp = reinterpret_cast<const T2*>(loc) + (int64_t)pg * p;
-        double2* co = sco[threadIdx.x / G];
         double2* tp = stau[threadIdx.x / G];
         for (int j = sl; j < p; j += G) tp[j] = cpow(tau, j);   // the table of k_l2l
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -335,12 +340,24 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
             b[l] = T2{tx, ty};
             co[l] = make_double2((double)tx, (double)ty);
         }
+        if constexpr (kLdsCoef)
+            for (int l = p + sl; l < P; l += G) co[l] = make_double2(0.0, 0.0);
         // the group lies in one wavefront
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if constexpr (!kLdsCoef) {
 #pragma unroll
-        for (int k = 0; k < P; ++k) bl[k] = k < p ? co[k] : make_double2(0.0, 0.0);
+            for (int k = 0; k < P; ++k) bl[k] = k < p ? co[k] : make_double2(0.0, 0.0);
+        }
+    } else if constexpr (kLdsCoef) {
+        for (int k = sl; k < P; k += G) {
+            if (k < p) { const T2 v = b[k]; co[k] = make_double2((double)v.x, (double)v.y); }
+            else co[k] = make_double2(0.0, 0.0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -351,12 +368,22 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
     for (int j = sl; j < n; j += G) {
         const int i = st + j;
         const double2 w = make_double2((X[i] - cx) * inv, (Y[i] - cy) * inv);
-        double2 acc = bl[P - 1];
+        double2 acc;
+        if constexpr (kLdsCoef) {
+            acc = co[P - 1];
+            for (int l = P - 2; l >= 0; --l) {
+                acc = cmul(acc, w);
+                acc.x += co[l].x;
+                acc.y += co[l].y;
+            }
+        } else {
+            acc = bl[P - 1];
 #pragma unroll
-        for (int l = P - 2; l >= 0; --l) {
-            acc = cmul(acc, w);
-            acc.x += bl[l].x;
-            acc.y += bl[l].y;
+            for (int l = P - 2; l >= 0; --l) {
+                acc = cmul(acc, w);
+                acc.x += bl[l].x;
+                acc.y += bl[l].y;
+            }
         }
         const double2 nf = nearf[i];
         const int o = perm[i];
@@ -397,33 +424,41 @@ void launch_p2m(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
     const GatherOut none{};
     const GatherOut& gg = go ? *go : none;
     if (nleaf == 0) return;
+    if (p > 32 && parent) throw Error(FMM_EINVAL, "P2M with the leaves' M2M needs p <= 32");
     const int G = leaf_lanes(leaf_max);
+    const int PB = p <= 16 ? 16 : 32;
     const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
+    // blocks of PB terms: the first one does the gather, the second (p > 32)
+    // reads the strengths it put into tree order
+    for (int k0 = 0; k0 < p; k0 += PB) {
+        const bool gat = go && k0 == 0;
+        const double2* mtk = (const double2*)(k0 == 0 ? mt : (go ? (const double*)go->mtree : mt));
 #define P2M_CASE(G_, P_)                                                                                   \
-    if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
+    if (G == G_ && PB == P_) {                                                                            \
         if constexpr (G_ == 16)                                                                           \
             if (parent) {                                                                                 \
-                if (go)                                                                                   \
+                if (gat)                                                                                  \
                     k_p2m<T, G_, P_, true, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, \
-                        Y, (const double2*)mt, p, (T*)mp, parent, binom, gg);                             \
+                        Y, mtk, p, k0, (T*)mp, parent, binom, gg);                                        \
                 else                                                                                      \
                     k_p2m<T, G_, P_, true, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, \
-                        Y, (const double2*)mt, p, (T*)mp, parent, binom, gg);                             \
+                        Y, mtk, p, k0, (T*)mp, parent, binom, gg);                                        \
                 check_launch("p2m");                                                                      \
-                return;                                                                                   \
+                continue;                                                                                 \
             }                                                                                             \
-        if (go)                                                                                           \
+        if (gat)                                                                                          \
             k_p2m<T, G_, P_, false, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, \
-                (const double2*)mt, p, (T*)mp, nullptr, nullptr, gg);                                     \
+                mtk, p, k0, (T*)mp, nullptr, nullptr, gg);                                                \
         else                                                                                              \
             k_p2m<T, G_, P_, false, false><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, \
-                (const double2*)mt, p, (T*)mp, nullptr, nullptr, gg);                                     \
+                mtk, p, k0, (T*)mp, nullptr, nullptr, gg);                                                \
         check_launch("p2m");                                                                              \
-        return;                                                                                           \
+        continue;                                                                                         \
     }
-    P2M_CASE(16, 16) P2M_CASE(32, 16) P2M_CASE(64, 16) P2M_CASE(16, 32) P2M_CASE(32, 32) P2M_CASE(64, 32)
+        P2M_CASE(16, 16) P2M_CASE(32, 16) P2M_CASE(64, 16) P2M_CASE(16, 32) P2M_CASE(32, 32) P2M_CASE(64, 32)
 #undef P2M_CASE
-    throw Error(FMM_EINVAL, "unsupported P2M configuration");
+        throw Error(FMM_EINVAL, "unsupported P2M configuration");
+    }
 }
 
 template <class T>
@@ -454,7 +489,7 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
     const int G = leaf_lanes(leaf_max);
     const unsigned grid = (unsigned)((nleaf + 4 * (64 / G) - 1) / (4 * (64 / G)));
 #define L2P_CASE(G_, P_)                                                                                   \
-    if (G == G_ && (p <= 16 ? 16 : 32) == P_) {                                                           \
+    if (G == G_ && (p <= 16 ? 16 : (p <= 32 ? 32 : 64)) == P_) {                                          \
         if (parent)                                                                                       \
             k_l2p<T, G_, P_, true><<<grid, 256, 0, s>>>(leaves, nleaf, bstart, bcount, geom, X, Y, (T*)loc, p, \
                                                         (const double2*)nearf, perm, (double2*)phi,       \
@@ -469,6 +504,7 @@ void launch_l2p(const int32_t* leaves, int nleaf, const int32_t* bstart, const i
         return;                                                                                           \
     }
     L2P_CASE(16, 16) L2P_CASE(32, 16) L2P_CASE(64, 16) L2P_CASE(16, 32) L2P_CASE(32, 32) L2P_CASE(64, 32)
+    L2P_CASE(16, 64) L2P_CASE(32, 64) L2P_CASE(64, 64)
 #undef L2P_CASE
     throw Error(FMM_EINVAL, "unsupported L2P configuration");
 }

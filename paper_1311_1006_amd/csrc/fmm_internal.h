@@ -41,7 +41,7 @@ inline void check_launch(const char* what) {
 
 // ------------------------------------------------------------- constants
 constexpr int kMaxLevels = 16;
-constexpr int kMaxP = 32;
+constexpr int kMaxP = 64;          // expansion terms at most (Table 4.1 reaches p = 39)
 // tree build
 constexpr int kTile = 2048;        // points per workgroup tile in the global split stages
 constexpr int kTileThreads = 256;
@@ -267,6 +267,7 @@ double rel_err2_device(const double* a, const double* ref, int64_t n, hipStream_
 constexpr int kNearStream = 0, kListStream = 1, kTopStream = 2;
 hipStream_t side_stream(int device, int which);
 void plan_join(Plan& pl, hipStream_t s);
+void plan_events(Plan& pl);
 void plan_finalize(Plan& pl);
 void plan_balance(Plan& pl, hipStream_t s);
 void list_totals_device(Plan& pl, hipStream_t s);
@@ -276,8 +277,11 @@ void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
-// the logarithmic potential u (real, input order) of real strengths q
-void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s);
+// the logarithmic potential u (real, input order) of real strengths q; mlog
+// (2 N doubles: q as complex numbers in input order) and c0 (one double per
+// box: the constant terms) are the plan's own buffers when mlog is NULL
+void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s, double* mlog = nullptr,
+                         double* c0 = nullptr);
 // the gather of an evaluation (strengths into tree order, P2P source records)
 // done by the P2M kernel as it reads every point of its leaves
 struct GatherOut {

@@ -4,7 +4,8 @@
 
 namespace fmm {
 
-constexpr int kBinomStride = 64;   // binomial table C(n, k), n, k < 64, row-major
+constexpr int kBinomStride = 64;   // binomial table C(n, k), k < 64, row-major
+constexpr int kBinomRows = 128;    // n < 128: M2L reads C(k + l, k) with k, l < p <= 64
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {

@@ -27,7 +27,9 @@
 // are summed by a butterfly.
 // FP32 path: v_mfma_f32_16x16x4f32 (output rows 4 kq + j), FP32 accumulation.
 // FP64 path: v_mfma_f64_16x16x4f64 (output rows kq + 4 j).
-// p <= 16 uses one 16-row block (PB = 1), p <= 32 two.
+// p <= 16 uses one 16-row block (PB = 1), p <= 32 two, p <= 48 three and
+// p <= 64 four (those with one box per wavefront: the expansion orders of the
+// strictest tolerances, where a wavefront's 16 pair slots stay full anyway).
 #include "fmm_internal.h"
 #include "kernels_common.h"
 
@@ -288,9 +290,12 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
         const auto base = M::kRowsConsecutive ? cpow_lane(c.w4, c.w8, kq) : cpow_lane(c.wv, c.w2, kq);   // w^r0
         const auto step = M::kRowsConsecutive ? c.wv : c.w4;
         const auto f0 = cmul(base, c.id);
+        const auto w16 = cmul(c.w8, c.w8);
+        auto frb = f0;
 #pragma unroll
         for (int rb = 0; rb < PB; ++rb) {
-            auto f = rb > 0 ? cmul(f0, cmul(c.w8, c.w8)) : f0;             // row r0 + 16: times w^16
+            if (rb > 0) frb = cmul(frb, w16);                               // row r0 + 16 rb: times w^(16 rb)
+            auto f = frb;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 fre[rb][j] = (T)f.x;
@@ -445,6 +450,10 @@ void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const i
         else if (slots == 8) m2l_one<T, 2, 2>(ARGS);
         else if (slots == 4) m2l_one<T, 2, 4>(ARGS);
         else throw Error(FMM_EINVAL, "unsupported M2L batch");
+    } else if (p <= 48) {          // three and four row blocks: one box per wavefront
+        m2l_one<T, 3, 1>(ARGS);
+    } else if (p <= 64) {
+        m2l_one<T, 4, 1>(ARGS);
     } else {
         throw Error(FMM_EINVAL, "unsupported M2L configuration");
     }

@@ -217,6 +217,6 @@ def test_invalid_arguments_raise(F):
     with pytest.raises(F.FmmError):
         F.build_tree(dev(bad), 2).download(0)
     tree = F.build_tree(dev(z), 2)
-    for p, th in ((0, 0.5), (33, 0.5), (10, 0.0), (10, 1.0)):
+    for p, th in ((0, 0.5), (65, 0.5), (10, 0.0), (10, 1.0)):
         with pytest.raises(F.FmmError):
             F.plan(tree, p, th)
