@@ -31,3 +31,15 @@ def same_tree(orc, F, z, L, offsets=None, prob=0, tree=None):
         s0, c = rng_o[b]
         assert np.array_equal(np.sort(perm_g[s0:s0 + c]), np.sort(perm_o[s0:s0 + c])), "box %d" % b
     return tree
+
+
+def einf(a, b):
+    """e_inf = max|a - b| / max|b| (the secondary error metric)."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def epoint(a, b):
+    """Largest error of one value in units of the RMS of the reference:
+    max_i |a_i - b_i| / (||b||_2 / sqrt(n)).  Catches a few values that are
+    far off while the 2-norm stays small."""
+    return float(np.max(np.abs(a - b)) / (np.linalg.norm(b) / np.sqrt(b.size)))
