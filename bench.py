@@ -30,6 +30,11 @@ PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X published dense FP32 matrix peak
 P2P_FLOP_PER_PAIR = 16      # per (target, source) pair: see the near-field kernel's header
 M2L_AUTO_SLOTS_MIXED = 8    # M2L pair slots per box chosen automatically for mixed precision
 ERR_TARGET = 1e-6           # relative error target of both forms against the FP64 direct sum
+PEAK_HBM_GBS = 8000.0       # GB/s, MI355X published HBM3E bandwidth
+# tree build: per point and binary split, the 8-byte split coordinate read for
+# the median selection plus the 20-byte payload (x, y, index) read and written
+# by the partition, and 4 bytes of bookkeeping
+TREE_BYTES_PER_POINT_SPLIT = 52
 
 
 def m2l_flop_per_pair(p):
@@ -380,6 +385,23 @@ def main():
         torch.cuda.synchronize()
         dte = (time.perf_counter() - t1) / args.steps
         phi = out.cpu().numpy()
+        # per-step device times (events on the stream the step is ordered on;
+        # the side streams join it before the end event): median and minimum
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a, b in evs:
+            a.record()
+            step(prec, cfg)
+            b.record()
+        torch.cuda.synchronize()
+        per_step = sorted(a.elapsed_time(b) for a, b in evs)
+        # the tree build alone, the same way
+        for a, b in evs:
+            a.record()
+            F.build_tree(zd, cfg[0])
+            b.record()
+        torch.cuda.synchronize()
+        per_tree = sorted(a.elapsed_time(b) for a, b in evs)
         # per-phase device times (hipEvents on the evaluation stream) of the same plan shape
         plt = F.plan(tree, order(cfg[0]), theta, prec, p2p_split=cfg[1], m2l_batch=cfg[2], timing=True)
         ph = {}
@@ -391,7 +413,9 @@ def main():
                     ph[k] = ph.get(k, 0.0) + st[k] / args.steps
         st = plt.stats()
         res[prec] = dict(L=cfg[0], p=order(cfg[0]), split=cfg[1], batch=cfg[2], t=dt, t_eval=dte, stats=st, phases=ph,
-                         p2p_us=ph["t_p2p_us"], m2l_us=ph["t_m2l_us"], phi=phi)
+                         p2p_us=ph["t_p2p_us"], m2l_us=ph["t_m2l_us"], phi=phi,
+                         step_ms_median=float(np.median(per_step)), step_ms_min=per_step[0],
+                         tree_us_median=1e3 * float(np.median(per_tree)), tree_us_min=1e3 * per_tree[0])
         log("%s: L=%d p=%d split=%d batch=%d step %.3f ms (%.1f Mpoints/s), evaluate %.3f ms, phases %s" %
             (prec, cfg[0], order(cfg[0]), cfg[1], cfg[2], dt * 1e3, n / dt / 1e6, dte * 1e3,
              " ".join("%s=%.1f" % (k[2:-3], v) for k, v in ph.items())))
@@ -401,6 +425,7 @@ def main():
     # ---- accuracy vs the FP64 direct sum (CPU oracle) on the subsample
     err = {}
     cpu_baseline = None
+    parity = None
     if not args.no_cpu:
         import oracle
         t0 = time.perf_counter()
@@ -408,13 +433,23 @@ def main():
         log("direct sum on %d targets: %.1f s" % (sub.size, time.perf_counter() - t0))
         for prec in res:
             err[prec] = oracle.rel_err2(res[prec]["phi"][sub], ref)
-            log("%s e2 vs direct: %.3e" % (prec, err[prec]))
-        # CPU oracle (serial FMM O2, its P2P loop OpenMP-parallel) on the full workload
+            err[prec + "_inf"] = oracle.rel_errinf(res[prec]["phi"][sub], ref)
+            log("%s vs direct: e2 %.3e, e_inf %.3e" % (prec, err[prec], err[prec + "_inf"]))
+        # CPU oracle (serial FMM O2, its P2P loop OpenMP-parallel) on the full
+        # workload; its result is the parity reference of the FP64 path at the
+        # same (p, theta, N_levels)
         L = best_cfg["fp64"][0]
         p = order(L)
         t0 = time.perf_counter()
-        oracle.fmm(z, m, p, theta, L)
+        o2 = oracle.fmm(z, m, p, theta, L)
         tc = time.perf_counter() - t0
+        parity = {"n_levels": L, "p": p, "theta": theta,
+                  "fp64_e2": oracle.rel_err2(res["fp64"]["phi"], o2),
+                  "fp64_einf": oracle.rel_errinf(res["fp64"]["phi"], o2)}
+        if res["mixed"]["L"] == L:
+            parity["mixed_e2"] = oracle.rel_err2(res["mixed"]["phi"], o2)
+            parity["mixed_einf"] = oracle.rel_errinf(res["mixed"]["phi"], o2)
+        log("parity against the oracle's serial FMM (all %d points): %s" % (n, parity))
         cpu_baseline = {"value": n / tc / 1e6, "unit": "Mpoints/s", "cores": oracle.threads(),
                         "kind": "oracle",
                         "sample": "one full serial-FMM evaluation (tree, lists, P2M..L2P, P2P) of the "
@@ -445,10 +480,22 @@ def main():
                 "traffic": profile_traffic("m2l_mixed_uniform_n1e6_L9_pmc.txt")
                 if slots == M2L_AUTO_SLOTS_MIXED else None,
                 "avg_us": mx["m2l_us"], "pairs": st["n_m2l_pairs"], "flop_per_pair": fpp}
-    if mx["m2l_us"] >= mx["p2p_us"]:
-        roofline, other = roof_m2l, {"p2p": roof_p2p}
-    else:
-        roofline, other = roof_p2p, {"m2l": roof_m2l}
+    # the tree build (every kernel of one build, HBM-bound): algorithmic bytes
+    # per build = TREE_BYTES_PER_POINT_SPLIT per point and binary split
+    # (2 (N_levels - 1) splits), over the build's median device time
+    nsplit = 2 * (mx["L"] - 1)
+    tree_bytes = TREE_BYTES_PER_POINT_SPLIT * nsplit * n
+    gbs = tree_bytes / (mx["tree_us_median"] * 1e-6) / 1e9
+    roof_tree = {"bound": "hbm", "kernel": "tree build (%d binary splits: global split stages + in-LDS stage)" % nsplit,
+                 "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                 "traffic": profile_traffic("tree_uniform_n1e6_L9_pmc.txt") if mx["L"] == 9 else None,
+                 "avg_us": mx["tree_us_median"], "min_us": mx["tree_us_min"],
+                 "bytes_per_build": tree_bytes, "bytes_per_point_split": TREE_BYTES_PER_POINT_SPLIT}
+    # the dominant one: the longest device time per step
+    cands = {"p2p": roof_p2p, "m2l": roof_m2l, "tree": roof_tree}
+    dom = max(cands, key=lambda k: cands[k]["avg_us"])
+    roofline = cands[dom]
+    other = {k: v for k, v in cands.items() if k != dom}
     line = {
         "metric": "Mpoints/s full FMM eval N=1e6 @rel err<=1e-6: mixed-prec vs plain FP64 GPU",
         "value": n / mx["t"] / 1e6,
@@ -466,8 +513,16 @@ def main():
                    "n": n, "p": mx["p"], "p_rule": p_rule, "theta": theta, "n_levels": mx["L"], "p2p_split": mx["split"],
                    "m2l_batch": mx["batch"], "precision": "mixed", "step": "build_tree+plan+evaluate"},
         "fp64": {"value": n / fp["t"] / 1e6, "n_levels": fp["L"], "p": fp["p"], "ms_per_step": fp["t"] * 1e3,
-                 "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64"), "phases_us": fp["phases"]},
-        "mixed": {"eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed"), "phases_us": mx["phases"]},
+                 "step_ms_median": fp["step_ms_median"], "step_ms_min": fp["step_ms_min"],
+                 "tree_us_median": fp["tree_us_median"],
+                 "eval_only_mpoints_s": n / fp["t_eval"] / 1e6, "e2": err.get("fp64"), "e_inf": err.get("fp64_inf"),
+                 "phases_us": fp["phases"]},
+        "mixed": {"step_ms_median": mx["step_ms_median"], "step_ms_min": mx["step_ms_min"],
+                  "tree_us_median": mx["tree_us_median"],
+                  "eval_only_mpoints_s": n / mx["t_eval"] / 1e6, "e2": err.get("mixed"), "e_inf": err.get("mixed_inf"),
+                  "phases_us": mx["phases"]},
+        "parity_fp64_vs_oracle_e2": parity["fp64_e2"] if parity else None,
+        "parity_vs_oracle_fmm": parity,
         "speedup_mixed_vs_fp64": fp["t"] / mx["t"],
         "roofline": roofline,
         "roofline_other": other,

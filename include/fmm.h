@@ -63,8 +63,15 @@ enum {
     FMM_FLAG_GRAPH = 1,       /* capture fmm_evaluate's kernels in a hipGraph on first
                                  use and replay it on later calls with the same
                                  pointers and stream */
-    FMM_FLAG_PHASE_TIMING = 2 /* record per-phase hipEvent timings into fmm_stats
+    FMM_FLAG_PHASE_TIMING = 2, /* record per-phase hipEvent timings into fmm_stats
                                  (adds one event pair per phase) */
+    FMM_FLAG_LEVELWISE = 4    /* run the far field's upward and downward passes level
+                                 by level (one launch per level of M2M and of L2L)
+                                 instead of by subtrees (trees whose problems all
+                                 have the same N_levels >= 3, p <= 32: P2M with two
+                                 M2M levels, three-level M2M subtrees, and an L2P
+                                 that shifts every ancestor's M2L sum into the
+                                 leaves directly); the two agree up to rounding */
 };
 
 /* Launch-shape knobs of one plan; 0 means "choose automatically". */
@@ -72,8 +79,9 @@ typedef struct {
     int p2p_split;   /* P2P: lane subgroups per wavefront (1, 2, 4); each subgroup takes
                         its own targets and one source per lane */
     int m2l_batch;   /* M2L: pair slots of one box in each 16-pair MFMA block: 16 (one
-                        box per wavefront), 8 or 4 (two or four boxes share a
-                        wavefront and its blocks); automatic: 8 mixed, 4 FP64 */
+                        box per wavefront), 8, 4, 2 or 1 (2, 4, 8 or 16 boxes share a
+                        wavefront and its blocks; with 1 every MFMA column is one box);
+                        automatic: 8 mixed, 4 FP64 */
     int flags;       /* FMM_FLAG_* */
     int reserved;
     double smooth_delta;   /* > 0: the near field (P2P) takes every term times the Gaussian

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm_hip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fmm.h")
 
 FMM_FP64, FMM_MIXED = 0, 1
-FMM_FLAG_GRAPH, FMM_FLAG_PHASE_TIMING = 1, 2
+FMM_FLAG_GRAPH, FMM_FLAG_PHASE_TIMING, FMM_FLAG_LEVELWISE = 1, 2, 4
 _PREC = {"fp64": FMM_FP64, "mixed": FMM_MIXED, FMM_FP64: FMM_FP64, FMM_MIXED: FMM_MIXED}
 
 
@@ -235,9 +235,12 @@ class Plan:
 
 
 def plan(tree, p, theta, precision="fp64", p2p_split=0, m2l_batch=0, graph=False, timing=False, smooth_delta=0.0,
-         stream=None):
-    tn = _Tuning(p2p_split, m2l_batch, (FMM_FLAG_GRAPH if graph else 0) | (FMM_FLAG_PHASE_TIMING if timing else 0), 0,
-                 float(smooth_delta))
+         stream=None, levelwise=False):
+    """levelwise: the far field's upward and downward passes level by level
+    (FMM_FLAG_LEVELWISE) instead of by subtrees."""
+    flags = ((FMM_FLAG_GRAPH if graph else 0) | (FMM_FLAG_PHASE_TIMING if timing else 0) |
+             (FMM_FLAG_LEVELWISE if levelwise else 0))
+    tn = _Tuning(p2p_split, m2l_batch, flags, 0, float(smooth_delta))
     h = C.c_void_p()
     _check(lib().fmm_plan(tree._h, p, float(theta), _PREC[precision], C.byref(tn), _stream(stream), C.byref(h)))
     return Plan(h, tree, p, theta, precision)

@@ -24,6 +24,9 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "
 
 # geometry, split axes and the theta-criterion: every operation rounded alone
 EXACT_FILES = {"tree_build.hip", "lists.hip"}
+# MFMA accumulators in ordinary vector registers (no copies out of the
+# accumulation registers after every product)
+MFMA_VGPR_FILES = {"m2l.hip"}
 
 
 def _compile(src):
@@ -33,6 +36,8 @@ def _compile(src):
         cmd += HIPFLAGS
     if os.path.basename(src) in EXACT_FILES:
         cmd += ["-ffp-contract=off"]
+    if os.path.basename(src) in MFMA_VGPR_FILES:
+        cmd += ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 target feature: harmless
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

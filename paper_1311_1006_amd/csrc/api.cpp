@@ -318,8 +318,9 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         if (tune) tn = *tune;
         FMM_REQUIRE(tn.p2p_split == 0 || tn.p2p_split == 1 || tn.p2p_split == 2 || tn.p2p_split == 4,
                     "p2p_split must be 0, 1, 2 or 4");
-        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 4 || tn.m2l_batch == 8 || tn.m2l_batch == 16,
-                    "m2l_batch must be 0, 4, 8 or 16");
+        FMM_REQUIRE(tn.m2l_batch == 0 || tn.m2l_batch == 1 || tn.m2l_batch == 2 || tn.m2l_batch == 4 ||
+                        tn.m2l_batch == 8 || tn.m2l_batch == 16,
+                    "m2l_batch must be 0, 1, 2, 4, 8 or 16");
         FMM_REQUIRE(tn.smooth_delta >= 0.0 && std::isfinite(tn.smooth_delta), "smooth_delta must be >= 0 and finite");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;

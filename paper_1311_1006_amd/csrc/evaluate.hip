@@ -46,6 +46,17 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
                 bool log_kernel);
 
+bool subtree_ok(int L, int p);
+template <class T>
+void launch_up_subtree(int nprob, int L, const int32_t* bstart, const int32_t* bcount, const double* geom,
+                       const double* X, const double* Y, const double* mt, int p, void* mp, const double* binom,
+                       const GatherOut* go, hipStream_t s);
+template <class T>
+void launch_down_subtree(int nprob, int L, const int32_t* bstart, const int32_t* bcount, const double* geom,
+                         const double* X, const double* Y, void* loc, int p, const double* nearf,
+                         const int32_t* perm, double* phi, double* phi_near, double* phi_far, const long long* guard,
+                         const double* binom, hipStream_t s);
+
 struct P2PItemH {
     int32_t leaf, t0, tn, pad;
 };
@@ -176,6 +187,27 @@ void alloc_eval_buffers(Plan& pl, hipStream_t s)
 // whether P2M also forms the M2M of the leaves' parents
 static bool leaf_m2m(const Plan& pl, const PlanExtra& ex) { return ex.leaf_m2m_in_p2m && pl.p <= 32; }
 
+// whether the far field runs by subtrees (subtree.hip): every problem of the
+// same depth L >= 3, the leaves holding every point, p <= 32
+static bool use_subtree(const Plan& pl, const PlanExtra& ex)
+{
+    const TreeSchedule& sc = *pl.tree->sched;
+    return ex.leaf_l2l_in_l2p && ex.gather_in_p2m && subtree_ok(sc.L[0], pl.p) &&
+           !(pl.tune.flags & FMM_FLAG_LEVELWISE);
+}
+
+// the whole upward pass by subtrees, with the gather
+template <class T>
+static void run_up_subtree(Plan& pl, const double* m, hipStream_t s)
+{
+    Tree& t = *pl.tree;
+    TreeSchedule& sc = *t.sched;
+    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p, (double4*)pl.src64.p, (float4*)pl.src32.p,
+                 (float2*)pl.srclo.p};
+    launch_up_subtree<T>(sc.nprob, sc.L[0], sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.mtree.p,
+                         pl.p, pl.mpole.p, pl.ex->binom.p, &go, s);
+}
+
 // gather (own kernel, or inside P2M) and P2M; m = strengths in input order
 template <class T>
 static void run_p2m(Plan& pl, PlanExtra& ex, const double* m, hipStream_t s)
@@ -260,6 +292,34 @@ static void run_far_down(Plan& pl, PlanExtra& ex, const void* mp, void* loc, hip
     // all above the cut.  Lists split into chunks, and phase timing, keep the
     // single launch.
     const int cut = std::min(sc.max_levels - 3, 6);
+    if (use_subtree(pl, ex) && !all_l2l) {
+        // M2L only: the L2L hand-over is part of the subtree L2P.  The top
+        // levels' M2L (a small, latency-bound launch) runs on the third
+        // stream beside the deeper levels'.
+        if (!tm.on && b.xitems.p == nullptr && b.total == sc.nbox && cut >= 1) {
+            if (!pl.ev_top0) {
+                FMM_HIP(hipEventCreateWithFlags(&pl.ev_top0, hipEventDisableTiming));
+                FMM_HIP(hipEventCreateWithFlags(&pl.ev_top1, hipEventDisableTiming));
+            }
+            hipStream_t ts = side_stream(t.device, kTopStream);
+            const int na = (int)ex.level_boxes_off[cut];
+            const int nb = (int)(ex.level_boxes_off[sc.max_levels] - na);
+            FMM_HIP(hipEventRecord(pl.ev_top0, s));
+            FMM_HIP(hipStreamWaitEvent(ts, pl.ev_top0, 0));
+            launch_m2l<T>(ex.d_level_boxes.p, na, nullptr, na, nullptr, nullptr, nullptr, false, pl.w_beg.p,
+                          pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, ts, pl.tune.m2l_batch, guard);
+            FMM_HIP(hipEventRecord(pl.ev_top1, ts));
+            launch_m2l<T>(ex.d_level_boxes.p + na, nb, nullptr, nb, nullptr, nullptr, nullptr, false, pl.w_beg.p,
+                          pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc, s, pl.tune.m2l_batch, guard);
+            FMM_HIP(hipStreamWaitEvent(s, pl.ev_top1, 0));
+        } else {
+            launch_m2l<T>(nullptr, (int)sc.nbox, b.xitems.p, (int)b.total, b.icnt.p, b.ioff.p, b.partial.p,
+                          b.total > sc.nbox, pl.w_beg.p, pl.w_cnt.p, pl.w_ids.p, t.geom.p, ex.binom.p, pl.p, mp, loc,
+                          s, pl.tune.m2l_batch, guard);
+        }
+        tm.mark();
+        return;
+    }
     const int ltop = std::min(cut - 2, lend - 1);      // last parent level of the side chain
     int lstart = 1;
     if (!tm.on && b.xitems.p == nullptr && b.total == sc.nbox && ltop >= 1) {
@@ -366,7 +426,10 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
         FMM_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     }
-    if (mixed) {
+    if (use_subtree(pl, ex)) {
+        if (mixed) run_up_subtree<float>(pl, m, s);
+        else run_up_subtree<double>(pl, m, s);
+    } else if (mixed) {
         run_p2m<float>(pl, ex, m, s);
         run_m2m<float>(pl, ex, pl.mpole.p, s);
     } else {
@@ -456,9 +519,16 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     tm.mark();
     const bool up = pl.upward_done && overlap;   // gather and upward pass enqueued by evaluate_upward
     pl.upward_done = false;
+    const bool sub = use_subtree(pl, ex);
     if (!up) {
-        if (mixed) run_p2m<float>(pl, ex, m, s);
-        else run_p2m<double>(pl, ex, m, s);
+        if (sub) {
+            if (mixed) run_up_subtree<float>(pl, m, s);
+            else run_up_subtree<double>(pl, m, s);
+        } else if (mixed) {
+            run_p2m<float>(pl, ex, m, s);
+        } else {
+            run_p2m<double>(pl, ex, m, s);
+        }
     }
     if (overlap) {
         // the near field starts after everything enqueued on `s` so far: the
@@ -470,7 +540,7 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
         run_p2p(pl, ex, pl.nstream, guard);
         FMM_HIP(hipEventRecord(pl.ev_join, pl.nstream));
     }
-    if (!up) {
+    if (!up && !sub) {
         if (mixed) run_m2m<float>(pl, ex, pl.mpole.p, s);
         else run_m2m<double>(pl, ex, pl.mpole.p, s);
     }
@@ -482,7 +552,11 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     if (overlap) FMM_HIP(hipStreamWaitEvent(s, pl.ev_join, 0));
     else run_p2p(pl, ex, s, nullptr);
     tm.mark();
-    if (mixed)
+    if (sub) {
+        auto down = mixed ? launch_down_subtree<float> : launch_down_subtree<double>;
+        down(sc.nprob, sc.L[0], sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.local.p, pl.p,
+             pl.near.p, t.perm.p, phi, phi_near, phi_far, guard, ex.binom.p, s);
+    } else if (mixed)
         launch_l2p<float>(ex.leaves.p, (int)sc.nleaf, sc.d_box_start.p, sc.d_box_count.p, ex.leaf_max, t.geom.p, t.x.p, t.y.p,
                           pl.local.p, pl.p, pl.near.p, t.perm.p, phi, phi_near, phi_far, s, guard,
                           ex.leaf_l2l_in_l2p ? sc.d_box_parent.p : nullptr, ex.binom.p);

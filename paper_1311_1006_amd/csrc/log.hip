@@ -42,9 +42,11 @@ constexpr InvK make_inv_k()
 }
 __constant__ InvK kInvK = make_inv_k();
 
-// c0 of every box from its weak list (zero without one): 32 lanes per box (a
-// weak list holds at most 27 entries), lane e takes pairs e, e + 32, ...; the
-// lanes' sums are added by a butterfly (a fixed order, so the result is
+// c0 of every box from its weak list (zero without one): 32 lanes per box,
+// lane e takes pairs e, e + 32, ... (on uniform inputs at theta = 0.5 most
+// lists are shorter than 64, so one or two passes; clustered inputs reach
+// lists of a few hundred entries, which take more passes of the same lanes);
+// the lanes' sums are added by a butterfly (a fixed order, so the result is
 // reproducible)
 template <class T>
 __global__ void __launch_bounds__(256)

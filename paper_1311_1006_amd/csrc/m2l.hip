@@ -367,28 +367,28 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
             ore[rb][j] = a;
             oim[rb][j] = b;
         }
-    // slot j (< 4) of an item writes element j of its rows (zeros for a box
-    // without weak pairs, so every box's local expansion is written)
+    // Every slot of an item holds the item's sums now.  Slot sl writes the
+    // elements j of its rows with j = sl (4 or more slots), or j = sl mod S
+    // (1 or 2 slots: a lane writes 4 or 2 of its rows).  A box without weak
+    // pairs gets zeros, so every box's local expansion is written.
     if (item_ok && sl < 4) {
 #pragma unroll
-        for (int rb = 0; rb < PB; ++rb) {
-            T vr = ore[rb][0], vi = oim[rb][0];
+        for (int rb = 0; rb < PB; ++rb)
 #pragma unroll
-            for (int j = 1; j < 4; ++j)
-                if (sl == j) { vr = ore[rb][j]; vi = oim[rb][j]; }
-            const int row = 16 * rb + r0 + (M::kRowsConsecutive ? sl : 4 * sl);
-            if (row < p) {
+            for (int j = 0; j < 4; ++j) {
+                if (S >= 4 ? j != sl : j % S != sl) continue;
+                const int row = 16 * rb + r0 + (M::kRowsConsecutive ? j : 4 * j);
+                if (row >= p) continue;
                 if (nch == 1) {
                     T* dst = loc + 2 * ((int64_t)g * p + row);
-                    dst[0] = vr;
-                    dst[1] = vi;
+                    dst[0] = ore[rb][j];
+                    dst[1] = oim[rb][j];
                 } else {                          // partial sum of a split list
                     double* dst = partial + 2 * ((int64_t)(ioff[xe.x] + xe.y) * p + row);
-                    dst[0] = (double)vr;
-                    dst[1] = (double)vi;
+                    dst[0] = (double)ore[rb][j];
+                    dst[1] = (double)oim[rb][j];
                 }
             }
-        }
     }
 }
 
@@ -444,11 +444,15 @@ void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const i
         if (slots == 16) m2l_one<T, 1, 1>(ARGS);
         else if (slots == 8) m2l_one<T, 1, 2>(ARGS);
         else if (slots == 4) m2l_one<T, 1, 4>(ARGS);
+        else if (slots == 2) m2l_one<T, 1, 8>(ARGS);
+        else if (slots == 1) m2l_one<T, 1, 16>(ARGS);
         else throw Error(FMM_EINVAL, "unsupported M2L batch");
     } else if (p <= 32) {
         if (slots == 16) m2l_one<T, 2, 1>(ARGS);
         else if (slots == 8) m2l_one<T, 2, 2>(ARGS);
         else if (slots == 4) m2l_one<T, 2, 4>(ARGS);
+        else if (slots == 2) m2l_one<T, 2, 8>(ARGS);
+        else if (slots == 1) m2l_one<T, 2, 16>(ARGS);
         else throw Error(FMM_EINVAL, "unsupported M2L batch");
     } else if (p <= 48) {          // three and four row blocks: one box per wavefront
         m2l_one<T, 3, 1>(ARGS);

@@ -13,7 +13,7 @@ import pytest
 
 from paper_1311_1006_amd import workloads as W
 
-from gpu_util import dev, e2, host, same_tree
+from gpu_util import dev, e2, einf, host, same_tree
 
 pytestmark = pytest.mark.gpu
 
@@ -101,17 +101,38 @@ def test_tree_many_tied_coordinates(orc, F):
     same_tree(orc, F, z, 5)
 
 
-@pytest.mark.parametrize("n,L,p", [(10000, 5, 17), (10007, 4, 12), (50000, 6, 16), (4096, 6, 20)])
-def test_fp64_fmm_matches_oracle_fmm(orc, F, n, L, p):
+@pytest.mark.parametrize("levelwise", [False, True])
+@pytest.mark.parametrize("n,L,p", [(10000, 5, 17), (10007, 4, 12), (50000, 6, 16), (4096, 6, 20), (3000, 3, 9),
+                                   (70000, 7, 30)])
+def test_fp64_fmm_matches_oracle_fmm(orc, F, n, L, p, levelwise):
+    # levelwise False: the far field by subtrees (P2M with two M2M levels,
+    # three-level M2M subtrees, L2P shifting every ancestor's M2L sum into the
+    # leaves); True: one launch per level of M2M and L2L
     z, m, _ = W.uniform(n, seed=n + 1)
     tree = F.build_tree(dev(z), L)
-    pl = F.plan(tree, p, 0.5, "fp64")
+    pl = F.plan(tree, p, 0.5, "fp64", levelwise=levelwise)
     phi = host(F.evaluate(pl, dev(m)))
     ref, rnear, rfar = orc.fmm(z, m, p, 0.5, L, parts=True)
     assert e2(phi, ref) <= 1e-12
     near, far = F.evaluate_parts(pl, dev(m))
     assert e2(host(near), rnear) <= 1e-12
     assert e2(host(far), rfar) <= 1e-12
+
+
+@pytest.mark.parametrize("n,L,p", [(20000, 5, 16), (60000, 7, 13), (30000, 6, 28)])
+def test_mixed_subtree_matches_levelwise(orc, F, n, L, p):
+    # the two forms of the far field in mixed precision: both within 1e-6 of
+    # the direct sum, and within 1e-6 of each other (e2 and e_inf)
+    z, m, _ = W.uniform(n, seed=n + 2)
+    tree = F.build_tree(dev(z), L)
+    md = dev(m)
+    a = host(F.evaluate(F.plan(tree, p, 0.5, "mixed"), md))
+    b = host(F.evaluate(F.plan(tree, p, 0.5, "mixed", levelwise=True), md))
+    ref = orc.direct(z, m)
+    for phi in (a, b):
+        assert e2(phi, ref) <= 1e-6
+        assert einf(phi, ref) <= 1e-6
+    assert e2(a, b) <= 1e-6 and einf(a, b) <= 1e-6
 
 
 @pytest.mark.parametrize("batch,p", [(4, 16), (8, 16), (16, 16), (8, 20), (16, 24)])
