@@ -53,8 +53,13 @@ def test_batch_of_many_problems_matches_single_problems(F, orc):
     pl = F.plan(tree, 16, 0.5, "mixed", graph=True)
     phi = host(F.evaluate(pl, dev(np.concatenate(ms))))
     for b in (0, 7, 21, 39):
-        one = host(F.evaluate(F.plan(F.build_tree(dev(zs[b]), Ls[b]), 16, 0.5, "mixed"), dev(ms[b])))
+        # problems of different depths run the far field level by level: a
+        # single problem run the same way gives the same bits; run by subtrees
+        # (the default for one problem) it differs by rounding only
+        tb = F.build_tree(dev(zs[b]), Ls[b])
+        one = host(F.evaluate(F.plan(tb, 16, 0.5, "mixed", levelwise=True), dev(ms[b])))
         np.testing.assert_array_equal(phi[off[b]:off[b + 1]], one)
+        assert e2(host(F.evaluate(F.plan(tb, 16, 0.5, "mixed"), dev(ms[b]))), one) <= 1e-6
         sub = W.subsample(len(zs[b]), 2000, seed=b)
         ref = orc.direct(zs[b], ms[b], sub)
         assert e2(one[sub], ref) <= 1e-6
@@ -105,7 +110,7 @@ def test_choose_order_rejects_bad_arguments(F):
     z, m, _ = W.uniform(1000, seed=1)
     tree = F.build_tree(dev(z), 3)
     md = dev(m)
-    for args in [(0.5, 1e-6, 0, 10), (0.5, 1e-6, 10, 9), (0.5, 1e-6, 4, 32), (1.0, 1e-6, 4, 10), (0.5, 0.0, 4, 10)]:
+    for args in [(0.5, 1e-6, 0, 10), (0.5, 1e-6, 10, 9), (0.5, 1e-6, 4, 49), (1.0, 1e-6, 4, 10), (0.5, 0.0, 4, 10)]:
         with pytest.raises(F.FmmError):
             F.choose_order(tree, md, *args)
 

@@ -207,7 +207,9 @@ def test_batch_equals_single_problems(orc, F):
     pl = F.plan(tree, 16, 0.5, "fp64")
     phi = host(F.evaluate(pl, dev(mc)))
     for b in range(len(zs)):
-        single = F.plan(F.build_tree(dev(zs[b]), Ls[b]), 16, 0.5, "fp64")
+        # problems of different depths: the far field level by level, as a
+        # single problem planned with levelwise=True
+        single = F.plan(F.build_tree(dev(zs[b]), Ls[b]), 16, 0.5, "fp64", levelwise=True)
         one = host(F.evaluate(single, dev(ms[b])))
         np.testing.assert_array_equal(phi[off[b]:off[b + 1]], one)
         assert e2(one, orc.fmm(zs[b], ms[b], 16, 0.5, Ls[b])) <= 1e-12
