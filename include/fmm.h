@@ -111,6 +111,7 @@ typedef struct {
     double t_upward_us, t_m2l_us, t_downward_us, t_p2p_us, t_total_us;
     double t_tree_us, t_plan_us;   /* last fmm_build_tree / fmm_plan device time, if timed */
     double t_l2l_us;
+    int64_t static_bytes;      /* working memory fmm_evaluate_static needs for this plan */
 } fmm_stats;
 
 /*
@@ -182,6 +183,29 @@ void fmm_plan_destroy(fmm_plan_t pl);
  * The plan keeps the local expansions of the last call for the adjoint.
  */
 int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream);
+
+/*
+ * fmm_evaluate_static -- fmm_evaluate for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same operator, same kernels and the same results as
+ * fmm_evaluate on the plan; the call itself allocates nothing.  The
+ * evaluation's working memory (strengths in tree order, near-field source
+ * records and sums, multipole and local coefficients, partial sums of split
+ * lists) is taken from a fixed device array of the library, 64 MiB per GPU,
+ * held from the first call on a GPU until the process ends.
+ *   m    DEVICE, complex [N] strengths, input order.
+ *   phi  DEVICE, complex [N] output, input order (overwritten).
+ * The plan's lists must be final: evaluate it once with fmm_evaluate, or
+ * call fmm_plan_stats, first (else FMM_ESTATE).  Must be called with the
+ * tree's device current (else FMM_EINVAL).  A plan whose evaluation needs
+ * more than 64 MiB (fmm_stats.static_bytes; about 75 B per point plus
+ * 2 p x 8 B (mixed) or 2 p x 16 B (FP64) per box) is refused with
+ * FMM_EINVAL.  The plan's own buffers and the state the adjoint reads are
+ * left as they were.  All calls on one GPU share its array: calls that
+ * overlap in time on one GPU (other streams, other threads) race.
+ * Errors: FMM_EINVAL, FMM_ESTATE, FMM_EDEVICE.
+ */
+int fmm_evaluate_static(fmm_plan_t pl, const double* m, double* phi, void* stream);
 
 /*
  * fmm_evaluate_parts -- same operator, near field (P2P) and far field

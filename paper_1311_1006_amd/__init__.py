@@ -45,7 +45,7 @@ class _Stats(C.Structure):
                 ("theta", C.c_double),
                 ("t_upward_us", C.c_double), ("t_m2l_us", C.c_double), ("t_downward_us", C.c_double),
                 ("t_p2p_us", C.c_double), ("t_total_us", C.c_double), ("t_tree_us", C.c_double),
-                ("t_plan_us", C.c_double), ("t_l2l_us", C.c_double)]
+                ("t_plan_us", C.c_double), ("t_l2l_us", C.c_double), ("static_bytes", C.c_int64)]
 
 
 class _TunerParams(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         "fmm_plan_destroy": (None, [vp]),
         "fmm_evaluate": (C.c_int, [vp, vp, vp, vp]),
         "fmm_evaluate_parts": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fmm_evaluate_static": (C.c_int, [vp, vp, vp, vp]),
         "fmm_evaluate_adjoint": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "fmm_plan_stats": (C.c_int, [vp, C.POINTER(_Stats)]),
         "fmm_tree_layout": (C.c_int, [vp, C.c_int, ip, i64p, i64p]),
@@ -252,6 +253,19 @@ def evaluate(pl, m, out=None, stream=None):
     if out is None:
         out = torch.empty_like(m)
     _check(lib().fmm_evaluate(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def evaluate_static(pl, m, out, stream=None):
+    """fmm_evaluate_static: phi = FMM(m) into the caller's `out`, the
+    evaluation's working memory taken from the library's fixed device array
+    (the call allocates nothing).  The plan's lists must be final (one
+    evaluate() or stats() first)."""
+    m = _dev_complex(m, "m")
+    if not out.is_contiguous():
+        raise TypeError("out must be contiguous")
+    out = _dev_complex(out, "out")
+    _check(lib().fmm_evaluate_static(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 

@@ -500,6 +500,17 @@ int fmm_evaluate(fmm_plan_t pl, const double* m, double* phi, void* stream)
     });
 }
 
+int fmm_evaluate_static(fmm_plan_t pl, const double* m, double* phi, void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m && phi, "NULL argument");
+        check_device_state();
+        hipStream_t s = (hipStream_t)stream;
+        plan_join(pl->pl, s);
+        evaluate_static(pl->pl, m, phi, s);
+    });
+}
+
 int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double* phi_far, void* stream)
 {
     return guarded([&] {
@@ -583,6 +594,7 @@ int fmm_plan_stats(fmm_plan_t pl, fmm_stats* st)
         st->t_total_us = P.t_total;
         st->t_tree_us = P.tree->t_build_us;
         st->t_plan_us = P.t_plan_us;
+        st->static_bytes = (int64_t)static_eval_bytes(P);
     });
 }
 

@@ -277,6 +277,10 @@ void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
+// fmm_evaluate_static: the evaluation with its working buffers in the fixed
+// device array of static_eval.hip, and the bytes of that array it needs
+void evaluate_static(Plan& pl, const double* m, double* phi, hipStream_t s);
+size_t static_eval_bytes(Plan& pl);
 // the logarithmic potential u (real, input order) of real strengths q; mlog
 // (2 N doubles: q as complex numbers in input order) and c0 (one double per
 // box: the constant terms) are the plan's own buffers when mlog is NULL

@@ -18,6 +18,8 @@ void evaluate_device(Plan&, const double*, double*, double*, double*, hipStream_
     no_device();
 }
 void evaluate_upward(Plan&, const double*, hipStream_t) { no_device(); }
+void evaluate_static(Plan&, const double*, double*, hipStream_t) { no_device(); }
+size_t static_eval_bytes(Plan&) { no_device(); }
 double rel_err2_device(const double*, const double*, int64_t, hipStream_t) { no_device(); }
 void upload_schedule(TreeSchedule&, hipStream_t) { no_device(); }
 void build_lists_begin(Plan&, hipStream_t, hipStream_t) { no_device(); }
