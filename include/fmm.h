@@ -55,7 +55,10 @@ enum fmm_status {
 enum fmm_precision {
     FMM_FP64 = 0,   /* every step in FP64 */
     FMM_MIXED = 1   /* P2P and M2L in FP32 (FP32 accumulation); FP64 box geometry,
-                       theta-tests, position differences and rescaling powers */
+                       theta-tests and position differences (P2P: double-float
+                       differences; M2L: the centre difference in FP64, then 1/d
+                       and the rescaling powers of r_S/d and -r_T/d in FP32);
+                       expansions stored in FP32 */
 };
 
 /* Flags of fmm_tuning.flags */

@@ -7,7 +7,7 @@ import pytest
 
 from paper_1311_1006_amd import workloads as W
 
-from gpu_util import dev, e2, host
+from gpu_util import dev, e2, einf, host
 
 pytestmark = pytest.mark.gpu
 
@@ -49,12 +49,15 @@ def test_adjoint_matches_direct_gradient(orc, F, prec):
     g = 2 * phi                              # L = sum |phi|^2
     gm, gz = F.evaluate_adjoint(pl, dev(m), g)
     rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))
-    tol = 1e-6 if prec == "fp64" else 1e-5
-    assert e2(host(gm), rgm) <= tol
-    assert e2(host(gz), rgz) <= tol
+    # measured (N = 2000, p = 16): FP64 2e-9 / 7e-11, mixed 1.2e-7 / 1.6e-7
+    # (the mixed error is that of the FP32 forward phi fed in as the cotangent
+    # plus the adjoint's own FP32 sums, each ~1e-7)
+    tol = 1e-6
+    assert e2(host(gm), rgm) <= tol and einf(host(gm), rgm) <= tol
+    assert e2(host(gz), rgz) <= tol and einf(host(gz), rgz) <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
 def test_adjoint_with_split_source_lists(orc, F, prec, tol):
     # one leaf of 5000 points: the adjoint near field is summed in source
     # chunks and combined; at one level the FMM is the direct sum

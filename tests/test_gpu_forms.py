@@ -6,7 +6,7 @@ import pytest
 
 from paper_1311_1006_amd import workloads as W
 
-from gpu_util import dev, e2, host
+from gpu_util import dev, e2, einf, host
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_batch_of_many_problems_matches_single_problems(F, orc):
         assert e2(host(F.evaluate(F.plan(tb, 16, 0.5, "mixed"), dev(ms[b]))), one) <= 1e-6
         sub = W.subsample(len(zs[b]), 2000, seed=b)
         ref = orc.direct(zs[b], ms[b], sub)
-        assert e2(one[sub], ref) <= 1e-6
+        assert e2(one[sub], ref) <= 1e-6 and einf(one[sub], ref) <= 1e-6
 
 
 def test_timestepping_with_tuner(F, orc):
@@ -77,7 +77,8 @@ def test_timestepping_with_tuner(F, orc):
         if step in (0, 7):
             zh = host(zt)
             sub = W.subsample(zh.size, 1000, seed=step)
-            errs[step] = e2(host(phi)[sub], orc.direct(zh, m, sub))
+            ref = orc.direct(zh, m, sub)
+            errs[step] = max(e2(host(phi)[sub], ref), einf(host(phi)[sub], ref))
 
     zf, hist = advect(dev(z), dev(m), 8, 1e-4, p=16, theta=0.5, precision="mixed", tuner=tu, callback=check)
     assert errs[0] <= 1e-6 and errs[7] <= 1e-6

@@ -143,7 +143,8 @@ def test_m2l_batch_shapes_match_oracle(orc, F, batch, p):
     pl = F.plan(tree, p, 0.5, "fp64", m2l_batch=batch)
     assert e2(host(F.evaluate(pl, dev(m))), orc.fmm(z, m, p, 0.5, 6)) <= 1e-12
     plm = F.plan(tree, p, 0.5, "mixed", m2l_batch=batch)
-    assert e2(host(F.evaluate(plm, dev(m))), orc.direct(z, m)) <= 1e-6
+    phim, ref = host(F.evaluate(plm, dev(m))), orc.direct(z, m)
+    assert e2(phim, ref) <= 1e-6 and einf(phim, ref) <= 1e-6
 
 
 def test_fp64_fmm_clustered_matches_oracle(orc, F):
@@ -183,17 +184,19 @@ def test_mixed_within_1e6_of_direct(orc, F, n, L, p):
     z, m, _ = W.uniform(n, seed=n + 2)
     pl = F.plan(F.build_tree(dev(z), L), p, 0.5, "mixed")
     phi = host(F.evaluate(pl, dev(m)))
-    assert e2(phi, orc.direct(z, m)) <= 1e-6
+    ref = orc.direct(z, m)
+    assert e2(phi, ref) <= 1e-6 and einf(phi, ref) <= 1e-6
 
 
 def test_coincident_points_are_excluded(orc, F):
     z, m, _ = W.uniform(3000, seed=6)
     z[100:110] = z[5]            # ten duplicates of one position
-    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-6)):
         pl = F.plan(F.build_tree(dev(z), 4), 14, 0.5, prec)
         phi = host(F.evaluate(pl, dev(m)))
         assert np.all(np.isfinite(phi))
-        assert e2(phi, orc.fmm(z, m, 14, 0.5, 4)) <= tol
+        ref = orc.fmm(z, m, 14, 0.5, 4)
+        assert e2(phi, ref) <= tol and einf(phi, ref) <= tol
 
 
 def test_batch_equals_single_problems(orc, F):

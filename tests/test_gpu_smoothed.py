@@ -8,7 +8,7 @@ import pytest
 
 from paper_1311_1006_amd import workloads as W
 
-from gpu_util import dev, e2, host
+from gpu_util import dev, e2, einf, host
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def test_smoothed_field_matches_direct_sum(F, orc, n, L):
     ref = orc.direct_smoothed(z, m, delta, targets=sub)
     for prec, p, bar in (("fp64", 30, 1e-12), ("mixed", 16, 1e-6)):
         phi = F.evaluate(F.plan(tree, p, 0.5, prec, smooth_delta=delta), dev(m))
-        assert e2(host(phi)[sub], ref) <= bar, prec
+        assert e2(host(phi)[sub], ref) <= bar and einf(host(phi)[sub], ref) <= bar, prec
     # the smoothing matters at this delta: the unsmoothed field differs
     plain = F.evaluate(F.plan(tree, 30, 0.5, "fp64"), dev(m))
     assert e2(host(plain)[sub], ref) > 1e-6
@@ -74,7 +74,8 @@ def test_kelvin_helmholtz_steps(F, orc):
         if step in (0, 5):
             zh = host(zt)
             sub = np.arange(0, zh.size, 13)
-            errs[step] = e2(host(phi)[sub], orc.direct_smoothed(zh, m, delta, targets=sub))
+            ref = orc.direct_smoothed(zh, m, delta, targets=sub)
+            errs[step] = max(e2(host(phi)[sub], ref), einf(host(phi)[sub], ref))
 
     zf, hist = advect(dev(z), dev(m), 6, 1e-3, p=16, precision="mixed", tuner=tu, callback=check,
                       smooth_delta=delta)
