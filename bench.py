@@ -147,6 +147,116 @@ def measure_timestepping(F, W, torch, dev, with_errors, steps=50, dt=1e-4, tune_
     return res
 
 
+def measure_clustered_breakdown(F, W, torch, dev, steps=30, dt=1e-4):
+    """Where the time of a clustered step goes: the clustered N = 1e6 set
+    advanced `steps` Euler steps with the tuner (as in the time-stepping
+    form), then the late positions and the start positions evaluated at the
+    tuner's best knobs and N_levels best - 1 .. best + 1: tree, plan (list
+    build; the call waits for the list totals), evaluate, and the phases of a
+    phase-timing plan; the list sizes; the spread of the leaf radii."""
+    from paper_1311_1006_amd.driver import advect, make_tuner
+    z, m = W.clustered(1_000_000, seed=0)
+    zd = torch.from_numpy(z).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    tu = make_tuner(z.size, cap=0.1, window=3, knob_interval=6)
+    zf, hist = advect(zd, md, steps, dt, p=16, theta=0.5, precision="mixed", tuner=tu)
+    prm = tu.best()[0]
+    knobs = dict(p2p_split=prm["p2p_split"], m2l_batch=prm["m2l_batch"])
+    out = torch.empty_like(md)
+
+    def ev(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        r = fn()
+        e1.record()
+        e1.synchronize()
+        return r, e0.elapsed_time(e1) * 1e3
+
+    res = {"steps": steps, "tuned": prm, "step_ms": [round(sec * 1e3, 3) for _, sec in hist]}
+    for label, zz in (("late", zf), ("start", zd)):
+        for L in (prm["n_levels"] - 1, prm["n_levels"], prm["n_levels"] + 1):
+            for _ in range(2):
+                F.evaluate(F.plan(F.build_tree(zz, L), 16, 0.5, "mixed", **knobs), md, out)
+            tr, t_tree = ev(lambda: F.build_tree(zz, L))
+            pl, t_plan = ev(lambda: F.plan(tr, 16, 0.5, "mixed", **knobs))
+            st = pl.stats()
+            _, t_eval = ev(lambda: F.evaluate(pl, md, out))
+            pt = F.plan(tr, 16, 0.5, "mixed", timing=True, **knobs)
+            for _ in range(2):
+                F.evaluate(pt, md, out)
+            torch.cuda.synchronize()
+            sp = pt.stats()
+            _, t_step = ev(lambda: F.evaluate(F.plan(F.build_tree(zz, L), 16, 0.5, "mixed", **knobs), md, out))
+            geom = tr.download(0)[2]
+            r = geom[-(4 ** (L - 1)):, 6]
+            rec = {"step_us": t_step, "tree_us": t_tree, "plan_us": t_plan, "evaluate_us": t_eval,
+                   "phases_us": {k: sp["t_" + k + "_us"] for k in ("upward", "m2l", "l2l", "p2p", "downward")},
+                   "n_p2p_pairs": st["n_p2p_pairs"], "n_m2l_pairs": st["n_m2l_pairs"],
+                   "p2p_pairs_per_s": st["n_p2p_pairs"] / (sp["t_p2p_us"] * 1e-6),
+                   "leaf_radius_quantiles_50_90_99_max": [float(v) for v in np.quantile(r, [0.5, 0.9, 0.99, 1.0])]}
+            res["%s_L%d" % (label, L)] = rec
+            log("clustered %s step, N_levels %d: %.0f us = tree %.0f + plan %.0f + evaluate %.0f (P2P %.0f, M2L %.0f), "
+                "%.3g P2P pairs, median leaf radius %.2e" % (label, L, t_step, t_tree, t_plan, t_eval, sp["t_p2p_us"],
+                                                            sp["t_m2l_us"], st["n_p2p_pairs"], rec["leaf_radius_quantiles_50_90_99_max"][0]))
+            del pl, pt, tr
+    return {"timestep_clustered_breakdown": res}
+
+
+def measure_kh_tuners(F, W, torch, dev, steps=300, dt=1e-4, tol=1e-6):
+    """Table 5.1's comparison (Sec. 5.1): the vortex sheet (Kelvin-Helmholtz
+    start, Gaussian smoother, mixed precision) run from the same start with
+    no tuning, AT1, AT2 and AT3b (AT3a balances CPU and GPU work and has no
+    counterpart on one GPU), for a small (N = 16,000) and a large (N = 1.5e6)
+    problem.  The large run starts one level below the level a short sweep
+    finds fastest (the paper starts it one below optimal), the small one at
+    that level.  The tuners walk N_levels and theta, p following theta by
+    Table 4.1's rule for tol (the untuned run keeps theta = 0.5 and that p);
+    AT3b also walks the launch-shape knobs.  Reports the total device time of
+    the run, its speedup over the untuned run and the N_levels/theta traces."""
+    from paper_1311_1006_amd.driver import advect, default_levels
+    out = {}
+    p0 = F.p_from_tol(tol, 0.5)
+    for name, n, below in (("small_n16000", 16000, 0), ("large_n1p5e6", 1_500_000, 1)):
+        z, m, sp = W.kelvin_helmholtz(n, seed=0)
+        delta = sp / 2
+        zd = torch.from_numpy(z).to(dev)
+        md = torch.from_numpy(m).to(dev)
+        ob = torch.empty_like(md)
+        Ld = default_levels(z.size)
+        sweep = {}
+        for L in range(max(1, Ld - 1), min(Ld + 1, default_levels(z.size, per_leaf=1)) + 1):
+            sweep[L] = _time(lambda: F.evaluate(F.plan(F.build_tree(zd, L), p0, 0.5, "mixed", smooth_delta=delta),
+                                                md, ob), 5, torch)
+        Lbest = min(sweep, key=sweep.get)
+        L0 = max(1, Lbest - below)
+        runs = {}
+        for scheme in ("none", "at1", "at2", "at3b"):
+            tu = None
+            if scheme != "none":
+                tu = F.Tuner(n_levels=L0, min_levels=max(1, L0 - 3), max_levels=default_levels(z.size, per_leaf=1),
+                             p2p_split=4, m2l_batch=8, algorithm=scheme, cap=0.1, window=3, knob_interval=6,
+                             level_interval=6, theta=0.5, theta_interval=4, theta_min=0.35, theta_max=0.65,
+                             tol=tol, seed=1)
+            zf, hist = advect(zd, md, steps, dt, p=p0, theta=0.5, precision="mixed", tuner=tu, n_levels=L0,
+                              smooth_delta=delta)
+            times = [sec for _, sec in hist]
+            runs[scheme] = {"total_ms": 1e3 * float(np.sum(times)), "median_step_ms": 1e3 * float(np.median(times)),
+                            "median_step_ms_second_half": 1e3 * float(np.median(times[len(times) // 2:])),
+                            "levels": [int(h["n_levels"]) for h, _ in hist],
+                            "theta": [round(float(h.get("theta", 0.5)), 2) for h, _ in hist]}
+            del zf
+        for r in runs.values():
+            r["speedup_vs_none"] = runs["none"]["total_ms"] / r["total_ms"]
+        out["kh_tuner_comparison_" + name] = {"n": int(z.size), "steps": steps, "tol": tol,
+                                              "sweep_ms": {str(k): v * 1e3 for k, v in sweep.items()},
+                                              "start_levels": L0, "runs": runs}
+        log("KH tuner comparison %s (start N_levels %d): %s" % (name, L0, ", ".join(
+            "%s %.1f ms (x%.2f)" % (k, r["total_ms"], r["speedup_vs_none"]) for k, r in runs.items())))
+    return out
+
+
 def measure_kh(F, W, torch, dev, reps, with_errors, steps=20, dt=1e-4):
     """The vortex sheet of Sec. 5.1 (Kelvin-Helmholtz start, about 1.5e6
     vortices, Gaussian smoother with delta = half the grid spacing): Euler
@@ -188,10 +298,11 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
     """(2) 128 problems of uneven size in one graph launch vs 128 sequential
     plain launches (same trees, levels, p, shapes); clustered time stepping
     with the tuner; (3) adjoint / forward time at N = 2e5, p = 16."""
-    from paper_1311_1006_amd.driver import default_levels
+    from paper_1311_1006_amd.driver import batch_levels, default_levels, tune_batch
     out = {}
     zs, ms, kinds = W.batch(nprob=128, seed=0)
-    Ls = [default_levels(len(z)) for z in zs]
+    sizes = [len(z) for z in zs]
+    Ls = batch_levels(sizes)
     off = [0]
     for z in zs:
         off.append(off[-1] + len(z))
@@ -208,14 +319,35 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
             tr = F.build_tree(zb, Ls[b])
             singles.append((tr, F.plan(tr, 16, 0.5, prec), mc[off[b]:off[b + 1]], oc[off[b]:off[b + 1]]))
         ts = _time(lambda: [F.evaluate(pl, mb, ob) for _, pl, mb, ob in singles], max(2, reps // 4), torch)
-        out["batch128_" + prec] = {"n_total": off[-1], "graph_ms": tb * 1e3, "sequential_ms": ts * 1e3,
-                                   "speedup": ts / tb, "mpoints_s": off[-1] / tb / 1e6}
-        log("batch of 128 (%s): graph %.3f ms, 128 sequential launches %.3f ms" % (prec, tb * 1e3, ts * 1e3))
         del singles, pg, tree
+        # the same batch autotuned (AT3b over a common level offset and the
+        # launch-shape knobs), then its best configuration timed like the default
+        t0 = time.perf_counter()
+        best, hist = tune_batch(zc, mc, off, 16, 0.5, prec, iterations=60, out=oc)
+        t_tune = time.perf_counter() - t0
+        tt = F.build_tree(zc, best["levels"], offsets=off)
+        pt = F.plan(tt, 16, 0.5, prec, p2p_split=best["p2p_split"], m2l_batch=best["m2l_batch"], graph=True)
+        tg = _time(lambda: F.evaluate(pt, mc, oc), reps, torch)
+        del pt, tt
+        out["batch128_" + prec] = {
+            "n_total": off[-1], "graph_ms": tb * 1e3, "sequential_ms": ts * 1e3, "speedup": ts / tb,
+            "mpoints_s": off[-1] / tb / 1e6,
+            "default": {"levels": "about 16 points per leaf", "p2p_split": 0, "m2l_batch": 0},
+            "tuned_graph_ms": tg * 1e3, "tuned_mpoints_s": off[-1] / tg / 1e6, "tuned_vs_default": tb / tg,
+            "tuned": {"level_offset": best["level_offset"], "p2p_split": best["p2p_split"],
+                      "m2l_batch": best["m2l_batch"]},
+            "tuning": {"iterations": len(hist), "wall_s": t_tune,
+                       "trace": [[h["level_offset"], h["p2p_split"], h["m2l_batch"], round(sec * 1e3, 4)]
+                                 for h, sec in hist]}}
+        log("batch of 128 (%s): graph %.3f ms (default), %.3f ms (autotuned: level offset %+d, split %d, "
+            "batch %d), 128 sequential launches %.3f ms" % (prec, tb * 1e3, tg * 1e3, best["level_offset"],
+                                                           best["p2p_split"], best["m2l_batch"], ts * 1e3))
     out.update(measure_timestepping(F, W, torch, dev, with_errors))
     out.update(measure_timestepping(F, W, torch, dev, with_errors, tune_theta=True))
     out.update(measure_theta(F, W, torch, dev, max(3, reps // 4)))
     out.update(measure_kh(F, W, torch, dev, max(3, reps // 4), with_errors))
+    out.update(measure_kh_tuners(F, W, torch, dev))
+    out.update(measure_clustered_breakdown(F, W, torch, dev))
     # field and its derivative (fmm_evaluate_field) against the plain evaluation
     z, m, _ = W.uniform(1_000_000, seed=0)
     zd = torch.from_numpy(z).to(dev)
@@ -273,6 +405,8 @@ def main():
     ap.add_argument("--levels", type=str, default="8,9,10")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-forms", action="store_true", help="skip the batch and adjoint measurements")
+    ap.add_argument("--clustered-breakdown", action="store_true",
+                    help="only the per-phase breakdown of the clustered time step (for kernel traces); no JSON")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="for hardware-counter runs: warmup + steps mixed-precision steps at the first "
                          "--levels value, then a 256 MiB device copy (counter calibration); no JSON")
@@ -334,6 +468,9 @@ def main():
         return (time.perf_counter() - t0) / k
 
     levels = [int(x) for x in args.levels.split(",") if 4 ** (int(x) - 1) <= n]
+    if args.clustered_breakdown:
+        measure_clustered_breakdown(F, W, torch, dev)
+        return
     if args.pmc_workload:
         for _ in range(args.warmup + args.steps):
             step("mixed", (levels[0], 0, 0))

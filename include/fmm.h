@@ -337,7 +337,9 @@ typedef struct fmm_tuner_s* fmm_tuner_t;
 enum { FMM_TUNER_AT3B = 0, FMM_TUNER_AT2 = 1, FMM_TUNER_AT1 = 2 };
 
 typedef struct {
-    int n_levels, p2p_split, m2l_batch;
+    int n_levels;
+    int p2p_split;              /* walked over 1, 2, 4 (AT3b) */
+    int m2l_batch;              /* walked over 1, 2, 4, 8, 16 (AT3b) */
     int p;                      /* expansion order for theta (see tol) */
     double theta;
 } fmm_tuner_params;

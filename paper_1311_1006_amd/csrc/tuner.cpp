@@ -29,6 +29,7 @@
 // pure performance knob (Sec. 2.3).
 #include <algorithm>
 #include <cmath>
+#include <iterator>
 #include <limits>
 #include <memory>
 #include <string>
@@ -39,7 +40,7 @@
 namespace {
 
 const int kSplits[] = {1, 2, 4};
-const int kBatches[] = {4, 8, 16};
+const int kBatches[] = {1, 2, 4, 8, 16};
 
 template <size_t N>
 int index_of(const int (&v)[N], int x)
@@ -249,11 +250,11 @@ static bool try_knobs(fmm_tuner_s& t, double i)
     for (int tries = 0; tries < 2 && t.pending == kNone; ++tries) {
         if ((t.knob_turn++ & 1) == 0) {
             int k = index_of(kSplits, t.cur.p2p_split) + t.split_dir;
-            if (k >= 0 && k < 3) { t.cur.p2p_split = kSplits[k]; t.pending = kSplit; }
+            if (k >= 0 && k < (int)std::size(kSplits)) { t.cur.p2p_split = kSplits[k]; t.pending = kSplit; }
             else t.split_dir = -t.split_dir;
         } else {
             int k = index_of(kBatches, t.cur.m2l_batch) + t.batch_dir;
-            if (k >= 0 && k < 3) { t.cur.m2l_batch = kBatches[k]; t.pending = kBatch; }
+            if (k >= 0 && k < (int)std::size(kBatches)) { t.cur.m2l_batch = kBatches[k]; t.pending = kBatch; }
             else t.batch_dir = -t.batch_dir;
         }
     }

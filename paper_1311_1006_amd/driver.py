@@ -58,6 +58,57 @@ def advect(z, m, steps, dt, p=16, theta=0.5, precision="mixed", tuner=None, n_le
     return z, hist
 
 
+def batch_levels(sizes, offset=0, per_leaf=16):
+    """Per-problem N_levels of a batch: about per_leaf points per leaf, all
+    moved by a common offset, each kept within 1 .. one point per leaf."""
+    return [max(1, min(default_levels(n, per_leaf) + offset, default_levels(n, per_leaf=1))) for n in sizes]
+
+
+def tune_batch(z, m, offsets, p, theta, precision, iterations=60, out=None, **kw):
+    """Online autotuning of one batch of problems (CSR offsets, one tree) for
+    repeated graph launches: the AT3b walk (Sec. 4.2, Algorithm 4) over a
+    level offset shared by every problem (batch_levels; the tuner's N_levels
+    3 is offset 0, its range 1 .. 5 offsets -2 .. +2) and the two launch-shape
+    knobs (P2P split, M2L pair slots).  Every iteration replays the graph of
+    the proposed configuration once (trees and plans are kept per
+    configuration; a plan's first call captures its graph and is not timed)
+    and reports the replay's device time.  Returns (best parameters with the
+    level offset and the per-problem levels, per-iteration (parameters,
+    seconds))."""
+    import torch
+    sizes = [int(offsets[b + 1] - offsets[b]) for b in range(len(offsets) - 1)]
+    if out is None:
+        out = torch.empty_like(m)
+    kw.setdefault("window", 2)
+    kw.setdefault("knob_interval", 4)
+    tu = Tuner(n_levels=3, min_levels=1, max_levels=5, p2p_split=4,
+               m2l_batch=8 if precision == "mixed" else 4, **kw)
+    trees, plans, hist = {}, {}, []
+    for _ in range(iterations):
+        prm = tu.next()
+        off = prm["n_levels"] - 3
+        Ls = tuple(batch_levels(sizes, off))
+        if Ls not in trees:
+            trees[Ls] = build_tree(z, list(Ls), offsets=list(offsets))
+        key = (Ls, prm["p2p_split"], prm["m2l_batch"])
+        if key not in plans:
+            plans[key] = plan(trees[Ls], p, theta, precision, p2p_split=prm["p2p_split"],
+                              m2l_batch=prm["m2l_batch"], graph=True)
+            evaluate(plans[key], m, out)             # captures the graph
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        evaluate(plans[key], m, out)
+        e1.record()
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        tu.observe(sec)
+        hist.append((dict(prm, level_offset=off), sec))
+    best = tu.best()[0]
+    off = best["n_levels"] - 3
+    return dict(best, level_offset=off, levels=batch_levels(sizes, off)), hist
+
+
 def make_tuner(n, **kw):
     """An AT3b-style tuner started at about 16 points per leaf."""
     L = default_levels(n)

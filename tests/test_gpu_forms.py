@@ -65,6 +65,33 @@ def test_batch_of_many_problems_matches_single_problems(F, orc):
         assert e2(one[sub], ref) <= 1e-6 and einf(one[sub], ref) <= 1e-6
 
 
+def test_tuned_batch_matches_single_problems(F, orc):
+    # the batch autotuner (level offset, P2P split, M2L slots) and its best
+    # configuration: every problem equals its own evaluation with the same
+    # levels and knobs, and stays within the mixed bar of the direct sum
+    from paper_1311_1006_amd.driver import batch_levels, tune_batch
+    zs, ms, _ = W.batch(nprob=16, seed=9, nmin=1000, nmax=20000)
+    sizes = [len(z) for z in zs]
+    off = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+    zc, mc = dev(np.concatenate(zs)), dev(np.concatenate(ms))
+    best, hist = tune_batch(zc, mc, off, 16, 0.5, "mixed", iterations=16)
+    assert len(hist) == 16 and all(sec > 0 for _, sec in hist)
+    assert -2 <= best["level_offset"] <= 2
+    assert best["levels"] == batch_levels(sizes, best["level_offset"])
+    knobs = dict(p2p_split=best["p2p_split"], m2l_batch=best["m2l_batch"])
+    tree = F.build_tree(zc, best["levels"], offsets=off)
+    phi = host(F.evaluate(F.plan(tree, 16, 0.5, "mixed", graph=True, **knobs), mc))
+    # problems of one depth run the far field by subtrees, else level by level
+    levelwise = len(set(best["levels"])) > 1
+    for b in (0, 5, 15):
+        tb = F.build_tree(dev(zs[b]), best["levels"][b])
+        one = host(F.evaluate(F.plan(tb, 16, 0.5, "mixed", levelwise=levelwise, **knobs), dev(ms[b])))
+        np.testing.assert_array_equal(phi[off[b]:off[b + 1]], one)
+        sub = W.subsample(sizes[b], 1000, seed=b)
+        ref = orc.direct(zs[b], ms[b], sub)
+        assert e2(one[sub], ref) <= 1e-6 and einf(one[sub], ref) <= 1e-6
+
+
 def test_timestepping_with_tuner(F, orc):
     # a smaller copy of the clustered, dynamically re-tuned workload
     import torch
