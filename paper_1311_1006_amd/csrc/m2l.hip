@@ -20,9 +20,11 @@
 // in FP64, the powers in FP32 (their rounding stays below that of the FP32
 // coefficients they multiply).
 // The blocks go in groups of four: each lane computes the geometry of one
-// pair of the group (centre difference, 1/d and the powers of u and w) once
-// and shares it through the wavefront's LDS with the other three lanes of
-// that pair's column; no workgroup barriers.  Source centres are loaded a
+// pair of the group once (centre difference, 1/d, the powers of u and w) and
+// shares it through the wavefront's LDS with the other three lanes of that
+// pair's column, including the starting power u^kq and the first row factor
+// of each of the four lanes, so that a lane reads its own instead of
+// selecting them; no workgroup barriers.  Source centres are loaded a
 // group ahead, coefficients a block ahead.  At the end the 16 pair slots
 // are summed by a butterfly.
 // FP32 path: v_mfma_f32_16x16x4f32 (output rows 4 kq + j), FP32 accumulation.
@@ -60,35 +62,18 @@ template <> struct Mfma<double> {
     static constexpr bool kRowsConsecutive = false;
 };
 
-__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
-{
-    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
-}
-
-__device__ __forceinline__ float2 csel(bool c, float2 a, float2 b)
-{
-    return make_float2(c ? a.x : b.x, c ? a.y : b.y);
-}
-
-// z^e for e in 0..3 from z and z^2 (e differs between lanes): one product of
-// two selected factors, so that no lane-indexed table is needed
-template <class C2>
-__device__ __forceinline__ C2 cpow_lane(C2 z, C2 z2, int e)
-{
-    C2 one;
-    one.x = 1;
-    one.y = 0;
-    return cmul(csel(e & 1, z, one), csel(e & 2, z2, one));
-}
-
 // The geometry of one pair, computed once by one lane and shared through
-// LDS with the four lanes that feed the pair's MFMA column: 1/d, u = rs_S/d
-// and its square and fourth power, w = -rs_T/d and its powers 2, 4, 8.
+// LDS with the four lanes (kq = 0..3) that feed the pair's MFMA column, with
+// u = rs_S/d and w = -rs_T/d: up[kq] = u^kq (the first power lane kq
+// scales), u4 = u^4 (its step), f0[kq] = (1/d) w^r0 (the factor of lane
+// kq's first output row r0: 4 kq for FP32, kq for FP64) and ws, the factor
+// between its consecutive rows (w for FP32, w^4 for FP64).
 template <class T>
 struct PairGeo {
     using T2 = typename Vec2<T>::type;
-    T2 id, u, u2, u4, wv, w2, w4, w8;
+    T2 up[4], f0[4], u4, ws;
 };
+constexpr int kGeoFields = 10;   // up[0..3], f0[0..3], u4, ws
 
 // Loads that stay where they are written: relaxed atomic loads of wavefront
 // scope are plain loads for the hardware, but the compiler neither sinks them
@@ -158,15 +143,22 @@ __device__ __forceinline__ PairGeo<float> make_geo(float, double ctx, double cty
     PairGeo<float> g;
     const float dx = (float)(ctx - sx), dy = (float)(cty - sy);
     const float den = valid ? __builtin_amdgcn_rcpf(dx * dx + dy * dy) : 0.f;
-    g.id = make_float2(dx * den, -dy * den);
+    const float2 id = make_float2(dx * den, -dy * den);
     const float rs = (float)rs_s, rt = (float)rsT;
-    g.u = make_float2(rs * g.id.x, rs * g.id.y);
-    g.wv = make_float2(-rt * g.id.x, -rt * g.id.y);
-    g.u2 = cmul(g.u, g.u);
-    g.u4 = cmul(g.u2, g.u2);
-    g.w2 = cmul(g.wv, g.wv);
-    g.w4 = cmul(g.w2, g.w2);
-    g.w8 = cmul(g.w4, g.w4);
+    const float2 u = make_float2(rs * id.x, rs * id.y);
+    const float2 w = make_float2(-rt * id.x, -rt * id.y);
+    const float2 u2 = cmul(u, u);
+    g.up[0] = make_float2(1.f, 0.f);
+    g.up[1] = u;
+    g.up[2] = u2;
+    g.up[3] = cmul(u2, u);
+    g.u4 = cmul(u2, u2);
+    const float2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+    g.f0[0] = id;                       // rows 4 kq + j: f0 = (1/d) w^(4 kq)
+    g.f0[1] = cmul(id, w4);
+    g.f0[2] = cmul(id, w8);
+    g.f0[3] = cmul(g.f0[1], w8);
+    g.ws = w;
     return g;
 }
 __device__ __forceinline__ PairGeo<double> make_geo(double, double ctx, double cty, double rsT, double sx, double sy,
@@ -175,14 +167,21 @@ __device__ __forceinline__ PairGeo<double> make_geo(double, double ctx, double c
     PairGeo<double> g;
     const double dx = ctx - sx, dy = cty - sy;
     const double den = valid ? rcp_nr(dx * dx + dy * dy) : 0.0;
-    g.id = make_double2(dx * den, -dy * den);
-    g.u = make_double2(rs * g.id.x, rs * g.id.y);
-    g.wv = make_double2(-rsT * g.id.x, -rsT * g.id.y);
-    g.u2 = cmul(g.u, g.u);
-    g.u4 = cmul(g.u2, g.u2);
-    g.w2 = cmul(g.wv, g.wv);
-    g.w4 = cmul(g.w2, g.w2);
-    g.w8 = cmul(g.w4, g.w4);
+    const double2 id = make_double2(dx * den, -dy * den);
+    const double2 u = make_double2(rs * id.x, rs * id.y);
+    const double2 w = make_double2(-rsT * id.x, -rsT * id.y);
+    const double2 u2 = cmul(u, u);
+    g.up[0] = make_double2(1.0, 0.0);
+    g.up[1] = u;
+    g.up[2] = u2;
+    g.up[3] = cmul(u2, u);
+    g.u4 = cmul(u2, u2);
+    const double2 w2 = cmul(w, w);
+    g.f0[0] = id;                       // rows kq + 4 j: f0 = (1/d) w^kq
+    g.f0[1] = cmul(id, w);
+    g.f0[2] = cmul(id, w2);
+    g.f0[3] = cmul(g.f0[1], w2);
+    g.ws = cmul(w2, w2);
     return g;
 }
 
@@ -259,39 +258,52 @@ k_m2l(const int32_t* __restrict__ boxes, const int2* __restrict__ xitems, int nx
     // list, padding replaced by pad_id).
     // one array per field ([field][block][column]): the 16 columns of a
     // block read 16 consecutive entries, free of bank conflicts
-    __shared__ T2 sgeo[4][8][4][16];
+    __shared__ T2 sgeo[4][kGeoFields][4][16];
     __shared__ int ssid[4][4][16];
     T2(*geo)[4][16] = sgeo[w];
     int(*gsid)[16] = ssid[w];
     auto put_geo = [&](const PairGeo<T>& c) {
-        geo[0][kq][q] = c.id; geo[1][kq][q] = c.u; geo[2][kq][q] = c.u2; geo[3][kq][q] = c.u4;
-        geo[4][kq][q] = c.wv; geo[5][kq][q] = c.w2; geo[6][kq][q] = c.w4; geo[7][kq][q] = c.w8;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            geo[e][kq][q] = c.up[e];
+            geo[4 + e][kq][q] = c.f0[e];
+        }
+        geo[8][kq][q] = c.u4;
+        geo[9][kq][q] = c.ws;
+    };
+    // what lane (kq, q) needs of the pair in column q of block j
+    struct LaneGeo {
+        T2 up, f0, u4, ws;
     };
     auto get_geo = [&](int j) {
-        PairGeo<T> c;
-        c.id = geo[0][j][q]; c.u = geo[1][j][q]; c.u2 = geo[2][j][q]; c.u4 = geo[3][j][q];
-        c.wv = geo[4][j][q]; c.w2 = geo[5][j][q]; c.w4 = geo[6][j][q]; c.w8 = geo[7][j][q];
+        LaneGeo c;
+        c.up = geo[kq][j][q];
+        c.f0 = geo[4 + kq][j][q];
+        c.u4 = geo[8][j][q];
+        c.ws = geo[9][j][q];
         return c;
     };
     const int last = nw > 0 ? nw - 1 : 0;
     auto raw_id = [&](int e) { return nw > 0 ? ld_pin(w_ids + wb + (e < last ? e : last)) : pad_id; };
     auto gpair = [&](int gi) { return (4 * gi + kq) * S + sl; };   // this lane's geometry pair in group gi
-    auto compute = [&](const PairGeo<T>& c, const T2 (&a)[KS]) {
+    auto compute = [&](const LaneGeo& c, const T2 (&a)[KS]) {
         // Terms k >= p meet zero columns of B and rows l >= p are not stored.
         T2 xv[KS];
         T fre[PB][4], fim[PB][4];
-        auto pw = cpow_lane(c.u, c.u2, kq);                             // u^kq
+        auto pw = c.up;                                                  // u^kq
 #pragma unroll
         for (int i = 0; i < KS; ++i) {
             xv[i] = scale_coef(pw, a[i]);
             if (i + 1 < KS) pw = cmul(pw, c.u4);
         }
         // row factors f_l = (1/d) w^l of this lane's output rows
-        const auto base = M::kRowsConsecutive ? cpow_lane(c.w4, c.w8, kq) : cpow_lane(c.wv, c.w2, kq);   // w^r0
-        const auto step = M::kRowsConsecutive ? c.wv : c.w4;
-        const auto f0 = cmul(base, c.id);
-        const auto w16 = cmul(c.w8, c.w8);
-        auto frb = f0;
+        const auto step = c.ws;
+        T2 w16 = step;                          // w^16: w^(1 * 16) (FP32) or (w^4)^4 (FP64)
+        if constexpr (PB > 1) {
+#pragma unroll
+            for (int e = 0; e < (M::kRowsConsecutive ? 4 : 2); ++e) w16 = cmul(w16, w16);
+        }
+        auto frb = c.f0;
 #pragma unroll
         for (int rb = 0; rb < PB; ++rb) {
             if (rb > 0) frb = cmul(frb, w16);                               // row r0 + 16 rb: times w^(16 rb)

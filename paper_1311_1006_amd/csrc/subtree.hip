@@ -65,7 +65,19 @@ __device__ __forceinline__ int sub_box(int b, int64_t NB, int l, int64_t j)
 template <int P>
 __device__ __forceinline__ void load_binom(double (*sb)[P], const double* __restrict__ binom)
 {
-    for (int i = threadIdx.x; i < P * P; i += blockDim.x) sb[i / P][i % P] = binom[(i / P) * kBinomStride + (i % P)];
+    // all loads in flight before the first store (blocks of 256 threads)
+    constexpr int R = (P * P + 255) / 256;
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        v[r] = i < P * P ? binom[(i / P) * kBinomStride + (i % P)] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        if (i < P * P) sb[i / P][i % P] = v[r];
+    }
 }
 
 // M2M into one parent by one wavefront: lane (c, j), c = lane/16 the child,
@@ -88,13 +100,18 @@ __device__ __forceinline__ void m2m_wave(int p, const double* __restrict__ geom,
         rho[c][jj] = sub_rpow(r, jj);
     }
     wave_sync();
+    // the sums run over the compile-time bound P (terms past k are skipped),
+    // so that their LDS loads are all issued before the first is used
     for (int k = j; k < p; k += 16) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int l = 0; l <= k; ++l) {
-            const double s = sb[k][l] * rho[c][l];
-            const double2 v = cmul(co[c][l], tau[c][k - l]);
-            acc.x += s * v.x;
-            acc.y += s * v.y;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            if (l <= k) {
+                const double s = sb[k][l] * rho[c][l];
+                const double2 v = cmul(co[c][l], tau[c][k - l]);
+                acc.x += s * v.x;
+                acc.y += s * v.y;
+            }
         }
         part[c][k] = acc;
     }
@@ -218,14 +235,25 @@ k_up_mid(int a, int D, int64_t NB, int nper, const double* __restrict__ geom, in
     const int b = blockIdx.x / nper;
     const int64_t jA = blockIdx.x % nper;
     load_binom<P>(sb, binom);
-    // level a+D: 4^D boxes
+    // level a+D: 4^D <= 64 boxes, all loads in flight before the first store
     const int nin = 1 << (2 * D);
-    for (int i = threadIdx.x; i < nin * P; i += 256) {
+    constexpr int R = 64 * P / 256;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + 256 * r;
         const int c = i / P, k = i % P;
-        if (k < p) {
+        v[r] = make_double2(0.0, 0.0);
+        if (c < nin && k < p) {
             const int64_t box = sub_box(b, NB, a + D, ((int64_t)jA << (2 * D)) + c);
-            sc0[c][k] = make_double2((double)mp[2 * (box * p + k)], (double)mp[2 * (box * p + k) + 1]);
+            v[r] = make_double2((double)mp[2 * (box * p + k)], (double)mp[2 * (box * p + k) + 1]);
         }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        const int c = i / P, k = i % P;
+        if (c < nin && k < p) sc0[c][k] = v[r];
     }
     __syncthreads();
     double2 (*cur)[P] = sc0;
@@ -292,11 +320,14 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
         wave_sync();
         for (int l = sl; l < p; l += 16) {
             double2 acc = make_double2(0.0, 0.0);
-            for (int k = l; k < p; ++k) {
-                const double s = sb[k][l];
-                const double2 v = cmul(sanc[gl][k], stab[gl][k - l]);
-                acc.x += s * v.x;
-                acc.y += s * v.y;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (k >= l && k < p) {
+                    const double s = sb[k][l];
+                    const double2 v = cmul(sanc[gl][k], stab[gl][k - l]);
+                    acc.x += s * v.x;
+                    acc.y += s * v.y;
+                }
             }
             const double rl = sub_rpow(rho, l);
             spart[gl][l] = make_double2(rl * acc.x, rl * acc.y);
@@ -326,11 +357,14 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
         wave_sync();
         for (int l = sl; l < p; l += 16) {
             double2 acc = make_double2(0.0, 0.0);
-            for (int k = l; k < p; ++k) {
-                const double s = sb[k][l];
-                const double2 v = cmul(sR[k], stab[c][k - l]);
-                acc.x += s * v.x;
-                acc.y += s * v.y;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (k >= l && k < p) {
+                    const double s = sb[k][l];
+                    const double2 v = cmul(sR[k], stab[c][k - l]);
+                    acc.x += s * v.x;
+                    acc.y += s * v.y;
+                }
             }
             const double rl = sub_rpow(rho, l);
             const T2 own = lo[(int64_t)C * p + l];
@@ -355,11 +389,14 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
                 continue;
             }
             double2 acc = make_double2(0.0, 0.0);
-            for (int k = l; k < p; ++k) {
-                const double s = sb[k][l];
-                const double2 v = cmul(sC[w][k], stab[gl][k - l]);
-                acc.x += s * v.x;
-                acc.y += s * v.y;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (k >= l && k < p) {
+                    const double s = sb[k][l];
+                    const double2 v = cmul(sC[w][k], stab[gl][k - l]);
+                    acc.x += s * v.x;
+                    acc.y += s * v.y;
+                }
             }
             const double rl = sub_rpow(rho, l);
             const T2 own = lo[(int64_t)leaf * p + l];

@@ -1100,7 +1100,8 @@ __global__ void k_copy_final(const TileInfo* __restrict__ tiles, const double* X
 // lists: an element is in the lower half of its sub-segment iff its
 // position in the split axis' list is below start + count/2.
 constexpr int kLdsThreads = 1024;
-constexpr int kPer = kLdsCap / kLdsThreads;
+constexpr int kLdsWaves = kLdsThreads / 64;
+constexpr int kPer = kLdsCap / kLdsThreads;     // positions (and buckets) per thread
 
 struct LdsSort {
     uint64_t key[kLdsCap];
@@ -1172,11 +1173,11 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
         lo = fmin(lo, __shfl_xor(lo, o, 64));
         hi = fmax(hi, __shfl_xor(hi, o, 64));
     }
-    if (lane == 0) { red[wid] = lo; red[16 + wid] = hi; }
+    if (lane == 0) { red[wid] = lo; red[kLdsWaves + wid] = hi; }
     for (int b = tid; b < NB; b += kLdsThreads) U.b.cnt[b] = 0;
     __syncthreads();
-    lo = red[0]; hi = red[16];
-    for (int w = 1; w < kLdsThreads / 64; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[16 + w]); }
+    lo = red[0]; hi = red[kLdsWaves];
+    for (int w = 1; w < kLdsWaves; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[kLdsWaves + w]); }
     const double ext = hi - lo;
     double scale = ext > 0.0 ? (double)NB / ext : 0.0;
     scale = scale < 1e300 ? scale : 0.0;
@@ -1188,13 +1189,13 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
         if (i < n) atomicAdd(&U.b.cnt[bk[u]], 1u);
     }
     __syncthreads();
-    // exclusive scan of the populations (thread t owns buckets 4t..4t+3) and
+    // exclusive scan of the populations (thread t owns buckets kPer t .. kPer t + kPer - 1) and
     // the largest population
-    uint32_t q[4];
+    uint32_t q[kPer];
     int loc = 0, mx = 0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        q[v] = U.b.cnt[4 * tid + v];
+    for (int v = 0; v < kPer; ++v) {
+        q[v] = U.b.cnt[kPer * tid + v];
         loc += (int)q[v];
         mx = max(mx, (int)q[v]);
     }
@@ -1202,15 +1203,15 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
     int tot;
     int run = block_excl_scan<kLdsThreads>(loc, sh, &tot);
-    if (lane == 0) sh[16 + wid] = mx;
+    if (lane == 0) sh[kLdsWaves + wid] = mx;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        U.b.cnt[4 * tid + v] = (uint32_t)run;
+    for (int v = 0; v < kPer; ++v) {
+        U.b.cnt[kPer * tid + v] = (uint32_t)run;
         run += (int)q[v];
     }
     __syncthreads();
     mx = 0;
-    for (int w = 0; w < kLdsThreads / 64; ++w) mx = max(mx, sh[16 + w]);
+    for (int w = 0; w < kLdsWaves; ++w) mx = max(mx, sh[kLdsWaves + w]);
     __syncthreads();
     if (mx > kBucketMax) {
         // bitonic fallback (uniform branch)
@@ -1276,10 +1277,27 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
     const double* yg = ((w.stage0 & 1) ? YB : YA) + w.start;
     const int32_t* is = ((w.stage0 & 1) ? IB : IA) + w.start;
     int n = w.count;
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) {
-        idxs[i] = (uint32_t)is[i];
-        xs[i] = xg[i];
-        ys[i] = yg[i];
+    {
+        // every load of the segment in flight before the first LDS store
+        uint32_t li[kPer];
+        double lx[kPer], ly[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = threadIdx.x + u * kLdsThreads;
+            const int ic = i < n ? i : 0;
+            li[u] = (uint32_t)is[ic];
+            lx[u] = xg[ic];
+            ly[u] = yg[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = threadIdx.x + u * kLdsThreads;
+            if (i < n) {
+                idxs[i] = li[u];
+                xs[i] = lx[u];
+                ys[i] = ly[u];
+            }
+        }
     }
     __syncthreads();
     lds_order(U, xs, idxs, n, LX, sh, red);
@@ -1358,10 +1376,10 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
         }
         int ev = __shfl_up(v, 1, 64), eh = __shfl_up(hf, 1, 64);
         if (lane == 0) { ev = 0; eh = 0; }
-        if (lane == 63) { sh[wid] = v; sh[16 + wid] = hf; }
+        if (lane == 63) { sh[wid] = v; sh[kLdsWaves + wid] = hf; }
         __syncthreads();
         int carry = 0;
-        for (int q = 0; q < wid; ++q) carry = sh[16 + q] ? sh[q] : carry + sh[q];
+        for (int q = 0; q < wid; ++q) carry = sh[kLdsWaves + q] ? sh[q] : carry + sh[q];
         const int cin = eh ? ev : carry + ev;
         // scatter the other list's elements in place (every read of the
         // lists and positions of this stage came before the barrier) and
@@ -1381,9 +1399,13 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
         __syncthreads();
     }
     // final order: sorted by (x, index) inside every leaf
-    for (int i = threadIdx.x; i < n; i += kLdsThreads) {
-        int id = LX[i];
-        Xo[w.start + i] = xs[id]; Yo[w.start + i] = ys[id]; Io[w.start + i] = (int32_t)idxs[id];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = threadIdx.x + u * kLdsThreads;
+        if (i < n) {
+            const int id = LX[i];
+            Xo[w.start + i] = xs[id]; Yo[w.start + i] = ys[id]; Io[w.start + i] = (int32_t)idxs[id];
+        }
     }
 }
 
