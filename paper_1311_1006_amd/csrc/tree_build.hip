@@ -1114,6 +1114,7 @@ struct LdsPos {
 struct LdsBucket {
     uint32_t cnt[kLdsCap];      // bucket populations, then bucket ends
     uint64_t key[kLdsCap];      // order keys in bucket order
+    uint16_t id[kLdsCap];       // local ids in bucket order (any order inside a bucket)
 };
 union LdsUnion {
     LdsSort s;
@@ -1149,9 +1150,10 @@ __device__ void lds_sort(LdsSort& S, const uint32_t* idxs, int n)
 // Local ids 0..n-1 of the segment ordered by (coordinate, input index) into
 // out.  Bucket sort: kLdsCap equal-width buckets between the segment's
 // minimum and maximum coordinate (a monotone map), an exclusive scan of the
-// populations, a scatter, and an insertion sort inside every bucket.  When a
-// bucket holds more than kBucketMax points (ties, tight clusters) the
-// bitonic sort runs instead.
+// populations, a scatter, and the place of every element inside its bucket
+// from the count of the bucket's elements that precede it.  When a bucket
+// holds more than kBucketMax points (ties, tight clusters) the bitonic sort
+// runs instead.
 constexpr int kBucketMax = 16;
 
 __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint32_t* idxs, int n, uint16_t* out,
@@ -1234,28 +1236,42 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
         if (i < n) {
             const uint32_t pos = atomicAdd(&U.b.cnt[bk[u]], 1u);
             U.b.key[pos] = okey(cv[u]);
-            out[pos] = (uint16_t)i;
+            U.b.id[pos] = (uint16_t)i;
         }
     }
     __syncthreads();
-    // insertion sort inside every bucket by (key, input index)
-    for (int b = tid; b < NB; b += kLdsThreads) {
-        const int e = (int)U.b.cnt[b], s0 = b == 0 ? 0 : (int)U.b.cnt[b - 1];
-        for (int a = s0 + 1; a < e; ++a) {
-            const uint64_t ka = U.b.key[a];
-            const uint16_t ia = out[a];
-            const uint32_t xa = idxs[ia];
-            int j = a - 1;
-            while (j >= s0) {
-                const uint64_t kj = U.b.key[j];
-                const uint16_t ij = out[j];
-                if (kj < ka || (kj == ka && idxs[ij] < xa)) break;
-                U.b.key[j + 1] = kj;
-                out[j + 1] = ij;
-                --j;
+    // the place of every element inside its bucket (at most kBucketMax
+    // elements): the count of the bucket's elements smaller in (key, input
+    // index); the reads of the bucket are independent, so they are issued
+    // together
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = tid + u * kLdsThreads;
+        if (i < n) {
+            const int b = bk[u];
+            const int e = (int)U.b.cnt[b], s0 = b == 0 ? 0 : (int)U.b.cnt[b - 1];
+            const uint64_t km = okey(cv[u]);
+            const uint32_t xm = idxs[i];
+            // the first kRankFirst keys of the bucket are read unconditionally
+            // (indices clamped into the bucket, which holds this element);
+            // the input index only for an exact tie; larger buckets go on
+            constexpr int kRankFirst = 8;
+            uint64_t kk[kRankFirst];
+#pragma unroll
+            for (int t = 0; t < kRankFirst; ++t) kk[t] = U.b.key[min(s0 + t, e - 1)];
+            int r = 0;
+#pragma unroll
+            for (int t = 0; t < kRankFirst; ++t) {
+                if (s0 + t < e) {
+                    r += kk[t] < km;
+                    if (kk[t] == km) r += idxs[U.b.id[s0 + t]] < xm;
+                }
             }
-            U.b.key[j + 1] = ka;
-            out[j + 1] = ia;
+            for (int q = s0 + kRankFirst; q < e; ++q) {
+                const uint64_t kq = U.b.key[q];
+                r += (kq < km) | ((kq == km) & (idxs[U.b.id[q]] < xm));
+            }
+            out[s0 + r] = (uint16_t)i;
         }
     }
     __syncthreads();
