@@ -35,14 +35,9 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
             avail = bcount[S];
             if (lane == 0) { st += off; avail -= off; }
         }
-        int x = avail;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = wave_incl_scan(avail);
         const int excl = x - avail;
-        const int total = __shfl(x, 63, 64);
+        const int total = __builtin_amdgcn_readlane(x, 63);
         const int cap = lim - staged;
         const int take = min(total, cap);
         const bool starts = avail > 0 && excl < take;
@@ -99,13 +94,8 @@ __device__ __forceinline__ void seek_source(const int32_t* __restrict__ s_ids, c
     while (e < e_end) {
         const int k = e + lane;
         const int c = k < e_end ? bcount[s_ids[e0 + k]] : 0;
-        int x = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        const int total = __shfl(x, 63, 64);
+        const int x = wave_incl_scan(c);
+        const int total = __builtin_amdgcn_readlane(x, 63);
         if (o >= total) {
             o -= total;
             e += 64;

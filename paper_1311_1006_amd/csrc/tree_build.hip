@@ -44,6 +44,7 @@
 #include <cstring>
 
 #include "fmm_internal.h"
+#include "kernels_common.h"
 
 // Box geometry, split axes and the theta-criterion must round every product
 // and sum on its own (no fused multiply-add), like a plain IEEE evaluation.
@@ -285,23 +286,20 @@ __device__ __forceinline__ void read_keys(const uint64_t* k, double* bb)
 
 // read_keys for a whole workgroup: lane c of wave 0 reads copy c and the
 // wave combines them; every thread receives the result (one barrier)
+static_assert(kKeyCopies == 32, "one key copy per lane of a half wavefront");
 __device__ __forceinline__ void block_read_keys(const uint64_t* k, double* bb)
 {
-    __shared__ uint64_t sk[4];
+    // the copies as doubles (an untouched copy decodes to NaN, which the
+    // minimum and maximum ignore, as the integer order placed it last)
+    __shared__ double sk[4];
     if (threadIdx.x < 64) {
         const int c = threadIdx.x & (kKeyCopies - 1);
-        uint64_t a = k[4 * c], b = k[4 * c + 1], d = k[4 * c + 2], e = k[4 * c + 3];
-#pragma unroll
-        for (int o = kKeyCopies / 2; o > 0; o >>= 1) {
-            const uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
-            const uint64_t d2 = __shfl_xor(d, o, 64), e2 = __shfl_xor(e, o, 64);
-            a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
-            d = d2 < d ? d2 : d; e = e2 > e ? e2 : e;
-        }
+        const double a = half_wave_min(okey_inv(k[4 * c])), b = half_wave_max(okey_inv(k[4 * c + 1]));
+        const double d = half_wave_min(okey_inv(k[4 * c + 2])), e = half_wave_max(okey_inv(k[4 * c + 3]));
         if (threadIdx.x == 0) { sk[0] = a; sk[1] = b; sk[2] = d; sk[3] = e; }
     }
     __syncthreads();
-    bb[0] = okey_inv(sk[0]); bb[1] = okey_inv(sk[1]); bb[2] = okey_inv(sk[2]); bb[3] = okey_inv(sk[3]);
+    bb[0] = sk[0]; bb[1] = sk[1]; bb[2] = sk[2]; bb[3] = sk[3];
 }
 
 // Two levels of bucket selection: the first histogram of a segment has
@@ -342,25 +340,19 @@ __device__ __forceinline__ Bucketer axis_bucketer(const double* bb, int axis)
 // read_keys of two segments for a whole workgroup (one barrier)
 __device__ __forceinline__ void block_read_keys2(const uint64_t* k0, const uint64_t* k1, double* b0, double* b1)
 {
-    __shared__ uint64_t sk[8];
+    __shared__ double sk[8];
     if (threadIdx.x < 64) {
-        const uint64_t* k = threadIdx.x < 32 ? k0 : k1;
+        const uint64_t* k = threadIdx.x < 32 ? k0 : k1;   // one segment per half wavefront
         const int c = threadIdx.x & (kKeyCopies - 1);
-        uint64_t a = k[4 * c], b = k[4 * c + 1], d = k[4 * c + 2], e = k[4 * c + 3];
-#pragma unroll
-        for (int o = kKeyCopies / 2; o > 0; o >>= 1) {
-            const uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
-            const uint64_t d2 = __shfl_xor(d, o, 64), e2 = __shfl_xor(e, o, 64);
-            a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
-            d = d2 < d ? d2 : d; e = e2 > e ? e2 : e;
-        }
+        const double a = half_wave_min(okey_inv(k[4 * c])), b = half_wave_max(okey_inv(k[4 * c + 1]));
+        const double d = half_wave_min(okey_inv(k[4 * c + 2])), e = half_wave_max(okey_inv(k[4 * c + 3]));
         if ((threadIdx.x & 31) == 0) {
             const int o = threadIdx.x >> 3;   // 0 or 4
             sk[o] = a; sk[o + 1] = b; sk[o + 2] = d; sk[o + 3] = e;
         }
     }
     __syncthreads();
-    for (int i = 0; i < 4; ++i) { b0[i] = okey_inv(sk[i]); b1[i] = okey_inv(sk[4 + i]); }
+    for (int i = 0; i < 4; ++i) { b0[i] = sk[i]; b1[i] = sk[4 + i]; }
 }
 
 // The bucketer of a segment, computed by the whole workgroup (every thread
@@ -397,12 +389,7 @@ template <int NT>
 __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
 {
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const int x = wave_incl_scan(v);
     if (lane == 63) sh[wid] = x;
     __syncthreads();
     int base = 0, tot = 0;
@@ -434,30 +421,25 @@ __global__ void k_fill_start(uint32_t* words, int64_t nwords, uint64_t* k, int64
 __device__ __forceinline__ void block_minmax_atomic(double x0, double x1, double y0, double y1,
                                                     uint64_t* keys, bool any)
 {
-    __shared__ uint64_t red[4][kTileThreads / 64];
-    uint64_t a = any ? okey(x0) : ~0ull, b = any ? okey(x1) : 0ull;
-    uint64_t c = any ? okey(y0) : ~0ull, d = any ? okey(y1) : 0ull;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t a2 = __shfl_xor(a, o, 64), b2 = __shfl_xor(b, o, 64);
-        uint64_t c2 = __shfl_xor(c, o, 64), d2 = __shfl_xor(d, o, 64);
-        a = a2 < a ? a2 : a; b = b2 > b ? b2 : b;
-        c = c2 < c ? c2 : c; d = d2 > d ? d2 : d;
-    }
+    __shared__ double red[4][kTileThreads / 64];
+    // over the wavefront as doubles (a thread without a point contributes
+    // +-infinity), turned into order keys once per workgroup
+    double a = wave_min(any ? x0 : INFINITY), b = wave_max(any ? x1 : -INFINITY);
+    double c = wave_min(any ? y0 : INFINITY), d = wave_max(any ? y1 : -INFINITY);
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; red[3][w] = d; }
     __syncthreads();
     if (threadIdx.x == 0) {
         keys += 4 * (blockIdx.x & (kKeyCopies - 1));
         for (int i = 1; i < kTileThreads / 64; ++i) {
-            a = red[0][i] < a ? red[0][i] : a; b = red[1][i] > b ? red[1][i] : b;
-            c = red[2][i] < c ? red[2][i] : c; d = red[3][i] > d ? red[3][i] : d;
+            a = fmin(a, red[0][i]); b = fmax(b, red[1][i]);
+            c = fmin(c, red[2][i]); d = fmax(d, red[3][i]);
         }
-        if (a != ~0ull) {
-            atomicMin((unsigned long long*)&keys[0], (unsigned long long)a);
-            atomicMax((unsigned long long*)&keys[1], (unsigned long long)b);
-            atomicMin((unsigned long long*)&keys[2], (unsigned long long)c);
-            atomicMax((unsigned long long*)&keys[3], (unsigned long long)d);
+        if (isfinite(a)) {
+            atomicMin((unsigned long long*)&keys[0], (unsigned long long)okey(a));
+            atomicMax((unsigned long long*)&keys[1], (unsigned long long)okey(b));
+            atomicMin((unsigned long long*)&keys[2], (unsigned long long)okey(c));
+            atomicMax((unsigned long long*)&keys[3], (unsigned long long)okey(d));
         }
     }
     __syncthreads();
@@ -853,19 +835,19 @@ k_collect(const TileInfo* __restrict__ tiles, const TileInfo* __restrict__ all_t
 __device__ __forceinline__ void block_minmax2_atomic(const double (&l)[4], const double (&u)[4], bool anyl,
                                                      bool anyu, uint64_t* keys_lo, uint64_t* keys_hi)
 {
-    __shared__ uint64_t red[8][kTileThreads / 64];
-    uint64_t k[8];
-    k[0] = anyl ? okey(l[0]) : ~0ull; k[1] = anyl ? okey(l[1]) : 0ull;
-    k[2] = anyl ? okey(l[2]) : ~0ull; k[3] = anyl ? okey(l[3]) : 0ull;
-    k[4] = anyu ? okey(u[0]) : ~0ull; k[5] = anyu ? okey(u[1]) : 0ull;
-    k[6] = anyu ? okey(u[2]) : ~0ull; k[7] = anyu ? okey(u[3]) : 0ull;
+    __shared__ double red[8][kTileThreads / 64];
+    // minima and maxima over the wavefront as doubles (a lane without a
+    // point contributes +-infinity), turned into order keys once per
+    // workgroup
+    double k[8];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
+    for (int q = 0; q < 4; ++q) {
+        const double inf = (q & 1) ? -INFINITY : INFINITY;
+        k[q] = anyl ? l[q] : inf;
+        k[4 + q] = anyu ? u[q] : inf;
+    }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint64_t v = __shfl_xor(k[q], o, 64);
-            k[q] = (q & 1) ? (v > k[q] ? v : k[q]) : (v < k[q] ? v : k[q]);
-        }
+    for (int q = 0; q < 8; ++q) k[q] = (q & 1) ? wave_max(k[q]) : wave_min(k[q]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -874,11 +856,11 @@ __device__ __forceinline__ void block_minmax2_atomic(const double (&l)[4], const
     // thread q < 8 combines value q over the waves and updates one key
     if (threadIdx.x < 8) {
         const int q = threadIdx.x;
-        uint64_t a = red[q][0];
-        for (int i = 1; i < kTileThreads / 64; ++i) a = (q & 1) ? (red[q][i] > a ? red[q][i] : a)
-                                                                : (red[q][i] < a ? red[q][i] : a);
+        double v = red[q][0];
+        for (int i = 1; i < kTileThreads / 64; ++i) v = (q & 1) ? fmax(v, red[q][i]) : fmin(v, red[q][i]);
         uint64_t* kk = (q < 4 ? keys_lo : keys_hi) + 4 * (blockIdx.x & (kKeyCopies - 1)) + (q & 3);
-        const bool empty = (q & 1) ? a == 0ull : a == ~0ull;
+        const bool empty = !isfinite(v);
+        const uint64_t a = empty ? 0ull : okey(v);
         if (!empty) {
             if (q & 1) atomicMax((unsigned long long*)kk, (unsigned long long)a);
             else atomicMin((unsigned long long*)kk, (unsigned long long)a);
@@ -1170,11 +1152,8 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
         cv[u] = i < n ? c[i] : 0.0;
         if (i < n) { lo = fmin(lo, cv[u]); hi = fmax(hi, cv[u]); }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = fmin(lo, __shfl_xor(lo, o, 64));
-        hi = fmax(hi, __shfl_xor(hi, o, 64));
-    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
     if (lane == 0) { red[wid] = lo; red[kLdsWaves + wid] = hi; }
     for (int b = tid; b < NB; b += kLdsThreads) U.b.cnt[b] = 0;
     __syncthreads();
@@ -1201,8 +1180,7 @@ __device__ void lds_order(LdsUnion& U, const double* __restrict__ c, const uint3
         loc += (int)q[v];
         mx = max(mx, (int)q[v]);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    mx = wave_max_i32(mx);
     int tot;
     int run = block_excl_scan<kLdsThreads>(loc, sh, &tot);
     if (lane == 0) sh[kLdsWaves + wid] = mx;
@@ -1380,18 +1358,9 @@ k_lds_split(const LdsWork* __restrict__ work, const double* XA, const double* YA
         }
         // segmented exclusive scan of the lower flags over the positions
         // (restarting at every sub-segment head): within the wavefront by
-        // shuffles, across wavefronts through one barrier
-        int v = run, hf = seen ? 1 : 0;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int pv = __shfl_up(v, o, 64), ph = __shfl_up(hf, o, 64);
-            if (lane >= o) {
-                if (!hf) v += pv;
-                hf |= ph;
-            }
-        }
-        int ev = __shfl_up(v, 1, 64), eh = __shfl_up(hf, 1, 64);
-        if (lane == 0) { ev = 0; eh = 0; }
+        // lane permutations, across wavefronts through one barrier
+        int v = run, hf = seen ? 1 : 0, ev, eh;
+        wave_seg_scan(hf, v, eh, ev);
         if (lane == 63) { sh[wid] = v; sh[kLdsWaves + wid] = hf; }
         __syncthreads();
         int carry = 0;
