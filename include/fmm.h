@@ -399,6 +399,21 @@ int fmm_choose_order(fmm_tree_t t, const double* m, double theta, double tol, in
 /* Thread-local message of the last failing call ("" if none). */
 const char* fmm_last_error(void);
 
+/* Test hooks for the allocation-failure paths (no paper passage: they check
+ * the error contract above).  fmm_debug_fail_alloc(after): the device
+ * allocation that comes `after` allocations from now (0: the next one)
+ * fails once with FMM_ENOMEM, as if the device were out of memory, in
+ * whatever call makes it; after < 0 cancels a pending failure.  The
+ * setting is process-wide (all devices and threads).  Always FMM_OK.
+ * fmm_debug_live_blocks(&n): n = device blocks currently held by trees,
+ * plans, schedules and evaluations; blocks the library keeps cached for
+ * reuse are not counted, so a sequence of calls whose handles are all
+ * destroyed returns n to its value before the sequence (schedules and
+ * launch tables cached per tree layout aside).  FMM_EINVAL if live is
+ * NULL. */
+int fmm_debug_fail_alloc(int64_t after);
+int fmm_debug_live_blocks(int64_t* live);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,8 @@ def lib():
         "fmm_choose_order": (C.c_int, [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, vp,
                                        C.POINTER(C.c_int), dp]),
         "fmm_last_error": (C.c_char_p, []),
+        "fmm_debug_fail_alloc": (C.c_int, [C.c_int64]),
+        "fmm_debug_live_blocks": (C.c_int, [i64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -121,6 +123,19 @@ def header_functions():
 def _check(rc):
     if rc != 0:
         raise FmmError(rc, lib().fmm_last_error().decode())
+
+
+def debug_fail_alloc(after):
+    """Make the device allocation `after` allocations from now fail once
+    with FMM_ENOMEM (after < 0: cancel)."""
+    _check(lib().fmm_debug_fail_alloc(int(after)))
+
+
+def debug_live_blocks():
+    """Device blocks held by live trees, plans and schedules."""
+    n = C.c_int64()
+    _check(lib().fmm_debug_live_blocks(C.byref(n)))
+    return n.value
 
 
 def _stream(stream):

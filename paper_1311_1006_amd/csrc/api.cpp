@@ -32,6 +32,8 @@ struct Block {
 std::mutex g_mu;
 std::multimap<std::pair<hipStream_t, size_t>, Block> g_free;
 std::map<void*, size_t> g_cls;
+int64_t g_live = 0;         // blocks handed out and not returned
+int64_t g_fail_after = -1;  // allocations left before an injected failure (-1: none)
 
 size_t size_class(size_t b)
 {
@@ -46,10 +48,16 @@ void* dev_alloc(size_t bytes, hipStream_t s)
     size_t c = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        if (g_fail_after == 0) {
+            g_fail_after = -1;
+            throw Error(FMM_ENOMEM, "device allocation of " + std::to_string(c) + " bytes failed (injected)");
+        }
+        if (g_fail_after > 0) --g_fail_after;
         auto it = g_free.find({s, c});
         if (it != g_free.end()) {
             Block b = it->second;
             g_free.erase(it);
+            ++g_live;
             return b.p;
         }
     }
@@ -75,6 +83,7 @@ void* dev_alloc(size_t bytes, hipStream_t s)
     }
     std::lock_guard<std::mutex> lk(g_mu);
     g_cls[p] = c;
+    ++g_live;
     return p;
 }
 
@@ -85,6 +94,7 @@ void dev_free(void* p, hipStream_t s)
     auto it = g_cls.find(p);
     if (it == g_cls.end()) return;
     g_free.insert({{s, it->second}, Block{p, it->second, s}});
+    --g_live;
 }
 
 // ------------------------------------------------------ pinned flag words
@@ -184,6 +194,24 @@ struct fmm_plan_s {
 extern "C" {
 
 const char* fmm_last_error(void) { return g_err.c_str(); }
+
+int fmm_debug_fail_alloc(int64_t after)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fail_after = after < 0 ? -1 : after;
+    return FMM_OK;
+}
+
+int fmm_debug_live_blocks(int64_t* live)
+{
+    if (!live) {
+        g_err = "live is NULL";
+        return FMM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    *live = g_live;
+    return FMM_OK;
+}
 
 int fmm_p_from_tol(double tol, double theta)
 {
@@ -324,7 +352,9 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         FMM_REQUIRE(tn.smooth_delta >= 0.0 && std::isfinite(tn.smooth_delta), "smooth_delta must be >= 0 and finite");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
-        auto pp = std::make_unique<fmm_plan_s>();
+        // a plan that fails half-way is released by fmm_plan_destroy, which
+        // waits for list work already enqueued before its buffers are reused
+        std::unique_ptr<fmm_plan_s, void (*)(fmm_plan_s*)> pp(new fmm_plan_s, fmm_plan_destroy);
         pp->tree = t;
         Plan& pl = pp->pl;
         pl.tree = &t->t;
@@ -412,9 +442,10 @@ void fmm_plan_destroy(fmm_plan_t pl)
     if (P.ev_top0) (void)hipEventDestroy(P.ev_top0);
     if (P.ev_top1) (void)hipEventDestroy(P.ev_top1);
     release_list_flag(P);
-    // list work still in flight (a plan never used) finishes before its
+    // list work still in flight (a plan never used, or one whose creation
+    // failed after its list kernels were enqueued) finishes before its
     // buffers go back to the pool
-    if (P.lists_pending && P.list_stream) (void)hipStreamSynchronize(P.list_stream);
+    if (P.list_stream && !P.finalized) (void)hipStreamSynchronize(P.list_stream);
     if (P.ev_tree) (void)hipEventDestroy(P.ev_tree);
     if (P.ev_lists_k) (void)hipEventDestroy(P.ev_lists_k);
     if (P.ev_spec) (void)hipEventDestroy(P.ev_spec);
