@@ -179,6 +179,9 @@ def measure_clustered_breakdown(F, W, torch, dev, steps=30, dt=1e-4):
         for L in (prm["n_levels"] - 1, prm["n_levels"], prm["n_levels"] + 1):
             for _ in range(2):
                 F.evaluate(F.plan(F.build_tree(zz, L), 16, 0.5, "mixed", **knobs), md, out)
+            # the whole step first, while no other tree or plan is alive (as in
+            # the time-stepping loop), then its parts one at a time
+            _, t_step = ev(lambda: F.evaluate(F.plan(F.build_tree(zz, L), 16, 0.5, "mixed", **knobs), md, out))
             tr, t_tree = ev(lambda: F.build_tree(zz, L))
             pl, t_plan = ev(lambda: F.plan(tr, 16, 0.5, "mixed", **knobs))
             st = pl.stats()
@@ -188,7 +191,6 @@ def measure_clustered_breakdown(F, W, torch, dev, steps=30, dt=1e-4):
                 F.evaluate(pt, md, out)
             torch.cuda.synchronize()
             sp = pt.stats()
-            _, t_step = ev(lambda: F.evaluate(F.plan(F.build_tree(zz, L), 16, 0.5, "mixed", **knobs), md, out))
             geom = tr.download(0)[2]
             r = geom[-(4 ** (L - 1)):, 6]
             rec = {"step_us": t_step, "tree_us": t_tree, "plan_us": t_plan, "evaluate_us": t_eval,

@@ -79,7 +79,7 @@ struct AdjSrc {
 template <class R, int TG, int SUB>
 __global__ void __launch_bounds__(256)
 k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
-          const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+          const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
           double* __restrict__ partial, const int32_t* __restrict__ bstart,
           const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
           const int32_t* __restrict__ s_ids, const double* __restrict__ X, const double* __restrict__ Y,
@@ -98,8 +98,6 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     const int2 xe = xitems ? xitems[xi] : make_int2(item_base + xi, 0);
     const P2PItemA it = items[xe.x];
     const int nch = icnt ? icnt[xe.x] : 1;
-    const int s_first = xe.y * kChunkSrc;
-    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     AdjSrc<R>* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -115,7 +113,10 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
 #pragma unroll
         for (int q = 0; q < 6; ++q) acc[t][q] = (R)0;
     }
-    const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
+    // the item's entries, or those of its chunk
+    const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
+    int e = nch == 1 ? 0 : xe.y * ce, off = 0;
+    const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
         const double x = X[j], y = Y[j];
         AdjSrc<R> s;
@@ -125,12 +126,8 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
         s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
         return s;
     };
-    int e = 0, off = 0;
-    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
-    for (int done = 0; done < s_len && e < ne;) {
-        const int ns = stage_sources<CAP>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load,
-                                          s_len - done);
-        done += ns;
+    while (e < ne) {
+        const int ns = stage_sources<CAP>(lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load);
         for (int c = 0; c < ns; c += NL) {
             int f = c + sl;
             AdjSrc<R> s = lds[f < ns ? f : 0];
@@ -278,18 +275,18 @@ static void adj_shape(int nt, bool mixed, int* tg, int* sub)
 
 template <class R, int TG, int SUB>
 static void launch_adj_one(const P2PItemA* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
-                           const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                           const int32_t* ioff, double* partial, const int32_t* bstart,
                            const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                            const double* X, const double* Y, const double* mt, const double* gb, double* out,
                            hipStream_t s)
 {
-    k_p2p_adj<R, TG, SUB><<<(nx + 3) / 4, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial,
+    k_p2p_adj<R, TG, SUB><<<(nx + 3) / 4, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial,
                                                        bstart, bcount, s_beg, s_cnt, s_ids, X, Y,
                                                        (const double2*)mt, (const double2*)gb, out);
 }
 
 void balance_launch(Plan::Balance& b, const void* items, int n, const std::vector<P2PClass>& cls,
-                    const int32_t* nsrc, hipStream_t s);
+                    const int32_t* s_cnt, const int32_t* bcount, hipStream_t s);
 void balance_finish(Plan::Balance& b, int n, int vals, hipStream_t s);
 void combine_chunks(const Plan::Balance& b, const void* items, int n, const int32_t* bstart, double* out,
                     hipStream_t s);
@@ -311,7 +308,7 @@ static void adjoint_near(Plan& pl, const double* gb_tree, hipStream_t s)
     Plan::Balance& ba = pl.bal_adj;
     if (ba.cls.empty()) {
         if (pl.split_p2p) {
-            balance_launch(ba, items, nadj, ex.adj_class, pl.nsrc.p, s);
+            balance_launch(ba, items, nadj, ex.adj_class, pl.s_cnt.p, sc.d_box_count.p, s);
             FMM_HIP(hipStreamSynchronize(s));
             balance_finish(ba, nadj, 6, s);
         } else {
@@ -327,7 +324,7 @@ static void adjoint_near(Plan& pl, const double* gb_tree, hipStream_t s)
         const int nx = (int)(x1 - x0);
 #define ACASE(R_, TG_, SUB_)                                                                                  \
     if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
-        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, pl.nsrc.p, ba.partial.p,  \
+        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, ba.partial.p,  \
                                       sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,  \
                                       t.x.p, t.y.p, pl.mtree.p, gb_tree, pl.near_d.p, s);                  \
         check_launch("p2p adjoint");                                                                          \

@@ -4,16 +4,16 @@
 // clustered inputs a few lists hold orders of magnitude more sources than
 // the rest, and one wavefront per leaf would leave the device idle while
 // those few finish.  So every near-field work item (a leaf's group of
-// targets) is cut into chunks of at most kChunkSrc consecutive sources of
-// the concatenated strong list.  A chunk of an item that has one chunk
+// targets) is cut into chunks of chunk_entries(n) consecutive entries of its
+// strong list (n: the leaf's point count), at most kChunkSrc sources each.  A chunk of an item that has one chunk
 // writes its targets directly; the chunks of a split item write partial sums
 // that a combine pass adds in chunk order, so the result stays deterministic.
 //
-// Plan time: per leaf the source count (one wavefront per leaf), per item its
-// chunk count, an exclusive scan, the expanded offsets of every launch class
-// (read by the host at the plan's synchronisation), then the (item, chunk)
-// list.
+// Plan time: per item its chunk count, an exclusive scan, the expanded
+// offsets of every launch class (read by the host at the plan's
+// synchronisation), then the (item, chunk) list.
 #include "fmm_internal.h"
+#include "p2p_common.h"
 #include "plan_extra.h"
 
 namespace fmm {
@@ -22,32 +22,15 @@ struct BalItem {
     int32_t leaf, t0, tn, pad;
 };
 
-// sources of every leaf's strong list
-__global__ void __launch_bounds__(256)
-k_leaf_nsrc(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__ s_beg,
-            const int32_t* __restrict__ s_cnt, const int32_t* __restrict__ s_ids, int64_t pool, int box_cap,
-            const int32_t* __restrict__ box_count, int32_t* nsrc)
-{
-    const int lane = threadIdx.x & 63;
-    const int li = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (li >= nleaf) return;
-    const int g = leaves[li];
-    const int64_t b = s_beg[g];
-    const int n = min(s_cnt[g], box_cap);     // entries actually written
-    long long v = 0;
-    for (int e = lane; e < n && b + e < pool; e += 64) v += box_count[s_ids[b + e]];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) nsrc[g] = (int32_t)(v < INT32_MAX ? v : INT32_MAX);
-}
-
-__global__ void k_item_chunks(const BalItem* __restrict__ items, int n, const int32_t* __restrict__ nsrc,
-                              int32_t* icnt)
+// chunks of every item: its leaf's strong-list entries over chunk_entries
+__global__ void k_item_chunks(const BalItem* __restrict__ items, int n, const int32_t* __restrict__ s_cnt,
+                              const int32_t* __restrict__ bcount, int32_t* icnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int ns = nsrc[items[i].leaf];
-    icnt[i] = ns > kChunkSrc ? (ns + kChunkSrc - 1) / kChunkSrc : 1;
+    const int leaf = items[i].leaf;
+    const int ne = s_cnt[leaf], ce = chunk_entries(bcount[leaf]);
+    icnt[i] = ne > ce ? (ne + ce - 1) / ce : 1;
 }
 
 // exclusive scan of icnt into ioff[0..n] (ioff[n] = total), blocks of 1024
@@ -134,8 +117,20 @@ k_item_combine(const BalItem* __restrict__ items, int n, const int32_t* __restri
     const int64_t o = ioff[i];
     const int64_t dst = (int64_t)bstart[it.leaf] + it.t0 + lane;
     for (int q = 0; q < vals; ++q) {
+        // the values of eight chunks are loaded together, then added in chunk
+        // order (one memory round trip per eight chunks instead of per chunk)
+        const double* pq = part + (o * kItemTargets + lane) * vals + q;
+        const int64_t step = (int64_t)kItemTargets * vals;
         double s = 0.0;
-        for (int k = 0; k < c; ++k) s += part[((o + k) * kItemTargets + lane) * vals + q];
+        int k = 0;
+        for (; k + 8 <= c; k += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = pq[(k + u) * step];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; k < c; ++k) s += pq[k * step];
         out[dst * vals + q] = s;
     }
 }
@@ -144,7 +139,7 @@ k_item_combine(const BalItem* __restrict__ items, int n, const int32_t* __restri
 // offsets; the copy of the class offsets into b.cls completes with the
 // caller's synchronisation.
 void balance_launch(Plan::Balance& b, const void* items, int n, const std::vector<P2PClass>& cls,
-                    const int32_t* nsrc, hipStream_t s)
+                    const int32_t* s_cnt, const int32_t* bcount, hipStream_t s)
 {
     const int ncls = (int)cls.size();
     b.icnt.alloc(std::max(n, 1), s);
@@ -159,7 +154,7 @@ void balance_launch(Plan::Balance& b, const void* items, int n, const std::vecto
     b.d_cls.alloc(ncls + 1, s);
     b.cls.assign(ncls + 1, 0);
     if (n > 0) {
-        k_item_chunks<<<(n + 255) / 256, 256, 0, s>>>((const BalItem*)items, n, nsrc, b.icnt.p);
+        k_item_chunks<<<(n + 255) / 256, 256, 0, s>>>((const BalItem*)items, n, s_cnt, bcount, b.icnt.p);
         k_iscan_reduce<<<nb, 1024, 0, s>>>(b.icnt.p, n, b.bsum.p);
         k_iscan_apply<<<nb, 1024, 0, s>>>(b.icnt.p, n, b.bsum.p, b.ioff.p);
         k_class_offsets<<<1, 64, 0, s>>>(b.ioff.p, b.d_base.p, ncls, b.d_cls.p);
@@ -192,18 +187,6 @@ void combine_chunks(const Plan::Balance& b, const void* items, int n, const int3
     check_launch("combine chunks");
 }
 
-// sources per leaf; box_cap bounds the entries read per list (the per-box
-// capacity of the one-pass list build, whose longer lists are truncated)
-void leaf_sources(Plan& pl, int box_cap, hipStream_t s)
-{
-    TreeSchedule& sc = *pl.tree->sched;
-    pl.nsrc.alloc(sc.nbox, s);
-    const int nl = (int)sc.nleaf;
-    k_leaf_nsrc<<<(nl + 3) / 4, 256, 0, s>>>(pl.ex->leaves.p, nl, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
-                                             (int64_t)pl.s_ids.n, box_cap, sc.d_box_count.p, pl.nsrc.p);
-    check_launch("leaf sources");
-}
-
 // M2L chunks per box from the weak-list length
 __global__ void k_box_chunks(int64_t nbox, const int32_t* __restrict__ w_cnt, int32_t* icnt)
 {
@@ -233,8 +216,7 @@ void plan_balance(Plan& pl, hipStream_t s)
         bp.cls.push_back(n);
         bp.total = n;
     } else {
-        leaf_sources(pl, INT_MAX, s);
-        balance_launch(bp, ex.p2p_items.p, n, ex.p2p_class, pl.nsrc.p, s);
+        balance_launch(bp, ex.p2p_items.p, n, ex.p2p_class, pl.s_cnt.p, sc.d_box_count.p, s);
     }
     if (!pl.split_m2l) {
         bm.xitems.release();

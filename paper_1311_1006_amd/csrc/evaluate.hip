@@ -41,7 +41,7 @@ void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int
                 hipStream_t, int, const long long*);
 void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
                 const int32_t* icnt,
-                const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
                 bool log_kernel);
@@ -371,7 +371,7 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* gua
         const int64_t x0 = b.cls[c], x1 = b.cls[c + 1];
         launch_p2p(mixed, k.tg, k.sub, ex.p2p_items.p, (int)x0, b.xitems.p ? b.xitems.p + x0 : nullptr,
                    (int)(x1 - x0), b.icnt.p, b.ioff.p,
-                   pl.nsrc.p, b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
+                   b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
                    mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard,
                    pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0,

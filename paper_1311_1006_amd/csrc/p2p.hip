@@ -211,7 +211,7 @@ __device__ __forceinline__ int butterfly_index(int lane)
 template <int TG, int SUB, int KERN>
 __global__ void __launch_bounds__(256)
 k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
-        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
@@ -230,8 +230,6 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
     const P2PItem it = items[xe.x];
     const int nch = icnt ? icnt[xe.x] : 1;
-    const int s_first = xe.y * kChunkSrc;
-    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     Src64* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -242,18 +240,18 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double4 v = src[base + (k < it.tn ? k : 0)];
         xi[t] = v.x; yi[t] = v.y; ar[t] = 0.0; ai[t] = 0.0;
     }
-    const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
+    // the item's entries, or those of its chunk
+    const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
+    int e = nch == 1 ? 0 : xe.y * ce, off = 0;
+    const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
         double4 v = src[j];
         Src64 s; s.x = v.x; s.y = v.y; s.mr = v.z; s.mi = v.w;
         return s;
     };
-    int e = 0, off = 0;
-    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
-    for (int done = 0; done < s_len && e < ne;) {
+    while (e < ne) {
         const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
-            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, s_len - done));
-        done += ns;
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
         if (lane < npad - ns) lds[ns + lane] = Src64{0.0, 0.0, 0.0, 0.0};
@@ -298,7 +296,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
 template <int TG, int SUB, int KERN>
 __global__ void __launch_bounds__(256)
 k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
-        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff, const int32_t* __restrict__ nsrc,
+        const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
@@ -317,8 +315,6 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
     const P2PItem it = items[xe.x];
     const int nch = icnt ? icnt[xe.x] : 1;
-    const int s_first = xe.y * kChunkSrc;
-    const int s_len = nch == 1 ? INT_MAX : min(kChunkSrc, nsrc[it.leaf] - s_first);
     Src32* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
@@ -331,19 +327,19 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         float2 b = lo[i];
         xh[t] = a.x; yh[t] = a.y; xl[t] = b.x; yl[t] = b.y; ar[t] = 0.f; ai[t] = 0.f;
     }
-    const int e0 = s_beg[it.leaf], ne = s_cnt[it.leaf];
+    // the item's entries, or those of its chunk
+    const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
+    int e = nch == 1 ? 0 : xe.y * ce, off = 0;
+    const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
         float4 a = src[j];
         float2 b = lo[j];
         Src32 s; s.xh = a.x; s.yh = a.y; s.mr = a.z; s.mi = a.w; s.xl = b.x; s.yl = b.y;
         return s;
     };
-    int e = 0, off = 0;
-    if (s_first > 0) seek_source(s_ids, bcount, e0, ne, s_first, e, off, lane);
-    for (int done = 0; done < s_len && e < ne;) {
+    while (e < ne) {
         const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
-            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, s_len - done));
-        done += ns;
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
         if (lane < npad - ns) lds[ns + lane] = Src32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -386,30 +382,30 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
 
 template <int TG, int SUB, int KERN>
 static void launch_kern(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx,
-                        const int32_t* icnt, const int32_t* ioff, const int32_t* nsrc, double* partial,
+                        const int32_t* icnt, const int32_t* ioff, double* partial,
                         const int32_t* bstart, const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt,
                         const int32_t* s_ids, const void* src, const void* lo, double* out, hipStream_t s,
                         const long long* guard, double id2)
 {
     const int grid = (nx + 3) / 4;
     if (mixed)
-        k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+        k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const float4*)src,
                                                    (const float2*)lo, (double2*)out, guard, (float)id2);
     else
-        k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart,
+        k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
                                                    guard, id2);
 }
 
 template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
-                       const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                       const int32_t* ioff, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                        const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
                        double id2, bool log_kernel)
 {
-#define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
+#define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
              lo, out, s, guard, id2
     if (log_kernel) launch_kern<TG, SUB, kKernLog>(ARGS);
     else if (id2 > 0.0) launch_kern<TG, SUB, kKernSmooth>(ARGS);
@@ -422,7 +418,7 @@ static void launch_one(bool mixed, const P2PItem* items, int item_base, const in
 // without chunk lists (xitems and icnt null), over items item_base + i
 void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
                 const int32_t* icnt,
-                const int32_t* ioff, const int32_t* nsrc, double* partial, const int32_t* bstart,
+                const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
                 bool log_kernel)
@@ -431,7 +427,7 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
-        launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, nsrc, partial, bstart, bcount, s_beg, s_cnt, \
+        launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, \
                               s_ids, src, lo, out, s, guard, id2, log_kernel);                                        \
         check_launch("p2p");                                                                              \
         return;                                                                                           \

@@ -7,6 +7,13 @@
 
 namespace fmm {
 
+// Entries of a strong list per near-field work chunk, for an item whose leaf
+// holds n points.  Every entry of a leaf's strong list is a leaf of the same
+// problem and level, whose point counts differ from n by at most one, so a
+// chunk holds at most kChunkSrc sources; chunk k of a split item starts at
+// entry k * chunk_entries(n), which needs no search of the list.
+__host__ __device__ inline int chunk_entries(int n) { return kChunkSrc / (n + 1) > 1 ? kChunkSrc / (n + 1) : 1; }
+
 // Gather sources of the strong list into LDS, resuming at (entry e, offset
 // off) and stopping after CAP sources (an entry may be split between
 // passes).  Entries are looked at 64 at a time (lane k: entry e + k, its
@@ -82,33 +89,6 @@ __device__ __forceinline__ int stage_sources(SRC* lds, int2* meta, int* mark, co
         wave_sync();
     }
     return staged;
-}
-
-// Entry e and offset off of source ordinal o of the concatenated strong list
-// (entries e0 .. e0 + e_end); e = e_end when o is past the end.
-__device__ __forceinline__ void seek_source(const int32_t* __restrict__ s_ids, const int32_t* __restrict__ bcount,
-                                            int e0, int e_end, int o, int& e, int& off, int lane)
-{
-    e = 0;
-    off = 0;
-    while (e < e_end) {
-        const int k = e + lane;
-        const int c = k < e_end ? bcount[s_ids[e0 + k]] : 0;
-        const int x = wave_incl_scan(c);
-        const int total = __builtin_amdgcn_readlane(x, 63);
-        if (o >= total) {
-            o -= total;
-            e += 64;
-            continue;
-        }
-        const unsigned long long m = __ballot(x > o);
-        const int f = __ffsll((long long)m) - 1;
-        const int xf = __shfl(x, f, 64), cf = __shfl(c, f, 64);
-        e += f;
-        off = o - (xf - cf);
-        return;
-    }
-    e = e_end;
 }
 
 }  // namespace fmm

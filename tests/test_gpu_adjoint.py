@@ -57,12 +57,16 @@ def test_adjoint_matches_direct_gradient(orc, F, prec):
     assert e2(host(gz), rgz) <= tol and einf(host(gz), rgz) <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
-def test_adjoint_with_split_source_lists(orc, F, prec, tol):
-    # one leaf of 5000 points: the adjoint near field is summed in source
-    # chunks and combined; at one level the FMM is the direct sum
-    z, m, _ = W.uniform(5000, seed=11)
-    pl = F.plan(F.build_tree(dev(z), 1), 8, 0.5, prec)
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 40, 1e-11), ("mixed", 16, 1e-6)])
+def test_adjoint_with_split_source_lists(orc, F, prec, p, tol):
+    # four tight clusters: boxes that straddle two clusters have strong lists
+    # of hundreds of leaves, so the adjoint near field is summed in work
+    # chunks of whole list entries whose partial sums are combined in order
+    z, m = W.clustered(20000, seed=3, nclusters=4, sigma=1e-5)
+    L = 6
+    pl = F.plan(F.build_tree(dev(z), L), p, 0.5, prec)
+    off, _ = pl.download_list(0, L - 1, 0)
+    assert np.diff(off).max() > 4 * (2048 // (20000 // 4 ** (L - 1) + 2))
     phi = F.evaluate(pl, dev(m))
     gm, gz = F.evaluate_adjoint(pl, dev(m), 2 * phi)
     rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))

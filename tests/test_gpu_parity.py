@@ -71,6 +71,11 @@ def test_clustered_long_lists_match_oracle(orc, F):
     for _ in range(2):   # the first plan learns the layout, the second uses it
         pl = F.plan(tree, 12, 0.5, "fp64")
         _lists_equal(orc, F, pl, geom, L, 0.5)
+    # the longest leaf lists are cut into several work chunks (chunks of
+    # 2048 / (points per leaf + 1) entries)
+    off, _ = pl.download_list(0, L - 1, 0)
+    npl = 100000 // 4 ** (L - 1)
+    assert np.diff(off).max() > 4 * (2048 // (npl + 2))
     phi = host(F.evaluate(pl, dev(m)))
     assert e2(phi, orc.fmm(z, m, 12, 0.5, L)) <= 1e-12
     # a fresh plan evaluated at once: the upward pass is enqueued before the
@@ -163,8 +168,9 @@ def test_fp64_single_level_is_direct_sum(orc, F):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 1e-6)])
 def test_split_source_lists_match_direct_sum(orc, F, prec, tol):
-    # one leaf of 5000 points: every near-field work item sums over 5000
-    # sources, split into chunks whose partial sums are combined in order
+    # one leaf of 5000 points: every near-field work item sums over a strong
+    # list of one entry with 5000 sources (a list is cut into chunks of whole
+    # entries, so this one is not cut)
     z, m, _ = W.uniform(5000, seed=6)
     pl = F.plan(F.build_tree(dev(z), 1), 8, 0.5, prec)
     phi = host(F.evaluate(pl, dev(m)))
