@@ -4,10 +4,11 @@
 // are the children of the boxes strongly coupled to its parent; a candidate
 // is weak (an M2L partner at this level) when the theta-criterion (2.3)
 // R + theta r <= theta d holds and strong otherwise; a box is always strong
-// with itself.  Each level is three kernels: count, exclusive scan (one
-// workgroup; it also offsets the level into the id pools), fill.  Fills are
-// bounds-checked against the pool capacity; an overflow flag makes the host
-// grow the pools and run the build again.
+// with itself.  The usual build is one pass with fixed per-box capacities;
+// otherwise every pass (a range of levels, or one level) is three kernels:
+// count, exclusive scan (it also offsets the pass into the id pools), fill.
+// Fills are bounds-checked against the pool capacity; an overflow flag makes
+// the host grow the pools and run the build again.
 #include <algorithm>
 #include <climits>
 #include <utility>
@@ -33,64 +34,6 @@ __device__ __forceinline__ bool well_separated(const double* gb, const double* g
     double tt = (t * t);
     double rhs = ((theta * theta) * s);
     return (s > 0.0) && (tt <= rhs);
-}
-
-struct LevelCtx {
-    const int32_t* boxes;     // global ids of this level's boxes
-    int n;
-    const int32_t* parent;
-    const int32_t* prob;
-    const int64_t* pbox;      // first box id per problem
-    int64_t lb, lbp;          // level_base(l), level_base(l-1)
-    const double* geom;       // [nbox][4] cx cy r rs
-    double theta;
-};
-
-// One wavefront per box: lanes take the candidates (children of the parent's
-// strong boxes, in ascending order) 64 at a time; ballots count them and,
-// in the fill pass, give every strong / weak candidate its ordered slot.
-template <bool FILL>
-__global__ void __launch_bounds__(256)
-k_level(LevelCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
-        int32_t* w_ids, int64_t cap_s, int64_t cap_w)
-{
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= c.n) return;
-    const int32_t g = c.boxes[i];
-    const int32_t P = c.parent[g];
-    const int64_t pb = c.pbox[c.prob[g]];
-    const double* gg = c.geom + 4 * (int64_t)g;
-    const int32_t ps = s_beg[P], pn = s_cnt[P];
-    const int ncand = 4 * pn;
-    int64_t sb = 0, wb = 0;
-    if (FILL) { sb = s_beg[g]; wb = w_beg[g]; }
-    int ns = 0, nw = 0;
-    for (int c0 = 0; c0 < ncand; c0 += 64) {
-        const int idx = c0 + lane;
-        bool valid = idx < ncand && (int64_t)ps + (idx >> 2) < cap_s;
-        bool weak = false;
-        int32_t cc = 0;
-        if (valid) {
-            const int32_t q = s_ids[ps + (idx >> 2)];
-            cc = (int32_t)(pb + c.lb + 4 * ((int64_t)q - pb - c.lbp) + (idx & 3));
-            weak = (cc != g) && well_separated(gg, c.geom + 4 * (int64_t)cc, c.theta);
-        }
-        const unsigned long long bw = __ballot(valid && weak), bs = __ballot(valid && !weak);
-        if (FILL && valid) {
-            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            if (weak) {
-                int64_t o = wb + nw + __popcll(bw & below);
-                if (o < cap_w) w_ids[o] = cc;
-            } else {
-                int64_t o = sb + ns + __popcll(bs & below);
-                if (o < cap_s) s_ids[o] = cc;
-            }
-        }
-        nw += __popcll(bw);
-        ns += __popcll(bs);
-    }
-    if (!FILL && lane == 0) { s_cnt[g] = ns; w_cnt[g] = nw; }
 }
 
 // Exclusive scan of the level's counts into pool offsets, in two passes over
@@ -166,18 +109,6 @@ k_scan_apply(const int32_t* boxes, int n, const int32_t* s_cnt, const int32_t* w
     }
 }
 
-__global__ void k_root_lists(const int32_t* roots, int n, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg,
-                             int32_t* w_cnt, int32_t* s_ids, long long* totals)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        int32_t r = roots[i];
-        s_beg[r] = i; s_cnt[r] = 1; s_ids[i] = r;
-        w_beg[r] = 0; w_cnt[r] = 0;
-    }
-    if (i == 0) { totals[0] = n; totals[1] = 0; totals[2] = 0; totals[3] = 0; }
-}
-
 // pairs of the near field: sum over leaves of n_T * (points of its strong
 // list); one wavefront per leaf, lanes over the list
 __global__ void __launch_bounds__(256)
@@ -217,8 +148,8 @@ k_count_p2p(const int32_t* leaves, int n, const int32_t* box_count, const int32_
 // level-by-level build gives.  A pass is count, scan, fill, so a few passes
 // replace four launches per level; a deeper pass repeats the upper levels of
 // its range once per box, so the passes are kept short near the leaves.  A
-// frontier larger than kFrontCap sets bit 1 of the overflow word and the
-// level-by-level build runs instead.
+// frontier larger than kFrontCap sets bit 1 of the overflow word; the layout
+// is then built one level per pass (k_traverse_sib below the root).
 constexpr int kFrontCap = 1024;
 
 struct TravCtx {
@@ -375,25 +306,37 @@ static void check_tree_flag(long long flag)
 }
 
 // Level ranges of the passes: the three deepest levels one at a time (by
-// sibling groups), everything above them in one pass from the root.
-static std::vector<std::pair<int, int>> traversal_passes(int levels)
+// sibling groups), everything above them in one pass from the root; or, for
+// a layout whose frontiers overflowed, every level on its own.
+static std::vector<std::pair<int, int>> traversal_passes(int levels, bool single = false)
 {
     std::vector<std::pair<int, int>> r;
     const int top = levels - 1;
+    if (single) {
+        // one level per pass (sibling groups below the root): no frontier,
+        // lists of any length
+        for (int l = 0; l <= top; ++l) r.push_back({l, l});
+        return r;
+    }
     if (levels <= 4) { r.push_back({0, top}); return r; }
     r.push_back({0, top - 3});
     for (int l = top - 2; l <= top; ++l) r.push_back({l, l});
     return r;
 }
 
-// A single level l >= 1 (the pass of the finest level), one wavefront per
-// group of four siblings: every candidate (a child of an entry of the
-// parent's strong list, read from the pool, so the list may have any length)
-// is loaded once and tested against the four siblings; each sibling's strong
-// and weak lists are compacted by ballots in candidate order, as in
-// k_traverse.  MODE 0 counts, MODE 1 fills at the scanned offsets, MODE 2
-// fills at fixed per-box capacities and also counts each leaf's near-field
-// sources and raises the chunk flags.
+// Candidates taken per loop trip of k_traverse_sib: four groups of 64 whose
+// id and geometry loads are all issued before the first test, so a long
+// parent list costs one memory round trip per 256 candidates.
+constexpr int kCandGroups = 4;
+
+// A single level l >= 1, one wavefront per group of four siblings: every
+// candidate (a child of an entry of the parent's strong list, read from the
+// pool, so the list may have any length) is loaded once and tested against
+// the four siblings; each sibling's strong and weak lists are compacted by
+// ballots in candidate order, as in k_traverse.  MODE 0 counts, MODE 1 fills
+// at the scanned offsets, MODE 2 fills at fixed per-box capacities and also
+// counts each leaf's near-field sources and raises the chunk flags.
+
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids,
@@ -429,43 +372,52 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
     int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
     long long src[4] = {0, 0, 0, 0};
     const int64_t ncand = 4 * (int64_t)nf;
-    for (int64_t c0 = 0; c0 < ncand; c0 += 64) {
-        const int64_t idx = c0 + lane;
-        bool valid = idx < ncand;
-        int32_t cc = 0;
-        double cg[4] = {0.0, 0.0, 0.0, 0.0};
-        long long cnt = 0;
-        if (valid) {
+    for (int64_t c0 = 0; c0 < ncand; c0 += 64 * kCandGroups) {
+        bool valid[kCandGroups];
+        int32_t cc[kCandGroups];
+        double cg[kCandGroups][4];
+        long long cnt[kCandGroups];
+#pragma unroll
+        for (int u = 0; u < kCandGroups; ++u) {
+            const int64_t idx = c0 + 64 * u + lane;
+            valid[u] = idx < ncand;
             const int64_t e = ab + (idx >> 2);
-            const int32_t q = e < cap_s ? s_ids[e] : (int32_t)pb;
+            int32_t q = (int32_t)(pb + lbp);
+            if (valid[u]) q = e < cap_s ? s_ids[e] : (int32_t)pb;
             const int64_t qj = (int64_t)q - pb - lbp;
-            if (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1)))) {
-                valid = false;                          // not a box of that level: never
+            if (valid[u] && (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1))))) {
+                valid[u] = false;                       // not a box of that level: never
                 overflow = true;                        // dereferenced, list rebuilt
-            } else {
-                cc = (int32_t)(pb + lb + 4 * qj + (idx & 3));
-                const double* gc = c.geom + 4 * (int64_t)cc;
-                cg[0] = gc[0]; cg[1] = gc[1]; cg[2] = gc[2];
-                if (MODE == 2) cnt = c.box_count[cc];
             }
+            cc[u] = valid[u] ? (int32_t)(pb + lb + 4 * qj + (idx & 3)) : (int32_t)g0;
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
-            const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
-            const bool strong = valid && !weak;
-            const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
-            if (FILL && strong) {
-                const int64_t o = sb[t] + ns[t] + __popcll(bs & below);
-                if (o < ls[t]) s_ids[o] = cc;
+        for (int u = 0; u < kCandGroups; ++u) {
+            const double* gc = c.geom + 4 * (int64_t)(valid[u] ? cc[u] : (int32_t)g0);
+            cg[u][0] = gc[0]; cg[u][1] = gc[1]; cg[u][2] = gc[2]; cg[u][3] = 0.0;
+            cnt[u] = MODE == 2 && valid[u] ? c.box_count[cc[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCandGroups; ++u) {
+            if (c0 + 64 * u >= ncand) break;       // uniform: no candidate left
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
+                const bool weak = valid[u] && (cc[u] != g0 + t) && well_separated(gb, cg[u], c.theta);
+                const bool strong = valid[u] && !weak;
+                const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
+                if (FILL && strong) {
+                    const int64_t o = sb[t] + ns[t] + __popcll(bs & below);
+                    if (o < ls[t]) s_ids[o] = cc[u];
+                }
+                if (FILL && weak) {
+                    const int64_t o = wb[t] + nw[t] + __popcll(bw & below);
+                    if (o < lw[t]) w_ids[o] = cc[u];
+                }
+                if (MODE == 2 && strong) src[t] += cnt[u];
+                ns[t] += __popcll(bs);
+                nw[t] += __popcll(bw);
             }
-            if (FILL && weak) {
-                const int64_t o = wb[t] + nw[t] + __popcll(bw & below);
-                if (o < lw[t]) w_ids[o] = cc;
-            }
-            if (MODE == 2 && strong) src[t] += cnt;
-            ns[t] += __popcll(bs);
-            nw[t] += __popcll(bw);
         }
     }
     if (MODE == 2) {
@@ -500,13 +452,13 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
 }
 
 static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_t cap_w, long long* totals,
-                                  const int64_t* pbox, long long* bsum, long long* snap)
+                                  const int64_t* pbox, long long* bsum, long long* snap, bool single)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const PlanExtra& ex = *pl.ex;
     k_totals_init<<<1, 64, 0, s>>>(totals, t.err.p);
-    for (auto [l0, l1] : traversal_passes(sc.max_levels)) {
+    for (auto [l0, l1] : traversal_passes(sc.max_levels, single)) {
         TravCtx c;
         c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
         c.n = (int)(ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]);
@@ -731,72 +683,37 @@ void build_lists_finish(Plan& pl)
     }
     DBuf<long long> snap; snap.alloc(2, s);
     DBuf<long long> bsum; bsum.alloc(2 * ((nb + 1023) / 1024), s);
-    int64_t cap_s = std::max<int64_t>(pl.n_strong, 24 * nb + 1024);
-    int64_t cap_w = std::max<int64_t>(pl.n_weak, 64 * nb + 1024);
-    bool levelwise = ex.levelwise_only;
+    // pool sizes: a per-box guess, or the totals of the last build of this
+    // layout grown by a quarter when larger, so that a layout whose lists
+    // outgrow the guess (clustered points) is built once, not twice
+    int64_t cap_s = std::max<int64_t>({pl.n_strong, 24 * nb + 1024, ex.pool_strong});
+    int64_t cap_w = std::max<int64_t>({pl.n_weak, 64 * nb + 1024, ex.pool_weak});
+    bool single = ex.levelwise_only;
     for (int attempt = 0; attempt < 4; ++attempt) {
         pl.s_ids.alloc(cap_s, s);
         pl.w_ids.alloc(cap_w, s);
-        if (!levelwise) {
-            build_lists_traversal(pl, s, cap_s, cap_w, totals_p, pbox_p, bsum.p, snap.p);
-            long long h[4];
-            FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
-            FMM_HIP(hipStreamSynchronize(s));
-            check_tree_flag(h[2]);
-            if (h[2] & 2) {                 // a frontier overflowed
-                levelwise = true;
-                ex.levelwise_only = true;
-                continue;
-            }
-            pl.n_strong = h[0];
-            pl.n_weak = h[1];
-            pl.totals_known = false;        // the pair count is summed on request
-            if (!(h[2] & 1)) {
-                if (grow) grow_capacities(pl, s);
-                pl.split_p2p = pl.split_m2l = true;   // decided by the chunk counts
-                return;
-            }
-            cap_s = h[0] + h[0] / 4 + 1024;
-            cap_w = h[1] + h[1] / 4 + 1024;
-            continue;
-        }
-        const int32_t* lv = pl.ex->d_level_boxes.p;
-        int nroot = (int)pl.ex->level_boxes[0].size();
-        k_root_lists<<<(nroot + 255) / 256, 256, 0, s>>>(lv, nroot, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p,
-                                                         pl.w_cnt.p, pl.s_ids.p, totals_p);
-        check_launch("root lists");
-        for (int l = 1; l < sc.max_levels; ++l) {
-            LevelCtx c;
-            c.boxes = lv + pl.ex->level_boxes_off[l];
-            c.n = (int)pl.ex->level_boxes[l].size();
-            if (c.n == 0) continue;
-            c.parent = sc.d_box_parent.p; c.prob = sc.d_box_prob.p; c.pbox = pbox_p;
-            c.lb = level_base(l); c.lbp = level_base(l - 1);
-            c.geom = t.geom.p; c.theta = pl.theta;
-            int g = (c.n + 3) / 4;
-            k_level<false><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
-                                             pl.w_ids.p, cap_s, cap_w);
-            int nb = (c.n + 1023) / 1024;
-            k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, totals_p, snap.p);
-            k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum.p, snap.p, pl.s_beg.p,
-                                             pl.w_beg.p, totals_p, cap_s, cap_w);
-            k_level<true><<<g, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
-                                            pl.w_ids.p, cap_s, cap_w);
-            check_launch("level lists");
-        }
+        build_lists_traversal(pl, s, cap_s, cap_w, totals_p, pbox_p, bsum.p, snap.p, single);
         long long h[4];
         FMM_HIP(hipMemcpyAsync(h, totals_p, sizeof(h), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
         check_tree_flag(h[2]);
+        if ((h[2] & 2) && !single) {        // a frontier overflowed: one level per pass
+            single = true;
+            ex.levelwise_only = true;
+            continue;
+        }
         pl.n_strong = h[0];
         pl.n_weak = h[1];
         pl.totals_known = false;            // the pair count is summed on request
-        if (!h[2]) {
-            pl.split_p2p = pl.split_m2l = true;       // decided by the chunk counts
+        ex.pool_strong = h[0] + h[0] / 4 + 1024;
+        ex.pool_weak = h[1] + h[1] / 4 + 1024;
+        if (!(h[2] & 3)) {
+            if (grow) grow_capacities(pl, s);
+            pl.split_p2p = pl.split_m2l = true;   // decided by the chunk counts
             return;
         }
-        cap_s = h[0] + h[0] / 4 + 1024;
-        cap_w = h[1] + h[1] / 4 + 1024;
+        cap_s = ex.pool_strong;
+        cap_w = ex.pool_weak;
     }
     throw Error(FMM_EDEVICE, "connectivity lists did not fit after growing the pools");
 }

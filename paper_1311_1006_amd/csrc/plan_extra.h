@@ -24,6 +24,7 @@ struct PlanExtra {
     bool gather_in_p2m = false;                     // the leaves hold every point: P2M does the gather
     int cap_strong = 0, cap_weak = 0;               // per-box list capacities of the one-pass build
     bool levelwise_only = false;                    // a frontier overflowed on this layout
+    int64_t pool_strong = 0, pool_weak = 0;        // id pool sizes for the next compact build
     bool compact_only = false;                      // fixed capacities would need too much memory
     DBuf<double> binom;                             // binomial table C(n, k), n, k < 64
     std::vector<std::vector<int32_t>> m2m_boxes;   // non-leaf boxes per level
