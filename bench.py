@@ -379,7 +379,29 @@ def measure_forms(F, W, torch, dev, reps, with_errors):
         out["log_n1e6_" + prec] = rec
         log("log kernel N=1e6 (%s, p=13): evaluate_log %.3f ms%s" % (prec, tl * 1e3,
             ", e2 %.2e" % rec["e2"] if "e2" in rec else ""))
-    del tree, phi, dphi
+    # evaluation points apart from the sources (fmm_evaluate_points, eq. 2.2):
+    # the same tree and 1e6 uniform points of their own
+    yp = np.random.default_rng(5)
+    y = yp.random(z.size) + 1j * yp.random(z.size)
+    ydev = torch.from_numpy(y).to(dev)
+    for prec in ("mixed", "fp64"):
+        pl = F.plan(tree, 13, 0.5, prec)
+        py = torch.empty_like(ydev)
+        te = _time(lambda: F.evaluate(pl, md, phi), reps, torch)
+        tp = _time(lambda: F.evaluate_points(pl, md, ydev, out=py), reps, torch)
+        rec = {"p": 13, "n_levels": 9, "n_points": int(y.size), "evaluate_ms": te * 1e3, "points_ms": tp * 1e3,
+               "mpoints_s": y.size / tp / 1e6}
+        if with_errors:
+            import oracle
+            sub = W.subsample(y.size, 2000, seed=6)
+            ref = oracle.direct_points(z, m, y[sub])
+            got = py.cpu().numpy()[sub]
+            rec["e2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            rec["e_inf"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+        out["points_n1e6_" + prec] = rec
+        log("evaluation points N=1e6 sources, 1e6 points (%s, p=13): evaluate_points %.3f ms (evaluate %.3f ms)%s"
+            % (prec, tp * 1e3, te * 1e3, ", e2 %.2e" % rec["e2"] if "e2" in rec else ""))
+    del tree, phi, dphi, ydev
     z, m, _ = W.uniform(200000, seed=0)
     zd = torch.from_numpy(z).to(dev)
     md = torch.from_numpy(m).to(dev)

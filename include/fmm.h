@@ -226,14 +226,44 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
  * the velocity, Sec. 5.1).  The near field is summed directly over the strong
  * lists, the far field is the derivative of each leaf's local expansion (Sec.
  * 2.1), whose truncation error is larger than that of phi by roughly the
- * factor p.  Evaluation points apart from the sources (eq. 2.2): build the
- * tree over the sources and the evaluation points together, the latter with
- * zero strength; the values at those points are the field of the sources
- * alone (a source at the position of an evaluation point is left out, as in
- * eq. 2.2).  phi, dphi: device complex128 [N], input order.  Errors as for
+ * factor p.  Evaluation points apart from the sources: fmm_evaluate_points.
+ * phi, dphi: device complex128 [N], input order.  Errors as for
  * fmm_evaluate.
  */
 int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi, void* stream);
+
+/*
+ * fmm_evaluate_points -- the field of the sources at M evaluation points
+ * apart from them (eq. 2.2),
+ *     phi_y[i] = sum_{x_j != y_i} m_j / (y_i - x_j),
+ * and, when dphi_y is not NULL, its derivative
+ *     dphi_y[i] = -sum_{x_j != y_i} m_j / (y_i - x_j)^2.
+ * The plan is one over the sources' tree (Sec. 2.2) and lists (Sec. 2.1):
+ * the points join neither, so they change no box and no list of the
+ * sources.  Each point goes down the tree into the deepest box B whose
+ * bounding box holds it; B's complete local expansion gives the field of the
+ * sources outside B's strong list (it converges there: the point lies in the
+ * boxes the theta-criterion was applied to), and each box of that list is
+ * descended: a box well separated from the point (criterion (2.3) for a box
+ * of radius zero) adds its multipole expansion at the point, a leaf that is
+ * not adds its sources directly, other boxes are opened.  A point outside
+ * the root's box is handled from the root down.  Accuracy as for
+ * fmm_evaluate at the plan's p and theta.
+ *   pl      a plan over a tree of ONE problem (else FMM_EINVAL) without a
+ *           smoothed near field (else FMM_EINVAL);
+ *   m       DEVICE, complex [N] source strengths, input order;
+ *   y       DEVICE, complex [M] evaluation points;
+ *   phi_y   DEVICE, complex [M] output;
+ *   dphi_y  DEVICE, complex [M] output, or NULL for none;
+ *   M       0 <= M < 2^31 - 1; M = 0: nothing is done.
+ * A point that is not finite receives NaN.  The call allocates device
+ * memory for the point order (8 B per point and 12 B per box), and leaves
+ * the far field of m in the plan's buffers, not a forward evaluation:
+ * fmm_evaluate_adjoint then needs a new fmm_evaluate first.  Errors:
+ * FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE.
+ */
+int fmm_evaluate_points(fmm_plan_t pl, const double* m, const double* y, int64_t M, double* phi_y, double* dphi_y,
+                        void* stream);
 
 /*
  * fmm_evaluate_log -- the logarithmic potential, the second kernel of the

@@ -102,6 +102,7 @@ def lib():
         "fmm_choose_order": (C.c_int, [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, vp,
                                        C.POINTER(C.c_int), dp]),
         "fmm_last_error": (C.c_char_p, []),
+        "fmm_evaluate_points": (C.c_int, [vp, vp, vp, C.c_int64, vp, vp, vp]),
         "fmm_debug_fail_alloc": (C.c_int, [C.c_int64]),
         "fmm_debug_live_blocks": (C.c_int, [i64p]),
     }
@@ -310,25 +311,31 @@ def evaluate_log(pl, q, out=None, stream=None):
     return out
 
 
+def evaluate_points(pl, m, y, field=False, out=None, stream=None):
+    """The field of the plan's sources (strengths m) at evaluation points y
+    apart from them (eq. 2.2; fmm_evaluate_points).  Returns phi at y, or
+    (phi, dphi) with field=True."""
+    import torch
+    m, y = _dev_complex(m, "m"), _dev_complex(y, "y")
+    phi = torch.empty_like(y) if out is None else out
+    dphi = torch.empty_like(y) if field else None
+    _check(lib().fmm_evaluate_points(pl._h, C.c_void_p(m.data_ptr()), C.c_void_p(y.data_ptr()), y.numel(),
+                                     C.c_void_p(phi.data_ptr()), C.c_void_p(dphi.data_ptr() if field else None),
+                                     _stream(stream)))
+    return (phi, dphi) if field else phi
+
+
 def evaluate_at(z, m, y, p=16, theta=0.5, n_levels=None, precision="fp64", field=False, stream=None):
     """The field of the sources (z, m) at separate evaluation points y (eq.
-    2.2): one tree over sources and points, the points with zero strength; a
-    source at the position of an evaluation point is left out.  Returns phi
-    at y, or (phi, dphi) with field=True."""
-    import torch
+    2.2): a tree and a plan over the sources alone, then fmm_evaluate_points.
+    Returns phi at y, or (phi, dphi) with field=True."""
     z, m, y = _dev_complex(z, "z"), _dev_complex(m, "m"), _dev_complex(y, "y")
-    n = z.numel()
-    zz = torch.cat([z, y])
-    mm = torch.cat([m, torch.zeros_like(y)])
     if n_levels is None:
         from .driver import default_levels
-        n_levels = default_levels(zz.numel())
-    tr = build_tree(zz, n_levels, stream=stream)
+        n_levels = default_levels(z.numel())
+    tr = build_tree(z, n_levels, stream=stream)
     pl = plan(tr, p, theta, precision, stream=stream)
-    if field:
-        phi, dphi = evaluate_field(pl, mm, stream=stream)
-        return phi[n:], dphi[n:]
-    return evaluate(pl, mm, stream=stream)[n:]
+    return evaluate_points(pl, m, y, field=field, stream=stream)
 
 
 def evaluate_parts(pl, m, stream=None):

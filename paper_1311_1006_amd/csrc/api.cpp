@@ -554,6 +554,21 @@ int fmm_evaluate_parts(fmm_plan_t pl, const double* m, double* phi_near, double*
     });
 }
 
+int fmm_evaluate_points(fmm_plan_t pl, const double* m, const double* y, int64_t M, double* phi_y, double* dphi_y,
+                        void* stream)
+{
+    return guarded([&] {
+        FMM_REQUIRE(pl && m, "NULL argument");
+        FMM_REQUIRE(M >= 0, "M must be >= 0");
+        FMM_REQUIRE(M == 0 || (y && phi_y), "NULL points or output");
+        FMM_REQUIRE(pl->pl.tune.smooth_delta == 0.0, "a smoothed near field is evaluated by fmm_evaluate only");
+        check_device_state();
+        plan_finalize(pl->pl);
+        plan_join(pl->pl, (hipStream_t)stream);
+        evaluate_points_device(pl->pl, m, y, M, phi_y, dphi_y, (hipStream_t)stream);
+    });
+}
+
 int fmm_evaluate_field(fmm_plan_t pl, const double* m, double* phi, double* dphi, void* stream)
 {
     return guarded([&] {

@@ -84,6 +84,16 @@ k_iscan_apply(const int32_t* __restrict__ v, int n, const int32_t* __restrict__ 
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = base + tot;
 }
 
+// exclusive scan of n int32 values into out[0..n] (out[n] = total); bsum
+// holds (n + 1023) / 1024 block sums
+void launch_exclusive_scan(const int32_t* v, int n, int32_t* bsum, int32_t* out, hipStream_t s)
+{
+    const int nb = (n + 1023) / 1024;
+    k_iscan_reduce<<<nb, 1024, 0, s>>>(v, n, bsum);
+    k_iscan_apply<<<nb, 1024, 0, s>>>(v, n, bsum, out);
+    check_launch("exclusive scan");
+}
+
 // expanded offsets of the launch classes: out[c] = ioff[base[c]]
 __global__ void k_class_offsets(const int32_t* __restrict__ ioff, const int64_t* __restrict__ base, int ncls,
                                 int64_t* out)

@@ -44,7 +44,7 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel);
+                bool log_kernel, const Targets& tgt = Targets{});
 
 bool subtree_ok(int L, int p);
 template <class T>
@@ -437,6 +437,29 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
         run_m2m<double>(pl, ex, pl.mpole.p, s);
     }
     pl.upward_done = true;
+}
+
+// The far field of every box and nothing at the sources: the upward pass
+// (with the gather of the source records) and the M2L / L2L sweep over every
+// level, so that the multipole expansion and the complete local expansion of
+// every box are in the plan's buffers (evaluation at points apart from the
+// sources).
+void far_field_all(Plan& pl, const double* m, hipStream_t s)
+{
+    PlanExtra& ex = *extra(pl);
+    PhaseTimer tm(false, s);
+    pl.upward_done = false;
+    if (pl.precision == FMM_MIXED) {
+        run_p2m<float>(pl, ex, m, s);
+        run_m2m<float>(pl, ex, pl.mpole.p, s);
+        run_far_down<float>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
+    } else {
+        run_p2m<double>(pl, ex, m, s);
+        run_m2m<double>(pl, ex, pl.mpole.p, s);
+        run_far_down<double>(pl, ex, pl.mpole.p, pl.local.p, s, tm, nullptr, true);
+    }
+    // the plan's buffers now hold the far field of m, not a forward evaluation
+    pl.have_forward = false;
 }
 
 void launch_real_to_complex(int64_t n, const double* q, double* m, hipStream_t s);

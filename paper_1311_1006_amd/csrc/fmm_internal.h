@@ -50,6 +50,17 @@ constexpr int kCandCap = 2048;     // candidates sorted in LDS by one workgroup
 constexpr int kLdsCap = 4096;      // segments at most this large finish in one workgroup
 constexpr int kChunkSrc = 2048;    // near-field sources per work chunk (longer lists are split)
 constexpr int kItemTargets = 32;   // targets per near-field work item, at most
+
+// Targets of the near-field kernels other than the leaves' own points
+// (evaluation points apart from the sources): records in the format of the
+// source records (FP64 double4 x, y, -, -; mixed float4 x_hi, y_hi, -, - with
+// float2 x_lo, y_lo), sorted by leaf, start[g] = the first target of leaf g.
+// start == nullptr: the targets are the leaves' own points.
+struct Targets {
+    const void* src = nullptr;
+    const float2* lo = nullptr;
+    const int32_t* start = nullptr;
+};
 constexpr int kChunkPairs = 128;   // M2L weak pairs per work chunk (longer lists are split)
 
 __host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
@@ -277,6 +288,8 @@ void list_totals_device(Plan& pl, hipStream_t s);
 void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, double* phi_far,
                      hipStream_t s, hipEvent_t lists_ev = nullptr, const long long* guard = nullptr);
 void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStream_t s);
+void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t M, double* phi, double* dphi,
+                            hipStream_t s);
 // fmm_evaluate_static: the evaluation with its working buffers in the fixed
 // device array of static_eval.hip, and the bytes of that array it needs
 void evaluate_static(Plan& pl, const double* m, double* phi, hipStream_t s);

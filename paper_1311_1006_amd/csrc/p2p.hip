@@ -215,7 +215,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
-        const long long* __restrict__ guard, double id2)
+        const long long* __restrict__ guard, double id2, const Targets tgt)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -229,15 +229,18 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
     const P2PItem it = items[xe.x];
+    if (it.tn == 0) return;                        // a spare item of a device-built list
     const int nch = icnt ? icnt[xe.x] : 1;
     Src64* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
-    const int base = bstart[it.leaf] + it.t0;
+    // the targets: the leaf's own points, or evaluation points apart from the sources
+    const int base = (tgt.start ? tgt.start : bstart)[it.leaf] + it.t0;
+    const double4* tsrc = tgt.start ? (const double4*)tgt.src : src;
     double xi[TG], yi[TG], ar[TG], ai[TG];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
-        double4 v = src[base + (k < it.tn ? k : 0)];
+        double4 v = tsrc[base + (k < it.tn ? k : 0)];
         xi[t] = v.x; yi[t] = v.y; ar[t] = 0.0; ai[t] = 0.0;
     }
     // the item's entries, or those of its chunk
@@ -300,7 +303,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
-        double2* __restrict__ out, const long long* __restrict__ guard, float id2)
+        double2* __restrict__ out, const long long* __restrict__ guard, float id2, const Targets tgt)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -314,17 +317,21 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     // (item, source chunk); without chunk lists every item is one chunk
     const int2 xe = xitems ? xitems[xi_] : make_int2(item_base + xi_, 0);
     const P2PItem it = items[xe.x];
+    if (it.tn == 0) return;                        // a spare item of a device-built list
     const int nch = icnt ? icnt[xe.x] : 1;
     Src32* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
-    const int base = bstart[it.leaf] + it.t0;
+    // the targets: the leaf's own points, or evaluation points apart from the sources
+    const int base = (tgt.start ? tgt.start : bstart)[it.leaf] + it.t0;
+    const float4* tsrc = tgt.start ? (const float4*)tgt.src : src;
+    const float2* tlo = tgt.start ? tgt.lo : lo;
     float xh[TG], yh[TG], xl[TG], yl[TG], ar[TG], ai[TG];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
         int i = base + (k < it.tn ? k : 0);
-        float4 a = src[i];
-        float2 b = lo[i];
+        float4 a = tsrc[i];
+        float2 b = tlo[i];
         xh[t] = a.x; yh[t] = a.y; xl[t] = b.x; yl[t] = b.y; ar[t] = 0.f; ai[t] = 0.f;
     }
     // the item's entries, or those of its chunk
@@ -385,17 +392,17 @@ static void launch_kern(bool mixed, const P2PItem* items, int item_base, const i
                         const int32_t* icnt, const int32_t* ioff, double* partial,
                         const int32_t* bstart, const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt,
                         const int32_t* s_ids, const void* src, const void* lo, double* out, hipStream_t s,
-                        const long long* guard, double id2)
+                        const long long* guard, double id2, const Targets& tgt)
 {
     const int grid = (nx + 3) / 4;
     if (mixed)
         k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                                   (const float2*)lo, (double2*)out, guard, (float)id2);
+                                                   (const float2*)lo, (double2*)out, guard, (float)id2, tgt);
     else
         k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
-                                                   guard, id2);
+                                                   guard, id2, tgt);
 }
 
 template <int TG, int SUB>
@@ -403,10 +410,10 @@ static void launch_one(bool mixed, const P2PItem* items, int item_base, const in
                        const int32_t* ioff, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                        const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
-                       double id2, bool log_kernel)
+                       double id2, bool log_kernel, const Targets& tgt)
 {
 #define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
-             lo, out, s, guard, id2
+             lo, out, s, guard, id2, tgt
     if (log_kernel) launch_kern<TG, SUB, kKernLog>(ARGS);
     else if (id2 > 0.0) launch_kern<TG, SUB, kKernSmooth>(ARGS);
     else launch_kern<TG, SUB, kKernPlain>(ARGS);
@@ -421,14 +428,14 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel)
+                bool log_kernel, const Targets& tgt)
 {
     if (nx == 0) return;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s, guard, id2, log_kernel);                                        \
+                              s_ids, src, lo, out, s, guard, id2, log_kernel, tgt);                                   \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }

@@ -10,6 +10,7 @@ namespace fmm {
 void plan_events(Plan&) { no_device(); }
 hipStream_t side_stream(int, int) { no_device(); }
 void field_device(Plan&, const double*, double*, double*, hipStream_t) { no_device(); }
+void evaluate_points_device(Plan&, const double*, const double*, int64_t, double*, double*, hipStream_t) { no_device(); }
 void plan_balance(Plan&, hipStream_t) { no_device(); }
 TreeSchedule* make_schedule(const std::vector<int64_t>&, const std::vector<int>&) { no_device(); }
 void adjoint_device(Plan&, const double*, const double*, double*, double*, hipStream_t) { no_device(); }

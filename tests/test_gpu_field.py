@@ -77,7 +77,7 @@ def test_separate_evaluation_points(F, orc):
     y = rng.random(5000) + 1j * rng.random(5000)
     y[:10] = z[:10]
     y[10:20] = 2.0 + 1j * rng.random(10)          # outside the sources' square
-    phi, dphi = F.evaluate_at(dev(z), dev(m), dev(y), p=30, field=True)
+    phi, dphi = F.evaluate_at(dev(z), dev(m), dev(y), p=40, field=True)
     assert e2(host(phi), orc.direct_points(z, m, y)) <= 1e-12
     assert e2(host(dphi), orc.direct_deriv_points(z, m, y)) <= 1e-12
     phim = F.evaluate_at(dev(z), dev(m), dev(y), p=16, precision="mixed")
