@@ -86,7 +86,12 @@ typedef struct {
                         wavefront and its blocks; with 1 every MFMA column is one box);
                         automatic: 8 mixed, 4 FP64 */
     int flags;       /* FMM_FLAG_* */
-    int reserved;
+    int p2p_targets; /* P2P: targets per lane, 1, 2, 4, 8 or 16 (FP64: at most 8); a work item
+                        then takes p2p_targets x (lane subgroups) targets of one leaf.  With
+                        p2p_split 0 the subgroups are the most that shape allows (4: 1..4
+                        targets per lane, 2: 8 or 16); a (targets, split) pair the kernel has
+                        no shape for (4 subgroups with 8 or 16, 2 with 1, 1 with 1 or 2) is
+                        FMM_EINVAL.  0: from the leaf size */
     double smooth_delta;   /* > 0: the near field (P2P) takes every term times the Gaussian
                               smoother g(r) = 1 - exp(-r^2/delta^2) of the vortex application
                               (Sec. 5.1, eq. 5.2); the far field is left unsmoothed, which is
@@ -94,6 +99,10 @@ typedef struct {
                               points of two well-separated boxes are at least the larger
                               radius apart at theta <= 0.5), so delta should be well below the
                               leaf radii.  fmm_evaluate and fmm_evaluate_parts only. 0: none */
+    int p2p_src_tile;      /* P2P: sources staged in LDS per pass of a work item, 64, 128 or
+                              256 (the LDS buffer); a list is summed in passes of this many
+                              sources.  0: 256 */
+    int reserved;
 } fmm_tuning;
 
 /* Host-side statistics of a plan (list sizes for the work model and the

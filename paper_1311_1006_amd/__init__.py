@@ -34,8 +34,8 @@ class FmmError(RuntimeError):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("p2p_split", C.c_int), ("m2l_batch", C.c_int), ("flags", C.c_int), ("reserved", C.c_int),
-                ("smooth_delta", C.c_double)]
+    _fields_ = [("p2p_split", C.c_int), ("m2l_batch", C.c_int), ("flags", C.c_int), ("p2p_targets", C.c_int),
+                ("smooth_delta", C.c_double), ("p2p_src_tile", C.c_int), ("reserved", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -252,12 +252,13 @@ class Plan:
 
 
 def plan(tree, p, theta, precision="fp64", p2p_split=0, m2l_batch=0, graph=False, timing=False, smooth_delta=0.0,
-         stream=None, levelwise=False):
+         stream=None, levelwise=False, p2p_targets=0, p2p_src_tile=0):
     """levelwise: the far field's upward and downward passes level by level
-    (FMM_FLAG_LEVELWISE) instead of by subtrees."""
+    (FMM_FLAG_LEVELWISE) instead of by subtrees.  p2p_split, p2p_targets,
+    p2p_src_tile, m2l_batch: the launch-shape knobs of fmm_tuning (0: auto)."""
     flags = ((FMM_FLAG_GRAPH if graph else 0) | (FMM_FLAG_PHASE_TIMING if timing else 0) |
              (FMM_FLAG_LEVELWISE if levelwise else 0))
-    tn = _Tuning(p2p_split, m2l_batch, flags, 0, float(smooth_delta))
+    tn = _Tuning(p2p_split, m2l_batch, flags, p2p_targets, float(smooth_delta), p2p_src_tile, 0)
     h = C.c_void_p()
     _check(lib().fmm_plan(tree._h, p, float(theta), _PREC[precision], C.byref(tn), _stream(stream), C.byref(h)))
     return Plan(h, tree, p, theta, precision)

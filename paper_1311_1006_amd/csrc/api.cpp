@@ -350,6 +350,14 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
                         tn.m2l_batch == 8 || tn.m2l_batch == 16,
                     "m2l_batch must be 0, 1, 2, 4, 8 or 16");
         FMM_REQUIRE(tn.smooth_delta >= 0.0 && std::isfinite(tn.smooth_delta), "smooth_delta must be >= 0 and finite");
+        FMM_REQUIRE(tn.p2p_targets == 0 || tn.p2p_targets == 1 || tn.p2p_targets == 2 || tn.p2p_targets == 4 ||
+                        tn.p2p_targets == 8 || tn.p2p_targets == 16,
+                    "p2p_targets must be 0, 1, 2, 4, 8 or 16");
+        FMM_REQUIRE(!(precision == FMM_FP64 && tn.p2p_targets > 8), "p2p_targets is at most 8 in FP64");
+        FMM_REQUIRE(tn.p2p_targets == 0 || p2p_shape_ok(tn.p2p_targets, tn.p2p_split),
+                    "no P2P shape for this p2p_targets and p2p_split");
+        FMM_REQUIRE(tn.p2p_src_tile == 0 || tn.p2p_src_tile == 64 || tn.p2p_src_tile == 128 || tn.p2p_src_tile == 256,
+                    "p2p_src_tile must be 0, 64, 128 or 256");
         check_device_state();
         hipStream_t s = (hipStream_t)stream;
         // a plan that fails half-way is released by fmm_plan_destroy, which
@@ -364,7 +372,7 @@ int fmm_plan(fmm_tree_t t, int p, double theta, int precision, const fmm_tuning*
         pl.tune = tn;
         {
             TreeSchedule& sc = *t->t.sched;
-            int key = precision * 64 + tn.p2p_split;
+            int key = (precision * 64 + tn.p2p_split) * 32 + tn.p2p_targets;   // the launch classes
             auto it = sc.plan_cache.find(key);
             if (it != sc.plan_cache.end()) {
                 pl.ex_ref = it->second;

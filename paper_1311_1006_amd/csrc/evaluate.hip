@@ -44,7 +44,7 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt = Targets{});
+                bool log_kernel, const Targets& tgt = Targets{}, int src_tile = 0);
 
 bool subtree_ok(int L, int p);
 template <class T>
@@ -63,9 +63,15 @@ struct P2PItemH {
 
 // P2P launch shape for a leaf of nt targets: SUB lane subgroups, TG targets
 // per lane (TG <= 8 in FP64, <= 16 in FP32, and 2 TG <= 64/SUB); a work item
-// covers at most TG*SUB targets.  `knob` (> 0) fixes SUB.
-static void p2p_shape(int nt, int knob, bool mixed, int* tg, int* sub)
+// covers at most TG*SUB targets.  `knob` (> 0) fixes SUB, `tknob` (> 0) TG
+// (with SUB then the most subgroups that TG allows unless knob fixes it).
+static void p2p_shape(int nt, int knob, int tknob, bool mixed, int* tg, int* sub)
 {
+    if (tknob > 0) {
+        *tg = tknob;
+        *sub = knob > 0 ? knob : (tknob <= 4 ? 4 : 2);
+        return;
+    }
     int tgmax = mixed ? 16 : 8;
     int s = knob > 0 ? knob : 4;   // measured best for 15..61 targets per leaf, both precisions
     int need = (nt + s - 1) / s;
@@ -142,7 +148,7 @@ void prepare_plan_host(Plan& pl, PlanExtra& ex, hipStream_t s)
     for (int32_t g : leaves) {
         int nt = sc.box_count[g];
         int tg, sub;
-        p2p_shape(nt, pl.tune.p2p_split, mixed, &tg, &sub);
+        p2p_shape(nt, pl.tune.p2p_split, pl.tune.p2p_targets, mixed, &tg, &sub);
         int chunk = tg * sub;
         for (int t0 = 0; t0 < nt; t0 += chunk)
             cls[{tg, sub}].push_back(P2PItemH{g, t0, std::min(chunk, nt - t0), 0});
@@ -375,7 +381,7 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* gua
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
                    mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard,
                    pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0,
-                   log_kernel);
+                   log_kernel, Targets{}, pl.tune.p2p_src_tile);
     }
     combine_chunks(b, ex.p2p_items.p, nitems, sc.d_box_start.p, pl.near.p, s);
 }

@@ -56,6 +56,14 @@ constexpr int kItemTargets = 32;   // targets per near-field work item, at most
 // source records (FP64 double4 x, y, -, -; mixed float4 x_hi, y_hi, -, - with
 // float2 x_lo, y_lo), sorted by leaf, start[g] = the first target of leaf g.
 // start == nullptr: the targets are the leaves' own points.
+// whether the near-field kernel has a shape with tg targets per lane and
+// `split` lane subgroups (split 0: some subgroup count does): 4 subgroups
+// take 1..4 targets per lane, 2 take 2..16, 1 takes 4..16
+inline bool p2p_shape_ok(int tg, int split)
+{
+    return split == 0 || (split == 4 && tg <= 4) || (split == 2 && tg >= 2) || (split == 1 && tg >= 4);
+}
+
 struct Targets {
     const void* src = nullptr;
     const float2* lo = nullptr;

@@ -215,7 +215,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
-        const long long* __restrict__ guard, double id2, const Targets tgt)
+        const long long* __restrict__ guard, double id2, const Targets tgt, int src_lim)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -254,7 +254,7 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     };
     while (e < ne) {
         const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
-            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load));
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, src_lim));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
         if (lane < npad - ns) lds[ns + lane] = Src64{0.0, 0.0, 0.0, 0.0};
@@ -303,7 +303,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
         const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
-        double2* __restrict__ out, const long long* __restrict__ guard, float id2, const Targets tgt)
+        double2* __restrict__ out, const long long* __restrict__ guard, float id2, const Targets tgt, int src_lim)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
@@ -346,7 +346,7 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     };
     while (e < ne) {
         const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
-            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load));
+            lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, src_lim));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
         if (lane < npad - ns) lds[ns + lane] = Src32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -392,17 +392,17 @@ static void launch_kern(bool mixed, const P2PItem* items, int item_base, const i
                         const int32_t* icnt, const int32_t* ioff, double* partial,
                         const int32_t* bstart, const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt,
                         const int32_t* s_ids, const void* src, const void* lo, double* out, hipStream_t s,
-                        const long long* guard, double id2, const Targets& tgt)
+                        const long long* guard, double id2, const Targets& tgt, int src_lim)
 {
     const int grid = (nx + 3) / 4;
     if (mixed)
         k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                                   (const float2*)lo, (double2*)out, guard, (float)id2, tgt);
+                                                   (const float2*)lo, (double2*)out, guard, (float)id2, tgt, src_lim);
     else
         k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
                                                    bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
-                                                   guard, id2, tgt);
+                                                   guard, id2, tgt, src_lim);
 }
 
 template <int TG, int SUB>
@@ -410,10 +410,10 @@ static void launch_one(bool mixed, const P2PItem* items, int item_base, const in
                        const int32_t* ioff, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                        const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
-                       double id2, bool log_kernel, const Targets& tgt)
+                       double id2, bool log_kernel, const Targets& tgt, int src_lim)
 {
 #define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
-             lo, out, s, guard, id2, tgt
+             lo, out, s, guard, id2, tgt, src_lim
     if (log_kernel) launch_kern<TG, SUB, kKernLog>(ARGS);
     else if (id2 > 0.0) launch_kern<TG, SUB, kKernSmooth>(ARGS);
     else launch_kern<TG, SUB, kKernPlain>(ARGS);
@@ -428,14 +428,17 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt)
+                bool log_kernel, const Targets& tgt, int src_tile)
 {
     if (nx == 0) return;
+    // sources staged per pass: the LDS buffer, or fewer (a multiple of every
+    // subgroup width, so the passes stay whole)
+    const int src_lim = src_tile > 0 && src_tile < kP2PSrcCap ? src_tile : kP2PSrcCap;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s, guard, id2, log_kernel, tgt);                                   \
+                              s_ids, src, lo, out, s, guard, id2, log_kernel, tgt, src_lim);                          \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }

@@ -60,7 +60,7 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt, const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                 const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt);
+                bool log_kernel, const Targets& tgt, int src_tile);
 
 // near-field work items over the points: at most kPtsItem points of one box
 // each, for the (4 targets per lane, 4 subgroups) shape
@@ -521,7 +521,7 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
         launch_p2p(mixed, 4, 4, items.p, 0, nullptr, (int)nx, nullptr, nullptr, nullptr, sc.d_box_start.p,
                    sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
                    mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p, mixed ? (const void*)pl.srclo.p : nullptr,
-                   tnear.p, s, nullptr, 0.0, false, tgt);
+                   tnear.p, s, nullptr, 0.0, false, tgt, pl.tune.p2p_src_tile);
     }
     // descents: the points that stopped above the leaves (box-order positions
     // before the first leaf), or with the derivative every point

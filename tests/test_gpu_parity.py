@@ -252,3 +252,33 @@ def test_invalid_arguments_raise(F):
     for p, th in ((0, 0.5), (65, 0.5), (10, 0.0), (10, 1.0)):
         with pytest.raises(F.FmmError):
             F.plan(tree, p, th)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_near_field_launch_shapes(orc, F, prec):
+    # every near-field launch shape (targets per lane x lane subgroups) and
+    # staging tile sums what the default shape sums: bit for bit across tiles
+    # (each lane meets its sources in the same order), to rounding across
+    # shapes (the lane reductions differ)
+    z, m, _ = W.uniform(60000, seed=81)
+    tree = F.build_tree(dev(z), 7)
+    md = dev(m)
+    ref = host(F.evaluate(F.plan(tree, 12, 0.5, prec), md))
+    assert e2(ref, orc.fmm(z, m, 12, 0.5, 7)) <= (1e-12 if prec == "fp64" else 1e-6)
+    for tile in (64, 128, 256):
+        assert np.array_equal(host(F.evaluate(F.plan(tree, 12, 0.5, prec, p2p_src_tile=tile), md)), ref), tile
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    shapes = [(1, 4), (2, 4), (4, 4), (2, 2), (4, 2), (8, 2), (4, 1), (8, 1), (8, 0)]
+    if prec == "mixed":
+        shapes += [(16, 2), (16, 1), (16, 0)]
+    for tg, split in shapes:
+        phi = host(F.evaluate(F.plan(tree, 12, 0.5, prec, p2p_targets=tg, p2p_split=split, p2p_src_tile=128), md))
+        assert e2(phi, ref) <= tol, (tg, split)
+    for bad in (dict(p2p_targets=8, p2p_split=4), dict(p2p_targets=1, p2p_split=2), dict(p2p_targets=3),
+                dict(p2p_src_tile=100)):
+        with pytest.raises(F.FmmError) as ex:
+            F.plan(tree, 12, 0.5, prec, **bad)
+        assert ex.value.code == -1, bad
+    if prec == "fp64":
+        with pytest.raises(F.FmmError):
+            F.plan(tree, 12, 0.5, prec, p2p_targets=16)
