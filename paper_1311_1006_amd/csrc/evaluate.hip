@@ -50,7 +50,7 @@ bool subtree_ok(int L, int p);
 template <class T>
 void launch_up_subtree(int nprob, int L, const int32_t* bstart, const int32_t* bcount, const double* geom,
                        const double* X, const double* Y, const double* mt, int p, void* mp, const double* binom,
-                       const GatherOut* go, hipStream_t s);
+                       const GatherOut* go, hipStream_t s, hipEvent_t after_leaves = nullptr);
 template <class T>
 void launch_down_subtree(int nprob, int L, const int32_t* bstart, const int32_t* bcount, const double* geom,
                          const double* X, const double* Y, void* loc, int p, const double* nearf,
@@ -204,14 +204,14 @@ static bool use_subtree(const Plan& pl, const PlanExtra& ex)
 
 // the whole upward pass by subtrees, with the gather
 template <class T>
-static void run_up_subtree(Plan& pl, const double* m, hipStream_t s)
+static void run_up_subtree(Plan& pl, const double* m, hipStream_t s, hipEvent_t after_leaves = nullptr)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p, (double4*)pl.src64.p, (float4*)pl.src32.p,
                  (float2*)pl.srclo.p};
     launch_up_subtree<T>(sc.nprob, sc.L[0], sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.mtree.p,
-                         pl.p, pl.mpole.p, pl.ex->binom.p, &go, s);
+                         pl.p, pl.mpole.p, pl.ex->binom.p, &go, s, after_leaves);
 }
 
 // gather (own kernel, or inside P2M) and P2M; m = strengths in input order
@@ -549,10 +549,14 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     const bool up = pl.upward_done && overlap;   // gather and upward pass enqueued by evaluate_upward
     pl.upward_done = false;
     const bool sub = use_subtree(pl, ex);
+    // by subtrees, the near field forks as soon as the leaves' kernel (which
+    // writes the source records) is done, beside the upper levels' M2M
+    const bool early_fork = overlap && !up && sub;
     if (!up) {
         if (sub) {
-            if (mixed) run_up_subtree<float>(pl, m, s);
-            else run_up_subtree<double>(pl, m, s);
+            hipEvent_t ev = early_fork ? pl.ev_fork : nullptr;
+            if (mixed) run_up_subtree<float>(pl, m, s, ev);
+            else run_up_subtree<double>(pl, m, s, ev);
         } else if (mixed) {
             run_p2m<float>(pl, ex, m, s);
         } else {
@@ -562,8 +566,9 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     if (overlap) {
         // the near field starts after everything enqueued on `s` so far: the
         // gather (with P2M), and the list and work-chunk kernels of the plan
-        // (which follow the upward pass when evaluate_upward ran first)
-        FMM_HIP(hipEventRecord(pl.ev_fork, s));
+        // (which follow the upward pass when evaluate_upward ran first); or,
+        // by subtrees, after the leaves' kernel (the event recorded there)
+        if (!early_fork) FMM_HIP(hipEventRecord(pl.ev_fork, s));
         FMM_HIP(hipStreamWaitEvent(pl.nstream, pl.ev_fork, 0));
         if (lists_ev) FMM_HIP(hipStreamWaitEvent(pl.nstream, lists_ev, 0));
         run_p2p(pl, ex, pl.nstream, guard);

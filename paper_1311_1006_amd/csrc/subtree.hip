@@ -434,7 +434,7 @@ bool subtree_ok(int L, int p) { return L >= 3 && p <= 32; }
 template <class T>
 void launch_up_subtree(int nprob, int L, const int32_t* bstart, const int32_t* bcount, const double* geom,
                        const double* X, const double* Y, const double* mt, int p, void* mp, const double* binom,
-                       const GatherOut* go, hipStream_t s)
+                       const GatherOut* go, hipStream_t s, hipEvent_t after_leaves)
 {
     const GatherOut none{};
     const GatherOut& gg = go ? *go : none;
@@ -453,6 +453,9 @@ void launch_up_subtree(int nprob, int L, const int32_t* bstart, const int32_t* b
     else throw Error(FMM_EINVAL, "subtree upward pass needs p <= 32");
 #undef UP_CASE
     check_launch("upward leaves");
+    // the gather is complete here: work that needs only the source records
+    // (the near field) may start
+    if (after_leaves) FMM_HIP(hipEventRecord(after_leaves, s));
     // levels L-4 .. 0 in subtrees of at most three levels
     for (int lv = L - 3; lv > 0;) {
         const int D = lv < 3 ? lv : 3;
@@ -487,7 +490,7 @@ void launch_down_subtree(int nprob, int L, const int32_t* bstart, const int32_t*
 #define INST(T)                                                                                           \
     template void launch_up_subtree<T>(int, int, const int32_t*, const int32_t*, const double*, const double*, \
                                        const double*, const double*, int, void*, const double*,          \
-                                       const GatherOut*, hipStream_t);                                   \
+                                       const GatherOut*, hipStream_t, hipEvent_t);                       \
     template void launch_down_subtree<T>(int, int, const int32_t*, const int32_t*, const double*,          \
                                          const double*, const double*, void*, int, const double*,          \
                                          const int32_t*, double*, double*, double*, const long long*,      \
