@@ -28,7 +28,7 @@ PEAK_FP32_VALU = 157.3      # TFLOP/s, MI355X published FP32 vector peak (packed
 PEAK_FP32_NOPACK = 78.6     # TFLOP/s, the same units issuing one FP32 op per lane per cycle
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X published dense FP32 matrix peak
 P2P_FLOP_PER_PAIR = 16      # per (target, source) pair: see the near-field kernel's header
-M2L_AUTO_SLOTS_MIXED = 8    # M2L pair slots per box chosen automatically for mixed precision
+M2L_AUTO_SLOTS_MIXED = 4    # M2L pair slots per box chosen automatically for mixed precision
 ERR_TARGET = 1e-6           # relative error target of both forms against the FP64 direct sum
 PEAK_HBM_GBS = 8000.0       # GB/s, MI355X published HBM3E bandwidth
 # tree build: per point and binary split, the 8-byte split coordinate read for
@@ -238,7 +238,7 @@ def measure_kh_tuners(F, W, torch, dev, steps=300, dt=1e-4, tol=1e-6):
             tu = None
             if scheme != "none":
                 tu = F.Tuner(n_levels=L0, min_levels=max(1, L0 - 3), max_levels=default_levels(z.size, per_leaf=1),
-                             p2p_split=4, m2l_batch=8, algorithm=scheme, cap=0.1, window=3, knob_interval=6,
+                             p2p_split=4, m2l_batch=4, algorithm=scheme, cap=0.1, window=3, knob_interval=6,
                              level_interval=6, theta=0.5, theta_interval=4, theta_min=0.35, theta_max=0.65,
                              tol=tol, seed=1)
             zf, hist = advect(zd, md, steps, dt, p=p0, theta=0.5, precision="mixed", tuner=tu, n_levels=L0,
@@ -517,7 +517,7 @@ def main():
             if best is None or dt < best[0]:
                 best = (dt, (L, 0, 0))
         L = best[1][0]
-        for cfg in ((L, 2, 0), (L, 0, 8), (L, 0, 16)):
+        for cfg in ((L, 2, 0), (L, 0, 2), (L, 0, 8)):
             dt = time_steps(prec, cfg, 3)
             log("sweep %s L=%d split=%d batch=%d: %.3f ms" % (prec, cfg[0], cfg[1], cfg[2], dt * 1e3))
             if dt < best[0]:

@@ -84,7 +84,7 @@ typedef struct {
     int m2l_batch;   /* M2L: pair slots of one box in each 16-pair MFMA block: 16 (one
                         box per wavefront), 8, 4, 2 or 1 (2, 4, 8 or 16 boxes share a
                         wavefront and its blocks; with 1 every MFMA column is one box);
-                        automatic: 8 mixed, 4 FP64 */
+                        automatic: 4 */
     int flags;       /* FMM_FLAG_* */
     int p2p_targets; /* P2P: targets per lane, 1, 2, 4, 8 or 16 (FP64: at most 8); a work item
                         then takes p2p_targets x (lane subgroups) targets of one leaf.  With

@@ -441,8 +441,9 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
 // expansion written (zeros for a box without weak pairs).  xitems[0 .. nx): (box index, chunk); icnt/ioff per
 // box index; partial holds the chunks of split lists.  batch: pair slots of
 // one item in each 16-pair MFMA block: 16 (one item per wavefront), 8 (two)
-// or 4 (four items share a wavefront); 0 = automatic (8 for FP32, 4 for
-// FP64: the fastest on the uniform million-point case).
+// or 4 (four items share a wavefront); 0 = automatic (4, the fastest in both
+// precisions on the uniform million-point case: mixed 81 us against 93 us
+// with 8 slots, FP64 146 us against 161 us).
 template <class T>
 void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const int32_t* icnt, const int32_t* ioff,
                 double* partial, bool split, const int32_t* w_beg, const int32_t* w_cnt, const int32_t* w_ids,
@@ -450,7 +451,7 @@ void launch_m2l(const int32_t* boxes, int n, const int2* xitems, int nx, const i
                 const long long* guard)
 {
     if (nx == 0) return;
-    const int slots = batch != 0 ? batch : (std::is_same<T, float>::value ? 8 : 4);
+    const int slots = batch != 0 ? batch : 4;
 #define ARGS boxes, xitems, nx, icnt, ioff, partial, w_beg, w_cnt, w_ids, geom, binom, p, mp, loc, s, guard
     if (p <= 16) {
         if (slots == 16) m2l_one<T, 1, 1>(ARGS);

@@ -81,8 +81,7 @@ def tune_batch(z, m, offsets, p, theta, precision, iterations=60, out=None, **kw
         out = torch.empty_like(m)
     kw.setdefault("window", 2)
     kw.setdefault("knob_interval", 4)
-    tu = Tuner(n_levels=3, min_levels=1, max_levels=5, p2p_split=4,
-               m2l_batch=8 if precision == "mixed" else 4, **kw)
+    tu = Tuner(n_levels=3, min_levels=1, max_levels=5, p2p_split=4, m2l_batch=4, **kw)
     trees, plans, hist = {}, {}, []
     for _ in range(iterations):
         prm = tu.next()
