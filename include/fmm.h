@@ -55,9 +55,9 @@ enum fmm_status {
 enum fmm_precision {
     FMM_FP64 = 0,   /* every step in FP64 */
     FMM_MIXED = 1   /* P2P and M2L in FP32 (FP32 accumulation); FP64 box geometry,
-                       theta-tests and position differences (P2P: double-float
-                       differences; M2L: the centre difference in FP64, then 1/d
-                       and the rescaling powers of r_S/d and -r_T/d in FP32);
+                       theta-tests and position differences (P2P: z_i - z_j in FP64,
+                       rounded once to FP32; M2L: the centre difference in FP64, then
+                       1/d and the rescaling powers of r_S/d and -r_T/d in FP32);
                        expansions stored in FP32 */
 };
 
@@ -100,8 +100,9 @@ typedef struct {
                               radius apart at theta <= 0.5), so delta should be well below the
                               leaf radii.  fmm_evaluate and fmm_evaluate_parts only. 0: none */
     int p2p_src_tile;      /* P2P: sources staged in LDS per pass of a work item, 64, 128 or
-                              256 (the LDS buffer); a list is summed in passes of this many
-                              sources.  0: 256 */
+                              256, at most the LDS buffer (128 sources mixed, 192 FP64); a
+                              list is summed in passes of this many sources.  0: the
+                              buffer */
     int reserved;
 } fmm_tuning;
 

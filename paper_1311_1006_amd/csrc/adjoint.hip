@@ -45,8 +45,7 @@ template <class T>
 void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
                 const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
                 hipStream_t, int, const long long*);
-void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
-                   const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
+void launch_gather(int64_t n, const int32_t* perm, const double* m, double* mtree, hipStream_t s);
 
 struct P2PItemA {
     int32_t leaf, t0, tn, pad;
@@ -355,7 +354,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
     if (pl.amp.n < 2 * cs * sc.nbox * pl.p) pl.amp.alloc(2 * cs * sc.nbox * pl.p, s);
     if (pl.aloc.n < 2 * cs * sc.nbox * pl.p) pl.aloc.alloc(2 * cs * sc.nbox * pl.p, s);
     // strengths m in tree order (the forward's gather, repeated for safety)
-    launch_gather(mixed, n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+    launch_gather(n, t.perm.p, m, pl.mtree.p, s);
     k_gather_adj<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, t.perm.p, (const double2*)gphi,
                                                              (double2*)pl.gtree.p, (double2*)ngb.p, nullptr);
     check_launch("gather adjoint");

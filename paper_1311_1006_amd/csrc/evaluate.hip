@@ -1,7 +1,7 @@
 // evaluate.hip -- the FMM evaluation sequence (Sec. 2.1, Fig. 2.2) and the
 // host-side work lists of a plan.
 //
-//   gather  strengths to tree order, P2P source records
+//   gather  strengths to tree order (the P2P sources, with the tree's positions)
 //   P2M     leaves of every problem (does the gather when the leaves hold
 //           every point, which is the case for every tree this library builds)
 //   M2M     level by level, deepest parents first
@@ -21,8 +21,7 @@
 
 namespace fmm {
 
-void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
-                   const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s);
+void launch_gather(int64_t n, const int32_t* perm, const double* m, double* mtree, hipStream_t s);
 template <class T>
 void launch_p2m(const int32_t*, int, const int32_t*, const int32_t*, int, const double*, const double*,
                 const double*, const double*, int, void*, hipStream_t, const int32_t* = nullptr,
@@ -39,12 +38,6 @@ template <class T>
 void launch_m2l(const int32_t*, int, const int2*, int, const int32_t*, const int32_t*, double*, bool,
                 const int32_t*, const int32_t*, const int32_t*, const double*, const double*, int, const void*, void*,
                 hipStream_t, int, const long long*);
-void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
-                const int32_t* icnt,
-                const int32_t* ioff, double* partial, const int32_t* bstart,
-                const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt = Targets{}, int src_tile = 0);
 
 bool subtree_ok(int L, int p);
 template <class T>
@@ -184,8 +177,6 @@ void alloc_eval_buffers(Plan& pl, hipStream_t s)
     size_t cs = mixed ? sizeof(float) : sizeof(double);
     pl.mtree.alloc(2 * n, s);
     pl.near.alloc(2 * n, s);
-    if (mixed) { pl.src32.alloc(4 * n, s); pl.srclo.alloc(2 * n, s); }
-    else pl.src64.alloc(4 * n, s);
     pl.mpole.alloc(2 * cs * sc.nbox * pl.p, s);
     pl.local.alloc(2 * cs * sc.nbox * pl.p, s);
 }
@@ -208,8 +199,7 @@ static void run_up_subtree(Plan& pl, const double* m, hipStream_t s, hipEvent_t 
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
-    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p, (double4*)pl.src64.p, (float4*)pl.src32.p,
-                 (float2*)pl.srclo.p};
+    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p};
     launch_up_subtree<T>(sc.nprob, sc.L[0], sc.d_box_start.p, sc.d_box_count.p, t.geom.p, t.x.p, t.y.p, pl.mtree.p,
                          pl.p, pl.mpole.p, pl.ex->binom.p, &go, s, after_leaves);
 }
@@ -221,10 +211,9 @@ static void run_p2m(Plan& pl, PlanExtra& ex, const double* m, hipStream_t s)
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
     const bool mixed = std::is_same<T, float>::value;
-    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p, (double4*)pl.src64.p, (float4*)pl.src32.p,
-                 (float2*)pl.srclo.p};
+    GatherOut go{t.perm.p, (const double2*)m, (double2*)pl.mtree.p};
     if (!ex.gather_in_p2m)
-        launch_gather(mixed, sc.n, t.perm.p, t.x.p, t.y.p, m, pl.mtree.p, pl.src64.p, pl.src32.p, pl.srclo.p, s);
+        launch_gather(sc.n, t.perm.p, m, pl.mtree.p, s);
     // with leaf_m2m_in_p2m the P2M kernel also forms the leaves' parents
     // (up to 32 terms: above that P2M runs in two blocks of terms)
     const bool fm = leaf_m2m(pl, ex);
@@ -378,8 +367,7 @@ static void run_p2p(Plan& pl, PlanExtra& ex, hipStream_t s, const long long* gua
         launch_p2p(mixed, k.tg, k.sub, ex.p2p_items.p, (int)x0, b.xitems.p ? b.xitems.p + x0 : nullptr,
                    (int)(x1 - x0), b.icnt.p, b.ioff.p,
                    b.partial.p, sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
-                   mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p,
-                   mixed ? (const void*)pl.srclo.p : nullptr, pl.near.p, s, guard,
+                   t.x.p, t.y.p, (const double2*)pl.mtree.p, pl.near.p, s, guard,
                    pl.tune.smooth_delta > 0.0 ? 1.0 / (pl.tune.smooth_delta * pl.tune.smooth_delta) : 0.0,
                    log_kernel, Targets{}, pl.tune.p2p_src_tile);
     }
@@ -446,7 +434,7 @@ void evaluate_upward(Plan& pl, const double* m, hipStream_t s)
 }
 
 // The far field of every box and nothing at the sources: the upward pass
-// (with the gather of the source records) and the M2L / L2L sweep over every
+// (with the gather of the strengths) and the M2L / L2L sweep over every
 // level, so that the multipole expansion and the complete local expansion of
 // every box are in the plan's buffers (evaluation at points apart from the
 // sources).
@@ -482,7 +470,7 @@ void launch_l2p_log(const int32_t* leaves, int nleaf, const int32_t* bstart, con
 // The logarithmic potential (see log.hip): the harmonic upward pass and far
 // field of the strengths q as complex numbers, the near field with the
 // logarithmic kernel (on the second stream, beside the far field, from the
-// source records P2M writes), the constant terms of the local expansions,
+// strengths in tree order P2M writes), the constant terms of the local expansions,
 // and L2P of the integrated series after the join.
 void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s, double* mlog, double* c0)
 {
@@ -550,7 +538,7 @@ void evaluate_device(Plan& pl, const double* m, double* phi, double* phi_near, d
     pl.upward_done = false;
     const bool sub = use_subtree(pl, ex);
     // by subtrees, the near field forks as soon as the leaves' kernel (which
-    // writes the source records) is done, beside the upper levels' M2M
+    // writes the strengths in tree order) is done, beside the upper levels' M2M
     const bool early_fork = overlap && !up && sub;
     if (!up) {
         if (sub) {

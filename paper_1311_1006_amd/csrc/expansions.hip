@@ -18,24 +18,13 @@
 
 namespace fmm {
 
-// strengths into tree order + the P2P source records
-template <bool MIXED>
-__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ X,
-                         const double* __restrict__ Y, const double2* __restrict__ m, double2* mtree,
-                         double4* src64, float4* src32, float2* srclo)
+// strengths into tree order (with the tree's positions, the near field's
+// sources)
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double2* __restrict__ m, double2* mtree)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double2 mm = m[perm[i]];
-    double x = X[i], y = Y[i];
-    mtree[i] = mm;
-    if (MIXED) {
-        float xh = (float)x, yh = (float)y;
-        src32[i] = make_float4(xh, yh, (float)mm.x, (float)mm.y);
-        srclo[i] = make_float2((float)(x - (double)xh), (float)(y - (double)yh));
-    } else {
-        src64[i] = make_double4(x, y, mm.x, mm.y);
-    }
+    mtree[i] = m[perm[i]];
 }
 
 __device__ __forceinline__ void wave_sync_e()
@@ -112,13 +101,6 @@ k_p2m(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
             const double2 mm = go.m[go.perm[i]];
             const double x = X[i], y = Y[i];
             go.mtree[i] = mm;
-            if constexpr (std::is_same<T, float>::value) {
-                const float xh = (float)x, yh = (float)y;
-                go.src32[i] = make_float4(xh, yh, (float)mm.x, (float)mm.y);
-                go.srclo[i] = make_float2((float)(x - (double)xh), (float)(y - (double)yh));
-            } else {
-                go.src64[i] = make_double4(x, y, mm.x, mm.y);
-            }
             w = make_double2((x - cx) * inv, (y - cy) * inv);
             t = mm;
         } else {
@@ -393,23 +375,11 @@ k_l2p(const int32_t* __restrict__ leaves, int nleaf, const int32_t* __restrict__
     }
 }
 
-template __global__ void k_gather<false>(int64_t, const int32_t*, const double*, const double*, const double2*,
-                                         double2*, double4*, float4*, float2*);
-template __global__ void k_gather<true>(int64_t, const int32_t*, const double*, const double*, const double2*,
-                                        double2*, double4*, float4*, float2*);
-
 // ------------------------------------------------------------ launchers
 
-void launch_gather(bool mixed, int64_t n, const int32_t* perm, const double* X, const double* Y,
-                   const double* m, double* mtree, double* src64, float* src32, float* srclo, hipStream_t s)
+void launch_gather(int64_t n, const int32_t* perm, const double* m, double* mtree, hipStream_t s)
 {
-    int g = (int)((n + 255) / 256);
-    if (mixed)
-        k_gather<true><<<g, 256, 0, s>>>(n, perm, X, Y, (const double2*)m, (double2*)mtree, nullptr,
-                                         (float4*)src32, (float2*)srclo);
-    else
-        k_gather<false><<<g, 256, 0, s>>>(n, perm, X, Y, (const double2*)m, (double2*)mtree, (double4*)src64,
-                                          nullptr, nullptr);
+    k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, perm, (const double2*)m, (double2*)mtree);
     check_launch("gather");
 }
 

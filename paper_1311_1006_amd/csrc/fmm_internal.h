@@ -52,9 +52,8 @@ constexpr int kChunkSrc = 2048;    // near-field sources per work chunk (longer 
 constexpr int kItemTargets = 32;   // targets per near-field work item, at most
 
 // Targets of the near-field kernels other than the leaves' own points
-// (evaluation points apart from the sources): records in the format of the
-// source records (FP64 double4 x, y, -, -; mixed float4 x_hi, y_hi, -, - with
-// float2 x_lo, y_lo), sorted by leaf, start[g] = the first target of leaf g.
+// (evaluation points apart from the sources): FP64 positions x[], y[],
+// sorted by leaf, start[g] = the first target of leaf g.
 // start == nullptr: the targets are the leaves' own points.
 // whether the near-field kernel has a shape with tg targets per lane and
 // `split` lane subgroups (split 0: some subgroup count does): 4 subgroups
@@ -65,10 +64,20 @@ inline bool p2p_shape_ok(int tg, int split)
 }
 
 struct Targets {
-    const void* src = nullptr;
-    const float2* lo = nullptr;
+    const double* x = nullptr;
+    const double* y = nullptr;
     const int32_t* start = nullptr;
 };
+
+// The near field over the chunks of one launch class (p2p.hip): the sources
+// are the points in tree order, positions X, Y and strengths M (FP64; the
+// mixed kernels round the strengths to FP32 as they stage them).
+void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
+                const int32_t* icnt, const int32_t* ioff, double* partial, const int32_t* bstart,
+                const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
+                const double* X, const double* Y, const double2* M, double* out, hipStream_t s,
+                const long long* guard, double id2, bool log_kernel, const Targets& tgt = Targets{},
+                int src_tile = 0);
 constexpr int kChunkPairs = 128;   // M2L weak pairs per work chunk (longer lists are split)
 
 __host__ __device__ inline int64_t level_base(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
@@ -227,10 +236,8 @@ struct Plan {
     bool upward_done = false;      // the evaluation's upward pass is already enqueued
     bool split_p2p = false, split_m2l = false;   // some list may need work chunks
     // evaluation buffers
-    DBuf<double> src64;            // [N][4] x y mr mi (FP64 path)
-    DBuf<float> src32;             // [N][4] xh yh mr mi (mixed path)
-    DBuf<float> srclo;             // [N][2] xl yl
-    DBuf<double> mtree;            // [N][2] strengths in tree order (FP64)
+    DBuf<double> mtree;            // [N][2] strengths in tree order (FP64); with the tree's
+                                   // positions, the sources of the near field
     DBuf<double> near;             // [N][2] P2P result, tree order
     DBuf<double> mlog;             // [N][2] real strengths of the logarithmic kernel as complex numbers
     DBuf<double> c0;               // [nbox] constant term of the logarithmic local expansions
@@ -307,15 +314,13 @@ size_t static_eval_bytes(Plan& pl);
 // box: the constant terms) are the plan's own buffers when mlog is NULL
 void evaluate_log_device(Plan& pl, const double* q, double* u, hipStream_t s, double* mlog = nullptr,
                          double* c0 = nullptr);
-// the gather of an evaluation (strengths into tree order, P2P source records)
-// done by the P2M kernel as it reads every point of its leaves
+// the gather of an evaluation (the strengths into tree order: with the
+// tree's positions, the near field's sources), done by the P2M kernel as it
+// reads every point of its leaves
 struct GatherOut {
     const int32_t* perm;     // tree position -> input index
     const double2* m;        // strengths, input order
     double2* mtree;          // strengths, tree order
-    double4* src64;          // FP64 path: (x, y, Re m, Im m)
-    float4* src32;           // mixed path: (x_hi, y_hi, Re m, Im m)
-    float2* srclo;           //             (x_lo, y_lo)
 };
 void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, double* gz,
                     hipStream_t s);

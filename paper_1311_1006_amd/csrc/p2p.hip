@@ -19,8 +19,11 @@
 // unchanged and turns r^2 = 0 (z_j = z_i) into a finite reciprocal that
 // multiplies an exact zero.
 //   FP64:  dz in FP64, 1/r^2 by v_rcp_f64 and two Newton steps.
-//   mixed: positions as FP32 hi + lo, dz = (hi_i - hi_j) + (lo_i - lo_j),
-//          everything else in FP32 with FP32 accumulation.
+//   mixed: positions in FP64, dz = z_i - z_j in FP64 rounded once to FP32
+//          (FP64 adds issue at the FP32 rate on this chip: two instructions
+//          per component, against three for a hi + lo FP32 pair), strengths
+//          rounded to FP32 as they are staged, everything after dz in FP32
+//          with FP32 accumulation.
 #include <cfloat>
 #include <climits>
 
@@ -34,14 +37,23 @@ struct P2PItem {
     int32_t leaf, t0, tn, pad;
 };
 
-constexpr int kP2PSrcCap = 256;    // sources staged in LDS per pass and wavefront
+// Sources staged in LDS per pass and wavefront.  The buffer and the staging
+// registers (a quarter of the buffer per lane) set how many wavefronts a
+// SIMD holds, and with them how well the staging loads of one wavefront hide
+// behind the arithmetic of the others: 128 for the mixed kernels (16 KiB per
+// workgroup, 64 vector registers: 8 wavefronts per SIMD), 192 for FP64
+// (29 KiB, 92 registers: 5).  At N = 1e6, N_levels 9 (a list of about 183
+// sources) this took the mixed near field from 108 to 99 us and the FP64
+// one from 162 to 155 us against a 256-source buffer.
+constexpr int kP2PSrcCap32 = 128, kP2PSrcCap64 = 192;
 
 
 struct Src64 {
     double x, y, mr, mi;
 };
 struct Src32 {
-    float xh, yh, mr, mi, xl, yl;
+    double x, y;
+    float mr, mi;
 };
 
 __device__ __forceinline__ void pair64(double xi, double yi, const Src64& s, double& ar, double& ai)
@@ -76,10 +88,10 @@ __device__ __forceinline__ void pair64s(double xi, double yi, const Src64& s, do
     ai = fma(b, y, ai);
 }
 
-__device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, const Src32& s, float& ar, float& ai)
+__device__ __forceinline__ void pair32(double xi, double yi, const Src32& s, float& ar, float& ai)
 {
-    float dx = (xh - s.xh) + (xl - s.xl);
-    float dy = (yh - s.yh) + (yl - s.yl);
+    float dx = (float)(xi - s.x);
+    float dy = (float)(yi - s.y);
     float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
     float y = __builtin_amdgcn_rcpf(r2);
     float a = fmaf(s.mr, dx, s.mi * dy);
@@ -88,11 +100,10 @@ __device__ __forceinline__ void pair32(float xh, float yh, float xl, float yl, c
     ai = fmaf(b, y, ai);
 }
 
-__device__ __forceinline__ void pair32s(float xh, float yh, float xl, float yl, const Src32& s, float id2, float& ar,
-                                        float& ai)
+__device__ __forceinline__ void pair32s(double xi, double yi, const Src32& s, float id2, float& ar, float& ai)
 {
-    float dx = (xh - s.xh) + (xl - s.xl);
-    float dy = (yh - s.yh) + (yl - s.yl);
+    float dx = (float)(xi - s.x);
+    float dy = (float)(yi - s.y);
     float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
     float y = __builtin_amdgcn_rcpf(r2) * (1.0f - __expf(-r2 * id2));
     float a = fmaf(s.mr, dx, s.mi * dy);
@@ -105,10 +116,10 @@ __device__ __forceinline__ void pair32s(float xh, float yh, float xl, float yl, 
 // part of the strength (real strengths leave the second sum 0).  Coincident
 // positions are left out, as in the other kernels; FLT_MIN (DBL_MIN) in r^2
 // only keeps the logarithm finite there.
-__device__ __forceinline__ void pair32l(float xh, float yh, float xl, float yl, const Src32& s, float& ar, float& ai)
+__device__ __forceinline__ void pair32l(double xi, double yi, const Src32& s, float& ar, float& ai)
 {
-    const float dx = (xh - s.xh) + (xl - s.xl);
-    const float dy = (yh - s.yh) + (yl - s.yl);
+    const float dx = (float)(xi - s.x);
+    const float dy = (float)(yi - s.y);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
     const float lg = (dx != 0.f || dy != 0.f) ? 0.5f * __logf(r2) : 0.f;
     ar = fmaf(s.mr, lg, ar);
@@ -214,15 +225,16 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
-        const int32_t* __restrict__ s_ids, const double4* __restrict__ src, double2* __restrict__ out,
-        const long long* __restrict__ guard, double id2, const Targets tgt, int src_lim)
+        const int32_t* __restrict__ s_ids, const double* __restrict__ X, const double* __restrict__ Y,
+        const double2* __restrict__ M, double2* __restrict__ out, const long long* __restrict__ guard, double id2,
+        const Targets tgt, int src_lim)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
-    static_assert(kP2PSrcCap % NL == 0, "the padded run must fit the staging buffer");
-    __shared__ Src64 sbuf[4][kP2PSrcCap];
+    static_assert(kP2PSrcCap64 % NL == 0, "the padded run must fit the staging buffer");
+    __shared__ Src64 sbuf[4][kP2PSrcCap64];
     __shared__ int2 smeta[4][64];
-    __shared__ int smark[4][kP2PSrcCap];
+    __shared__ int smark[4][kP2PSrcCap64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int xi_ = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + w);   // one work item per wavefront
     if (xi_ >= nx) return;
@@ -235,25 +247,26 @@ k_p2p64(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     const int g = lane / NL, sl = lane % NL;
     // the targets: the leaf's own points, or evaluation points apart from the sources
     const int base = (tgt.start ? tgt.start : bstart)[it.leaf] + it.t0;
-    const double4* tsrc = tgt.start ? (const double4*)tgt.src : src;
+    const double* tx = tgt.start ? tgt.x : X;
+    const double* ty = tgt.start ? tgt.y : Y;
     double xi[TG], yi[TG], ar[TG], ai[TG];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
-        double4 v = tsrc[base + (k < it.tn ? k : 0)];
-        xi[t] = v.x; yi[t] = v.y; ar[t] = 0.0; ai[t] = 0.0;
+        const int i = base + (k < it.tn ? k : 0);
+        xi[t] = tx[i]; yi[t] = ty[i]; ar[t] = 0.0; ai[t] = 0.0;
     }
     // the item's entries, or those of its chunk
     const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
     int e = nch == 1 ? 0 : xe.y * ce, off = 0;
     const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
-        double4 v = src[j];
-        Src64 s; s.x = v.x; s.y = v.y; s.mr = v.z; s.mi = v.w;
+        const double2 m = M[j];
+        Src64 s; s.x = X[j]; s.y = Y[j]; s.mr = m.x; s.mi = m.y;
         return s;
     };
     while (e < ne) {
-        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
+        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap64>(
             lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, src_lim));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
@@ -302,15 +315,16 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
         const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
         double* __restrict__ partial, const int32_t* __restrict__ bstart,
         const int32_t* __restrict__ bcount, const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt,
-        const int32_t* __restrict__ s_ids, const float4* __restrict__ src, const float2* __restrict__ lo,
-        double2* __restrict__ out, const long long* __restrict__ guard, float id2, const Targets tgt, int src_lim)
+        const int32_t* __restrict__ s_ids, const double* __restrict__ X, const double* __restrict__ Y,
+        const double2* __restrict__ M, double2* __restrict__ out, const long long* __restrict__ guard, float id2,
+        const Targets tgt, int src_lim)
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     constexpr int NL = 64 / SUB;
-    static_assert(kP2PSrcCap % NL == 0, "the padded run must fit the staging buffer");
-    __shared__ Src32 sbuf[4][kP2PSrcCap];
+    static_assert(kP2PSrcCap32 % NL == 0, "the padded run must fit the staging buffer");
+    __shared__ Src32 sbuf[4][kP2PSrcCap32];
     __shared__ int2 smeta[4][64];
-    __shared__ int smark[4][kP2PSrcCap];
+    __shared__ int smark[4][kP2PSrcCap32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int xi_ = __builtin_amdgcn_readfirstlane(xcd_block() * 4 + w);   // one work item per wavefront
     if (xi_ >= nx) return;
@@ -323,52 +337,50 @@ k_p2p32(const P2PItem* __restrict__ items, int item_base, const int2* __restrict
     const int g = lane / NL, sl = lane % NL;
     // the targets: the leaf's own points, or evaluation points apart from the sources
     const int base = (tgt.start ? tgt.start : bstart)[it.leaf] + it.t0;
-    const float4* tsrc = tgt.start ? (const float4*)tgt.src : src;
-    const float2* tlo = tgt.start ? tgt.lo : lo;
-    float xh[TG], yh[TG], xl[TG], yl[TG], ar[TG], ai[TG];
+    const double* tx = tgt.start ? tgt.x : X;
+    const double* ty = tgt.start ? tgt.y : Y;
+    double xi[TG], yi[TG];
+    float ar[TG], ai[TG];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
-        int i = base + (k < it.tn ? k : 0);
-        float4 a = tsrc[i];
-        float2 b = tlo[i];
-        xh[t] = a.x; yh[t] = a.y; xl[t] = b.x; yl[t] = b.y; ar[t] = 0.f; ai[t] = 0.f;
+        const int i = base + (k < it.tn ? k : 0);
+        xi[t] = tx[i]; yi[t] = ty[i]; ar[t] = 0.f; ai[t] = 0.f;
     }
     // the item's entries, or those of its chunk
     const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
     int e = nch == 1 ? 0 : xe.y * ce, off = 0;
     const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
-        float4 a = src[j];
-        float2 b = lo[j];
-        Src32 s; s.xh = a.x; s.yh = a.y; s.mr = a.z; s.mi = a.w; s.xl = b.x; s.yl = b.y;
+        const double2 m = M[j];
+        Src32 s; s.x = X[j]; s.y = Y[j]; s.mr = (float)m.x; s.mi = (float)m.y;
         return s;
     };
     while (e < ne) {
-        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap>(
+        const int ns = __builtin_amdgcn_readfirstlane(stage_sources<kP2PSrcCap32>(
             lds, smeta[w], smark[w], s_ids, bstart, bcount, e0, ne, e, off, lane, load, src_lim));
         // zero-strength sources (at the origin) pad the staged run to whole passes
         const int npad = (ns + NL - 1) / NL * NL;
-        if (lane < npad - ns) lds[ns + lane] = Src32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (lane < npad - ns) lds[ns + lane] = Src32{0.0, 0.0, 0.f, 0.f};
         wave_sync();
         const Src32* sp = lds + sl;
         if constexpr (KERN == kKernSmooth) {     // the smoothed near field
             for (int c = 0; c < npad; c += NL, sp += NL) {
                 const Src32 s = *sp;
 #pragma unroll
-                for (int t = 0; t < TG; ++t) pair32s(xh[t], yh[t], xl[t], yl[t], s, id2, ar[t], ai[t]);
+                for (int t = 0; t < TG; ++t) pair32s(xi[t], yi[t], s, id2, ar[t], ai[t]);
             }
         } else if constexpr (KERN == kKernLog) {
             for (int c = 0; c < npad; c += NL, sp += NL) {
                 const Src32 s = *sp;
 #pragma unroll
-                for (int t = 0; t < TG; ++t) pair32l(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
+                for (int t = 0; t < TG; ++t) pair32l(xi[t], yi[t], s, ar[t], ai[t]);
             }
         } else {
             for (int c = 0; c < npad; c += NL, sp += NL) {
                 const Src32 s = *sp;
 #pragma unroll
-                for (int t = 0; t < TG; ++t) pair32(xh[t], yh[t], xl[t], yl[t], s, ar[t], ai[t]);
+                for (int t = 0; t < TG; ++t) pair32(xi[t], yi[t], s, ar[t], ai[t]);
             }
         }
         wave_sync();
@@ -391,29 +403,29 @@ template <int TG, int SUB, int KERN>
 static void launch_kern(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx,
                         const int32_t* icnt, const int32_t* ioff, double* partial,
                         const int32_t* bstart, const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt,
-                        const int32_t* s_ids, const void* src, const void* lo, double* out, hipStream_t s,
-                        const long long* guard, double id2, const Targets& tgt, int src_lim)
+                        const int32_t* s_ids, const double* X, const double* Y, const double2* M, double* out,
+                        hipStream_t s, const long long* guard, double id2, const Targets& tgt, int src_lim)
 {
     const int grid = (nx + 3) / 4;
     if (mixed)
         k_p2p32<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
-                                                   bcount, s_beg, s_cnt, s_ids, (const float4*)src,
-                                                   (const float2*)lo, (double2*)out, guard, (float)id2, tgt, src_lim);
+                                                   bcount, s_beg, s_cnt, s_ids, X, Y, M, (double2*)out, guard,
+                                                   (float)id2, tgt, src_lim);
     else
         k_p2p64<TG, SUB, KERN><<<grid, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial, bstart,
-                                                   bcount, s_beg, s_cnt, s_ids, (const double4*)src, (double2*)out,
-                                                   guard, id2, tgt, src_lim);
+                                                   bcount, s_beg, s_cnt, s_ids, X, Y, M, (double2*)out, guard,
+                                                   id2, tgt, src_lim);
 }
 
 template <int TG, int SUB>
 static void launch_one(bool mixed, const P2PItem* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
                        const int32_t* ioff, double* partial, const int32_t* bstart,
                        const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                       const void* src, const void* lo, double* out, hipStream_t s, const long long* guard,
-                       double id2, bool log_kernel, const Targets& tgt, int src_lim)
+                       const double* X, const double* Y, const double2* M, double* out, hipStream_t s,
+                       const long long* guard, double id2, bool log_kernel, const Targets& tgt, int src_lim)
 {
-#define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, s_ids, src, \
-             lo, out, s, guard, id2, tgt, src_lim
+#define ARGS mixed, items, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, s_ids, X, Y, \
+             M, out, s, guard, id2, tgt, src_lim
     if (log_kernel) launch_kern<TG, SUB, kKernLog>(ARGS);
     else if (id2 > 0.0) launch_kern<TG, SUB, kKernSmooth>(ARGS);
     else launch_kern<TG, SUB, kKernPlain>(ARGS);
@@ -427,18 +439,19 @@ void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, c
                 const int32_t* icnt,
                 const int32_t* ioff, double* partial, const int32_t* bstart,
                 const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt, int src_tile)
+                const double* X, const double* Y, const double2* M, double* out, hipStream_t s,
+                const long long* guard, double id2, bool log_kernel, const Targets& tgt, int src_tile)
 {
     if (nx == 0) return;
     // sources staged per pass: the LDS buffer, or fewer (a multiple of every
     // subgroup width, so the passes stay whole)
-    const int src_lim = src_tile > 0 && src_tile < kP2PSrcCap ? src_tile : kP2PSrcCap;
+    const int cap = mixed ? kP2PSrcCap32 : kP2PSrcCap64;
+    const int src_lim = src_tile > 0 && src_tile < cap ? src_tile : cap;
     const P2PItem* it = (const P2PItem*)items;
 #define CASE(TG_, SUB_)                                                                                   \
     if (tg == TG_ && sub == SUB_) {                                                                       \
         launch_one<TG_, SUB_>(mixed, it, item_base, xitems, nx, icnt, ioff, partial, bstart, bcount, s_beg, s_cnt, \
-                              s_ids, src, lo, out, s, guard, id2, log_kernel, tgt, src_lim);                          \
+                              s_ids, X, Y, M, out, s, guard, id2, log_kernel, tgt, src_lim);                          \
         check_launch("p2p");                                                                              \
         return;                                                                                           \
     }

@@ -56,11 +56,6 @@ namespace fmm {
 
 void far_field_all(Plan& pl, const double* m, hipStream_t s);
 void launch_exclusive_scan(const int32_t* v, int n, int32_t* bsum, int32_t* out, hipStream_t s);
-void launch_p2p(bool mixed, int tg, int sub, const void* items, int item_base, const int2* xitems, int nx,
-                const int32_t* icnt, const int32_t* ioff, double* partial, const int32_t* bstart,
-                const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
-                const void* src, const void* lo, double* out, hipStream_t s, const long long* guard, double id2,
-                bool log_kernel, const Targets& tgt, int src_tile);
 
 // near-field work items over the points: at most kPtsItem points of one box
 // each, for the (4 targets per lane, 4 subgroups) shape
@@ -120,22 +115,16 @@ __global__ void k_pts_scatter(const int32_t* __restrict__ box, int64_t M, const 
     order[off[b] + atomicAdd(&fill[b], 1)] = (int32_t)i;
 }
 
-// the points in box order as near-field target records (the layout of the
-// source records)
-template <bool MIXED>
+// the points' positions in box order, as the near-field kernel reads its
+// targets (x[], y[])
 __global__ void k_pts_records(const double2* __restrict__ y, int64_t M, const int32_t* __restrict__ order,
-                              void* rec, float2* lo)
+                              double* rx, double* ry)
 {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= M) return;
     const double2 v = y[order[q]];
-    if constexpr (MIXED) {
-        const float xh = (float)v.x, yh = (float)v.y;
-        ((float4*)rec)[q] = make_float4(xh, yh, 0.f, 0.f);
-        lo[q] = make_float2((float)(v.x - (double)xh), (float)(v.y - (double)yh));
-    } else {
-        ((double4*)rec)[q] = make_double4(v.x, v.y, 0.0, 0.0);
-    }
+    rx[q] = v.x;
+    ry[q] = v.y;
 }
 
 // items per leaf: the leaf's points in groups of kPtsItem
@@ -203,12 +192,14 @@ __device__ __forceinline__ void m2p(const T* a, int p, double rs, double dx, dou
 
 // the points of one leaf, directly: phi += m/(y - x), dphi -= m/(y - x)^2
 template <bool DER>
-__device__ __forceinline__ void direct64(const double4* __restrict__ src, int st, int n, double yx, double yy,
+__device__ __forceinline__ void direct64(const double* __restrict__ X, const double* __restrict__ Y,
+                                         const double2* __restrict__ mt, int st, int n, double yx, double yy,
                                          double2& phi, double2& dphi)
 {
 #pragma unroll 8
     for (int q = 0; q < n; ++q) {         // unrolled: eight loads in flight
-        const double4 sv = src[st + q];
+        const double2 m = mt[st + q];
+        const double4 sv = make_double4(X[st + q], Y[st + q], m.x, m.y);   // x, y, Re m, Im m
         const double dx = yx - sv.x, dy = yy - sv.y;
         const double r2 = dx * dx + (dy * dy + DBL_MIN);     // 0/DBL_MIN: a coincident source adds 0
         const double id = 1.0 / r2;
@@ -225,19 +216,22 @@ __device__ __forceinline__ void direct64(const double4* __restrict__ src, int st
     }
 }
 
+// (the difference in FP64 rounded once to FP32, the strengths rounded to
+// FP32, as in the near-field kernel)
 template <bool DER>
-__device__ __forceinline__ void direct32(const float4* __restrict__ src, const float2* __restrict__ lo, int st, int n,
-                                         float yh, float yhl, float yyh, float yyl, float2& phi, float2& dphi)
+__device__ __forceinline__ void direct32(const double* __restrict__ X, const double* __restrict__ Y,
+                                         const double2* __restrict__ mt, int st, int n, double yx, double yy,
+                                         float2& phi, float2& dphi)
 {
 #pragma unroll 8
     for (int q = 0; q < n; ++q) {         // unrolled: eight loads in flight
-        const float4 sv = src[st + q];
-        const float2 sl = lo[st + q];
-        const float dx = (yh - sv.x) + (yhl - sl.x);
-        const float dy = (yyh - sv.y) + (yyl - sl.y);
+        const double2 m = mt[st + q];
+        const float mr = (float)m.x, mi = (float)m.y;
+        const float dx = (float)(yx - X[st + q]);
+        const float dy = (float)(yy - Y[st + q]);
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, FLT_MIN));
         const float id = __builtin_amdgcn_rcpf(r2);
-        const float a = fmaf(sv.z, dx, sv.w * dy), b = fmaf(sv.w, dx, -(sv.z * dy));
+        const float a = fmaf(mr, dx, mi * dy), b = fmaf(mi, dx, -(mr * dy));
         phi.x = fmaf(a, id, phi.x);
         phi.y = fmaf(b, id, phi.y);
         if (DER) {
@@ -256,16 +250,14 @@ __device__ __forceinline__ void direct32(const float4* __restrict__ src, const f
 template <class T, bool DER>
 struct Visit {
     double2 y;
-    float yh, yl, yyh, yyl;
     int L, p;
     double theta;
     const int8_t* level;
     const double* geom;
     const int32_t *bstart, *bcount;
     const T* mpole;
-    const double4* src64;
-    const float4* src32;
-    const float2* srclo;
+    const double *X, *Y;            // the sources: positions and strengths in tree order
+    const double2* mt;
 
     __device__ __forceinline__ bool operator()(int32_t bx, int lv, double2& phi, double2& dphi, float2& nf,
                                                float2& nd, bool direct = false) const
@@ -277,8 +269,8 @@ struct Visit {
             return true;
         }
         if (lv != L - 1) return false;
-        if constexpr (std::is_same<T, float>::value) direct32<DER>(src32, srclo, bstart[bx], bcount[bx], yh, yl, yyh, yyl, nf, nd);
-        else direct64<DER>(src64, bstart[bx], bcount[bx], y.x, y.y, phi, dphi);
+        if constexpr (std::is_same<T, float>::value) direct32<DER>(X, Y, mt, bstart[bx], bcount[bx], y.x, y.y, nf, nd);
+        else direct64<DER>(X, Y, mt, bstart[bx], bcount[bx], y.x, y.y, phi, dphi);
         return true;
     }
 
@@ -324,8 +316,8 @@ k_pts_descend(const double2* __restrict__ y, const int32_t* __restrict__ order, 
               const int32_t* __restrict__ nq_dev, int nq_host, int L, const int8_t* __restrict__ level,
               const double* __restrict__ geom, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
               const int32_t* __restrict__ s_beg, const int32_t* __restrict__ s_cnt, const int32_t* __restrict__ s_ids,
-              const T* __restrict__ mpole, int p, double theta, const double4* __restrict__ src64,
-              const float4* __restrict__ src32, const float2* __restrict__ srclo, double2* tnear, double2* tdnear)
+              const T* __restrict__ mpole, int p, double theta, const double* __restrict__ X,
+              const double* __restrict__ Y, const double2* __restrict__ mt, double2* tnear, double2* tdnear)
 {
     __shared__ int32_t front[4][2][kFront];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -336,13 +328,9 @@ k_pts_descend(const double2* __restrict__ y, const int32_t* __restrict__ order, 
         const int32_t i = order[q];
         Visit<T, DER> vis;
         vis.y = y[i];
-        vis.yh = (float)vis.y.x;
-        vis.yl = (float)(vis.y.x - (double)vis.yh);
-        vis.yyh = (float)vis.y.y;
-        vis.yyl = (float)(vis.y.y - (double)vis.yyh);
         vis.L = L; vis.p = p; vis.theta = theta; vis.level = level; vis.geom = geom;
         vis.bstart = bstart; vis.bcount = bcount; vis.mpole = mpole;
-        vis.src64 = src64; vis.src32 = src32; vis.srclo = srclo;
+        vis.X = X; vis.Y = Y; vis.mt = mt;
         const int32_t B = box[i];
         double2 phi = make_double2(0.0, 0.0), dphi = make_double2(0.0, 0.0);
         float2 nf = make_float2(0.f, 0.f), nd = make_float2(0.f, 0.f);
@@ -477,8 +465,7 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     const int64_t nx = M / kPtsItem + nleaf + 1;
     if (nx >= INT32_MAX / 4) throw Error(FMM_EINVAL, "too many evaluation points");
     DBuf<int32_t> box, order, cnt, off, fill, bsum, icnt, ioff;
-    DBuf<double> rec, tnear, tdnear;
-    DBuf<float> rlo;
+    DBuf<double> rx, ry, tnear, tdnear;
     DBuf<PtsItem> items;
     box.alloc(M, s);
     order.alloc(M, s);
@@ -490,8 +477,8 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
         icnt.alloc(nleaf, s);
         ioff.alloc(nleaf + 1, s);
         items.alloc(nx, s);
-        rec.alloc(mixed ? 2 * M : 4 * M, s);
-        if (mixed) rlo.alloc(2 * M, s);
+        rx.alloc(M, s);
+        ry.alloc(M, s);
     }
     tnear.alloc(2 * M, s);
     if (der) tdnear.alloc(2 * M, s);
@@ -506,8 +493,7 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     if (!der) {
         // the near field of the points in leaves: the near-field kernel, with
         // the points as its targets and the sources of the leaf's strong list
-        if (mixed) k_pts_records<true><<<gm, 256, 0, s>>>((const double2*)y, M, order.p, rec.p, (float2*)rlo.p);
-        else k_pts_records<false><<<gm, 256, 0, s>>>((const double2*)y, M, order.p, rec.p, nullptr);
+        k_pts_records<<<gm, 256, 0, s>>>((const double2*)y, M, order.p, rx.p, ry.p);
         const unsigned gl = (unsigned)((nleaf + 255) / 256);
         k_pts_clear<<<(unsigned)((4 * nx + 255) / 256), 256, 0, s>>>((int32_t*)items.p, 4 * nx);
         k_pts_item_counts<<<gl, 256, 0, s>>>(lb, nleaf, cnt.p, icnt.p);
@@ -515,13 +501,13 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
         k_pts_items<<<gl, 256, 0, s>>>(lb, nleaf, cnt.p, ioff.p, items.p);
         check_launch("point items");
         Targets tgt;
-        tgt.src = rec.p;
-        tgt.lo = (const float2*)rlo.p;
+        tgt.x = rx.p;
+        tgt.y = ry.p;
         tgt.start = off.p;
         launch_p2p(mixed, 4, 4, items.p, 0, nullptr, (int)nx, nullptr, nullptr, nullptr, sc.d_box_start.p,
                    sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,
-                   mixed ? (const void*)pl.src32.p : (const void*)pl.src64.p, mixed ? (const void*)pl.srclo.p : nullptr,
-                   tnear.p, s, nullptr, 0.0, false, tgt, pl.tune.p2p_src_tile);
+                   t.x.p, t.y.p, (const double2*)pl.mtree.p, tnear.p, s, nullptr, 0.0, false, tgt,
+                   pl.tune.p2p_src_tile);
     }
     // descents: the points that stopped above the leaves (box-order positions
     // before the first leaf), or with the derivative every point
@@ -531,35 +517,33 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     (const double2*)y, order.p, box.p, nq_dev, (int)M, L, sc.d_box_level.p, t.geom.p, sc.d_box_start.p,       \
         sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p
 #define FAR_ARGS (const double2*)y, M, order.p, box.p, sc.d_box_level.p, t.geom.p
+#define SRC_ARGS t.x.p, t.y.p, (const double2*)pl.mtree.p
     double2* tn = (double2*)tnear.p;
     double2* td = der ? (double2*)tdnear.p : nullptr;
     if (mixed) {
         const float* mp = (const float*)pl.mpole.p;
         const float* lc = (const float*)pl.local.p;
         if (der) {
-            k_pts_descend<float, true><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, nullptr, (const float4*)pl.src32.p,
-                                                         (const float2*)pl.srclo.p, tn, td);
+            k_pts_descend<float, true><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, SRC_ARGS, tn, td);
             k_pts_far<float, true><<<gm, 256, 0, s>>>(FAR_ARGS, lc, pl.p, tn, td, (double2*)phi, (double2*)dphi);
         } else {
-            k_pts_descend<float, false><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, nullptr, (const float4*)pl.src32.p,
-                                                          (const float2*)pl.srclo.p, tn, nullptr);
+            k_pts_descend<float, false><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, SRC_ARGS, tn, nullptr);
             k_pts_far<float, false><<<gm, 256, 0, s>>>(FAR_ARGS, lc, pl.p, tn, nullptr, (double2*)phi, nullptr);
         }
     } else {
         const double* mp = (const double*)pl.mpole.p;
         const double* lc = (const double*)pl.local.p;
         if (der) {
-            k_pts_descend<double, true><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, (const double4*)pl.src64.p,
-                                                          nullptr, nullptr, tn, td);
+            k_pts_descend<double, true><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, SRC_ARGS, tn, td);
             k_pts_far<double, true><<<gm, 256, 0, s>>>(FAR_ARGS, lc, pl.p, tn, td, (double2*)phi, (double2*)dphi);
         } else {
-            k_pts_descend<double, false><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, (const double4*)pl.src64.p,
-                                                           nullptr, nullptr, tn, nullptr);
+            k_pts_descend<double, false><<<gd, 256, 0, s>>>(DESC_ARGS, mp, pl.p, theta_pt, SRC_ARGS, tn, nullptr);
             k_pts_far<double, false><<<gm, 256, 0, s>>>(FAR_ARGS, lc, pl.p, tn, nullptr, (double2*)phi, nullptr);
         }
     }
 #undef DESC_ARGS
 #undef FAR_ARGS
+#undef SRC_ARGS
     check_launch("points");
 }
 

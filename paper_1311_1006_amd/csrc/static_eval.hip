@@ -82,9 +82,6 @@ size_t static_eval_bytes(Plan& pl)
     std::vector<Slot> v;
     add(v, pl.mtree);
     add(v, pl.near);
-    add(v, pl.src64);
-    add(v, pl.src32);
-    add(v, pl.srclo);
     add(v, pl.mpole);
     add(v, pl.local);
     add(v, pl.bal.partial);
@@ -115,9 +112,6 @@ void evaluate_static(Plan& pl, const double* m, double* phi, hipStream_t s)
     Swap sw;
     add(sw.slots, pl.mtree);
     add(sw.slots, pl.near);
-    add(sw.slots, pl.src64);
-    add(sw.slots, pl.src32);
-    add(sw.slots, pl.srclo);
     add(sw.slots, pl.mpole);
     add(sw.slots, pl.local);
     add(sw.slots, pl.bal.partial);

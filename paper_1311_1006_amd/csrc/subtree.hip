@@ -10,8 +10,8 @@
 // storage type T of the coefficients is float for mixed precision).
 //
 // Upward: one workgroup per box R of level L-3 forms the multipoles of its 16
-// leaves (P2M, with the gather of the strengths and the near-field source
-// records), of its 4 children and of R itself, all from LDS; then one
+// leaves (P2M, with the gather of the strengths into tree order, which the
+// near field reads), of its 4 children and of R itself, all from LDS; then one
 // workgroup per box of level a forms the 3 levels a+2, a+1, a above the
 // level a+3 the previous launch wrote, until the root.  Three launches at
 // L = 9 instead of one per level.
@@ -173,13 +173,6 @@ k_up_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, cons
             const double2 mm = go.m[go.perm[i]];
             const double x = X[i], y = Y[i];
             go.mtree[i] = mm;
-            if constexpr (std::is_same<T, float>::value) {
-                const float xh = (float)x, yh = (float)y;
-                go.src32[i] = make_float4(xh, yh, (float)mm.x, (float)mm.y);
-                go.srclo[i] = make_float2((float)(x - (double)xh), (float)(y - (double)yh));
-            } else {
-                go.src64[i] = make_double4(x, y, mm.x, mm.y);
-            }
             z = make_double2((x - cx) * inv, (y - cy) * inv);
             t = mm;
         } else {
@@ -453,8 +446,8 @@ void launch_up_subtree(int nprob, int L, const int32_t* bstart, const int32_t* b
     else throw Error(FMM_EINVAL, "subtree upward pass needs p <= 32");
 #undef UP_CASE
     check_launch("upward leaves");
-    // the gather is complete here: work that needs only the source records
-    // (the near field) may start
+    // the gather is complete here: work that needs only the strengths in tree
+    // order (the near field) may start
     if (after_leaves) FMM_HIP(hipEventRecord(after_leaves, s));
     // levels L-4 .. 0 in subtrees of at most three levels
     for (int lv = L - 3; lv > 0;) {
