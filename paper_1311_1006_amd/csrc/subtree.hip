@@ -61,40 +61,64 @@ __device__ __forceinline__ int sub_box(int b, int64_t NB, int l, int64_t j)
     return (int)((int64_t)b * NB + level_base(l) + j);
 }
 
-// The binomial table C(k, l), k, l < P, into LDS (row k, column l)
+// The binomial table C(k, l), k, l < P, into LDS (row k, column l), in two
+// steps so that other loads can be issued between them: the loads into
+// registers (all in flight before the first store), then the stores
+template <int P>
+struct BinomRegs {
+    static constexpr int R = (P * P + 255) / 256;   // blocks of 256 threads
+    double v[R];
+};
+template <int P>
+__device__ __forceinline__ BinomRegs<P> binom_load(const double* __restrict__ binom)
+{
+    BinomRegs<P> b;
+#pragma unroll
+    for (int r = 0; r < BinomRegs<P>::R; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        b.v[r] = binom[(i < P * P ? i / P : 0) * kBinomStride + (i < P * P ? i % P : 0)];
+    }
+    return b;
+}
+template <int P>
+__device__ __forceinline__ void binom_store(double (*sb)[P], const BinomRegs<P>& b)
+{
+#pragma unroll
+    for (int r = 0; r < BinomRegs<P>::R; ++r) {
+        const int i = threadIdx.x + 256 * r;
+        if (i < P * P) sb[i / P][i % P] = b.v[r];
+    }
+}
 template <int P>
 __device__ __forceinline__ void load_binom(double (*sb)[P], const double* __restrict__ binom)
 {
-    // all loads in flight before the first store (blocks of 256 threads)
-    constexpr int R = (P * P + 255) / 256;
-    double v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = threadIdx.x + 256 * r;
-        v[r] = i < P * P ? binom[(i / P) * kBinomStride + (i % P)] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = threadIdx.x + 256 * r;
-        if (i < P * P) sb[i / P][i % P] = v[r];
-    }
+    binom_store<P>(sb, binom_load<P>(binom));
 }
 
 // M2M into one parent by one wavefront: lane (c, j), c = lane/16 the child,
 // forms child c's contribution to the coefficients k = j, j + 16 of the
 // parent; co[c] holds child c's coefficients (as stored, in FP64).  The
 // contributions land in part[c][k]; the caller adds them in child order.
-template <int P>
-__device__ __forceinline__ void m2m_wave(int p, const double* __restrict__ geom, int par, int child,
-                                         const double2 (*co)[P], double2 (*tau)[P], double (*rho)[P],
-                                         double2 (*part)[P], const double (*sb)[P])
+// The geometry an M2M step needs (centre and scaling radius of the parent
+// and of the lane's child), loaded ahead of the step.
+struct M2MGeo {
+    double px, py, prs, cx, cy, crs;
+};
+__device__ __forceinline__ M2MGeo m2m_geo(const double* __restrict__ geom, int par, int child)
 {
-    const int lane = threadIdx.x & 63, c = lane >> 4, j = lane & 15;
     const double* gp = geom + 4 * (int64_t)par;
     const double* gc = geom + 4 * (int64_t)child;
-    const double prs = gp[3];
-    const double r = gc[3] / prs;
-    const double2 t = make_double2((gc[0] - gp[0]) / prs, (gc[1] - gp[1]) / prs);
+    return M2MGeo{gp[0], gp[1], gp[3], gc[0], gc[1], gc[3]};
+}
+
+template <int P>
+__device__ __forceinline__ void m2m_wave(int p, const M2MGeo& g, const double2 (*co)[P], double2 (*tau)[P],
+                                         double (*rho)[P], double2 (*part)[P], const double (*sb)[P])
+{
+    const int lane = threadIdx.x & 63, c = lane >> 4, j = lane & 15;
+    const double prs = g.prs;
+    const double r = g.crs / prs;
+    const double2 t = make_double2((g.cx - g.px) / prs, (g.cy - g.py) / prs);
     for (int jj = j; jj < p; jj += 16) {
         tau[c][jj] = sub_cpow(t, jj);
         rho[c][jj] = sub_rpow(r, jj);
@@ -159,7 +183,7 @@ k_up_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, cons
     const int64_t jR = blockIdx.x % nroot;
     const int R = sub_box(b, NB, L - 3, jR);
     const int leaf = sub_box(b, NB, L - 1, 16 * jR + gl);
-    load_binom<P>(sb, binom);
+    const BinomRegs<P> bin = binom_load<P>(binom);   // stored to LDS after P2M
     const int st = bstart[leaf], n = bcount[leaf];
     const double cx = geom[4 * (int64_t)leaf], cy = geom[4 * (int64_t)leaf + 1];
     const double inv = 1.0 / geom[4 * (int64_t)leaf + 3];
@@ -198,15 +222,17 @@ k_up_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, cons
             else sco[gl][k].x = (double)tv;
         }
     }
+    binom_store<P>(sb, bin);
     __syncthreads();   // the binomial table; the leaves of each wavefront are its own lanes'
     // the children of R: wavefront w forms child w from leaves 4w .. 4w+3
     const int cw = sub_box(b, NB, L - 2, 4 * jR + w);
-    m2m_wave<P>(p, geom, cw, sub_box(b, NB, L - 1, 16 * jR + 4 * w + (lane >> 4)), sco + 4 * w, stau[w], srho[w],
-                spart[w], sb);
+    m2m_wave<P>(p, m2m_geo(geom, cw, sub_box(b, NB, L - 1, 16 * jR + 4 * w + (lane >> 4))), sco + 4 * w, stau[w],
+                srho[w], spart[w], sb);
     for (int k = lane; k < p; k += 64) store_coef<T>(mp, cw, p, k, m2m_sum<P>(spart[w], k), &spar[w][k]);
     __syncthreads();
     if (w == 0) {
-        m2m_wave<P>(p, geom, R, sub_box(b, NB, L - 2, 4 * jR + (lane >> 4)), spar, stau[0], srho[0], spart[0], sb);
+        m2m_wave<P>(p, m2m_geo(geom, R, sub_box(b, NB, L - 2, 4 * jR + (lane >> 4))), spar, stau[0], srho[0],
+                    spart[0], sb);
         for (int k = lane; k < p; k += 64) store_coef<T>(mp, R, p, k, m2m_sum<P>(spart[0], k), nullptr);
     }
 }
@@ -224,10 +250,28 @@ k_up_mid(int a, int D, int64_t NB, int nper, const double* __restrict__ geom, in
     __shared__ double2 stau[4][4][P];
     __shared__ double srho[4][4][P];
     __shared__ double2 spart[4][4][P];
+    __shared__ double sg[85][3];          // centre and scaling radius of the boxes under A
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = blockIdx.x / nper;
     const int64_t jA = blockIdx.x % nper;
-    load_binom<P>(sb, binom);
+    const BinomRegs<P> bin = binom_load<P>(binom);
+    // the geometry of A's subtree, levels a .. a+D (at most 85 boxes), loaded
+    // once for all the M2M steps: slot t = (4^d - 1)/3 + i holds box i of
+    // level a+d under A (a thread past the last slot loads the last again)
+    const int ngeo = ((4 << (2 * D)) - 1) / 3;
+    double gv[3];
+    {
+        const int t = min((int)threadIdx.x, ngeo - 1);
+        int d = 0, base = 0;
+        while (t >= base + (1 << (2 * d))) {
+            base += 1 << (2 * d);
+            ++d;
+        }
+        const int64_t box = sub_box(b, NB, a + d, ((int64_t)jA << (2 * d)) + (t - base));
+        gv[0] = geom[4 * box];
+        gv[1] = geom[4 * box + 1];
+        gv[2] = geom[4 * box + 3];
+    }
     // level a+D: 4^D <= 64 boxes, all loads in flight before the first store
     const int nin = 1 << (2 * D);
     constexpr int R = 64 * P / 256;
@@ -242,6 +286,9 @@ k_up_mid(int a, int D, int64_t NB, int nper, const double* __restrict__ geom, in
             v[r] = make_double2((double)mp[2 * (box * p + k)], (double)mp[2 * (box * p + k) + 1]);
         }
     }
+    binom_store<P>(sb, bin);
+    if ((int)threadIdx.x < ngeo)
+        for (int e = 0; e < 3; ++e) sg[threadIdx.x][e] = gv[e];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = threadIdx.x + 256 * r;
@@ -255,8 +302,10 @@ k_up_mid(int a, int D, int64_t NB, int nper, const double* __restrict__ geom, in
         const int lv = a + d, np = 1 << (2 * d);   // parents at level lv under A
         for (int q = w; q < np; q += 4) {
             const int par = sub_box(b, NB, lv, ((int64_t)jA << (2 * d)) + q);
-            const int ch = sub_box(b, NB, lv + 1, ((int64_t)jA << (2 * d + 2)) + 4 * q + (lane >> 4));
-            m2m_wave<P>(p, geom, par, ch, cur + 4 * q, stau[w], srho[w], spart[w], sb);
+            const double* gp = sg[((1 << (2 * d)) - 1) / 3 + q];
+            const double* gc = sg[((4 << (2 * d)) - 1) / 3 + 4 * q + (lane >> 4)];
+            m2m_wave<P>(p, M2MGeo{gp[0], gp[1], gp[2], gc[0], gc[1], gc[2]}, cur + 4 * q, stau[w], srho[w], spart[w],
+                        sb);
             for (int k = lane; k < p; k += 64) store_coef<T>(mp, par, p, k, m2m_sum<P>(spart[w], k), &nxt[q][k]);
             wave_sync();   // spart is rewritten by the next parent of this wavefront
         }
@@ -270,6 +319,11 @@ k_up_mid(int a, int D, int64_t NB, int nper, const double* __restrict__ geom, in
 // ---------------------------------------------------------------- downward
 
 // One workgroup per box R of level L-3.  See the file header.
+// Every global load that does not depend on a computed value (the geometry
+// and the M2L sums of R, of its ancestors, of its children and of the leaf
+// of each 16-lane group, the leaf's first 32 points with their near field)
+// is issued at the start, so the workgroup waits for memory twice (the
+// points' loads need the leaf's start) instead of once per phase.
 template <class T, int P>
 __global__ void __launch_bounds__(256)
 k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
@@ -279,6 +333,8 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
 {
     if (guard != nullptr && *guard != 0) return;   // lists flagged: this launch is void
     using T2 = typename Vec2<T>::type;
+    constexpr int KP = P / 16;          // coefficients per lane of a 16-lane group
+    constexpr int NPT = 2;              // points per lane loaded ahead (a leaf's first 32)
     __shared__ double sb[P][P];
     __shared__ double2 sanc[16][P];     // ancestor coefficients (their M2L sums), then the leaves' expansions
     __shared__ double2 stab[16][P];     // tau powers, one table per 16-lane group
@@ -292,23 +348,62 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
     const int R = sub_box(b, NB, lR, jR);
     const int leaf = sub_box(b, NB, L - 1, 16 * jR + gl);
     const T2* lo = reinterpret_cast<const T2*>(loc);
-    load_binom<P>(sb, binom);
-    // leaf data first, so that its loads overlap the shifts
+    const BinomRegs<P> bin = binom_load<P>(binom);
+    // ---- loads: every one unconditional, at an index clamped into range (a
+    // load under a branch would be waited for where the branch ends); the
+    // lanes that have no use for a value never read it
     const int st = bstart[leaf], n = bcount[leaf];
     const double lcx = geom[4 * (int64_t)leaf], lcy = geom[4 * (int64_t)leaf + 1], lrs = geom[4 * (int64_t)leaf + 3];
     const double Rx = geom[4 * (int64_t)R], Ry = geom[4 * (int64_t)R + 1], Rrs = geom[4 * (int64_t)R + 3];
-    // ---- the ancestors (levels 0 .. lR-1) into R: group gl takes level gl
+    // group gl < nanc: the ancestor of level gl
     const int nanc = lR;
-    if (gl < nanc) {
-        const int A = sub_box(b, NB, gl, jR >> (2 * (lR - gl)));
-        const double* ga = geom + 4 * (int64_t)A;
-        const double ars = ga[3];
-        const double2 t = make_double2((Rx - ga[0]) / ars, (Ry - ga[1]) / ars);
+    const bool anc = gl < nanc;
+    const int A = anc ? sub_box(b, NB, gl, jR >> (2 * (lR - gl))) : R;
+    const double ax = geom[4 * (int64_t)A], ay = geom[4 * (int64_t)A + 1], ars = geom[4 * (int64_t)A + 3];
+    T2 ca[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) ca[q] = lo[(int64_t)A * p + min(sl + 16 * q, p - 1)];
+    // thread l < p: R's own sum
+    const T2 cR = lo[(int64_t)R * p + min((int)threadIdx.x, p - 1)];
+    // group c of wavefront 0 (every wavefront loads it; only wavefront 0
+    // uses it): child c of R
+    const int Cg = sub_box(b, NB, L - 2, 4 * jR + (gl & 3));
+    const double cgx = geom[4 * (int64_t)Cg], cgy = geom[4 * (int64_t)Cg + 1], cgrs = geom[4 * (int64_t)Cg + 3];
+    T2 cc[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) cc[q] = lo[(int64_t)Cg * p + min(sl + 16 * q, p - 1)];
+    // wavefront w: child w of R, the parent of its four leaves; the leaf's own sum
+    const int Cw = sub_box(b, NB, L - 2, 4 * jR + w);
+    const double cwx = geom[4 * (int64_t)Cw], cwy = geom[4 * (int64_t)Cw + 1], cwrs = geom[4 * (int64_t)Cw + 3];
+    T2 cl[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) cl[q] = lo[(int64_t)leaf * p + min(sl + 16 * q, p - 1)];
+    // the leaf's first points (a lane past the leaf's end reads point 0)
+    double px[NPT], py[NPT];
+    double2 pn[NPT];
+    int po[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int j = sl + 16 * q;
+        const int i = j < n ? st + j : 0;
+        px[q] = X[i];
+        py[q] = Y[i];
+        pn[q] = nearf[i];
+        po[q] = perm[i];
+    }
+    binom_store<P>(sb, bin);
+    __syncthreads();   // every wavefront reads rows of the table the others wrote
+    // ---- the ancestors (levels 0 .. lR-1) into R: group gl takes level gl
+    if (anc) {
+        const double2 t = make_double2((Rx - ax) / ars, (Ry - ay) / ars);
         const double rho = Rrs / ars;
-        for (int k = sl; k < p; k += 16) {
-            const T2 c = lo[(int64_t)A * p + k];
-            sanc[gl][k] = make_double2((double)c.x, (double)c.y);
-            stab[gl][k] = sub_cpow(t, k);
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const int k = sl + 16 * q;
+            if (k < p) {
+                sanc[gl][k] = make_double2((double)ca[q].x, (double)ca[q].y);
+                stab[gl][k] = sub_cpow(t, k);
+            }
         }
         wave_sync();
         for (int l = sl; l < p; l += 16) {
@@ -328,10 +423,9 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
     }
     __syncthreads();
     // R's complete expansion: its own M2L sum, then the ancestors top-down
-    if (threadIdx.x < p) {
+    if ((int)threadIdx.x < p) {
         const int l = threadIdx.x;
-        const T2 c = lo[(int64_t)R * p + l];
-        double2 acc = make_double2((double)c.x, (double)c.y);
+        double2 acc = make_double2((double)cR.x, (double)cR.y);
         for (int a = 0; a < nanc; ++a) {
             acc.x += spart[a][l].x;
             acc.y += spart[a][l].y;
@@ -342,13 +436,14 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
     // ---- R into its four children: wavefront 0, lane (c, l)
     if (w == 0) {
         const int c = gl;
-        const int C = sub_box(b, NB, L - 2, 4 * jR + c);
-        const double* gc = geom + 4 * (int64_t)C;
-        const double2 t = make_double2((gc[0] - Rx) / Rrs, (gc[1] - Ry) / Rrs);
-        const double rho = gc[3] / Rrs;
+        const double2 t = make_double2((cgx - Rx) / Rrs, (cgy - Ry) / Rrs);
+        const double rho = cgrs / Rrs;
         for (int k = sl; k < p; k += 16) stab[c][k] = sub_cpow(t, k);
         wave_sync();
-        for (int l = sl; l < p; l += 16) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const int l = sl + 16 * q;
+            if (l >= p) continue;
             double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
@@ -360,23 +455,21 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
                 }
             }
             const double rl = sub_rpow(rho, l);
-            const T2 own = lo[(int64_t)C * p + l];
-            sC[c][l] = make_double2((double)own.x + rl * acc.x, (double)own.y + rl * acc.y);
+            sC[c][l] = make_double2((double)cc[q].x + rl * acc.x, (double)cc[q].y + rl * acc.y);
         }
     }
     __syncthreads();
     // ---- child w into its four leaves (wavefront w, group gl = leaf 4w + m):
     // the leaf's complete expansion, stored (the storage type) and kept for L2P
     {
-        const int C = sub_box(b, NB, L - 2, 4 * jR + w);
-        const double* gc = geom + 4 * (int64_t)C;
-        const double crs = gc[3];
-        const double2 t = make_double2((lcx - gc[0]) / crs, (lcy - gc[1]) / crs);
-        const double rho = lrs / crs;
+        const double2 t = make_double2((lcx - cwx) / cwrs, (lcy - cwy) / cwrs);
+        const double rho = lrs / cwrs;
         for (int k = sl; k < p; k += 16) stab[gl][k] = sub_cpow(t, k);
         wave_sync();
         T2* lw = reinterpret_cast<T2*>(loc);
-        for (int l = sl; l < P; l += 16) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const int l = sl + 16 * q;
             if (l >= p) {
                 sanc[gl][l] = make_double2(0.0, 0.0);
                 continue;
@@ -392,8 +485,7 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
                 }
             }
             const double rl = sub_rpow(rho, l);
-            const T2 own = lo[(int64_t)leaf * p + l];
-            const T tx = (T)((double)own.x + rl * acc.x), ty = (T)((double)own.y + rl * acc.y);
+            const T tx = (T)((double)cl[q].x + rl * acc.x), ty = (T)((double)cl[q].y + rl * acc.y);
             lw[(int64_t)leaf * p + l] = T2{tx, ty};
             sanc[gl][l] = make_double2((double)tx, (double)ty);
         }
@@ -402,9 +494,24 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
     // ---- L2P at the leaf's points (Horner), plus the near field, to input order
     const double inv = 1.0 / lrs;
     const double2* co = sanc[gl];
-    for (int j = sl; j < n; j += 16) {
+    for (int j = sl, q = 0; j < n; j += 16, ++q) {
         const int i = st + j;
-        const double2 z = make_double2((X[i] - lcx) * inv, (Y[i] - lcy) * inv);
+        double x, y, nfx, nfy;
+        int o;
+        if (q < NPT) {
+            // (a run-time index into the arrays would move them to scratch)
+            x = q == 0 ? px[0] : px[NPT - 1];
+            y = q == 0 ? py[0] : py[NPT - 1];
+            nfx = q == 0 ? pn[0].x : pn[NPT - 1].x;
+            nfy = q == 0 ? pn[0].y : pn[NPT - 1].y;
+            o = q == 0 ? po[0] : po[NPT - 1];
+        } else {
+            x = X[i]; y = Y[i];
+            const double2 nf = nearf[i];
+            nfx = nf.x; nfy = nf.y;
+            o = perm[i];
+        }
+        const double2 z = make_double2((x - lcx) * inv, (y - lcy) * inv);
         double2 acc = co[P - 1];
 #pragma unroll
         for (int l = P - 2; l >= 0; --l) {
@@ -412,10 +519,8 @@ k_down_leaf(int L, int64_t NB, int nroot, const int32_t* __restrict__ bstart, co
             acc.x += co[l].x;
             acc.y += co[l].y;
         }
-        const double2 nf = nearf[i];
-        const int o = perm[i];
-        if (phi) phi[o] = make_double2(acc.x + nf.x, acc.y + nf.y);
-        if (phi_near) phi_near[o] = nf;
+        if (phi) phi[o] = make_double2(acc.x + nfx, acc.y + nfy);
+        if (phi_near) phi_near[o] = make_double2(nfx, nfy);
         if (phi_far) phi_far[o] = acc;
     }
 }
