@@ -156,6 +156,8 @@ struct TravCtx {
     const int32_t* boxes;     // global ids of the pass's boxes (levels l0..l1)
     int n;
     int l0;
+    int64_t first = -1;       // >= 0: a single problem, and box i of the pass is box first + i
+                              // of level l0 (no id, level or problem loads)
     int cs, cw;               // per-box list capacities of the one-pass build
     const int32_t* prob;
     const int8_t* level;
@@ -347,13 +349,32 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
     // one sibling group per wavefront: its values are uniform (scalar registers)
     const int i = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + wv) * 4);
     if (i >= c.n) return;
-    const int64_t g0 = c.boxes[i];                    // first of four siblings
-    const int L = c.level[g0];
-    const int64_t pb = c.pbox[c.prob[g0]];
+    int64_t g0, pb;                                   // first of four siblings, its problem's base
+    int L;
+    if (c.first >= 0) {
+        g0 = c.first + i;
+        L = c.l0;
+        pb = 0;
+    } else {
+        g0 = c.boxes[i];
+        L = c.level[g0];
+        pb = c.pbox[c.prob[g0]];
+    }
     const int64_t jl = g0 - pb - level_base(L);
     bool overflow = false, cap_overflow = false;
     const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
-    const int64_t ab = s_beg[a0];
+    // the parent's strong list: with fixed capacities it starts at a0 * cs,
+    // so the ids of the first loop trip are loaded beside its length (the
+    // entries past the length are loaded but never used)
+    const int64_t ab = MODE == 2 ? a0 * c.cs : (int64_t)s_beg[a0];
+    int32_t q_first[kCandGroups];
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int u = 0; u < kCandGroups; ++u) {
+            const int64_t e = ab + ((64 * u + lane) >> 2);
+            q_first[u] = s_ids[e < cap_s ? e : cap_s - 1];
+        }
+    }
     int nf = s_cnt[a0];
     if (MODE == 2 && nf > c.cs) { cap_overflow = true; nf = c.cs; }
     double gx[4], gy[4], gr[4];
@@ -383,7 +404,10 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
             valid[u] = idx < ncand;
             const int64_t e = ab + (idx >> 2);
             int32_t q = (int32_t)(pb + lbp);
-            if (valid[u]) q = e < cap_s ? s_ids[e] : (int32_t)pb;
+            if (valid[u]) {
+                if (MODE == 2 && c0 == 0) q = e < cap_s ? q_first[u] : (int32_t)pb;
+                else q = e < cap_s ? s_ids[e] : (int32_t)pb;
+            }
             const int64_t qj = (int64_t)q - pb - lbp;
             if (valid[u] && (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1))))) {
                 valid[u] = false;                       // not a box of that level: never
@@ -467,6 +491,7 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         c.cs = c.cw = 0;
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
+        c.first = sc.nprob == 1 && sc.pbox[0] == 0 && l0 == l1 ? level_base(l0) : -1;
         c.child0 = nullptr; c.box_count = nullptr; c.nsrc = nullptr;
         const bool sib = l0 == l1 && l0 >= 1;   // one level: sibling groups
         const unsigned grid = (unsigned)((c.n + 3) / 4), sgrid = (unsigned)((c.n / 4 + 3) / 4);
@@ -542,6 +567,7 @@ static void build_lists_direct(Plan& pl, hipStream_t s, long long* totals, const
         c.cw = ex.cap_weak;
         c.prob = sc.d_box_prob.p; c.level = sc.d_box_level.p; c.pbox = pbox;
         c.geom = t.geom.p; c.theta = pl.theta;
+        c.first = sc.nprob == 1 && sc.pbox[0] == 0 && l0 == l1 ? level_base(l0) : -1;
         c.child0 = ex.child0.p; c.box_count = sc.d_box_count.p; c.nsrc = pl.nsrc.p;
         if (l0 == l1 && l0 >= 1) {
             // one level: sibling groups (the level's box list is four-aligned)
