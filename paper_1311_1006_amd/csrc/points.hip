@@ -223,8 +223,10 @@ __device__ __forceinline__ void direct32(const double* __restrict__ X, const dou
                                          const double2* __restrict__ mt, int st, int n, double yx, double yy,
                                          float2& phi, float2& dphi)
 {
-#pragma unroll 8
-    for (int q = 0; q < n; ++q) {         // unrolled: eight loads in flight
+    // unrolled by four: with eight sources' loads in flight the descent kernel
+    // held 129 vector registers (3 wavefronts per SIMD) and ran 1.6x longer
+#pragma unroll 4
+    for (int q = 0; q < n; ++q) {
         const double2 m = mt[st + q];
         const float mr = (float)m.x, mi = (float)m.y;
         const float dx = (float)(yx - X[st + q]);
