@@ -158,6 +158,8 @@ struct TravCtx {
     int l0;
     int64_t first = -1;       // >= 0: a single problem, and box i of the pass is box first + i
                               // of level l0 (no id, level or problem loads)
+    int32_t* long_q = nullptr;   // count and fill passes by sibling groups: the groups whose
+    int32_t* long_n = nullptr;   // parent list is long, queued for k_traverse_long (and their count)
     int cs, cw;               // per-box list capacities of the one-pass build
     const int32_t* prob;
     const int8_t* level;
@@ -326,6 +328,17 @@ static std::vector<std::pair<int, int>> traversal_passes(int levels, bool single
     return r;
 }
 
+// A sibling group whose parent's strong list is longer than this is handled
+// by a whole workgroup (k_traverse_long) in the count and fill passes: one
+// wavefront walking a list of thousands of boxes (clustered points, where a
+// leaf holding a point far from the others is strong with most of its level)
+// took milliseconds alone.
+constexpr int kLongList = 1024;
+constexpr int kLongWaves = 16;      // wavefronts of a k_traverse_long workgroup
+static_assert(kLongWaves == 16, "the counts of a trip are summed over 16 lanes");
+constexpr int kLongGrid = 256;      // its workgroups (they take the queued groups in turn)
+constexpr int kLongFromLevel = 6;   // a parent level of fewer than kLongList boxes has no long list
+
 // Candidates taken per loop trip of k_traverse_sib: four groups of 64 whose
 // id and geometry loads are all issued before the first test, so a long
 // parent list costs one memory round trip per 256 candidates.
@@ -377,6 +390,12 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
     }
     int nf = s_cnt[a0];
     if (MODE == 2 && nf > c.cs) { cap_overflow = true; nf = c.cs; }
+    // a long parent list: the count pass queues the group for
+    // k_traverse_long, the fill pass finds it queued
+    if (MODE != 2 && c.long_q != nullptr && nf > kLongList) {
+        if (MODE == 0 && lane == 0) c.long_q[atomicAdd(c.long_n, 1)] = i;
+        return;
+    }
     double gx[4], gy[4], gr[4];
     int64_t sb[4], wb[4], ls[4], lw[4];
 #pragma unroll
@@ -475,6 +494,126 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
     }
 }
 
+// The count (MODE 0) and fill (MODE 1) passes of the sibling groups that
+// k_traverse_sib queued: a workgroup of kLongWaves wavefronts per group,
+// 64 * kLongWaves candidates per loop trip (wavefront w takes the w-th run of
+// 64).  Every wavefront's strong and weak counts of a trip go through LDS, so
+// the lists are written in candidate order, as k_traverse_sib writes them.
+// The workgroups take the queued groups in turn until the queue is done.
+template <int MODE>
+__global__ void __launch_bounds__(1024)
+k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __restrict__ qn, int32_t* s_beg,
+                int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids, int32_t* w_ids, int64_t cap_s,
+                int64_t cap_w, long long* totals)
+{
+    static_assert(MODE == 0 || MODE == 1, "count or fill");
+    __shared__ int cnt_s[4][kLongWaves], cnt_w[4][kLongWaves];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int nq = *qn;
+    bool overflow = false;
+    for (int k = blockIdx.x; k < nq; k += gridDim.x) {
+        const int i = queue[k];
+        int64_t g0, pb;
+        int L;
+        if (c.first >= 0) {
+            g0 = c.first + i;
+            L = c.l0;
+            pb = 0;
+        } else {
+            g0 = c.boxes[i];
+            L = c.level[g0];
+            pb = c.pbox[c.prob[g0]];
+        }
+        const int64_t jl = g0 - pb - level_base(L);
+        const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
+        const int64_t ab = s_beg[a0];
+        const int nf = s_cnt[a0];
+        double gx[4], gy[4], gr[4];
+        int64_t sb[4], wb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double* gg = c.geom + 4 * (g0 + t);
+            gx[t] = gg[0]; gy[t] = gg[1]; gr[t] = gg[2];
+            sb[t] = MODE == 1 ? (int64_t)s_beg[g0 + t] : 0;
+            wb[t] = MODE == 1 ? (int64_t)w_beg[g0 + t] : 0;
+        }
+        const int64_t lb = level_base(L), lbp = level_base(L - 1);
+        int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
+        const int64_t ncand = 4 * (int64_t)nf;
+        for (int64_t c0 = 0; c0 < ncand; c0 += 64 * kLongWaves) {
+            const int64_t idx = c0 + 64 * wv + lane;
+            bool valid = idx < ncand;
+            const int64_t e = ab + (idx >> 2);
+            int32_t q = (int32_t)(pb + lbp);
+            if (valid) q = e < cap_s ? s_ids[e] : (int32_t)pb;
+            const int64_t qj = (int64_t)q - pb - lbp;
+            if (valid && (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1))))) {
+                valid = false;                          // not a box of that level: never
+                overflow = true;                        // dereferenced, list rebuilt
+            }
+            const int32_t cc = valid ? (int32_t)(pb + lb + 4 * qj + (idx & 3)) : (int32_t)g0;
+            const double* gc = c.geom + 4 * (int64_t)cc;
+            const double cg[4] = {gc[0], gc[1], gc[2], 0.0};
+            unsigned long long bs[4], bw[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
+                const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
+                bs[t] = __ballot(valid && !weak);
+                bw[t] = __ballot(weak);
+                if (lane == 0) {
+                    cnt_s[t][wv] = __popcll(bs[t]);
+                    cnt_w[t][wv] = __popcll(bw[t]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                // this wavefront's offsets in the trip and the trip's totals:
+                // lane w < kLongWaves reads wavefront w's counts, sums over the
+                // first kLongWaves lanes (the other lanes hold zeros)
+                const int a = lane < kLongWaves ? cnt_s[t][lane] : 0, b = lane < kLongWaves ? cnt_w[t][lane] : 0;
+                int ps = lane < wv ? a : 0, pw = lane < wv ? b : 0, ts = a, tw = b;
+#pragma unroll
+                for (int o = kLongWaves / 2; o > 0; o >>= 1) {
+                    ps += __shfl_xor(ps, o, 64);
+                    pw += __shfl_xor(pw, o, 64);
+                    ts += __shfl_xor(ts, o, 64);
+                    tw += __shfl_xor(tw, o, 64);
+                }
+                ps = __builtin_amdgcn_readfirstlane(ps);
+                pw = __builtin_amdgcn_readfirstlane(pw);
+                ts = __builtin_amdgcn_readfirstlane(ts);
+                tw = __builtin_amdgcn_readfirstlane(tw);
+                if (MODE == 1) {
+                    if ((bs[t] >> lane) & 1ull) {
+                        const int64_t o = sb[t] + ns[t] + ps + __popcll(bs[t] & below);
+                        if (o < cap_s) s_ids[o] = cc;
+                    }
+                    if ((bw[t] >> lane) & 1ull) {
+                        const int64_t o = wb[t] + nw[t] + pw + __popcll(bw[t] & below);
+                        if (o < cap_w) w_ids[o] = cc;
+                    }
+                }
+                ns[t] += ts;
+                nw[t] += tw;
+            }
+            __syncthreads();   // the counts are rewritten by the next trip
+        }
+        if (MODE == 0 && threadIdx.x == 0) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                s_cnt[g0 + t] = ns[t];
+                w_cnt[g0 + t] = nw[t];
+            }
+        }
+    }
+    if (__ballot(overflow) != 0ull && lane == 0) atomicOr((unsigned long long*)&totals[2], 2ull);
+}
+
+__global__ void k_zero_counter(int32_t* p) { if (threadIdx.x == 0) *p = 0; }
+
 static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_t cap_w, long long* totals,
                                   const int64_t* pbox, long long* bsum, long long* snap, bool single)
 {
@@ -482,6 +621,14 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
     TreeSchedule& sc = *t.sched;
     const PlanExtra& ex = *pl.ex;
     k_totals_init<<<1, 64, 0, s>>>(totals, t.err.p);
+    // the queue of sibling groups with long parent lists: its count, then at
+    // most one entry per group of the largest sibling pass
+    int64_t max_groups = 0;
+    for (auto [l0, l1] : traversal_passes(sc.max_levels, single))
+        if (l0 == l1 && l0 >= kLongFromLevel)
+            max_groups = std::max<int64_t>(max_groups, (ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]) / 4);
+    DBuf<int32_t> lq;
+    if (max_groups > 0) lq.alloc(max_groups + 1, s);
     for (auto [l0, l1] : traversal_passes(sc.max_levels, single)) {
         TravCtx c;
         c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
@@ -494,6 +641,12 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         c.first = sc.nprob == 1 && sc.pbox[0] == 0 && l0 == l1 ? level_base(l0) : -1;
         c.child0 = nullptr; c.box_count = nullptr; c.nsrc = nullptr;
         const bool sib = l0 == l1 && l0 >= 1;   // one level: sibling groups
+        const bool longq = sib && l0 >= kLongFromLevel;
+        if (longq) {
+            c.long_n = lq.p;
+            c.long_q = lq.p + 1;
+            k_zero_counter<<<1, 64, 0, s>>>(c.long_n);
+        }
         const unsigned grid = (unsigned)((c.n + 3) / 4), sgrid = (unsigned)((c.n / 4 + 3) / 4);
         if (sib)
             k_traverse_sib<0><<<sgrid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
@@ -501,6 +654,10 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         else
             k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
+        if (longq)
+            k_traverse_long<0><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, pl.s_beg.p, pl.s_cnt.p,
+                                                                     pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
+                                                                     cap_s, cap_w, totals);
         const int nb = (c.n + 1023) / 1024;
         k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, totals, snap);
         k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, snap, pl.s_beg.p,
@@ -511,6 +668,10 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         else
             k_traverse<1><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
+        if (longq)
+            k_traverse_long<1><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, pl.s_beg.p, pl.s_cnt.p,
+                                                                     pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
+                                                                     cap_s, cap_w, totals);
         check_launch("traversal lists");
     }
 }
