@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "fmm_internal.h"
+#include "kernels_common.h"
 #include "plan_extra.h"
 
 // Box geometry, split axes and the theta-criterion must round every product
@@ -335,7 +336,7 @@ static std::vector<std::pair<int, int>> traversal_passes(int levels, bool single
 // took milliseconds alone.
 constexpr int kLongList = 1024;
 constexpr int kLongWaves = 16;      // wavefronts of a k_traverse_long workgroup
-static_assert(kLongWaves == 16, "the counts of a trip are summed over 16 lanes");
+constexpr int kLongGroups = 4;      // runs of 64 candidates per wavefront and loop trip
 constexpr int kLongGrid = 256;      // its workgroups (they take the queued groups in turn)
 constexpr int kLongFromLevel = 6;   // a parent level of fewer than kLongList boxes has no long list
 
@@ -496,10 +497,12 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
 
 // The count (MODE 0) and fill (MODE 1) passes of the sibling groups that
 // k_traverse_sib queued: a workgroup of kLongWaves wavefronts per group,
-// 64 * kLongWaves candidates per loop trip (wavefront w takes the w-th run of
-// 64).  Every wavefront's strong and weak counts of a trip go through LDS, so
-// the lists are written in candidate order, as k_traverse_sib writes them.
-// The workgroups take the queued groups in turn until the queue is done.
+// kLongGroups * 64 * kLongWaves candidates per loop trip (run r = u *
+// kLongWaves + w of 64 belongs to wavefront w, u < kLongGroups; every load of
+// a trip is issued before its first test).  The strong and weak counts of
+// every run go through LDS and are scanned over the runs, so the lists are
+// written in candidate order, as k_traverse_sib writes them.  The
+// workgroups take the queued groups in turn until the queue is done.
 template <int MODE>
 __global__ void __launch_bounds__(1024)
 k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __restrict__ qn, int32_t* s_beg,
@@ -507,7 +510,9 @@ k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __r
                 int64_t cap_w, long long* totals)
 {
     static_assert(MODE == 0 || MODE == 1, "count or fill");
-    __shared__ int cnt_s[4][kLongWaves], cnt_w[4][kLongWaves];
+    constexpr int G = kLongGroups, NR = kLongGroups * kLongWaves;   // runs of 64 per trip
+    static_assert(NR == 64, "one run per lane in the scan of a trip's counts");
+    __shared__ int cnt_s[4][NR], cnt_w[4][NR];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int nq = *qn;
@@ -541,63 +546,72 @@ k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __r
         const int64_t lb = level_base(L), lbp = level_base(L - 1);
         int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
         const int64_t ncand = 4 * (int64_t)nf;
-        for (int64_t c0 = 0; c0 < ncand; c0 += 64 * kLongWaves) {
-            const int64_t idx = c0 + 64 * wv + lane;
-            bool valid = idx < ncand;
-            const int64_t e = ab + (idx >> 2);
-            int32_t q = (int32_t)(pb + lbp);
-            if (valid) q = e < cap_s ? s_ids[e] : (int32_t)pb;
-            const int64_t qj = (int64_t)q - pb - lbp;
-            if (valid && (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1))))) {
-                valid = false;                          // not a box of that level: never
-                overflow = true;                        // dereferenced, list rebuilt
-            }
-            const int32_t cc = valid ? (int32_t)(pb + lb + 4 * qj + (idx & 3)) : (int32_t)g0;
-            const double* gc = c.geom + 4 * (int64_t)cc;
-            const double cg[4] = {gc[0], gc[1], gc[2], 0.0};
-            unsigned long long bs[4], bw[4];
+        for (int64_t c0 = 0; c0 < ncand; c0 += 64 * NR) {
+            bool valid[G];
+            int32_t cc[G];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
-                const bool weak = valid && (cc != g0 + t) && well_separated(gb, cg, c.theta);
-                bs[t] = __ballot(valid && !weak);
-                bw[t] = __ballot(weak);
-                if (lane == 0) {
-                    cnt_s[t][wv] = __popcll(bs[t]);
-                    cnt_w[t][wv] = __popcll(bw[t]);
+            for (int u = 0; u < G; ++u) {
+                const int64_t idx = c0 + 64 * (u * kLongWaves + wv) + lane;
+                valid[u] = idx < ncand;
+                const int64_t e = ab + (idx >> 2);
+                int32_t q = (int32_t)(pb + lbp);
+                if (valid[u]) q = e < cap_s ? s_ids[e] : (int32_t)pb;
+                const int64_t qj = (int64_t)q - pb - lbp;
+                if (valid[u] && (qj < 0 || qj >= (int64_t(1) << (2 * (L - 1))))) {
+                    valid[u] = false;                   // not a box of that level: never
+                    overflow = true;                    // dereferenced, list rebuilt
                 }
+                cc[u] = valid[u] ? (int32_t)(pb + lb + 4 * qj + (idx & 3)) : (int32_t)g0;
             }
+            double cg[G][4];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const double* gc = c.geom + 4 * (int64_t)cc[u];
+                cg[u][0] = gc[0]; cg[u][1] = gc[1]; cg[u][2] = gc[2]; cg[u][3] = 0.0;
+            }
+            // bit 2 (t G + u) strong, the next bit weak
+            uint32_t bits = 0;
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double gb[4] = {gx[t], gy[t], gr[t], 0.0};
+                    const bool weak = valid[u] && (cc[u] != g0 + t) && well_separated(gb, cg[u], c.theta);
+                    const bool strong = valid[u] && !weak;
+                    bits |= ((uint32_t)strong | ((uint32_t)weak << 1)) << (2 * (t * G + u));
+                    const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
+                    if (lane == 0) {
+                        cnt_s[t][u * kLongWaves + wv] = __popcll(bs);
+                        cnt_w[t][u * kLongWaves + wv] = __popcll(bw);
+                    }
+                }
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                // this wavefront's offsets in the trip and the trip's totals:
-                // lane w < kLongWaves reads wavefront w's counts, sums over the
-                // first kLongWaves lanes (the other lanes hold zeros)
-                const int a = lane < kLongWaves ? cnt_s[t][lane] : 0, b = lane < kLongWaves ? cnt_w[t][lane] : 0;
-                int ps = lane < wv ? a : 0, pw = lane < wv ? b : 0, ts = a, tw = b;
-#pragma unroll
-                for (int o = kLongWaves / 2; o > 0; o >>= 1) {
-                    ps += __shfl_xor(ps, o, 64);
-                    pw += __shfl_xor(pw, o, 64);
-                    ts += __shfl_xor(ts, o, 64);
-                    tw += __shfl_xor(tw, o, 64);
-                }
-                ps = __builtin_amdgcn_readfirstlane(ps);
-                pw = __builtin_amdgcn_readfirstlane(pw);
-                ts = __builtin_amdgcn_readfirstlane(ts);
-                tw = __builtin_amdgcn_readfirstlane(tw);
+                // lane r holds the counts of run r; inclusive scans over the runs
+                const int a = cnt_s[t][lane], b = cnt_w[t][lane];
+                const int xa = wave_incl_scan(a), xb = wave_incl_scan(b);
                 if (MODE == 1) {
-                    if ((bs[t] >> lane) & 1ull) {
-                        const int64_t o = sb[t] + ns[t] + ps + __popcll(bs[t] & below);
-                        if (o < cap_s) s_ids[o] = cc;
-                    }
-                    if ((bw[t] >> lane) & 1ull) {
-                        const int64_t o = wb[t] + nw[t] + pw + __popcll(bw[t] & below);
-                        if (o < cap_w) w_ids[o] = cc;
+                    const int ea = xa - a, eb = xb - b;
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        const int r = u * kLongWaves + wv;      // this wavefront's run of group u
+                        const int ps = __builtin_amdgcn_readlane(ea, r), pw = __builtin_amdgcn_readlane(eb, r);
+                        const int sh = 2 * (t * G + u);
+                        const bool strong = (bits >> sh) & 1u, weak = (bits >> (sh + 1)) & 1u;
+                        const unsigned long long bs = __ballot(strong), bw = __ballot(weak);
+                        if (strong) {
+                            const int64_t o = sb[t] + ns[t] + ps + __popcll(bs & below);
+                            if (o < cap_s) s_ids[o] = cc[u];
+                        }
+                        if (weak) {
+                            const int64_t o = wb[t] + nw[t] + pw + __popcll(bw & below);
+                            if (o < cap_w) w_ids[o] = cc[u];
+                        }
                     }
                 }
-                ns[t] += ts;
-                nw[t] += tw;
+                ns[t] += __builtin_amdgcn_readlane(xa, 63);
+                nw[t] += __builtin_amdgcn_readlane(xb, 63);
             }
             __syncthreads();   // the counts are rewritten by the next trip
         }
