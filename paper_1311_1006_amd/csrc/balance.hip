@@ -127,18 +127,19 @@ k_item_combine(const BalItem* __restrict__ items, int n, const int32_t* __restri
     const int64_t o = ioff[i];
     const int64_t dst = (int64_t)bstart[it.leaf] + it.t0 + lane;
     for (int q = 0; q < vals; ++q) {
-        // the values of eight chunks are loaded together, then added in chunk
-        // order (one memory round trip per eight chunks instead of per chunk)
+        // the values of sixteen chunks are loaded together, then added in
+        // chunk order (one memory round trip per sixteen chunks instead of per
+        // chunk)
         const double* pq = part + (o * kItemTargets + lane) * vals + q;
         const int64_t step = (int64_t)kItemTargets * vals;
         double s = 0.0;
         int k = 0;
-        for (; k + 8 <= c; k += 8) {
-            double v[8];
+        for (; k + 16 <= c; k += 16) {
+            double v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = pq[(k + u) * step];
+            for (int u = 0; u < 16; ++u) v[u] = pq[(k + u) * step];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
+            for (int u = 0; u < 16; ++u) s += v[u];
         }
         for (; k < c; ++k) s += pq[k * step];
         out[dst * vals + q] = s;

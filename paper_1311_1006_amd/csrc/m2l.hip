@@ -428,9 +428,27 @@ __global__ void k_m2l_combine(const int32_t* __restrict__ boxes, int n, const in
     if (c <= 1) return;
     const int64_t o = ioff[i];
     double re = 0.0, im = 0.0;
-    for (int k = 0; k < c; ++k) {
-        re += partial[2 * ((o + k) * p + row)];
-        im += partial[2 * ((o + k) * p + row) + 1];
+    // the values of eight chunks are loaded together, then added in chunk
+    // order (a list of thousands of chunks took a memory round trip per chunk)
+    const double* pr = partial + 2 * (o * p + row);
+    const int64_t step = 2 * (int64_t)p;
+    int k = 0;
+    for (; k + 8 <= c; k += 8) {
+        double vr[8], vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            vr[u] = pr[(k + u) * step];
+            vi[u] = pr[(k + u) * step + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            re += vr[u];
+            im += vi[u];
+        }
+    }
+    for (; k < c; ++k) {
+        re += pr[k * step];
+        im += pr[k * step + 1];
     }
     T* dst = loc + 2 * ((int64_t)(boxes ? boxes[i] : i) * p + row);
     dst[0] = (T)re;
