@@ -337,7 +337,9 @@ static std::vector<std::pair<int, int>> traversal_passes(int levels, bool single
 constexpr int kLongList = 1024;
 constexpr int kLongWaves = 16;      // wavefronts of a k_traverse_long workgroup
 constexpr int kLongGroups = 4;      // runs of 64 candidates per wavefront and loop trip
-constexpr int kLongGrid = 256;      // its workgroups (they take the queued groups in turn)
+constexpr int kLongGrid = 256;      // its workgroups (they take the work units in turn)
+constexpr int kLongUnits = 16;      // work units of a split group (runs of consecutive trips)
+constexpr int kLongSplitCap = 4096; // queued groups split into units (later ones are one unit)
 constexpr int kLongFromLevel = 6;   // a parent level of fewer than kLongList boxes has no long list
 
 // Candidates taken per loop trip of k_traverse_sib: four groups of 64 whose
@@ -496,28 +498,38 @@ k_traverse_sib(TravCtx c, int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_
 }
 
 // The count (MODE 0) and fill (MODE 1) passes of the sibling groups that
-// k_traverse_sib queued: a workgroup of kLongWaves wavefronts per group,
-// kLongGroups * 64 * kLongWaves candidates per loop trip (run r = u *
+// k_traverse_sib queued, by a workgroup of kLongWaves wavefronts per work
+// unit, kLongGroups * 64 * kLongWaves candidates per loop trip (run r = u *
 // kLongWaves + w of 64 belongs to wavefront w, u < kLongGroups; every load of
 // a trip is issued before its first test).  The strong and weak counts of
 // every run go through LDS and are scanned over the runs, so the lists are
-// written in candidate order, as k_traverse_sib writes them.  The
-// workgroups take the queued groups in turn until the queue is done.
+// written in candidate order, as k_traverse_sib writes them.  The first
+// kLongSplitCap queued groups are split into kLongUnits units of consecutive
+// trips: the count pass writes each unit's counts to ucnt, k_long_finish
+// turns them into offsets (exclusive prefixes in unit order) and the
+// siblings' list lengths, and the fill pass starts each unit at its offset.
+// Later queued groups are one unit.  The workgroups take the units in turn.
 template <int MODE>
 __global__ void __launch_bounds__(1024)
-k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __restrict__ qn, int32_t* s_beg,
-                int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids, int32_t* w_ids, int64_t cap_s,
-                int64_t cap_w, long long* totals)
+k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __restrict__ qn, int32_t* ucnt,
+                int32_t* s_beg, int32_t* s_cnt, int32_t* w_beg, int32_t* w_cnt, int32_t* s_ids, int32_t* w_ids,
+                int64_t cap_s, int64_t cap_w, long long* totals)
 {
     static_assert(MODE == 0 || MODE == 1, "count or fill");
     constexpr int G = kLongGroups, NR = kLongGroups * kLongWaves;   // runs of 64 per trip
     static_assert(NR == 64, "one run per lane in the scan of a trip's counts");
+    constexpr int64_t kTrip = 64 * NR;                               // candidates per trip
     __shared__ int cnt_s[4][NR], cnt_w[4][NR];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int nq = *qn;
+    const int ks = min(nq, kLongSplitCap);                           // split groups
+    const int64_t nunits = (int64_t)ks * kLongUnits + (nq - ks);
     bool overflow = false;
-    for (int k = blockIdx.x; k < nq; k += gridDim.x) {
+    for (int64_t unit = blockIdx.x; unit < nunits; unit += gridDim.x) {
+        const bool split = unit < (int64_t)ks * kLongUnits;
+        const int k = split ? (int)(unit / kLongUnits) : ks + (int)(unit - (int64_t)ks * kLongUnits);
+        const int j = split ? (int)(unit % kLongUnits) : 0;
         const int i = queue[k];
         int64_t g0, pb;
         int L;
@@ -534,19 +546,36 @@ k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __r
         const int64_t a0 = pb + level_base(L - 1) + (jl >> 2);
         const int64_t ab = s_beg[a0];
         const int nf = s_cnt[a0];
+        const int64_t ncand = 4 * (int64_t)nf;
+        const int64_t ntrip = (ncand + kTrip - 1) / kTrip;
+        int64_t tr0 = 0, tr1 = ntrip;                                // this unit's trips
+        if (split) {
+            const int64_t tpu = (ntrip + kLongUnits - 1) / kLongUnits;
+            tr0 = min(ntrip, (int64_t)j * tpu);
+            tr1 = min(ntrip, tr0 + tpu);
+        }
         double gx[4], gy[4], gr[4];
         int64_t sb[4], wb[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const double* gg = c.geom + 4 * (g0 + t);
             gx[t] = gg[0]; gy[t] = gg[1]; gr[t] = gg[2];
-            sb[t] = MODE == 1 ? (int64_t)s_beg[g0 + t] : 0;
-            wb[t] = MODE == 1 ? (int64_t)w_beg[g0 + t] : 0;
+            sb[t] = 0;
+            wb[t] = 0;
+            if (MODE == 1) {
+                sb[t] = s_beg[g0 + t];
+                wb[t] = w_beg[g0 + t];
+                if (split) {                            // the unit's offsets in the lists
+                    const int64_t uo = ((int64_t)k * kLongUnits + j) * 8 + 2 * t;
+                    sb[t] += ucnt[uo];
+                    wb[t] += ucnt[uo + 1];
+                }
+            }
         }
         const int64_t lb = level_base(L), lbp = level_base(L - 1);
         int ns[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
-        const int64_t ncand = 4 * (int64_t)nf;
-        for (int64_t c0 = 0; c0 < ncand; c0 += 64 * NR) {
+        for (int64_t tr = tr0; tr < tr1; ++tr) {
+            const int64_t c0 = tr * kTrip;
             bool valid[G];
             int32_t cc[G];
 #pragma unroll
@@ -618,12 +647,41 @@ k_traverse_long(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __r
         if (MODE == 0 && threadIdx.x == 0) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                s_cnt[g0 + t] = ns[t];
-                w_cnt[g0 + t] = nw[t];
+                if (split) {
+                    const int64_t uo = ((int64_t)k * kLongUnits + j) * 8 + 2 * t;
+                    ucnt[uo] = ns[t];
+                    ucnt[uo + 1] = nw[t];
+                } else {
+                    s_cnt[g0 + t] = ns[t];
+                    w_cnt[g0 + t] = nw[t];
+                }
             }
         }
     }
     if (__ballot(overflow) != 0ull && lane == 0) atomicOr((unsigned long long*)&totals[2], 2ull);
+}
+
+// Between the count and the fill pass: for every split group (thread: group
+// k, value v = 2 sibling + strong/weak), its units' counts become exclusive
+// prefixes in unit order, and their sum the sibling's list length.
+__global__ void k_long_finish(TravCtx c, const int32_t* __restrict__ queue, const int32_t* __restrict__ qn,
+                              int32_t* ucnt, int32_t* s_cnt, int32_t* w_cnt)
+{
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int ks = min(*qn, kLongSplitCap);
+    if (x >= (int64_t)ks * 8) return;
+    const int k = (int)(x >> 3), v = (int)(x & 7);
+    int run = 0;
+    for (int jj = 0; jj < kLongUnits; ++jj) {
+        int32_t* pv = ucnt + ((int64_t)k * kLongUnits + jj) * 8 + v;
+        const int cval = *pv;
+        *pv = run;
+        run += cval;
+    }
+    const int i = queue[k];
+    const int64_t g0 = c.first >= 0 ? c.first + i : (int64_t)c.boxes[i];
+    if (v & 1) w_cnt[g0 + (v >> 1)] = run;
+    else s_cnt[g0 + (v >> 1)] = run;
 }
 
 __global__ void k_zero_counter(int32_t* p) { if (threadIdx.x == 0) *p = 0; }
@@ -641,8 +699,11 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
     for (auto [l0, l1] : traversal_passes(sc.max_levels, single))
         if (l0 == l1 && l0 >= kLongFromLevel)
             max_groups = std::max<int64_t>(max_groups, (ex.level_boxes_off[l1 + 1] - ex.level_boxes_off[l0]) / 4);
-    DBuf<int32_t> lq;
-    if (max_groups > 0) lq.alloc(max_groups + 1, s);
+    DBuf<int32_t> lq, ucnt;
+    if (max_groups > 0) {
+        lq.alloc(max_groups + 1, s);
+        ucnt.alloc((size_t)std::min<int64_t>(max_groups, kLongSplitCap) * kLongUnits * 8, s);
+    }
     for (auto [l0, l1] : traversal_passes(sc.max_levels, single)) {
         TravCtx c;
         c.boxes = ex.d_level_boxes.p + ex.level_boxes_off[l0];
@@ -668,10 +729,13 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
         else
             k_traverse<0><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
-        if (longq)
-            k_traverse_long<0><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, pl.s_beg.p, pl.s_cnt.p,
-                                                                     pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
-                                                                     cap_s, cap_w, totals);
+        if (longq) {
+            k_traverse_long<0><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, ucnt.p, pl.s_beg.p,
+                                                                     pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                                                     pl.w_ids.p, cap_s, cap_w, totals);
+            k_long_finish<<<(unsigned)(kLongSplitCap * 8 / 256), 256, 0, s>>>(c, c.long_q, c.long_n, ucnt.p,
+                                                                              pl.s_cnt.p, pl.w_cnt.p);
+        }
         const int nb = (c.n + 1023) / 1024;
         k_scan_reduce<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, totals, snap);
         k_scan_apply<<<nb, 1024, 0, s>>>(c.boxes, c.n, pl.s_cnt.p, pl.w_cnt.p, bsum, snap, pl.s_beg.p,
@@ -683,9 +747,9 @@ static void build_lists_traversal(Plan& pl, hipStream_t s, int64_t cap_s, int64_
             k_traverse<1><<<grid, 256, 0, s>>>(c, pl.s_beg.p, pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
                                                pl.w_ids.p, cap_s, cap_w, totals);
         if (longq)
-            k_traverse_long<1><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, pl.s_beg.p, pl.s_cnt.p,
-                                                                     pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p, pl.w_ids.p,
-                                                                     cap_s, cap_w, totals);
+            k_traverse_long<1><<<kLongGrid, 64 * kLongWaves, 0, s>>>(c, c.long_q, c.long_n, ucnt.p, pl.s_beg.p,
+                                                                     pl.s_cnt.p, pl.w_beg.p, pl.w_cnt.p, pl.s_ids.p,
+                                                                     pl.w_ids.p, cap_s, cap_w, totals);
         check_launch("traversal lists");
     }
 }
