@@ -73,10 +73,37 @@ __global__ void k_pts_clear(int32_t* a, int64_t n)
 // the deepest box whose disc (centre c, radius r: the disc of the
 // theta-criterion, around the tight bounding box) holds each point, going
 // down from the root into the child that holds it with the smallest
-// |y - c| / r, and the points per box
-__global__ void k_pts_locate(const double2* __restrict__ y, int64_t M, int L, const double* __restrict__ geom,
-                             int32_t* box, int32_t* cnt)
+// |y - c| / r, and the points per box.  The geometry of levels 1 ..
+// kLocTop is read from a copy in LDS (the first kLocTop of a point's
+// dependent loads), deeper levels from the tree.
+constexpr int kLocTop = 4;
+constexpr int kLocTopBoxes = 340;   // boxes of levels 1 .. kLocTop
+__device__ __forceinline__ void locate_child(const double2 q, const double* g, int k, int& best, double& bq)
 {
+    const double dx = q.x - g[0], dy = q.y - g[1];
+    const double d2 = dx * dx + dy * dy, r2 = g[2] * g[2];
+    if (!(d2 <= r2)) return;                                // outside (a zero-radius disc holds its centre)
+    const double qk = r2 > 0.0 ? d2 / r2 : 0.0;
+    if (qk < bq) {
+        bq = qk;
+        best = k;
+    }
+}
+__global__ void __launch_bounds__(256)
+k_pts_locate(const double2* __restrict__ y, int64_t M, int L, const double* __restrict__ geom, int32_t* box,
+             int32_t* cnt)
+{
+    static_assert(kLocTopBoxes == ((4 << (2 * kLocTop)) - 1) / 3 - 1, "levels 1 .. kLocTop");
+    __shared__ double sg[kLocTopBoxes][3];
+    const int top = L - 1 < kLocTop ? L - 1 : kLocTop;     // levels cached
+    const int ntop = (int)(level_base(top + 1) - 1);
+    for (int t = threadIdx.x; t < ntop; t += blockDim.x) {
+        const double* g = geom + 4 * (int64_t)(t + 1);
+        sg[t][0] = g[0];
+        sg[t][1] = g[1];
+        sg[t][2] = g[2];
+    }
+    __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= M) return;
     const double2 q = y[i];
@@ -85,16 +112,10 @@ __global__ void k_pts_locate(const double2* __restrict__ y, int64_t M, int L, co
         const int64_t c0 = level_base(l + 1) + 4 * j;
         int best = -1;
         double bq = 2.0;     // the smallest (|y - c| / r)^2 so far; at most 1 inside a disc
-        for (int k = 0; k < 4; ++k) {
-            const double* g = geom + 4 * (c0 + k);
-            const double dx = q.x - g[0], dy = q.y - g[1];
-            const double d2 = dx * dx + dy * dy, r2 = g[2] * g[2];
-            if (!(d2 <= r2)) continue;                       // outside (a zero-radius disc holds its centre)
-            const double qk = r2 > 0.0 ? d2 / r2 : 0.0;
-            if (qk < bq) {
-                bq = qk;
-                best = k;
-            }
+        if (l + 1 <= top) {
+            for (int k = 0; k < 4; ++k) locate_child(q, sg[c0 + k - 1], k, best, bq);
+        } else {
+            for (int k = 0; k < 4; ++k) locate_child(q, geom + 4 * (c0 + k), k, best, bq);
         }
         if (best < 0) break;
         b = c0 + best;
