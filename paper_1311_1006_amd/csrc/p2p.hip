@@ -1,7 +1,8 @@
 // p2p.hip -- near-field direct sums over the finest-level strong lists
 // (Sec. 2.1: pairs not accounted for by M2L shifts are evaluated directly;
-// Sec. 3.1: both G(x_i,x_j) and G(x_j,x_i) are computed, so there is no
-// write conflict and the result is deterministic).
+// as in Sec. 3.1, a pair of neighbouring leaves is evaluated once from each
+// side, each work item writing only its own targets: no two items write the
+// same output and the result is deterministic).
 //
 //     phi_i += sum_{S in strong(leaf(i))} sum_{j in S, z_j != z_i} m_j / (z_i - z_j)
 //
