@@ -86,6 +86,24 @@ def test_clustered_long_lists_match_oracle(orc, F):
             assert np.array_equal(host(F.evaluate(F.plan(tree, 12, 0.5, prec), dev(m))), ref)
 
 
+def test_far_point_long_lists_match_oracle(orc, F):
+    # one point far from a uniform cloud: every box that holds it stretches
+    # to it and is strong with nearly every box of its level, so parent lists
+    # reach about 4^(N_levels - 2) boxes (65536 here): their sibling groups
+    # are split over several workgroups of several loop trips each
+    z, m, _ = W.uniform(270000, seed=91)
+    z[123] = 1000.0 + 1000.0j
+    L = 10
+    tree = same_tree(orc, F, z, L)
+    geom = orc.tree(z, L)[2]
+    pl = F.plan(tree, 8, 0.5, "fp64")
+    _lists_equal(orc, F, pl, geom, L, 0.5)
+    off, _ = pl.download_list(0, L - 2, 0)
+    assert np.diff(off).max() > 16384          # a parent list of more than 16 loop trips
+    phi = host(F.evaluate(pl, dev(m)))
+    assert e2(phi, orc.fmm(z, m, 8, 0.5, L)) <= 1e-12
+
+
 def test_tree_exact_select_fallback(orc, F):
     # a segment whose median bucket holds > 2048 points with identical
     # coordinates cannot be resolved by bucketing: the exact radix select runs
