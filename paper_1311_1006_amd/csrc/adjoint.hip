@@ -72,7 +72,8 @@ __global__ void k_gather_adj(int64_t n, const int32_t* __restrict__ perm, const 
 // transposing butterfly.
 template <class R>
 struct AdjSrc {
-    R x, y, xl, yl, mr, mi, gr, gi;
+    double x, y;           // positions in FP64: dz is formed in FP64, then rounded to R
+    R mr, mi, gr, gi;
 };
 
 template <class R, int TG, int SUB>
@@ -100,15 +101,14 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     AdjSrc<R>* lds = sbuf[w];
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
-    R xh[TG], yh[TG], xl[TG], yl[TG];
+    double tx[TG], ty[TG];   // the targets' positions
     R acc[TG][6];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
         int i = base + (k < it.tn ? k : 0);
-        double x = X[i], y = Y[i];
-        xh[t] = (R)x; yh[t] = (R)y;
-        xl[t] = (R)(x - (double)xh[t]); yl[t] = (R)(y - (double)yh[t]);
+        tx[t] = X[i];
+        ty[t] = Y[i];
 #pragma unroll
         for (int q = 0; q < 6; ++q) acc[t][q] = (R)0;
     }
@@ -117,10 +117,9 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     int e = nch == 1 ? 0 : xe.y * ce, off = 0;
     const int ne = nch == 1 ? s_cnt[it.leaf] : min(s_cnt[it.leaf], e + ce);
     auto load = [&](int j) {
-        const double x = X[j], y = Y[j];
         AdjSrc<R> s;
-        s.x = (R)x; s.y = (R)y;
-        s.xl = (R)(x - (double)s.x); s.yl = (R)(y - (double)s.y);
+        s.x = X[j];
+        s.y = Y[j];
         const double2 mm = mt[j], gg = gb[j];
         s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
         return s;
@@ -133,8 +132,8 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
             if (f >= ns) { s.mr = (R)0; s.mi = (R)0; s.gr = (R)0; s.gi = (R)0; }
 #pragma unroll
             for (int t = 0; t < TG; ++t) {
-                R dx = (xh[t] - s.x) + (xl[t] - s.xl);
-                R dy = (yh[t] - s.y) + (yl[t] - s.yl);
+                R dx = (R)(tx[t] - s.x);
+                R dy = (R)(ty[t] - s.y);
                 R r2 = dx * dx + dy * dy;
                 R q;
                 if (sizeof(R) == 8) {
