@@ -69,14 +69,16 @@ __global__ void k_gather_adj(int64_t n, const int32_t* __restrict__ perm, const 
 // (coincident positions excluded).  Same lane layout as the forward P2P:
 // SUB subgroups, TG targets per lane, one source per lane, sources staged in
 // LDS; the 6 accumulators of a target (padded to 8) are summed by a
-// transposing butterfly.
+// transposing butterfly.  With DER only C_k is formed (the field derivative
+// needs nothing else): 2 accumulators per target, written to entries 4 and 5
+// of the target's six; entries 0-3 are then left undefined.
 template <class R>
 struct AdjSrc {
     double x, y;           // positions in FP64: dz is formed in FP64, then rounded to R
     R mr, mi, gr, gi;
 };
 
-template <class R, int TG, int SUB>
+template <class R, int TG, int SUB, bool DER>
 __global__ void __launch_bounds__(256)
 k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restrict__ xitems, int nx,
           const int32_t* __restrict__ icnt, const int32_t* __restrict__ ioff,
@@ -87,7 +89,9 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
 {
     constexpr int NL = 64 / SUB;
     constexpr int CAP = sizeof(R) == 4 ? 256 : 128;
-    constexpr int V = 8 * TG;
+    constexpr int NA = DER ? 2 : 6;                // accumulators per target
+    constexpr int VS = DER ? 2 : 8;                // their stride (a power of two)
+    constexpr int V = VS * TG;
     __shared__ AdjSrc<R> sbuf[4][CAP];
     __shared__ int2 smeta[4][64];
     __shared__ int smark[4][CAP];
@@ -102,7 +106,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     const int g = lane / NL, sl = lane % NL;
     const int base = bstart[it.leaf] + it.t0;
     double tx[TG], ty[TG];   // the targets' positions
-    R acc[TG][6];
+    R acc[TG][NA];
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         int k = g * TG + t;
@@ -110,7 +114,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
         tx[t] = X[i];
         ty[t] = Y[i];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) acc[t][q] = (R)0;
+        for (int q = 0; q < NA; ++q) acc[t][q] = (R)0;
     }
     // the item's entries, or those of its chunk
     const int e0 = s_beg[it.leaf], ce = chunk_entries(bcount[it.leaf]);
@@ -120,7 +124,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
         AdjSrc<R> s;
         s.x = X[j];
         s.y = Y[j];
-        const double2 mm = mt[j], gg = gb[j];
+        const double2 mm = mt[j], gg = DER ? make_double2(0.0, 0.0) : gb[j];
         s.mr = (R)mm.x; s.mi = (R)mm.y; s.gr = (R)gg.x; s.gi = (R)gg.y;
         return s;
     };
@@ -147,12 +151,17 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
                 // w = 1/dz = conj(dz)/|dz|^2, w2 = w*w
                 R wr = dx * q, wi = -dy * q;
                 R w2r = wr * wr - wi * wi, w2i = (R)2 * wr * wi;
-                acc[t][0] += s.gr * wr - s.gi * wi;
-                acc[t][1] += s.gr * wi + s.gi * wr;
-                acc[t][2] += s.gr * w2r - s.gi * w2i;
-                acc[t][3] += s.gr * w2i + s.gi * w2r;
-                acc[t][4] += s.mr * w2r - s.mi * w2i;
-                acc[t][5] += s.mr * w2i + s.mi * w2r;
+                if constexpr (DER) {
+                    acc[t][0] += s.mr * w2r - s.mi * w2i;
+                    acc[t][1] += s.mr * w2i + s.mi * w2r;
+                } else {
+                    acc[t][0] += s.gr * wr - s.gi * wi;
+                    acc[t][1] += s.gr * wi + s.gi * wr;
+                    acc[t][2] += s.gr * w2r - s.gi * w2i;
+                    acc[t][3] += s.gr * w2i + s.gi * w2r;
+                    acc[t][4] += s.mr * w2r - s.mi * w2i;
+                    acc[t][5] += s.mr * w2i + s.mi * w2r;
+                }
             }
         }
         wave_sync();
@@ -161,9 +170,9 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v[8 * t + q] = acc[t][q];
-        v[8 * t + 6] = (R)0;
-        v[8 * t + 7] = (R)0;
+        for (int q = 0; q < NA; ++q) v[VS * t + q] = acc[t][q];
+#pragma unroll
+        for (int q = NA; q < VS; ++q) v[VS * t + q] = (R)0;
     }
     // transposing butterfly over the NL lanes of the subgroup: afterwards this
     // lane holds the totals of value indices base + i, i < NV
@@ -174,7 +183,7 @@ k_p2p_adj(const P2PItemA* __restrict__ items, int item_base, const int2* __restr
     if (writer) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int idx = base0 + i, t = idx >> 3, q = idx & 7;
+            const int idx = base0 + i, t = idx / VS, q = idx % VS + (DER ? 4 : 0);
             const int k = g * TG + t;
             if (q < 6 && k < it.tn) {
                 if (nch == 1) out[6 * (int64_t)(base + k) + q] = (double)v[i];
@@ -269,14 +278,14 @@ static void adj_shape(int nt, bool mixed, int* tg, int* sub)
     *tg = t;
 }
 
-template <class R, int TG, int SUB>
+template <class R, int TG, int SUB, bool DER>
 static void launch_adj_one(const P2PItemA* items, int item_base, const int2* xitems, int nx, const int32_t* icnt,
                            const int32_t* ioff, double* partial, const int32_t* bstart,
                            const int32_t* bcount, const int32_t* s_beg, const int32_t* s_cnt, const int32_t* s_ids,
                            const double* X, const double* Y, const double* mt, const double* gb, double* out,
                            hipStream_t s)
 {
-    k_p2p_adj<R, TG, SUB><<<(nx + 3) / 4, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial,
+    k_p2p_adj<R, TG, SUB, DER><<<(nx + 3) / 4, 256, 0, s>>>(items, item_base, xitems, nx, icnt, ioff, partial,
                                                        bstart, bcount, s_beg, s_cnt, s_ids, X, Y,
                                                        (const double2*)mt, (const double2*)gb, out);
 }
@@ -288,10 +297,11 @@ void combine_chunks(const Plan::Balance& b, const void* items, int n, const int3
                     hipStream_t s);
 
 // Near-field sums of the transposed chain for the weights gb (tree order),
-// into pl.near_d (6 doubles per point, see k_p2p_adj), in source chunks when
+// into pl.near_d (6 doubles per point, see k_p2p_adj; with der only the
+// derivative sum C, in entries 4 and 5, and gb unused), in source chunks when
 // some strong list is long (the chunk lists of the adjoint items are made
 // once per plan).  pl.mtree holds the strengths in tree order.
-static void adjoint_near(Plan& pl, const double* gb_tree, hipStream_t s)
+static void adjoint_near(Plan& pl, const double* gb_tree, bool der, hipStream_t s)
 {
     Tree& t = *pl.tree;
     TreeSchedule& sc = *t.sched;
@@ -320,7 +330,8 @@ static void adjoint_near(Plan& pl, const double* gb_tree, hipStream_t s)
         const int nx = (int)(x1 - x0);
 #define ACASE(R_, TG_, SUB_)                                                                                  \
     if (c.tg == TG_ && c.sub == SUB_) {                                                                       \
-        launch_adj_one<R_, TG_, SUB_>(items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, ba.partial.p,  \
+        (der ? launch_adj_one<R_, TG_, SUB_, true> : launch_adj_one<R_, TG_, SUB_, false>)(                   \
+                                      items, (int)x0, xit, nx, ba.icnt.p, ba.ioff.p, ba.partial.p,            \
                                       sc.d_box_start.p, sc.d_box_count.p, pl.s_beg.p, pl.s_cnt.p, pl.s_ids.p,  \
                                       t.x.p, t.y.p, pl.mtree.p, gb_tree, pl.near_d.p, s);                  \
         check_launch("p2p adjoint");                                                                          \
@@ -375,7 +386,7 @@ void adjoint_device(Plan& pl, const double* m, const double* gphi, double* gm, d
         }
     };
     if (mixed) far(float()); else far(double());
-    adjoint_near(pl, pl.gtree.p, s);
+    adjoint_near(pl, pl.gtree.p, false, s);
     // combination and scatter: G lanes per leaf, P terms held per lane
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
     const int P = pl.p <= 16 ? 16 : (pl.p <= 32 ? 32 : 64);
@@ -463,8 +474,8 @@ void field_device(Plan& pl, const double* m, double* phi, double* dphi, hipStrea
     const bool mixed = pl.precision == FMM_MIXED;
     // the forward evaluation: phi, the local expansions and m in tree order
     evaluate_device(pl, m, phi, nullptr, nullptr, s);
-    // near-field sums with both weights the strengths: near_d[4..5] = sum m_j w^2
-    adjoint_near(pl, pl.mtree.p, s);
+    // near-field derivative sums: near_d[4..5] = sum m_j w^2
+    adjoint_near(pl, pl.mtree.p, true, s);
     const int nleaf = (int)sc.nleaf;
     const int G = ex.leaf_max <= 16 ? 16 : (ex.leaf_max <= 32 ? 32 : 64);
     const int P = pl.p <= 16 ? 16 : (pl.p <= 32 ? 32 : 64);
