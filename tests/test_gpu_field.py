@@ -58,6 +58,30 @@ def test_clustered_and_ragged_inputs(F, orc):
     assert e2(host(dphi)[sub], orc.direct_deriv_points(z, m, z[sub])) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,p,tol", [("fp64", 40, 1e-11), ("mixed", 16, 1e-6)])
+def test_field_with_split_source_lists_then_adjoint(F, orc, prec, p, tol):
+    # four tight clusters: boxes between clusters have strong lists of
+    # hundreds of leaves, so the derivative's near field is summed in work
+    # chunks whose partial sums are combined in order.  The adjoint on the
+    # same plan shares the near-field buffer and the chunk partials (of which
+    # the derivative writes only its own two sums): it must not see them, and
+    # the derivative evaluated again after it must be the same bit for bit.
+    z, m = W.clustered(20000, seed=3, nclusters=4, sigma=1e-5)
+    L = 6
+    pl = F.plan(F.build_tree(dev(z), L), p, 0.5, prec)
+    off, _ = pl.download_list(0, L - 1, 0)
+    assert np.diff(off).max() > 4 * (2048 // (20000 // 4 ** (L - 1) + 2))
+    sub = np.arange(0, z.size, 7)
+    refd = orc.direct_deriv_points(z, m, z[sub])
+    phi, dphi = F.evaluate_field(pl, dev(m))
+    assert e2(host(dphi)[sub], refd) <= tol and einf(host(dphi)[sub], refd) <= tol
+    gm, gz = F.evaluate_adjoint(pl, dev(m), 2 * phi)
+    rgm, rgz = orc.grad_direct(z, m, 2 * orc.direct(z, m))
+    assert e2(host(gm), rgm) <= tol and e2(host(gz), rgz) <= tol
+    _, dphi2 = F.evaluate_field(pl, dev(m))
+    np.testing.assert_array_equal(host(dphi2), host(dphi))
+
+
 def test_tiny_problems(F):
     # one point: no field; two points: dphi_0 = -m_1/(z_0 - z_1)^2 exactly enough
     _, d1 = F.evaluate_field(F.plan(F.build_tree(dev(np.array([0.3 + 0.4j])), 1), 8, 0.5), dev(np.array([2.0 + 1j])))
