@@ -332,9 +332,12 @@ constexpr int kFront = 512;   // frontier boxes per wavefront (LDS)
 // points, or puts its four children in the next frontier; a box whose
 // children no longer fit is descended by its lane alone.  The lanes' sums
 // are added by a fixed butterfly, so the result does not depend on timing.
-// Results go to tnear (and tdnear) in box order.
+// Results go to tnear (and tdnear) in box order.  A descent is a chain of
+// dependent loads, so wavefronts in flight set its rate: the mixed kernel
+// without the derivative is held to 80 registers (six wavefronts per SIMD,
+// no spills); the others need 97-120 and would spill below that.
 template <class T, bool DER>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !DER ? 6 : 1)))
 k_pts_descend(const double2* __restrict__ y, const int32_t* __restrict__ order, const int32_t* __restrict__ box,
               const int32_t* __restrict__ nq_dev, int nq_host, int L, const int8_t* __restrict__ level,
               const double* __restrict__ geom, const int32_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
@@ -534,7 +537,10 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     }
     // descents: the points that stopped above the leaves (box-order positions
     // before the first leaf), or with the derivative every point
-    const unsigned gd = (unsigned)std::min<int64_t>((M + 3) / 4, 1024);
+    // workgroups of the descents: those the occupancy holds at once (six
+    // wavefronts per SIMD for the mixed kernel without the derivative, four
+    // for the others)
+    const unsigned gd = (unsigned)std::min<int64_t>((M + 3) / 4, mixed && !der ? 1536 : 1024);
     const int32_t* nq_dev = der ? nullptr : off.p + lb;
 #define DESC_ARGS                                                                                             \
     (const double2*)y, order.p, box.p, nq_dev, (int)M, L, sc.d_box_level.p, t.geom.p, sc.d_box_start.p,       \
