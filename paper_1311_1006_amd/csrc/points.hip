@@ -73,7 +73,8 @@ __global__ void k_pts_clear(int32_t* a, int64_t n)
 // the deepest box whose disc (centre c, radius r: the disc of the
 // theta-criterion, around the tight bounding box) holds each point, going
 // down from the root into the child that holds it with the smallest
-// |y - c| / r, and the points per box.  The geometry of levels 1 ..
+// |y - c| / r, the points per box and each point's rank among its box's
+// points (the order the counter gave them).  The geometry of levels 1 ..
 // kLocTop is read from a copy in LDS (the first kLocTop of a point's
 // dependent loads), deeper levels from the tree.
 constexpr int kLocTop = 4;
@@ -91,7 +92,7 @@ __device__ __forceinline__ void locate_child(const double2 q, const double* g, i
 }
 __global__ void __launch_bounds__(256)
 k_pts_locate(const double2* __restrict__ y, int64_t M, int L, const double* __restrict__ geom, int32_t* box,
-             int32_t* cnt)
+             int32_t* cnt, int32_t* rank)
 {
     static_assert(kLocTopBoxes == ((4 << (2 * kLocTop)) - 1) / 3 - 1, "levels 1 .. kLocTop");
     __shared__ double sg[kLocTopBoxes][3];
@@ -122,18 +123,18 @@ k_pts_locate(const double2* __restrict__ y, int64_t M, int L, const double* __re
         j = 4 * j + best;
     }
     box[i] = (int32_t)b;
-    atomicAdd(&cnt[b], 1);
+    rank[i] = atomicAdd(&cnt[b], 1);
 }
 
-// sorted position of every point (the order inside a box is immaterial: each
-// point's value depends on its own position only)
+// sorted position of every point: its box's offset plus its rank in the box
+// (the order inside a box is immaterial: each point's value depends on its
+// own position only)
 __global__ void k_pts_scatter(const int32_t* __restrict__ box, int64_t M, const int32_t* __restrict__ off,
-                              int32_t* fill, int32_t* order)
+                              const int32_t* __restrict__ rank, int32_t* order)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const int32_t b = box[i];
-    order[off[b] + atomicAdd(&fill[b], 1)] = (int32_t)i;
+    order[off[box[i]] + rank[i]] = (int32_t)i;
 }
 
 // the points' positions in box order, as the near-field kernel reads its
@@ -490,13 +491,13 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     // item list: at most M / kPtsItem + nleaf items (spares have no target)
     const int64_t nx = M / kPtsItem + nleaf + 1;
     if (nx >= INT32_MAX / 4) throw Error(FMM_EINVAL, "too many evaluation points");
-    DBuf<int32_t> box, order, cnt, off, fill, bsum, icnt, ioff;
+    DBuf<int32_t> box, rank, order, cnt, off, bsum, icnt, ioff;
     DBuf<double> rx, ry, tnear, tdnear;
     DBuf<PtsItem> items;
     box.alloc(M, s);
+    rank.alloc(M, s);
     order.alloc(M, s);
     cnt.alloc(nb, s);
-    fill.alloc(nb, s);
     off.alloc(nb + 1, s);
     bsum.alloc((std::max<int64_t>(nb, nleaf) + 1023) / 1024, s);
     if (!der) {
@@ -511,10 +512,9 @@ void evaluate_points_device(Plan& pl, const double* m, const double* y, int64_t 
     far_field_all(pl, m, s);
     const unsigned gb = (unsigned)((nb + 255) / 256), gm = (unsigned)((M + 255) / 256);
     k_pts_clear<<<gb, 256, 0, s>>>(cnt.p, nb);
-    k_pts_clear<<<gb, 256, 0, s>>>(fill.p, nb);
-    k_pts_locate<<<gm, 256, 0, s>>>((const double2*)y, M, L, t.geom.p, box.p, cnt.p);
+    k_pts_locate<<<gm, 256, 0, s>>>((const double2*)y, M, L, t.geom.p, box.p, cnt.p, rank.p);
     launch_exclusive_scan(cnt.p, (int)nb, bsum.p, off.p, s);
-    k_pts_scatter<<<gm, 256, 0, s>>>(box.p, M, off.p, fill.p, order.p);
+    k_pts_scatter<<<gm, 256, 0, s>>>(box.p, M, off.p, rank.p, order.p);
     check_launch("point order");
     if (!der) {
         // the near field of the points in leaves: the near-field kernel, with
